@@ -1,0 +1,171 @@
+"""Pins of the oracle against numbers and closed forms the paper fixes."""
+import os
+
+import numpy as np
+import pytest
+
+import lbm_inputs as li
+from oracle import lbm, mms, symbol
+from oracle import material as mat
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def read_table(name):
+    rows = {}
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            rows[parts[0]] = [float(x) for x in parts[1:]]
+    return rows
+
+
+def printed_match(value, printed):
+    """|value - printed| within half a unit of the last of the 3 significant digits the
+    paper prints, plus a 1e-3 relative allowance for rounding order."""
+    exp = np.floor(np.log10(abs(printed)))
+    half_ulp = 0.5 * 10 ** (exp - 2)
+    return abs(value - printed) <= half_ulp + 1e-3 * abs(printed)
+
+
+@pytest.mark.slow
+def test_periodic_mms_matches_paper_table():
+    """Table tab:mms-error-summary, periodic rows, n = 128: second-order and equilibrium
+    initialisation, E_L2 of u, P and sigma."""
+    table = read_table("periodic_mms_table.txt")
+    for key, second in (("second_order", True), ("equilibrium", False)):
+        e = mms.relative_errors(128, second_order=second)
+        for got, want in zip((e["u"], e["P"], e["sigma"]), table[key]):
+            assert printed_match(got, want), (key, got, want)
+
+
+def test_periodic_mms_second_order_convergence():
+    """Second order with the second-order initialisation; about first order with the
+    equilibrium one (Sec. 4.1, App. B)."""
+    e = {n: mms.relative_errors(n) for n in (16, 32, 64)}
+    for q in ("u", "P", "sigma"):
+        order = np.log2(e[32][q] / e[64][q])
+        assert order >= 1.9, (q, order)
+    eq = {n: mms.relative_errors(n, second_order=False) for n in (32, 64)}
+    order = np.log2(eq[32]["u"] / eq[64]["u"])
+    assert 0.8 <= order <= 1.6
+    assert eq[64]["u"] > 10 * e[64]["u"]
+
+
+def test_mms_field_ranges():
+    """Sec. 4.1: at t = 0.1 the exact J ranges over [0.781, 1.205] and max |F - I| = 0.244
+    (the norm matches the Frobenius norm)."""
+    g = read_table("periodic_mms_field.txt")
+    X, Y = mms.grid(512)
+    f = mms.fields(X, Y, 0.1)
+    J = mat.det(f["F"])
+    Ft = f["F"] - np.eye(2)[:, :, None, None]
+    assert printed_match(J.min(), g["J_min"][0])
+    assert printed_match(J.max(), g["J_max"][0])
+    assert printed_match(np.sqrt((Ft ** 2).sum((0, 1))).max(), g["max_F_minus_I"][0])
+
+
+def test_mms_body_force_closes_the_balance():
+    """b of eq:mms-body-force makes the exact field solve d_t^2 u = Div P + b; check Div P
+    by central differences of P(F(X)) (independent of the tangent contraction)."""
+    X, Y = mms.grid(64)
+    t = 0.05
+    b = mms.body_force("lognh", 1.0, 2.0 / 3.0, X, Y, t)
+    h = 1e-5
+    def P_at(Xq, Yq):
+        return mat.stress("lognh", mms.fields(Xq, Yq, t)["F"], 1.0, 2.0 / 3.0)
+    divP = ((P_at(X + h, Y) - P_at(X - h, Y))[:, 0] + (P_at(X, Y + h) - P_at(X, Y - h))[:, 1]) / (2 * h)
+    acc = mms.fields(X, Y, t)["a"]
+    assert np.abs(acc - divP - b).max() <= 1e-6 * np.abs(acc).max()
+
+
+def test_linear_symbol_stability_limit():
+    """Linear stability about the rest state (24 x 24 symbol): stable at c = 2 for
+    mu = 0.1, lam = 0.2 (c_p / c = 0.316) and unstable at c = 1 (c_p / c = 0.632)."""
+    assert symbol.spectral_radius(2.0, 2.0, "lognh", 0.1, 0.2, n=16) <= 1.0 + 1e-12
+    assert symbol.spectral_radius(1.0, 2.0, "lognh", 0.1, 0.2, n=16) > 1.2
+
+
+def test_linear_symbol_speeds_converge_to_lame():
+    """The lattice S and P speeds tend to sqrt(mu) and sqrt(lam + 2 mu) (the acoustic
+    tensor at F = I) with second-order error in the wavenumber."""
+    mu, lam = 0.1, 0.2
+    errs = []
+    for n in (32, 64, 128):
+        modes = symbol.elastic_modes((0.0, 2 * np.pi / n), 2.0, 2.0, "lognh", mu, lam)
+        speeds = sorted(m[0] for m in modes)[-4:]
+        errs.append((abs(speeds[0] - np.sqrt(mu)), abs(speeds[-1] - np.sqrt(lam + 2 * mu))))
+    errs = np.array(errs)
+    assert errs[-1, 0] / np.sqrt(mu) < 1e-4 and errs[-1, 1] / np.sqrt(lam + 2 * mu) < 1e-4
+    assert np.all(np.log2(errs[1] / errs[2]) > 1.9)
+
+
+def test_shear_wave_frequency_matches_symbol():
+    """Standing S-wave of the 64 x 64 shear-wave workload (v1 = 1e-3 sin(2 pi Y / 64),
+    c = 2, omega = 2, 200 steps): the mode amplitude a(t) = 2 <v1 sin(k Y)> oscillates at
+    the symbol's S frequency to 1e-5 and at sqrt(mu) k to 5e-4."""
+    from scipy.optimize import least_squares
+    n, mu, lam = 64, 0.1, 0.2
+    pb = lbm.Problem(nx=n, ny=n, c=2.0, omega=2.0, law="lognh", mu=mu, lam=lam)
+    st = lbm.initial_state(pb, li.shear_wave_v0(n, n))
+    k = 2 * np.pi / n
+    sk = np.sin(k * (np.arange(n) + 0.5))[:, None]
+    amps, times = [], []
+    for m in range(201):
+        U, _ = lbm.observe(pb, st)
+        amps.append(2 * np.mean(U[0] * sk))
+        times.append(m * pb.dt)
+        if m < 200:
+            lbm.step(pb, st)
+    amps, times = np.array(amps), np.array(times)
+    fit = least_squares(lambda p: p[0] * np.cos(p[1] * times) - amps, [amps[0], np.sqrt(mu) * k],
+                        xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    c_meas = fit.x[1] / k
+    c_sym = symbol.elastic_modes((0.0, k), 2.0, 2.0, "lognh", mu, lam)[2][0]
+    assert abs(c_meas - c_sym) / c_sym <= 1e-5
+    assert abs(c_meas - np.sqrt(mu)) / np.sqrt(mu) <= 5e-4
+
+
+def test_finite_shear_wave_is_amplitude_independent():
+    """Sec. 5.3 finite-amplitude shear wave (mu = 2, k = 4 pi, n = 80, c = 5, omega = 2):
+    along the J = 1 path P21 = mu F21 exactly, F11 = F22 = 1 and F12 = 0 stay exact, so the
+    lattice error is the same for Ak = 0.2 and Ak = 0.5 and equals the phase error of the
+    linear S mode given by the symbol."""
+    n, c, mu, lam, k = 80, 5.0, 2.0, 1.0, 4 * np.pi
+    cs = np.sqrt(mu)
+    dx = 1.0 / n
+    X = np.broadcast_to(((np.arange(n) + 0.5) * dx)[None, :], (n, n))
+    errs = {}
+    nsteps = 24
+    for law in ("nh", "lognh"):
+        for Ak in (0.2, 0.5):
+            A = Ak / k
+            pb = lbm.Problem(nx=n, ny=n, c=c, omega=2.0, law=law, mu=mu, lam=lam, dx=dx)
+            ph = k * X
+            u0 = np.zeros((2, n, n))
+            u0[1] = A * np.sin(ph)
+            v0 = np.zeros((2, n, n))
+            v0[1] = -A * cs * k * np.cos(ph)
+            F0 = np.zeros((2, 2, n, n))
+            F0[0, 0] = F0[1, 1] = 1.0
+            F0[1, 0] = A * k * np.cos(ph)
+            dUdX = np.zeros((6, n, n))
+            dUdX[1] = A * cs * k * k * np.sin(ph)
+            dUdX[4] = -A * k * k * np.sin(ph)
+            st = lbm.initial_state(pb, v0, u0, dU=(dUdX, np.zeros((6, n, n))), F0=F0)
+            U, u = lbm.run(pb, st, nsteps)
+            assert np.abs(U[2] - 1).max() < 1e-13 and np.abs(U[5] - 1).max() < 1e-13
+            assert np.abs(U[3]).max() < 1e-13 and np.abs(U[0]).max() < 1e-13
+            t = nsteps * pb.dt
+            v2 = -A * cs * k * np.cos(k * X - cs * k * t)
+            errs[(law, Ak)] = np.sqrt(((U[1] - v2) ** 2).sum() / (v2 ** 2).sum())
+    vals = np.array(list(errs.values()))
+    assert vals.max() - vals.min() <= 1e-9 * vals.max()
+    # linear phase error of the S mode over the run
+    c_sym = symbol.elastic_modes((k, 0.0), c, 2.0, "lognh", mu, lam, dx=dx)[2][0]
+    t = nsteps * dx / c
+    phase_err = abs(c_sym - cs) * k * t
+    assert abs(vals[0] - phase_err) <= 0.05 * phase_err + 1e-6
