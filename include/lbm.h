@@ -1,0 +1,239 @@
+/*
+ * lbm.h - C ABI of the MI355X library for the total-Lagrangian vectorial lattice
+ * Boltzmann method (D2Q4 lattice, six-component vector populations) of Feng & Chu,
+ * "A total-Lagrangian vectorial lattice Boltzmann method for finite-strain hyperelastic
+ * dynamics", arXiv 2605.26677.  Section, equation and table names below are the paper's.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every pointer named "device" is a device pointer on the current HIP device, owned by
+ *    the caller.  The library never allocates, frees or synchronises: each call only
+ *    enqueues kernels on `stream` (a hipStream_t passed as void*; NULL = null stream) and
+ *    returns.  Argument errors are returned synchronously as lbm_status codes, launch
+ *    errors as LBM_ERR_LAUNCH; numerical faults found on the device are OR-ed into the
+ *    caller's fault word (LBM_FAULT_*) without stopping the stream.
+ *  - Grid: nx x ny nodes; node (a, b) sits at X = ((a + 1/2) dx, (b + 1/2) dx), so the
+ *    half-way walls of Sec. 3.6 lie at X = 0, X = nx dx, Y = 0, Y = ny dx.  Time step
+ *    dt = dx / c (Sec. 2.1: c = dx/dt is the nondimensional lattice speed).
+ *  - Field planes: a "plane" is nx*ny values, row-major (index b*nx + a).  Arrays of
+ *    several planes place plane k at offset k*nx*ny unless stated otherwise.
+ *  - Population buffers: 24 planes, plane p = 6*q + k, at offset p*lbm_plane_stride()
+ *    elements; q is the D2Q4 direction in the paper's order (1,0), (0,1), (-1,0), (0,-1)
+ *    (Sec. 3.1), k the component of U = (v1, v2, F11, F12, F21, F22) (eq:state-vector).
+ *    A buffer holds post-collision populations f* (eq:collision) of one time level; for
+ *    the shifted storages it holds g* = f* - (0, 0, 1/4, 0, 0, 1/4), i.e. F is carried
+ *    as F - I (the equilibrium of the reference state U = (0, 0, 1, 0, 0, 1) is U/4,
+ *    because P(I) = 0 for every law of Appendix A).
+ *  - Time levels: after lbm_init the state holds f*^0 and the displacement accumulator
+ *    u*^1; lbm_step advances f*^n to f*^{n+1} (streaming, half-way wall rules with data at
+ *    t^{n+1/2}, moments at level n+1, collision) and u*^{n+1} to u*^{n+2}.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+enum {
+    LBM_OK = 0,
+    LBM_ERR_ARG = 1,          /* invalid argument (sizes, enums, NULL pointers, pairing) */
+    LBM_ERR_UNSUPPORTED = 2,  /* combination not provided by the library */
+    LBM_ERR_CFL = 3,          /* lattice speed too low for the material (see lbm_check_cfl) */
+    LBM_ERR_LAUNCH = 4        /* a kernel launch failed (hipGetLastError) */
+};
+
+/* Population storage.  F32/F16 carry F - I and compute in FP32; F64 stores the plain
+ * (unshifted) populations and computes in FP64. */
+enum { LBM_F32_SHIFTED = 0, LBM_F16_SHIFTED = 1, LBM_F64_PLAIN = 2 };
+
+/* Hyperelastic closures of Appendix A: logarithmic neo-Hookean (eq:lognh-model,
+ * P = mu (F - F^-T) + lam ln J F^-T), compressible neo-Hookean (eq:nh-model,
+ * P = mu (F - F^-T) + lam/2 (J^2 - 1) F^-T), St. Venant-Kirchhoff (eq:svk-model). */
+enum { LBM_LOGNH = 0, LBM_NH = 1, LBM_SVK = 2 };
+
+/* Edge kinds: periodic, velocity Dirichlet (eq:dirichlet-boundary-rule), nominal-traction
+ * Neumann (eq:neumann-boundary-rule).  Periodic edges must pair: XMIN with XMAX, YMIN
+ * with YMAX. */
+enum { LBM_PERIODIC = 0, LBM_VELOCITY = 1, LBM_TRACTION = 2 };
+enum { LBM_XMIN = 0, LBM_XMAX = 1, LBM_YMIN = 2, LBM_YMAX = 3 };
+
+/* Bits of the device fault word. */
+enum {
+    LBM_FAULT_J = 1,          /* det F <= 0 at some node (Sec. 2.2: admissible states have J > 0) */
+    LBM_FAULT_NONFINITE = 2,  /* a recovered state value is not finite */
+    LBM_FAULT_NEWTON = 4      /* a traction-boundary Newton solve failed (Sec. 3.6) */
+};
+
+/* Number of FP64 values written by lbm_diagnostics. */
+#define LBM_DIAG_COUNT 10
+
+typedef struct {
+    int32_t nx, ny;            /* grid nodes, >= 4 along any axis with walls, >= 2 otherwise */
+    int32_t material;          /* LBM_LOGNH | LBM_NH | LBM_SVK */
+    int32_t storage;           /* LBM_F32_SHIFTED | LBM_F16_SHIFTED | LBM_F64_PLAIN */
+    int32_t bc[4];             /* per edge LBM_XMIN..LBM_YMAX: LBM_PERIODIC | LBM_VELOCITY | LBM_TRACTION */
+    int32_t newton_max_iter;   /* traction Newton updates per link; <= 0 selects 8 */
+    int32_t force_unstable;    /* nonzero: skip the lattice-speed audit */
+    double dx;                 /* lattice spacing (> 0) */
+    double c;                  /* lattice speed dx/dt (> 0) */
+    double omega;              /* BGK rate, 0 < omega <= 2 (eq:collision; 2 is nondissipative) */
+    double newton_tol;         /* relative Newton tolerance; <= 0 selects 1e-14 (F64) or 1e-6 (F32/F16) */
+} lbm_params;
+
+typedef struct {
+    void *pop[2];              /* device: two population buffers of lbm_pop_bytes() each */
+    int32_t cur;               /* index of the buffer that holds the current level */
+    void *ustar;               /* device, lbm_ustar_bytes(): u* of eq:trapezoid-u; F32/F16:
+                                  4 float planes (hi1, hi2, c1, c2), u* = hi - c (compensated
+                                  summation); F64: 2 double planes */
+    const float *mu, *lam;     /* device: per-node Lame fields (1 plane each), or NULL for mu0/lam0 */
+    double mu0, lam0;          /* uniform values used when the field pointer is NULL */
+    double mu_max, lam_max;    /* host-known upper bounds of the fields (CFL audit);
+                                  ignored when the field pointer is NULL */
+    const float *body;         /* device: body acceleration b, 2 planes, or NULL for b0 */
+    double b0[2];              /* uniform body acceleration when body is NULL */
+    void *aux;                 /* device, lbm_aux_bytes(): traction-wall staging (F^b per link) */
+    uint32_t *fault;           /* device: fault word (LBM_FAULT_* bits are OR-ed in) */
+} lbm_state;
+
+/* Boundary data at t^{n+1/2} (eq:boundary-general): for velocity edges the prescribed
+ * velocity v_D, for traction edges the nominal traction T (force per reference length,
+ * eq:neumann-continuum).  value[e] is uniform along edge e unless field[e] is non-NULL:
+ * then field[e] is a device array of 2*L doubles (component-major, L = ny for x-edges,
+ * nx for y-edges, position along the edge = a or b). */
+typedef struct {
+    double value[4][2];
+    const double *field[4];
+} lbm_edge_data;
+
+/* ------------------------------------------------------------------ sizes */
+
+/* Elements between consecutive population planes (>= nx*ny, padded). */
+size_t lbm_plane_stride(const lbm_params *p);
+/* Bytes of one population buffer: 24 * lbm_plane_stride() * element size. */
+size_t lbm_pop_bytes(const lbm_params *p);
+/* Bytes of the u* accumulator. */
+size_t lbm_ustar_bytes(const lbm_params *p);
+/* Bytes of the traction-wall staging buffer (forward and adjoint). */
+size_t lbm_aux_bytes(const lbm_params *p);
+/* Bytes of one per-level state record (6 planes of the compute type: v1, v2, F - I). */
+size_t lbm_record_bytes(const lbm_params *p);
+/* Bytes of device scratch needed by lbm_diagnostics. */
+size_t lbm_diag_scratch_bytes(const lbm_params *p);
+
+/* ------------------------------------------------------------------ checks */
+
+/* Validates p.  Returns LBM_ERR_ARG or LBM_ERR_UNSUPPORTED on bad input, else LBM_OK. */
+lbm_status lbm_check_params(const lbm_params *p);
+
+/* Lattice-speed audit (Sec. 4 audits c against the largest tangent wave speed, Table
+ * tab:validation-setup): at F = I the fastest wave is the P wave, sqrt(lam + 2 mu); the
+ * linearised D2Q4 x 6 step is stable for sqrt(lam + 2 mu) / c <= 1/2 at omega = 2.
+ * Returns LBM_ERR_CFL above that ratio, LBM_OK otherwise. */
+lbm_status lbm_check_cfl(const lbm_params *p, double mu_max, double lam_max);
+
+/* ------------------------------------------------------------------ forward */
+
+/* Second-order population initialisation (Sec. 3.4, eq:init-compact, eq:init-Zq-components,
+ * eq:init-deltaPq, eq:init-expanded), computed in FP64 with second-order finite
+ * differences (one-sided next to non-periodic walls) and rounded to the storage type;
+ * then the first collision (eq:collision at level 0) so that s->pop[s->cur] holds f*^0,
+ * and u*^1 = u0 - (dt/2) v0 + dt v^0 (eq:trapezoid-u).
+ *   v0: device, 2 double planes, initial velocity.
+ *   u0: device, 2 double planes, initial displacement (F0 = I + grad u0), or NULL for 0.
+ *   r0: factor applied to the body force at t = 0 (B^0 = r0 b).
+ * Uses s->pop[1 - s->cur] as scratch.  Runs the CFL audit unless force_unstable. */
+lbm_status lbm_init(const lbm_params *p, lbm_state *s, const double *v0, const double *u0,
+                    double r0, void *stream);
+
+/* One time step (Sec. 3.7), level n -> n+1, fused in one pass over the grid: pull
+ * streaming (eq:streaming) from s->pop[s->cur], half-way reconstruction of every missing
+ * link with the data at t^{n+1/2} (eq:boundary-general; traction links first solve for
+ * F^b, Sec. 3.6), moments with B^{n+1} = r_np1 b (eq:moment-U), P(F) in registers,
+ * equilibrium (eq:feq), collision with trapezoidal forcing (eq:collision), store into
+ * s->pop[1 - s->cur], u* update.  Flips s->cur on success.
+ *   r_n, r_np1: body-force factors at levels n and n+1.
+ *   at_half: boundary data at t^{n+1/2}; may be NULL when all edges are periodic.
+ *   record: device, lbm_record_bytes(), receives U^{n+1} (v, F - I), or NULL. */
+lbm_status lbm_step(const lbm_params *p, lbm_state *s, int64_t n, double r_n, double r_np1,
+                    const lbm_edge_data *at_half, void *record, void *stream);
+
+/* Displacement at the current level n (eq:trapezoid-u): u^n = u*^{n+1} - (dt/2) v^n with
+ * v^n recovered from the stored post-collision populations (sum_q f* = U + (dt/2) B).
+ *   r_n: body-force factor at level n.  u_out: device, 2 double planes. */
+lbm_status lbm_displacement(const lbm_params *p, const lbm_state *s, double r_n, double *u_out,
+                            void *stream);
+
+/* State U^n = (v1, v2, F11-1, F12, F21, F22-1) of the current level, recovered from the
+ * stored populations.  U_out: device, 6 double planes. */
+lbm_status lbm_moments(const lbm_params *p, const lbm_state *s, double r_n, double *U_out,
+                       void *stream);
+
+/* FP64 reductions over the current level: out[0..1] sum of v, out[2..5] sum of F - I,
+ * out[6] energy sum(|v|^2/2 + W(F)) dx^2, out[7] min J, out[8] max |F - I| (Frobenius),
+ * out[9] max over nodes of the P-wave-bound ratio sqrt(lam_max(Q(n;F)))/c with the
+ * acoustic tensor of eq:acoustic-tensor-section2 scanned over 180 directions.
+ *   out: device, LBM_DIAG_COUNT doubles.  scratch: device, lbm_diag_scratch_bytes(). */
+lbm_status lbm_diagnostics(const lbm_params *p, const lbm_state *s, double r_n, double *out,
+                           void *scratch, void *stream);
+
+/* ------------------------------------------------------------------ adjoint */
+
+typedef struct {
+    void *adj[2];              /* device: two adjoint population buffers, lbm_adj_bytes() each */
+    int32_t cur;               /* buffer holding lambda^{m+1} = dL/df^{m+1} before a step */
+    double *g_mu, *g_lam;      /* device, 1 plane each: accumulated dL/dmu, dL/dlam, or NULL */
+    double *g_body;            /* device, 2 planes: accumulated dL/db, or NULL */
+    const int32_t *probe;      /* device: nprobe node indices (b*nx + a), distinct */
+    const double *ubar;        /* device: 2*nprobe values (component-major), dL/du^N at the probes */
+    int32_t nprobe;
+    int64_t nsteps;            /* N, the level at which u^N enters the loss */
+    void *aux;                 /* device, lbm_aux_bytes(): traction-wall adjoint staging */
+} lbm_adj_state;
+
+/* Bytes of one adjoint population buffer (24 planes of the compute type). */
+size_t lbm_adj_bytes(const lbm_params *p);
+
+/* One step of the hand-written adjoint of lbm_step, level m (reverse of eq:collision
+ * and eq:streaming with the Jacobian actions eq:jacobian-actions and eq:feq-derivative):
+ * from lambda^{m+1} in a->adj[a->cur] (zero-filled by the caller before m = N) and the
+ * record of U^m, it forms lambda*^m by pull (wall links: transposed rules of
+ * eq:boundary-general, traction links also through the boundary Newton solve by the
+ * implicit function theorem), dL/dU^m = omega sum_q (f^eq_q)'^T lambda*^m_q + probe and
+ * wall sources, lambda^m = (1 - omega) lambda*^m + dL/dU^m into a->adj[1 - a->cur], and
+ * adds this level's parts of dL/dmu, dL/dlam, dL/db.  Flips a->cur.
+ *   fwd: the forward state (parameters mu, lam, body; pop/ustar are not read).
+ *   r_m: body factor at level m.  at_half: boundary data at t^{m+1/2} (step m -> m+1).
+ *   record_m: device, U^m as written by lbm_step(record) or lbm_record_state. */
+lbm_status lbm_adjoint_step(const lbm_params *p, const lbm_state *fwd, lbm_adj_state *a,
+                            int64_t m, double r_m, const lbm_edge_data *at_half,
+                            const void *record_m, void *stream);
+
+/* Adjoint of lbm_init: from lambda^0 = dL/df(0) in a->adj[a->cur], writes dL/dv0 into
+ * g_v0 (device, 2 double planes; includes the direct term of u*^0 = u0 - (dt/2) v0) and
+ * adds the initialisation parts of dL/dmu, dL/dlam, dL/db.  v0, u0, r0 as given to
+ * lbm_init.  Uses a->adj[1 - a->cur] as scratch. */
+lbm_status lbm_adjoint_init(const lbm_params *p, const lbm_state *fwd, lbm_adj_state *a,
+                            const double *v0, const double *u0, double r0, double *g_v0,
+                            void *stream);
+
+/* Writes U^n of the current level in record format (6 planes of the compute type). */
+lbm_status lbm_record_state(const lbm_params *p, const lbm_state *s, double r_n, void *record,
+                            void *stream);
+
+/* ------------------------------------------------------------------ misc */
+
+const char *lbm_status_string(lbm_status st);
+/* Library version string. */
+const char *lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

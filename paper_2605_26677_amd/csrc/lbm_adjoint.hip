@@ -1,0 +1,480 @@
+// Hand-written adjoint of the D2Q4 x 6 step on gfx950.
+//
+// The adjoint buffer holds lambda^m = dL/df^m (pre-collision populations of level m) in
+// the compute type.  One adjoint step at level m, mirroring the forward step:
+//   lambda*^m_q(X) = lambda^{m+1}_q(X + c_q)          (transpose of eq:streaming, a pull)
+//   lambda*^m_{-d}(X0) = D lambda^{m+1}_d(X0)         (transpose of eq:boundary-general)
+//   g = dL/dU^m = omega sum_q (f^eq_q)'(U^m)^T lambda*^m_q (+ probe and traction sources)
+//   lambda^m_q = (1 - omega) lambda*^m_q + g           (transpose of eq:collision, eq:moment-U)
+// with (f^eq_q)' from eq:feq-derivative and the Jacobian actions of eq:jacobian-actions
+// through the tangent C = dP/dF (eq:stress-and-tangent), here used transposed:
+//   A_X^T l = (-l3, -l5, -(l1 C_11kB + l2 C_21kB)), A_Y^T l = (-l4, -l6, -(l1 C_12kB + l2 C_22kB)).
+// Parameter gradients accumulate in FP64 per node.
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+#include "lbm_kernel_util.hpp"
+
+namespace lbm {
+
+template <typename R>
+__device__ __forceinline__ R D_sign(int bc, int k) {
+    // velocity rule diag(-1,-1,1,1,1,1), traction rule diag(1,1,-1,-1,-1,-1)
+    const bool vrow = k < 2;
+    if (bc == LBM_VELOCITY) return vrow ? R(-1) : R(1);
+    return vrow ? R(1) : R(-1);
+}
+
+template <int ST, int LAW, bool WALLS, bool FIELDS>
+__global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
+    using R = typename Storage<ST>::real;
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny;
+    const int tpr = (nx + kBlock - 1) / kBlock;
+    const int tile = remap_tile(blockIdx.x, gridDim.x);
+    const int y = tile / tpr;
+    const int x = (tile - y * tpr) * kBlock + threadIdx.x;
+    if (x >= nx) return;
+    const int64_t st = cm.stride;
+    const int64_t n = int64_t(nx) * ny;
+    const R* __restrict__ src = (const R*)a.src;
+    R* __restrict__ dst = (R*)a.dst;
+    const int idx = y * nx + x;
+
+    // lambda*_q(X) pulls lambda_q from X + c_q: q0 from (x+1, y), q1 from (x, y+1),
+    // q2 from (x-1, y), q3 from (x, y-1).  Beyond a wall the slot is the outgoing link of
+    // that wall: q0 at XMAX, q1 at YMAX, q2 at XMIN, q3 at YMIN.
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+    bool w0 = false, w1 = false, w2 = false, w3 = false;
+    if (xp >= nx) { if (WALLS && !cm.periodic_x) { w0 = true; xp = x; } else xp = 0; }
+    if (yp >= ny) { if (WALLS && !cm.periodic_y) { w1 = true; yp = y; } else yp = 0; }
+    if (xm < 0) { if (WALLS && !cm.periodic_x) { w2 = true; xm = x; } else xm = nx - 1; }
+    if (ym < 0) { if (WALLS && !cm.periodic_y) { w3 = true; ym = y; } else ym = ny - 1; }
+    const int sidx[4] = {y * nx + xp, yp * nx + x, y * nx + xm, ym * nx + x};
+    R l[4][6];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) l[q][k] = src[(6 * q + k) * st + sidx[q]];
+    if constexpr (WALLS) {
+        // outgoing slot od of edge e takes D_e lambda_d(own node), d the missing direction
+        if (w0) for (int k = 0; k < 6; ++k) l[0][k] = D_sign<R>(cm.bc[LBM_XMAX], k) * src[(12 + k) * st + idx];
+        if (w2) for (int k = 0; k < 6; ++k) l[2][k] = D_sign<R>(cm.bc[LBM_XMIN], k) * src[(0 + k) * st + idx];
+        if (w1) for (int k = 0; k < 6; ++k) l[1][k] = D_sign<R>(cm.bc[LBM_YMAX], k) * src[(18 + k) * st + idx];
+        if (w3) for (int k = 0; k < 6; ++k) l[3][k] = D_sign<R>(cm.bc[LBM_YMIN], k) * src[(6 + k) * st + idx];
+    }
+
+    const R* rec = (const R*)a.record;
+    R ft[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ft[k] = rec[(2 + k) * n + idx];
+    R mu, lam;
+    params_at<FIELDS, R>(cm, idx, mu, lam);
+    R C[16];
+    tangent<R, LAW, true>(ft, mu, lam, C);
+
+    R s6[6], dxl[6], dyl[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        s6[k] = l[0][k] + l[1][k] + l[2][k] + l[3][k];
+        dxl[k] = l[0][k] - l[2][k];
+        dyl[k] = l[1][k] - l[3][k];
+    }
+    R AT[6];
+    AT[0] = -dxl[2] - dyl[3];
+    AT[1] = -dxl[4] - dyl[5];
+#pragma unroll
+    for (int kB = 0; kB < 4; ++kB)
+        AT[2 + kB] = -(dxl[0] * C[kB] + dxl[1] * C[8 + kB]) - (dyl[0] * C[4 + kB] + dyl[1] * C[12 + kB]);
+    const R om = R(cm.omega);
+    const R c2 = R(2.0 / cm.c);
+    R gU[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gU[k] = om * R(0.25) * (s6[k] + c2 * AT[k]);
+    const R omc = R(1) - om;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) dst[(6 * q + k) * st + idx] = omc * l[q][k] + gU[k];
+
+    // parameter gradients of this level's collision
+    const R hc = R(0.5 / cm.c);
+    if (a.g_mu || a.g_lam) {
+        R Pm[4], Pl[4];
+        piola_partials<R, LAW, true>(ft, Pm, Pl);
+        if (a.g_mu)
+            a.g_mu[idx] += double(om * hc * -(dxl[0] * Pm[0] + dxl[1] * Pm[2] + dyl[0] * Pm[1] + dyl[1] * Pm[3]));
+        if (a.g_lam)
+            a.g_lam[idx] += double(om * hc * -(dxl[0] * Pl[0] + dxl[1] * Pl[2] + dyl[0] * Pl[1] + dyl[1] * Pl[3]));
+    }
+    if (a.g_body) {
+        const double hdt = 0.5 * cm.dt, srcw = cm.dt * (2.0 - cm.omega) * 0.125;
+        a.g_body[idx] += a.r_m * (hdt * double(gU[0]) + srcw * double(s6[0]));
+        a.g_body[n + idx] += a.r_m * (hdt * double(gU[1]) + srcw * double(s6[1]));
+    }
+}
+
+// Traction edge, stage 1 (one thread per wall link): F^b is rebuilt from the record of
+// U^m exactly as in the forward step, then dL/dF^b = lambda^{m+1}_d(X0)_F / 2 is carried
+// through the Newton solve by the implicit function theorem: with y = J^{-T} (dL/da),
+// the tangential column receives -N_A y_i C_iAjB and mu, lam receive -N_A y_i dP_iA/dp.
+template <int ST, int LAW, bool FIELDS>
+__global__ void __launch_bounds__(kBlock) adj_traction_kernel(AdjArgs a) {
+    using R = typename Storage<ST>::real;
+    const Common& cm = a.cm;
+    const int e = a.edge;
+    const EdgeGeom G = edge_geom(e);
+    const int L = (G.A == 0) ? cm.ny : cm.nx;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= L) return;
+    const bool per_t = (G.A == 0) ? cm.periodic_y : cm.periodic_x;
+    const int A = G.A, Bx = 1 - G.A;
+    const int64_t n = int64_t(cm.nx) * cm.ny;
+    const R* rec = (const R*)a.record;
+    const R hdt = R(0.5 * cm.dt);
+    const R inv2h = R(1.0 / (2.0 * cm.dx));
+    const Stencil sten = tangential_stencil(s, L, per_t);
+    R Ghat[2][2], Fa[2][2];
+    for (int r = 0; r < 2; ++r) {
+        R Us[3][6];
+        for (int j = 0; j < 3; ++j) {
+            const int id = edge_node(G, cm.nx, cm.ny, r, sten.p[j]);
+            for (int k = 0; k < 6; ++k) Us[j][k] = rec[k * n + id];
+        }
+        for (int k = 0; k < 2; ++k) {
+            R dv = R(0);
+            for (int j = 0; j < 3; ++j) dv += R(sten.w[j]) * Us[j][k];
+            Ghat[r][k] = Us[sten.self][2 + 2 * k + Bx] + hdt * dv * inv2h;
+            Fa[r][k] = Us[sten.self][2 + 2 * k + A];
+        }
+    }
+    R tang[2], acol[2], Tv[2];
+    for (int k = 0; k < 2; ++k) {
+        tang[k] = R(1.5) * Ghat[0][k] - R(0.5) * Ghat[1][k];
+        acol[k] = R(1.5) * Fa[0][k] - R(0.5) * Fa[1][k];
+        Tv[k] = edge_value<R>(a.ed, e, k, s, L);
+    }
+    const int id0 = edge_node(G, cm.nx, cm.ny, 0, s);
+    R mu, lam;
+    params_at<FIELDS, R>(cm, id0, mu, lam);
+    newton_column<R, LAW, true>(A, R(G.NA), tang, Tv, mu, lam, acol, cm.newton_max_iter, R(cm.newton_tol));
+    R f[4];
+    f[A] = acol[0]; f[2 + A] = acol[1];
+    f[Bx] = tang[0]; f[2 + Bx] = tang[1];
+    const R* src = (const R*)a.src;
+    R Fbar[4];
+    for (int k = 0; k < 4; ++k) Fbar[k] = R(0.5) * src[(6 * G.d + 2 + k) * cm.stride + id0];
+    R C[16];
+    tangent<R, LAW, true>(f, mu, lam, C);
+    const R NA = R(G.NA);
+    const R j00 = NA * C[4 * A + A], j01 = NA * C[4 * A + 2 + A];
+    const R j10 = NA * C[8 + 4 * A + A], j11 = NA * C[8 + 4 * A + 2 + A];
+    const R det = j00 * j11 - j01 * j10;
+    const R ab0 = Fbar[A], ab1 = Fbar[2 + A];
+    // y = J^{-T} abar
+    const R y0 = (j11 * ab0 - j10 * ab1) / det;
+    const R y1 = (-j01 * ab0 + j00 * ab1) / det;
+    R tbar[2];
+    for (int jj = 0; jj < 2; ++jj)
+        tbar[jj] = Fbar[2 * jj + Bx] - NA * (y0 * C[4 * A + 2 * jj + Bx] + y1 * C[8 + 4 * A + 2 * jj + Bx]);
+    if (a.g_mu || a.g_lam) {
+        R Pm[4], Pl[4];
+        piola_partials<R, LAW, true>(f, Pm, Pl);
+        if (a.g_mu) a.g_mu[id0] += double(-NA * (y0 * Pm[A] + y1 * Pm[2 + A]));
+        if (a.g_lam) a.g_lam[id0] += double(-NA * (y0 * Pl[A] + y1 * Pl[2 + A]));
+    }
+    int off[4], len[4];
+    edge_offsets(cm.nx, cm.ny, off, len);
+    R* aux = (R*)a.aux + 2 * (int64_t)(off[e] + s);
+    aux[0] = tbar[0];
+    aux[1] = tbar[1];
+}
+
+// Traction edge, stage 2 (one thread per node of the wall row and first interior row):
+// transpose of the extrapolation 3/2 G(X0) - 1/2 G(X1) and of G = F_{.B} + (dt/2) d_B v,
+// giving dL/dU^m at those nodes; it enters lambda^m_q for every q and the body gradient.
+template <int ST>
+__global__ void __launch_bounds__(kBlock) adj_traction_scatter_kernel(AdjArgs a) {
+    using R = typename Storage<ST>::real;
+    const Common& cm = a.cm;
+    const int e = a.edge;
+    const EdgeGeom G = edge_geom(e);
+    const int L = (G.A == 0) ? cm.ny : cm.nx;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * L) return;
+    const int r = t / L, s = t - r * L;
+    const bool per_t = (G.A == 0) ? cm.periodic_y : cm.periodic_x;
+    const int Bx = 1 - G.A;
+    const int64_t n = int64_t(cm.nx) * cm.ny;
+    int off[4], len[4];
+    edge_offsets(cm.nx, cm.ny, off, len);
+    const R* aux = (const R*)a.aux + 2 * (int64_t)off[e];
+    const R wr = (r == 0) ? R(1.5) : R(-0.5);
+    const R hdt = R(0.5 * cm.dt);
+    const R inv2h = R(1.0 / (2.0 * cm.dx));
+    R E[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    for (int k = 0; k < 2; ++k) {
+        E[2 + 2 * k + Bx] = wr * aux[2 * s + k];
+        E[k] = hdt * wr * fd_along_T<R>([&](int s2) { return aux[2 * s2 + k]; }, s, L, per_t, inv2h);
+    }
+    const int id = edge_node(G, cm.nx, cm.ny, r, s);
+    R* dst = (R*)a.dst;
+    for (int q = 0; q < 4; ++q)
+        for (int k = 0; k < 6; ++k) dst[(6 * q + k) * cm.stride + id] += E[k];
+    if (a.g_body) {
+        a.g_body[id] += a.r_m * double(hdt * E[0]);
+        a.g_body[n + id] += a.r_m * double(hdt * E[1]);
+    }
+}
+
+// Probe source of the displacement loss at level m: u^N = u0 - (dt/2) v0 + dt sum_{m<N} v^m
+// + (dt/2) v^N (eq:trapezoid-u), so dL/dv^m = weight * ubar with weight dt (m < N) or
+// dt/2 (m = N).  One thread walks the probes in order, so repeated cells accumulate.
+template <int ST>
+__global__ void adj_probe_kernel(AdjArgs a) {
+    using R = typename Storage<ST>::real;
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const Common& cm = a.cm;
+    const int64_t n = int64_t(cm.nx) * cm.ny;
+    R* dst = (R*)a.dst;
+    const double hdt = 0.5 * cm.dt;
+    for (int p = 0; p < a.nprobe; ++p) {
+        const int id = a.probe[p];
+        for (int k = 0; k < 2; ++k) {
+            const double src = a.probe_weight * a.ubar[k * a.nprobe + p];
+            for (int q = 0; q < 4; ++q) dst[(6 * q + k) * cm.stride + id] += R(src);
+            if (a.g_body) a.g_body[k * n + id] += a.r_m * hdt * src;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- adjoint of the init
+
+// Per node: the transposes of eq:init-expanded, eq:init-deltaPq and eq:init-Zq-components
+// (F0 held fixed).  Writes the seeds (dL/dv0 direct, dL/d(d_X v0), dL/d(d_Y v0)) as
+// scratch planes 6..11 and adds the parameter and body parts.
+template <int ST, int LAW, bool FIELDS>
+__global__ void __launch_bounds__(kBlock) adj_init_kernel(AdjInitArgs a) {
+    using R = typename Storage<ST>::real;
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny;
+    const int64_t n = int64_t(nx) * ny;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int y = int(idx / nx), x = int(idx - int64_t(y) * nx);
+    double* scr = (double*)a.scratch;
+    const double c = cm.c, hdt = 0.5 * cm.dt;
+    const double inv2h = 1.0 / (2.0 * cm.dx);
+    double U0[6], dX[6], dY[6];
+    for (int k = 0; k < 6; ++k) {
+        const double* pl = scr + k * n;
+        U0[k] = pl[idx];
+        dX[k] = fd_along<double>([&](int s) { return pl[int64_t(y) * nx + s]; }, x, nx, cm.periodic_x, inv2h);
+        dY[k] = fd_along<double>([&](int s) { return pl[int64_t(s) * nx + x]; }, y, ny, cm.periodic_y, inv2h);
+    }
+    double mu, lam;
+    params_at<FIELDS, double>(cm, (int)idx, mu, lam);
+    double C[16], Cm[16], Cl[16], Pm[4], Pl[4];
+    tangent<double, LAW, true>(&U0[2], mu, lam, C);
+    tangent<double, LAW, true>(&U0[2], 1.0, 0.0, Cm);
+    tangent<double, LAW, true>(&U0[2], 0.0, 1.0, Cl);
+    piola_partials<double, LAW, true>(&U0[2], Pm, Pl);
+    const R* l0 = (const R*)a.lam0;
+    double vb[2] = {0, 0}, vXb[2] = {0, 0}, vYb[2] = {0, 0}, Bb[2] = {0, 0};
+    double dPXb[4] = {0, 0, 0, 0}, dPYb[4] = {0, 0, 0, 0};
+    double gmu = 0.0, glam = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        const double i = dir_i(q), j = dir_j(q);
+        double ell[6];
+        for (int k = 0; k < 6; ++k) ell[k] = double(l0[(6 * q + k) * cm.stride + idx]);
+        // equilibrium part f^eq_q(U0)
+        vb[0] += 0.25 * (ell[0] - (2.0 / c) * (i * ell[2] + j * ell[3]));
+        vb[1] += 0.25 * (ell[1] - (2.0 / c) * (i * ell[4] + j * ell[5]));
+        gmu += (0.5 / c) * -(i * (ell[0] * Pm[0] + ell[1] * Pm[2]) + j * (ell[0] * Pm[1] + ell[1] * Pm[3]));
+        glam += (0.5 / c) * -(i * (ell[0] * Pl[0] + ell[1] * Pl[2]) + j * (ell[0] * Pl[1] + ell[1] * Pl[3]));
+        // correction part -(dt/2) D_q f^eq
+        double w[6];
+        for (int k = 0; k < 6; ++k) w[k] = -hdt * ell[k];
+        const double Z1b = 0.25 * (w[0] - (2.0 * i / c) * w[2] - (2.0 * j / c) * w[3]);
+        const double Z2b = 0.25 * (w[1] - (2.0 * i / c) * w[4] - (2.0 * j / c) * w[5]);
+        const double dPb[4] = {-(0.5 / c) * i * w[0], -(0.5 / c) * j * w[0], -(0.5 / c) * i * w[1],
+                               -(0.5 / c) * j * w[1]};
+        double ZF[4];
+        ZF[0] = dX[0] + c * (i * dX[2] + j * dY[2]);
+        ZF[1] = dY[0] + c * (i * dX[3] + j * dY[3]);
+        ZF[2] = dX[1] + c * (i * dX[4] + j * dY[4]);
+        ZF[3] = dY[1] + c * (i * dX[5] + j * dY[5]);
+        double ZFb[4];
+        for (int kB = 0; kB < 4; ++kB) {
+            double sacc = 0.25 * w[2 + kB];
+            for (int iA = 0; iA < 4; ++iA) sacc += C[4 * iA + kB] * dPb[iA];
+            ZFb[kB] = sacc;
+        }
+        for (int iA = 0; iA < 4; ++iA) {
+            double sm = 0.0, sl = 0.0;
+            for (int kB = 0; kB < 4; ++kB) {
+                sm += Cm[4 * iA + kB] * ZF[kB];
+                sl += Cl[4 * iA + kB] * ZF[kB];
+            }
+            gmu += dPb[iA] * sm;
+            glam += dPb[iA] * sl;
+        }
+        Bb[0] += Z1b;
+        Bb[1] += Z2b;
+        dPXb[0] += Z1b;
+        dPYb[1] += Z1b;
+        dPXb[2] += Z2b;
+        dPYb[3] += Z2b;
+        vXb[0] += c * i * Z1b + ZFb[0];
+        vYb[0] += c * j * Z1b + ZFb[1];
+        vXb[1] += c * i * Z2b + ZFb[2];
+        vYb[1] += c * j * Z2b + ZFb[3];
+    }
+    for (int iA = 0; iA < 4; ++iA) {
+        double smx = 0.0, smy = 0.0, slx = 0.0, sly = 0.0;
+        for (int kB = 0; kB < 4; ++kB) {
+            smx += Cm[4 * iA + kB] * dX[2 + kB];
+            smy += Cm[4 * iA + kB] * dY[2 + kB];
+            slx += Cl[4 * iA + kB] * dX[2 + kB];
+            sly += Cl[4 * iA + kB] * dY[2 + kB];
+        }
+        gmu += dPXb[iA] * smx + dPYb[iA] * smy;
+        glam += dPXb[iA] * slx + dPYb[iA] * sly;
+    }
+    if (a.g_mu) a.g_mu[idx] += gmu;
+    if (a.g_lam) a.g_lam[idx] += glam;
+    if (a.g_body) {
+        a.g_body[idx] += a.r0 * Bb[0];
+        a.g_body[n + idx] += a.r0 * Bb[1];
+    }
+    scr[6 * n + idx] = vb[0];
+    scr[7 * n + idx] = vb[1];
+    scr[8 * n + idx] = vXb[0];
+    scr[9 * n + idx] = vXb[1];
+    scr[10 * n + idx] = vYb[0];
+    scr[11 * n + idx] = vYb[1];
+}
+
+// dL/dv0 = direct seed + (finite-difference operators)^T applied to the gradient seeds.
+__global__ void __launch_bounds__(kBlock) adj_init_gather_kernel(AdjInitArgs a) {
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny;
+    const int64_t n = int64_t(nx) * ny;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int y = int(idx / nx), x = int(idx - int64_t(y) * nx);
+    const double* scr = (const double*)a.scratch;
+    const double inv2h = 1.0 / (2.0 * cm.dx);
+    for (int k = 0; k < 2; ++k) {
+        const double* pX = scr + (8 + k) * n;
+        const double* pY = scr + (10 + k) * n;
+        double v = scr[(6 + k) * n + idx];
+        v += fd_along_T<double>([&](int s) { return pX[int64_t(y) * nx + s]; }, x, nx, cm.periodic_x, inv2h);
+        v += fd_along_T<double>([&](int s) { return pY[int64_t(s) * nx + x]; }, y, ny, cm.periodic_y, inv2h);
+        a.g_v0[k * n + idx] = v;
+    }
+}
+
+// u*^0 = u0 - (dt/2) v0 contributes -(dt/2) ubar at the probes.
+__global__ void adj_init_probe_kernel(AdjInitArgs a) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int64_t n = int64_t(a.cm.nx) * a.cm.ny;
+    const double hdt = 0.5 * a.cm.dt;
+    for (int p = 0; p < a.nprobe; ++p)
+        for (int k = 0; k < 2; ++k) a.g_v0[k * n + a.probe[p]] -= hdt * a.ubar[k * a.nprobe + p];
+}
+
+// ---------------------------------------------------------------- dispatch
+
+static inline unsigned nblk(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+template <int ST, int LAW>
+static hipError_t adjoint_st_law(const AdjArgs& a0, hipStream_t s) {
+    AdjArgs a = a0;
+    const bool walls = !(a.cm.periodic_x && a.cm.periodic_y);
+    const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
+    // stage 1 of every traction edge reads lambda^{m+1} before the bulk kernel writes lambda^m
+    for (int e = 0; e < 4; ++e) {
+        if (a.cm.bc[e] != LBM_TRACTION) continue;
+        a.edge = e;
+        const int L = (e == LBM_XMIN || e == LBM_XMAX) ? a.cm.ny : a.cm.nx;
+        int off[4], len[4];
+        edge_offsets(a.cm.nx, a.cm.ny, off, len);
+        // each edge stages its tbar values in its own slice of aux
+        if (fields) hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, true>), dim3(nblk(L)), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, false>), dim3(nblk(L)), dim3(kBlock), 0, s, a);
+    }
+    const int tpr = (a.cm.nx + kBlock - 1) / kBlock;
+    const dim3 grid(unsigned(int64_t(tpr) * a.cm.ny));
+    if (walls) {
+        if (fields) hipLaunchKernelGGL((adjoint_kernel<ST, LAW, true, true>), grid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((adjoint_kernel<ST, LAW, true, false>), grid, dim3(kBlock), 0, s, a);
+    } else {
+        if (fields) hipLaunchKernelGGL((adjoint_kernel<ST, LAW, false, true>), grid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((adjoint_kernel<ST, LAW, false, false>), grid, dim3(kBlock), 0, s, a);
+    }
+    // stage 2, one edge at a time (corner nodes belong to two edges)
+    for (int e = 0; e < 4; ++e) {
+        if (a.cm.bc[e] != LBM_TRACTION) continue;
+        a.edge = e;
+        const int L = (e == LBM_XMIN || e == LBM_XMAX) ? a.cm.ny : a.cm.nx;
+        hipLaunchKernelGGL((adj_traction_scatter_kernel<ST>), dim3(nblk(2 * L)), dim3(kBlock), 0, s, a);
+    }
+    if (a.nprobe > 0 && a.probe_weight != 0.0) hipLaunchKernelGGL((adj_probe_kernel<ST>), dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t adjoint_st(const AdjArgs& a, hipStream_t s) {
+    switch (a.cm.material) {
+        case LBM_LOGNH: return adjoint_st_law<ST, LBM_LOGNH>(a, s);
+        case LBM_NH: return adjoint_st_law<ST, LBM_NH>(a, s);
+        default: return adjoint_st_law<ST, LBM_SVK>(a, s);
+    }
+}
+
+hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s) {
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: return adjoint_st<LBM_F32_SHIFTED>(a, s);
+        case LBM_F16_SHIFTED: return adjoint_st<LBM_F16_SHIFTED>(a, s);
+        default: return adjoint_st<LBM_F64_PLAIN>(a, s);
+    }
+}
+
+template <int ST, int LAW>
+static void adj_init_st_law(const AdjInitArgs& a, hipStream_t s, dim3 grid) {
+    const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
+    if (fields) hipLaunchKernelGGL((adj_init_kernel<ST, LAW, true>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((adj_init_kernel<ST, LAW, false>), grid, dim3(kBlock), 0, s, a);
+}
+
+template <int ST>
+static void adj_init_st(const AdjInitArgs& a, hipStream_t s, dim3 grid) {
+    switch (a.cm.material) {
+        case LBM_LOGNH: adj_init_st_law<ST, LBM_LOGNH>(a, s, grid); break;
+        case LBM_NH: adj_init_st_law<ST, LBM_NH>(a, s, grid); break;
+        default: adj_init_st_law<ST, LBM_SVK>(a, s, grid); break;
+    }
+}
+
+hipError_t launch_adjoint_init(const AdjInitArgs& a, hipStream_t s) {
+    const dim3 grid(nblk(int64_t(a.cm.nx) * a.cm.ny));
+    // U0 = (v0, grad u0) into scratch planes 0..5, as lbm_init builds it
+    InitArgs ia{};
+    ia.cm = a.cm;
+    ia.v0 = a.v0;
+    ia.u0 = a.u0;
+    ia.r0 = a.r0;
+    ia.scratch = a.scratch;
+    hipError_t err = launch_init_state(ia, s);
+    if (err != hipSuccess) return err;
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: adj_init_st<LBM_F32_SHIFTED>(a, s, grid); break;
+        case LBM_F16_SHIFTED: adj_init_st<LBM_F16_SHIFTED>(a, s, grid); break;
+        default: adj_init_st<LBM_F64_PLAIN>(a, s, grid); break;
+    }
+    hipLaunchKernelGGL(adj_init_gather_kernel, grid, dim3(kBlock), 0, s, a);
+    if (a.nprobe > 0) hipLaunchKernelGGL(adj_init_probe_kernel, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

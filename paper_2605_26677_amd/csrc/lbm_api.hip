@@ -1,0 +1,302 @@
+// C ABI of the library (declared in include/lbm.h): argument validation, buffer sizes and
+// the launch sequence of each entry point.  No allocation, no synchronisation.
+#include <math.h>
+#include <string.h>
+
+#include "lbm_internal.hpp"
+
+using namespace lbm;
+
+namespace {
+
+bool any_wall(const lbm_params* p) {
+    for (int e = 0; e < 4; ++e)
+        if (p->bc[e] != LBM_PERIODIC) return true;
+    return false;
+}
+
+bool has_traction(const lbm_params* p) {
+    for (int e = 0; e < 4; ++e)
+        if (p->bc[e] == LBM_TRACTION) return true;
+    return false;
+}
+
+size_t real_size(const lbm_params* p) { return p->storage == LBM_F64_PLAIN ? 8 : 4; }
+
+size_t pop_elem_size(const lbm_params* p) {
+    return p->storage == LBM_F64_PLAIN ? 8 : (p->storage == LBM_F16_SHIFTED ? 2 : 4);
+}
+
+Common make_common(const lbm_params* p, const lbm_state* s) {
+    Common cm{};
+    cm.nx = p->nx;
+    cm.ny = p->ny;
+    cm.stride = (int64_t)lbm_plane_stride(p);
+    for (int e = 0; e < 4; ++e) cm.bc[e] = p->bc[e];
+    cm.periodic_x = p->bc[LBM_XMIN] == LBM_PERIODIC;
+    cm.periodic_y = p->bc[LBM_YMIN] == LBM_PERIODIC;
+    cm.material = p->material;
+    cm.storage = p->storage;
+    cm.dx = p->dx;
+    cm.c = p->c;
+    cm.omega = p->omega;
+    cm.dt = p->dx / p->c;
+    cm.newton_max_iter = p->newton_max_iter > 0 ? p->newton_max_iter : 8;
+    cm.newton_tol = p->newton_tol > 0 ? p->newton_tol : (p->storage == LBM_F64_PLAIN ? 1e-14 : 1e-6);
+    if (s) {
+        cm.mu0 = s->mu0;
+        cm.lam0 = s->lam0;
+        cm.b0[0] = s->b0[0];
+        cm.b0[1] = s->b0[1];
+        cm.mu = s->mu;
+        cm.lam = s->lam;
+        cm.body = s->body;
+        cm.fault = s->fault;
+    }
+    return cm;
+}
+
+EdgeData make_edges(const lbm_edge_data* ed) {
+    EdgeData out{};
+    if (ed) {
+        for (int e = 0; e < 4; ++e) {
+            out.value[e][0] = ed->value[e][0];
+            out.value[e][1] = ed->value[e][1];
+            out.field[e] = ed->field[e];
+        }
+    }
+    return out;
+}
+
+lbm_status check_state(const lbm_params* p, const lbm_state* s) {
+    if (!s || !s->pop[0] || !s->pop[1] || !s->ustar || !s->fault) return LBM_ERR_ARG;
+    if (s->cur != 0 && s->cur != 1) return LBM_ERR_ARG;
+    if (has_traction(p) && !s->aux) return LBM_ERR_ARG;
+    return LBM_OK;
+}
+
+lbm_status launched(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_ERR_LAUNCH; }
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_plane_stride(const lbm_params* p) {
+    // round up to 64 elements, and keep planes off a common large power-of-two alignment
+    // so that the 24 streams of one pass do not start on the same HBM channel
+    size_t n = (size_t)p->nx * (size_t)p->ny;
+    size_t st = (n + 63) / 64 * 64;
+    if (st % 4096 == 0) st += 64;
+    return st;
+}
+
+size_t lbm_pop_bytes(const lbm_params* p) { return 24 * lbm_plane_stride(p) * pop_elem_size(p); }
+
+size_t lbm_ustar_bytes(const lbm_params* p) {
+    const size_t n = (size_t)p->nx * (size_t)p->ny;
+    return p->storage == LBM_F64_PLAIN ? 2 * n * 8 : 4 * n * 4;
+}
+
+size_t lbm_aux_bytes(const lbm_params* p) { return (size_t)(2 * p->nx + 2 * p->ny) * 4 * 8; }
+
+size_t lbm_record_bytes(const lbm_params* p) {
+    return 6 * (size_t)p->nx * (size_t)p->ny * real_size(p);
+}
+
+size_t lbm_adj_bytes(const lbm_params* p) { return 24 * lbm_plane_stride(p) * real_size(p); }
+
+size_t lbm_diag_scratch_bytes(const lbm_params* p) {
+    (void)p;
+    return (size_t)kDiagBlocks * LBM_DIAG_COUNT * sizeof(double);
+}
+
+lbm_status lbm_check_params(const lbm_params* p) {
+    if (!p) return LBM_ERR_ARG;
+    if (p->nx < 3 || p->ny < 3) return LBM_ERR_ARG;
+    if ((int64_t)p->nx * (int64_t)p->ny >= ((int64_t)1 << 31)) return LBM_ERR_ARG;
+    if (p->material < LBM_LOGNH || p->material > LBM_SVK) return LBM_ERR_ARG;
+    if (p->storage < LBM_F32_SHIFTED || p->storage > LBM_F64_PLAIN) return LBM_ERR_ARG;
+    for (int e = 0; e < 4; ++e)
+        if (p->bc[e] < LBM_PERIODIC || p->bc[e] > LBM_TRACTION) return LBM_ERR_ARG;
+    if ((p->bc[LBM_XMIN] == LBM_PERIODIC) != (p->bc[LBM_XMAX] == LBM_PERIODIC)) return LBM_ERR_ARG;
+    if ((p->bc[LBM_YMIN] == LBM_PERIODIC) != (p->bc[LBM_YMAX] == LBM_PERIODIC)) return LBM_ERR_ARG;
+    if (any_wall(p) && (p->nx < 4 || p->ny < 4)) return LBM_ERR_ARG;
+    if (!(p->dx > 0) || !(p->c > 0) || !(p->omega > 0) || !(p->omega <= 2.0)) return LBM_ERR_ARG;
+    return LBM_OK;
+}
+
+lbm_status lbm_check_cfl(const lbm_params* p, double mu_max, double lam_max) {
+    if (!p || !(p->c > 0)) return LBM_ERR_ARG;
+    const double cp = sqrt(fmax(lam_max + 2.0 * mu_max, 0.0));
+    return (cp / p->c > 0.5) ? LBM_ERR_CFL : LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_params* p, lbm_state* s, const double* v0, const double* u0, double r0,
+                    void* stream) {
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if ((st = check_state(p, s)) != LBM_OK) return st;
+    if (!v0) return LBM_ERR_ARG;
+    if (!p->force_unstable) {
+        const double mu = s->mu ? s->mu_max : s->mu0;
+        const double lam = s->lam ? s->lam_max : s->lam0;
+        if ((st = lbm_check_cfl(p, mu, lam)) != LBM_OK) return st;
+    }
+    InitArgs a{};
+    a.cm = make_common(p, s);
+    a.v0 = v0;
+    a.u0 = u0;
+    a.r0 = r0;
+    a.scratch = s->pop[1 - s->cur];
+    a.dst = s->pop[s->cur];
+    a.ustar = s->ustar;
+    return launched(launch_init(a, (hipStream_t)stream));
+}
+
+lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, double r_np1,
+                    const lbm_edge_data* at_half, void* record, void* stream) {
+    (void)n;
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if ((st = check_state(p, s)) != LBM_OK) return st;
+    const hipStream_t hs = (hipStream_t)stream;
+    const Common cm = make_common(p, s);
+    const EdgeData ed = make_edges(at_half);
+    for (int e = 0; e < 4; ++e) {
+        if (p->bc[e] != LBM_TRACTION) continue;
+        TractionArgs t{};
+        t.cm = cm;
+        t.pop = s->pop[s->cur];
+        t.aux = s->aux;
+        t.r_n = r_n;
+        t.ed = ed;
+        t.edge = e;
+        if (launch_traction(t, hs) != hipSuccess) return LBM_ERR_LAUNCH;
+    }
+    StepArgs a{};
+    a.cm = cm;
+    a.src = s->pop[s->cur];
+    a.dst = s->pop[1 - s->cur];
+    a.ustar = s->ustar;
+    a.aux = s->aux;
+    a.record = record;
+    a.r_np1 = r_np1;
+    a.ed = ed;
+    if (launch_step(a, hs) != hipSuccess) return LBM_ERR_LAUNCH;
+    s->cur = 1 - s->cur;
+    return LBM_OK;
+}
+
+static lbm_status recover_common(const lbm_params* p, const lbm_state* s, double r_n, void* out,
+                                 RecoverArgs& a) {
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if ((st = check_state(p, s)) != LBM_OK) return st;
+    if (!out) return LBM_ERR_ARG;
+    a = RecoverArgs{};
+    a.cm = make_common(p, s);
+    a.pop = s->pop[s->cur];
+    a.ustar = s->ustar;
+    a.r_n = r_n;
+    a.out = out;
+    return LBM_OK;
+}
+
+lbm_status lbm_displacement(const lbm_params* p, const lbm_state* s, double r_n, double* u_out, void* stream) {
+    RecoverArgs a;
+    lbm_status st = recover_common(p, s, r_n, u_out, a);
+    if (st != LBM_OK) return st;
+    return launched(launch_displacement(a, (hipStream_t)stream));
+}
+
+lbm_status lbm_moments(const lbm_params* p, const lbm_state* s, double r_n, double* U_out, void* stream) {
+    RecoverArgs a;
+    lbm_status st = recover_common(p, s, r_n, U_out, a);
+    if (st != LBM_OK) return st;
+    return launched(launch_moments(a, (hipStream_t)stream));
+}
+
+lbm_status lbm_record_state(const lbm_params* p, const lbm_state* s, double r_n, void* record, void* stream) {
+    RecoverArgs a;
+    lbm_status st = recover_common(p, s, r_n, record, a);
+    if (st != LBM_OK) return st;
+    return launched(launch_record(a, (hipStream_t)stream));
+}
+
+lbm_status lbm_diagnostics(const lbm_params* p, const lbm_state* s, double r_n, double* out, void* scratch,
+                           void* stream) {
+    RecoverArgs a;
+    lbm_status st = recover_common(p, s, r_n, out, a);
+    if (st != LBM_OK) return st;
+    if (!scratch) return LBM_ERR_ARG;
+    a.scratch = scratch;
+    return launched(launch_diagnostics(a, (hipStream_t)stream));
+}
+
+lbm_status lbm_adjoint_step(const lbm_params* p, const lbm_state* fwd, lbm_adj_state* adj, int64_t m,
+                            double r_m, const lbm_edge_data* at_half, const void* record_m, void* stream) {
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if (!fwd || !adj || !adj->adj[0] || !adj->adj[1] || !record_m) return LBM_ERR_ARG;
+    if (adj->cur != 0 && adj->cur != 1) return LBM_ERR_ARG;
+    if (has_traction(p) && !adj->aux) return LBM_ERR_ARG;
+    if (adj->nprobe < 0 || (adj->nprobe > 0 && (!adj->probe || !adj->ubar))) return LBM_ERR_ARG;
+    if (m < 0 || m > adj->nsteps) return LBM_ERR_ARG;
+    AdjArgs a{};
+    a.cm = make_common(p, fwd);
+    a.src = adj->adj[adj->cur];
+    a.dst = adj->adj[1 - adj->cur];
+    a.record = record_m;
+    a.g_mu = adj->g_mu;
+    a.g_lam = adj->g_lam;
+    a.g_body = adj->g_body;
+    a.aux = adj->aux;
+    a.r_m = r_m;
+    a.ed = make_edges(at_half);
+    a.probe = adj->probe;
+    a.ubar = adj->ubar;
+    a.nprobe = adj->nprobe;
+    a.probe_weight = (m == adj->nsteps ? 0.5 : 1.0) * a.cm.dt;
+    if (launch_adjoint(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
+    adj->cur = 1 - adj->cur;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_init(const lbm_params* p, const lbm_state* fwd, lbm_adj_state* adj, const double* v0,
+                            const double* u0, double r0, double* g_v0, void* stream) {
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if (!fwd || !adj || !adj->adj[0] || !adj->adj[1] || !v0 || !g_v0) return LBM_ERR_ARG;
+    if (adj->cur != 0 && adj->cur != 1) return LBM_ERR_ARG;
+    if (adj->nprobe < 0 || (adj->nprobe > 0 && (!adj->probe || !adj->ubar))) return LBM_ERR_ARG;
+    AdjInitArgs a{};
+    a.cm = make_common(p, fwd);
+    a.lam0 = adj->adj[adj->cur];
+    a.scratch = adj->adj[1 - adj->cur];
+    a.v0 = v0;
+    a.u0 = u0;
+    a.r0 = r0;
+    a.g_mu = adj->g_mu;
+    a.g_lam = adj->g_lam;
+    a.g_body = adj->g_body;
+    a.g_v0 = g_v0;
+    a.probe = adj->probe;
+    a.ubar = adj->ubar;
+    a.nprobe = adj->nprobe;
+    return launched(launch_adjoint_init(a, (hipStream_t)stream));
+}
+
+const char* lbm_status_string(lbm_status st) {
+    switch (st) {
+        case LBM_OK: return "ok";
+        case LBM_ERR_ARG: return "invalid argument";
+        case LBM_ERR_UNSUPPORTED: return "unsupported combination";
+        case LBM_ERR_CFL: return "lattice speed too low for the material (sqrt(lam + 2 mu) / c > 1/2)";
+        case LBM_ERR_LAUNCH: return "kernel launch failed";
+        default: return "unknown status";
+    }
+}
+
+const char* lbm_version(void) { return "tlvlbm 0.1 (gfx950)"; }
+
+}  // extern "C"

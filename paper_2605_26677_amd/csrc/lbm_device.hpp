@@ -1,0 +1,304 @@
+// Device building blocks of the D2Q4 x 6 vectorial LBM: storage traits, the hyperelastic
+// closures of the paper's Appendix A evaluated in registers, their tangents
+// (eq:stress-and-tangent), and small helpers shared by the forward and adjoint kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------- storage traits
+
+template <int ST> struct Storage;
+template <> struct Storage<LBM_F32_SHIFTED> {
+    using pop_t = float;
+    using real = float;
+    static constexpr bool shifted = true;
+};
+template <> struct Storage<LBM_F16_SHIFTED> {
+    using pop_t = _Float16;
+    using real = float;
+    static constexpr bool shifted = true;
+};
+template <> struct Storage<LBM_F64_PLAIN> {
+    using pop_t = double;
+    using real = double;
+    static constexpr bool shifted = false;
+};
+
+template <typename T, typename R> __device__ __forceinline__ R load_as(const T* p) {
+    return static_cast<R>(*p);
+}
+// float -> _Float16 conversion is round-to-nearest-even with subnormals kept.
+template <typename T, typename R> __device__ __forceinline__ void store_as(T* p, R v) {
+    *p = static_cast<T>(v);
+}
+
+__device__ __forceinline__ float log1p_r(float x) { return log1pf(x); }
+__device__ __forceinline__ double log1p_r(double x) { return log1p(x); }
+__device__ __forceinline__ float log_r(float x) { return logf(x); }
+__device__ __forceinline__ double log_r(double x) { return log(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+__device__ __forceinline__ bool finite_r(float x) { return isfinite(x); }
+__device__ __forceinline__ bool finite_r(double x) { return isfinite(x); }
+
+// D2Q4 directions in the paper's order (Sec. 3.1).
+__host__ __device__ constexpr int dir_i(int q) { return q == 0 ? 1 : (q == 2 ? -1 : 0); }
+__host__ __device__ constexpr int dir_j(int q) { return q == 1 ? 1 : (q == 3 ? -1 : 0); }
+
+// ---------------------------------------------------------------- kinematics
+//
+// A deformation state is passed as four numbers f[0..3] = (11, 12, 21, 22): the shift
+// F - I when SHIFTED, the plain F otherwise.  With the shift, J - 1 and F - F^{-T} are
+// formed without subtracting nearly equal numbers:
+//   delta = J - 1 = f11 + f22 + (f11 f22 - f12 f21),
+//   F - H = (1/J) [[f11 - f22 + delta (1 + f11), J f12 + f21],
+//                  [J f21 + f12, f22 - f11 + delta (1 + f22)]],   H = F^{-T}.
+
+template <typename R> struct Kin {
+    R J, invJ, L;          // det F, 1/J, ln J
+    R H[4];                // F^{-T}
+    R FmH[4];              // F - F^{-T}
+    R Jsq_m1;              // J^2 - 1
+};
+
+template <typename R, bool SHIFTED>
+__device__ __forceinline__ Kin<R> kinematics(const R f[4]) {
+    Kin<R> k;
+    if constexpr (SHIFTED) {
+        const R d = f[0] + f[3] + (f[0] * f[3] - f[1] * f[2]);
+        k.J = R(1) + d;
+        k.invJ = R(1) / k.J;
+        k.L = log1p_r(d);
+        k.Jsq_m1 = d * (R(2) + d);
+        k.H[0] = (R(1) + f[3]) * k.invJ;
+        k.H[1] = -f[2] * k.invJ;
+        k.H[2] = -f[1] * k.invJ;
+        k.H[3] = (R(1) + f[0]) * k.invJ;
+        k.FmH[0] = (f[0] - f[3] + d * (R(1) + f[0])) * k.invJ;
+        k.FmH[1] = (k.J * f[1] + f[2]) * k.invJ;
+        k.FmH[2] = (k.J * f[2] + f[1]) * k.invJ;
+        k.FmH[3] = (f[3] - f[0] + d * (R(1) + f[3])) * k.invJ;
+    } else {
+        k.J = f[0] * f[3] - f[1] * f[2];
+        k.invJ = R(1) / k.J;
+        k.L = log_r(k.J);
+        k.Jsq_m1 = k.J * k.J - R(1);
+        k.H[0] = f[3] * k.invJ;
+        k.H[1] = -f[2] * k.invJ;
+        k.H[2] = -f[1] * k.invJ;
+        k.H[3] = f[0] * k.invJ;
+        for (int a = 0; a < 4; ++a) k.FmH[a] = f[a] - k.H[a];
+    }
+    return k;
+}
+
+template <typename R, bool SHIFTED>
+__device__ __forceinline__ void full_F(const R f[4], R F[4]) {
+    if constexpr (SHIFTED) {
+        F[0] = R(1) + f[0]; F[1] = f[1]; F[2] = f[2]; F[3] = R(1) + f[3];
+    } else {
+        F[0] = f[0]; F[1] = f[1]; F[2] = f[2]; F[3] = f[3];
+    }
+}
+
+// Green-Lagrange strain E = (F^T F - I)/2 as (E11, E12, E22); from the shift
+// E = (F~ + F~^T + F~^T F~)/2.
+template <typename R, bool SHIFTED>
+__device__ __forceinline__ void green_lagrange(const R f[4], R& E11, R& E12, R& E22) {
+    if constexpr (SHIFTED) {
+        E11 = f[0] + R(0.5) * (f[0] * f[0] + f[2] * f[2]);
+        E22 = f[3] + R(0.5) * (f[1] * f[1] + f[3] * f[3]);
+        E12 = R(0.5) * (f[1] + f[2] + f[0] * f[1] + f[2] * f[3]);
+    } else {
+        E11 = R(0.5) * (f[0] * f[0] + f[2] * f[2] - R(1));
+        E22 = R(0.5) * (f[1] * f[1] + f[3] * f[3] - R(1));
+        E12 = R(0.5) * (f[0] * f[1] + f[2] * f[3]);
+    }
+}
+
+// ---------------------------------------------------------------- first Piola stress
+// P(F) of Appendix A in registers; also returns J for the admissibility check.
+
+template <typename R, int LAW, bool SHIFTED>
+__device__ __forceinline__ void piola(const R f[4], R mu, R lam, R P[4], R& J) {
+    if constexpr (LAW == LBM_SVK) {
+        R E11, E12, E22;
+        green_lagrange<R, SHIFTED>(f, E11, E12, E22);
+        const R tr = E11 + E22;
+        const R S11 = R(2) * mu * E11 + lam * tr, S22 = R(2) * mu * E22 + lam * tr;
+        const R S12 = R(2) * mu * E12;
+        R F[4];
+        full_F<R, SHIFTED>(f, F);
+        P[0] = F[0] * S11 + F[1] * S12;
+        P[1] = F[0] * S12 + F[1] * S22;
+        P[2] = F[2] * S11 + F[3] * S12;
+        P[3] = F[2] * S12 + F[3] * S22;
+        if constexpr (SHIFTED) J = R(1) + (f[0] + f[3] + (f[0] * f[3] - f[1] * f[2]));
+        else J = f[0] * f[3] - f[1] * f[2];
+    } else {
+        const Kin<R> k = kinematics<R, SHIFTED>(f);
+        const R vol = (LAW == LBM_LOGNH) ? lam * k.L : R(0.5) * lam * k.Jsq_m1;
+        for (int a = 0; a < 4; ++a) P[a] = mu * k.FmH[a] + vol * k.H[a];
+        J = k.J;
+    }
+}
+
+// dP/dmu and dP/dlam (every law here is linear in the two parameters).
+template <typename R, int LAW, bool SHIFTED>
+__device__ __forceinline__ void piola_partials(const R f[4], R Pm[4], R Pl[4]) {
+    R J;
+    piola<R, LAW, SHIFTED>(f, R(1), R(0), Pm, J);
+    piola<R, LAW, SHIFTED>(f, R(0), R(1), Pl, J);
+}
+
+// ---------------------------------------------------------------- tangent
+// C[i][A][k][B] = dP_iA / dF_kB stored at index 8 i + 4 A + 2 k + B.  The closed forms
+// follow by differentiating Appendix A (H = F^{-T}, L = ln J, S = lam tr E I + 2 mu E):
+//   log-NH: mu d_ik d_AB + (mu - lam L) H_iB H_kA + lam H_iA H_kB
+//   NH:     mu d_ik d_AB + (mu - lam (J^2 - 1)/2) H_iB H_kA + lam J^2 H_iA H_kB
+//   SVK:    d_ik S_AB + lam F_iA F_kB + mu (F_iB F_kA + (F F^T)_ik d_AB)
+
+template <typename R, int LAW, bool SHIFTED>
+__device__ __forceinline__ void tangent(const R f[4], R mu, R lam, R C[16]) {
+    if constexpr (LAW == LBM_SVK) {
+        R E11, E12, E22;
+        green_lagrange<R, SHIFTED>(f, E11, E12, E22);
+        const R tr = E11 + E22;
+        const R S[4] = {R(2) * mu * E11 + lam * tr, R(2) * mu * E12, R(2) * mu * E12,
+                        R(2) * mu * E22 + lam * tr};
+        R F[4];
+        full_F<R, SHIFTED>(f, F);
+        R FFt[4];
+        FFt[0] = F[0] * F[0] + F[1] * F[1];
+        FFt[1] = F[0] * F[2] + F[1] * F[3];
+        FFt[2] = FFt[1];
+        FFt[3] = F[2] * F[2] + F[3] * F[3];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int A = 0; A < 2; ++A)
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int B = 0; B < 2; ++B) {
+                        R v = lam * F[2 * i + A] * F[2 * k + B] + mu * F[2 * i + B] * F[2 * k + A];
+                        if (i == k) v += S[2 * A + B];
+                        if (A == B) v += mu * FFt[2 * i + k];
+                        C[8 * i + 4 * A + 2 * k + B] = v;
+                    }
+    } else {
+        const Kin<R> kk = kinematics<R, SHIFTED>(f);
+        R a, b;
+        if constexpr (LAW == LBM_LOGNH) {
+            a = mu - lam * kk.L;
+            b = lam;
+        } else {
+            a = mu - R(0.5) * lam * kk.Jsq_m1;
+            b = lam * kk.J * kk.J;
+        }
+        const R* H = kk.H;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int A = 0; A < 2; ++A)
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int B = 0; B < 2; ++B) {
+                        R v = a * H[2 * i + B] * H[2 * k + A] + b * H[2 * i + A] * H[2 * k + B];
+                        if (i == k && A == B) v += mu;
+                        C[8 * i + 4 * A + 2 * k + B] = v;
+                    }
+    }
+}
+
+// Strain energy W(F) (Appendix A), used by the diagnostics.
+template <typename R, int LAW, bool SHIFTED>
+__device__ __forceinline__ R energy(const R f[4], R mu, R lam) {
+    if constexpr (LAW == LBM_SVK) {
+        R E11, E12, E22;
+        green_lagrange<R, SHIFTED>(f, E11, E12, E22);
+        const R tr = E11 + E22;
+        return R(0.5) * lam * tr * tr + mu * (E11 * E11 + R(2) * E12 * E12 + E22 * E22);
+    } else {
+        const Kin<R> k = kinematics<R, SHIFTED>(f);
+        // tr C - 2 - 2 ln J, with tr C - 2 = 2 (f11 + f22) + |f|^2 in shifted form
+        R trCm2;
+        if constexpr (SHIFTED)
+            trCm2 = R(2) * (f[0] + f[3]) + f[0] * f[0] + f[1] * f[1] + f[2] * f[2] + f[3] * f[3];
+        else
+            trCm2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2] + f[3] * f[3] - R(2);
+        const R dev = R(0.5) * mu * (trCm2 - R(2) * k.L);
+        if constexpr (LAW == LBM_LOGNH) return dev + R(0.5) * lam * k.L * k.L;
+        else return dev + R(0.25) * lam * (k.Jsq_m1 - R(2) * k.L);
+    }
+}
+
+// ---------------------------------------------------------------- grid helpers
+
+struct Grid {
+    int nx, ny;
+    int64_t stride;      // elements between population planes
+    int periodic_x, periodic_y;
+};
+
+// Second-order first derivative of g along an axis of length L at position s: central
+// differences, periodic wrap, or the one-sided three-point formula at the ends of a
+// non-periodic axis.  get(s') returns the value at s'.
+template <typename R, typename Get>
+__device__ __forceinline__ R fd_along(Get get, int s, int L, bool periodic, R inv2h) {
+    if (periodic) {
+        const int sp = (s + 1 == L) ? 0 : s + 1;
+        const int sm = (s == 0) ? L - 1 : s - 1;
+        return (get(sp) - get(sm)) * inv2h;
+    }
+    if (s == 0) return (R(-3) * get(0) + R(4) * get(1) - get(2)) * inv2h;
+    if (s == L - 1) return (R(3) * get(L - 1) - R(4) * get(L - 2) + get(L - 3)) * inv2h;
+    return (get(s + 1) - get(s - 1)) * inv2h;
+}
+
+// Column s of the same difference operator, applied as a transpose:
+// sum over rows s' of D[s', s] * gbar(s').
+template <typename R, typename Get>
+__device__ __forceinline__ R fd_along_T(Get gbar, int s, int L, bool periodic, R inv2h) {
+    if (periodic) {
+        const int sp = (s + 1 == L) ? 0 : s + 1;
+        const int sm = (s == 0) ? L - 1 : s - 1;
+        return (gbar(sm) - gbar(sp)) * inv2h;
+    }
+    R acc = R(0);
+    // central rows s' in [1, L-2]: D[s', s'+1] = +1, D[s', s'-1] = -1
+    if (s - 1 >= 1 && s - 1 <= L - 2) acc += gbar(s - 1);
+    if (s + 1 >= 1 && s + 1 <= L - 2) acc -= gbar(s + 1);
+    // row 0: (-3, 4, -1) on columns 0, 1, 2
+    if (s == 0) acc += R(-3) * gbar(0);
+    if (s == 1) acc += R(4) * gbar(0);
+    if (s == 2) acc += R(-1) * gbar(0);
+    // row L-1: (1, -4, 3) on columns L-3, L-2, L-1
+    if (s == L - 1) acc += R(3) * gbar(L - 1);
+    if (s == L - 2) acc += R(-4) * gbar(L - 1);
+    if (s == L - 3) acc += R(1) * gbar(L - 1);
+    return acc * inv2h;
+}
+
+// Per-edge geometry (Sec. 3.6): outward normal, axis A the normal is aligned with,
+// missing incoming direction d = -N and its opposite.
+struct EdgeGeom {
+    int A;        // 0 for x-edges (normal along X), 1 for y-edges
+    int NA;       // normal component along A (+1 or -1)
+    int d;        // missing incoming direction at the wall nodes
+    int od;       // outgoing direction -d = N
+};
+__host__ __device__ constexpr EdgeGeom edge_geom(int e) {
+    return e == LBM_XMIN ? EdgeGeom{0, -1, 0, 2}
+         : e == LBM_XMAX ? EdgeGeom{0, 1, 2, 0}
+         : e == LBM_YMIN ? EdgeGeom{1, -1, 1, 3}
+                         : EdgeGeom{1, 1, 3, 1};
+}
+
+}  // namespace lbm

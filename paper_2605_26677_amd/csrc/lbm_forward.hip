@@ -1,0 +1,663 @@
+// Forward kernels of the D2Q4 x 6 vectorial LBM on gfx950: the fused collide-stream step
+// (Sec. 3.7), the traction-wall F^b solve (Sec. 3.6), the second-order initialisation
+// (Sec. 3.4) and the recoveries from stored post-collision populations (Sec. 3.5).
+//
+// Layout: 24 SoA planes per population buffer, plane 6 q + k at offset (6 q + k) * stride,
+// node (a, b) at b * nx + a.  One thread per node, 256-node tiles along a row; the tile
+// order is remapped so that each of the eight XCDs sweeps a contiguous band of rows (its
+// L2 then serves the one-element overlap of the x -/+ 1 pulls between adjacent tiles).
+#include <algorithm>
+
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+#include "lbm_kernel_util.hpp"
+
+namespace lbm {
+
+// F^b of every link of one traction edge at step n -> n+1 (Sec. 3.6).  Reading of the
+// extrapolation the paper leaves open: with X0 the wall node and X1 the first interior
+// node, G = F_{.B} + (dt/2) d_B v (the kinematic identity moves F by half a step) and the
+// tangential column is 3/2 G(X0) - 1/2 G(X1) (linear extrapolation to the half-way wall);
+// the Newton guess for the normal column is 3/2 F_{.A}(X0) - 1/2 F_{.A}(X1).
+template <int ST, int LAW, bool FIELDS>
+__global__ void __launch_bounds__(kBlock) traction_kernel(TractionArgs a) {
+    using Tr = Storage<ST>;
+    using R = typename Tr::real;
+    using T = typename Tr::pop_t;
+    constexpr bool SH = Tr::shifted;
+    const Common& cm = a.cm;
+    const int e = a.edge;
+    const EdgeGeom G = edge_geom(e);
+    const int L = (G.A == 0) ? cm.ny : cm.nx;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= L) return;
+    const bool per_t = (G.A == 0) ? cm.periodic_y : cm.periodic_x;
+    const int Bx = 1 - G.A;
+    const T* pop = (const T*)a.pop;
+    const int64_t n = int64_t(cm.nx) * cm.ny;
+    const R hdt = R(0.5 * cm.dt);
+    const R inv2h = R(1.0 / (2.0 * cm.dx));
+    const Stencil sten = tangential_stencil(s, L, per_t);
+    R Ghat[2][2], Fa[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        R Us[3][6];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int id = edge_node(G, cm.nx, cm.ny, r, sten.p[j]);
+            double b0, b1;
+            body_at<FIELDS>(cm, id, n, a.r_n, b0, b1);
+            recover_node<T, R>(pop, cm.stride, id, hdt * R(b0), hdt * R(b1), Us[j]);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            R dv = R(0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dv += R(sten.w[j]) * Us[j][k];
+            dv *= inv2h;
+            Ghat[r][k] = Us[sten.self][2 + 2 * k + Bx] + hdt * dv;
+            Fa[r][k] = Us[sten.self][2 + 2 * k + G.A];
+        }
+    }
+    R tang[2], acol[2], Tv[2];
+    for (int k = 0; k < 2; ++k) {
+        tang[k] = R(1.5) * Ghat[0][k] - R(0.5) * Ghat[1][k];
+        acol[k] = R(1.5) * Fa[0][k] - R(0.5) * Fa[1][k];
+        Tv[k] = edge_value<R>(a.ed, e, k, s, L);
+    }
+    const int id0 = edge_node(G, cm.nx, cm.ny, 0, s);
+    R mu, lam;
+    params_at<FIELDS, R>(cm, id0, mu, lam);
+    const bool ok = newton_column<R, LAW, SH>(G.A, R(G.NA), tang, Tv, mu, lam, acol,
+                                             cm.newton_max_iter, R(cm.newton_tol));
+    if (!ok) atomicOr(cm.fault, (uint32_t)LBM_FAULT_NEWTON);
+    int off[4], len[4];
+    edge_offsets(cm.nx, cm.ny, off, len);
+    R* aux = (R*)a.aux + 4 * (int64_t)(off[e] + s);
+    for (int k = 0; k < 2; ++k) {
+        aux[2 * k + G.A] = acol[k];
+        aux[2 * k + Bx] = tang[k];
+    }
+}
+
+// ---------------------------------------------------------------- the fused step
+
+// Missing link d at a wall node of edge e (eq:boundary-general):
+// f_d = D f*_{-d}(X) + S_d, velocity rule eq:dirichlet-boundary-rule,
+// traction rule eq:neumann-boundary-rule.  In shifted storage only the traction F rows
+// change: g_d = -g*_{-d} + (F^b - I)/2 (F^b arrives from the staging buffer as F^b - I).
+template <typename T, typename R>
+__device__ __forceinline__ void wall_link(const Common& cm, const EdgeData& ed, const void* auxp,
+                                          int e, int s, const T* src, int idx, R out[6]) {
+    const EdgeGeom G = edge_geom(e);
+    const int L = (G.A == 0) ? cm.ny : cm.nx;
+    R o[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) o[k] = R(src[(6 * G.od + k) * cm.stride + idx]);
+    const R w0 = edge_value<R>(ed, e, 0, s, L), w1 = edge_value<R>(ed, e, 1, s, L);
+    const R c = R(cm.c);
+    if (cm.bc[e] == LBM_VELOCITY) {
+        const R N0 = (G.A == 0) ? R(G.NA) : R(0), N1 = (G.A == 1) ? R(G.NA) : R(0);
+        out[0] = -o[0] + R(0.5) * w0;
+        out[1] = -o[1] + R(0.5) * w1;
+        out[2] = o[2] + N0 * w0 / c;
+        out[3] = o[3] + N1 * w0 / c;
+        out[4] = o[4] + N0 * w1 / c;
+        out[5] = o[5] + N1 * w1 / c;
+    } else {
+        int off[4], len[4];
+        edge_offsets(cm.nx, cm.ny, off, len);
+        const R* Fb = (const R*)auxp + 4 * (int64_t)(off[e] + s);
+        out[0] = o[0] + w0 / c;
+        out[1] = o[1] + w1 / c;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[2 + k] = -o[2 + k] + R(0.5) * Fb[k];
+    }
+}
+
+template <int ST, int LAW, bool WALLS, bool FIELDS>
+__global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
+    using Tr = Storage<ST>;
+    using R = typename Tr::real;
+    using T = typename Tr::pop_t;
+    constexpr bool SH = Tr::shifted;
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny;
+    const int tpr = (nx + kBlock - 1) / kBlock;
+    const int tile = remap_tile(blockIdx.x, gridDim.x);
+    const int y = tile / tpr;
+    const int x = (tile - y * tpr) * kBlock + threadIdx.x;
+    if (x >= nx) return;
+    const int64_t st = cm.stride;
+    const int64_t n = int64_t(nx) * ny;
+    const T* __restrict__ src = (const T*)a.src;
+    T* __restrict__ dst = (T*)a.dst;
+    const int idx = y * nx + x;
+
+    // pull sources: q0 (1,0) from (x-1, y), q1 (0,1) from (x, y-1), q2 (-1,0) from (x+1, y),
+    // q3 (0,-1) from (x, y+1) (eq:streaming); a source beyond a wall is a missing link.
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+    bool miss0 = false, miss1 = false, miss2 = false, miss3 = false;
+    if (xm < 0) { if (WALLS && !cm.periodic_x) { miss0 = true; xm = x; } else xm = nx - 1; }
+    if (xp >= nx) { if (WALLS && !cm.periodic_x) { miss2 = true; xp = x; } else xp = 0; }
+    if (ym < 0) { if (WALLS && !cm.periodic_y) { miss1 = true; ym = y; } else ym = ny - 1; }
+    if (yp >= ny) { if (WALLS && !cm.periodic_y) { miss3 = true; yp = y; } else yp = 0; }
+    const int sidx[4] = {y * nx + xm, ym * nx + x, y * nx + xp, yp * nx + x};
+
+    R g[4][6];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) g[q][k] = R(src[(6 * q + k) * st + sidx[q]]);
+
+    if constexpr (WALLS) {
+        if (miss0) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMIN, y, src, idx, g[0]);
+        if (miss2) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMAX, y, src, idx, g[2]);
+        if (miss1) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMIN, x, src, idx, g[1]);
+        if (miss3) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMAX, x, src, idx, g[3]);
+    }
+
+    // moments with the half-step source (eq:moment-U)
+    double bd0, bd1;
+    body_at<FIELDS>(cm, idx, n, a.r_np1, bd0, bd1);
+    const R B0 = R(bd0), B1 = R(bd1);
+    const R dt = R(cm.dt), hdt = R(0.5 * cm.dt);
+    R U[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) U[k] = g[0][k] + g[1][k] + g[2][k] + g[3][k];
+    U[0] += hdt * B0;
+    U[1] += hdt * B1;
+
+    // constitutive response in registers, fluxes (eq:flux-vectors), equilibrium (eq:feq)
+    R mu, lam;
+    params_at<FIELDS, R>(cm, idx, mu, lam);
+    R P[4], J;
+    piola<R, LAW, SH>(&U[2], mu, lam, P, J);
+    const R PhiX[6] = {-P[0], -P[2], -U[0], R(0), -U[1], R(0)};
+    const R PhiY[6] = {-P[1], -P[3], R(0), -U[0], R(0), -U[1]};
+    const R c2 = R(2.0 / cm.c);
+    const R om = R(cm.omega);
+    const R srcw = R(cm.dt * (2.0 - cm.omega) * 0.125);
+
+    // collision with trapezoidal forcing (eq:collision), store to the own node
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const R i = R(dir_i(q)), j = R(dir_j(q));
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const R feq = R(0.25) * (U[k] + c2 * (i * PhiX[k] + j * PhiY[k]));
+            R v = g[q][k] + om * (feq - g[q][k]);
+            if (k == 0) v += srcw * B0;
+            if (k == 1) v += srcw * B1;
+            dst[(6 * q + k) * st + idx] = T(v);
+        }
+    }
+
+    // displacement quadrature u*^{n+2} = u*^{n+1} + dt v^{n+1} (eq:trapezoid-u)
+    if constexpr (ST == LBM_F64_PLAIN) {
+        double* us = (double*)a.ustar;
+        us[idx] += dt * U[0];
+        us[n + idx] += dt * U[1];
+    } else {
+        float* us = (float*)a.ustar;
+#pragma unroll
+        for (int cpt = 0; cpt < 2; ++cpt) {
+            float hi = us[cpt * n + idx];
+            float cc = us[(2 + cpt) * n + idx];
+            const float yv = float(dt * U[cpt]) - cc;
+            const float t = hi + yv;
+            cc = (t - hi) - yv;
+            us[cpt * n + idx] = t;
+            us[(2 + cpt) * n + idx] = cc;
+        }
+    }
+
+    if (a.record) {
+        R* rec = (R*)a.record;
+        rec[idx] = U[0];
+        rec[n + idx] = U[1];
+        rec[2 * n + idx] = SH ? U[2] : U[2] - R(1);
+        rec[3 * n + idx] = U[3];
+        rec[4 * n + idx] = U[4];
+        rec[5 * n + idx] = SH ? U[5] : U[5] - R(1);
+    }
+
+    bool nonfinite = false;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U[k]);
+    const bool jbad = J <= R(0);
+    if (nonfinite || jbad)
+        atomicOr(cm.fault, (jbad ? (uint32_t)LBM_FAULT_J : 0u) | (nonfinite ? (uint32_t)LBM_FAULT_NONFINITE : 0u));
+}
+
+// ---------------------------------------------------------------- recoveries
+
+template <int ST, bool FIELDS, int MODE>   // MODE 0 moments (double), 1 record (R), 2 displacement
+__global__ void __launch_bounds__(kBlock) recover_kernel(RecoverArgs a) {
+    using Tr = Storage<ST>;
+    using R = typename Tr::real;
+    using T = typename Tr::pop_t;
+    constexpr bool SH = Tr::shifted;
+    const Common& cm = a.cm;
+    const int64_t n = int64_t(cm.nx) * cm.ny;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    double b0, b1;
+    body_at<FIELDS>(cm, (int)idx, n, a.r_n, b0, b1);
+    const double hdt = 0.5 * cm.dt;
+    R U[6];
+    recover_node<T, R>((const T*)a.pop, cm.stride, (int)idx, R(hdt * b0), R(hdt * b1), U);
+    if constexpr (MODE == 0) {
+        double* out = (double*)a.out;
+        for (int k = 0; k < 6; ++k) {
+            double v = double(U[k]);
+            if (!SH && (k == 2 || k == 5)) v -= 1.0;
+            out[k * n + idx] = v;
+        }
+    } else if constexpr (MODE == 1) {
+        R* out = (R*)a.out;
+        for (int k = 0; k < 6; ++k) {
+            R v = U[k];
+            if (!SH && (k == 2 || k == 5)) v -= R(1);
+            out[k * n + idx] = v;
+        }
+    } else {
+        double* out = (double*)a.out;
+        for (int cpt = 0; cpt < 2; ++cpt) {
+            double ustar;
+            if constexpr (ST == LBM_F64_PLAIN) {
+                ustar = ((const double*)a.ustar)[cpt * n + idx];
+            } else {
+                const float* us = (const float*)a.ustar;
+                ustar = double(us[cpt * n + idx]) - double(us[(2 + cpt) * n + idx]);
+            }
+            out[cpt * n + idx] = ustar - hdt * double(U[cpt]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- diagnostics
+
+template <int ST, int LAW, bool FIELDS>
+__global__ void __launch_bounds__(kBlock) diag_kernel(RecoverArgs a) {
+    using Tr = Storage<ST>;
+    using R = typename Tr::real;
+    using T = typename Tr::pop_t;
+    constexpr bool SH = Tr::shifted;
+    const Common& cm = a.cm;
+    const int64_t n = int64_t(cm.nx) * cm.ny;
+    double acc[LBM_DIAG_COUNT];
+    for (int k = 0; k < LBM_DIAG_COUNT; ++k) acc[k] = 0.0;
+    acc[7] = 1e300;
+    acc[8] = 0.0;
+    acc[9] = 0.0;
+    const double hdt = 0.5 * cm.dt;
+    // 1-degree rotation for the direction scan of the acoustic tensor
+    const R cd = R(0.99984769515639123916), sd = R(0.017452406437283512820);
+    for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < n;
+         idx += int64_t(gridDim.x) * blockDim.x) {
+        double b0, b1;
+        body_at<FIELDS>(cm, (int)idx, n, a.r_n, b0, b1);
+        R U[6];
+        recover_node<T, R>((const T*)a.pop, cm.stride, (int)idx, R(hdt * b0), R(hdt * b1), U);
+        R mu, lam;
+        params_at<FIELDS, R>(cm, (int)idx, mu, lam);
+        R ft[4] = {U[2], U[3], U[4], U[5]};
+        if (!SH) { ft[0] -= R(1); ft[3] -= R(1); }
+        acc[0] += double(U[0]);
+        acc[1] += double(U[1]);
+        for (int k = 0; k < 4; ++k) acc[2 + k] += double(ft[k]);
+        const R W = energy<R, LAW, true>(ft, mu, lam);
+        acc[6] += double(R(0.5) * (U[0] * U[0] + U[1] * U[1]) + W);
+        const R J = R(1) + ft[0] + ft[3] + (ft[0] * ft[3] - ft[1] * ft[2]);
+        acc[7] = fmin(acc[7], double(J));
+        acc[8] = fmax(acc[8], double(sqrt_r(ft[0] * ft[0] + ft[1] * ft[1] + ft[2] * ft[2] + ft[3] * ft[3])));
+        R C[16];
+        tangent<R, LAW, true>(ft, mu, lam, C);
+        R cs = R(1), sn = R(0), best = R(0);
+        for (int t = 0; t < 180; ++t) {
+            const R nn[2] = {cs, sn};
+            R Q[4];
+            for (int i = 0; i < 2; ++i)
+                for (int k = 0; k < 2; ++k) {
+                    R v = R(0);
+                    for (int A = 0; A < 2; ++A)
+                        for (int B = 0; B < 2; ++B) v += nn[A] * C[8 * i + 4 * A + 2 * k + B] * nn[B];
+                    Q[2 * i + k] = v;
+                }
+            const R tr = R(0.5) * (Q[0] + Q[3]);
+            const R dd = R(0.5) * (Q[0] - Q[3]);
+            const R off = R(0.5) * (Q[1] + Q[2]);
+            const R lmax = tr + sqrt_r(dd * dd + off * off);
+            best = best > lmax ? best : lmax;
+            const R c2 = cs * cd - sn * sd;
+            sn = sn * cd + cs * sd;
+            cs = c2;
+        }
+        acc[9] = fmax(acc[9], double(sqrt_r(best)) / cm.c);
+    }
+    acc[6] *= cm.dx * cm.dx;
+    // block reduction in FP64
+    __shared__ double red[kBlock];
+    double* part = (double*)a.scratch + int64_t(blockIdx.x) * LBM_DIAG_COUNT;
+    for (int k = 0; k < LBM_DIAG_COUNT; ++k) {
+        red[threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                const double o = red[threadIdx.x + w];
+                double& m = red[threadIdx.x];
+                m = (k == 7) ? fmin(m, o) : (k >= 8 ? fmax(m, o) : m + o);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[k] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) diag_final_kernel(const double* part, int nblocks, double* out) {
+    __shared__ double red[kBlock];
+    for (int k = 0; k < LBM_DIAG_COUNT; ++k) {
+        double m = (k == 7) ? 1e300 : 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+            const double o = part[b * LBM_DIAG_COUNT + k];
+            m = (k == 7) ? fmin(m, o) : (k >= 8 ? fmax(m, o) : m + o);
+        }
+        red[threadIdx.x] = m;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                const double o = red[threadIdx.x + w];
+                double& r = red[threadIdx.x];
+                r = (k == 7) ? fmin(r, o) : (k >= 8 ? fmax(r, o) : r + o);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = red[0];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- initialisation
+
+// U0 = (v0, grad u0) as 6 double planes (F - I = grad u0 by second-order differences).
+__global__ void __launch_bounds__(kBlock) init_state_kernel(InitArgs a) {
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny;
+    const int64_t n = int64_t(nx) * ny;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int y = int(idx / nx), x = int(idx - int64_t(y) * nx);
+    double* U0 = (double*)a.scratch;
+    U0[idx] = a.v0[idx];
+    U0[n + idx] = a.v0[n + idx];
+    const double inv2h = 1.0 / (2.0 * cm.dx);
+    for (int cpt = 0; cpt < 2; ++cpt) {
+        double gx = 0.0, gy = 0.0;
+        if (a.u0) {
+            const double* u = a.u0 + cpt * n;
+            gx = fd_along<double>([&](int s) { return u[int64_t(y) * nx + s]; }, x, nx, cm.periodic_x, inv2h);
+            gy = fd_along<double>([&](int s) { return u[int64_t(s) * nx + x]; }, y, ny, cm.periodic_y, inv2h);
+        }
+        U0[(2 + 2 * cpt) * n + idx] = gx;
+        U0[(3 + 2 * cpt) * n + idx] = gy;
+    }
+}
+
+// Second-order populations (eq:init-compact with eq:init-Zq-components, eq:init-deltaPq,
+// eq:init-expanded) in FP64 shifted form, then the first collision (level 0) and u*^1.
+template <int ST, int LAW, bool FIELDS>
+__global__ void __launch_bounds__(kBlock) init_pop_kernel(InitArgs a) {
+    using Tr = Storage<ST>;
+    using T = typename Tr::pop_t;
+    constexpr bool SH = Tr::shifted;
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny;
+    const int64_t n = int64_t(nx) * ny;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int y = int(idx / nx), x = int(idx - int64_t(y) * nx);
+    const double* U0p = (const double*)a.scratch;
+    const double c = cm.c, dt = cm.dt, hdt = 0.5 * cm.dt;
+    const double inv2h = 1.0 / (2.0 * cm.dx);
+    double U0[6], dX[6], dY[6];
+    for (int k = 0; k < 6; ++k) {
+        const double* pl = U0p + k * n;
+        U0[k] = pl[idx];
+        dX[k] = fd_along<double>([&](int s) { return pl[int64_t(y) * nx + s]; }, x, nx, cm.periodic_x, inv2h);
+        dY[k] = fd_along<double>([&](int s) { return pl[int64_t(s) * nx + x]; }, y, ny, cm.periodic_y, inv2h);
+    }
+    double mu, lam, b0, b1;
+    params_at<FIELDS, double>(cm, (int)idx, mu, lam);
+    body_at<FIELDS>(cm, (int)idx, n, a.r0, b0, b1);
+    double C[16], P0[4], J;
+    tangent<double, LAW, true>(&U0[2], mu, lam, C);
+    piola<double, LAW, true>(&U0[2], mu, lam, P0, J);
+    // d_alpha P = C : d_alpha F
+    double dPX[4], dPY[4];
+    for (int iA = 0; iA < 4; ++iA) {
+        double sx = 0.0, sy = 0.0;
+        for (int kB = 0; kB < 4; ++kB) {
+            sx += C[4 * iA + kB] * dX[2 + kB];
+            sy += C[4 * iA + kB] * dY[2 + kB];
+        }
+        dPX[iA] = sx;
+        dPY[iA] = sy;
+    }
+    const double PhiX[6] = {-P0[0], -P0[2], -U0[0], 0.0, -U0[1], 0.0};
+    const double PhiY[6] = {-P0[1], -P0[3], 0.0, -U0[0], 0.0, -U0[1]};
+    double g0[4][6];
+    for (int q = 0; q < 4; ++q) {
+        const double i = dir_i(q), j = dir_j(q);
+        double Z[6];
+        Z[0] = b0 + dPX[0] + dPY[1] + c * (i * dX[0] + j * dY[0]);
+        Z[1] = b1 + dPX[2] + dPY[3] + c * (i * dX[1] + j * dY[1]);
+        Z[2] = dX[0] + c * (i * dX[2] + j * dY[2]);
+        Z[3] = dY[0] + c * (i * dX[3] + j * dY[3]);
+        Z[4] = dX[1] + c * (i * dX[4] + j * dY[4]);
+        Z[5] = dY[1] + c * (i * dX[5] + j * dY[5]);
+        double dP[4];
+        for (int iA = 0; iA < 4; ++iA) {
+            double sacc = 0.0;
+            for (int kB = 0; kB < 4; ++kB) sacc += C[4 * iA + kB] * Z[2 + kB];
+            dP[iA] = sacc;
+        }
+        const double D[6] = {
+            0.25 * (Z[0] - (2.0 / c) * (i * dP[0] + j * dP[1])),
+            0.25 * (Z[1] - (2.0 / c) * (i * dP[2] + j * dP[3])),
+            0.25 * (Z[2] - (2.0 * i / c) * Z[0]),
+            0.25 * (Z[3] - (2.0 * j / c) * Z[0]),
+            0.25 * (Z[4] - (2.0 * i / c) * Z[1]),
+            0.25 * (Z[5] - (2.0 * j / c) * Z[1]),
+        };
+        for (int k = 0; k < 6; ++k) {
+            const double feq = 0.25 * (U0[k] + (2.0 / c) * (i * PhiX[k] + j * PhiY[k]));
+            g0[q][k] = feq - hdt * D[k];
+        }
+    }
+    // first collision at level 0 (eq:moment-U, eq:collision)
+    double U[6];
+    for (int k = 0; k < 6; ++k) U[k] = g0[0][k] + g0[1][k] + g0[2][k] + g0[3][k];
+    U[0] += hdt * b0;
+    U[1] += hdt * b1;
+    double P[4];
+    piola<double, LAW, true>(&U[2], mu, lam, P, J);
+    const double QX[6] = {-P[0], -P[2], -U[0], 0.0, -U[1], 0.0};
+    const double QY[6] = {-P[1], -P[3], 0.0, -U[0], 0.0, -U[1]};
+    const double srcw = dt * (2.0 - cm.omega) * 0.125;
+    T* dst = (T*)a.dst;
+    for (int q = 0; q < 4; ++q) {
+        const double i = dir_i(q), j = dir_j(q);
+        for (int k = 0; k < 6; ++k) {
+            const double feq = 0.25 * (U[k] + (2.0 / c) * (i * QX[k] + j * QY[k]));
+            double v = g0[q][k] + cm.omega * (feq - g0[q][k]);
+            if (k == 0) v += srcw * b0;
+            if (k == 1) v += srcw * b1;
+            if (!SH && (k == 2 || k == 5)) v += 0.25;
+            dst[(6 * q + k) * cm.stride + idx] = T(v);
+        }
+    }
+    // u*^1 = u0 - (dt/2) v0 + dt v^0 (eq:trapezoid-u)
+    for (int cpt = 0; cpt < 2; ++cpt) {
+        const double u0 = a.u0 ? a.u0[cpt * n + idx] : 0.0;
+        const double us1 = u0 - hdt * a.v0[cpt * n + idx] + dt * U[cpt];
+        if constexpr (ST == LBM_F64_PLAIN) {
+            ((double*)a.ustar)[cpt * n + idx] = us1;
+        } else {
+            float* us = (float*)a.ustar;
+            const float hi = float(us1);
+            us[cpt * n + idx] = hi;
+            us[(2 + cpt) * n + idx] = float(double(hi) - us1);
+        }
+    }
+    bool bad = !(J > 0.0);
+    if (bad) atomicOr(cm.fault, (uint32_t)LBM_FAULT_J);
+}
+
+// ---------------------------------------------------------------- dispatch
+
+static inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+template <int ST, int LAW>
+static hipError_t step_st_law(const StepArgs& a, hipStream_t s) {
+    const bool walls = !(a.cm.periodic_x && a.cm.periodic_y);
+    const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
+    const int tpr = (a.cm.nx + kBlock - 1) / kBlock;
+    const dim3 grid(unsigned(int64_t(tpr) * a.cm.ny));
+    if (walls) {
+        if (fields) hipLaunchKernelGGL((step_kernel<ST, LAW, true, true>), grid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<ST, LAW, true, false>), grid, dim3(kBlock), 0, s, a);
+    } else {
+        if (fields) hipLaunchKernelGGL((step_kernel<ST, LAW, false, true>), grid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<ST, LAW, false, false>), grid, dim3(kBlock), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t step_st(const StepArgs& a, hipStream_t s) {
+    switch (a.cm.material) {
+        case LBM_LOGNH: return step_st_law<ST, LBM_LOGNH>(a, s);
+        case LBM_NH: return step_st_law<ST, LBM_NH>(a, s);
+        default: return step_st_law<ST, LBM_SVK>(a, s);
+    }
+}
+
+hipError_t launch_step(const StepArgs& a, hipStream_t s) {
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: return step_st<LBM_F32_SHIFTED>(a, s);
+        case LBM_F16_SHIFTED: return step_st<LBM_F16_SHIFTED>(a, s);
+        default: return step_st<LBM_F64_PLAIN>(a, s);
+    }
+}
+
+template <int ST, int LAW>
+static hipError_t traction_st_law(const TractionArgs& a, hipStream_t s) {
+    const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
+    const int L = (a.edge == LBM_XMIN || a.edge == LBM_XMAX) ? a.cm.ny : a.cm.nx;
+    if (fields) hipLaunchKernelGGL((traction_kernel<ST, LAW, true>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((traction_kernel<ST, LAW, false>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t traction_st(const TractionArgs& a, hipStream_t s) {
+    switch (a.cm.material) {
+        case LBM_LOGNH: return traction_st_law<ST, LBM_LOGNH>(a, s);
+        case LBM_NH: return traction_st_law<ST, LBM_NH>(a, s);
+        default: return traction_st_law<ST, LBM_SVK>(a, s);
+    }
+}
+
+hipError_t launch_traction(const TractionArgs& a, hipStream_t s) {
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: return traction_st<LBM_F32_SHIFTED>(a, s);
+        case LBM_F16_SHIFTED: return traction_st<LBM_F16_SHIFTED>(a, s);
+        default: return traction_st<LBM_F64_PLAIN>(a, s);
+    }
+}
+
+template <int MODE>
+static hipError_t recover_dispatch(const RecoverArgs& a, hipStream_t s) {
+    const bool fields = a.cm.body != nullptr;
+    const dim3 grid(nblocks(int64_t(a.cm.nx) * a.cm.ny));
+#define LBM_RECOVER(ST_)                                                                         \
+    if (fields) hipLaunchKernelGGL((recover_kernel<ST_, true, MODE>), grid, dim3(kBlock), 0, s, a); \
+    else hipLaunchKernelGGL((recover_kernel<ST_, false, MODE>), grid, dim3(kBlock), 0, s, a);
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: { LBM_RECOVER(LBM_F32_SHIFTED) break; }
+        case LBM_F16_SHIFTED: { LBM_RECOVER(LBM_F16_SHIFTED) break; }
+        default: { LBM_RECOVER(LBM_F64_PLAIN) break; }
+    }
+#undef LBM_RECOVER
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const RecoverArgs& a, hipStream_t s) { return recover_dispatch<0>(a, s); }
+hipError_t launch_record(const RecoverArgs& a, hipStream_t s) { return recover_dispatch<1>(a, s); }
+hipError_t launch_displacement(const RecoverArgs& a, hipStream_t s) { return recover_dispatch<2>(a, s); }
+
+template <int ST, int LAW>
+static void diag_st_law(const RecoverArgs& a, hipStream_t s) {
+    const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
+    const int64_t n = int64_t(a.cm.nx) * a.cm.ny;
+    const unsigned nb = unsigned(std::min<int64_t>(kDiagBlocks, (n + kBlock - 1) / kBlock));
+    if (fields) hipLaunchKernelGGL((diag_kernel<ST, LAW, true>), dim3(nb), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((diag_kernel<ST, LAW, false>), dim3(nb), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)a.scratch, (int)nb,
+                       (double*)a.out);
+}
+
+template <int ST>
+static void diag_st(const RecoverArgs& a, hipStream_t s) {
+    switch (a.cm.material) {
+        case LBM_LOGNH: diag_st_law<ST, LBM_LOGNH>(a, s); break;
+        case LBM_NH: diag_st_law<ST, LBM_NH>(a, s); break;
+        default: diag_st_law<ST, LBM_SVK>(a, s); break;
+    }
+}
+
+hipError_t launch_diagnostics(const RecoverArgs& a, hipStream_t s) {
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: diag_st<LBM_F32_SHIFTED>(a, s); break;
+        case LBM_F16_SHIFTED: diag_st<LBM_F16_SHIFTED>(a, s); break;
+        default: diag_st<LBM_F64_PLAIN>(a, s); break;
+    }
+    return hipGetLastError();
+}
+
+template <int ST, int LAW>
+static void init_st_law(const InitArgs& a, hipStream_t s, dim3 grid) {
+    const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
+    if (fields) hipLaunchKernelGGL((init_pop_kernel<ST, LAW, true>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((init_pop_kernel<ST, LAW, false>), grid, dim3(kBlock), 0, s, a);
+}
+
+template <int ST>
+static void init_st(const InitArgs& a, hipStream_t s, dim3 grid) {
+    switch (a.cm.material) {
+        case LBM_LOGNH: init_st_law<ST, LBM_LOGNH>(a, s, grid); break;
+        case LBM_NH: init_st_law<ST, LBM_NH>(a, s, grid); break;
+        default: init_st_law<ST, LBM_SVK>(a, s, grid); break;
+    }
+}
+
+hipError_t launch_init_state(const InitArgs& a, hipStream_t s) {
+    const dim3 grid(nblocks(int64_t(a.cm.nx) * a.cm.ny));
+    hipLaunchKernelGGL(init_state_kernel, grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const InitArgs& a, hipStream_t s) {
+    const dim3 grid(nblocks(int64_t(a.cm.nx) * a.cm.ny));
+    hipLaunchKernelGGL(init_state_kernel, grid, dim3(kBlock), 0, s, a);
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: init_st<LBM_F32_SHIFTED>(a, s, grid); break;
+        case LBM_F16_SHIFTED: init_st<LBM_F16_SHIFTED>(a, s, grid); break;
+        default: init_st<LBM_F64_PLAIN>(a, s, grid); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lbm

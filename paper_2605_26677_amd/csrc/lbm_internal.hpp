@@ -1,0 +1,125 @@
+// Internal launch interface between the C-ABI layer (lbm_api.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+namespace lbm {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
+constexpr int kDiagBlocks = 1024;    // partial sums of the diagnostics reduction
+
+// Offsets of each edge's links in the traction staging buffer (links, not bytes).
+__host__ __device__ inline void edge_offsets(int nx, int ny, int off[4], int len[4]) {
+    len[LBM_XMIN] = ny; len[LBM_XMAX] = ny; len[LBM_YMIN] = nx; len[LBM_YMAX] = nx;
+    off[LBM_XMIN] = 0; off[LBM_XMAX] = ny; off[LBM_YMIN] = 2 * ny; off[LBM_YMAX] = 2 * ny + nx;
+}
+
+struct EdgeData {
+    double value[4][2];
+    const double* field[4];
+};
+
+struct Common {
+    int nx, ny;
+    int64_t stride;                  // elements between population planes
+    int bc[4];
+    int periodic_x, periodic_y;
+    int material, storage;
+    double dx, c, omega, dt;
+    double mu0, lam0, b0[2];
+    const float* mu;
+    const float* lam;
+    const float* body;
+    uint32_t* fault;
+    int newton_max_iter;
+    double newton_tol;
+};
+
+struct StepArgs {
+    Common cm;
+    const void* src;                 // f*^n
+    void* dst;                       // f*^{n+1}
+    void* ustar;
+    const void* aux;                 // F^b per traction link (compute type, 4 per link)
+    void* record;                    // U^{n+1} or NULL
+    double r_np1;
+    EdgeData ed;                     // data at t^{n+1/2}
+};
+
+struct TractionArgs {
+    Common cm;
+    const void* pop;                 // f*^n
+    void* aux;
+    double r_n;
+    EdgeData ed;
+    int edge;
+};
+
+struct RecoverArgs {
+    Common cm;
+    const void* pop;
+    const void* ustar;
+    double r_n;
+    void* out;                       // double planes (moments / displacement) or record
+    void* scratch;                   // diagnostics partials
+};
+
+struct InitArgs {
+    Common cm;
+    const double* v0;
+    const double* u0;
+    double r0;
+    void* scratch;                   // U0 as 6 double planes (stride n)
+    void* dst;                       // f*^0
+    void* ustar;
+};
+
+struct AdjArgs {
+    Common cm;
+    const void* src;                 // lambda^{m+1}
+    void* dst;                       // lambda^m
+    const void* record;              // U^m
+    double* g_mu;
+    double* g_lam;
+    double* g_body;
+    void* aux;
+    double r_m;
+    EdgeData ed;
+    int edge;
+    const int32_t* probe;
+    const double* ubar;
+    int nprobe;
+    double probe_weight;             // dt * (1 or 1/2)
+};
+
+struct AdjInitArgs {
+    Common cm;
+    const void* lam0;                // lambda^0
+    void* scratch;                   // 12 double planes: U0 (6) and the v0 seeds (6)
+    const double* v0;
+    const double* u0;
+    double r0;
+    double* g_mu;
+    double* g_lam;
+    double* g_body;
+    double* g_v0;
+    const int32_t* probe;
+    const double* ubar;
+    int nprobe;
+};
+
+hipError_t launch_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_traction(const TractionArgs& a, hipStream_t s);
+hipError_t launch_moments(const RecoverArgs& a, hipStream_t s);
+hipError_t launch_record(const RecoverArgs& a, hipStream_t s);
+hipError_t launch_displacement(const RecoverArgs& a, hipStream_t s);
+hipError_t launch_diagnostics(const RecoverArgs& a, hipStream_t s);
+hipError_t launch_init(const InitArgs& a, hipStream_t s);
+hipError_t launch_init_state(const InitArgs& a, hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s);
+hipError_t launch_adjoint_init(const AdjInitArgs& a, hipStream_t s);
+
+}  // namespace lbm

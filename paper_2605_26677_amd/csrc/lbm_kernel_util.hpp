@@ -1,0 +1,157 @@
+// Device helpers shared by the forward and adjoint kernels: tile order, boundary data,
+// per-node parameters, state recovery from stored populations, the traction-boundary
+// Newton solve and the geometry of the half-way walls.
+#pragma once
+
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD b mod 8);
+// hand XCD x the contiguous tile range [x per, (x + 1) per).
+__device__ __forceinline__ int remap_tile(int b, int nb) {
+    const int per = nb >> 3;
+    if (b >= per * 8) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+template <typename R>
+__device__ __forceinline__ R edge_value(const EdgeData& ed, int e, int comp, int s, int L) {
+    const double* f = ed.field[e];
+    return f ? R(f[comp * L + s]) : R(ed.value[e][comp]);
+}
+
+template <bool FIELDS>
+__device__ __forceinline__ void body_at(const Common& cm, int idx, int64_t n, double r, double& b0, double& b1) {
+    if (FIELDS && cm.body) {
+        b0 = r * double(cm.body[idx]);
+        b1 = r * double(cm.body[n + idx]);
+    } else {
+        b0 = r * cm.b0[0];
+        b1 = r * cm.b0[1];
+    }
+}
+
+template <bool FIELDS, typename R>
+__device__ __forceinline__ void params_at(const Common& cm, int idx, R& mu, R& lam) {
+    if (FIELDS && cm.mu) mu = R(cm.mu[idx]); else mu = R(cm.mu0);
+    if (FIELDS && cm.lam) lam = R(cm.lam[idx]); else lam = R(cm.lam0);
+}
+
+// Sum of the four stored post-collision populations of one node minus (dt/2) B: the
+// state of that level (sum_q f* = U + (dt/2) B, from eq:collision with sum_q w = 1/2).
+template <typename T, typename R>
+__device__ __forceinline__ void recover_node(const T* pop, int64_t st, int idx, R hb0, R hb1, R U[6]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        R s = R(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s += R(pop[(6 * q + k) * st + idx]);
+        U[k] = s;
+    }
+    U[0] -= hb0;
+    U[1] -= hb1;
+}
+
+// ---------------------------------------------------------------- traction Newton
+// Normal column a = F^b_{.A} of the boundary deformation gradient from
+// N_A P_iA(F^b) = T_i (Sec. 3.6, eq:neumann-boundary-rule).  Newton steps
+// delta = -J^{-1} r with J_ik = N_A C_iAkA; step lengths 1, 1/2, ..., 2^-10, the first with
+// det F^b > 0 and a smaller |r| is taken; stop at |r| <= tol (|T| + mu |F^b - I|), when no
+// step length is accepted, or after max_iter updates.  Returns false on failure.
+template <typename R, int LAW, bool SH>
+__device__ bool newton_column(int A, R NA, const R tang[2], const R T[2], R mu, R lam, R a[2],
+                              int max_iter, R tol) {
+    const int B = 1 - A;
+    auto assemble = [&](const R ac[2], R f[4]) {
+        f[A] = ac[0]; f[2 + A] = ac[1];
+        f[B] = tang[0]; f[2 + B] = tang[1];
+    };
+    auto resid = [&](const R ac[2], R r[2], R& J) {
+        R f[4], P[4];
+        assemble(ac, f);
+        piola<R, LAW, SH>(f, mu, lam, P, J);
+        r[0] = NA * P[A] - T[0];
+        r[1] = NA * P[2 + A] - T[1];
+    };
+    auto scale = [&](const R ac[2]) {
+        R f[4];
+        assemble(ac, f);
+        R s2;
+        if constexpr (SH) s2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2] + f[3] * f[3];
+        else s2 = (f[0] - R(1)) * (f[0] - R(1)) + f[1] * f[1] + f[2] * f[2] + (f[3] - R(1)) * (f[3] - R(1));
+        return sqrt_r(T[0] * T[0] + T[1] * T[1]) + mu * sqrt_r(s2);
+    };
+    R r[2], J;
+    resid(a, r, J);
+    for (int it = 0; it < max_iter; ++it) {
+        const R rn = sqrt_r(r[0] * r[0] + r[1] * r[1]);
+        if (rn <= tol * scale(a)) break;
+        R f[4], C[16];
+        assemble(a, f);
+        tangent<R, LAW, SH>(f, mu, lam, C);
+        const R j00 = NA * C[4 * A + A], j01 = NA * C[4 * A + 2 + A];
+        const R j10 = NA * C[8 + 4 * A + A], j11 = NA * C[8 + 4 * A + 2 + A];
+        const R det = j00 * j11 - j01 * j10;
+        const R d0 = -(j11 * r[0] - j01 * r[1]) / det;
+        const R d1 = -(-j10 * r[0] + j00 * r[1]) / det;
+        R alpha = R(1);
+        bool accepted = false;
+        for (int ls = 0; ls < 11; ++ls) {
+            const R trial[2] = {a[0] + alpha * d0, a[1] + alpha * d1};
+            R rt[2], Jt;
+            resid(trial, rt, Jt);
+            if (Jt > R(0) && sqrt_r(rt[0] * rt[0] + rt[1] * rt[1]) < rn) {
+                a[0] = trial[0]; a[1] = trial[1];
+                r[0] = rt[0]; r[1] = rt[1];
+                J = Jt;
+                accepted = true;
+                break;
+            }
+            alpha *= R(0.5);
+        }
+        if (!accepted) break;
+    }
+    const R rn = sqrt_r(r[0] * r[0] + r[1] * r[1]);
+    return (rn <= R(1e-4) * scale(a)) && (J > R(0)) && finite_r(rn);
+}
+
+// Tangential stencil of the traction-wall extrapolation at position s of an edge of
+// length L: positions p[] and weights w[] (in units of 1/(2 dx)), and which entry is s.
+struct Stencil {
+    int p[3];
+    int w[3];
+    int self;
+};
+__device__ __forceinline__ Stencil tangential_stencil(int s, int L, bool periodic) {
+    Stencil t;
+    if (periodic || (s >= 1 && s <= L - 2)) {
+        t.p[0] = (s == 0) ? L - 1 : s - 1;
+        t.p[1] = (s + 1 == L) ? 0 : s + 1;
+        t.p[2] = s;
+        t.w[0] = -1; t.w[1] = 1; t.w[2] = 0;
+        t.self = 2;
+    } else if (s == 0) {
+        t.p[0] = 0; t.p[1] = 1; t.p[2] = 2;
+        t.w[0] = -3; t.w[1] = 4; t.w[2] = -1;
+        t.self = 0;
+    } else {
+        t.p[0] = L - 1; t.p[1] = L - 2; t.p[2] = L - 3;
+        t.w[0] = 3; t.w[1] = -4; t.w[2] = 1;
+        t.self = 0;
+    }
+    return t;
+}
+
+// Node index of row r (0 = wall row, 1 = first interior row) at position s2 of edge e.
+__device__ __forceinline__ int edge_node(const EdgeGeom& G, int nx, int ny, int r, int s2) {
+    if (G.A == 0) {
+        const int x = (G.NA < 0) ? r : nx - 1 - r;
+        return s2 * nx + x;
+    }
+    const int y = (G.NA < 0) ? r : ny - 1 - r;
+    return y * nx + s2;
+}
+
+}  // namespace lbm

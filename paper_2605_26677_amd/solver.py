@@ -1,0 +1,165 @@
+"""Device-resident solver state and thin wrappers of the C ABI (include/lbm.h).
+
+PyTorch supplies device memory and the stream; every compute step is a call into the
+HIP library.  A ``Solver`` owns the two population buffers, the displacement accumulator,
+the traction staging buffer, the fault word and the optional per-node parameter fields.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class EdgeData:
+    """Boundary data at one half step: per edge either a pair (uniform along the edge) or
+    a (2, L) float64 device tensor."""
+
+    def __init__(self, values=None):
+        self.c = L.lbm_edge_data()
+        self._keep = []
+        for e in range(4):
+            v = None if values is None else values[e]
+            if v is None:
+                continue
+            if isinstance(v, torch.Tensor):
+                t = v.to(torch.float64).contiguous()
+                self._keep.append(t)
+                self.c.field[e] = t.data_ptr()
+            else:
+                self.c.value[e][0] = float(v[0])
+                self.c.value[e][1] = float(v[1])
+
+
+class Solver:
+    def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
+                 bc=("periodic",) * 4, mu=0.1, lam=0.2, body=None, newton_max_iter=0,
+                 newton_tol=0.0, force_unstable=False, device="cuda"):
+        self.device = torch.device(device)
+        p = L.lbm_params()
+        p.nx, p.ny = int(nx), int(ny)
+        p.material = L.MATERIAL[material]
+        p.storage = L.STORAGE[storage]
+        for e in range(4):
+            p.bc[e] = L.BC[bc[e]]
+        p.newton_max_iter = int(newton_max_iter)
+        p.force_unstable = int(bool(force_unstable))
+        p.dx, p.c, p.omega, p.newton_tol = float(dx), float(c), float(omega), float(newton_tol)
+        self.p = p
+        self.lib = L.lib()
+        L.check(self.lib.lbm_check_params(ctypes.byref(p)), "lbm_check_params")
+        self.nx, self.ny = int(nx), int(ny)
+        self.storage, self.material = storage, material
+        self.dt = float(dx) / float(c)
+        pb = self.lib.lbm_pop_bytes(ctypes.byref(p))
+        self.pop = [torch.empty(pb, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.ustar = torch.zeros(self.lib.lbm_ustar_bytes(ctypes.byref(p)), dtype=torch.uint8, device=self.device)
+        self.aux = torch.zeros(self.lib.lbm_aux_bytes(ctypes.byref(p)), dtype=torch.uint8, device=self.device)
+        self.fault = torch.zeros(1, dtype=torch.int32, device=self.device)
+        s = L.lbm_state()
+        s.pop[0], s.pop[1] = self.pop[0].data_ptr(), self.pop[1].data_ptr()
+        s.cur = 0
+        s.ustar = self.ustar.data_ptr()
+        s.aux = self.aux.data_ptr()
+        s.fault = self.fault.data_ptr()
+        self.s = s
+        self.set_parameters(mu, lam, body)
+
+    # ------------------------------------------------------------ parameters
+    def set_parameters(self, mu, lam, body=None):
+        s = self.s
+        self.mu_t = self.lam_t = self.body_t = None
+        if np.isscalar(mu):
+            s.mu, s.mu0, s.mu_max = None, float(mu), float(mu)
+        else:
+            self.mu_t = torch.as_tensor(mu, dtype=torch.float32, device=self.device).contiguous()
+            s.mu, s.mu_max = self.mu_t.data_ptr(), float(self.mu_t.max())
+        if np.isscalar(lam):
+            s.lam, s.lam0, s.lam_max = None, float(lam), float(lam)
+        else:
+            self.lam_t = torch.as_tensor(lam, dtype=torch.float32, device=self.device).contiguous()
+            s.lam, s.lam_max = self.lam_t.data_ptr(), float(self.lam_t.max())
+        if body is None:
+            s.body, s.b0[0], s.b0[1] = None, 0.0, 0.0
+        elif isinstance(body, (tuple, list)):
+            s.body, s.b0[0], s.b0[1] = None, float(body[0]), float(body[1])
+        else:
+            self.body_t = torch.as_tensor(body, dtype=torch.float32, device=self.device).contiguous()
+            s.body = self.body_t.data_ptr()
+
+    # ------------------------------------------------------------ sizes
+    @property
+    def plane_stride(self):
+        return int(self.lib.lbm_plane_stride(ctypes.byref(self.p)))
+
+    @property
+    def record_bytes(self):
+        return int(self.lib.lbm_record_bytes(ctypes.byref(self.p)))
+
+    @property
+    def real_dtype(self):
+        return torch.float64 if self.storage == "f64" else torch.float32
+
+    def new_record(self):
+        return torch.empty((6, self.ny, self.nx), dtype=self.real_dtype, device=self.device)
+
+    # ------------------------------------------------------------ entry points
+    def init(self, v0, u0=None, r0=0.0):
+        self._v0 = torch.as_tensor(v0, dtype=torch.float64, device=self.device).contiguous()
+        self._u0 = None if u0 is None else torch.as_tensor(u0, dtype=torch.float64, device=self.device).contiguous()
+        self.s.cur = 0
+        self.fault.zero_()
+        self.ustar.zero_()
+        L.check(self.lib.lbm_init(ctypes.byref(self.p), ctypes.byref(self.s), _ptr(self._v0), _ptr(self._u0),
+                                  float(r0), _stream()), "lbm_init")
+
+    def step(self, n, r_n=1.0, r_np1=1.0, edges=None, record=None):
+        ed = edges if isinstance(edges, EdgeData) else EdgeData(edges)
+        L.check(self.lib.lbm_step(ctypes.byref(self.p), ctypes.byref(self.s), int(n), float(r_n), float(r_np1),
+                                  ctypes.byref(ed.c), _ptr(record), _stream()), "lbm_step")
+
+    def moments(self, r_n=1.0):
+        out = torch.empty((6, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        L.check(self.lib.lbm_moments(ctypes.byref(self.p), ctypes.byref(self.s), float(r_n), _ptr(out),
+                                     _stream()), "lbm_moments")
+        return out
+
+    def displacement(self, r_n=1.0):
+        out = torch.empty((2, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        L.check(self.lib.lbm_displacement(ctypes.byref(self.p), ctypes.byref(self.s), float(r_n), _ptr(out),
+                                          _stream()), "lbm_displacement")
+        return out
+
+    def record_state(self, r_n, out):
+        L.check(self.lib.lbm_record_state(ctypes.byref(self.p), ctypes.byref(self.s), float(r_n), _ptr(out),
+                                          _stream()), "lbm_record_state")
+        return out
+
+    def diagnostics(self, r_n=1.0):
+        out = torch.empty(L.LBM_DIAG_COUNT, dtype=torch.float64, device=self.device)
+        scratch = torch.empty(self.lib.lbm_diag_scratch_bytes(ctypes.byref(self.p)), dtype=torch.uint8,
+                              device=self.device)
+        L.check(self.lib.lbm_diagnostics(ctypes.byref(self.p), ctypes.byref(self.s), float(r_n), _ptr(out),
+                                         _ptr(scratch), _stream()), "lbm_diagnostics")
+        return out
+
+    def populations(self):
+        """Current post-collision populations as a (4, 6, ny, nx) view in the storage dtype
+        (shifted storages hold f* - (0, 0, 1/4, 0, 0, 1/4))."""
+        dt = {"f32": torch.float32, "f16": torch.float16, "f64": torch.float64}[self.storage]
+        st = self.plane_stride
+        buf = self.pop[self.s.cur].view(dt)
+        n = self.nx * self.ny
+        return torch.as_strided(buf, (4, 6, self.ny, self.nx), (6 * st, st, self.nx, 1))
+
+    def faults(self):
+        return int(self.fault.item())

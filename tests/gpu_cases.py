@@ -1,0 +1,118 @@
+"""Shared case definitions for the GPU parity tests: one description drives both the HIP
+library (through the C ABI) and the FP64 oracle, from the same seeded inputs."""
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+import lbm_inputs as li
+
+
+@dataclass
+class Case:
+    name: str
+    nx: int
+    ny: int
+    c: float
+    omega: float
+    steps: int
+    law: str = "lognh"
+    mu: object = 0.1
+    lam: object = 0.2
+    body: object = None                  # None, (b1, b2) uniform, or (2, ny, nx) float32-exact field
+    ramp_steps: int = 0                  # r(n) = min(1, n / ramp_steps); 0 = no ramp
+    kinds: Sequence[str] = ("periodic",) * 4
+    data: Sequence = field(default_factory=lambda: [(0.0, 0.0)] * 4)
+    v0: Optional[np.ndarray] = None
+    u0: Optional[np.ndarray] = None
+    dx: float = 1.0
+
+    def ramp(self, n):
+        return 1.0 if self.ramp_steps == 0 else min(1.0, n / self.ramp_steps)
+
+
+def shear_wave_case(steps=200):
+    """64 x 64 periodic shear wave, log-NH mu = 0.1, lam = 0.2, c = 2, omega = 2."""
+    return Case("shear_wave_64", 64, 64, 2.0, 2.0, steps, v0=li.shear_wave_v0(64, 64))
+
+
+def random_field_case(nx, ny, steps, law="lognh", rms=5e-3, seeds=(301, 302)):
+    v0 = np.stack([li.gaussian_random_field(nx, ny, seeds[0], rms),
+                   li.gaussian_random_field(nx, ny, seeds[1], rms)])
+    return Case(f"random_{law}_{nx}x{ny}", nx, ny, 2.0, 2.0, steps, law=law, v0=v0)
+
+
+def block_case(nx=96, ny=80, steps=300, law="lognh", fields=False):
+    """Block with a velocity wall (v = 0) on the left and traction-free walls elsewhere
+    under a ramped downward body force."""
+    mu = li.lognormal_field(nx, ny, 401, 0.1, 0.3, 8.0) if fields else 0.1
+    lam = li.lognormal_field(nx, ny, 402, 0.3, 0.3, 8.0) if fields else 0.3
+    body = li.uniform_body(nx, ny, (0.0, -2e-4)) if fields else (0.0, -2e-4)
+    v0 = np.stack([li.gaussian_random_field(nx, ny, 403, 1e-3), li.gaussian_random_field(nx, ny, 404, 1e-3)])
+    return Case(f"block_{law}_{'fields' if fields else 'uniform'}", nx, ny, 2.5, 1.99, steps, law=law,
+                mu=mu, lam=lam, body=body, ramp_steps=50,
+                kinds=("velocity", "traction", "traction", "traction"), v0=v0)
+
+
+def mixed_case(nx=40, ny=36, steps=120, law="lognh"):
+    """Every edge kind with nonzero data: moving velocity wall, loaded traction walls."""
+    v0 = np.stack([li.gaussian_random_field(nx, ny, 11, 1e-3), li.gaussian_random_field(nx, ny, 12, 1e-3)])
+    u0 = np.stack([li.gaussian_random_field(nx, ny, 13, 0.05), li.gaussian_random_field(nx, ny, 14, 0.05)])
+    return Case(f"mixed_{law}", nx, ny, 2.5, 1.95, steps, law=law, mu=0.1, lam=0.25,
+                body=(1e-5, -3e-5), ramp_steps=20,
+                kinds=("velocity", "traction", "traction", "velocity"),
+                data=[(1e-4, -2e-4), (3e-4, 1e-4), (-2e-4, 2e-4), (0.0, 1e-4)], v0=v0, u0=u0)
+
+
+# ------------------------------------------------------------------ oracle side
+
+def oracle_problem(case):
+    from oracle import lbm
+    body = case.body
+    if body is not None and isinstance(body, tuple):
+        body = np.broadcast_to(np.array(body, dtype=np.float64)[:, None, None], (2, case.ny, case.nx)).copy()
+    edges = [lbm.Edge(k, (lambda t, d=d: np.array(d, dtype=np.float64))) for k, d in zip(case.kinds, case.data)]
+    return lbm.Problem(nx=case.nx, ny=case.ny, c=case.c, omega=case.omega, law=case.law, mu=case.mu,
+                       lam=case.lam, dx=case.dx, body=body, ramp=case.ramp, edges=edges)
+
+
+def run_oracle(case, steps=None):
+    from oracle import lbm
+    pb = oracle_problem(case)
+    st = lbm.initial_state(pb, case.v0, case.u0)
+    U, u = lbm.run(pb, st, case.steps if steps is None else steps)
+    fstar = lbm.post_collision(pb, st)
+    return U, u, fstar
+
+
+# ------------------------------------------------------------------ library side
+
+def make_solver(case, storage):
+    from paper_2605_26677_amd.solver import Solver
+    return Solver(case.nx, case.ny, c=case.c, omega=case.omega, dx=case.dx, material=case.law,
+                  storage=storage, bc=tuple(case.kinds), mu=case.mu, lam=case.lam, body=case.body)
+
+
+def run_library(case, storage, steps=None):
+    import torch
+    sv = make_solver(case, storage)
+    sv.init(case.v0, case.u0, r0=case.ramp(0))
+    N = case.steps if steps is None else steps
+    for n in range(N):
+        sv.step(n, case.ramp(n), case.ramp(n + 1), edges=list(case.data))
+    U = sv.moments(case.ramp(N))
+    u = sv.displacement(case.ramp(N))
+    torch.cuda.synchronize()
+    return sv, U.cpu().numpy(), u.cpu().numpy()
+
+
+def shifted_state(U):
+    """Oracle U (unshifted F) -> (v, F - I)."""
+    out = U.copy()
+    out[2] -= 1.0
+    out[5] -= 1.0
+    return out
+
+
+def rel_l2(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum()) / np.sqrt((b ** 2).sum()))

@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point that
+include/lbm.h declares, and its size and validation functions behave as documented.
+No call here touches the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2605_26677_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in L.SIGNATURES, name
+
+
+def _params(nx=64, ny=64, storage=L.LBM_F32_SHIFTED, bc=(0, 0, 0, 0), c=2.0, omega=2.0):
+    p = L.lbm_params()
+    p.nx, p.ny, p.storage, p.material = nx, ny, storage, L.LBM_LOGNH
+    for e in range(4):
+        p.bc[e] = bc[e]
+    p.dx, p.c, p.omega = 1.0, c, omega
+    return p
+
+
+def test_sizes():
+    lib = L.lib()
+    p = _params(8192, 8192)
+    st = lib.lbm_plane_stride(ctypes.byref(p))
+    assert st >= 8192 * 8192 and st % 64 == 0 and st % 4096 != 0
+    assert lib.lbm_pop_bytes(ctypes.byref(p)) == 24 * st * 4
+    assert lib.lbm_ustar_bytes(ctypes.byref(p)) == 4 * 8192 * 8192 * 4
+    assert lib.lbm_record_bytes(ctypes.byref(p)) == 6 * 8192 * 8192 * 4
+    p64 = _params(100, 37, storage=L.LBM_F64_PLAIN)
+    assert lib.lbm_pop_bytes(ctypes.byref(p64)) == 24 * lib.lbm_plane_stride(ctypes.byref(p64)) * 8
+    p16 = _params(100, 37, storage=L.LBM_F16_SHIFTED)
+    assert lib.lbm_pop_bytes(ctypes.byref(p16)) == 24 * lib.lbm_plane_stride(ctypes.byref(p16)) * 2
+    assert lib.lbm_adj_bytes(ctypes.byref(p16)) == 24 * lib.lbm_plane_stride(ctypes.byref(p16)) * 4
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda p: setattr(p, "nx", 2), L.LBM_ERR_ARG),
+    (lambda p: setattr(p, "storage", 7), L.LBM_ERR_ARG),
+    (lambda p: setattr(p, "material", -1), L.LBM_ERR_ARG),
+    (lambda p: p.bc.__setitem__(0, L.LBM_VELOCITY), L.LBM_ERR_ARG),      # unpaired periodic
+    (lambda p: setattr(p, "omega", 2.5), L.LBM_ERR_ARG),
+    (lambda p: setattr(p, "c", 0.0), L.LBM_ERR_ARG),
+    (lambda p: setattr(p, "nx", 70000), L.LBM_ERR_ARG),                    # nx * ny >= 2^31
+])
+def test_parameter_validation(mutate, code):
+    lib = L.lib()
+    p = _params(ny=40000)
+    p.ny = 64
+    mutate(p)
+    if p.nx == 70000:
+        p.ny = 40000
+    assert lib.lbm_check_params(ctypes.byref(p)) == code
+
+
+def test_walls_need_four_nodes():
+    lib = L.lib()
+    p = _params(3, 16, bc=(1, 2, 0, 0))
+    assert lib.lbm_check_params(ctypes.byref(p)) == L.LBM_ERR_ARG
+    p.nx = 4
+    assert lib.lbm_check_params(ctypes.byref(p)) == L.LBM_OK
+
+
+def test_cfl_audit():
+    """sqrt(lam + 2 mu) / c <= 1/2: c = 2 passes and c = 1 is refused for mu = 0.1,
+    lam = 0.2 (the oracle's linear symbol shows the c = 1 step is unstable)."""
+    lib = L.lib()
+    p = _params(c=2.0)
+    assert lib.lbm_check_cfl(ctypes.byref(p), 0.1, 0.2) == L.LBM_OK
+    p.c = 1.0
+    assert lib.lbm_check_cfl(ctypes.byref(p), 0.1, 0.2) == L.LBM_ERR_CFL
+
+
+def test_calls_reject_missing_buffers():
+    lib = L.lib()
+    p = _params()
+    s = L.lbm_state()
+    assert lib.lbm_step(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, None, None, None) == L.LBM_ERR_ARG
+    assert lib.lbm_init(ctypes.byref(p), ctypes.byref(s), None, None, 0.0, None) == L.LBM_ERR_ARG
+    a = L.lbm_adj_state()
+    assert lib.lbm_adjoint_step(ctypes.byref(p), ctypes.byref(s), ctypes.byref(a), 0, 1.0, None, None,
+                                None) == L.LBM_ERR_ARG
+    for st in range(5):
+        assert lib.lbm_status_string(st)
