@@ -27,6 +27,57 @@ METRIC = "MLUPS fwd & fwd+adjoint at 8192², FP32 vs FP64, % of HBM roofline"
 BYTES_PER_LU = {"f32": 96 + 96 + 32, "f16": 48 + 48 + 32, "f64": 192 + 192 + 32}
 
 
+PROFILE_PMC = os.path.join(ROOT, "profiles", "step_f32_lognh_periodic_8192_pmc.txt")
+STEP_SOURCES = ("lbm_forward.hip", "lbm_device.hpp", "lbm_kernel_util.hpp", "lbm_internal.hpp")
+
+
+def step_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_26677_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n):
+    """HBM bytes per step launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (scaled by the same counters on a copy of known size), or None when the
+    summary is missing, was taken at another size, or the kernel source changed since."""
+    if not os.path.exists(PROFILE_PMC):
+        return None
+    kv = {}
+    with open(PROFILE_PMC) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != step_source_hash() or kv.get("grid") != f"{n}x{n}":
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def copy_ceiling():
+    """Bandwidth of a plain device copy (torch elementwise kernel, 4 GiB read + 4 GiB
+    written): the practical ceiling beside the published 8 TB/s."""
+    import torch
+    a = torch.ones(2 ** 30, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 2 ** 32 / (ms * 1e-3) / 1e9
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -59,6 +110,52 @@ def time_forward(n, storage, steps, warmup, v0, law="lognh"):
     return ms, faults
 
 
+def time_forward_adjoint(n, steps, K, nprobe=16):
+    """Forward + checkpointed adjoint of the probe-displacement loss with per-node mu, lam
+    (log-normal, median 0.1 / 0.2, sigma_log 0.3, correlation length 32), FP32 storage."""
+    import torch
+    import lbm_inputs as li
+    from paper_2605_26677_amd.rollout import RolloutConfig, rollout
+    mu = torch.tensor(li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0), device="cuda", requires_grad=True)
+    lam = torch.tensor(li.lognormal_field(n, n, 402, 0.2, 0.3, 32.0), device="cuda", requires_grad=True)
+    body = torch.zeros((2, n, n), dtype=torch.float64, device="cuda", requires_grad=True)
+    v0 = torch.tensor(make_inputs(n), device="cuda", requires_grad=True)
+    ys, xs = li.random_probes(n, n, nprobe, 405)
+    probes = torch.tensor(ys * n + xs, dtype=torch.int64)
+    # c from the audit bound sqrt(lam_max + 2 mu_max) / c <= 1/2 with margin
+    c = float(np.ceil(2.0 * np.sqrt(float(lam.max()) + 2 * float(mu.max())) * 1.1 * 4) / 4)
+    cfg = RolloutConfig(nx=n, ny=n, c=c, omega=2.0, nsteps=steps, probes=probes, storage="f32",
+                        checkpoint_every=K)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    u = rollout(mu, lam, body, v0, cfg)
+    e1.record()
+    (u ** 2).sum().backward()
+    e2.record()
+    torch.cuda.synchronize()
+    t_f, t_b = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    mem = torch.cuda.max_memory_allocated() / 2 ** 30
+    ok = all(torch.isfinite(t.grad).all().item() for t in (mu, lam, v0))
+    return dict(ms_fwd=t_f, ms_bwd=t_b, mlups=n * n * steps / ((t_f + t_b) * 1e-3) / 1e6,
+                bwd_over_fwd=t_b / t_f, peak_mem_GiB=mem, grads_finite=ok, steps=steps, K=K, c=c)
+
+
+def profile_run(n, steps):
+    """Short run for rocprofv3: a plain device copy of known size (counter calibration)
+    followed by FP32 steps of the benchmark workload."""
+    import torch
+    a = torch.ones(2 ** 29, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    v0 = make_inputs(n)
+    ms, faults = time_forward(n, "f32", steps, 3, v0)
+    print(json.dumps({"profile": True, "copy_bytes_each_way": 2 ** 31, "ms_per_step": ms, "faults": faults}))
+
+
 def cpu_baseline(budget_s=20.0):
     """The FP64 oracle on the host: 1024 x 1024 sample of the same workload."""
     from oracle import lbm as olbm
@@ -87,6 +184,10 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=500)
     ap.add_argument("--only", default="", help="comma list of f32,f64,f16 to time (default all)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=200)
+    ap.add_argument("--adjoint-every", type=int, default=50)
+    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (copy + 20 f32 steps)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -94,6 +195,9 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     n = args.size
+    if args.profile:
+        profile_run(n, 20)
+        return
     log(f"bench: generating {n}x{n} inputs")
     v0 = make_inputs(n)
     only = [s for s in args.only.split(",") if s] or ["f32", "f64", "f16"]
@@ -107,8 +211,15 @@ def main():
         res[storage] = dict(ms_per_step=ms, mlups=mlups, algorithmic_GBps=gbs,
                             frac_hbm=gbs * 1e9 / PEAK_HBM, faults=faults, steps=steps)
         log(f"bench: {storage}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {gbs:.0f} GB/s")
+    if not args.no_adjoint:
+        log(f"bench: forward + adjoint, {args.adjoint_steps} steps, checkpoint every {args.adjoint_every}")
+        res["fwd_adj_f32"] = time_forward_adjoint(n, args.adjoint_steps, args.adjoint_every)
+        log(f"bench: fwd+adj: {res['fwd_adj_f32']}")
+    log("bench: copy ceiling")
+    copy_gbs = copy_ceiling()
     main_key = "f32" if "f32" in res else only[0]
     r = res[main_key]
+    traffic = measured_traffic(n) if main_key == "f32" else None
     out = {
         "metric": METRIC, "value": r["mlups"], "unit": "MLUPS", "n_gpus": 1,
         "steps": r["steps"], "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
@@ -118,7 +229,9 @@ def main():
                                f"log-NH mu=0.1 lam=0.2, c=2, omega=2, {main_key} storage",
                    "grid": [n, n], "storage": main_key},
         "roofline": {"bound": "hbm", "achieved": r["algorithmic_GBps"], "peak": PEAK_HBM / 1e9,
-                     "unit": "GB/s", "frac": r["frac_hbm"], "traffic": None},
+                     "unit": "GB/s", "frac": r["frac_hbm"], "traffic": traffic,
+                     "algorithmic_bytes_per_launch": BYTES_PER_LU[main_key] * n * n,
+                     "copy_ceiling_GBps": copy_gbs},
         "variants": res,
     }
     if not args.no_cpu:

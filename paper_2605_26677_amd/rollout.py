@@ -1,0 +1,193 @@
+"""Differentiable rollout: forward steps through lbm_step, gradients through the
+hand-written adjoint kernels (lbm_adjoint_step, lbm_adjoint_init) with checkpointed
+recomputation.
+
+The quantity differentiated is the displacement at probe nodes after N steps,
+u^N(X_p) (eq:trapezoid-u), with respect to per-node mu and lam fields, the per-node body
+force field b (the force at level n is r(n) b) and the initial velocity v0.
+
+Checkpointing: the forward pass keeps the post-collision populations every K levels
+("every-K"); the backward pass walks the segments in reverse, restores the segment's
+snapshot, replays it while recording the state U^m of each level (lbm_step(record)),
+then runs the adjoint steps of that segment from its last level down to its first.
+Memory: ceil((N + 1) / K) snapshots of lbm_pop_bytes() plus K + 1 records of
+lbm_record_bytes().  ``schedule="nested"`` splits the replay recursively (segment
+lengths K1 > K2 > ... ) for runs whose snapshots would not fit a memory budget.
+"""
+import ctypes
+from dataclasses import dataclass, field
+from typing import Callable, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+from .solver import EdgeData, Solver, _ptr, _stream
+
+
+@dataclass
+class RolloutConfig:
+    nx: int
+    ny: int
+    c: float
+    omega: float
+    nsteps: int
+    probes: torch.Tensor                              # (P,) int node indices b * nx + a
+    dx: float = 1.0
+    material: str = "lognh"
+    storage: str = "f32"
+    bc: Sequence[str] = ("periodic",) * 4
+    ramp: Callable[[int], float] = lambda n: 1.0      # r(n)
+    edges: Optional[Callable[[int], Sequence]] = None  # n -> data at t^{n+1/2} (4 pairs)
+    u0: Optional[torch.Tensor] = None
+    checkpoint_every: int = 100
+    levels: Sequence[int] = field(default_factory=list)   # nested segment lengths, outermost first
+    newton_max_iter: int = 0
+
+
+def _edges(cfg, n):
+    return EdgeData(None if cfg.edges is None else cfg.edges(n))
+
+
+class _Adjoint:
+    """Device buffers and the C struct of the adjoint state."""
+
+    def __init__(self, sv: Solver, cfg: RolloutConfig, ubar: torch.Tensor):
+        dev = sv.device
+        nb = sv.lib.lbm_adj_bytes(ctypes.byref(sv.p))
+        self.buf = [torch.zeros(nb, dtype=torch.uint8, device=dev) for _ in range(2)]
+        n = sv.nx * sv.ny
+        self.g_mu = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.g_lam = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.g_body = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+        self.g_v0 = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+        self.aux = torch.zeros(sv.lib.lbm_aux_bytes(ctypes.byref(sv.p)), dtype=torch.uint8, device=dev)
+        self.probe = cfg.probes.to(device=dev, dtype=torch.int32).contiguous()
+        self.ubar = ubar.to(device=dev, dtype=torch.float64).contiguous()
+        a = L.lbm_adj_state()
+        a.adj[0], a.adj[1] = self.buf[0].data_ptr(), self.buf[1].data_ptr()
+        a.cur = 0
+        a.g_mu, a.g_lam, a.g_body = self.g_mu.data_ptr(), self.g_lam.data_ptr(), self.g_body.data_ptr()
+        a.probe, a.ubar = self.probe.data_ptr(), self.ubar.data_ptr()
+        a.nprobe = int(self.probe.numel())
+        a.nsteps = int(cfg.nsteps)
+        a.aux = self.aux.data_ptr()
+        self.a = a
+
+    def step(self, sv, cfg, m, record):
+        L.check(sv.lib.lbm_adjoint_step(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), int(m),
+                                        float(cfg.ramp(m)), ctypes.byref(_edges(cfg, m).c), _ptr(record),
+                                        _stream()), "lbm_adjoint_step")
+
+    def init(self, sv, cfg, v0, u0):
+        L.check(sv.lib.lbm_adjoint_init(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), _ptr(v0),
+                                        _ptr(u0), float(cfg.ramp(0)), _ptr(self.g_v0), _stream()),
+                "lbm_adjoint_init")
+
+
+def _restore(sv, snap):
+    sv.pop[sv.s.cur].copy_(snap[0])
+
+
+def _step_to_snapshot(sv, cfg, n):
+    """Step n -> n + 1 and keep (f*^{n+1}, U^{n+1}); the record comes from the step kernel
+    itself, exactly as a replay would produce it, so every schedule sees the same records."""
+    rec = sv.new_record()
+    sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=rec)
+    return (sv.pop[sv.s.cur].clone(), rec)
+
+
+def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
+    """Adjoint levels end-1 .. start, starting from the snapshot of level `start`."""
+    _restore(sv, snap)
+    recs[0].copy_(snap[1])
+    for n in range(start, end - 1):
+        sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=recs[n + 1 - start])
+    for m in range(end - 1, start - 1, -1):
+        adj.step(sv, cfg, m, recs[m - start])
+
+
+def _reverse_nested(sv, cfg, adj, start, end, snap, lengths, recs):
+    """Reverse levels [start, end) holding only the snapshot of `start`: split into
+    sub-segments of lengths[0], re-run forward to take their snapshots, recurse."""
+    if not lengths or end - start <= len(recs):
+        _reverse_segment(sv, cfg, adj, start, end, snap, recs)
+        return
+    K = lengths[0]
+    bounds = list(range(start, end, K)) + [end]
+    snaps = [snap]
+    _restore(sv, snap)
+    for i in range(len(bounds) - 2):
+        for n in range(bounds[i], bounds[i + 1] - 1):
+            sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n))
+        snaps.append(_step_to_snapshot(sv, cfg, bounds[i + 1] - 1))
+    for i in range(len(bounds) - 2, -1, -1):
+        _reverse_nested(sv, cfg, adj, bounds[i], bounds[i + 1], snaps[i], lengths[1:], recs)
+        snaps.pop()
+
+
+class LBMRollout(torch.autograd.Function):
+    """u^N at the probes (2, P) as a differentiable function of (mu, lam, body, v0).
+
+    mu, lam (ny, nx) and body (2, ny, nx) are used by the library in float32 (pass float64
+    leaves holding float32-representable values to receive FP64 gradients); v0 (2, ny, nx)
+    is used in float64.  Gradients are accumulated in FP64 and returned in each input's
+    dtype."""
+
+    @staticmethod
+    def forward(ctx, mu, lam, body, v0, cfg: RolloutConfig):
+        sv = Solver(cfg.nx, cfg.ny, c=cfg.c, omega=cfg.omega, dx=cfg.dx, material=cfg.material,
+                    storage=cfg.storage, bc=tuple(cfg.bc), mu=mu.detach(), lam=lam.detach(),
+                    body=body.detach(), newton_max_iter=cfg.newton_max_iter, device=mu.device)
+        v0d = v0.detach().to(torch.float64).contiguous()
+        u0 = None if cfg.u0 is None else cfg.u0.to(device=mu.device, dtype=torch.float64).contiguous()
+        sv.init(v0d, u0, r0=cfg.ramp(0))
+        N = cfg.nsteps
+        K = cfg.levels[0] if cfg.levels else cfg.checkpoint_every
+        snaps = {0: (sv.pop[sv.s.cur].clone(), sv.record_state(cfg.ramp(0), sv.new_record()))}
+        for n in range(N):
+            if (n + 1) % K == 0:
+                snaps[n + 1] = _step_to_snapshot(sv, cfg, n)
+            else:
+                sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n))
+        u = sv.displacement(cfg.ramp(N))
+        probes = cfg.probes.to(device=mu.device, dtype=torch.long)
+        out = u.reshape(2, -1)[:, probes]
+        ctx.sv, ctx.cfg, ctx.snaps, ctx.v0, ctx.u0 = sv, cfg, snaps, v0d, u0
+        ctx.dtypes = (mu.dtype, lam.dtype, body.dtype, v0.dtype)
+        ctx.faults = sv.faults
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        sv, cfg, snaps = ctx.sv, ctx.cfg, ctx.snaps
+        N = cfg.nsteps
+        adj = _Adjoint(sv, cfg, grad_out.detach())
+        if cfg.levels:
+            K0 = cfg.levels[0]
+            inner = list(cfg.levels[1:])
+            nrec = (inner[-1] if inner else K0) + 1
+            recs = [sv.new_record() for _ in range(nrec)]
+            bounds = list(range(0, N + 1, K0))
+            if bounds[-1] != N + 1:
+                bounds.append(N + 1)
+            for i in range(len(bounds) - 2, -1, -1):
+                _reverse_nested(sv, cfg, adj, bounds[i], bounds[i + 1], snaps[bounds[i]], inner, recs)
+        else:
+            K = cfg.checkpoint_every
+            recs = [sv.new_record() for _ in range(K + 1)]
+            starts = list(range(0, N + 1, K))
+            for i in range(len(starts) - 1, -1, -1):
+                start = starts[i]
+                end = min(start + K, N + 1)
+                _reverse_segment(sv, cfg, adj, start, end, snaps[start], recs)
+        adj.init(sv, cfg, ctx.v0, ctx.u0)
+        ny, nx = cfg.ny, cfg.nx
+        g_mu = adj.g_mu.view(ny, nx).to(ctx.dtypes[0])
+        g_lam = adj.g_lam.view(ny, nx).to(ctx.dtypes[1])
+        g_body = adj.g_body.view(2, ny, nx).to(ctx.dtypes[2])
+        g_v0 = adj.g_v0.view(2, ny, nx).to(ctx.dtypes[3])
+        return g_mu, g_lam, g_body, g_v0, None
+
+
+def rollout(mu, lam, body, v0, cfg: RolloutConfig):
+    return LBMRollout.apply(mu, lam, body, v0, cfg)

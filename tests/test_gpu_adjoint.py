@@ -1,0 +1,134 @@
+"""Parity of the HIP adjoint (lbm_adjoint_step, lbm_adjoint_init behind LBMRollout) with
+the oracle's hand-written adjoint, schedule independence of the checkpointing, and
+agreement with central differences of the FP64 forward.
+
+Bars (relative L2 of each gradient field against the oracle):
+  F64 storage: 1e-9 (same FP64 arithmetic, different order and F carried plainly on the
+      forward side);
+  F32 storage: 1e-4 (the gradient accuracy the FP32 adjoint is held to).
+Directional derivatives of the FP32 adjoint against FP64 central differences: 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as li
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(kind, nx=24, ny=20, steps=30):
+    mu = li.lognormal_field(nx, ny, 401, 0.1, 0.3, 4.0)
+    lam = li.lognormal_field(nx, ny, 402, 0.2, 0.3, 4.0)
+    body = li.uniform_body(nx, ny, (2e-4, -5e-4))
+    v0 = np.stack([li.gaussian_random_field(nx, ny, 403, 1e-3), li.gaussian_random_field(nx, ny, 404, 1e-3)])
+    ys, xs = li.random_probes(nx, ny, 6, 405)
+    if kind == "periodic":
+        bc, data, omega = ("periodic",) * 4, [(0, 0)] * 4, 2.0
+    elif kind == "walls":
+        bc, data, omega = ("velocity", "traction", "traction", "traction"), [(0, 0), (2e-4, 0), (0, 0), (0, -3e-4)], 1.99
+    else:
+        bc, data, omega = ("traction", "traction", "velocity", "traction"), [(1e-4, 0), (0, 0), (1e-4, -1e-4), (0, 2e-4)], 1.95
+    return dict(nx=nx, ny=ny, steps=steps, mu=mu, lam=lam, body=body, v0=v0, probes=(ys, xs), bc=bc, data=data,
+                omega=omega, c=2.5, ramp=lambda n: min(1.0, n / 10))
+
+
+def _oracle_grads(cs, law="lognh"):
+    from oracle import adjoint as adj
+    from oracle import lbm
+    edges = [lbm.Edge(k, (lambda t, d=d: np.array(d, dtype=float))) for k, d in zip(cs["bc"], cs["data"])]
+    pb = lbm.Problem(nx=cs["nx"], ny=cs["ny"], c=cs["c"], omega=cs["omega"], law=law, mu=cs["mu"],
+                     lam=cs["lam"], body=cs["body"], ramp=cs["ramp"], edges=edges)
+    target = np.zeros((2, len(cs["probes"][0])))
+    return adj.gradients(pb, cs["v0"], cs["steps"], cs["probes"], target)
+
+
+def _gpu_grads(cs, storage, law="lognh", **kw):
+    from paper_2605_26677_amd.rollout import RolloutConfig, rollout
+    dev = "cuda"
+    ys, xs = cs["probes"]
+    probes = torch.tensor(ys * cs["nx"] + xs, dtype=torch.int64)
+    cfg = RolloutConfig(nx=cs["nx"], ny=cs["ny"], c=cs["c"], omega=cs["omega"], nsteps=cs["steps"], probes=probes,
+                        material=law, storage=storage, bc=cs["bc"], ramp=cs["ramp"],
+                        edges=lambda n: cs["data"], **kw)
+    # float64 leaves holding float32-exact values: the library computes with them in
+    # float32 and returns FP64 gradients
+    mu = torch.tensor(cs["mu"], dtype=torch.float64, device=dev, requires_grad=True)
+    lam = torch.tensor(cs["lam"], dtype=torch.float64, device=dev, requires_grad=True)
+    body = torch.tensor(cs["body"], dtype=torch.float64, device=dev, requires_grad=True)
+    v0 = torch.tensor(cs["v0"], dtype=torch.float64, device=dev, requires_grad=True)
+    u = rollout(mu, lam, body, v0, cfg)
+    loss = (u.double() ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    g = dict(mu=mu.grad.double().cpu().numpy(), lam=lam.grad.double().cpu().numpy(),
+             body=body.grad.double().cpu().numpy(), v0=v0.grad.double().cpu().numpy())
+    return float(loss.detach()), g
+
+
+def _rel(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum()) / np.sqrt((b ** 2).sum()))
+
+
+@pytest.mark.parametrize("kind", ["periodic", "walls", "mixed"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("law", ["lognh", "svk"])
+def test_adjoint_matches_oracle(kind, storage, law):
+    cs = _case(kind)
+    Lo, go = _oracle_grads(cs, law)
+    Lg, gg = _gpu_grads(cs, storage, law, checkpoint_every=7)
+    errs = {k: _rel(gg[k], go[k]) for k in go}
+    print(f"\n[adjoint {kind} {law} {storage}] loss rel {abs(Lg - Lo) / Lo:.2e} " +
+          " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    bar = 1e-9 if storage == "f64" else 1e-4
+    assert abs(Lg - Lo) <= (1e-10 if storage == "f64" else 1e-5) * Lo
+    for k, e in errs.items():
+        assert e <= bar, (k, e)
+
+
+def test_checkpoint_schedules_agree_bitwise():
+    """Replay is deterministic, so every-K with different K and the nested schedule give
+    identical gradients."""
+    cs = _case("walls", steps=40)
+    _, g1 = _gpu_grads(cs, "f32", checkpoint_every=1)
+    _, g2 = _gpu_grads(cs, "f32", checkpoint_every=9)
+    _, g3 = _gpu_grads(cs, "f32", checkpoint_every=40)
+    _, g4 = _gpu_grads(cs, "f32", levels=[16, 4])
+    for k in g1:
+        assert np.array_equal(g1[k], g2[k]) and np.array_equal(g1[k], g3[k]) and np.array_equal(g1[k], g4[k]), k
+
+
+def test_adjoint_against_fp64_central_differences():
+    """Directional derivatives of the FP32 adjoint gradient vs central differences of the
+    FP64 forward on the GPU (96 x 80 block with walls, 200 steps, 4 random directions).
+    Parameters live in float32, so the exact perturbed values p+ and p- are used."""
+    from paper_2605_26677_amd.rollout import RolloutConfig, rollout
+    cs = _case("walls", nx=96, ny=80, steps=200)
+    _, g = _gpu_grads(cs, "f32", checkpoint_every=50)
+    ys, xs = cs["probes"]
+    probes = torch.tensor(ys * cs["nx"] + xs, dtype=torch.int64)
+    cfg = RolloutConfig(nx=cs["nx"], ny=cs["ny"], c=cs["c"], omega=cs["omega"], nsteps=cs["steps"], probes=probes,
+                        storage="f64", bc=cs["bc"], ramp=cs["ramp"], edges=lambda n: cs["data"])
+
+    def loss(p):
+        with torch.no_grad():
+            u = rollout(*(torch.tensor(p[k], device="cuda", dtype=torch.float32 if k != "v0" else torch.float64)
+                          for k in ("mu", "lam", "body", "v0")), cfg)
+        return float((u.double() ** 2).sum())
+
+    base = {k: cs[k] for k in ("mu", "lam", "body", "v0")}
+    scale = dict(mu=0.1, lam=0.2, body=5e-4, v0=1e-3)
+    eps = 1e-3
+    for d in li.fd_directions({k: base[k].shape for k in base}, 4, 406):
+        plus, minus = {}, {}
+        for k in base:
+            step = eps * scale[k] * d[k]
+            if k == "v0":
+                plus[k], minus[k] = base[k] + step, base[k] - step
+            else:
+                plus[k] = li.round_f32(base[k] + step)
+                minus[k] = li.round_f32(base[k] - step)
+        fd = loss(plus) - loss(minus)
+        an = sum((g[k] * (plus[k] - minus[k])).sum() for k in base)
+        print(f"\nFD {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
+        assert abs(fd - an) <= 1e-4 * abs(fd)
