@@ -17,13 +17,18 @@
  *    dt = dx / c (Sec. 2.1: c = dx/dt is the nondimensional lattice speed).
  *  - Field planes: a "plane" is nx*ny values, row-major (index b*nx + a).  Arrays of
  *    several planes place plane k at offset k*nx*ny unless stated otherwise.
- *  - Population buffers: 24 planes, plane p = 6*q + k, at offset p*lbm_plane_stride()
- *    elements; q is the D2Q4 direction in the paper's order (1,0), (0,1), (-1,0), (0,-1)
- *    (Sec. 3.1), k the component of U = (v1, v2, F11, F12, F21, F22) (eq:state-vector).
- *    A buffer holds post-collision populations f* (eq:collision) of one time level; for
- *    the shifted storages it holds g* = f* - (0, 0, 1/4, 0, 0, 1/4), i.e. F is carried
- *    as F - I (the equilibrium of the reference state U = (0, 0, 1, 0, 0, 1) is U/4,
- *    because P(I) = 0 for every law of Appendix A).
+ *  - Tiled arrays: populations, the u* accumulator and state records are stored in tiles
+ *    of W = lbm_tile_width() (= 64) consecutive nodes of one row, each tile holding all of
+ *    its planes contiguously: element (p, a, b) of an array of NP planes is at index
+ *    ((b * T + a / W) * NP + p) * W + a % W, T = ceil(nx / W) tiles per row
+ *    (lbm_padded_nodes() = T * W * ny nodes, padding nodes unused).
+ *  - Population buffers: NP = 24 planes, p = 6*q + k; q is the D2Q4 direction in the
+ *    paper's order (1,0), (0,1), (-1,0), (0,-1) (Sec. 3.1), k the component of
+ *    U = (v1, v2, F11, F12, F21, F22) (eq:state-vector).  A buffer holds post-collision
+ *    populations f* (eq:collision) of one time level; for the shifted storages it holds
+ *    g* = f* - (0, 0, 1/4, 0, 0, 1/4), i.e. F is carried as F - I (the equilibrium of the
+ *    reference state U = (0, 0, 1, 0, 0, 1) is U/4, because P(I) = 0 for every law of
+ *    Appendix A).
  *  - Time levels: after lbm_init the state holds f*^0 and the displacement accumulator
  *    u*^1; lbm_step advances f*^n to f*^{n+1} (streaming, half-way wall rules with data at
  *    t^{n+1/2}, moments at level n+1, collision) and u*^{n+1} to u*^{n+2}.
@@ -88,9 +93,9 @@ typedef struct {
 typedef struct {
     void *pop[2];              /* device: two population buffers of lbm_pop_bytes() each */
     int32_t cur;               /* index of the buffer that holds the current level */
-    void *ustar;               /* device, lbm_ustar_bytes(): u* of eq:trapezoid-u; F32/F16:
-                                  4 float planes (hi1, hi2, c1, c2), u* = hi - c (compensated
-                                  summation); F64: 2 double planes */
+    void *ustar;               /* device, lbm_ustar_bytes(): u* of eq:trapezoid-u, tiled;
+                                  F32/F16: 4 float planes (hi1, hi2, c1, c2), u* = hi - c
+                                  (compensated summation); F64: 2 double planes */
     const float *mu, *lam;     /* device: per-node Lame fields (1 plane each), or NULL for mu0/lam0 */
     double mu0, lam0;          /* uniform values used when the field pointer is NULL */
     double mu_max, lam_max;    /* host-known upper bounds of the fields (CFL audit);
@@ -113,15 +118,17 @@ typedef struct {
 
 /* ------------------------------------------------------------------ sizes */
 
-/* Elements between consecutive population planes (>= nx*ny, padded). */
-size_t lbm_plane_stride(const lbm_params *p);
-/* Bytes of one population buffer: 24 * lbm_plane_stride() * element size. */
+/* Nodes per tile of the tiled arrays (64). */
+size_t lbm_tile_width(void);
+/* Nodes of a tiled array including row padding: ceil(nx / 64) * 64 * ny. */
+size_t lbm_padded_nodes(const lbm_params *p);
+/* Bytes of one population buffer: 24 * lbm_padded_nodes() * element size. */
 size_t lbm_pop_bytes(const lbm_params *p);
 /* Bytes of the u* accumulator. */
 size_t lbm_ustar_bytes(const lbm_params *p);
 /* Bytes of the traction-wall staging buffer (forward and adjoint). */
 size_t lbm_aux_bytes(const lbm_params *p);
-/* Bytes of one per-level state record (6 planes of the compute type: v1, v2, F - I). */
+/* Bytes of one per-level state record (6 tiled planes of the compute type: v1, v2, F - I). */
 size_t lbm_record_bytes(const lbm_params *p);
 /* Bytes of device scratch needed by lbm_diagnostics. */
 size_t lbm_diag_scratch_bytes(const lbm_params *p);
@@ -196,7 +203,7 @@ typedef struct {
     void *aux;                 /* device, lbm_aux_bytes(): traction-wall adjoint staging */
 } lbm_adj_state;
 
-/* Bytes of one adjoint population buffer (24 planes of the compute type). */
+/* Bytes of one adjoint population buffer (24 tiled planes of the compute type). */
 size_t lbm_adj_bytes(const lbm_params *p);
 
 /* One step of the hand-written adjoint of lbm_step, level m (reverse of eq:collision
@@ -222,7 +229,7 @@ lbm_status lbm_adjoint_init(const lbm_params *p, const lbm_state *fwd, lbm_adj_s
                             const double *v0, const double *u0, double r0, double *g_v0,
                             void *stream);
 
-/* Writes U^n of the current level in record format (6 planes of the compute type). */
+/* Writes U^n of the current level in record format (6 tiled planes of the compute type). */
 lbm_status lbm_record_state(const lbm_params *p, const lbm_state *s, double r_n, void *record,
                             void *stream);
 

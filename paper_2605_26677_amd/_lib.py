@@ -55,7 +55,8 @@ class lbm_adj_state(ctypes.Structure):
 
 P = ctypes.POINTER
 SIGNATURES = {
-    "lbm_plane_stride": (ctypes.c_size_t, [P(lbm_params)]),
+    "lbm_tile_width": (ctypes.c_size_t, []),
+    "lbm_padded_nodes": (ctypes.c_size_t, [P(lbm_params)]),
     "lbm_pop_bytes": (ctypes.c_size_t, [P(lbm_params)]),
     "lbm_ustar_bytes": (ctypes.c_size_t, [P(lbm_params)]),
     "lbm_aux_bytes": (ctypes.c_size_t, [P(lbm_params)]),

@@ -28,17 +28,14 @@ template <int ST, int LAW, bool WALLS, bool FIELDS>
 __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
     using R = typename Storage<ST>::real;
     const Common& cm = a.cm;
-    const int nx = cm.nx, ny = cm.ny;
-    const int tpr = (nx + kBlock - 1) / kBlock;
-    const int tile = remap_tile(blockIdx.x, gridDim.x);
-    const int y = tile / tpr;
-    const int x = (tile - y * tpr) * kBlock + threadIdx.x;
-    if (x >= nx) return;
-    const int64_t st = cm.stride;
+    const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
+    int x, y;
+    if (!tile_thread(nx, ny, ntile, x, y)) return;
     const int64_t n = int64_t(nx) * ny;
     const R* __restrict__ src = (const R*)a.src;
     R* __restrict__ dst = (R*)a.dst;
     const int idx = y * nx + x;
+    const int64_t own = tile_base(ntile, 24, x, y);
 
     // lambda*_q(X) pulls lambda_q from X + c_q: q0 from (x+1, y), q1 from (x, y+1),
     // q2 from (x-1, y), q3 from (x, y-1).  Beyond a wall the slot is the outgoing link of
@@ -49,24 +46,25 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
     if (yp >= ny) { if (WALLS && !cm.periodic_y) { w1 = true; yp = y; } else yp = 0; }
     if (xm < 0) { if (WALLS && !cm.periodic_x) { w2 = true; xm = x; } else xm = nx - 1; }
     if (ym < 0) { if (WALLS && !cm.periodic_y) { w3 = true; ym = y; } else ym = ny - 1; }
-    const int sidx[4] = {y * nx + xp, yp * nx + x, y * nx + xm, ym * nx + x};
+    const int64_t sb[4] = {tile_base(ntile, 24, xp, y), tile_base(ntile, 24, x, yp),
+                           tile_base(ntile, 24, xm, y), tile_base(ntile, 24, x, ym)};
     R l[4][6];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) l[q][k] = src[(6 * q + k) * st + sidx[q]];
+        for (int k = 0; k < 6; ++k) l[q][k] = src[sb[q] + (6 * q + k) * kTile];
     if constexpr (WALLS) {
         // outgoing slot od of edge e takes D_e lambda_d(own node), d the missing direction
-        if (w0) for (int k = 0; k < 6; ++k) l[0][k] = D_sign<R>(cm.bc[LBM_XMAX], k) * src[(12 + k) * st + idx];
-        if (w2) for (int k = 0; k < 6; ++k) l[2][k] = D_sign<R>(cm.bc[LBM_XMIN], k) * src[(0 + k) * st + idx];
-        if (w1) for (int k = 0; k < 6; ++k) l[1][k] = D_sign<R>(cm.bc[LBM_YMAX], k) * src[(18 + k) * st + idx];
-        if (w3) for (int k = 0; k < 6; ++k) l[3][k] = D_sign<R>(cm.bc[LBM_YMIN], k) * src[(6 + k) * st + idx];
+        if (w0) for (int k = 0; k < 6; ++k) l[0][k] = D_sign<R>(cm.bc[LBM_XMAX], k) * src[own + (12 + k) * kTile];
+        if (w2) for (int k = 0; k < 6; ++k) l[2][k] = D_sign<R>(cm.bc[LBM_XMIN], k) * src[own + (0 + k) * kTile];
+        if (w1) for (int k = 0; k < 6; ++k) l[1][k] = D_sign<R>(cm.bc[LBM_YMAX], k) * src[own + (18 + k) * kTile];
+        if (w3) for (int k = 0; k < 6; ++k) l[3][k] = D_sign<R>(cm.bc[LBM_YMIN], k) * src[own + (6 + k) * kTile];
     }
 
-    const R* rec = (const R*)a.record;
+    const R* rec = (const R*)a.record + tile_base(ntile, 6, x, y);
     R ft[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) ft[k] = rec[(2 + k) * n + idx];
+    for (int k = 0; k < 4; ++k) ft[k] = rec[(2 + k) * kTile];
     R mu, lam;
     params_at<FIELDS, R>(cm, idx, mu, lam);
     R C[16];
@@ -94,7 +92,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) dst[(6 * q + k) * st + idx] = omc * l[q][k] + gU[k];
+        for (int k = 0; k < 6; ++k) store_stream(dst + own + (6 * q + k) * kTile, omc * l[q][k] + gU[k]);
 
     // parameter gradients of this level's collision
     const R hc = R(0.5 / cm.c);
@@ -137,8 +135,9 @@ __global__ void __launch_bounds__(kBlock) adj_traction_kernel(AdjArgs a) {
     for (int r = 0; r < 2; ++r) {
         R Us[3][6];
         for (int j = 0; j < 3; ++j) {
-            const int id = edge_node(G, cm.nx, cm.ny, r, sten.p[j]);
-            for (int k = 0; k < 6; ++k) Us[j][k] = rec[k * n + id];
+            const XY nd = edge_node(G, cm.nx, cm.ny, r, sten.p[j]);
+            const int64_t rb = tile_base(cm.ntile, 6, nd.x, nd.y);
+            for (int k = 0; k < 6; ++k) Us[j][k] = rec[rb + k * kTile];
         }
         for (int k = 0; k < 2; ++k) {
             R dv = R(0);
@@ -153,7 +152,8 @@ __global__ void __launch_bounds__(kBlock) adj_traction_kernel(AdjArgs a) {
         acol[k] = R(1.5) * Fa[0][k] - R(0.5) * Fa[1][k];
         Tv[k] = edge_value<R>(a.ed, e, k, s, L);
     }
-    const int id0 = edge_node(G, cm.nx, cm.ny, 0, s);
+    const XY n0 = edge_node(G, cm.nx, cm.ny, 0, s);
+    const int id0 = n0.y * cm.nx + n0.x;
     R mu, lam;
     params_at<FIELDS, R>(cm, id0, mu, lam);
     newton_column<R, LAW, true>(A, R(G.NA), tang, Tv, mu, lam, acol, cm.newton_max_iter, R(cm.newton_tol));
@@ -162,7 +162,8 @@ __global__ void __launch_bounds__(kBlock) adj_traction_kernel(AdjArgs a) {
     f[Bx] = tang[0]; f[2 + Bx] = tang[1];
     const R* src = (const R*)a.src;
     R Fbar[4];
-    for (int k = 0; k < 4; ++k) Fbar[k] = R(0.5) * src[(6 * G.d + 2 + k) * cm.stride + id0];
+    const int64_t wb = tile_base(cm.ntile, 24, n0.x, n0.y);
+    for (int k = 0; k < 4; ++k) Fbar[k] = R(0.5) * src[wb + (6 * G.d + 2 + k) * kTile];
     R C[16];
     tangent<R, LAW, true>(f, mu, lam, C);
     const R NA = R(G.NA);
@@ -216,10 +217,11 @@ __global__ void __launch_bounds__(kBlock) adj_traction_scatter_kernel(AdjArgs a)
         E[2 + 2 * k + Bx] = wr * aux[2 * s + k];
         E[k] = hdt * wr * fd_along_T<R>([&](int s2) { return aux[2 * s2 + k]; }, s, L, per_t, inv2h);
     }
-    const int id = edge_node(G, cm.nx, cm.ny, r, s);
-    R* dst = (R*)a.dst;
+    const XY nd = edge_node(G, cm.nx, cm.ny, r, s);
+    const int id = nd.y * cm.nx + nd.x;
+    R* dst = (R*)a.dst + tile_base(cm.ntile, 24, nd.x, nd.y);
     for (int q = 0; q < 4; ++q)
-        for (int k = 0; k < 6; ++k) dst[(6 * q + k) * cm.stride + id] += E[k];
+        for (int k = 0; k < 6; ++k) dst[(6 * q + k) * kTile] += E[k];
     if (a.g_body) {
         a.g_body[id] += a.r_m * double(hdt * E[0]);
         a.g_body[n + id] += a.r_m * double(hdt * E[1]);
@@ -239,9 +241,11 @@ __global__ void adj_probe_kernel(AdjArgs a) {
     const double hdt = 0.5 * cm.dt;
     for (int p = 0; p < a.nprobe; ++p) {
         const int id = a.probe[p];
+        const int py = id / cm.nx, px = id - py * cm.nx;
+        R* d = dst + tile_base(cm.ntile, 24, px, py);
         for (int k = 0; k < 2; ++k) {
             const double src = a.probe_weight * a.ubar[k * a.nprobe + p];
-            for (int q = 0; q < 4; ++q) dst[(6 * q + k) * cm.stride + id] += R(src);
+            for (int q = 0; q < 4; ++q) d[(6 * q + k) * kTile] += R(src);
             if (a.g_body) a.g_body[k * n + id] += a.r_m * hdt * src;
         }
     }
@@ -285,7 +289,7 @@ __global__ void __launch_bounds__(kBlock) adj_init_kernel(AdjInitArgs a) {
     for (int q = 0; q < 4; ++q) {
         const double i = dir_i(q), j = dir_j(q);
         double ell[6];
-        for (int k = 0; k < 6; ++k) ell[k] = double(l0[(6 * q + k) * cm.stride + idx]);
+        for (int k = 0; k < 6; ++k) ell[k] = double(l0[tile_base(cm.ntile, 24, x, y) + (6 * q + k) * kTile]);
         // equilibrium part f^eq_q(U0)
         vb[0] += 0.25 * (ell[0] - (2.0 / c) * (i * ell[2] + j * ell[3]));
         vb[1] += 0.25 * (ell[1] - (2.0 / c) * (i * ell[4] + j * ell[5]));
@@ -403,8 +407,7 @@ static hipError_t adjoint_st_law(const AdjArgs& a0, hipStream_t s) {
         if (fields) hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, true>), dim3(nblk(L)), dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, false>), dim3(nblk(L)), dim3(kBlock), 0, s, a);
     }
-    const int tpr = (a.cm.nx + kBlock - 1) / kBlock;
-    const dim3 grid(unsigned(int64_t(tpr) * a.cm.ny));
+    const dim3 grid(unsigned((int64_t(a.cm.ntile) * a.cm.ny + 3) / 4));
     if (walls) {
         if (fields) hipLaunchKernelGGL((adjoint_kernel<ST, LAW, true, true>), grid, dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL((adjoint_kernel<ST, LAW, true, false>), grid, dim3(kBlock), 0, s, a);

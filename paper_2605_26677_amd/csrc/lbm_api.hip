@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 
 using namespace lbm;
@@ -31,7 +32,7 @@ Common make_common(const lbm_params* p, const lbm_state* s) {
     Common cm{};
     cm.nx = p->nx;
     cm.ny = p->ny;
-    cm.stride = (int64_t)lbm_plane_stride(p);
+    cm.ntile = (p->nx + kTile - 1) / kTile;
     for (int e = 0; e < 4; ++e) cm.bc[e] = p->bc[e];
     cm.periodic_x = p->bc[LBM_XMIN] == LBM_PERIODIC;
     cm.periodic_y = p->bc[LBM_YMIN] == LBM_PERIODIC;
@@ -81,29 +82,24 @@ lbm_status launched(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_ERR_LA
 
 extern "C" {
 
-size_t lbm_plane_stride(const lbm_params* p) {
-    // round up to 64 elements, and keep planes off a common large power-of-two alignment
-    // so that the 24 streams of one pass do not start on the same HBM channel
-    size_t n = (size_t)p->nx * (size_t)p->ny;
-    size_t st = (n + 63) / 64 * 64;
-    if (st % 4096 == 0) st += 64;
-    return st;
+size_t lbm_tile_width(void) { return (size_t)kTile; }
+
+size_t lbm_padded_nodes(const lbm_params* p) {
+    const size_t ntile = ((size_t)p->nx + kTile - 1) / kTile;
+    return ntile * kTile * (size_t)p->ny;
 }
 
-size_t lbm_pop_bytes(const lbm_params* p) { return 24 * lbm_plane_stride(p) * pop_elem_size(p); }
+size_t lbm_pop_bytes(const lbm_params* p) { return 24 * lbm_padded_nodes(p) * pop_elem_size(p); }
 
 size_t lbm_ustar_bytes(const lbm_params* p) {
-    const size_t n = (size_t)p->nx * (size_t)p->ny;
-    return p->storage == LBM_F64_PLAIN ? 2 * n * 8 : 4 * n * 4;
+    return p->storage == LBM_F64_PLAIN ? 2 * lbm_padded_nodes(p) * 8 : 4 * lbm_padded_nodes(p) * 4;
 }
 
 size_t lbm_aux_bytes(const lbm_params* p) { return (size_t)(2 * p->nx + 2 * p->ny) * 4 * 8; }
 
-size_t lbm_record_bytes(const lbm_params* p) {
-    return 6 * (size_t)p->nx * (size_t)p->ny * real_size(p);
-}
+size_t lbm_record_bytes(const lbm_params* p) { return 6 * lbm_padded_nodes(p) * real_size(p); }
 
-size_t lbm_adj_bytes(const lbm_params* p) { return 24 * lbm_plane_stride(p) * real_size(p); }
+size_t lbm_adj_bytes(const lbm_params* p) { return 24 * lbm_padded_nodes(p) * real_size(p); }
 
 size_t lbm_diag_scratch_bytes(const lbm_params* p) {
     (void)p;

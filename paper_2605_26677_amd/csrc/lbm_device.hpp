@@ -239,13 +239,25 @@ __device__ __forceinline__ R energy(const R f[4], R mu, R lam) {
     }
 }
 
-// ---------------------------------------------------------------- grid helpers
+// ---------------------------------------------------------------- tiled layout
+//
+// Arrays of per-node planes (populations: 24, u*: 4 or 2, records: 6) are stored in
+// tiles of kTile consecutive nodes of one row; a tile holds all its planes contiguously:
+// element (p, x, y) of an np-plane array sits at ((y * ntile + x / kTile) * np + p) * kTile
+// + x mod kTile, ntile = ceil(nx / kTile).  One wavefront of 64 lanes covers one tile, so
+// a pass over the grid reads and writes a few long contiguous runs per wavefront instead
+// of one short run in each of 24 + 24 + 4 + 4 widely separated planes.
 
-struct Grid {
-    int nx, ny;
-    int64_t stride;      // elements between population planes
-    int periodic_x, periodic_y;
-};
+constexpr int kTile = 64;
+
+__host__ __device__ __forceinline__ int64_t tile_base(int ntile, int np, int x, int y) {
+    return ((int64_t(y) * ntile + (x >> 6)) * np) * kTile + (x & (kTile - 1));
+}
+
+// Store that bypasses the caches' allocate-on-write (each value is written once per pass).
+template <typename T> __device__ __forceinline__ void store_stream(T* p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
 
 // Second-order first derivative of g along an axis of length L at position s: central
 // differences, periodic wrap, or the one-sided three-point formula at the ends of a

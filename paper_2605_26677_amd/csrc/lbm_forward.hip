@@ -2,10 +2,12 @@
 // (Sec. 3.7), the traction-wall F^b solve (Sec. 3.6), the second-order initialisation
 // (Sec. 3.4) and the recoveries from stored post-collision populations (Sec. 3.5).
 //
-// Layout: 24 SoA planes per population buffer, plane 6 q + k at offset (6 q + k) * stride,
-// node (a, b) at b * nx + a.  One thread per node, 256-node tiles along a row; the tile
-// order is remapped so that each of the eight XCDs sweeps a contiguous band of rows (its
-// L2 then serves the one-element overlap of the x -/+ 1 pulls between adjacent tiles).
+// Layout: populations, u* and records in 64-node row tiles holding all their planes
+// contiguously (tile_base in lbm_device.hpp).  One thread per node, one wavefront per tile,
+// four tiles per workgroup; the tile order is remapped so that each of the eight XCDs
+// sweeps a contiguous band of rows (its L2 then serves the one-element overlap of the
+// x -/+ 1 pulls between adjacent tiles).  Each stored value is written once per pass, with
+// non-temporal stores.
 #include <algorithm>
 
 #include "lbm_device.hpp"
@@ -44,10 +46,10 @@ __global__ void __launch_bounds__(kBlock) traction_kernel(TractionArgs a) {
         R Us[3][6];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const int id = edge_node(G, cm.nx, cm.ny, r, sten.p[j]);
+            const XY nd = edge_node(G, cm.nx, cm.ny, r, sten.p[j]);
             double b0, b1;
-            body_at<FIELDS>(cm, id, n, a.r_n, b0, b1);
-            recover_node<T, R>(pop, cm.stride, id, hdt * R(b0), hdt * R(b1), Us[j]);
+            body_at<FIELDS>(cm, nd.y * cm.nx + nd.x, n, a.r_n, b0, b1);
+            recover_node<T, R>(pop, cm.ntile, nd.x, nd.y, hdt * R(b0), hdt * R(b1), Us[j]);
         }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -65,9 +67,9 @@ __global__ void __launch_bounds__(kBlock) traction_kernel(TractionArgs a) {
         acol[k] = R(1.5) * Fa[0][k] - R(0.5) * Fa[1][k];
         Tv[k] = edge_value<R>(a.ed, e, k, s, L);
     }
-    const int id0 = edge_node(G, cm.nx, cm.ny, 0, s);
+    const XY n0 = edge_node(G, cm.nx, cm.ny, 0, s);
     R mu, lam;
-    params_at<FIELDS, R>(cm, id0, mu, lam);
+    params_at<FIELDS, R>(cm, n0.y * cm.nx + n0.x, mu, lam);
     const bool ok = newton_column<R, LAW, SH>(G.A, R(G.NA), tang, Tv, mu, lam, acol,
                                              cm.newton_max_iter, R(cm.newton_tol));
     if (!ok) atomicOr(cm.fault, (uint32_t)LBM_FAULT_NEWTON);
@@ -88,12 +90,12 @@ __global__ void __launch_bounds__(kBlock) traction_kernel(TractionArgs a) {
 // change: g_d = -g*_{-d} + (F^b - I)/2 (F^b arrives from the staging buffer as F^b - I).
 template <typename T, typename R>
 __device__ __forceinline__ void wall_link(const Common& cm, const EdgeData& ed, const void* auxp,
-                                          int e, int s, const T* src, int idx, R out[6]) {
+                                          int e, int s, const T* src, int64_t own, R out[6]) {
     const EdgeGeom G = edge_geom(e);
     const int L = (G.A == 0) ? cm.ny : cm.nx;
     R o[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) o[k] = R(src[(6 * G.od + k) * cm.stride + idx]);
+    for (int k = 0; k < 6; ++k) o[k] = R(src[own + (6 * G.od + k) * kTile]);
     const R w0 = edge_value<R>(ed, e, 0, s, L), w1 = edge_value<R>(ed, e, 1, s, L);
     const R c = R(cm.c);
     if (cm.bc[e] == LBM_VELOCITY) {
@@ -122,17 +124,14 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     using T = typename Tr::pop_t;
     constexpr bool SH = Tr::shifted;
     const Common& cm = a.cm;
-    const int nx = cm.nx, ny = cm.ny;
-    const int tpr = (nx + kBlock - 1) / kBlock;
-    const int tile = remap_tile(blockIdx.x, gridDim.x);
-    const int y = tile / tpr;
-    const int x = (tile - y * tpr) * kBlock + threadIdx.x;
-    if (x >= nx) return;
-    const int64_t st = cm.stride;
+    const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
+    int x, y;
+    if (!tile_thread(nx, ny, ntile, x, y)) return;
     const int64_t n = int64_t(nx) * ny;
     const T* __restrict__ src = (const T*)a.src;
     T* __restrict__ dst = (T*)a.dst;
     const int idx = y * nx + x;
+    const int64_t own = tile_base(ntile, 24, x, y);
 
     // pull sources: q0 (1,0) from (x-1, y), q1 (0,1) from (x, y-1), q2 (-1,0) from (x+1, y),
     // q3 (0,-1) from (x, y+1) (eq:streaming); a source beyond a wall is a missing link.
@@ -142,19 +141,20 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     if (xp >= nx) { if (WALLS && !cm.periodic_x) { miss2 = true; xp = x; } else xp = 0; }
     if (ym < 0) { if (WALLS && !cm.periodic_y) { miss1 = true; ym = y; } else ym = ny - 1; }
     if (yp >= ny) { if (WALLS && !cm.periodic_y) { miss3 = true; yp = y; } else yp = 0; }
-    const int sidx[4] = {y * nx + xm, ym * nx + x, y * nx + xp, yp * nx + x};
+    const int64_t sb[4] = {tile_base(ntile, 24, xm, y), tile_base(ntile, 24, x, ym),
+                           tile_base(ntile, 24, xp, y), tile_base(ntile, 24, x, yp)};
 
     R g[4][6];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) g[q][k] = R(src[(6 * q + k) * st + sidx[q]]);
+        for (int k = 0; k < 6; ++k) g[q][k] = R(src[sb[q] + (6 * q + k) * kTile]);
 
     if constexpr (WALLS) {
-        if (miss0) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMIN, y, src, idx, g[0]);
-        if (miss2) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMAX, y, src, idx, g[2]);
-        if (miss1) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMIN, x, src, idx, g[1]);
-        if (miss3) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMAX, x, src, idx, g[3]);
+        if (miss0) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMIN, y, src, own, g[0]);
+        if (miss2) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMAX, y, src, own, g[2]);
+        if (miss1) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMIN, x, src, own, g[1]);
+        if (miss3) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMAX, x, src, own, g[3]);
     }
 
     // moments with the half-step source (eq:moment-U)
@@ -189,37 +189,37 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
             R v = g[q][k] + om * (feq - g[q][k]);
             if (k == 0) v += srcw * B0;
             if (k == 1) v += srcw * B1;
-            dst[(6 * q + k) * st + idx] = T(v);
+            store_stream(dst + own + (6 * q + k) * kTile, T(v));
         }
     }
 
     // displacement quadrature u*^{n+2} = u*^{n+1} + dt v^{n+1} (eq:trapezoid-u)
     if constexpr (ST == LBM_F64_PLAIN) {
-        double* us = (double*)a.ustar;
-        us[idx] += dt * U[0];
-        us[n + idx] += dt * U[1];
+        double* us = (double*)a.ustar + tile_base(ntile, 2, x, y);
+        store_stream(us, us[0] + dt * U[0]);
+        store_stream(us + kTile, us[kTile] + dt * U[1]);
     } else {
-        float* us = (float*)a.ustar;
+        float* us = (float*)a.ustar + tile_base(ntile, 4, x, y);
 #pragma unroll
         for (int cpt = 0; cpt < 2; ++cpt) {
-            float hi = us[cpt * n + idx];
-            float cc = us[(2 + cpt) * n + idx];
+            const float hi = us[cpt * kTile];
+            float cc = us[(2 + cpt) * kTile];
             const float yv = float(dt * U[cpt]) - cc;
             const float t = hi + yv;
             cc = (t - hi) - yv;
-            us[cpt * n + idx] = t;
-            us[(2 + cpt) * n + idx] = cc;
+            store_stream(us + cpt * kTile, t);
+            store_stream(us + (2 + cpt) * kTile, cc);
         }
     }
 
     if (a.record) {
-        R* rec = (R*)a.record;
-        rec[idx] = U[0];
-        rec[n + idx] = U[1];
-        rec[2 * n + idx] = SH ? U[2] : U[2] - R(1);
-        rec[3 * n + idx] = U[3];
-        rec[4 * n + idx] = U[4];
-        rec[5 * n + idx] = SH ? U[5] : U[5] - R(1);
+        R* rec = (R*)a.record + tile_base(ntile, 6, x, y);
+        rec[0] = U[0];
+        rec[kTile] = U[1];
+        rec[2 * kTile] = SH ? U[2] : U[2] - R(1);
+        rec[3 * kTile] = U[3];
+        rec[4 * kTile] = U[4];
+        rec[5 * kTile] = SH ? U[5] : U[5] - R(1);
     }
 
     bool nonfinite = false;
@@ -242,11 +242,12 @@ __global__ void __launch_bounds__(kBlock) recover_kernel(RecoverArgs a) {
     const int64_t n = int64_t(cm.nx) * cm.ny;
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= n) return;
+    const int y = int(idx / cm.nx), x = int(idx - int64_t(y) * cm.nx);
     double b0, b1;
     body_at<FIELDS>(cm, (int)idx, n, a.r_n, b0, b1);
     const double hdt = 0.5 * cm.dt;
     R U[6];
-    recover_node<T, R>((const T*)a.pop, cm.stride, (int)idx, R(hdt * b0), R(hdt * b1), U);
+    recover_node<T, R>((const T*)a.pop, cm.ntile, x, y, R(hdt * b0), R(hdt * b1), U);
     if constexpr (MODE == 0) {
         double* out = (double*)a.out;
         for (int k = 0; k < 6; ++k) {
@@ -255,21 +256,21 @@ __global__ void __launch_bounds__(kBlock) recover_kernel(RecoverArgs a) {
             out[k * n + idx] = v;
         }
     } else if constexpr (MODE == 1) {
-        R* out = (R*)a.out;
+        R* out = (R*)a.out + tile_base(cm.ntile, 6, x, y);
         for (int k = 0; k < 6; ++k) {
             R v = U[k];
             if (!SH && (k == 2 || k == 5)) v -= R(1);
-            out[k * n + idx] = v;
+            out[k * kTile] = v;
         }
     } else {
         double* out = (double*)a.out;
         for (int cpt = 0; cpt < 2; ++cpt) {
             double ustar;
             if constexpr (ST == LBM_F64_PLAIN) {
-                ustar = ((const double*)a.ustar)[cpt * n + idx];
+                ustar = ((const double*)a.ustar)[tile_base(cm.ntile, 2, x, y) + cpt * kTile];
             } else {
-                const float* us = (const float*)a.ustar;
-                ustar = double(us[cpt * n + idx]) - double(us[(2 + cpt) * n + idx]);
+                const float* us = (const float*)a.ustar + tile_base(cm.ntile, 4, x, y);
+                ustar = double(us[cpt * kTile]) - double(us[(2 + cpt) * kTile]);
             }
             out[cpt * n + idx] = ustar - hdt * double(U[cpt]);
         }
@@ -296,10 +297,11 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(RecoverArgs a) {
     const R cd = R(0.99984769515639123916), sd = R(0.017452406437283512820);
     for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < n;
          idx += int64_t(gridDim.x) * blockDim.x) {
+        const int y = int(idx / cm.nx), x = int(idx - int64_t(y) * cm.nx);
         double b0, b1;
         body_at<FIELDS>(cm, (int)idx, n, a.r_n, b0, b1);
         R U[6];
-        recover_node<T, R>((const T*)a.pop, cm.stride, (int)idx, R(hdt * b0), R(hdt * b1), U);
+        recover_node<T, R>((const T*)a.pop, cm.ntile, x, y, R(hdt * b0), R(hdt * b1), U);
         R mu, lam;
         params_at<FIELDS, R>(cm, (int)idx, mu, lam);
         R ft[4] = {U[2], U[3], U[4], U[5]};
@@ -486,7 +488,7 @@ __global__ void __launch_bounds__(kBlock) init_pop_kernel(InitArgs a) {
     const double QX[6] = {-P[0], -P[2], -U[0], 0.0, -U[1], 0.0};
     const double QY[6] = {-P[1], -P[3], 0.0, -U[0], 0.0, -U[1]};
     const double srcw = dt * (2.0 - cm.omega) * 0.125;
-    T* dst = (T*)a.dst;
+    T* dst = (T*)a.dst + tile_base(cm.ntile, 24, x, y);
     for (int q = 0; q < 4; ++q) {
         const double i = dir_i(q), j = dir_j(q);
         for (int k = 0; k < 6; ++k) {
@@ -495,7 +497,7 @@ __global__ void __launch_bounds__(kBlock) init_pop_kernel(InitArgs a) {
             if (k == 0) v += srcw * b0;
             if (k == 1) v += srcw * b1;
             if (!SH && (k == 2 || k == 5)) v += 0.25;
-            dst[(6 * q + k) * cm.stride + idx] = T(v);
+            dst[(6 * q + k) * kTile] = T(v);
         }
     }
     // u*^1 = u0 - (dt/2) v0 + dt v^0 (eq:trapezoid-u)
@@ -503,12 +505,12 @@ __global__ void __launch_bounds__(kBlock) init_pop_kernel(InitArgs a) {
         const double u0 = a.u0 ? a.u0[cpt * n + idx] : 0.0;
         const double us1 = u0 - hdt * a.v0[cpt * n + idx] + dt * U[cpt];
         if constexpr (ST == LBM_F64_PLAIN) {
-            ((double*)a.ustar)[cpt * n + idx] = us1;
+            ((double*)a.ustar)[tile_base(cm.ntile, 2, x, y) + cpt * kTile] = us1;
         } else {
-            float* us = (float*)a.ustar;
+            float* us = (float*)a.ustar + tile_base(cm.ntile, 4, x, y);
             const float hi = float(us1);
-            us[cpt * n + idx] = hi;
-            us[(2 + cpt) * n + idx] = float(double(hi) - us1);
+            us[cpt * kTile] = hi;
+            us[(2 + cpt) * kTile] = float(double(hi) - us1);
         }
     }
     bool bad = !(J > 0.0);
@@ -523,8 +525,7 @@ template <int ST, int LAW>
 static hipError_t step_st_law(const StepArgs& a, hipStream_t s) {
     const bool walls = !(a.cm.periodic_x && a.cm.periodic_y);
     const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
-    const int tpr = (a.cm.nx + kBlock - 1) / kBlock;
-    const dim3 grid(unsigned(int64_t(tpr) * a.cm.ny));
+    const dim3 grid(unsigned((int64_t(a.cm.ntile) * a.cm.ny + 3) / 4));
     if (walls) {
         if (fields) hipLaunchKernelGGL((step_kernel<ST, LAW, true, true>), grid, dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL((step_kernel<ST, LAW, true, false>), grid, dim3(kBlock), 0, s, a);

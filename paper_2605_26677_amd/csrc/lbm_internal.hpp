@@ -24,7 +24,7 @@ struct EdgeData {
 
 struct Common {
     int nx, ny;
-    int64_t stride;                  // elements between population planes
+    int ntile;                       // tiles of kTile nodes per row
     int bc[4];
     int periodic_x, periodic_y;
     int material, storage;

@@ -42,12 +42,13 @@ __device__ __forceinline__ void params_at(const Common& cm, int idx, R& mu, R& l
 // Sum of the four stored post-collision populations of one node minus (dt/2) B: the
 // state of that level (sum_q f* = U + (dt/2) B, from eq:collision with sum_q w = 1/2).
 template <typename T, typename R>
-__device__ __forceinline__ void recover_node(const T* pop, int64_t st, int idx, R hb0, R hb1, R U[6]) {
+__device__ __forceinline__ void recover_node(const T* pop, int ntile, int x, int y, R hb0, R hb1, R U[6]) {
+    const int64_t b = tile_base(ntile, 24, x, y);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         R s = R(0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s += R(pop[(6 * q + k) * st + idx]);
+        for (int q = 0; q < 4; ++q) s += R(pop[b + (6 * q + k) * kTile]);
         U[k] = s;
     }
     U[0] -= hb0;
@@ -144,14 +145,23 @@ __device__ __forceinline__ Stencil tangential_stencil(int s, int L, bool periodi
     return t;
 }
 
-// Node index of row r (0 = wall row, 1 = first interior row) at position s2 of edge e.
-__device__ __forceinline__ int edge_node(const EdgeGeom& G, int nx, int ny, int r, int s2) {
-    if (G.A == 0) {
-        const int x = (G.NA < 0) ? r : nx - 1 - r;
-        return s2 * nx + x;
-    }
-    const int y = (G.NA < 0) ? r : ny - 1 - r;
-    return y * nx + s2;
+// Node (x, y) of row r (0 = wall row, 1 = first interior row) at position s2 of edge e.
+struct XY {
+    int x, y;
+};
+__device__ __forceinline__ XY edge_node(const EdgeGeom& G, int nx, int ny, int r, int s2) {
+    if (G.A == 0) return XY{(G.NA < 0) ? r : nx - 1 - r, s2};
+    return XY{s2, (G.NA < 0) ? r : ny - 1 - r};
+}
+
+// Tile-grid position of this thread for kernels with one wavefront per tile and four
+// tiles per 256-thread workgroup.  Returns false for lanes beyond the grid.
+__device__ __forceinline__ bool tile_thread(int nx, int ny, int ntile, int& x, int& y) {
+    const int tl = remap_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (tl >= ntile * ny) return false;
+    y = tl / ntile;
+    x = (tl - y * ntile) * kTile + (threadIdx.x & (kTile - 1));
+    return x < nx;
 }
 
 }  // namespace lbm

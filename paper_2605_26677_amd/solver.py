@@ -98,8 +98,9 @@ class Solver:
 
     # ------------------------------------------------------------ sizes
     @property
-    def plane_stride(self):
-        return int(self.lib.lbm_plane_stride(ctypes.byref(self.p)))
+    def tiles_per_row(self):
+        w = int(self.lib.lbm_tile_width())
+        return (self.nx + w - 1) // w
 
     @property
     def record_bytes(self):
@@ -110,7 +111,8 @@ class Solver:
         return torch.float64 if self.storage == "f64" else torch.float32
 
     def new_record(self):
-        return torch.empty((6, self.ny, self.nx), dtype=self.real_dtype, device=self.device)
+        """A state record (6 tiled planes of the compute type, see lbm.h)."""
+        return torch.empty(self.record_bytes // self.real_dtype.itemsize, dtype=self.real_dtype, device=self.device)
 
     # ------------------------------------------------------------ entry points
     def init(self, v0, u0=None, r0=0.0):
@@ -153,13 +155,14 @@ class Solver:
         return out
 
     def populations(self):
-        """Current post-collision populations as a (4, 6, ny, nx) view in the storage dtype
-        (shifted storages hold f* - (0, 0, 1/4, 0, 0, 1/4))."""
+        """Current post-collision populations as a (4, 6, ny, nx) tensor in the storage dtype
+        (shifted storages hold f* - (0, 0, 1/4, 0, 0, 1/4)), gathered from the tiled layout."""
         dt = {"f32": torch.float32, "f16": torch.float16, "f64": torch.float64}[self.storage]
-        st = self.plane_stride
-        buf = self.pop[self.s.cur].view(dt)
-        n = self.nx * self.ny
-        return torch.as_strided(buf, (4, 6, self.ny, self.nx), (6 * st, st, self.nx, 1))
+        w = int(self.lib.lbm_tile_width())
+        T = self.tiles_per_row
+        buf = self.pop[self.s.cur].view(dt).view(self.ny, T, 24, w)
+        planes = buf.permute(2, 0, 1, 3).reshape(24, self.ny, T * w)[:, :, : self.nx]
+        return planes.reshape(4, 6, self.ny, self.nx)
 
     def faults(self):
         return int(self.fault.item())

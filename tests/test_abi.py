@@ -38,17 +38,18 @@ def _params(nx=64, ny=64, storage=L.LBM_F32_SHIFTED, bc=(0, 0, 0, 0), c=2.0, ome
 
 def test_sizes():
     lib = L.lib()
+    assert lib.lbm_tile_width() == 64
     p = _params(8192, 8192)
-    st = lib.lbm_plane_stride(ctypes.byref(p))
-    assert st >= 8192 * 8192 and st % 64 == 0 and st % 4096 != 0
-    assert lib.lbm_pop_bytes(ctypes.byref(p)) == 24 * st * 4
+    assert lib.lbm_padded_nodes(ctypes.byref(p)) == 8192 * 8192
+    assert lib.lbm_pop_bytes(ctypes.byref(p)) == 24 * 8192 * 8192 * 4
     assert lib.lbm_ustar_bytes(ctypes.byref(p)) == 4 * 8192 * 8192 * 4
     assert lib.lbm_record_bytes(ctypes.byref(p)) == 6 * 8192 * 8192 * 4
     p64 = _params(100, 37, storage=L.LBM_F64_PLAIN)
-    assert lib.lbm_pop_bytes(ctypes.byref(p64)) == 24 * lib.lbm_plane_stride(ctypes.byref(p64)) * 8
+    assert lib.lbm_padded_nodes(ctypes.byref(p64)) == 128 * 37        # rows padded to whole tiles
+    assert lib.lbm_pop_bytes(ctypes.byref(p64)) == 24 * 128 * 37 * 8
     p16 = _params(100, 37, storage=L.LBM_F16_SHIFTED)
-    assert lib.lbm_pop_bytes(ctypes.byref(p16)) == 24 * lib.lbm_plane_stride(ctypes.byref(p16)) * 2
-    assert lib.lbm_adj_bytes(ctypes.byref(p16)) == 24 * lib.lbm_plane_stride(ctypes.byref(p16)) * 4
+    assert lib.lbm_pop_bytes(ctypes.byref(p16)) == 24 * 128 * 37 * 2
+    assert lib.lbm_adj_bytes(ctypes.byref(p16)) == 24 * 128 * 37 * 4
 
 
 @pytest.mark.parametrize("mutate,code", [
