@@ -153,7 +153,9 @@ def profile_run(n, steps):
     del a, b
     v0 = make_inputs(n)
     ms, faults = time_forward(n, "f32", steps, 3, v0)
-    print(json.dumps({"profile": True, "copy_bytes_each_way": 2 ** 31, "ms_per_step": ms, "faults": faults}))
+    adj = time_forward_adjoint(n, 20, 10)
+    print(json.dumps({"profile": True, "copy_bytes_each_way": 2 ** 31, "ms_per_step": ms, "faults": faults,
+                      "fwd_adj": adj}))
 
 
 def cpu_baseline(budget_s=20.0):

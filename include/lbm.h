@@ -95,12 +95,21 @@ typedef struct {
     int32_t cur;               /* index of the buffer that holds the current level */
     void *ustar;               /* device, lbm_ustar_bytes(): u* of eq:trapezoid-u, tiled;
                                   F32/F16: 4 float planes (hi1, hi2, c1, c2), u* = hi - c
-                                  (compensated summation); F64: 2 double planes */
+                                  (compensated summation); F64: 2 double planes.  May be
+                                  NULL for lbm_step (the quadrature is then skipped, as in
+                                  a replay for the adjoint) but not for lbm_init or
+                                  lbm_displacement */
     const float *mu, *lam;     /* device: per-node Lame fields (1 plane each), or NULL for mu0/lam0 */
     double mu0, lam0;          /* uniform values used when the field pointer is NULL */
     double mu_max, lam_max;    /* host-known upper bounds of the fields (CFL audit);
                                   ignored when the field pointer is NULL */
-    const float *body;         /* device: body acceleration b, 2 planes, or NULL for b0 */
+    const float *body;         /* device: body acceleration b, 2 planes, or NULL for b0; the
+                                  force at level m is r(m) b (the r factors are per call) */
+    const float *body_prev;    /* device, optional: body field of the previous level for
+                                  lbm_step (level n of the step n -> n+1, read where the step
+                                  recovers the state of level n: traction walls); NULL means
+                                  the same field as body.  Lets a caller drive a force that is
+                                  not a fixed field times a ramp by swapping two buffers. */
     double b0[2];              /* uniform body acceleration when body is NULL */
     void *aux;                 /* device, lbm_aux_bytes(): traction-wall staging (F^b per link) */
     uint32_t *fault;           /* device: fault word (LBM_FAULT_* bits are OR-ed in) */
@@ -180,6 +189,12 @@ lbm_status lbm_displacement(const lbm_params *p, const lbm_state *s, double r_n,
  * stored populations.  U_out: device, 6 double planes. */
 lbm_status lbm_moments(const lbm_params *p, const lbm_state *s, double r_n, double *U_out,
                        void *stream);
+
+/* Stress recovery at the current level (Sec. 3.5): first Piola stress P(F) of the
+ * selected law and Cauchy stress sigma = J^{-1} P F^T.  P_out: device, 4 double planes
+ * (P11, P12, P21, P22); sigma_out: device, 3 double planes (s11, s12, s22), or NULL. */
+lbm_status lbm_stress(const lbm_params *p, const lbm_state *s, double r_n, double *P_out,
+                      double *sigma_out, void *stream);
 
 /* FP64 reductions over the current level: out[0..1] sum of v, out[2..5] sum of F - I,
  * out[6] energy sum(|v|^2/2 + W(F)) dx^2, out[7] min J, out[8] max |F - I| (Frobenius),

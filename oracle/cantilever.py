@@ -1,0 +1,77 @@
+"""Cantilever bending-wave workload of Sec. 5.4, FP64.
+
+Test infrastructure only (see the package docstring).
+
+Reference domain [0, 4] x [0, 1] on 160 x 40 nodes (dx = 1/40); left edge clamped
+(velocity wall, v = 0), top and bottom traction free, right edge loaded by the nominal
+traction T = (0, p_R(t) w(Y)) with the Ricker pulse
+p_R(t) = 2 p0 / (sqrt(3 s) pi^(1/4)) (1 - z^2) exp(-z^2 / 2), z = (t - t0) / s, for
+0 <= t <= 2 and T = 0 afterwards (p0 = 0.15, s = 0.215, t0 = 1); compressible neo-Hookean
+(eq:nh-model) with mu = 1, nu = 0.2 (lam = 2 mu nu / (1 - 2 nu)); c = 10, tau = 1/omega =
+0.5025; second-order initialisation from rest.
+
+Reading of the taper w(Y) (the paper says only that it is smooth, vanishes over eight
+lattice nodes near the loaded-end corners and is normalised to preserve the resultant):
+w_b = sin^2(pi (d + 1/2) / 16) for the node at distance d < 8 (in nodes) from the nearer
+corner, 1 elsewhere, then scaled so that sum_b w_b dx = 1 (the resultant of T equals
+p_R times the edge length).
+"""
+import numpy as np
+
+from . import lbm
+
+NX, NY = 160, 40
+LENGTH, HEIGHT = 4.0, 1.0
+P0, S, T0 = 0.15, 0.215, 1.0
+MU, NU = 1.0, 0.2
+LAM = 2.0 * MU * NU / (1.0 - 2.0 * NU)
+C = 10.0
+OMEGA = 1.0 / 0.5025
+
+
+def ricker(t):
+    z = (t - T0) / S
+    p = 2.0 * P0 / (np.sqrt(3.0 * S) * np.pi ** 0.25) * (1.0 - z * z) * np.exp(-0.5 * z * z)
+    return p if 0.0 <= t <= 2.0 else 0.0
+
+
+def taper(ny=NY, width=8):
+    d = np.minimum(np.arange(ny), ny - 1 - np.arange(ny))
+    w = np.where(d < width, np.sin(np.pi * (d + 0.5) / (2 * width)) ** 2, 1.0)
+    dx = HEIGHT / ny
+    return w / (w.sum() * dx)
+
+
+def problem(law="nh"):
+    dx = LENGTH / NX
+    w = taper()
+
+    def right_traction(t):
+        return np.array([np.zeros(NY), ricker(t) * w])
+
+    edges = [lbm.Edge("velocity"), lbm.Edge("traction", right_traction),
+             lbm.Edge("traction"), lbm.Edge("traction")]
+    return lbm.Problem(nx=NX, ny=NY, c=C, omega=OMEGA, law=law, mu=MU, lam=LAM, dx=dx, edges=edges)
+
+
+def run(t_end=12.0, every=None):
+    """Runs to t_end; returns the J range at t_end, the maximum over time of the absolute
+    vertical displacement at the free end (right-edge nodes), the maximum over time of the
+    displacement magnitude over the beam, and the final (U, u)."""
+    pb = problem()
+    st = lbm.initial_state(pb, np.zeros((2, NY, NX)))
+    nsteps = int(round(t_end / pb.dt))
+    tip_max = 0.0
+    umag_max = 0.0
+    for k in range(nsteps):
+        _, u = lbm.step(pb, st)
+        tip_max = max(tip_max, float(np.abs(u[1, :, -1]).max()))
+        umag_max = max(umag_max, float(np.sqrt((u ** 2).sum(0)).max()))
+    U, u = lbm.observe(pb, st)
+    tip_max = max(tip_max, float(np.abs(u[1, :, -1]).max()))
+    umag_max = max(umag_max, float(np.sqrt((u ** 2).sum(0)).max()))
+    F = lbm.F_of(U)
+    from . import material as mat
+    J = mat.det(F)
+    return dict(J_min=float(J.min()), J_max=float(J.max()), tip_max=tip_max, umag_max=umag_max,
+                steps=nsteps, U=U, u=u)

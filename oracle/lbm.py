@@ -255,7 +255,7 @@ def newton_normal_column(law, A, NA, tang, T, mu, lam, guess, max_iter, tol):
     and the first one with det F^b > 0 and a strictly smaller |r| is taken; a node stops
     when |r| <= tol (|T| + mu |F^b - I|), when no step length is accepted, or after
     max_iter updates.  Returns (a, failed) where failed flags |r| above 1e-4 of that scale
-    or det F^b <= 0."""
+    (plus the rounding floor of the unshifted evaluation) or det F^b <= 0."""
     Bax = 1 - A
 
     def residual(a):
@@ -304,7 +304,9 @@ def newton_normal_column(law, A, NA, tang, T, mu, lam, guess, max_iter, tol):
         active &= accepted
         a, r = a_new, r_new
     rn = np.sqrt((r * r).sum(0))
-    failed = (rn > 1e-4 * scale_of(a)) | (mat.det(_assemble(A, a, tang)) <= 0)
+    # the unshifted F leaves a rounding floor of order eps (|T| + 2 mu) in the residual
+    floor = 1e3 * np.finfo(np.float64).eps * (np.sqrt((T * T).sum(0)) + 2.0 * mu)
+    failed = (rn > 1e-4 * scale_of(a) + floor) | (mat.det(_assemble(A, a, tang)) <= 0)
     del Bax
     return a, failed
 

@@ -106,3 +106,84 @@ def relative_errors(n, t_end=0.1, second_order=True, **kw):
     def rel(a, b):
         return float(np.sqrt(((a - b) ** 2).sum()) / np.sqrt((b ** 2).sum()))
     return dict(u=rel(u, ex["u"]), P=rel(Ph, Pe), sigma=rel(Sh, Se), steps=nsteps)
+
+
+# ----------------------------------------------------------------------------- boundary MMS
+
+def boundary_setup(n, mode="dirichlet", c=5.0, omega=2.0, law="lognh", mu=1.0, lam=2.0 / 3.0):
+    """Manufactured solution of Sec. 4.2 on the bounded square (0, 1)^2 with half-way walls.
+
+    mode 'dirichlet': exact material velocity v = d_t u on every side
+    (eq:boundary-mms-dirichlet); mode 'mixed': exact velocity on X = 0 and Y = 0, exact
+    nominal traction P(I + grad u) N on X = 1 and Y = 1 (eq:boundary-mms-mixed).  The wall
+    data are evaluated at the half-way wall points and at t^{n+1/2} (eq:boundary-general)."""
+    from .lbm import Edge, XMIN, XMAX, YMIN, YMAX
+    X, Y = grid(n)
+    dx = 1.0 / n
+    dt = dx / c
+    s = (np.arange(n) + 0.5) / n
+
+    def wall_points(e):
+        if e == XMIN:
+            return np.zeros(n), s
+        if e == XMAX:
+            return np.ones(n), s
+        if e == YMIN:
+            return s, np.zeros(n)
+        return s, np.ones(n)
+
+    normals = {XMIN: (-1.0, 0.0), XMAX: (1.0, 0.0), YMIN: (0.0, -1.0), YMAX: (0.0, 1.0)}
+
+    def velocity_data(e):
+        Xw, Yw = wall_points(e)
+        return lambda t: fields(Xw, Yw, t)["v"]
+
+    def traction_data(e):
+        Xw, Yw = wall_points(e)
+        N = np.array(normals[e])
+
+        def T(t):
+            P = mat.stress(law, fields(Xw, Yw, t)["F"], mu, lam)
+            return np.einsum("iA...,A->i...", P, N)
+        return T
+
+    kinds = {XMIN: "velocity", YMIN: "velocity",
+             XMAX: "velocity" if mode == "dirichlet" else "traction",
+             YMAX: "velocity" if mode == "dirichlet" else "traction"}
+    edges = []
+    for e in range(4):
+        data = velocity_data(e) if kinds[e] == "velocity" else traction_data(e)
+        edges.append(Edge(kinds[e], data))
+    pb = lbm.Problem(nx=n, ny=n, c=c, omega=omega, law=law, mu=mu, lam=lam, dx=dx,
+                     body=lambda m: body_force(law, mu, lam, X, Y, m * dt), edges=edges)
+    f0 = fields(X, Y, 0.0)
+    F0 = f0["F"]
+    U0 = np.array([f0["v"][0], f0["v"][1], F0[0, 0], F0[0, 1], F0[1, 0], F0[1, 1]])
+    dUdX = np.array([f0["dv_dX"][0], f0["dv_dX"][1], f0["dF_dX"][0, 0], f0["dF_dX"][0, 1],
+                     f0["dF_dX"][1, 0], f0["dF_dX"][1, 1]])
+    dUdY = np.array([f0["dv_dY"][0], f0["dv_dY"][1], f0["dF_dY"][0, 0], f0["dF_dY"][0, 1],
+                     f0["dF_dY"][1, 0], f0["dF_dY"][1, 1]])
+    f = lbm.second_order_populations(pb, U0, dUdX, dUdY, pb.B(0))
+    st = lbm.State(f=f, ustar=f0["u"] - 0.5 * dt * f0["v"], n=0)
+    return pb, st, (X, Y)
+
+
+def boundary_errors(n, mode="dirichlet", t_end=0.1, layers=2, **kw):
+    """E_L2 of u, P and sigma over the full domain and after removing `layers` grid layers
+    next to the boundary (Sec. 4.2, Table tab:mms-error-summary)."""
+    pb, st, (X, Y) = boundary_setup(n, mode, **kw)
+    nsteps = int(round(t_end / pb.dt))
+    U, u = lbm.run(pb, st, nsteps)
+    ex = fields(X, Y, nsteps * pb.dt)
+    Fh = lbm.F_of(U)
+    Ph, Pe = mat.stress(pb.law, Fh, pb.mu, pb.lam), mat.stress(pb.law, ex["F"], pb.mu, pb.lam)
+    Sh, Se = mat.cauchy(pb.law, Fh, pb.mu, pb.lam), mat.cauchy(pb.law, ex["F"], pb.mu, pb.lam)
+
+    def rel(a, b, sl=(slice(None), slice(None))):
+        a = a[(Ellipsis,) + sl]
+        b = b[(Ellipsis,) + sl]
+        return float(np.sqrt(((a - b) ** 2).sum()) / np.sqrt((b ** 2).sum()))
+    inner = (slice(layers, n - layers), slice(layers, n - layers))
+    return dict(u=rel(u, ex["u"]), P=rel(Ph, Pe), sigma=rel(Sh, Se),
+                u_in=rel(u, ex["u"], inner), P_in=rel(Ph, Pe, inner), sigma_in=rel(Sh, Se, inner),
+                steps=nsteps)

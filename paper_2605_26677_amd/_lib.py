@@ -38,7 +38,7 @@ class lbm_state(ctypes.Structure):
     _fields_ = [
         ("pop", c_vp * 2), ("cur", c_i32), ("ustar", c_vp), ("mu", c_vp), ("lam", c_vp),
         ("mu0", c_dbl), ("lam0", c_dbl), ("mu_max", c_dbl), ("lam_max", c_dbl),
-        ("body", c_vp), ("b0", c_dbl * 2), ("aux", c_vp), ("fault", c_vp),
+        ("body", c_vp), ("body_prev", c_vp), ("b0", c_dbl * 2), ("aux", c_vp), ("fault", c_vp),
     ]
 
 
@@ -69,6 +69,7 @@ SIGNATURES = {
     "lbm_step": (c_i32, [P(lbm_params), P(lbm_state), c_i64, c_dbl, c_dbl, P(lbm_edge_data), c_vp, c_vp]),
     "lbm_displacement": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp]),
     "lbm_moments": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp]),
+    "lbm_stress": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp, c_vp]),
     "lbm_diagnostics": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp, c_vp]),
     "lbm_adjoint_step": (c_i32, [P(lbm_params), P(lbm_state), P(lbm_adj_state), c_i64, c_dbl,
                                  P(lbm_edge_data), c_vp, c_vp]),

@@ -407,13 +407,14 @@ static hipError_t adjoint_st_law(const AdjArgs& a0, hipStream_t s) {
         if (fields) hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, true>), dim3(nblk(L)), dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, false>), dim3(nblk(L)), dim3(kBlock), 0, s, a);
     }
-    const dim3 grid(unsigned((int64_t(a.cm.ntile) * a.cm.ny + 3) / 4));
+    const dim3 grid(unsigned((int64_t(a.cm.ntile) * a.cm.ny + kTilesPerBlock - 1) / kTilesPerBlock));
+    const dim3 block(kTile * kTilesPerBlock);
     if (walls) {
-        if (fields) hipLaunchKernelGGL((adjoint_kernel<ST, LAW, true, true>), grid, dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((adjoint_kernel<ST, LAW, true, false>), grid, dim3(kBlock), 0, s, a);
+        if (fields) hipLaunchKernelGGL((adjoint_kernel<ST, LAW, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((adjoint_kernel<ST, LAW, true, false>), grid, block, 0, s, a);
     } else {
-        if (fields) hipLaunchKernelGGL((adjoint_kernel<ST, LAW, false, true>), grid, dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((adjoint_kernel<ST, LAW, false, false>), grid, dim3(kBlock), 0, s, a);
+        if (fields) hipLaunchKernelGGL((adjoint_kernel<ST, LAW, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((adjoint_kernel<ST, LAW, false, false>), grid, block, 0, s, a);
     }
     // stage 2, one edge at a time (corner nodes belong to two edges)
     for (int e = 0; e < 4; ++e) {

@@ -52,6 +52,7 @@ Common make_common(const lbm_params* p, const lbm_state* s) {
         cm.mu = s->mu;
         cm.lam = s->lam;
         cm.body = s->body;
+        cm.body_prev = s->body_prev;
         cm.fault = s->fault;
     }
     return cm;
@@ -69,8 +70,9 @@ EdgeData make_edges(const lbm_edge_data* ed) {
     return out;
 }
 
-lbm_status check_state(const lbm_params* p, const lbm_state* s) {
-    if (!s || !s->pop[0] || !s->pop[1] || !s->ustar || !s->fault) return LBM_ERR_ARG;
+lbm_status check_state(const lbm_params* p, const lbm_state* s, bool need_ustar = true) {
+    if (!s || !s->pop[0] || !s->pop[1] || !s->fault) return LBM_ERR_ARG;
+    if (need_ustar && !s->ustar) return LBM_ERR_ARG;
     if (s->cur != 0 && s->cur != 1) return LBM_ERR_ARG;
     if (has_traction(p) && !s->aux) return LBM_ERR_ARG;
     return LBM_OK;
@@ -154,7 +156,7 @@ lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, do
     (void)n;
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
-    if ((st = check_state(p, s)) != LBM_OK) return st;
+    if ((st = check_state(p, s, false)) != LBM_OK) return st;
     const hipStream_t hs = (hipStream_t)stream;
     const Common cm = make_common(p, s);
     const EdgeData ed = make_edges(at_half);
@@ -162,6 +164,7 @@ lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, do
         if (p->bc[e] != LBM_TRACTION) continue;
         TractionArgs t{};
         t.cm = cm;
+        if (cm.body_prev) t.cm.body = cm.body_prev;
         t.pop = s->pop[s->cur];
         t.aux = s->aux;
         t.r_n = r_n;
@@ -184,10 +187,10 @@ lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, do
 }
 
 static lbm_status recover_common(const lbm_params* p, const lbm_state* s, double r_n, void* out,
-                                 RecoverArgs& a) {
+                                 RecoverArgs& a, bool need_ustar = false) {
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
-    if ((st = check_state(p, s)) != LBM_OK) return st;
+    if ((st = check_state(p, s, need_ustar)) != LBM_OK) return st;
     if (!out) return LBM_ERR_ARG;
     a = RecoverArgs{};
     a.cm = make_common(p, s);
@@ -200,7 +203,7 @@ static lbm_status recover_common(const lbm_params* p, const lbm_state* s, double
 
 lbm_status lbm_displacement(const lbm_params* p, const lbm_state* s, double r_n, double* u_out, void* stream) {
     RecoverArgs a;
-    lbm_status st = recover_common(p, s, r_n, u_out, a);
+    lbm_status st = recover_common(p, s, r_n, u_out, a, true);
     if (st != LBM_OK) return st;
     return launched(launch_displacement(a, (hipStream_t)stream));
 }
@@ -217,6 +220,15 @@ lbm_status lbm_record_state(const lbm_params* p, const lbm_state* s, double r_n,
     lbm_status st = recover_common(p, s, r_n, record, a);
     if (st != LBM_OK) return st;
     return launched(launch_record(a, (hipStream_t)stream));
+}
+
+lbm_status lbm_stress(const lbm_params* p, const lbm_state* s, double r_n, double* P_out, double* sigma_out,
+                      void* stream) {
+    RecoverArgs a;
+    lbm_status st = recover_common(p, s, r_n, P_out, a);
+    if (st != LBM_OK) return st;
+    a.out2 = sigma_out;
+    return launched(launch_stress(a, (hipStream_t)stream));
 }
 
 lbm_status lbm_diagnostics(const lbm_params* p, const lbm_state* s, double r_n, double* out, void* scratch,

@@ -144,11 +144,18 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     const int64_t sb[4] = {tile_base(ntile, 24, xm, y), tile_base(ntile, 24, x, ym),
                            tile_base(ntile, 24, xp, y), tile_base(ntile, 24, x, yp)};
 
+    // x-neighbour pulls come from the own tile (but for one lane), so issue them first
     R g[4][6];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int k = 0; k < 6; ++k) {
+        g[0][k] = R(src[sb[0] + k * kTile]);
+        g[2][k] = R(src[sb[2] + (12 + k) * kTile]);
+    }
 #pragma unroll
-        for (int k = 0; k < 6; ++k) g[q][k] = R(src[sb[q] + (6 * q + k) * kTile]);
+    for (int k = 0; k < 6; ++k) {
+        g[1][k] = R(src[sb[1] + (6 + k) * kTile]);
+        g[3][k] = R(src[sb[3] + (18 + k) * kTile]);
+    }
 
     if constexpr (WALLS) {
         if (miss0) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMIN, y, src, own, g[0]);
@@ -194,7 +201,9 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     }
 
     // displacement quadrature u*^{n+2} = u*^{n+1} + dt v^{n+1} (eq:trapezoid-u)
-    if constexpr (ST == LBM_F64_PLAIN) {
+    if (!a.ustar) {
+        // replay for the adjoint: the accumulator is not needed
+    } else if constexpr (ST == LBM_F64_PLAIN) {
         double* us = (double*)a.ustar + tile_base(ntile, 2, x, y);
         store_stream(us, us[0] + dt * U[0]);
         store_stream(us + kTile, us[kTile] + dt * U[1]);
@@ -274,6 +283,44 @@ __global__ void __launch_bounds__(kBlock) recover_kernel(RecoverArgs a) {
             }
             out[cpt * n + idx] = ustar - hdt * double(U[cpt]);
         }
+    }
+}
+
+// ---------------------------------------------------------------- stresses
+
+// P(F) and sigma = J^{-1} P F^T (Sec. 3.5) of the recovered state, in FP64 from the
+// stored populations (shifted evaluation for every storage: F - I is formed first).
+template <int ST, int LAW, bool FIELDS>
+__global__ void __launch_bounds__(kBlock) stress_kernel(RecoverArgs a) {
+    using Tr = Storage<ST>;
+    using R = typename Tr::real;
+    using T = typename Tr::pop_t;
+    constexpr bool SH = Tr::shifted;
+    const Common& cm = a.cm;
+    const int64_t n = int64_t(cm.nx) * cm.ny;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int y = int(idx / cm.nx), x = int(idx - int64_t(y) * cm.nx);
+    double b0, b1;
+    body_at<FIELDS>(cm, (int)idx, n, a.r_n, b0, b1);
+    const double hdt = 0.5 * cm.dt;
+    R U[6];
+    recover_node<T, R>((const T*)a.pop, cm.ntile, x, y, R(hdt * b0), R(hdt * b1), U);
+    double ft[4] = {double(U[2]), double(U[3]), double(U[4]), double(U[5])};
+    if (!SH) { ft[0] -= 1.0; ft[3] -= 1.0; }
+    double mu, lam;
+    params_at<FIELDS, double>(cm, (int)idx, mu, lam);
+    double P[4], J;
+    piola<double, LAW, true>(ft, mu, lam, P, J);
+    double* Po = (double*)a.out;
+    for (int k = 0; k < 4; ++k) Po[k * n + idx] = P[k];
+    if (a.out2) {
+        const double F[4] = {1.0 + ft[0], ft[1], ft[2], 1.0 + ft[3]};
+        const double iJ = 1.0 / J;
+        double* So = (double*)a.out2;
+        So[idx] = iJ * (P[0] * F[0] + P[1] * F[1]);
+        So[n + idx] = iJ * (P[0] * F[2] + P[1] * F[3]);
+        So[2 * n + idx] = iJ * (P[2] * F[2] + P[3] * F[3]);
     }
 }
 
@@ -525,13 +572,14 @@ template <int ST, int LAW>
 static hipError_t step_st_law(const StepArgs& a, hipStream_t s) {
     const bool walls = !(a.cm.periodic_x && a.cm.periodic_y);
     const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
-    const dim3 grid(unsigned((int64_t(a.cm.ntile) * a.cm.ny + 3) / 4));
+    const dim3 grid(unsigned((int64_t(a.cm.ntile) * a.cm.ny + kTilesPerBlock - 1) / kTilesPerBlock));
+    const dim3 block(kTile * kTilesPerBlock);
     if (walls) {
-        if (fields) hipLaunchKernelGGL((step_kernel<ST, LAW, true, true>), grid, dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((step_kernel<ST, LAW, true, false>), grid, dim3(kBlock), 0, s, a);
+        if (fields) hipLaunchKernelGGL((step_kernel<ST, LAW, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<ST, LAW, true, false>), grid, block, 0, s, a);
     } else {
-        if (fields) hipLaunchKernelGGL((step_kernel<ST, LAW, false, true>), grid, dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((step_kernel<ST, LAW, false, false>), grid, dim3(kBlock), 0, s, a);
+        if (fields) hipLaunchKernelGGL((step_kernel<ST, LAW, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<ST, LAW, false, false>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }
@@ -598,6 +646,32 @@ static hipError_t recover_dispatch(const RecoverArgs& a, hipStream_t s) {
 hipError_t launch_moments(const RecoverArgs& a, hipStream_t s) { return recover_dispatch<0>(a, s); }
 hipError_t launch_record(const RecoverArgs& a, hipStream_t s) { return recover_dispatch<1>(a, s); }
 hipError_t launch_displacement(const RecoverArgs& a, hipStream_t s) { return recover_dispatch<2>(a, s); }
+
+template <int ST, int LAW>
+static void stress_st_law(const RecoverArgs& a, hipStream_t s) {
+    const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
+    const dim3 grid(nblocks(int64_t(a.cm.nx) * a.cm.ny));
+    if (fields) hipLaunchKernelGGL((stress_kernel<ST, LAW, true>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((stress_kernel<ST, LAW, false>), grid, dim3(kBlock), 0, s, a);
+}
+
+template <int ST>
+static void stress_st(const RecoverArgs& a, hipStream_t s) {
+    switch (a.cm.material) {
+        case LBM_LOGNH: stress_st_law<ST, LBM_LOGNH>(a, s); break;
+        case LBM_NH: stress_st_law<ST, LBM_NH>(a, s); break;
+        default: stress_st_law<ST, LBM_SVK>(a, s); break;
+    }
+}
+
+hipError_t launch_stress(const RecoverArgs& a, hipStream_t s) {
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: stress_st<LBM_F32_SHIFTED>(a, s); break;
+        case LBM_F16_SHIFTED: stress_st<LBM_F16_SHIFTED>(a, s); break;
+        default: stress_st<LBM_F64_PLAIN>(a, s); break;
+    }
+    return hipGetLastError();
+}
 
 template <int ST, int LAW>
 static void diag_st_law(const RecoverArgs& a, hipStream_t s) {

@@ -8,7 +8,9 @@
 
 namespace lbm {
 
-constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
+constexpr int kBlock = 256;          // threads per workgroup of the node-indexed kernels
+constexpr int kTilesPerBlock = 2;    // 64-node tiles (one wavefront each) per workgroup of the
+                                     // step and adjoint kernels
 constexpr int kDiagBlocks = 1024;    // partial sums of the diagnostics reduction
 
 // Offsets of each edge's links in the traction staging buffer (links, not bytes).
@@ -33,6 +35,7 @@ struct Common {
     const float* mu;
     const float* lam;
     const float* body;
+    const float* body_prev;          // field of level n for the step n -> n+1 (or NULL)
     uint32_t* fault;
     int newton_max_iter;
     double newton_tol;
@@ -64,6 +67,7 @@ struct RecoverArgs {
     const void* ustar;
     double r_n;
     void* out;                       // double planes (moments / displacement) or record
+    void* out2;                      // second output (Cauchy stress) or NULL
     void* scratch;                   // diagnostics partials
 };
 
@@ -117,6 +121,7 @@ hipError_t launch_moments(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_record(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_displacement(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_diagnostics(const RecoverArgs& a, hipStream_t s);
+hipError_t launch_stress(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_init_state(const InitArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s);

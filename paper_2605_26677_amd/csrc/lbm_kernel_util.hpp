@@ -115,7 +115,11 @@ __device__ bool newton_column(int A, R NA, const R tang[2], const R T[2], R mu, 
         if (!accepted) break;
     }
     const R rn = sqrt_r(r[0] * r[0] + r[1] * r[1]);
-    return (rn <= R(1e-4) * scale(a)) && (J > R(0)) && finite_r(rn);
+    // With the plain F the residual cannot drop below the rounding of terms of size
+    // |T| + 2 mu (P subtracts O(mu) quantities); the shifted form has no such floor.
+    const R eps = sizeof(R) == 8 ? R(2.220446049250313e-16) : R(1.1920929e-7);
+    const R floor = SH ? R(0) : R(1e3) * eps * (sqrt_r(T[0] * T[0] + T[1] * T[1]) + R(2) * mu);
+    return (rn <= R(1e-4) * scale(a) + floor) && (J > R(0)) && finite_r(rn);
 }
 
 // Tangential stencil of the traction-wall extrapolation at position s of an edge of
@@ -154,10 +158,10 @@ __device__ __forceinline__ XY edge_node(const EdgeGeom& G, int nx, int ny, int r
     return XY{s2, (G.NA < 0) ? r : ny - 1 - r};
 }
 
-// Tile-grid position of this thread for kernels with one wavefront per tile and four
-// tiles per 256-thread workgroup.  Returns false for lanes beyond the grid.
+// Tile-grid position of this thread for kernels with one wavefront per tile and
+// blockDim.x / 64 tiles per workgroup.  Returns false for lanes beyond the grid.
 __device__ __forceinline__ bool tile_thread(int nx, int ny, int ntile, int& x, int& y) {
-    const int tl = remap_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int tl = remap_tile(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (tl >= ntile * ny) return false;
     y = tl / ntile;
     x = (tl - y * ntile) * kTile + (threadIdx.x & (kTile - 1));

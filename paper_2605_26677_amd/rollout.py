@@ -88,20 +88,21 @@ def _restore(sv, snap):
     sv.pop[sv.s.cur].copy_(snap[0])
 
 
-def _step_to_snapshot(sv, cfg, n):
+def _step_to_snapshot(sv, cfg, n, ustar=True):
     """Step n -> n + 1 and keep (f*^{n+1}, U^{n+1}); the record comes from the step kernel
     itself, exactly as a replay would produce it, so every schedule sees the same records."""
     rec = sv.new_record()
-    sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=rec)
+    sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=rec, ustar=ustar)
     return (sv.pop[sv.s.cur].clone(), rec)
 
 
 def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
-    """Adjoint levels end-1 .. start, starting from the snapshot of level `start`."""
+    """Adjoint levels end-1 .. start, starting from the snapshot of level `start`.  The
+    replay skips the displacement quadrature (the adjoint does not read u*)."""
     _restore(sv, snap)
     recs[0].copy_(snap[1])
     for n in range(start, end - 1):
-        sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=recs[n + 1 - start])
+        sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=recs[n + 1 - start], ustar=False)
     for m in range(end - 1, start - 1, -1):
         adj.step(sv, cfg, m, recs[m - start])
 
@@ -118,8 +119,8 @@ def _reverse_nested(sv, cfg, adj, start, end, snap, lengths, recs):
     _restore(sv, snap)
     for i in range(len(bounds) - 2):
         for n in range(bounds[i], bounds[i + 1] - 1):
-            sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n))
-        snaps.append(_step_to_snapshot(sv, cfg, bounds[i + 1] - 1))
+            sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), ustar=False)
+        snaps.append(_step_to_snapshot(sv, cfg, bounds[i + 1] - 1, ustar=False))
     for i in range(len(bounds) - 2, -1, -1):
         _reverse_nested(sv, cfg, adj, bounds[i], bounds[i + 1], snaps[i], lengths[1:], recs)
         snaps.pop()

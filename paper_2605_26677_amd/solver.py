@@ -96,6 +96,14 @@ class Solver:
             self.body_t = torch.as_tensor(body, dtype=torch.float32, device=self.device).contiguous()
             s.body = self.body_t.data_ptr()
 
+    def set_body_levels(self, body_prev, body_next):
+        """Per-step body force fields: body_prev for level n, body_next for level n + 1
+        of the next lbm_step (float32 device tensors (2, ny, nx); use r = 1)."""
+        self._body_prev = body_prev.contiguous()
+        self.body_t = body_next.contiguous()
+        self.s.body = self.body_t.data_ptr()
+        self.s.body_prev = self._body_prev.data_ptr()
+
     # ------------------------------------------------------------ sizes
     @property
     def tiles_per_row(self):
@@ -124,10 +132,17 @@ class Solver:
         L.check(self.lib.lbm_init(ctypes.byref(self.p), ctypes.byref(self.s), _ptr(self._v0), _ptr(self._u0),
                                   float(r0), _stream()), "lbm_init")
 
-    def step(self, n, r_n=1.0, r_np1=1.0, edges=None, record=None):
+    def step(self, n, r_n=1.0, r_np1=1.0, edges=None, record=None, ustar=True):
+        """lbm_step; ustar=False skips the displacement quadrature (replays)."""
         ed = edges if isinstance(edges, EdgeData) else EdgeData(edges)
-        L.check(self.lib.lbm_step(ctypes.byref(self.p), ctypes.byref(self.s), int(n), float(r_n), float(r_np1),
-                                  ctypes.byref(ed.c), _ptr(record), _stream()), "lbm_step")
+        keep = self.s.ustar
+        if not ustar:
+            self.s.ustar = None
+        try:
+            L.check(self.lib.lbm_step(ctypes.byref(self.p), ctypes.byref(self.s), int(n), float(r_n),
+                                      float(r_np1), ctypes.byref(ed.c), _ptr(record), _stream()), "lbm_step")
+        finally:
+            self.s.ustar = keep
 
     def moments(self, r_n=1.0):
         out = torch.empty((6, self.ny, self.nx), dtype=torch.float64, device=self.device)
@@ -140,6 +155,15 @@ class Solver:
         L.check(self.lib.lbm_displacement(ctypes.byref(self.p), ctypes.byref(self.s), float(r_n), _ptr(out),
                                           _stream()), "lbm_displacement")
         return out
+
+    def stress(self, r_n=1.0):
+        """(P (2, 2, ny, nx), sigma (2, 2, ny, nx)) in FP64 at the current level."""
+        P = torch.empty((4, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        S = torch.empty((3, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        L.check(self.lib.lbm_stress(ctypes.byref(self.p), ctypes.byref(self.s), float(r_n), _ptr(P), _ptr(S),
+                                    _stream()), "lbm_stress")
+        sig = torch.stack([S[0], S[1], S[1], S[2]])
+        return P.view(2, 2, self.ny, self.nx), sig.view(2, 2, self.ny, self.nx)
 
     def record_state(self, r_n, out):
         L.check(self.lib.lbm_record_state(ctypes.byref(self.p), ctypes.byref(self.s), float(r_n), _ptr(out),

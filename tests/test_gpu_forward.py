@@ -188,3 +188,21 @@ def test_fault_bits_forced_from_host():
     sv.step(0, edges=[(0, 0), (0.05, 0.02), (0, 0), (0, 0)])
     torch.cuda.synchronize()
     assert sv.faults() & 4
+
+
+@pytest.mark.parametrize("storage,bar", [("f64", 1e-10), ("f32", 1e-5)])
+@pytest.mark.parametrize("law", ["lognh", "nh", "svk"])
+def test_stress_recovery(storage, bar, law):
+    """lbm_stress: P(F) and sigma = J^-1 P F^T (Sec. 3.5) of the recovered state."""
+    from oracle import material as mat
+    case = mixed_case(law=law)
+    Uo, _, _ = run_oracle(case)
+    sv, _, _ = run_library(case, storage)
+    P, S = (t.cpu().numpy() for t in sv.stress(case.ramp(case.steps)))
+    F = np.array([[Uo[2], Uo[3]], [Uo[4], Uo[5]]])
+    Pe = mat.stress(law, F, case.mu, case.lam)
+    Se = mat.cauchy(law, F, case.mu, case.lam)
+    eP = rel_l2(P, Pe)
+    eS = rel_l2(S, Se)
+    print(f"\n[stress {law} {storage}] P={eP:.2e} sigma={eS:.2e}")
+    assert eP <= bar and eS <= bar
