@@ -14,6 +14,16 @@ the tests by central differences of P (and P itself by central differences of W)
 import numpy as np
 
 LAWS = ("lognh", "nh", "svk")
+INVARIANT_LAWS = ("mr", "yeoh", "gent")
+ALL_LAWS = LAWS + INVARIANT_LAWS
+
+# Law constants of the invariant-based closures, in units of mu (Appendix A sets
+# c10 + c01 = mu/2 for Mooney-Rivlin and c1 = mu/2 for Yeoh; the split and the higher Yeoh
+# coefficients and the Gent limit are not printed, these are readings):
+#   mr:   c10 = a mu, c01 = (1/2 - a) mu            (param a)
+#   yeoh: c1 = mu/2, c2 = b2 mu, c3 = b3 mu          (params b2, b3)
+#   gent: J_m                                        (param J_m)
+DEFAULT_PARAMS = {"mr": (0.3,), "yeoh": (0.05, 0.01), "gent": (20.0,)}
 
 
 def det(F):
@@ -38,8 +48,39 @@ def green_lagrange(F):
     return 0.5 * (C - _eye_like(F))
 
 
-def energy(law, F, mu, lam):
+def _invariants(F):
+    """eq:modified-invariants with the plane-strain embedding (out-of-plane stretch 1):
+    I1 = tr C + 1, I2 = J^2 + tr C, barI1 = J^(-2/3) I1, barI2 = J^(-4/3) I2."""
+    J = det(F)
+    trC = np.einsum("mA...,mA...->...", F, F)
+    I1 = trC + 1.0
+    I2 = J * J + trC
+    return J, I1, I2, J ** (-2.0 / 3.0) * I1, J ** (-4.0 / 3.0) * I2
+
+
+def _G1_G2(F):
+    """eq:modified-invariant-gradients: G1 = d barI1/dF, G2 = d barI2/dF."""
+    J, I1, I2, _, _ = _invariants(F)
+    H = inv_transpose(F)
+    G1 = J ** (-2.0 / 3.0) * (2.0 * F - (2.0 / 3.0) * I1 * H)
+    G2 = J ** (-4.0 / 3.0) * (2.0 * F + (2.0 * J * J - (4.0 / 3.0) * I2) * H)
+    return G1, G2
+
+
+def energy(law, F, mu, lam, params=None):
     """Strain energy density W(F) per reference area (Appendix A)."""
+    if law in INVARIANT_LAWS:
+        prm = DEFAULT_PARAMS[law] if params is None else params
+        J, I1, I2, bI1, bI2 = _invariants(F)
+        vol = 0.5 * lam * np.log(J) ** 2
+        A = bI1 - 3.0
+        if law == "mr":                      # eq:mr-model
+            a = prm[0]
+            return a * mu * A + (0.5 - a) * mu * (bI2 - 3.0) + vol
+        if law == "yeoh":                    # eq:yeoh-model
+            return 0.5 * mu * A + prm[0] * mu * A ** 2 + prm[1] * mu * A ** 3 + vol
+        Jm = prm[0]                          # eq:gent-model
+        return -0.5 * mu * Jm * np.log(1.0 - A / Jm) + vol
     J = det(F)
     trC = np.einsum("mA...,mA...->...", F, F)
     if law == "lognh":                       # eq:lognh-model
@@ -56,8 +97,22 @@ def energy(law, F, mu, lam):
     raise ValueError(law)
 
 
-def stress(law, F, mu, lam):
+def stress(law, F, mu, lam, params=None):
     """First Piola-Kirchhoff stress P(F) (Appendix A)."""
+    if law in INVARIANT_LAWS:
+        prm = DEFAULT_PARAMS[law] if params is None else params
+        J, I1, I2, bI1, bI2 = _invariants(F)
+        G1, G2 = _G1_G2(F)
+        H = inv_transpose(F)
+        vol = lam * np.log(J) * H
+        A = bI1 - 3.0
+        if law == "mr":                      # P = c10 G1 + c01 G2 + lam ln J H
+            a = prm[0]
+            return a * mu * G1 + (0.5 - a) * mu * G2 + vol
+        if law == "yeoh":                    # P = (c1 + 2 c2 A + 3 c3 A^2) G1 + lam ln J H
+            return (0.5 * mu + 2.0 * prm[0] * mu * A + 3.0 * prm[1] * mu * A ** 2) * G1 + vol
+        Jm = prm[0]                          # P = mu / (2 (1 - A/J_m)) G1 + lam ln J H
+        return mu / (2.0 * (1.0 - A / Jm)) * G1 + vol
     if law in ("lognh", "nh"):
         J = det(F)
         H = inv_transpose(F)
@@ -74,8 +129,21 @@ def stress(law, F, mu, lam):
     raise ValueError(law)
 
 
-def tangent(law, F, mu, lam):
+def tangent(law, F, mu, lam, params=None):
     """C_iAkB = dP_iA / dF_kB, shape (2, 2, 2, 2, ...)."""
+    if law in INVARIANT_LAWS:
+        # complex-step differentiation of P: dP/dF_kB = Im P(F + i h e_kB) / h, exact to
+        # rounding for real-analytic P (no subtraction of nearly equal numbers)
+        h = 1e-30
+        out = np.empty((2, 2, 2, 2) + F.shape[2:])
+        mu_c = np.asarray(mu) + 0j
+        lam_c = np.asarray(lam) + 0j
+        for k in range(2):
+            for B in range(2):
+                Fc = F.astype(np.complex128)
+                Fc[k, B] += 1j * h
+                out[:, :, k, B] = stress(law, Fc, mu_c, lam_c, params).imag / h
+        return out
     d = np.eye(2)
     shape = F.shape[2:]
     dd = np.einsum("ik,AB->iAkB", d, d).reshape((2, 2, 2, 2) + (1,) * len(shape))
@@ -104,14 +172,14 @@ def tangent(law, F, mu, lam):
     raise ValueError(law)
 
 
-def stress_parameter_partials(law, F):
-    """(dP/dmu, dP/dlam).  Every law here is linear in (mu, lam), so these are P at unit
-    parameters."""
-    return stress(law, F, 1.0, 0.0), stress(law, F, 0.0, 1.0)
+def stress_parameter_partials(law, F, params=None):
+    """(dP/dmu, dP/dlam).  Every law here is linear in (mu, lam) (the invariant laws'
+    constants are multiples of mu), so these are P at unit parameters."""
+    return stress(law, F, 1.0, 0.0, params), stress(law, F, 0.0, 1.0, params)
 
 
-def tangent_parameter_partials(law, F):
-    return tangent(law, F, 1.0, 0.0), tangent(law, F, 0.0, 1.0)
+def tangent_parameter_partials(law, F, params=None):
+    return tangent(law, F, 1.0, 0.0, params), tangent(law, F, 0.0, 1.0, params)
 
 
 def acoustic_tensor(law, F, mu, lam, n):

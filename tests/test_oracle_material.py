@@ -4,7 +4,21 @@ import pytest
 
 from oracle import material as mat
 
-LAWS = mat.LAWS
+LAWS = mat.ALL_LAWS
+
+
+def lame_tangent(mu, lam):
+    d = np.eye(2)
+    return (mu * (np.einsum("ik,AB->iAkB", d, d) + np.einsum("iB,kA->iAkB", d, d))
+            + lam * np.einsum("iA,kB->iAkB", d, d))
+
+
+def small_strain_lambda(law, mu, lam):
+    """In-plane Lame constant of the linearised law.  The invariant laws split W into an
+    isochoric part in the 3D modified invariants (out-of-plane stretch 1) and the bulk
+    term lam/2 (ln J)^2, so their small-strain energy is mu |dev3 eps|^2 + lam/2 (tr eps)^2
+    = mu eps:eps + (lam - 2 mu / 3)/2 (tr eps)^2: the plane Lame constant is lam - 2 mu/3."""
+    return lam - 2.0 * mu / 3.0 if law in mat.INVARIANT_LAWS else lam
 
 
 def random_F(rng, n, strain=0.3):
@@ -58,25 +72,25 @@ def test_reference_state_is_stress_free_exactly(law):
 
 @pytest.mark.parametrize("law", LAWS)
 def test_small_strain_limit_is_lame(law):
-    """C(I) = mu (d_ik d_AB + d_iB d_kA) + lam d_iA d_kB (linear elasticity)."""
+    """C(I) = mu (d_ik d_AB + d_iB d_kA) + lam' d_iA d_kB (linear elasticity), with
+    lam' = lam for the Lame-parametrised laws and lam - 2 mu/3 for the invariant laws,
+    whose shear modulus is 2 (c10 + c01) = 2 c1 = mu (Appendix A)."""
     mu, lam = 0.3, 0.8
     Cc = mat.tangent(law, np.eye(2), mu, lam)
-    d = np.eye(2)
-    lame = (mu * (np.einsum("ik,AB->iAkB", d, d) + np.einsum("iB,kA->iAkB", d, d))
-            + lam * np.einsum("iA,kB->iAkB", d, d))
-    assert np.allclose(Cc, lame, atol=1e-15)
+    assert np.allclose(Cc, lame_tangent(mu, small_strain_lambda(law, mu, lam)), atol=1e-14)
 
 
 @pytest.mark.parametrize("law", LAWS)
 def test_acoustic_speeds_at_rest(law):
-    """Eigenvalues of Q(n; I) are mu and lam + 2 mu for every direction n
+    """Eigenvalues of Q(n; I) are mu and lam' + 2 mu for every direction n
     (eq:acoustic-tensor-section2 at F = I: S- and P-wave speeds)."""
     mu, lam = 0.1, 0.2
+    lp = small_strain_lambda(law, mu, lam)
     for th in np.linspace(0, np.pi, 7):
         Q = mat.acoustic_tensor(law, np.eye(2), mu, lam, (np.cos(th), np.sin(th)))
         ev = np.sort(np.linalg.eigvalsh(Q))
-        assert np.allclose(ev, [mu, lam + 2 * mu], atol=1e-15)
-    assert np.isclose(mat.max_tangent_speed(law, np.eye(2), mu, lam), np.sqrt(lam + 2 * mu))
+        assert np.allclose(ev, [mu, lp + 2 * mu], atol=1e-14)
+    assert np.isclose(mat.max_tangent_speed(law, np.eye(2), mu, lam), np.sqrt(lp + 2 * mu))
 
 
 @pytest.mark.parametrize("law", LAWS)
@@ -102,6 +116,51 @@ def test_isochoric_shear_path(law):
     F[1, 0] = g
     P = mat.stress(law, F, 2.0, 7.0)
     assert np.allclose(P[1, 0], 2.0 * g, atol=1e-15)
+
+
+@pytest.mark.parametrize("law", mat.INVARIANT_LAWS)
+def test_invariant_laws_on_isochoric_shear(law):
+    """On F = [[1, 0], [g, 1]]: J = 1, barI1 - 3 = barI2 - 3 = g^2, so W reduces to a
+    polynomial (or log) in g and P21 = dW/dg in closed form: MR mu g, Yeoh
+    mu g + 4 c2 g^3 + 6 c3 g^5, Gent mu g / (1 - g^2 / J_m)."""
+    g = np.linspace(-0.6, 0.6, 13)
+    F = np.zeros((2, 2, g.size))
+    F[0, 0] = F[1, 1] = 1.0
+    F[1, 0] = g
+    mu = 1.7
+    prm = {"mr": (0.2,), "yeoh": (0.11, 0.03), "gent": (2.5,)}[law]
+    P = mat.stress(law, F, mu, 9.0, prm)
+    if law == "mr":
+        want = mu * g
+    elif law == "yeoh":
+        want = mu * g + 4 * prm[0] * mu * g ** 3 + 6 * prm[1] * mu * g ** 5
+    else:
+        want = mu * g / (1.0 - g * g / prm[0])
+    assert np.allclose(P[1, 0], want, rtol=1e-13, atol=1e-15)
+    W = mat.energy(law, F, mu, 9.0, prm)
+    if law == "mr":
+        Wwant = mu / 2 * g ** 2
+    elif law == "yeoh":
+        Wwant = mu / 2 * g ** 2 + prm[0] * mu * g ** 4 + prm[1] * mu * g ** 6
+    else:
+        Wwant = -mu * prm[0] / 2 * np.log(1 - g ** 2 / prm[0])
+    assert np.allclose(W, Wwant, rtol=1e-13, atol=1e-15)
+
+
+def test_invariant_law_special_cases_coincide():
+    """Yeoh with c2 = c3 = 0, Mooney-Rivlin with c01 = 0 and Gent as J_m -> infinity all
+    reduce to the same isochoric neo-Hookean law mu/2 (barI1 - 3) + lam/2 (ln J)^2."""
+    rng = np.random.default_rng(7)
+    F = random_F(rng, 30)
+    mu, lam = 0.9, 1.4
+    P_y = mat.stress("yeoh", F, mu, lam, (0.0, 0.0))
+    P_m = mat.stress("mr", F, mu, lam, (0.5,))
+    P_g = mat.stress("gent", F, mu, lam, (1e12,))
+    assert np.allclose(P_y, P_m, rtol=1e-14, atol=1e-15)
+    assert np.allclose(P_g, P_m, rtol=1e-10, atol=1e-12)
+    C_y = mat.tangent("yeoh", F, mu, lam, (0.0, 0.0))
+    C_m = mat.tangent("mr", F, mu, lam, (0.5,))
+    assert np.allclose(C_y, C_m, rtol=1e-13, atol=1e-14)
 
 
 def test_parameter_partials_are_linear():
