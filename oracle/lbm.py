@@ -46,7 +46,7 @@ class Problem:
     ny: int
     c: float                                    # lattice speed dx/dt (Sec. 2.1)
     omega: float                                # BGK relaxation rate (eq:collision)
-    law: str = "lognh"
+    law: object = "lognh"                       # name, or (name, constants) for MR / Yeoh / Gent
     mu: object = 0.1                            # scalar or (ny, nx)
     lam: object = 0.2
     dx: float = 1.0

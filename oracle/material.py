@@ -17,13 +17,26 @@ LAWS = ("lognh", "nh", "svk")
 INVARIANT_LAWS = ("mr", "yeoh", "gent")
 ALL_LAWS = LAWS + INVARIANT_LAWS
 
-# Law constants of the invariant-based closures, in units of mu (Appendix A sets
-# c10 + c01 = mu/2 for Mooney-Rivlin and c1 = mu/2 for Yeoh; the split and the higher Yeoh
-# coefficients and the Gent limit are not printed, these are readings):
-#   mr:   c10 = a mu, c01 = (1/2 - a) mu            (param a)
-#   yeoh: c1 = mu/2, c2 = b2 mu, c3 = b3 mu          (params b2, b3)
-#   gent: J_m                                        (param J_m)
-DEFAULT_PARAMS = {"mr": (0.3,), "yeoh": (0.05, 0.01), "gent": (20.0,)}
+# Law constants of the invariant-based closures.  The coefficients are given as multiples
+# of mu, so that P stays linear in (mu, lam) over a heterogeneous mu field:
+#   mr:   (k10, k01)      c10 = k10 mu, c01 = k01 mu
+#   yeoh: (k1, k2, k3)    c1 = k1 mu, c2 = k2 mu, c3 = k3 mu
+#   gent: (J_m,)
+# Appendix A fixes c10 + c01 = mu/2 and c1 = mu/2 when no constants are supplied; the
+# split of the Mooney-Rivlin pair, the higher Yeoh coefficients and the Gent limit are not
+# printed, the defaults below are readings.
+DEFAULT_PARAMS = {"mr": (0.3, 0.2), "yeoh": (0.5, 0.05, 0.01), "gent": (20.0,)}
+
+
+def law_name(law):
+    """A law is a name from ALL_LAWS or a pair (name, constants) for the invariant laws."""
+    return law[0] if isinstance(law, tuple) else law
+
+
+def _law(law, params):
+    if isinstance(law, tuple):
+        return law[0], tuple(law[1])
+    return law, (DEFAULT_PARAMS.get(law) if params is None else tuple(params))
 
 
 def det(F):
@@ -69,16 +82,15 @@ def _G1_G2(F):
 
 def energy(law, F, mu, lam, params=None):
     """Strain energy density W(F) per reference area (Appendix A)."""
+    law, prm = _law(law, params)
     if law in INVARIANT_LAWS:
-        prm = DEFAULT_PARAMS[law] if params is None else params
         J, I1, I2, bI1, bI2 = _invariants(F)
         vol = 0.5 * lam * np.log(J) ** 2
         A = bI1 - 3.0
         if law == "mr":                      # eq:mr-model
-            a = prm[0]
-            return a * mu * A + (0.5 - a) * mu * (bI2 - 3.0) + vol
+            return prm[0] * mu * A + prm[1] * mu * (bI2 - 3.0) + vol
         if law == "yeoh":                    # eq:yeoh-model
-            return 0.5 * mu * A + prm[0] * mu * A ** 2 + prm[1] * mu * A ** 3 + vol
+            return prm[0] * mu * A + prm[1] * mu * A ** 2 + prm[2] * mu * A ** 3 + vol
         Jm = prm[0]                          # eq:gent-model
         return -0.5 * mu * Jm * np.log(1.0 - A / Jm) + vol
     J = det(F)
@@ -99,18 +111,17 @@ def energy(law, F, mu, lam, params=None):
 
 def stress(law, F, mu, lam, params=None):
     """First Piola-Kirchhoff stress P(F) (Appendix A)."""
+    law, prm = _law(law, params)
     if law in INVARIANT_LAWS:
-        prm = DEFAULT_PARAMS[law] if params is None else params
         J, I1, I2, bI1, bI2 = _invariants(F)
         G1, G2 = _G1_G2(F)
         H = inv_transpose(F)
         vol = lam * np.log(J) * H
         A = bI1 - 3.0
         if law == "mr":                      # P = c10 G1 + c01 G2 + lam ln J H
-            a = prm[0]
-            return a * mu * G1 + (0.5 - a) * mu * G2 + vol
+            return prm[0] * mu * G1 + prm[1] * mu * G2 + vol
         if law == "yeoh":                    # P = (c1 + 2 c2 A + 3 c3 A^2) G1 + lam ln J H
-            return (0.5 * mu + 2.0 * prm[0] * mu * A + 3.0 * prm[1] * mu * A ** 2) * G1 + vol
+            return (prm[0] + 2.0 * prm[1] * A + 3.0 * prm[2] * A ** 2) * mu * G1 + vol
         Jm = prm[0]                          # P = mu / (2 (1 - A/J_m)) G1 + lam ln J H
         return mu / (2.0 * (1.0 - A / Jm)) * G1 + vol
     if law in ("lognh", "nh"):
@@ -131,6 +142,7 @@ def stress(law, F, mu, lam, params=None):
 
 def tangent(law, F, mu, lam, params=None):
     """C_iAkB = dP_iA / dF_kB, shape (2, 2, 2, 2, ...)."""
+    law, params = _law(law, params)
     if law in INVARIANT_LAWS:
         # complex-step differentiation of P: dP/dF_kB = Im P(F + i h e_kB) / h, exact to
         # rounding for real-analytic P (no subtraction of nearly equal numbers)
@@ -182,9 +194,9 @@ def tangent_parameter_partials(law, F, params=None):
     return tangent(law, F, 1.0, 0.0, params), tangent(law, F, 0.0, 1.0, params)
 
 
-def acoustic_tensor(law, F, mu, lam, n):
+def acoustic_tensor(law, F, mu, lam, n, params=None):
     """Q_ik(n; F) = n_A C_iAkB n_B (eq:acoustic-tensor-section2)."""
-    Cc = tangent(law, F, mu, lam)
+    Cc = tangent(law, F, mu, lam, params)
     n = np.asarray(n, dtype=np.float64)
     return np.einsum("A,iAkB...,B->ik...", n, Cc, n)
 
@@ -203,7 +215,7 @@ def max_tangent_speed(law, F, mu, lam, dtheta_deg=0.25):
     return np.sqrt(best)
 
 
-def cauchy(law, F, mu, lam):
+def cauchy(law, F, mu, lam, params=None):
     """sigma = J^{-1} P F^T (Sec. 3.5)."""
-    P = stress(law, F, mu, lam)
+    P = stress(law, F, mu, lam, params)
     return np.einsum("iA...,kA...->ik...", P, F) / det(F)

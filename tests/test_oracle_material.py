@@ -121,27 +121,27 @@ def test_isochoric_shear_path(law):
 @pytest.mark.parametrize("law", mat.INVARIANT_LAWS)
 def test_invariant_laws_on_isochoric_shear(law):
     """On F = [[1, 0], [g, 1]]: J = 1, barI1 - 3 = barI2 - 3 = g^2, so W reduces to a
-    polynomial (or log) in g and P21 = dW/dg in closed form: MR mu g, Yeoh
-    mu g + 4 c2 g^3 + 6 c3 g^5, Gent mu g / (1 - g^2 / J_m)."""
+    polynomial (or log) in g and P21 = dW/dg in closed form: MR 2 (c10 + c01) g, Yeoh
+    2 c1 g + 4 c2 g^3 + 6 c3 g^5, Gent mu g / (1 - g^2 / J_m)."""
     g = np.linspace(-0.6, 0.6, 13)
     F = np.zeros((2, 2, g.size))
     F[0, 0] = F[1, 1] = 1.0
     F[1, 0] = g
     mu = 1.7
-    prm = {"mr": (0.2,), "yeoh": (0.11, 0.03), "gent": (2.5,)}[law]
+    prm = {"mr": (0.2, 0.45), "yeoh": (0.5, 0.11, 0.03), "gent": (2.5,)}[law]
     P = mat.stress(law, F, mu, 9.0, prm)
     if law == "mr":
-        want = mu * g
+        want = 2 * (prm[0] + prm[1]) * mu * g
     elif law == "yeoh":
-        want = mu * g + 4 * prm[0] * mu * g ** 3 + 6 * prm[1] * mu * g ** 5
+        want = 2 * prm[0] * mu * g + 4 * prm[1] * mu * g ** 3 + 6 * prm[2] * mu * g ** 5
     else:
         want = mu * g / (1.0 - g * g / prm[0])
     assert np.allclose(P[1, 0], want, rtol=1e-13, atol=1e-15)
     W = mat.energy(law, F, mu, 9.0, prm)
     if law == "mr":
-        Wwant = mu / 2 * g ** 2
+        Wwant = (prm[0] + prm[1]) * mu * g ** 2
     elif law == "yeoh":
-        Wwant = mu / 2 * g ** 2 + prm[0] * mu * g ** 4 + prm[1] * mu * g ** 6
+        Wwant = prm[0] * mu * g ** 2 + prm[1] * mu * g ** 4 + prm[2] * mu * g ** 6
     else:
         Wwant = -mu * prm[0] / 2 * np.log(1 - g ** 2 / prm[0])
     assert np.allclose(W, Wwant, rtol=1e-13, atol=1e-15)
@@ -153,13 +153,13 @@ def test_invariant_law_special_cases_coincide():
     rng = np.random.default_rng(7)
     F = random_F(rng, 30)
     mu, lam = 0.9, 1.4
-    P_y = mat.stress("yeoh", F, mu, lam, (0.0, 0.0))
-    P_m = mat.stress("mr", F, mu, lam, (0.5,))
+    P_y = mat.stress("yeoh", F, mu, lam, (0.5, 0.0, 0.0))
+    P_m = mat.stress(("mr", (0.5, 0.0)), F, mu, lam)
     P_g = mat.stress("gent", F, mu, lam, (1e12,))
     assert np.allclose(P_y, P_m, rtol=1e-14, atol=1e-15)
     assert np.allclose(P_g, P_m, rtol=1e-10, atol=1e-12)
-    C_y = mat.tangent("yeoh", F, mu, lam, (0.0, 0.0))
-    C_m = mat.tangent("mr", F, mu, lam, (0.5,))
+    C_y = mat.tangent("yeoh", F, mu, lam, (0.5, 0.0, 0.0))
+    C_m = mat.tangent(("mr", (0.5, 0.0)), F, mu, lam)
     assert np.allclose(C_y, C_m, rtol=1e-13, atol=1e-14)
 
 
