@@ -58,8 +58,19 @@ enum { LBM_F32_SHIFTED = 0, LBM_F16_SHIFTED = 1, LBM_F64_PLAIN = 2 };
 
 /* Hyperelastic closures of Appendix A: logarithmic neo-Hookean (eq:lognh-model,
  * P = mu (F - F^-T) + lam ln J F^-T), compressible neo-Hookean (eq:nh-model,
- * P = mu (F - F^-T) + lam/2 (J^2 - 1) F^-T), St. Venant-Kirchhoff (eq:svk-model). */
-enum { LBM_LOGNH = 0, LBM_NH = 1, LBM_SVK = 2 };
+ * P = mu (F - F^-T) + lam/2 (J^2 - 1) F^-T), St. Venant-Kirchhoff (eq:svk-model), and the
+ * invariant-based Mooney-Rivlin (eq:mr-model), Yeoh (eq:yeoh-model) and Gent
+ * (eq:gent-model) laws in the plane-strain modified invariants of eq:modified-invariants,
+ * each with the bulk term lam/2 (ln J)^2.  The invariant laws take their constants from
+ * lbm_params.law_k as multiples of mu, so that P stays linear in (mu, lam) over a
+ * heterogeneous mu field:
+ *   LBM_MR:   law_k = (c10/mu, c01/mu, unused)   (Appendix A's default: c10 + c01 = mu/2)
+ *   LBM_YEOH: law_k = (c1/mu, c2/mu, c3/mu)      (Appendix A's default: c1 = mu/2)
+ *   LBM_GENT: law_k = (J_m, unused, unused); a state with barI1 - 3 >= J_m is
+ *             inadmissible and is reported like J <= 0.
+ * Their small-strain shear modulus is 2 (c10 + c01), 2 c1 and mu respectively, and their
+ * small-strain plane Lame constant is lam - 2/3 of that shear modulus. */
+enum { LBM_LOGNH = 0, LBM_NH = 1, LBM_SVK = 2, LBM_MR = 3, LBM_YEOH = 4, LBM_GENT = 5 };
 
 /* Edge kinds: periodic, velocity Dirichlet (eq:dirichlet-boundary-rule), nominal-traction
  * Neumann (eq:neumann-boundary-rule).  Periodic edges must pair: XMIN with XMAX, YMIN
@@ -69,7 +80,8 @@ enum { LBM_XMIN = 0, LBM_XMAX = 1, LBM_YMIN = 2, LBM_YMAX = 3 };
 
 /* Bits of the device fault word. */
 enum {
-    LBM_FAULT_J = 1,          /* det F <= 0 at some node (Sec. 2.2: admissible states have J > 0) */
+    LBM_FAULT_J = 1,          /* inadmissible state at some node: det F <= 0 (Sec. 2.2), or
+                                 barI1 - 3 >= J_m for the Gent law (Appendix A) */
     LBM_FAULT_NONFINITE = 2,  /* a recovered state value is not finite */
     LBM_FAULT_NEWTON = 4      /* a traction-boundary Newton solve failed (Sec. 3.6) */
 };
@@ -79,7 +91,7 @@ enum {
 
 typedef struct {
     int32_t nx, ny;            /* grid nodes, >= 4 along any axis with walls, >= 2 otherwise */
-    int32_t material;          /* LBM_LOGNH | LBM_NH | LBM_SVK */
+    int32_t material;          /* LBM_LOGNH | LBM_NH | LBM_SVK | LBM_MR | LBM_YEOH | LBM_GENT */
     int32_t storage;           /* LBM_F32_SHIFTED | LBM_F16_SHIFTED | LBM_F64_PLAIN */
     int32_t bc[4];             /* per edge LBM_XMIN..LBM_YMAX: LBM_PERIODIC | LBM_VELOCITY | LBM_TRACTION */
     int32_t newton_max_iter;   /* traction Newton updates per link; <= 0 selects 8 */
@@ -88,6 +100,9 @@ typedef struct {
     double c;                  /* lattice speed dx/dt (> 0) */
     double omega;              /* BGK rate, 0 < omega <= 2 (eq:collision; 2 is nondissipative) */
     double newton_tol;         /* relative Newton tolerance; <= 0 selects 1e-14 (F64) or 1e-6 (F32/F16) */
+    double law_k[3];           /* constants of the invariant-based laws (see LBM_MR); ignored
+                                  by the others.  MR: both >= 0 with a positive sum; Yeoh:
+                                  c1/mu > 0; Gent: J_m > 0 */
 } lbm_params;
 
 typedef struct {
@@ -148,9 +163,11 @@ size_t lbm_diag_scratch_bytes(const lbm_params *p);
 lbm_status lbm_check_params(const lbm_params *p);
 
 /* Lattice-speed audit (Sec. 4 audits c against the largest tangent wave speed, Table
- * tab:validation-setup): at F = I the fastest wave is the P wave, sqrt(lam + 2 mu); the
- * linearised D2Q4 x 6 step is stable for sqrt(lam + 2 mu) / c <= 1/2 at omega = 2.
- * Returns LBM_ERR_CFL above that ratio, LBM_OK otherwise. */
+ * tab:validation-setup): at F = I the fastest wave is the P wave, sqrt(lam + 2 mu) for the
+ * Lame-parametrised laws and sqrt(lam + 4/3 G) for the invariant laws with small-strain
+ * shear modulus G; the linearised D2Q4 x 6 step is stable for a P-wave speed of at most
+ * c/2 at omega = 2.  Returns LBM_ERR_CFL above that ratio, LBM_OK otherwise.  Finite
+ * strains can raise the tangent speeds (lbm_diagnostics out[9] audits the current state). */
 lbm_status lbm_check_cfl(const lbm_params *p, double mu_max, double lam_max);
 
 /* ------------------------------------------------------------------ forward */
@@ -161,11 +178,15 @@ lbm_status lbm_check_cfl(const lbm_params *p, double mu_max, double lam_max);
  * then the first collision (eq:collision at level 0) so that s->pop[s->cur] holds f*^0,
  * and u*^1 = u0 - (dt/2) v0 + dt v^0 (eq:trapezoid-u).
  *   v0: device, 2 double planes, initial velocity.
- *   u0: device, 2 double planes, initial displacement (F0 = I + grad u0), or NULL for 0.
+ *   u0: device, 2 double planes, initial displacement, or NULL for 0.
+ *   Fbar: host, 4 doubles (F11, F12, F21, F22) of a uniform predeformation, or NULL for I:
+ *     the initial deformation gradient is Fbar + grad u0 (Sec. 5.2 starts waves on a
+ *     homogeneous finite state).  The affine part (Fbar - I) X of the displacement is not
+ *     carried in u*: lbm_displacement returns the part that starts from u0.
  *   r0: factor applied to the body force at t = 0 (B^0 = r0 b).
  * Uses s->pop[1 - s->cur] as scratch.  Runs the CFL audit unless force_unstable. */
 lbm_status lbm_init(const lbm_params *p, lbm_state *s, const double *v0, const double *u0,
-                    double r0, void *stream);
+                    const double *Fbar, double r0, void *stream);
 
 /* One time step (Sec. 3.7), level n -> n+1, fused in one pass over the grid: pull
  * streaming (eq:streaming) from s->pop[s->cur], half-way reconstruction of every missing
@@ -238,11 +259,11 @@ lbm_status lbm_adjoint_step(const lbm_params *p, const lbm_state *fwd, lbm_adj_s
 
 /* Adjoint of lbm_init: from lambda^0 = dL/df(0) in a->adj[a->cur], writes dL/dv0 into
  * g_v0 (device, 2 double planes; includes the direct term of u*^0 = u0 - (dt/2) v0) and
- * adds the initialisation parts of dL/dmu, dL/dlam, dL/db.  v0, u0, r0 as given to
+ * adds the initialisation parts of dL/dmu, dL/dlam, dL/db.  v0, u0, Fbar, r0 as given to
  * lbm_init.  Uses a->adj[1 - a->cur] as scratch. */
 lbm_status lbm_adjoint_init(const lbm_params *p, const lbm_state *fwd, lbm_adj_state *a,
-                            const double *v0, const double *u0, double r0, double *g_v0,
-                            void *stream);
+                            const double *v0, const double *u0, const double *Fbar, double r0,
+                            double *g_v0, void *stream);
 
 /* Writes U^n of the current level in record format (6 tiled planes of the compute type). */
 lbm_status lbm_record_state(const lbm_params *p, const lbm_state *s, double r_n, void *record,

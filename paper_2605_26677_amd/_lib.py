@@ -13,14 +13,18 @@ LIB_PATH = os.environ.get("LBM_LIBRARY", os.path.join(_HERE, "liblbm.so"))
 # enums of lbm.h
 LBM_OK, LBM_ERR_ARG, LBM_ERR_UNSUPPORTED, LBM_ERR_CFL, LBM_ERR_LAUNCH = range(5)
 LBM_F32_SHIFTED, LBM_F16_SHIFTED, LBM_F64_PLAIN = range(3)
-LBM_LOGNH, LBM_NH, LBM_SVK = range(3)
+LBM_LOGNH, LBM_NH, LBM_SVK, LBM_MR, LBM_YEOH, LBM_GENT = range(6)
 LBM_PERIODIC, LBM_VELOCITY, LBM_TRACTION = range(3)
 LBM_XMIN, LBM_XMAX, LBM_YMIN, LBM_YMAX = range(4)
 LBM_FAULT_J, LBM_FAULT_NONFINITE, LBM_FAULT_NEWTON = 1, 2, 4
 LBM_DIAG_COUNT = 10
 
 STORAGE = {"f32": LBM_F32_SHIFTED, "f16": LBM_F16_SHIFTED, "f64": LBM_F64_PLAIN}
-MATERIAL = {"lognh": LBM_LOGNH, "nh": LBM_NH, "svk": LBM_SVK}
+MATERIAL = {"lognh": LBM_LOGNH, "nh": LBM_NH, "svk": LBM_SVK, "mr": LBM_MR, "yeoh": LBM_YEOH,
+            "gent": LBM_GENT}
+# law_k used when a caller gives none: Appendix A fixes c10 + c01 = mu/2 (Mooney-Rivlin) and
+# c1 = mu/2 (Yeoh); the split, c2, c3 and the Gent limit J_m are choices of this binding.
+LAW_K_DEFAULT = {"mr": (0.3, 0.2, 0.0), "yeoh": (0.5, 0.05, 0.01), "gent": (20.0, 0.0, 0.0)}
 BC = {"periodic": LBM_PERIODIC, "velocity": LBM_VELOCITY, "traction": LBM_TRACTION}
 
 c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -31,6 +35,7 @@ class lbm_params(ctypes.Structure):
         ("nx", c_i32), ("ny", c_i32), ("material", c_i32), ("storage", c_i32),
         ("bc", c_i32 * 4), ("newton_max_iter", c_i32), ("force_unstable", c_i32),
         ("dx", c_dbl), ("c", c_dbl), ("omega", c_dbl), ("newton_tol", c_dbl),
+        ("law_k", c_dbl * 3),
     ]
 
 
@@ -65,7 +70,7 @@ SIGNATURES = {
     "lbm_diag_scratch_bytes": (ctypes.c_size_t, [P(lbm_params)]),
     "lbm_check_params": (c_i32, [P(lbm_params)]),
     "lbm_check_cfl": (c_i32, [P(lbm_params), c_dbl, c_dbl]),
-    "lbm_init": (c_i32, [P(lbm_params), P(lbm_state), c_vp, c_vp, c_dbl, c_vp]),
+    "lbm_init": (c_i32, [P(lbm_params), P(lbm_state), c_vp, c_vp, c_vp, c_dbl, c_vp]),
     "lbm_step": (c_i32, [P(lbm_params), P(lbm_state), c_i64, c_dbl, c_dbl, P(lbm_edge_data), c_vp, c_vp]),
     "lbm_displacement": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp]),
     "lbm_moments": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp]),
@@ -73,8 +78,8 @@ SIGNATURES = {
     "lbm_diagnostics": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp, c_vp]),
     "lbm_adjoint_step": (c_i32, [P(lbm_params), P(lbm_state), P(lbm_adj_state), c_i64, c_dbl,
                                  P(lbm_edge_data), c_vp, c_vp]),
-    "lbm_adjoint_init": (c_i32, [P(lbm_params), P(lbm_state), P(lbm_adj_state), c_vp, c_vp, c_dbl,
-                                 c_vp, c_vp]),
+    "lbm_adjoint_init": (c_i32, [P(lbm_params), P(lbm_state), P(lbm_adj_state), c_vp, c_vp, c_vp,
+                                 c_dbl, c_vp, c_vp]),
     "lbm_record_state": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp]),
     "lbm_status_string": (ctypes.c_char_p, [c_i32]),
     "lbm_version": (ctypes.c_char_p, []),

@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
     R mu, lam;
     params_at<FIELDS, R>(cm, idx, mu, lam);
     R C[16];
-    tangent<R, LAW, true>(ft, mu, lam, C);
+    tangent<R, LAW, true>(ft, mu, lam, law_consts<R>(cm), C);
 
     R s6[6], dxl[6], dyl[6];
 #pragma unroll
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
     const R hc = R(0.5 / cm.c);
     if (a.g_mu || a.g_lam) {
         R Pm[4], Pl[4];
-        piola_partials<R, LAW, true>(ft, Pm, Pl);
+        piola_partials<R, LAW, true>(ft, law_consts<R>(cm), Pm, Pl);
         if (a.g_mu)
             a.g_mu[idx] += double(om * hc * -(dxl[0] * Pm[0] + dxl[1] * Pm[2] + dyl[0] * Pm[1] + dyl[1] * Pm[3]));
         if (a.g_lam)
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(kBlock) adj_traction_kernel(AdjArgs a) {
     const int id0 = n0.y * cm.nx + n0.x;
     R mu, lam;
     params_at<FIELDS, R>(cm, id0, mu, lam);
-    newton_column<R, LAW, true>(A, R(G.NA), tang, Tv, mu, lam, acol, cm.newton_max_iter, R(cm.newton_tol));
+    newton_column<R, LAW, true>(A, R(G.NA), tang, Tv, mu, lam, law_consts<R>(cm), acol, cm.newton_max_iter, R(cm.newton_tol));
     R f[4];
     f[A] = acol[0]; f[2 + A] = acol[1];
     f[Bx] = tang[0]; f[2 + Bx] = tang[1];
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(kBlock) adj_traction_kernel(AdjArgs a) {
     const int64_t wb = tile_base(cm.ntile, 24, n0.x, n0.y);
     for (int k = 0; k < 4; ++k) Fbar[k] = R(0.5) * src[wb + (6 * G.d + 2 + k) * kTile];
     R C[16];
-    tangent<R, LAW, true>(f, mu, lam, C);
+    tangent<R, LAW, true>(f, mu, lam, law_consts<R>(cm), C);
     const R NA = R(G.NA);
     const R j00 = NA * C[4 * A + A], j01 = NA * C[4 * A + 2 + A];
     const R j10 = NA * C[8 + 4 * A + A], j11 = NA * C[8 + 4 * A + 2 + A];
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) adj_traction_kernel(AdjArgs a) {
         tbar[jj] = Fbar[2 * jj + Bx] - NA * (y0 * C[4 * A + 2 * jj + Bx] + y1 * C[8 + 4 * A + 2 * jj + Bx]);
     if (a.g_mu || a.g_lam) {
         R Pm[4], Pl[4];
-        piola_partials<R, LAW, true>(f, Pm, Pl);
+        piola_partials<R, LAW, true>(f, law_consts<R>(cm), Pm, Pl);
         if (a.g_mu) a.g_mu[id0] += double(-NA * (y0 * Pm[A] + y1 * Pm[2 + A]));
         if (a.g_lam) a.g_lam[id0] += double(-NA * (y0 * Pl[A] + y1 * Pl[2 + A]));
     }
@@ -278,10 +278,10 @@ __global__ void __launch_bounds__(kBlock) adj_init_kernel(AdjInitArgs a) {
     double mu, lam;
     params_at<FIELDS, double>(cm, (int)idx, mu, lam);
     double C[16], Cm[16], Cl[16], Pm[4], Pl[4];
-    tangent<double, LAW, true>(&U0[2], mu, lam, C);
-    tangent<double, LAW, true>(&U0[2], 1.0, 0.0, Cm);
-    tangent<double, LAW, true>(&U0[2], 0.0, 1.0, Cl);
-    piola_partials<double, LAW, true>(&U0[2], Pm, Pl);
+    tangent<double, LAW, true>(&U0[2], mu, lam, law_consts<double>(cm), C);
+    tangent<double, LAW, true>(&U0[2], 1.0, 0.0, law_consts<double>(cm), Cm);
+    tangent<double, LAW, true>(&U0[2], 0.0, 1.0, law_consts<double>(cm), Cl);
+    piola_partials<double, LAW, true>(&U0[2], law_consts<double>(cm), Pm, Pl);
     const R* l0 = (const R*)a.lam0;
     double vb[2] = {0, 0}, vXb[2] = {0, 0}, vYb[2] = {0, 0}, Bb[2] = {0, 0};
     double dPXb[4] = {0, 0, 0, 0}, dPYb[4] = {0, 0, 0, 0};
@@ -432,6 +432,9 @@ static hipError_t adjoint_st(const AdjArgs& a, hipStream_t s) {
     switch (a.cm.material) {
         case LBM_LOGNH: return adjoint_st_law<ST, LBM_LOGNH>(a, s);
         case LBM_NH: return adjoint_st_law<ST, LBM_NH>(a, s);
+        case LBM_MR: return adjoint_st_law<ST, LBM_MR>(a, s);
+        case LBM_YEOH: return adjoint_st_law<ST, LBM_YEOH>(a, s);
+        case LBM_GENT: return adjoint_st_law<ST, LBM_GENT>(a, s);
         default: return adjoint_st_law<ST, LBM_SVK>(a, s);
     }
 }
@@ -456,6 +459,9 @@ static void adj_init_st(const AdjInitArgs& a, hipStream_t s, dim3 grid) {
     switch (a.cm.material) {
         case LBM_LOGNH: adj_init_st_law<ST, LBM_LOGNH>(a, s, grid); break;
         case LBM_NH: adj_init_st_law<ST, LBM_NH>(a, s, grid); break;
+        case LBM_MR: adj_init_st_law<ST, LBM_MR>(a, s, grid); break;
+        case LBM_YEOH: adj_init_st_law<ST, LBM_YEOH>(a, s, grid); break;
+        case LBM_GENT: adj_init_st_law<ST, LBM_GENT>(a, s, grid); break;
         default: adj_init_st_law<ST, LBM_SVK>(a, s, grid); break;
     }
 }
@@ -467,6 +473,7 @@ hipError_t launch_adjoint_init(const AdjInitArgs& a, hipStream_t s) {
     ia.cm = a.cm;
     ia.v0 = a.v0;
     ia.u0 = a.u0;
+    for (int k = 0; k < 4; ++k) ia.Fbar[k] = a.Fbar[k];
     ia.r0 = a.r0;
     ia.scratch = a.scratch;
     hipError_t err = launch_init_state(ia, s);

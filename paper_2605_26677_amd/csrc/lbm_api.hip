@@ -44,6 +44,7 @@ Common make_common(const lbm_params* p, const lbm_state* s) {
     cm.dt = p->dx / p->c;
     cm.newton_max_iter = p->newton_max_iter > 0 ? p->newton_max_iter : 8;
     cm.newton_tol = p->newton_tol > 0 ? p->newton_tol : (p->storage == LBM_F64_PLAIN ? 1e-14 : 1e-6);
+    for (int k = 0; k < 3; ++k) cm.law_k[k] = p->law_k[k];
     if (s) {
         cm.mu0 = s->mu0;
         cm.lam0 = s->lam0;
@@ -80,6 +81,17 @@ lbm_status check_state(const lbm_params* p, const lbm_state* s, bool need_ustar 
 
 lbm_status launched(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_ERR_LAUNCH; }
 
+// Uniform predeformation: I when none is given; rejected unless finite with det > 0.
+bool predeformation(const double* Fbar, double out[4]) {
+    const double I[4] = {1.0, 0.0, 0.0, 1.0};
+    const double* f = Fbar ? Fbar : I;
+    for (int k = 0; k < 4; ++k) {
+        if (!isfinite(f[k])) return false;
+        out[k] = f[k];
+    }
+    return out[0] * out[3] - out[1] * out[2] > 0.0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -112,7 +124,12 @@ lbm_status lbm_check_params(const lbm_params* p) {
     if (!p) return LBM_ERR_ARG;
     if (p->nx < 3 || p->ny < 3) return LBM_ERR_ARG;
     if ((int64_t)p->nx * (int64_t)p->ny >= ((int64_t)1 << 31)) return LBM_ERR_ARG;
-    if (p->material < LBM_LOGNH || p->material > LBM_SVK) return LBM_ERR_ARG;
+    if (p->material < LBM_LOGNH || p->material > LBM_GENT) return LBM_ERR_ARG;
+    if (p->material == LBM_MR &&
+        !(p->law_k[0] >= 0 && p->law_k[1] >= 0 && p->law_k[0] + p->law_k[1] > 0)) return LBM_ERR_ARG;
+    if (p->material == LBM_YEOH &&
+        !(p->law_k[0] > 0 && isfinite(p->law_k[1]) && isfinite(p->law_k[2]))) return LBM_ERR_ARG;
+    if (p->material == LBM_GENT && !(p->law_k[0] > 0 && isfinite(p->law_k[0]))) return LBM_ERR_ARG;
     if (p->storage < LBM_F32_SHIFTED || p->storage > LBM_F64_PLAIN) return LBM_ERR_ARG;
     for (int e = 0; e < 4; ++e)
         if (p->bc[e] < LBM_PERIODIC || p->bc[e] > LBM_TRACTION) return LBM_ERR_ARG;
@@ -125,16 +142,25 @@ lbm_status lbm_check_params(const lbm_params* p) {
 
 lbm_status lbm_check_cfl(const lbm_params* p, double mu_max, double lam_max) {
     if (!p || !(p->c > 0)) return LBM_ERR_ARG;
-    const double cp = sqrt(fmax(lam_max + 2.0 * mu_max, 0.0));
+    double cp2 = lam_max + 2.0 * mu_max;
+    if (p->material == LBM_MR || p->material == LBM_YEOH || p->material == LBM_GENT) {
+        // small-strain shear modulus of the invariant laws, and lam' + 2 G = lam + 4 G / 3
+        const double G = p->material == LBM_MR ? 2.0 * (p->law_k[0] + p->law_k[1]) * mu_max
+                       : p->material == LBM_YEOH ? 2.0 * p->law_k[0] * mu_max : mu_max;
+        cp2 = lam_max + 4.0 / 3.0 * G;
+    }
+    const double cp = sqrt(fmax(cp2, 0.0));
     return (cp / p->c > 0.5) ? LBM_ERR_CFL : LBM_OK;
 }
 
-lbm_status lbm_init(const lbm_params* p, lbm_state* s, const double* v0, const double* u0, double r0,
-                    void* stream) {
+lbm_status lbm_init(const lbm_params* p, lbm_state* s, const double* v0, const double* u0,
+                    const double* Fbar, double r0, void* stream) {
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
     if ((st = check_state(p, s)) != LBM_OK) return st;
     if (!v0) return LBM_ERR_ARG;
+    double F0[4];
+    if (!predeformation(Fbar, F0)) return LBM_ERR_ARG;
     if (!p->force_unstable) {
         const double mu = s->mu ? s->mu_max : s->mu0;
         const double lam = s->lam ? s->lam_max : s->lam0;
@@ -144,6 +170,7 @@ lbm_status lbm_init(const lbm_params* p, lbm_state* s, const double* v0, const d
     a.cm = make_common(p, s);
     a.v0 = v0;
     a.u0 = u0;
+    for (int k = 0; k < 4; ++k) a.Fbar[k] = F0[k];
     a.r0 = r0;
     a.scratch = s->pop[1 - s->cur];
     a.dst = s->pop[s->cur];
@@ -271,10 +298,12 @@ lbm_status lbm_adjoint_step(const lbm_params* p, const lbm_state* fwd, lbm_adj_s
 }
 
 lbm_status lbm_adjoint_init(const lbm_params* p, const lbm_state* fwd, lbm_adj_state* adj, const double* v0,
-                            const double* u0, double r0, double* g_v0, void* stream) {
+                            const double* u0, const double* Fbar, double r0, double* g_v0, void* stream) {
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
     if (!fwd || !adj || !adj->adj[0] || !adj->adj[1] || !v0 || !g_v0) return LBM_ERR_ARG;
+    double F0[4];
+    if (!predeformation(Fbar, F0)) return LBM_ERR_ARG;
     if (adj->cur != 0 && adj->cur != 1) return LBM_ERR_ARG;
     if (adj->nprobe < 0 || (adj->nprobe > 0 && (!adj->probe || !adj->ubar))) return LBM_ERR_ARG;
     AdjInitArgs a{};
@@ -283,6 +312,7 @@ lbm_status lbm_adjoint_init(const lbm_params* p, const lbm_state* fwd, lbm_adj_s
     a.scratch = adj->adj[1 - adj->cur];
     a.v0 = v0;
     a.u0 = u0;
+    for (int k = 0; k < 4; ++k) a.Fbar[k] = F0[k];
     a.r0 = r0;
     a.g_mu = adj->g_mu;
     a.g_lam = adj->g_lam;

@@ -39,6 +39,8 @@ template <typename T, typename R> __device__ __forceinline__ void store_as(T* p,
 
 __device__ __forceinline__ float log1p_r(float x) { return log1pf(x); }
 __device__ __forceinline__ double log1p_r(double x) { return log1p(x); }
+__device__ __forceinline__ float expm1_r(float x) { return expm1f(x); }
+__device__ __forceinline__ double expm1_r(double x) { return expm1(x); }
 __device__ __forceinline__ float log_r(float x) { return logf(x); }
 __device__ __forceinline__ double log_r(double x) { return log(x); }
 __device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
@@ -121,12 +123,177 @@ __device__ __forceinline__ void green_lagrange(const R f[4], R& E11, R& E12, R& 
     }
 }
 
+// ---------------------------------------------------------------- law constants
+// Constants of the invariant-based closures as multiples of mu (P stays linear in mu and
+// lam): Mooney-Rivlin (k0, k1) = (c10, c01)/mu; Yeoh (k0, k1, k2) = (c1, c2, c3)/mu;
+// Gent k0 = J_m.  Unused by the Lame-parametrised laws.
+template <typename R> struct LawK {
+    R k0, k1, k2;
+};
+
+// ---------------------------------------------------------------- forward-mode duals
+// A value with its derivatives along four seed directions; used to differentiate the
+// invariant-based stresses (one pass gives all 16 tangent entries).
+template <typename R> struct Dual4 {
+    R v;
+    R d[4];
+};
+template <typename R> __device__ __forceinline__ Dual4<R> operator+(const Dual4<R>& a, const Dual4<R>& b) {
+    Dual4<R> r;
+    r.v = a.v + b.v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.d[i] = a.d[i] + b.d[i];
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> operator+(const Dual4<R>& a, R b) {
+    Dual4<R> r = a;
+    r.v = a.v + b;
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> operator+(R a, const Dual4<R>& b) { return b + a; }
+template <typename R> __device__ __forceinline__ Dual4<R> operator-(const Dual4<R>& a) {
+    Dual4<R> r;
+    r.v = -a.v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.d[i] = -a.d[i];
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> operator-(const Dual4<R>& a, const Dual4<R>& b) {
+    Dual4<R> r;
+    r.v = a.v - b.v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.d[i] = a.d[i] - b.d[i];
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> operator-(const Dual4<R>& a, R b) {
+    Dual4<R> r = a;
+    r.v = a.v - b;
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> operator-(R a, const Dual4<R>& b) {
+    Dual4<R> r = -b;
+    r.v = a - b.v;
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> operator*(const Dual4<R>& a, const Dual4<R>& b) {
+    Dual4<R> r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> operator*(const Dual4<R>& a, R b) {
+    Dual4<R> r;
+    r.v = a.v * b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.d[i] = a.d[i] * b;
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> operator*(R a, const Dual4<R>& b) { return b * a; }
+template <typename R> __device__ __forceinline__ Dual4<R> operator/(const Dual4<R>& a, const Dual4<R>& b) {
+    const R inv = R(1) / b.v;
+    Dual4<R> r;
+    r.v = a.v * inv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) * inv;
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> operator/(R a, const Dual4<R>& b) {
+    const R inv = R(1) / b.v;
+    Dual4<R> r;
+    r.v = a * inv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.d[i] = -r.v * b.d[i] * inv;
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> log1p_r(const Dual4<R>& a) {
+    const R s = R(1) / (R(1) + a.v);
+    Dual4<R> r;
+    r.v = log1p_r(a.v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.d[i] = a.d[i] * s;
+    return r;
+}
+template <typename R> __device__ __forceinline__ Dual4<R> expm1_r(const Dual4<R>& a) {
+    Dual4<R> r;
+    r.v = expm1_r(a.v);
+    const R s = r.v + R(1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.d[i] = a.d[i] * s;
+    return r;
+}
+
+// ---------------------------------------------------------------- invariant-based closures
+// Mooney-Rivlin, Yeoh and Gent (eq:mr-model, eq:yeoh-model, eq:gent-model) on the shift
+// f = F - I, for a scalar S that is R or Dual4<R>.  With t = tr C - 2 = I1 - 3,
+// s = J^2 - 1 = delta (2 + delta), L = ln J = log1p(delta) and j = J^{-2/3} = 1 + expm1(-2L/3),
+// the invariant gradients of eq:modified-invariant-gradients become
+//   G1 = j [2 (F - H) - (2/3) t H],
+//   G2 = j^2 [2 (F - H) + ((2/3) s - (4/3) t) H],
+// and A = barI1 - 3 = j t + 3 expm1(-2L/3): every term vanishes at F = I on its own, so
+// small strains do not cancel against O(1) quantities.  Outputs P and (J, A) for the
+// admissibility checks (J > 0; Gent also A < J_m).
+template <typename S, typename R, int LAW>
+__device__ __forceinline__ void piola_invariant(const S f[4], R mu, R lam, const LawK<R>& lk, S P[4],
+                                                S& J, S& A) {
+    const S d = f[0] + f[3] + (f[0] * f[3] - f[1] * f[2]);
+    J = R(1) + d;
+    const S invJ = R(1) / J;
+    const S L = log1p_r(d);
+    const S H[4] = {(R(1) + f[3]) * invJ, -(f[2] * invJ), -(f[1] * invJ), (R(1) + f[0]) * invJ};
+    const S FmH[4] = {(f[0] - f[3] + d * (R(1) + f[0])) * invJ, (J * f[1] + f[2]) * invJ,
+                      (J * f[2] + f[1]) * invJ, (f[3] - f[0] + d * (R(1) + f[3])) * invJ};
+    const S t = R(2) * (f[0] + f[3]) + (f[0] * f[0] + f[1] * f[1] + f[2] * f[2] + f[3] * f[3]);
+    const S em = expm1_r(R(-2.0 / 3.0) * L);
+    const S j = R(1) + em;
+    A = j * t + R(3) * em;
+    const S volL = lam * L;
+    if constexpr (LAW == LBM_MR) {
+        const S sJ = d * (R(2) + d);
+        const S a1 = (mu * lk.k0) * j;
+        const S a2 = (mu * lk.k1) * (j * j);
+        const S h1 = R(-2.0 / 3.0) * t;
+        const S h2 = R(2.0 / 3.0) * sJ + R(-4.0 / 3.0) * t;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            P[a] = a1 * (R(2) * FmH[a] + h1 * H[a]) + a2 * (R(2) * FmH[a] + h2 * H[a]) + volL * H[a];
+    } else {
+        S alpha;
+        if constexpr (LAW == LBM_YEOH) alpha = mu * (lk.k0 + A * (R(2) * lk.k1 + R(3) * lk.k2 * A));
+        else alpha = (R(0.5) * mu) / (R(1) - A * (R(1) / lk.k0));
+        const S aj = alpha * j;
+        const S h1 = R(-2.0 / 3.0) * t;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) P[a] = aj * (R(2) * FmH[a] + h1 * H[a]) + volL * H[a];
+    }
+}
+
+template <int LAW> constexpr bool invariant_law() {
+    return LAW == LBM_MR || LAW == LBM_YEOH || LAW == LBM_GENT;
+}
+
+// Shifted copy of a plain or shifted deformation state.
+template <typename R, bool SHIFTED>
+__device__ __forceinline__ void to_shift(const R f[4], R fs[4]) {
+    fs[0] = SHIFTED ? f[0] : f[0] - R(1);
+    fs[1] = f[1];
+    fs[2] = f[2];
+    fs[3] = SHIFTED ? f[3] : f[3] - R(1);
+}
+
 // ---------------------------------------------------------------- first Piola stress
-// P(F) of Appendix A in registers; also returns J for the admissibility check.
+// P(F) of Appendix A in registers; also returns J for the admissibility check (J is
+// reported as 0 for a Gent state beyond the limit A < J_m, so that every caller's J > 0
+// test also rejects it).
 
 template <typename R, int LAW, bool SHIFTED>
-__device__ __forceinline__ void piola(const R f[4], R mu, R lam, R P[4], R& J) {
-    if constexpr (LAW == LBM_SVK) {
+__device__ __forceinline__ void piola(const R f[4], R mu, R lam, const LawK<R>& lk, R P[4], R& J) {
+    if constexpr (invariant_law<LAW>()) {
+        R fs[4], A;
+        to_shift<R, SHIFTED>(f, fs);
+        piola_invariant<R, R, LAW>(fs, mu, lam, lk, P, J, A);
+        if (LAW == LBM_GENT && !(A < lk.k0)) J = R(0);
+    } else if constexpr (LAW == LBM_SVK) {
         R E11, E12, E22;
         green_lagrange<R, SHIFTED>(f, E11, E12, E22);
         const R tr = E11 + E22;
@@ -150,10 +317,10 @@ __device__ __forceinline__ void piola(const R f[4], R mu, R lam, R P[4], R& J) {
 
 // dP/dmu and dP/dlam (every law here is linear in the two parameters).
 template <typename R, int LAW, bool SHIFTED>
-__device__ __forceinline__ void piola_partials(const R f[4], R Pm[4], R Pl[4]) {
+__device__ __forceinline__ void piola_partials(const R f[4], const LawK<R>& lk, R Pm[4], R Pl[4]) {
     R J;
-    piola<R, LAW, SHIFTED>(f, R(1), R(0), Pm, J);
-    piola<R, LAW, SHIFTED>(f, R(0), R(1), Pl, J);
+    piola<R, LAW, SHIFTED>(f, R(1), R(0), lk, Pm, J);
+    piola<R, LAW, SHIFTED>(f, R(0), R(1), lk, Pl, J);
 }
 
 // ---------------------------------------------------------------- tangent
@@ -162,10 +329,27 @@ __device__ __forceinline__ void piola_partials(const R f[4], R Pm[4], R Pl[4]) {
 //   log-NH: mu d_ik d_AB + (mu - lam L) H_iB H_kA + lam H_iA H_kB
 //   NH:     mu d_ik d_AB + (mu - lam (J^2 - 1)/2) H_iB H_kA + lam J^2 H_iA H_kB
 //   SVK:    d_ik S_AB + lam F_iA F_kB + mu (F_iB F_kA + (F F^T)_ik d_AB)
+// The invariant-based laws are differentiated in forward mode (Dual4 seeded with the four
+// entries of F), which is exact up to rounding like the closed forms.
 
 template <typename R, int LAW, bool SHIFTED>
-__device__ __forceinline__ void tangent(const R f[4], R mu, R lam, R C[16]) {
-    if constexpr (LAW == LBM_SVK) {
+__device__ __forceinline__ void tangent(const R f[4], R mu, R lam, const LawK<R>& lk, R C[16]) {
+    if constexpr (invariant_law<LAW>()) {
+        R fs[4];
+        to_shift<R, SHIFTED>(f, fs);
+        Dual4<R> fd[4], P[4], J, A;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            fd[a].v = fs[a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) fd[a].d[b] = (a == b) ? R(1) : R(0);
+        }
+        piola_invariant<Dual4<R>, R, LAW>(fd, mu, lam, lk, P, J, A);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) C[4 * a + b] = P[a].d[b];
+    } else if constexpr (LAW == LBM_SVK) {
         R E11, E12, E22;
         green_lagrange<R, SHIFTED>(f, E11, E12, E22);
         const R tr = E11 + E22;
@@ -219,8 +403,27 @@ __device__ __forceinline__ void tangent(const R f[4], R mu, R lam, R C[16]) {
 
 // Strain energy W(F) (Appendix A), used by the diagnostics.
 template <typename R, int LAW, bool SHIFTED>
-__device__ __forceinline__ R energy(const R f[4], R mu, R lam) {
-    if constexpr (LAW == LBM_SVK) {
+__device__ __forceinline__ R energy(const R f[4], R mu, R lam, const LawK<R>& lk) {
+    if constexpr (invariant_law<LAW>()) {
+        R fs[4];
+        to_shift<R, SHIFTED>(f, fs);
+        const R d = fs[0] + fs[3] + (fs[0] * fs[3] - fs[1] * fs[2]);
+        const R L = log1p_r(d);
+        const R t = R(2) * (fs[0] + fs[3]) + (fs[0] * fs[0] + fs[1] * fs[1] + fs[2] * fs[2] + fs[3] * fs[3]);
+        const R em = expm1_r(R(-2.0 / 3.0) * L);
+        const R A = (R(1) + em) * t + R(3) * em;
+        const R vol = R(0.5) * lam * L * L;
+        if constexpr (LAW == LBM_MR) {
+            // barI2 - 3 = J^{-4/3} (s + t) + 3 expm1(-4L/3), s = J^2 - 1
+            const R em4 = expm1_r(R(-4.0 / 3.0) * L);
+            const R A2 = (R(1) + em4) * (d * (R(2) + d) + t) + R(3) * em4;
+            return mu * (lk.k0 * A + lk.k1 * A2) + vol;
+        } else if constexpr (LAW == LBM_YEOH) {
+            return mu * A * (lk.k0 + A * (lk.k1 + A * lk.k2)) + vol;
+        } else {
+            return R(-0.5) * mu * lk.k0 * log1p_r(-A / lk.k0) + vol;
+        }
+    } else if constexpr (LAW == LBM_SVK) {
         R E11, E12, E22;
         green_lagrange<R, SHIFTED>(f, E11, E12, E22);
         const R tr = E11 + E22;

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(kBlock) traction_kernel(TractionArgs a) {
     const XY n0 = edge_node(G, cm.nx, cm.ny, 0, s);
     R mu, lam;
     params_at<FIELDS, R>(cm, n0.y * cm.nx + n0.x, mu, lam);
-    const bool ok = newton_column<R, LAW, SH>(G.A, R(G.NA), tang, Tv, mu, lam, acol,
+    const bool ok = newton_column<R, LAW, SH>(G.A, R(G.NA), tang, Tv, mu, lam, law_consts<R>(cm), acol,
                                              cm.newton_max_iter, R(cm.newton_tol));
     if (!ok) atomicOr(cm.fault, (uint32_t)LBM_FAULT_NEWTON);
     int off[4], len[4];
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     R mu, lam;
     params_at<FIELDS, R>(cm, idx, mu, lam);
     R P[4], J;
-    piola<R, LAW, SH>(&U[2], mu, lam, P, J);
+    piola<R, LAW, SH>(&U[2], mu, lam, law_consts<R>(cm), P, J);
     const R PhiX[6] = {-P[0], -P[2], -U[0], R(0), -U[1], R(0)};
     const R PhiY[6] = {-P[1], -P[3], R(0), -U[0], R(0), -U[1]};
     const R c2 = R(2.0 / cm.c);
@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(kBlock) stress_kernel(RecoverArgs a) {
     double mu, lam;
     params_at<FIELDS, double>(cm, (int)idx, mu, lam);
     double P[4], J;
-    piola<double, LAW, true>(ft, mu, lam, P, J);
+    piola<double, LAW, true>(ft, mu, lam, law_consts<double>(cm), P, J);
     double* Po = (double*)a.out;
     for (int k = 0; k < 4; ++k) Po[k * n + idx] = P[k];
     if (a.out2) {
@@ -356,13 +356,13 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(RecoverArgs a) {
         acc[0] += double(U[0]);
         acc[1] += double(U[1]);
         for (int k = 0; k < 4; ++k) acc[2 + k] += double(ft[k]);
-        const R W = energy<R, LAW, true>(ft, mu, lam);
+        const R W = energy<R, LAW, true>(ft, mu, lam, law_consts<R>(cm));
         acc[6] += double(R(0.5) * (U[0] * U[0] + U[1] * U[1]) + W);
         const R J = R(1) + ft[0] + ft[3] + (ft[0] * ft[3] - ft[1] * ft[2]);
         acc[7] = fmin(acc[7], double(J));
         acc[8] = fmax(acc[8], double(sqrt_r(ft[0] * ft[0] + ft[1] * ft[1] + ft[2] * ft[2] + ft[3] * ft[3])));
         R C[16];
-        tangent<R, LAW, true>(ft, mu, lam, C);
+        tangent<R, LAW, true>(ft, mu, lam, law_consts<R>(cm), C);
         R cs = R(1), sn = R(0), best = R(0);
         for (int t = 0; t < 180; ++t) {
             const R nn[2] = {cs, sn};
@@ -430,7 +430,8 @@ __global__ void __launch_bounds__(kBlock) diag_final_kernel(const double* part, 
 
 // ---------------------------------------------------------------- initialisation
 
-// U0 = (v0, grad u0) as 6 double planes (F - I = grad u0 by second-order differences).
+// U0 = (v0, F - I) as 6 double planes, F - I = (Fbar - I) + grad u0 by second-order
+// differences.
 __global__ void __launch_bounds__(kBlock) init_state_kernel(InitArgs a) {
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny;
@@ -449,8 +450,8 @@ __global__ void __launch_bounds__(kBlock) init_state_kernel(InitArgs a) {
             gx = fd_along<double>([&](int s) { return u[int64_t(y) * nx + s]; }, x, nx, cm.periodic_x, inv2h);
             gy = fd_along<double>([&](int s) { return u[int64_t(s) * nx + x]; }, y, ny, cm.periodic_y, inv2h);
         }
-        U0[(2 + 2 * cpt) * n + idx] = gx;
-        U0[(3 + 2 * cpt) * n + idx] = gy;
+        U0[(2 + 2 * cpt) * n + idx] = (a.Fbar[2 * cpt] - (cpt == 0 ? 1.0 : 0.0)) + gx;
+        U0[(3 + 2 * cpt) * n + idx] = (a.Fbar[2 * cpt + 1] - (cpt == 1 ? 1.0 : 0.0)) + gy;
     }
 }
 
@@ -481,8 +482,8 @@ __global__ void __launch_bounds__(kBlock) init_pop_kernel(InitArgs a) {
     params_at<FIELDS, double>(cm, (int)idx, mu, lam);
     body_at<FIELDS>(cm, (int)idx, n, a.r0, b0, b1);
     double C[16], P0[4], J;
-    tangent<double, LAW, true>(&U0[2], mu, lam, C);
-    piola<double, LAW, true>(&U0[2], mu, lam, P0, J);
+    tangent<double, LAW, true>(&U0[2], mu, lam, law_consts<double>(cm), C);
+    piola<double, LAW, true>(&U0[2], mu, lam, law_consts<double>(cm), P0, J);
     // d_alpha P = C : d_alpha F
     double dPX[4], dPY[4];
     for (int iA = 0; iA < 4; ++iA) {
@@ -531,7 +532,7 @@ __global__ void __launch_bounds__(kBlock) init_pop_kernel(InitArgs a) {
     U[0] += hdt * b0;
     U[1] += hdt * b1;
     double P[4];
-    piola<double, LAW, true>(&U[2], mu, lam, P, J);
+    piola<double, LAW, true>(&U[2], mu, lam, law_consts<double>(cm), P, J);
     const double QX[6] = {-P[0], -P[2], -U[0], 0.0, -U[1], 0.0};
     const double QY[6] = {-P[1], -P[3], 0.0, -U[0], 0.0, -U[1]};
     const double srcw = dt * (2.0 - cm.omega) * 0.125;
@@ -589,6 +590,9 @@ static hipError_t step_st(const StepArgs& a, hipStream_t s) {
     switch (a.cm.material) {
         case LBM_LOGNH: return step_st_law<ST, LBM_LOGNH>(a, s);
         case LBM_NH: return step_st_law<ST, LBM_NH>(a, s);
+        case LBM_MR: return step_st_law<ST, LBM_MR>(a, s);
+        case LBM_YEOH: return step_st_law<ST, LBM_YEOH>(a, s);
+        case LBM_GENT: return step_st_law<ST, LBM_GENT>(a, s);
         default: return step_st_law<ST, LBM_SVK>(a, s);
     }
 }
@@ -615,6 +619,9 @@ static hipError_t traction_st(const TractionArgs& a, hipStream_t s) {
     switch (a.cm.material) {
         case LBM_LOGNH: return traction_st_law<ST, LBM_LOGNH>(a, s);
         case LBM_NH: return traction_st_law<ST, LBM_NH>(a, s);
+        case LBM_MR: return traction_st_law<ST, LBM_MR>(a, s);
+        case LBM_YEOH: return traction_st_law<ST, LBM_YEOH>(a, s);
+        case LBM_GENT: return traction_st_law<ST, LBM_GENT>(a, s);
         default: return traction_st_law<ST, LBM_SVK>(a, s);
     }
 }
@@ -660,6 +667,9 @@ static void stress_st(const RecoverArgs& a, hipStream_t s) {
     switch (a.cm.material) {
         case LBM_LOGNH: stress_st_law<ST, LBM_LOGNH>(a, s); break;
         case LBM_NH: stress_st_law<ST, LBM_NH>(a, s); break;
+        case LBM_MR: stress_st_law<ST, LBM_MR>(a, s); break;
+        case LBM_YEOH: stress_st_law<ST, LBM_YEOH>(a, s); break;
+        case LBM_GENT: stress_st_law<ST, LBM_GENT>(a, s); break;
         default: stress_st_law<ST, LBM_SVK>(a, s); break;
     }
 }
@@ -689,6 +699,9 @@ static void diag_st(const RecoverArgs& a, hipStream_t s) {
     switch (a.cm.material) {
         case LBM_LOGNH: diag_st_law<ST, LBM_LOGNH>(a, s); break;
         case LBM_NH: diag_st_law<ST, LBM_NH>(a, s); break;
+        case LBM_MR: diag_st_law<ST, LBM_MR>(a, s); break;
+        case LBM_YEOH: diag_st_law<ST, LBM_YEOH>(a, s); break;
+        case LBM_GENT: diag_st_law<ST, LBM_GENT>(a, s); break;
         default: diag_st_law<ST, LBM_SVK>(a, s); break;
     }
 }
@@ -714,6 +727,9 @@ static void init_st(const InitArgs& a, hipStream_t s, dim3 grid) {
     switch (a.cm.material) {
         case LBM_LOGNH: init_st_law<ST, LBM_LOGNH>(a, s, grid); break;
         case LBM_NH: init_st_law<ST, LBM_NH>(a, s, grid); break;
+        case LBM_MR: init_st_law<ST, LBM_MR>(a, s, grid); break;
+        case LBM_YEOH: init_st_law<ST, LBM_YEOH>(a, s, grid); break;
+        case LBM_GENT: init_st_law<ST, LBM_GENT>(a, s, grid); break;
         default: init_st_law<ST, LBM_SVK>(a, s, grid); break;
     }
 }

@@ -39,6 +39,7 @@ struct Common {
     uint32_t* fault;
     int newton_max_iter;
     double newton_tol;
+    double law_k[3];                 // invariant-law constants (lbm_params.law_k)
 };
 
 struct StepArgs {
@@ -75,6 +76,7 @@ struct InitArgs {
     Common cm;
     const double* v0;
     const double* u0;
+    double Fbar[4];                  // uniform predeformation (I when none is given)
     double r0;
     void* scratch;                   // U0 as 6 double planes (stride n)
     void* dst;                       // f*^0
@@ -105,6 +107,7 @@ struct AdjInitArgs {
     void* scratch;                   // 12 double planes: U0 (6) and the v0 seeds (6)
     const double* v0;
     const double* u0;
+    double Fbar[4];
     double r0;
     double* g_mu;
     double* g_lam;

@@ -39,6 +39,11 @@ __device__ __forceinline__ void params_at(const Common& cm, int idx, R& mu, R& l
     if (FIELDS && cm.lam) lam = R(cm.lam[idx]); else lam = R(cm.lam0);
 }
 
+template <typename R>
+__device__ __forceinline__ LawK<R> law_consts(const Common& cm) {
+    return LawK<R>{R(cm.law_k[0]), R(cm.law_k[1]), R(cm.law_k[2])};
+}
+
 // Sum of the four stored post-collision populations of one node minus (dt/2) B: the
 // state of that level (sum_q f* = U + (dt/2) B, from eq:collision with sum_q w = 1/2).
 template <typename T, typename R>
@@ -62,8 +67,8 @@ __device__ __forceinline__ void recover_node(const T* pop, int ntile, int x, int
 // det F^b > 0 and a smaller |r| is taken; stop at |r| <= tol (|T| + mu |F^b - I|), when no
 // step length is accepted, or after max_iter updates.  Returns false on failure.
 template <typename R, int LAW, bool SH>
-__device__ bool newton_column(int A, R NA, const R tang[2], const R T[2], R mu, R lam, R a[2],
-                              int max_iter, R tol) {
+__device__ bool newton_column(int A, R NA, const R tang[2], const R T[2], R mu, R lam,
+                              const LawK<R>& lk, R a[2], int max_iter, R tol) {
     const int B = 1 - A;
     auto assemble = [&](const R ac[2], R f[4]) {
         f[A] = ac[0]; f[2 + A] = ac[1];
@@ -72,7 +77,7 @@ __device__ bool newton_column(int A, R NA, const R tang[2], const R T[2], R mu, 
     auto resid = [&](const R ac[2], R r[2], R& J) {
         R f[4], P[4];
         assemble(ac, f);
-        piola<R, LAW, SH>(f, mu, lam, P, J);
+        piola<R, LAW, SH>(f, mu, lam, lk, P, J);
         r[0] = NA * P[A] - T[0];
         r[1] = NA * P[2 + A] - T[1];
     };
@@ -91,7 +96,7 @@ __device__ bool newton_column(int A, R NA, const R tang[2], const R T[2], R mu, 
         if (rn <= tol * scale(a)) break;
         R f[4], C[16];
         assemble(a, f);
-        tangent<R, LAW, SH>(f, mu, lam, C);
+        tangent<R, LAW, SH>(f, mu, lam, lk, C);
         const R j00 = NA * C[4 * A + A], j01 = NA * C[4 * A + 2 + A];
         const R j10 = NA * C[8 + 4 * A + A], j11 = NA * C[8 + 4 * A + 2 + A];
         const R det = j00 * j11 - j01 * j10;

@@ -21,7 +21,7 @@ from typing import Callable, Optional, Sequence
 import torch
 
 from . import _lib as L
-from .solver import EdgeData, Solver, _ptr, _stream
+from .solver import EdgeData, Solver, _ptr, _stream, host_matrix
 
 
 @dataclass
@@ -42,6 +42,8 @@ class RolloutConfig:
     checkpoint_every: int = 100
     levels: Sequence[int] = field(default_factory=list)   # nested segment lengths, outermost first
     newton_max_iter: int = 0
+    law_k: Optional[Sequence[float]] = None            # invariant-law constants (lbm.h law_k)
+    Fbar: Optional[Sequence[Sequence[float]]] = None   # uniform predeformation at t = 0
 
 
 def _edges(cfg, n):
@@ -80,7 +82,8 @@ class _Adjoint:
 
     def init(self, sv, cfg, v0, u0):
         L.check(sv.lib.lbm_adjoint_init(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), _ptr(v0),
-                                        _ptr(u0), float(cfg.ramp(0)), _ptr(self.g_v0), _stream()),
+                                        _ptr(u0), host_matrix(cfg.Fbar), float(cfg.ramp(0)), _ptr(self.g_v0),
+                                        _stream()),
                 "lbm_adjoint_init")
 
 
@@ -138,10 +141,11 @@ class LBMRollout(torch.autograd.Function):
     def forward(ctx, mu, lam, body, v0, cfg: RolloutConfig):
         sv = Solver(cfg.nx, cfg.ny, c=cfg.c, omega=cfg.omega, dx=cfg.dx, material=cfg.material,
                     storage=cfg.storage, bc=tuple(cfg.bc), mu=mu.detach(), lam=lam.detach(),
-                    body=body.detach(), newton_max_iter=cfg.newton_max_iter, device=mu.device)
+                    body=body.detach(), newton_max_iter=cfg.newton_max_iter, law_k=cfg.law_k,
+                    device=mu.device)
         v0d = v0.detach().to(torch.float64).contiguous()
         u0 = None if cfg.u0 is None else cfg.u0.to(device=mu.device, dtype=torch.float64).contiguous()
-        sv.init(v0d, u0, r0=cfg.ramp(0))
+        sv.init(v0d, u0, r0=cfg.ramp(0), Fbar=cfg.Fbar)
         N = cfg.nsteps
         K = cfg.levels[0] if cfg.levels else cfg.checkpoint_every
         snaps = {0: (sv.pop[sv.s.cur].clone(), sv.record_state(cfg.ramp(0), sv.new_record()))}

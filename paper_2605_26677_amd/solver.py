@@ -40,10 +40,20 @@ class EdgeData:
                 self.c.value[e][1] = float(v[1])
 
 
+def host_matrix(F):
+    """A (2, 2) matrix as a host array of 4 doubles (row-major), or None."""
+    if F is None:
+        return None
+    vals = [float(v) for v in torch.as_tensor(F, dtype=torch.float64).reshape(-1).tolist()]
+    if len(vals) != 4:
+        raise ValueError("a 2 x 2 matrix is expected")
+    return (ctypes.c_double * 4)(*vals)
+
+
 class Solver:
     def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
                  bc=("periodic",) * 4, mu=0.1, lam=0.2, body=None, newton_max_iter=0,
-                 newton_tol=0.0, force_unstable=False, device="cuda"):
+                 newton_tol=0.0, force_unstable=False, law_k=None, device="cuda"):
         self.device = torch.device(device)
         p = L.lbm_params()
         p.nx, p.ny = int(nx), int(ny)
@@ -54,6 +64,11 @@ class Solver:
         p.newton_max_iter = int(newton_max_iter)
         p.force_unstable = int(bool(force_unstable))
         p.dx, p.c, p.omega, p.newton_tol = float(dx), float(c), float(omega), float(newton_tol)
+        k = law_k if law_k is not None else L.LAW_K_DEFAULT.get(material, (0.0, 0.0, 0.0))
+        k = tuple(float(v) for v in k) + (0.0,) * (3 - len(k))
+        for i in range(3):
+            p.law_k[i] = k[i]
+        self.law_k = k
         self.p = p
         self.lib = L.lib()
         L.check(self.lib.lbm_check_params(ctypes.byref(p)), "lbm_check_params")
@@ -123,14 +138,15 @@ class Solver:
         return torch.empty(self.record_bytes // self.real_dtype.itemsize, dtype=self.real_dtype, device=self.device)
 
     # ------------------------------------------------------------ entry points
-    def init(self, v0, u0=None, r0=0.0):
+    def init(self, v0, u0=None, r0=0.0, Fbar=None):
+        """lbm_init; Fbar (2, 2) is an optional uniform predeformation (F = Fbar + grad u0)."""
         self._v0 = torch.as_tensor(v0, dtype=torch.float64, device=self.device).contiguous()
         self._u0 = None if u0 is None else torch.as_tensor(u0, dtype=torch.float64, device=self.device).contiguous()
         self.s.cur = 0
         self.fault.zero_()
         self.ustar.zero_()
         L.check(self.lib.lbm_init(ctypes.byref(self.p), ctypes.byref(self.s), _ptr(self._v0), _ptr(self._u0),
-                                  float(r0), _stream()), "lbm_init")
+                                  host_matrix(Fbar), float(r0), _stream()), "lbm_init")
 
     def step(self, n, r_n=1.0, r_np1=1.0, edges=None, record=None, ustar=True):
         """lbm_step; ustar=False skips the displacement quadrature (replays)."""

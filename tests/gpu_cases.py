@@ -7,6 +7,19 @@ import numpy as np
 
 import lbm_inputs as li
 
+ALL_LAWS = ("lognh", "nh", "svk", "mr", "yeoh", "gent")
+# constants of the invariant laws used by the parity cases (multiples of mu, J_m for Gent):
+# a Mooney-Rivlin split with both terms present, a Yeoh law with strong higher terms and a
+# Gent law with a low locking limit, so that every term of each law shows in the results
+LAW_K = {"mr": (0.3, 0.2, 0.0), "yeoh": (0.5, 0.2, 0.1), "gent": (3.0, 0.0, 0.0)}
+
+
+def oracle_law(law, law_k=None):
+    """The oracle's law argument: the name, or (name, constants) for the invariant laws."""
+    if law not in LAW_K:
+        return law
+    return (law, tuple(LAW_K[law] if law_k is None else law_k))
+
 
 @dataclass
 class Case:
@@ -26,6 +39,7 @@ class Case:
     v0: Optional[np.ndarray] = None
     u0: Optional[np.ndarray] = None
     dx: float = 1.0
+    law_k: Optional[tuple] = None        # invariant-law constants (None: LAW_K[law])
 
     def ramp(self, n):
         return 1.0 if self.ramp_steps == 0 else min(1.0, n / self.ramp_steps)
@@ -72,7 +86,8 @@ def oracle_problem(case):
     if body is not None and isinstance(body, tuple):
         body = np.broadcast_to(np.array(body, dtype=np.float64)[:, None, None], (2, case.ny, case.nx)).copy()
     edges = [lbm.Edge(k, (lambda t, d=d: np.array(d, dtype=np.float64))) for k, d in zip(case.kinds, case.data)]
-    return lbm.Problem(nx=case.nx, ny=case.ny, c=case.c, omega=case.omega, law=case.law, mu=case.mu,
+    return lbm.Problem(nx=case.nx, ny=case.ny, c=case.c, omega=case.omega,
+                       law=oracle_law(case.law, case.law_k), mu=case.mu,
                        lam=case.lam, dx=case.dx, body=body, ramp=case.ramp, edges=edges)
 
 
@@ -89,8 +104,10 @@ def run_oracle(case, steps=None):
 
 def make_solver(case, storage):
     from paper_2605_26677_amd.solver import Solver
+    law_k = case.law_k if case.law_k is not None else LAW_K.get(case.law)
     return Solver(case.nx, case.ny, c=case.c, omega=case.omega, dx=case.dx, material=case.law,
-                  storage=storage, bc=tuple(case.kinds), mu=case.mu, lam=case.lam, body=case.body)
+                  storage=storage, bc=tuple(case.kinds), mu=case.mu, lam=case.lam, body=case.body,
+                  law_k=law_k)
 
 
 def run_library(case, storage, steps=None):

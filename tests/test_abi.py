@@ -71,6 +71,45 @@ def test_parameter_validation(mutate, code):
     assert lib.lbm_check_params(ctypes.byref(p)) == code
 
 
+@pytest.mark.parametrize("material,law_k,code", [
+    (L.LBM_MR, (0.3, 0.2, 0.0), L.LBM_OK),
+    (L.LBM_MR, (0.5, 0.0, 0.0), L.LBM_OK),
+    (L.LBM_MR, (0.0, 0.0, 0.0), L.LBM_ERR_ARG),       # no shear stiffness
+    (L.LBM_MR, (0.6, -0.1, 0.0), L.LBM_ERR_ARG),
+    (L.LBM_YEOH, (0.5, 0.05, 0.01), L.LBM_OK),
+    (L.LBM_YEOH, (0.0, 0.05, 0.01), L.LBM_ERR_ARG),
+    (L.LBM_GENT, (20.0, 0.0, 0.0), L.LBM_OK),
+    (L.LBM_GENT, (0.0, 0.0, 0.0), L.LBM_ERR_ARG),
+    (L.LBM_SVK, (0.0, 0.0, 0.0), L.LBM_OK),           # ignored by the Lame-parametrised laws
+    (6, (0.0, 0.0, 0.0), L.LBM_ERR_ARG),
+])
+def test_law_constant_validation(material, law_k, code):
+    lib = L.lib()
+    p = _params()
+    p.material = material
+    for i in range(3):
+        p.law_k[i] = law_k[i]
+    assert lib.lbm_check_params(ctypes.byref(p)) == code
+
+
+def test_cfl_audit_invariant_laws():
+    """The invariant laws' small-strain P-wave speed is sqrt(lam + 4 G / 3) with G the
+    small-strain shear modulus: MR 2 (c10 + c01), Yeoh 2 c1, Gent mu."""
+    lib = L.lib()
+    p = _params(c=2.0)
+    mu, lam = 1.0, 0.5
+    for material, k, G in ((L.LBM_MR, (0.3, 0.2, 0), 1.0), (L.LBM_YEOH, (0.75, 0, 0), 1.5),
+                           (L.LBM_GENT, (20.0, 0, 0), 1.0)):
+        p.material = material
+        for i in range(3):
+            p.law_k[i] = k[i]
+        cp = (lam + 4.0 * G / 3.0) ** 0.5
+        p.c = 2.0 * cp * 1.001
+        assert lib.lbm_check_cfl(ctypes.byref(p), mu, lam) == L.LBM_OK
+        p.c = 2.0 * cp * 0.999
+        assert lib.lbm_check_cfl(ctypes.byref(p), mu, lam) == L.LBM_ERR_CFL
+
+
 def test_walls_need_four_nodes():
     lib = L.lib()
     p = _params(3, 16, bc=(1, 2, 0, 0))
@@ -94,7 +133,7 @@ def test_calls_reject_missing_buffers():
     p = _params()
     s = L.lbm_state()
     assert lib.lbm_step(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, None, None, None) == L.LBM_ERR_ARG
-    assert lib.lbm_init(ctypes.byref(p), ctypes.byref(s), None, None, 0.0, None) == L.LBM_ERR_ARG
+    assert lib.lbm_init(ctypes.byref(p), ctypes.byref(s), None, None, None, 0.0, None) == L.LBM_ERR_ARG
     a = L.lbm_adj_state()
     assert lib.lbm_adjoint_step(ctypes.byref(p), ctypes.byref(s), ctypes.byref(a), 0, 1.0, None, None,
                                 None) == L.LBM_ERR_ARG

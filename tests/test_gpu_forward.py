@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import lbm_inputs as li
-from gpu_cases import (Case, block_case, mixed_case, random_field_case, rel_l2, run_library,
+from gpu_cases import (ALL_LAWS, Case, block_case, mixed_case, random_field_case, rel_l2, run_library,
                        run_oracle, shear_wave_case, shifted_state, make_solver)
 
 pytestmark = pytest.mark.gpu
@@ -55,7 +55,7 @@ def test_shear_wave_parity(storage):
         assert errs["pop"] <= bar
 
 
-@pytest.mark.parametrize("law", ["lognh", "nh", "svk"])
+@pytest.mark.parametrize("law", ALL_LAWS)
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_random_field_parity(law, storage):
     """Periodic grid spanning several 256-wide tiles with a ragged tail (300 x 40)."""
@@ -75,7 +75,7 @@ def test_block_with_walls_parity(fields, storage):
     assert errs["v"] <= bar and errs["Ft"] <= bar and errs["u"] <= bar
 
 
-@pytest.mark.parametrize("law", ["lognh", "nh", "svk"])
+@pytest.mark.parametrize("law", ALL_LAWS)
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_mixed_edges_parity(law, storage):
     """Moving velocity walls and loaded traction walls, F0 = I + grad u0, corners."""
@@ -93,7 +93,7 @@ def test_ragged_wall_grid_parity():
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("kinds", [("periodic",) * 4, ("velocity", "traction", "traction", "traction"),
                                    ("traction",) * 4, ("periodic", "periodic", "velocity", "traction")])
-@pytest.mark.parametrize("law", ["lognh", "nh", "svk"])
+@pytest.mark.parametrize("law", ALL_LAWS)
 def test_rest_state_bitwise(storage, kinds, law):
     """F0 = I, v0 = 0, b = 0, zero wall data: P(I) = 0 keeps every stored population exactly
     at its reference value (0 in shifted storage, U_ref/4 in plain)."""

@@ -23,7 +23,9 @@ def _problem(mu, lam, body, kinds, omega, law):
     ("velocity", "traction", "traction", "traction"),
     ("traction",) * 4,
 ])
-@pytest.mark.parametrize("omega,law", [(2.0, "lognh"), (1.9, "lognh"), (1.95, "svk"), (1.95, "nh")])
+@pytest.mark.parametrize("omega,law", [(2.0, "lognh"), (1.9, "lognh"), (1.95, "svk"), (1.95, "nh"),
+                                       (1.95, ("mr", (0.3, 0.2))), (2.0, ("yeoh", (0.5, 0.2, 0.1))),
+                                       (1.95, ("gent", (3.0,)))])
 def test_adjoint_matches_central_differences(kinds, omega, law):
     mu = li.lognormal_field(NX, NY, 1, 0.1, 0.3, 3.0)
     lam = li.lognormal_field(NX, NY, 2, 0.2, 0.3, 3.0)
