@@ -141,6 +141,84 @@ def time_forward_adjoint(n, steps, K, nprobe=16):
                 bwd_over_fwd=t_b / t_f, peak_mem_GiB=mem, grads_finite=ok, steps=steps, K=K, c=c)
 
 
+def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0):
+    """The large adjoint workload: n x n, velocity wall (v = 0) at the bottom, traction
+    (0, -2e-4 min(1, t/(2000 dt))) on the top evaluated at t^{m+1/2}, traction-free sides,
+    per-node log-NH mu, lam log-normal fields (median 0.1 / 0.4, sigma_log 0.3, correlation
+    length 32), c = 10 (traction-free corners go unstable over thousands of steps at
+    lattice speeds near the P-wave bound), omega = 2 - 1.6/n, loss sum |u|^2 at 256
+    random probes after `steps` steps, FP32 forward and
+    adjoint with FP64 gradient accumulation, checkpoint levels planned for a device-memory
+    budget.  Reports forward + adjoint throughput, peak device memory against the budget
+    and the relative error of directional derivatives against FP64 central differences."""
+    import torch
+    import lbm_inputs as li
+    from paper_2605_26677_amd.rollout import RolloutConfig, checkpoint_plan, memory_model, rollout
+    budget = int(budget_gib * 2 ** 30)
+    levels = checkpoint_plan(n, n, "f32", steps, budget)
+    model = memory_model(n, n, "f32", steps, levels)
+    log(f"bench: adjoint at scale {n}^2 x {steps}, levels {levels}, model peak {model['peak'] / 2**30:.1f} GiB")
+    mu0 = li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0)
+    lam0 = li.lognormal_field(n, n, 402, 0.4, 0.3, 32.0)
+    ys, xs = li.random_probes(n, n, 256, 405)
+    probes = torch.tensor(ys * n + xs, dtype=torch.int64)
+    top = lambda m: (0.0, -2e-4 * min(1.0, (m + 0.5) / 2000.0))
+    common = dict(nx=n, ny=n, c=c, omega=2.0 - 1.6 / n, nsteps=steps, probes=probes,
+                  bc=("traction", "traction", "velocity", "traction"),
+                  edges=lambda m: [(0.0, 0.0), (0.0, 0.0), (0.0, 0.0), top(m)])
+    dev = "cuda"
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    base_mem = torch.cuda.memory_allocated()
+    mu = torch.tensor(mu0, dtype=torch.float64, device=dev, requires_grad=True)
+    lam = torch.tensor(lam0, dtype=torch.float64, device=dev, requires_grad=True)
+    body = torch.zeros((2, n, n), dtype=torch.float64, device=dev, requires_grad=True)
+    v0 = torch.zeros((2, n, n), dtype=torch.float64, device=dev, requires_grad=True)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    u = rollout(mu, lam, body, v0, RolloutConfig(storage="f32", levels=levels, **common))
+    e1.record()
+    torch.cuda.synchronize()
+    log(f"bench: forward done, {e0.elapsed_time(e1) / 1e3:.1f} s")
+    (u.double() ** 2).sum().backward()
+    e2.record()
+    torch.cuda.synchronize()
+    t_f, t_b = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    peak = torch.cuda.max_memory_allocated() - base_mem
+    log(f"bench: backward done, {t_b / 1e3:.1f} s, peak {peak / 2**30:.1f} GiB")
+    g = {k: t.grad.cpu().numpy() for k, t in (("mu", mu), ("lam", lam), ("body", body), ("v0", v0))}
+    del mu, lam, body, v0, u
+    torch.cuda.empty_cache()
+    cfg64 = RolloutConfig(storage="f64", **common)
+
+    def loss(p):
+        with torch.no_grad():
+            uu = rollout(*(torch.tensor(p[k], device=dev, dtype=torch.float32 if k != "v0" else torch.float64)
+                           for k in ("mu", "lam", "body", "v0")), cfg64)
+        return float((uu.double() ** 2).sum())
+
+    base = dict(mu=mu0, lam=lam0, body=np.zeros((2, n, n)), v0=np.zeros((2, n, n)))
+    scale = dict(mu=0.1, lam=0.4, body=1e-6, v0=1e-4)
+    errs = []
+    for d in li.fd_directions({k: base[k].shape for k in base}, fd_dirs, 406):
+        plus, minus = {}, {}
+        for k in base:
+            step = 1e-3 * scale[k] * d[k]
+            if k == "v0":
+                plus[k], minus[k] = base[k] + step, base[k] - step
+            else:
+                plus[k], minus[k] = li.round_f32(base[k] + step), li.round_f32(base[k] - step)
+        fd = loss(plus) - loss(minus)
+        an = sum((g[k] * (plus[k] - minus[k])).sum() for k in base)
+        errs.append(abs(fd - an) / abs(fd))
+        log(f"bench: FD {fd:.6e} adjoint {an:.6e} rel {errs[-1]:.2e}")
+    return dict(grid=[n, n], steps=steps, levels=levels, budget_GiB=budget_gib,
+                model_peak_GiB=model["peak"] / 2 ** 30, peak_mem_GiB=peak / 2 ** 30,
+                forward_passes=model["forward_passes"], ms_fwd=t_f, ms_bwd=t_b, bwd_over_fwd=t_b / t_f,
+                mlups=n * n * steps / ((t_f + t_b) * 1e-3) / 1e6, fd_rel_err=errs, c=c)
+
+
 def profile_run(n, steps):
     """Short run for rocprofv3: a plain device copy of known size (counter calibration)
     followed by FP32 steps of the benchmark workload."""
@@ -190,6 +268,12 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (copy + 20 f32 steps)")
+    ap.add_argument("--adjoint-at-scale", action="store_true",
+                    help="the 4096^2 adjoint workload under a 64 GiB checkpoint budget (separate JSON line)")
+    ap.add_argument("--scale-size", type=int, default=4096)
+    ap.add_argument("--scale-steps", type=int, default=20000)
+    ap.add_argument("--scale-budget-gib", type=float, default=64.0)
+    ap.add_argument("--scale-fd-dirs", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -199,6 +283,10 @@ def main():
     n = args.size
     if args.profile:
         profile_run(n, 20)
+        return
+    if args.adjoint_at_scale:
+        r = adjoint_at_scale(args.scale_size, args.scale_steps, args.scale_budget_gib, args.scale_fd_dirs)
+        print(json.dumps({"adjoint_at_scale": r}), flush=True)
         return
     log(f"bench: generating {n}x{n} inputs")
     v0 = make_inputs(n)

@@ -10,10 +10,13 @@ Checkpointing: the forward pass keeps the post-collision populations every K lev
 ("every-K"); the backward pass walks the segments in reverse, restores the segment's
 snapshot, replays it while recording the state U^m of each level (lbm_step(record)),
 then runs the adjoint steps of that segment from its last level down to its first.
-Memory: ceil((N + 1) / K) snapshots of lbm_pop_bytes() plus K + 1 records of
-lbm_record_bytes().  ``schedule="nested"`` splits the replay recursively (segment
-lengths K1 > K2 > ... ) for runs whose snapshots would not fit a memory budget.
+Memory: floor(N / K) + 1 snapshots of lbm_pop_bytes() + lbm_record_bytes() plus K + 1
+records.  ``levels=[K0, K1, ...]`` splits the replay recursively (segment lengths
+K0 > K1 > ...): each extra level re-runs the forward once more and divides the number of
+live snapshots; ``checkpoint_plan`` picks the shallowest nesting whose peak device memory
+fits a byte budget (``memory_model`` is the accounting it uses).
 """
+import math
 import ctypes
 from dataclasses import dataclass, field
 from typing import Callable, Optional, Sequence
@@ -44,6 +47,77 @@ class RolloutConfig:
     newton_max_iter: int = 0
     law_k: Optional[Sequence[float]] = None            # invariant-law constants (lbm.h law_k)
     Fbar: Optional[Sequence[Sequence[float]]] = None   # uniform predeformation at t = 0
+
+
+def _sizes(nx, ny, storage):
+    p = L.lbm_params()
+    p.nx, p.ny, p.storage = int(nx), int(ny), L.STORAGE[storage]
+    lib = L.lib()
+    nodes = int(nx) * int(ny)
+    return dict(pop=lib.lbm_pop_bytes(ctypes.byref(p)), rec=lib.lbm_record_bytes(ctypes.byref(p)),
+                ustar=lib.lbm_ustar_bytes(ctypes.byref(p)), adj=lib.lbm_adj_bytes(ctypes.byref(p)),
+                aux=lib.lbm_aux_bytes(ctypes.byref(p)), nodes=nodes)
+
+
+def memory_model(nx, ny, storage, nsteps, levels, leaf_bytes_per_node=48):
+    """Peak device bytes of ``rollout`` with nested segment lengths ``levels`` (outermost
+    first; [K] is every-K), as the sum of
+      fixed:     two population buffers, u*, the float32 mu, lam, b planes, the FP64 v0,
+                 u and gradient planes, two adjoint buffers, and the caller's leaf tensors
+                 (leaf_bytes_per_node: FP64 mu, lam, b, v0 = 48);
+      snapshots: the forward's floor(N / K0) + 1 (f*, record) pairs, plus, while the
+                 first top segment is reversed, ceil(K_{l-1} / K_l) - 1 more per level;
+      records:   K_last + 1 records for the innermost replay."""
+    z = _sizes(nx, ny, storage)
+    n, N = z["nodes"], int(nsteps)
+    fixed = (2 * z["pop"] + z["ustar"] + 2 * z["aux"] + 16 * n + 16 * n + 16 * n
+             + 2 * z["adj"] + 48 * n + leaf_bytes_per_node * n)
+    pair = z["pop"] + z["rec"]
+    K = [int(k) for k in levels]
+    snaps = (N // K[0] + 1) * pair
+    for a, b in zip(K[:-1], K[1:]):
+        snaps += (math.ceil((a + 1) / b) - 1) * pair
+    records = (K[-1] + 1) * z["rec"]
+    return dict(fixed=fixed, snapshots=snaps, records=records, peak=fixed + snaps + records,
+                forward_passes=len(K) + 1)
+
+
+def checkpoint_plan(nx, ny, storage, nsteps, budget_bytes, max_depth=8, leaf_bytes_per_node=48):
+    """Segment lengths for ``RolloutConfig.levels`` whose ``memory_model`` peak fits
+    budget_bytes with the fewest nesting levels (each level costs one forward replay).
+    For depth d the segment lengths follow the geometric split K_l ~ N / x^(l+1) that
+    balances the snapshot and record terms, refined by a small scan of x.  Raises
+    ValueError when even max_depth levels do not fit."""
+    N = int(nsteps)
+    z = _sizes(nx, ny, storage)
+    ratio = z["rec"] / (z["pop"] + z["rec"])
+    best = None
+    for d in range(1, max_depth + 1):
+        x0 = max(1.0 + 1e-9, (N * ratio) ** (1.0 / (d + 1)))
+        cands = []
+        for f in (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.25, 1.4, 1.6, 1.8, 2.0):
+            x = max(1.0 + 1e-9, x0 * f)
+            K = []
+            for lvl in range(d):
+                k = max(1, int(round(N / x ** (lvl + 1))))
+                if K and k >= K[-1]:
+                    k = K[-1] - 1
+                if k < 1:
+                    break
+                K.append(k)
+            if len(K) != d:
+                continue
+            m = memory_model(nx, ny, storage, N, K, leaf_bytes_per_node)
+            cands.append((m["peak"], K, m))
+        if not cands:
+            continue
+        peak, K, m = min(cands, key=lambda t: t[0])
+        if best is None or peak < best[0]:
+            best = (peak, K, m)
+        if peak <= budget_bytes:
+            return K
+    raise ValueError(f"no nesting up to depth {max_depth} fits {budget_bytes / 2**30:.1f} GiB "
+                     f"(best {best[0] / 2**30:.1f} GiB with levels {best[1]})")
 
 
 def _edges(cfg, n):
@@ -148,9 +222,12 @@ class LBMRollout(torch.autograd.Function):
         sv.init(v0d, u0, r0=cfg.ramp(0), Fbar=cfg.Fbar)
         N = cfg.nsteps
         K = cfg.levels[0] if cfg.levels else cfg.checkpoint_every
-        snaps = {0: (sv.pop[sv.s.cur].clone(), sv.record_state(cfg.ramp(0), sv.new_record()))}
+        # checkpoints only when a gradient will be asked for (a no-grad evaluation, such as
+        # a finite-difference probe, keeps nothing)
+        keep = any(ctx.needs_input_grad[:4])
+        snaps = {0: (sv.pop[sv.s.cur].clone(), sv.record_state(cfg.ramp(0), sv.new_record()))} if keep else {}
         for n in range(N):
-            if (n + 1) % K == 0:
+            if keep and (n + 1) % K == 0:
                 snaps[n + 1] = _step_to_snapshot(sv, cfg, n)
             else:
                 sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n))

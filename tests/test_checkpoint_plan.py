@@ -1,0 +1,41 @@
+"""Host-side checks of the checkpoint planner (no GPU): the memory accounting and the
+choice of the shallowest nesting that fits a budget."""
+import pytest
+
+from paper_2605_26677_amd.rollout import checkpoint_plan, memory_model
+
+
+def test_every_k_accounting():
+    """Every-K at 512^2 FP32: floor(N/K) + 1 snapshot pairs (96 + 24 B per node) and
+    K + 1 records (24 B per node)."""
+    n, N, K = 512, 2000, 100
+    m = memory_model(n, n, "f32", N, [K])
+    nodes = n * n
+    assert m["snapshots"] == (N // K + 1) * 120 * nodes
+    assert m["records"] == (K + 1) * 24 * nodes
+    assert m["forward_passes"] == 2
+
+
+def test_nesting_trades_memory_for_replays():
+    n, N = 4096, 20000
+    flat = memory_model(n, n, "f32", N, [141])
+    nested = memory_model(n, n, "f32", N, [2000, 100])
+    assert nested["peak"] < flat["peak"] and nested["forward_passes"] == flat["forward_passes"] + 1
+
+
+@pytest.mark.parametrize("budget_gib", [64, 96, 128, 256])
+def test_plan_fits_budget_with_fewest_levels(budget_gib):
+    n, N = 4096, 20000
+    B = budget_gib * 2 ** 30
+    K = checkpoint_plan(n, n, "f32", N, B)
+    assert memory_model(n, n, "f32", N, K)["peak"] <= B
+    assert all(a > b for a, b in zip(K, K[1:]))
+    if len(K) > 1:
+        # one level fewer does not fit at any split the planner considers
+        with pytest.raises(ValueError):
+            checkpoint_plan(n, n, "f32", N, B, max_depth=len(K) - 1)
+
+
+def test_plan_refuses_impossible_budget():
+    with pytest.raises(ValueError):
+        checkpoint_plan(4096, 4096, "f32", 20000, 8 * 2 ** 30)

@@ -145,3 +145,106 @@ def test_adjoint_against_fp64_central_differences():
         an = sum((g[k] * (plus[k] - minus[k])).sum() for k in base)
         print(f"\nFD {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
         assert abs(fd - an) <= 1e-4 * abs(fd)
+
+
+def test_adjoint_512_2000_steps_against_fp64_central_differences():
+    """The 512^2 adjoint workload: velocity wall (v = 0) on the left, traction-free
+    elsewhere, per-node log-normal mu, lam (median 0.1 / 0.2, sigma_log 0.3, correlation
+    length 32), body force (0, -1e-5) ramped over 500 steps, loss sum |u - u_target|^2 at
+    16 random probes after 2000 steps; FP32 forward and adjoint with FP64 gradient
+    accumulation and a checkpoint every 100 steps; c = 10, omega = 2 - 1.6/512 (with
+    traction-free corners the step goes unstable over a few thousand steps for
+    c_p/c above about 0.35, so the wall workloads use c = 10).  Directional derivatives
+    along 8 random directions in (mu, lam, b, v0) against FP64 central differences: 1e-4
+    relative, and every value finite."""
+    from paper_2605_26677_amd.rollout import RolloutConfig, rollout
+    n, N = 512, 2000
+    mu0 = li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0)
+    lam0 = li.lognormal_field(n, n, 402, 0.2, 0.3, 32.0)
+    body0 = li.uniform_body(n, n, (0.0, -1e-5))
+    v00 = np.stack([li.gaussian_random_field(n, n, 403, 1e-4), li.gaussian_random_field(n, n, 404, 1e-4)])
+    ys, xs = li.random_probes(n, n, 16, 405)
+    probes = torch.tensor(ys * n + xs, dtype=torch.int64)
+    target = torch.tensor(np.random.default_rng(407).normal(0.0, 1e-4, (2, 16)), device="cuda")
+    common = dict(nx=n, ny=n, c=10.0, omega=2.0 - 1.6 / n, nsteps=N, probes=probes,
+                  bc=("velocity", "traction", "traction", "traction"), ramp=lambda m: min(1.0, m / 500),
+                  edges=lambda m: [(0.0, 0.0)] * 4)
+    dev = "cuda"
+    mu = torch.tensor(mu0, dtype=torch.float64, device=dev, requires_grad=True)
+    lam = torch.tensor(lam0, dtype=torch.float64, device=dev, requires_grad=True)
+    body = torch.tensor(body0, dtype=torch.float64, device=dev, requires_grad=True)
+    v0 = torch.tensor(v00, dtype=torch.float64, device=dev, requires_grad=True)
+    u = rollout(mu, lam, body, v0, RolloutConfig(storage="f32", checkpoint_every=100, **common))
+    assert torch.isfinite(u).all()
+    ((u.double() - target) ** 2).sum().backward()
+    g = dict(mu=mu.grad.cpu().numpy(), lam=lam.grad.cpu().numpy(), body=body.grad.cpu().numpy(),
+             v0=v0.grad.cpu().numpy())
+    assert all(np.isfinite(v).all() for v in g.values())
+    cfg64 = RolloutConfig(storage="f64", **common)
+
+    def loss(p):
+        with torch.no_grad():
+            uu = rollout(*(torch.tensor(p[k], device=dev, dtype=torch.float32 if k != "v0" else torch.float64)
+                           for k in ("mu", "lam", "body", "v0")), cfg64)
+        return float(((uu.double() - target) ** 2).sum())
+
+    base = dict(mu=mu0, lam=lam0, body=body0, v0=v00)
+    scale = dict(mu=0.1, lam=0.2, body=1e-5, v0=1e-4)
+    worst = 0.0
+    for d in li.fd_directions({k: base[k].shape for k in base}, 8, 406):
+        plus, minus = {}, {}
+        for k in base:
+            step = 1e-3 * scale[k] * d[k]
+            if k == "v0":
+                plus[k], minus[k] = base[k] + step, base[k] - step
+            else:
+                plus[k], minus[k] = li.round_f32(base[k] + step), li.round_f32(base[k] - step)
+        fd = loss(plus) - loss(minus)
+        an = sum((g[k] * (plus[k] - minus[k])).sum() for k in base)
+        assert np.isfinite(fd) and np.isfinite(an) and fd != 0.0
+        worst = max(worst, abs(fd - an) / abs(fd))
+        print(f"\n[adjoint 512^2 x 2000] FD {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
+    assert worst <= 1e-4
+
+
+def test_checkpoint_plan_memory_model_matches_measurement():
+    """A nested plan chosen for a budget that the every-K schedule cannot meet: the
+    measured peak of the caching allocator stays within the budget and within 15 % of the
+    planner's memory model, and the gradients equal those of a flat schedule bitwise."""
+    from paper_2605_26677_amd.rollout import RolloutConfig, checkpoint_plan, memory_model, rollout
+    n, N = 1024, 400
+    flat_best = min(memory_model(n, n, "f32", N, [k])["peak"] for k in range(5, 200))
+    budget = int(0.8 * flat_best)
+    levels = checkpoint_plan(n, n, "f32", N, budget)
+    assert len(levels) >= 2
+    model = memory_model(n, n, "f32", N, levels)["peak"]
+    mu0 = li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0)
+    lam0 = li.lognormal_field(n, n, 402, 0.2, 0.3, 32.0)
+    ys, xs = li.random_probes(n, n, 16, 405)
+    probes = torch.tensor(ys * n + xs, dtype=torch.int64)
+    common = dict(nx=n, ny=n, c=2.75, omega=2.0, nsteps=N, probes=probes, storage="f32")
+
+    def run(cfg):
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        dev = "cuda"
+        mu = torch.tensor(mu0, dtype=torch.float64, device=dev, requires_grad=True)
+        lam = torch.tensor(lam0, dtype=torch.float64, device=dev, requires_grad=True)
+        body = torch.zeros((2, n, n), dtype=torch.float64, device=dev, requires_grad=True)
+        v0 = torch.tensor(np.stack([li.gaussian_random_field(n, n, 403, 1e-3),
+                                    li.gaussian_random_field(n, n, 404, 1e-3)]), device=dev, requires_grad=True)
+        (rollout(mu, lam, body, v0, cfg) ** 2).sum().backward()
+        torch.cuda.synchronize()
+        peak = torch.cuda.max_memory_allocated() - base
+        return peak, [t.grad.cpu().numpy() for t in (mu, lam, body, v0)]
+
+    peak, g_nested = run(RolloutConfig(levels=levels, **common))
+    print(f"\n[checkpoint plan {n}^2 x {N}] levels {levels} budget {budget / 2**30:.2f} GiB "
+          f"model {model / 2**30:.2f} GiB measured {peak / 2**30:.2f} GiB")
+    assert peak <= budget
+    assert 0.85 * model <= peak <= 1.05 * model
+    _, g_flat = run(RolloutConfig(checkpoint_every=50, **common))
+    for a, b in zip(g_nested, g_flat):
+        assert np.array_equal(a, b)
