@@ -167,7 +167,11 @@ lbm_status lbm_check_params(const lbm_params *p);
  * Lame-parametrised laws and sqrt(lam + 4/3 G) for the invariant laws with small-strain
  * shear modulus G; the linearised D2Q4 x 6 step is stable for a P-wave speed of at most
  * c/2 at omega = 2.  Returns LBM_ERR_CFL above that ratio, LBM_OK otherwise.  Finite
- * strains can raise the tangent speeds (lbm_diagnostics out[9] audits the current state). */
+ * strains can raise the tangent speeds (lbm_diagnostics out[9] audits the current state).
+ * Grids whose walls meet at corners need more margin over long runs: a slowly growing
+ * corner instability was observed at a P-wave speed of c/4 after some thousands of steps
+ * (none at c/5 over 8000 steps, nor at c/16 over 20000); the bound of c/2 is the periodic
+ * one. */
 lbm_status lbm_check_cfl(const lbm_params *p, double mu_max, double lam_max);
 
 /* ------------------------------------------------------------------ forward */
