@@ -110,6 +110,40 @@ def time_forward(n, storage, steps, warmup, v0, law="lognh"):
     return ms, faults
 
 
+def time_launch_bound(n=256, steps=4000, block=100):
+    """The same step on a small grid where the host launch cost dominates: per-step eager
+    calls against blocks of steps replayed from a captured HIP graph (Solver.advance)."""
+    import torch
+    from paper_2605_26677_amd.solver import Solver
+    v0 = make_inputs(n)
+    out = {}
+    for mode in ("eager", "graph"):
+        sv = Solver(n, n, c=2.0, omega=2.0, storage="f32", mu=0.1, lam=0.2)
+        sv.init(v0)
+        for k in range(20):
+            sv.step(k)
+        if mode == "graph":
+            sv.advance(20, 2 * block, block=block)      # capture outside the timed region
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        if mode == "eager":
+            for k in range(steps):
+                sv.step(k)
+        else:
+            sv.advance(0, steps, block=block)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[f"{mode}_ms_per_step"] = ms
+        out[f"{mode}_mlups"] = n * n / (ms * 1e-3) / 1e6
+        assert sv.faults() == 0
+        del sv
+    out["grid"] = [n, n]
+    out["speedup"] = out["eager_ms_per_step"] / out["graph_ms_per_step"]
+    return out
+
+
 def time_forward_adjoint(n, steps, K, nprobe=16):
     """Forward + checkpointed adjoint of the probe-displacement loss with per-node mu, lam
     (log-normal, median 0.1 / 0.2, sigma_log 0.3, correlation length 32), FP32 storage."""
@@ -301,6 +335,9 @@ def main():
         res[storage] = dict(ms_per_step=ms, mlups=mlups, algorithmic_GBps=gbs,
                             frac_hbm=gbs * 1e9 / PEAK_HBM, faults=faults, steps=steps)
         log(f"bench: {storage}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {gbs:.0f} GB/s")
+    log("bench: launch-bound grid, eager vs captured graph")
+    res["launch_bound_256"] = time_launch_bound()
+    log(f"bench: launch-bound: {res['launch_bound_256']}")
     if not args.no_adjoint:
         log(f"bench: forward + adjoint, {args.adjoint_steps} steps, checkpoint every {args.adjoint_every}")
         res["fwd_adj_f32"] = time_forward_adjoint(n, args.adjoint_steps, args.adjoint_every)

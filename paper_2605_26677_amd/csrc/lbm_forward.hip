@@ -3,11 +3,11 @@
 // (Sec. 3.4) and the recoveries from stored post-collision populations (Sec. 3.5).
 //
 // Layout: populations, u* and records in 64-node row tiles holding all their planes
-// contiguously (tile_base in lbm_device.hpp).  One thread per node, one wavefront per tile,
-// four tiles per workgroup; the tile order is remapped so that each of the eight XCDs
-// sweeps a contiguous band of rows (its L2 then serves the one-element overlap of the
-// x -/+ 1 pulls between adjacent tiles).  Each stored value is written once per pass, with
-// non-temporal stores.
+// contiguously (tile_base in lbm_device.hpp).  One thread per node, one wavefront per
+// tile, kTilesPerBlock tiles per workgroup; the tile order is remapped so that each of the
+// eight XCDs sweeps a contiguous band of rows (its L2 then serves the one-element overlap
+// of the x -/+ 1 pulls between adjacent tiles).  Each stored value is written once per
+// pass, with non-temporal stores.
 #include <algorithm>
 
 #include "lbm_device.hpp"

@@ -50,6 +50,52 @@ def host_matrix(F):
     return (ctypes.c_double * 4)(*vals)
 
 
+def _edge_key(edges):
+    """Hashable description of wall data: values, or tensor identities (a captured graph
+    holds the tensor's address)."""
+    if edges is None:
+        return None
+    key = []
+    for v in edges:
+        if v is None:
+            key.append(None)
+        elif isinstance(v, torch.Tensor):
+            key.append(("t", v.data_ptr(), tuple(v.shape)))
+        else:
+            key.append((float(v[0]), float(v[1])))
+    return tuple(key)
+
+
+class StepGraph:
+    """A fixed sequence of lbm_step calls recorded once as a HIP graph (the library's
+    launches are captured from torch's capture stream) and replayed as one launch.
+
+    Every argument is frozen at capture: step factors, wall data (values, or the addresses
+    of field tensors, which the graph keeps alive), record buffers, and the two population
+    buffers in the order they had then.  ``replay`` therefore requires the solver to hold
+    the same current buffer as at capture, and afterwards sets it to the buffer the
+    sequence ends in.  The library records no memset and allocates nothing, so its
+    launches are capture-safe; the capture itself executes nothing."""
+
+    def __init__(self, solver, steps):
+        self.sv = solver
+        self.start_cur = solver.s.cur
+        self._keep = [st.get("edges") for st in steps] + [st.get("record") for st in steps]
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            for st in steps:
+                solver.step(**st)
+        self.end_cur = solver.s.cur
+        solver.s.cur = self.start_cur
+        self.nsteps = len(steps)
+
+    def replay(self):
+        if self.sv.s.cur != self.start_cur:
+            raise RuntimeError("StepGraph.replay: the solver's current buffer differs from the capture's")
+        self.graph.replay()
+        self.sv.s.cur = self.end_cur
+
+
 class Solver:
     def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
                  bc=("periodic",) * 4, mu=0.1, lam=0.2, body=None, newton_max_iter=0,
@@ -159,6 +205,49 @@ class Solver:
                                       float(r_np1), ctypes.byref(ed.c), _ptr(record), _stream()), "lbm_step")
         finally:
             self.s.ustar = keep
+
+    def capture(self, steps):
+        """Records a fixed sequence of lbm_step calls as one HIP graph (``StepGraph``).
+        ``steps`` is a list of dicts with the keyword arguments of ``step``."""
+        return StepGraph(self, steps)
+
+    def advance(self, n0, count, ramp=None, edges=None, block=64):
+        """Steps n0 .. n0 + count - 1 with ramp factors ``ramp(n)`` (default 1) and wall data
+        ``edges(n)`` (default zero): whole blocks of ``block`` steps whose arguments equal
+        those of the first captured block replay one captured graph, the rest run eagerly.
+        For launch-bound grids this removes the per-step host cost."""
+        ramp = ramp or (lambda n: 1.0)
+        edges = edges or (lambda n: None)
+
+        def args(n):
+            return dict(n=n, r_n=float(ramp(n)), r_np1=float(ramp(n + 1)), edges=edges(n))
+
+        def same(a, b):
+            return (a["r_n"] == b["r_n"] and a["r_np1"] == b["r_np1"]
+                    and _edge_key(a["edges"]) == _edge_key(b["edges"]))
+
+        graph, proto = None, None
+        n, end = n0, n0 + count
+        block += block % 2          # keep the buffer parity of a replay
+        while n < end:
+            blk = [args(m) for m in range(n, min(end, n + block))]
+            if len(blk) == block and graph is None and self._graph_ok(blk):
+                proto = blk
+                graph = self.capture(blk)
+            if (graph is not None and len(blk) == block and self.s.cur == graph.start_cur
+                    and all(same(a, b) for a, b in zip(blk, proto))):
+                graph.replay()
+            else:
+                for a in blk:
+                    self.step(**a)
+            n += len(blk)
+
+    @staticmethod
+    def _graph_ok(blk):
+        # a block is capturable when its per-step arguments repeat exactly (every step
+        # index argument is unused by the kernels, so only factors and wall data matter)
+        return all(a["r_n"] == blk[0]["r_n"] and a["r_np1"] == blk[0]["r_np1"]
+                   and _edge_key(a["edges"]) == _edge_key(blk[0]["edges"]) for a in blk)
 
     def moments(self, r_n=1.0):
         out = torch.empty((6, self.ny, self.nx), dtype=torch.float64, device=self.device)

@@ -206,3 +206,41 @@ def test_stress_recovery(storage, bar, law):
     eS = rel_l2(S, Se)
     print(f"\n[stress {law} {storage}] P={eP:.2e} sigma={eS:.2e}")
     assert eP <= bar and eS <= bar
+
+
+@pytest.mark.parametrize("kinds,storage", [(("periodic",) * 4, "f32"),
+                                           (("velocity", "traction", "traction", "traction"), "f32"),
+                                           (("velocity", "traction", "traction", "traction"), "f64")])
+def test_step_graph_replays_match_eager(kinds, storage):
+    """A captured block of steps replayed four times, with eager work (moments, a host
+    synchronisation) between the replays, gives bitwise the eager result after every
+    replay; ``advance`` (captured blocks plus an eager tail) matches too."""
+    import torch
+    from gpu_cases import block_case
+    case = block_case(nx=96, ny=80, steps=0)
+    case.kinds = kinds
+    case.ramp_steps = 0
+    data = [(0.0, 0.0), (1e-4, 0.0), (0.0, 0.0), (0.0, -1e-4)]
+    eager = make_solver(case, storage)
+    graph = make_solver(case, storage)
+    for sv in (eager, graph):
+        sv.init(case.v0, r0=1.0)
+        sv.step(0, edges=data)                 # loads the kernels before any capture
+    g = graph.capture([dict(n=m, edges=data) for m in range(1, 11)])
+    for rep in range(4):
+        for m in range(1 + 10 * rep, 11 + 10 * rep):
+            eager.step(m, edges=data)
+        g.replay()
+        Ue, Ug = eager.moments(), graph.moments()
+        torch.cuda.synchronize()
+        assert torch.equal(Ue, Ug), rep
+        assert torch.equal(eager.displacement(), graph.displacement())
+    eager2 = make_solver(case, storage)
+    adv = make_solver(case, storage)
+    for sv in (eager2, adv):
+        sv.init(case.v0, r0=1.0)
+    for m in range(150):
+        eager2.step(m, edges=data)
+    adv.advance(0, 150, edges=lambda n: data, block=32)
+    assert torch.equal(eager2.moments(), adv.moments())
+    assert eager2.faults() == 0 and adv.faults() == 0

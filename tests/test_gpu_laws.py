@@ -153,3 +153,22 @@ def test_predeformed_acoustic_speeds(law, storage, bar):
             print(f"\n[acoustic {law} {name} branch {branch} {storage}] c_ac={c_ac:.6f} c_gpu={c_gpu:.9f} "
                   f"vs oracle {d_or:.2e} vs acoustic tensor {d_ac:.2e}")
             assert d_or <= bar and d_ac <= 5e-4
+
+
+def test_gent_locking_limit_is_reported():
+    """A shear wave with max F21 = 0.3 has barI1 - 3 = 0.09 (J = 1): beyond a Gent limit
+    J_m = 0.05 the state is inadmissible and fault bit 1 is raised (init and step); with
+    J_m = 1 the same run is clean."""
+    from paper_2605_26677_amd.solver import Solver
+    n = 64
+    k = 2 * np.pi / n
+    x = np.arange(n) + 0.5
+    u0 = np.zeros((2, n, n))
+    u0[1] = np.broadcast_to((0.3 / k) * np.sin(k * x)[None, :], (n, n))
+    for jm, expect in ((0.05, True), (1.0, False)):
+        sv = Solver(n, n, c=4.0, omega=2.0, material="gent", storage="f32", mu=0.1, lam=0.2,
+                    law_k=(jm, 0.0, 0.0))
+        sv.init(np.zeros((2, n, n)), u0)
+        sv.step(0)
+        torch.cuda.synchronize()
+        assert bool(sv.faults() & 1) == expect, (jm, sv.faults())
