@@ -155,3 +155,72 @@ def test_periodic_1024_fp32_against_fp64_20000_steps():
     ev, eF, eu = _rel(U32[:2], U64[:2]), _rel(U32[2:], U64[2:]), _rel(u32, u64)
     print(f"\n[periodic 1024 f32 vs f64, 20000 steps] v={ev:.2e} F-I={eF:.2e} u={eu:.2e}")
     assert ev <= 3e-5 and eF <= 3e-5 and eu <= 1e-5
+
+
+def test_largest_fp32_grid_windows():
+    """The largest FP32 grid one MI355X holds, ragged in x: 32700 x 32768 nodes
+    (1.07e9; two population buffers of 103 GB, u* 17 GB), periodic, 16 steps.  Buffer
+    offsets pass 2^32 elements, so every index of the step kernel must be 64-bit.  The
+    stored populations of sampled windows (the corners, the ragged x wrap and random
+    places) are read straight from the tiled buffers and compared with the oracle's
+    post-collision populations on a periodic window with a k + 2 margin.  The initial
+    velocity is a sum of three periodic plane waves (amplitude 5e-3), built on the
+    device; the oracle takes the same values read back.  Bar: 1e-5 relative L2."""
+    from oracle import lbm
+    from paper_2605_26677_amd.solver import Solver
+    nx, ny, steps, win = 32700, 32768, 16, 24
+    margin = steps + 2
+    dev = "cuda"
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    sv = Solver(nx, ny, c=2.0, omega=2.0, material="lognh", storage="f32", mu=0.1, lam=0.2)
+    rng = np.random.default_rng(11)
+    modes = [(int(rng.integers(1, 40)), int(rng.integers(1, 40)), float(rng.uniform(0, 2 * np.pi))) for _ in range(3)]
+
+    def v0_block(ys, xs):
+        Y, X = np.meshgrid(ys.astype(np.float64), xs.astype(np.float64), indexing="ij")
+        out = np.zeros((2,) + Y.shape)
+        for i, (kx, ky, ph) in enumerate(modes):
+            w = 2 * np.pi * (kx * (X + 0.5) / nx + ky * (Y + 0.5) / ny) + ph
+            out[i % 2] += 5e-3 * np.sin(w)
+        return out
+
+    v0 = torch.zeros((2, ny, nx), dtype=torch.float64, device=dev)
+    X = torch.arange(nx, dtype=torch.float64, device=dev)[None, :]
+    rows = 2048
+    for y0 in range(0, ny, rows):
+        Y = torch.arange(y0, min(ny, y0 + rows), dtype=torch.float64, device=dev)[:, None]
+        for i, (kx, ky, ph) in enumerate(modes):
+            w = 2 * np.pi * (kx * (X + 0.5) / nx + ky * (Y + 0.5) / ny) + ph
+            v0[i % 2, y0:y0 + rows] += 5e-3 * torch.sin(w)
+    sv.init(v0)
+    del v0
+    torch.cuda.empty_cache()
+    for k in range(steps):
+        sv.step(k)
+    torch.cuda.synchronize()
+    assert sv.faults() == 0
+    T = (nx + 63) // 64
+    pop = sv.pop[sv.s.cur].view(torch.float32)
+    starts = [(0, 0), (ny - win, nx - win), (100, nx - 10), (ny - 7, 5)] + \
+             [(int(rng.integers(0, ny - win)), int(rng.integers(0, nx - win))) for _ in range(2)]
+    for (y0, x0) in starts:
+        ys = (np.arange(win) + y0) % ny
+        xs = (np.arange(win) + x0) % nx
+        p = np.arange(24)
+        idx = ((ys[None, :, None] * T + xs[None, None, :] // 64) * 24 + p[:, None, None]) * 64 + xs[None, None, :] % 64
+        g = pop[torch.from_numpy(idx.reshape(-1)).to(dev)].double().cpu().numpy().reshape(4, 6, win, win)
+        size = win + 2 * margin
+        wy = (np.arange(size) + y0 - margin) % ny
+        wx = (np.arange(size) + x0 - margin) % nx
+        pb = lbm.Problem(nx=size, ny=size, c=2.0, omega=2.0, law="lognh", mu=0.1, lam=0.2)
+        st = lbm.initial_state(pb, v0_block(wy, wx))
+        lbm.run(pb, st, steps)
+        fo = lbm.post_collision(pb, st)[:, :, margin:margin + win, margin:margin + win].copy()
+        fo[:, 2] -= 0.25
+        fo[:, 5] -= 0.25
+        err = float(np.sqrt(((g - fo) ** 2).sum() / (fo ** 2).sum()))
+        print(f"\n[largest grid {nx}x{ny} f32 window at {y0},{x0}] populations rel L2 {err:.2e}")
+        assert err <= 1e-5
+    del sv, pop
+    torch.cuda.empty_cache()

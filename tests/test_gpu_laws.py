@@ -172,3 +172,37 @@ def test_gent_locking_limit_is_reported():
         sv.step(0)
         torch.cuda.synchronize()
         assert bool(sv.faults() & 1) == expect, (jm, sv.faults())
+
+
+@pytest.mark.parametrize("law", ALL_LAWS)
+@pytest.mark.parametrize("storage,bar", [("f64", 1e-11), ("f32", 1e-5)])
+def test_diagnostics_at_finite_strain(law, storage, bar):
+    """lbm_diagnostics on F = I + grad u0 with |F - I| ~ 0.2: sum of F - I, energy
+    sum(|v|^2/2 + W(F)) dx^2, min J, max |F - I| and the tangent-speed audit
+    max_X max_n sqrt(lam_max(Q(n; F))) / c over the same 180 one-degree directions,
+    against the oracle."""
+    from oracle import lbm
+    from oracle import material as mat
+    nx, ny = 72, 40
+    mu, lam, c, dx = 0.5, 0.7, 8.0, 0.05
+    # displacement in units of dx, so that |F - I| ~ 0.2 whatever the spacing
+    u0 = dx * np.stack([li.gaussian_random_field(nx, ny, 21, 0.12), li.gaussian_random_field(nx, ny, 22, 0.12)])
+    v0 = np.stack([li.gaussian_random_field(nx, ny, 23, 1e-2), li.gaussian_random_field(nx, ny, 24, 1e-2)])
+    sv = _solver(law, storage, nx, ny, c=c, omega=2.0, dx=dx, mu=mu, lam=lam)
+    sv.init(v0, u0)
+    d = sv.diagnostics().cpu().numpy()
+    torch.cuda.synchronize()
+    pb = lbm.Problem(nx=nx, ny=ny, c=c, omega=2.0, law=oracle_law(law), mu=mu, lam=lam, dx=dx)
+    st = lbm.initial_state(pb, v0, u0)
+    U, _ = lbm.observe(pb, st)
+    do = lbm.diagnostics(pb, U)
+    F = lbm.F_of(U)
+    audit = float(mat.max_tangent_speed(oracle_law(law), F, mu, lam, dtheta_deg=1.0).max()) / c
+    rel = lambda a, b: abs(a - b) / abs(b)
+    # sum of F - I of a periodic displacement vanishes up to rounding: compare it on the
+    # scale of its terms (node count times max |F - I|)
+    errs = dict(sumFt=float(np.abs(d[2:6] - do["sumFt"]).max() / (nx * ny * do["maxFt"])),
+                energy=rel(d[6], do["energy"]), minJ=abs(d[7] - do["minJ"]), maxFt=rel(d[8], do["maxFt"]),
+                audit=rel(d[9], audit))
+    print(f"\n[diagnostics {law} {storage}] audit {d[9]:.6f} " + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+    assert max(errs.values()) <= bar, errs
