@@ -23,8 +23,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12          # MI355X HBM3E peak, bytes/s
 METRIC = "MLUPS fwd & fwd+adjoint at 8192², FP32 vs FP64, % of HBM roofline"
-# algorithmic bytes per lattice update of one step (24 populations read + written, u*)
-BYTES_PER_LU = {"f32": 96 + 96 + 32, "f16": 48 + 48 + 32, "f64": 192 + 192 + 32}
+# algorithmic bytes per lattice update of one step, averaged over the 16-step cycle of the
+# displacement accumulator: 24 populations read + written; u* = U + S with S (float)
+# read + written every step and U (double) read + written every 16th step (FP64: u* read
+# + written every step)
+BYTES_PER_LU = {"f32": 96 + 96 + 16 + 32 / 16, "f16": 48 + 48 + 16 + 32 / 16, "f64": 192 + 192 + 32}
 
 
 PROFILE_PMC = os.path.join(ROOT, "profiles", "step_f32_lognh_periodic_8192_pmc.txt")

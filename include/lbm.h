@@ -109,10 +109,13 @@ typedef struct {
     void *pop[2];              /* device: two population buffers of lbm_pop_bytes() each */
     int32_t cur;               /* index of the buffer that holds the current level */
     void *ustar;               /* device, lbm_ustar_bytes(): u* of eq:trapezoid-u, tiled;
-                                  F32/F16: 4 float planes (hi1, hi2, c1, c2), u* = hi - c
-                                  (compensated summation); F64: 2 double planes.  May be
-                                  NULL for lbm_step (the quadrature is then skipped, as in
-                                  a replay for the adjoint) but not for lbm_init or
+                                  F64: 2 double planes.  F32/F16: u* = U + S with S 2 float
+                                  planes (tiled, first) and U 2 double planes (tiled, after
+                                  S): each step adds dt v to S, and the step n -> n+1 with
+                                  (n + 1) % 16 == 0 moves S into U, so S never sums more
+                                  than 16 increments in FP32 (n should count levels).  May
+                                  be NULL for lbm_step (the quadrature is then skipped, as
+                                  in a replay for the adjoint) but not for lbm_init or
                                   lbm_displacement */
     const float *mu, *lam;     /* device: per-node Lame fields (1 plane each), or NULL for mu0/lam0 */
     double mu0, lam0;          /* uniform values used when the field pointer is NULL */

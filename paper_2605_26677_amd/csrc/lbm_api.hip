@@ -106,7 +106,8 @@ size_t lbm_padded_nodes(const lbm_params* p) {
 size_t lbm_pop_bytes(const lbm_params* p) { return 24 * lbm_padded_nodes(p) * pop_elem_size(p); }
 
 size_t lbm_ustar_bytes(const lbm_params* p) {
-    return p->storage == LBM_F64_PLAIN ? 2 * lbm_padded_nodes(p) * 8 : 4 * lbm_padded_nodes(p) * 4;
+    // FP64: 2 double planes; shifted storages: 2 float planes S and 2 double planes U
+    return p->storage == LBM_F64_PLAIN ? 2 * lbm_padded_nodes(p) * 8 : lbm_padded_nodes(p) * (2 * 4 + 2 * 8);
 }
 
 size_t lbm_aux_bytes(const lbm_params* p) { return (size_t)(2 * p->nx + 2 * p->ny) * 4 * 8; }
@@ -180,7 +181,6 @@ lbm_status lbm_init(const lbm_params* p, lbm_state* s, const double* v0, const d
 
 lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, double r_np1,
                     const lbm_edge_data* at_half, void* record, void* stream) {
-    (void)n;
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
     if ((st = check_state(p, s, false)) != LBM_OK) return st;
@@ -206,6 +206,7 @@ lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, do
     a.ustar = s->ustar;
     a.aux = s->aux;
     a.record = record;
+    a.fold = (n + 1) % kUstarBlock == 0;
     a.r_np1 = r_np1;
     a.ed = ed;
     if (launch_step(a, hs) != hipSuccess) return LBM_ERR_LAUNCH;

@@ -457,6 +457,26 @@ __host__ __device__ __forceinline__ int64_t tile_base(int ntile, int np, int x, 
     return ((int64_t(y) * ntile + (x >> 6)) * np) * kTile + (x & (kTile - 1));
 }
 
+// Displacement accumulator of the shifted storages (F32, F16): u* = U + S, with S two
+// tiled float planes that collect dt v over at most kUstarBlock steps and U two tiled
+// double planes (after the S planes) that receive S at the steps n -> n+1 with
+// (n + 1) % kUstarBlock == 0.  S restarts from zero every block, so its rounding stays on
+// the scale of one block's increment while U keeps the sum exact to FP64; a step moves
+// 16 bytes per node instead of the 32 of a compensated float pair.
+constexpr int kUstarBlock = 16;
+
+struct UstarRefs {
+    float* S;
+    double* U;
+};
+__host__ __device__ __forceinline__ UstarRefs ustar_refs(void* base, int ntile, int ny, int x, int y) {
+    const int64_t padded = int64_t(ntile) * kTile * ny;
+    UstarRefs r;
+    r.S = (float*)base + tile_base(ntile, 2, x, y);
+    r.U = (double*)((float*)base + 2 * padded) + tile_base(ntile, 2, x, y);
+    return r;
+}
+
 // Store that bypasses the caches' allocate-on-write (each value is written once per pass).
 template <typename T> __device__ __forceinline__ void store_stream(T* p, T v) {
     __builtin_nontemporal_store(v, p);

@@ -208,16 +208,17 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
         store_stream(us, us[0] + dt * U[0]);
         store_stream(us + kTile, us[kTile] + dt * U[1]);
     } else {
-        float* us = (float*)a.ustar + tile_base(ntile, 4, x, y);
+        // u* = U + S: S += dt v; at a block boundary S moves into U (ustar_refs)
+        const UstarRefs r = ustar_refs(a.ustar, ntile, ny, x, y);
 #pragma unroll
         for (int cpt = 0; cpt < 2; ++cpt) {
-            const float hi = us[cpt * kTile];
-            float cc = us[(2 + cpt) * kTile];
-            const float yv = float(dt * U[cpt]) - cc;
-            const float t = hi + yv;
-            cc = (t - hi) - yv;
-            store_stream(us + cpt * kTile, t);
-            store_stream(us + (2 + cpt) * kTile, cc);
+            const float sn = r.S[cpt * kTile] + float(dt * U[cpt]);
+            if (a.fold) {
+                store_stream(r.U + cpt * kTile, r.U[cpt * kTile] + double(sn));
+                store_stream(r.S + cpt * kTile, 0.0f);
+            } else {
+                store_stream(r.S + cpt * kTile, sn);
+            }
         }
     }
 
@@ -278,8 +279,8 @@ __global__ void __launch_bounds__(kBlock) recover_kernel(RecoverArgs a) {
             if constexpr (ST == LBM_F64_PLAIN) {
                 ustar = ((const double*)a.ustar)[tile_base(cm.ntile, 2, x, y) + cpt * kTile];
             } else {
-                const float* us = (const float*)a.ustar + tile_base(cm.ntile, 4, x, y);
-                ustar = double(us[cpt * kTile]) - double(us[(2 + cpt) * kTile]);
+                const UstarRefs r = ustar_refs(const_cast<void*>(a.ustar), cm.ntile, cm.ny, x, y);
+                ustar = r.U[cpt * kTile] + double(r.S[cpt * kTile]);
             }
             out[cpt * n + idx] = ustar - hdt * double(U[cpt]);
         }
@@ -555,10 +556,9 @@ __global__ void __launch_bounds__(kBlock) init_pop_kernel(InitArgs a) {
         if constexpr (ST == LBM_F64_PLAIN) {
             ((double*)a.ustar)[tile_base(cm.ntile, 2, x, y) + cpt * kTile] = us1;
         } else {
-            float* us = (float*)a.ustar + tile_base(cm.ntile, 4, x, y);
-            const float hi = float(us1);
-            us[cpt * kTile] = hi;
-            us[(2 + cpt) * kTile] = float(double(hi) - us1);
+            const UstarRefs r = ustar_refs(a.ustar, cm.ntile, cm.ny, x, y);
+            r.U[cpt * kTile] = us1;
+            r.S[cpt * kTile] = 0.0f;
         }
     }
     bool bad = !(J > 0.0);

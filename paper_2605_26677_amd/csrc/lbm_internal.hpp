@@ -49,6 +49,7 @@ struct StepArgs {
     void* ustar;
     const void* aux;                 // F^b per traction link (compute type, 4 per link)
     void* record;                    // U^{n+1} or NULL
+    int fold;                        // shifted storages: move S into U this step (ustar_refs)
     double r_np1;
     EdgeData ed;                     // data at t^{n+1/2}
 };

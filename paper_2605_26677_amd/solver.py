@@ -74,8 +74,9 @@ class StepGraph:
     of field tensors, which the graph keeps alive), record buffers, and the two population
     buffers in the order they had then.  ``replay`` therefore requires the solver to hold
     the same current buffer as at capture, and afterwards sets it to the buffer the
-    sequence ends in.  The library records no memset and allocates nothing, so its
-    launches are capture-safe; the capture itself executes nothing."""
+    sequence ends in.  The fold of the displacement accumulator (every 16th level) is
+    frozen with the step indices.  The library records no memset and allocates nothing,
+    so its launches are capture-safe; the capture itself executes nothing."""
 
     def __init__(self, solver, steps):
         self.sv = solver
@@ -228,7 +229,9 @@ class Solver:
 
         graph, proto = None, None
         n, end = n0, n0 + count
-        block += block % 2          # keep the buffer parity of a replay
+        # whole multiples of 16 steps keep both the buffer parity and the phase of the
+        # displacement accumulator's 16-step fold (lbm.h, lbm_state.ustar)
+        block = max(16, -(-block // 16) * 16)
         while n < end:
             blk = [args(m) for m in range(n, min(end, n + block))]
             if len(blk) == block and graph is None and self._graph_ok(blk):

@@ -42,7 +42,7 @@ def test_sizes():
     p = _params(8192, 8192)
     assert lib.lbm_padded_nodes(ctypes.byref(p)) == 8192 * 8192
     assert lib.lbm_pop_bytes(ctypes.byref(p)) == 24 * 8192 * 8192 * 4
-    assert lib.lbm_ustar_bytes(ctypes.byref(p)) == 4 * 8192 * 8192 * 4
+    assert lib.lbm_ustar_bytes(ctypes.byref(p)) == (2 * 4 + 2 * 8) * 8192 * 8192   # S float + U double
     assert lib.lbm_record_bytes(ctypes.byref(p)) == 6 * 8192 * 8192 * 4
     p64 = _params(100, 37, storage=L.LBM_F64_PLAIN)
     assert lib.lbm_padded_nodes(ctypes.byref(p64)) == 128 * 37        # rows padded to whole tiles

@@ -225,10 +225,12 @@ def test_step_graph_replays_match_eager(kinds, storage):
     graph = make_solver(case, storage)
     for sv in (eager, graph):
         sv.init(case.v0, r0=1.0)
-        sv.step(0, edges=data)                 # loads the kernels before any capture
-    g = graph.capture([dict(n=m, edges=data) for m in range(1, 11)])
+        for m in range(16):                    # also loads the kernels before any capture
+            sv.step(m, edges=data)
+    # a block of 16 levels: replays keep the phase of the 16-level displacement fold
+    g = graph.capture([dict(n=m, edges=data) for m in range(16, 32)])
     for rep in range(4):
-        for m in range(1 + 10 * rep, 11 + 10 * rep):
+        for m in range(16 + 16 * rep, 32 + 16 * rep):
             eager.step(m, edges=data)
         g.replay()
         Ue, Ug = eager.moments(), graph.moments()
