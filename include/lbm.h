@@ -244,10 +244,19 @@ typedef struct {
     int32_t nprobe;
     int64_t nsteps;            /* N, the level at which u^N enters the loss */
     void *aux;                 /* device, lbm_aux_bytes(): traction-wall adjoint staging */
+    void *gsum;                /* device, lbm_adj_sum_bytes(), zero-filled by the caller before
+                                  m = N - 1; F32/F16 storage only (FP64 storage adds to the
+                                  gradients directly), required there when any gradient
+                                  pointer is set.  The bulk parts of dL/dmu, dL/dlam, dL/db are
+                                  summed here in FP32 (4 tiled planes) and moved into the FP64
+                                  gradients at every level m with m % 16 == 0, which includes
+                                  the last step m = 0; it is zero again after that step */
 } lbm_adj_state;
 
 /* Bytes of one adjoint population buffer (24 tiled planes of the compute type). */
 size_t lbm_adj_bytes(const lbm_params *p);
+/* Bytes of the FP32 gradient block sums (lbm_adj_state.gsum). */
+size_t lbm_adj_sum_bytes(const lbm_params *p);
 
 /* One step of the hand-written adjoint of lbm_step, level m (reverse of eq:collision
  * and eq:streaming with the Jacobian actions eq:jacobian-actions and eq:feq-derivative):
@@ -256,7 +265,9 @@ size_t lbm_adj_bytes(const lbm_params *p);
  * eq:boundary-general, traction links also through the boundary Newton solve by the
  * implicit function theorem), dL/dU^m = omega sum_q (f^eq_q)'^T lambda*^m_q + probe and
  * wall sources, lambda^m = (1 - omega) lambda*^m + dL/dU^m into a->adj[1 - a->cur], and
- * adds this level's parts of dL/dmu, dL/dlam, dL/db.  Flips a->cur.
+ * adds this level's parts of dL/dmu, dL/dlam, dL/db (bulk parts through a->gsum, see
+ * there; the steps must run m = N-1, ..., 0 for the block sums to be folded).  Flips
+ * a->cur.
  *   fwd: the forward state (parameters mu, lam, body; pop/ustar are not read).
  *   r_m: body factor at level m.  at_half: boundary data at t^{m+1/2} (step m -> m+1).
  *   record_m: device, U^m as written by lbm_step(record) or lbm_record_state. */

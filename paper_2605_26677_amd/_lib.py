@@ -55,6 +55,7 @@ class lbm_adj_state(ctypes.Structure):
     _fields_ = [
         ("adj", c_vp * 2), ("cur", c_i32), ("g_mu", c_vp), ("g_lam", c_vp), ("g_body", c_vp),
         ("probe", c_vp), ("ubar", c_vp), ("nprobe", c_i32), ("nsteps", c_i64), ("aux", c_vp),
+        ("gsum", c_vp),
     ]
 
 
@@ -67,6 +68,7 @@ SIGNATURES = {
     "lbm_aux_bytes": (ctypes.c_size_t, [P(lbm_params)]),
     "lbm_record_bytes": (ctypes.c_size_t, [P(lbm_params)]),
     "lbm_adj_bytes": (ctypes.c_size_t, [P(lbm_params)]),
+    "lbm_adj_sum_bytes": (ctypes.c_size_t, [P(lbm_params)]),
     "lbm_diag_scratch_bytes": (ctypes.c_size_t, [P(lbm_params)]),
     "lbm_check_params": (c_i32, [P(lbm_params)]),
     "lbm_check_cfl": (c_i32, [P(lbm_params), c_dbl, c_dbl]),

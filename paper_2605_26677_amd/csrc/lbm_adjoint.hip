@@ -94,20 +94,41 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) store_stream(dst + own + (6 * q + k) * kTile, omc * l[q][k] + gU[k]);
 
-    // parameter gradients of this level's collision
+    // parameter gradients of this level's collision.  FP64 storage adds them to the FP64
+    // gradients directly; the shifted storages sum them in FP32 per block (gsum, 4 tiled
+    // planes mu, lam, b1, b2) and move the block sums into the FP64 gradients at the
+    // levels m with m % kGradBlock == 0 (the last adjoint step, m = 0, always folds)
     const R hc = R(0.5 / cm.c);
+    R inc[4] = {R(0), R(0), R(0), R(0)};
     if (a.g_mu || a.g_lam) {
         R Pm[4], Pl[4];
         piola_partials<R, LAW, true>(ft, law_consts<R>(cm), Pm, Pl);
-        if (a.g_mu)
-            a.g_mu[idx] += double(om * hc * -(dxl[0] * Pm[0] + dxl[1] * Pm[2] + dyl[0] * Pm[1] + dyl[1] * Pm[3]));
-        if (a.g_lam)
-            a.g_lam[idx] += double(om * hc * -(dxl[0] * Pl[0] + dxl[1] * Pl[2] + dyl[0] * Pl[1] + dyl[1] * Pl[3]));
+        inc[0] = om * hc * -(dxl[0] * Pm[0] + dxl[1] * Pm[2] + dyl[0] * Pm[1] + dyl[1] * Pm[3]);
+        inc[1] = om * hc * -(dxl[0] * Pl[0] + dxl[1] * Pl[2] + dyl[0] * Pl[1] + dyl[1] * Pl[3]);
     }
     if (a.g_body) {
-        const double hdt = 0.5 * cm.dt, srcw = cm.dt * (2.0 - cm.omega) * 0.125;
-        a.g_body[idx] += a.r_m * (hdt * double(gU[0]) + srcw * double(s6[0]));
-        a.g_body[n + idx] += a.r_m * (hdt * double(gU[1]) + srcw * double(s6[1]));
+        const R hdtr = R(0.5 * cm.dt), srcw = R(cm.dt * (2.0 - cm.omega) * 0.125), rm = R(a.r_m);
+        inc[2] = rm * (hdtr * gU[0] + srcw * s6[0]);
+        inc[3] = rm * (hdtr * gU[1] + srcw * s6[1]);
+    }
+    double* const g64[4] = {a.g_mu, a.g_lam, a.g_body, a.g_body ? a.g_body + n : nullptr};
+    if constexpr (ST == LBM_F64_PLAIN) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (g64[j]) g64[j][idx] += double(inc[j]);
+    } else if (g64[0] || g64[1] || g64[2]) {
+        float* gs = (float*)a.gsum + tile_base(ntile, 4, x, y);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!g64[j]) continue;
+            const float sj = gs[j * kTile] + float(inc[j]);
+            if (a.fold) {
+                g64[j][idx] += double(sj);
+                store_stream(gs + j * kTile, 0.0f);
+            } else {
+                store_stream(gs + j * kTile, sj);
+            }
+        }
     }
 }
 

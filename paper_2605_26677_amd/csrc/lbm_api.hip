@@ -116,6 +116,8 @@ size_t lbm_record_bytes(const lbm_params* p) { return 6 * lbm_padded_nodes(p) * 
 
 size_t lbm_adj_bytes(const lbm_params* p) { return 24 * lbm_padded_nodes(p) * real_size(p); }
 
+size_t lbm_adj_sum_bytes(const lbm_params* p) { return 4 * lbm_padded_nodes(p) * sizeof(float); }
+
 size_t lbm_diag_scratch_bytes(const lbm_params* p) {
     (void)p;
     return (size_t)kDiagBlocks * LBM_DIAG_COUNT * sizeof(double);
@@ -278,6 +280,8 @@ lbm_status lbm_adjoint_step(const lbm_params* p, const lbm_state* fwd, lbm_adj_s
     if (has_traction(p) && !adj->aux) return LBM_ERR_ARG;
     if (adj->nprobe < 0 || (adj->nprobe > 0 && (!adj->probe || !adj->ubar))) return LBM_ERR_ARG;
     if (m < 0 || m > adj->nsteps) return LBM_ERR_ARG;
+    if (p->storage != LBM_F64_PLAIN && (adj->g_mu || adj->g_lam || adj->g_body) && !adj->gsum)
+        return LBM_ERR_ARG;
     AdjArgs a{};
     a.cm = make_common(p, fwd);
     a.src = adj->adj[adj->cur];
@@ -286,6 +290,8 @@ lbm_status lbm_adjoint_step(const lbm_params* p, const lbm_state* fwd, lbm_adj_s
     a.g_mu = adj->g_mu;
     a.g_lam = adj->g_lam;
     a.g_body = adj->g_body;
+    a.gsum = adj->gsum;
+    a.fold = m % kGradBlock == 0;
     a.aux = adj->aux;
     a.r_m = r_m;
     a.ed = make_edges(at_half);

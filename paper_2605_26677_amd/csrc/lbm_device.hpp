@@ -464,6 +464,9 @@ __host__ __device__ __forceinline__ int64_t tile_base(int ntile, int np, int x, 
 // the scale of one block's increment while U keeps the sum exact to FP64; a step moves
 // 16 bytes per node instead of the 32 of a compensated float pair.
 constexpr int kUstarBlock = 16;
+// Levels per FP32 block sum of the adjoint's parameter gradients (same scheme: the FP64
+// gradient receives a block sum every kGradBlock levels).
+constexpr int kGradBlock = 16;
 
 struct UstarRefs {
     float* S;

@@ -92,6 +92,8 @@ struct AdjArgs {
     double* g_mu;
     double* g_lam;
     double* g_body;
+    void* gsum;                      // FP32 block sums of the gradients (4 tiled planes)
+    int fold;                        // move the block sums into the FP64 gradients
     void* aux;
     double r_m;
     EdgeData ed;

@@ -56,6 +56,7 @@ def _sizes(nx, ny, storage):
     nodes = int(nx) * int(ny)
     return dict(pop=lib.lbm_pop_bytes(ctypes.byref(p)), rec=lib.lbm_record_bytes(ctypes.byref(p)),
                 ustar=lib.lbm_ustar_bytes(ctypes.byref(p)), adj=lib.lbm_adj_bytes(ctypes.byref(p)),
+                gsum=lib.lbm_adj_sum_bytes(ctypes.byref(p)),
                 aux=lib.lbm_aux_bytes(ctypes.byref(p)), nodes=nodes)
 
 
@@ -63,7 +64,8 @@ def memory_model(nx, ny, storage, nsteps, levels, leaf_bytes_per_node=48):
     """Peak device bytes of ``rollout`` with nested segment lengths ``levels`` (outermost
     first; [K] is every-K), as the sum of
       fixed:     two population buffers, u*, the float32 mu, lam, b planes, the FP64 v0,
-                 u and gradient planes, two adjoint buffers, and the caller's leaf tensors
+                 u and gradient planes, two adjoint buffers and the gradient block sums,
+                 and the caller's leaf tensors
                  (leaf_bytes_per_node: FP64 mu, lam, b, v0 = 48);
       snapshots: the forward's floor(N / K0) + 1 (f*, record) pairs, plus, while the
                  first top segment is reversed, ceil(K_{l-1} / K_l) - 1 more per level;
@@ -71,7 +73,7 @@ def memory_model(nx, ny, storage, nsteps, levels, leaf_bytes_per_node=48):
     z = _sizes(nx, ny, storage)
     n, N = z["nodes"], int(nsteps)
     fixed = (2 * z["pop"] + z["ustar"] + 2 * z["aux"] + 16 * n + 16 * n + 16 * n
-             + 2 * z["adj"] + 48 * n + leaf_bytes_per_node * n)
+             + 2 * z["adj"] + z["gsum"] + 48 * n + leaf_bytes_per_node * n)
     pair = z["pop"] + z["rec"]
     K = [int(k) for k in levels]
     snaps = (N // K[0] + 1) * pair
@@ -137,6 +139,7 @@ class _Adjoint:
         self.g_body = torch.zeros(2 * n, dtype=torch.float64, device=dev)
         self.g_v0 = torch.zeros(2 * n, dtype=torch.float64, device=dev)
         self.aux = torch.zeros(sv.lib.lbm_aux_bytes(ctypes.byref(sv.p)), dtype=torch.uint8, device=dev)
+        self.gsum = torch.zeros(sv.lib.lbm_adj_sum_bytes(ctypes.byref(sv.p)), dtype=torch.uint8, device=dev)
         self.probe = cfg.probes.to(device=dev, dtype=torch.int32).contiguous()
         self.ubar = ubar.to(device=dev, dtype=torch.float64).contiguous()
         a = L.lbm_adj_state()
@@ -147,6 +150,7 @@ class _Adjoint:
         a.nprobe = int(self.probe.numel())
         a.nsteps = int(cfg.nsteps)
         a.aux = self.aux.data_ptr()
+        a.gsum = self.gsum.data_ptr()
         self.a = a
 
     def step(self, sv, cfg, m, record):
