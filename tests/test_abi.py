@@ -139,3 +139,21 @@ def test_calls_reject_missing_buffers():
                                 None) == L.LBM_ERR_ARG
     for st in range(5):
         assert lib.lbm_status_string(st)
+
+
+def test_adjoint_step_requires_block_sums_for_shifted_storage():
+    """Gradients of a F32/F16 adjoint step are summed through lbm_adj_state.gsum: a call
+    with a gradient pointer and no gsum is refused before any launch; FP64 storage adds to
+    the gradients directly and needs none."""
+    lib = L.lib()
+    fake = 256                       # never dereferenced: argument checks come first
+    s = L.lbm_state()
+    s.pop[0], s.pop[1], s.fault = fake, fake, fake
+    a = L.lbm_adj_state()
+    a.adj[0], a.adj[1] = fake, fake
+    a.g_mu = fake
+    a.nsteps = 10
+    p = _params()
+    assert lib.lbm_adj_sum_bytes(ctypes.byref(p)) == 4 * 64 * 64 * 4
+    assert lib.lbm_adjoint_step(ctypes.byref(p), ctypes.byref(s), ctypes.byref(a), 3, 1.0, None,
+                                ctypes.c_void_p(fake), None) == L.LBM_ERR_ARG
