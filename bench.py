@@ -342,6 +342,16 @@ def main():
         res[storage] = dict(ms_per_step=ms, mlups=mlups, algorithmic_GBps=gbs,
                             frac_hbm=gbs * 1e9 / PEAK_HBM, faults=faults, steps=steps)
         log(f"bench: {storage}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {gbs:.0f} GB/s")
+    if "f32" in only:
+        # the St. Venant-Kirchhoff variant of the same workload (FP32 storage)
+        steps = args.variant_steps
+        log(f"bench: timing svk f32 forward, {steps} steps")
+        ms, faults = time_forward(n, "f32", steps, args.warmup, v0, law="svk")
+        mlups = n * n / (ms * 1e-3) / 1e6
+        gbs = BYTES_PER_LU["f32"] * n * n / (ms * 1e-3) / 1e9
+        res["svk_f32"] = dict(ms_per_step=ms, mlups=mlups, algorithmic_GBps=gbs, frac_hbm=gbs * 1e9 / PEAK_HBM,
+                              faults=faults, steps=steps)
+        log(f"bench: svk f32: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {gbs:.0f} GB/s")
     log("bench: launch-bound grid, eager vs captured graph")
     res["launch_bound_256"] = time_launch_bound()
     log(f"bench: launch-bound: {res['launch_bound_256']}")
