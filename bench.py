@@ -182,7 +182,7 @@ def time_forward_adjoint(n, steps, K, nprobe=16):
                 bwd_over_fwd=t_b / t_f, peak_mem_GiB=mem, grads_finite=ok, steps=steps, K=K, c=c)
 
 
-def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0):
+def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0, host_gib=0.0):
     """The large adjoint workload: n x n, velocity wall (v = 0) at the bottom, traction
     (0, -2e-4 min(1, t/(2000 dt))) on the top evaluated at t^{m+1/2}, traction-free sides,
     per-node log-NH mu, lam log-normal fields (median 0.1 / 0.4, sigma_log 0.3, correlation
@@ -194,11 +194,12 @@ def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0):
     and the relative error of directional derivatives against FP64 central differences."""
     import torch
     import lbm_inputs as li
-    from paper_2605_26677_amd.rollout import RolloutConfig, checkpoint_plan, memory_model, rollout
+    from paper_2605_26677_amd.rollout import RolloutConfig, plan_checkpoints, rollout
     budget = int(budget_gib * 2 ** 30)
-    levels = checkpoint_plan(n, n, "f32", steps, budget)
-    model = memory_model(n, n, "f32", steps, levels)
-    log(f"bench: adjoint at scale {n}^2 x {steps}, levels {levels}, model peak {model['peak'] / 2**30:.1f} GiB")
+    plan = plan_checkpoints(n, n, "f32", steps, budget, int(host_gib * 2 ** 30))
+    levels, host_top, model = plan["levels"], plan["host_top"], plan["model"]
+    log(f"bench: adjoint at scale {n}^2 x {steps}, levels {levels}, outer level on host {host_top}, "
+        f"model device peak {model['peak'] / 2**30:.1f} GiB, host {model['host'] / 2**30:.1f} GiB")
     mu0 = li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0)
     lam0 = li.lognormal_field(n, n, 402, 0.4, 0.3, 32.0)
     ys, xs = li.random_probes(n, n, 256, 405)
@@ -218,7 +219,7 @@ def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0):
     v0 = torch.zeros((2, n, n), dtype=torch.float64, device=dev, requires_grad=True)
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     e0.record()
-    u = rollout(mu, lam, body, v0, RolloutConfig(storage="f32", levels=levels, **common))
+    u = rollout(mu, lam, body, v0, RolloutConfig(storage="f32", levels=levels, host_top=host_top, **common))
     e1.record()
     torch.cuda.synchronize()
     log(f"bench: forward done, {e0.elapsed_time(e1) / 1e3:.1f} s")
@@ -254,7 +255,8 @@ def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0):
         an = sum((g[k] * (plus[k] - minus[k])).sum() for k in base)
         errs.append(abs(fd - an) / abs(fd))
         log(f"bench: FD {fd:.6e} adjoint {an:.6e} rel {errs[-1]:.2e}")
-    return dict(grid=[n, n], steps=steps, levels=levels, budget_GiB=budget_gib,
+    return dict(grid=[n, n], steps=steps, levels=levels, host_top=host_top, budget_GiB=budget_gib,
+                host_budget_GiB=host_gib, model_host_GiB=model["host"] / 2 ** 30,
                 model_peak_GiB=model["peak"] / 2 ** 30, peak_mem_GiB=peak / 2 ** 30,
                 forward_passes=model["forward_passes"], ms_fwd=t_f, ms_bwd=t_b, bwd_over_fwd=t_b / t_f,
                 mlups=n * n * steps / ((t_f + t_b) * 1e-3) / 1e6, fd_rel_err=errs, c=c)
@@ -315,6 +317,8 @@ def main():
     ap.add_argument("--scale-steps", type=int, default=20000)
     ap.add_argument("--scale-budget-gib", type=float, default=64.0)
     ap.add_argument("--scale-fd-dirs", type=int, default=1)
+    ap.add_argument("--scale-host-gib", type=float, default=48.0,
+                    help="pinned host memory for the outermost checkpoints (0: device only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
@@ -326,7 +330,8 @@ def main():
         profile_run(n, 20)
         return
     if args.adjoint_at_scale:
-        r = adjoint_at_scale(args.scale_size, args.scale_steps, args.scale_budget_gib, args.scale_fd_dirs)
+        r = adjoint_at_scale(args.scale_size, args.scale_steps, args.scale_budget_gib, args.scale_fd_dirs,
+                             host_gib=args.scale_host_gib)
         print(json.dumps({"adjoint_at_scale": r}), flush=True)
         return
     log(f"bench: generating {n}x{n} inputs")

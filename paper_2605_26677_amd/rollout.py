@@ -47,6 +47,7 @@ class RolloutConfig:
     newton_max_iter: int = 0
     law_k: Optional[Sequence[float]] = None            # invariant-law constants (lbm.h law_k)
     Fbar: Optional[Sequence[Sequence[float]]] = None   # uniform predeformation at t = 0
+    host_top: bool = False                             # outermost snapshots in pinned host memory
 
 
 def _sizes(nx, ny, storage):
@@ -60,7 +61,7 @@ def _sizes(nx, ny, storage):
                 aux=lib.lbm_aux_bytes(ctypes.byref(p)), nodes=nodes)
 
 
-def memory_model(nx, ny, storage, nsteps, levels, leaf_bytes_per_node=48):
+def memory_model(nx, ny, storage, nsteps, levels, leaf_bytes_per_node=48, host_top=False):
     """Peak device bytes of ``rollout`` with nested segment lengths ``levels`` (outermost
     first; [K] is every-K), as the sum of
       fixed:     two population buffers, u*, the float32 mu, lam, b planes, the FP64 v0,
@@ -69,19 +70,22 @@ def memory_model(nx, ny, storage, nsteps, levels, leaf_bytes_per_node=48):
                  (leaf_bytes_per_node: FP64 mu, lam, b, v0 = 48);
       snapshots: the forward's floor(N / K0) + 1 (f*, record) pairs, plus, while the
                  first top segment is reversed, ceil(K_{l-1} / K_l) - 1 more per level;
-      records:   K_last + 1 records for the innermost replay."""
+      records:   K_last + 1 records for the innermost replay.
+    With host_top the forward's snapshots (the outermost level) live in pinned host
+    memory instead (``host`` bytes) and leave the device."""
     z = _sizes(nx, ny, storage)
     n, N = z["nodes"], int(nsteps)
     fixed = (2 * z["pop"] + z["ustar"] + 2 * z["aux"] + 16 * n + 16 * n + 16 * n
              + 2 * z["adj"] + z["gsum"] + 48 * n + leaf_bytes_per_node * n)
     pair = z["pop"] + z["rec"]
     K = [int(k) for k in levels]
-    snaps = (N // K[0] + 1) * pair
+    top = (N // K[0] + 1) * pair
+    snaps = 0 if host_top else top
     for a, b in zip(K[:-1], K[1:]):
         snaps += (math.ceil((a + 1) / b) - 1) * pair
     records = (K[-1] + 1) * z["rec"]
     return dict(fixed=fixed, snapshots=snaps, records=records, peak=fixed + snaps + records,
-                forward_passes=len(K) + 1)
+                host=top if host_top else 0, forward_passes=len(K) + 1)
 
 
 def checkpoint_plan(nx, ny, storage, nsteps, budget_bytes, max_depth=8, leaf_bytes_per_node=48):
@@ -120,6 +124,64 @@ def checkpoint_plan(nx, ny, storage, nsteps, budget_bytes, max_depth=8, leaf_byt
             return K
     raise ValueError(f"no nesting up to depth {max_depth} fits {budget_bytes / 2**30:.1f} GiB "
                      f"(best {best[0] / 2**30:.1f} GiB with levels {best[1]})")
+
+
+def plan_checkpoints(nx, ny, storage, nsteps, device_budget_bytes, host_budget_bytes=0, max_depth=8,
+                     leaf_bytes_per_node=48):
+    """Checkpoint schedule with the fewest forward replays whose device peak fits
+    device_budget_bytes, optionally keeping the outermost level in pinned host memory
+    (at most host_budget_bytes; one host-to-device copy of a snapshot per outer segment).
+    Returns dict(levels=[...], host_top=bool, model=memory_model(...))."""
+    N = int(nsteps)
+    best = None
+    for d in range(1, max_depth + 1):
+        options = []
+        try:
+            K = checkpoint_plan(nx, ny, storage, N, device_budget_bytes, max_depth=d,
+                                leaf_bytes_per_node=leaf_bytes_per_node)
+            if len(K) == d:
+                options.append((K, False))
+        except ValueError:
+            pass
+        if host_budget_bytes > 0:
+            z = _sizes(nx, ny, storage)
+            pair = z["pop"] + z["rec"]
+            k0_min = max(1, math.ceil(N / max(1, host_budget_bytes // pair - 1)))
+            for K0 in sorted({int(k0_min * f) for f in (1.0, 1.1, 1.25, 1.5, 2.0, 3.0, 4.0)} | {k0_min}):
+                if K0 > N:
+                    continue
+                if d == 1:
+                    K = [K0]
+                else:
+                    # inner levels split one outer segment as the device-only plan would
+                    try:
+                        inner = checkpoint_plan(nx, ny, storage, K0 + 1, device_budget_bytes, max_depth=d - 1,
+                                                leaf_bytes_per_node=leaf_bytes_per_node)
+                    except ValueError:
+                        continue
+                    if len(inner) != d - 1 or inner[0] >= K0:
+                        continue
+                    K = [K0] + inner
+                m = memory_model(nx, ny, storage, N, K, leaf_bytes_per_node, host_top=True)
+                if m["host"] <= host_budget_bytes:
+                    options.append((K, True))
+        fits = []
+        for K, host in options:
+            m = memory_model(nx, ny, storage, N, K, leaf_bytes_per_node, host_top=host)
+            if m["peak"] <= device_budget_bytes:
+                fits.append((m["peak"], K, host, m))
+        if fits:
+            peak, K, host, m = min(fits, key=lambda t: t[0])
+            return dict(levels=K, host_top=host, model=m)
+    raise ValueError(f"no schedule up to depth {max_depth} fits {device_budget_bytes / 2**30:.1f} GiB of device "
+                     f"memory and {host_budget_bytes / 2**30:.1f} GiB of host memory")
+
+
+def _host_copy(t):
+    """Pinned host copy of a device tensor, ordered on the current stream."""
+    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+    h.copy_(t, non_blocking=True)
+    return h
 
 
 def _edges(cfg, n):
@@ -166,7 +228,7 @@ class _Adjoint:
 
 
 def _restore(sv, snap):
-    sv.pop[sv.s.cur].copy_(snap[0])
+    sv.pop[sv.s.cur].copy_(snap[0], non_blocking=True)
 
 
 def _step_to_snapshot(sv, cfg, n, ustar=True):
@@ -181,7 +243,7 @@ def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
     """Adjoint levels end-1 .. start, starting from the snapshot of level `start`.  The
     replay skips the displacement quadrature (the adjoint does not read u*)."""
     _restore(sv, snap)
-    recs[0].copy_(snap[1])
+    recs[0].copy_(snap[1], non_blocking=True)
     for n in range(start, end - 1):
         sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=recs[n + 1 - start], ustar=False)
     for m in range(end - 1, start - 1, -1):
@@ -230,9 +292,12 @@ class LBMRollout(torch.autograd.Function):
         # a finite-difference probe, keeps nothing)
         keep = any(ctx.needs_input_grad[:4])
         snaps = {0: (sv.pop[sv.s.cur].clone(), sv.record_state(cfg.ramp(0), sv.new_record()))} if keep else {}
+        if keep and cfg.host_top:
+            snaps[0] = tuple(_host_copy(t) for t in snaps[0])
         for n in range(N):
             if keep and (n + 1) % K == 0:
-                snaps[n + 1] = _step_to_snapshot(sv, cfg, n)
+                snap = _step_to_snapshot(sv, cfg, n)
+                snaps[n + 1] = tuple(_host_copy(t) for t in snap) if cfg.host_top else snap
             else:
                 sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n))
         u = sv.displacement(cfg.ramp(N))

@@ -39,3 +39,18 @@ def test_plan_fits_budget_with_fewest_levels(budget_gib):
 def test_plan_refuses_impossible_budget():
     with pytest.raises(ValueError):
         checkpoint_plan(4096, 4096, "f32", 20000, 8 * 2 ** 30)
+
+
+def test_host_top_level_cuts_replays_within_budgets():
+    """With the outermost snapshots in pinned host memory the 4096^2 x 20000 FP32 adjoint
+    fits 64 GiB of device memory with two levels (three forward passes) instead of four."""
+    from paper_2605_26677_amd.rollout import plan_checkpoints
+    n, N = 4096, 20000
+    dev, host = 64 * 2 ** 30, 48 * 2 ** 30
+    flat = plan_checkpoints(n, n, "f32", N, dev)
+    with_host = plan_checkpoints(n, n, "f32", N, dev, host)
+    assert not flat["host_top"] and with_host["host_top"]
+    assert with_host["model"]["forward_passes"] < flat["model"]["forward_passes"]
+    assert with_host["model"]["peak"] <= dev and with_host["model"]["host"] <= host
+    m = memory_model(n, n, "f32", N, with_host["levels"], host_top=True)
+    assert m["host"] == (N // with_host["levels"][0] + 1) * (96 + 24) * n * n

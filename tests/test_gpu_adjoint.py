@@ -268,3 +268,13 @@ def test_checkpoint_plan_memory_model_matches_measurement():
     _, g_flat = run(RolloutConfig(checkpoint_every=50, **common))
     for a, b in zip(g_nested, g_flat):
         assert np.array_equal(a, b)
+
+
+def test_host_checkpoints_match_device_checkpoints():
+    """The outermost snapshots kept in pinned host memory give bitwise the gradients of the
+    same schedule with device snapshots."""
+    cs = _case("walls", nx=96, ny=80, steps=120)
+    _, g_dev = _gpu_grads(cs, "f32", levels=[30, 8])
+    _, g_host = _gpu_grads(cs, "f32", levels=[30, 8], host_top=True)
+    for k in g_dev:
+        assert np.array_equal(g_dev[k], g_host[k]), k
