@@ -202,7 +202,8 @@ lbm_status lbm_init(const lbm_params *p, lbm_state *s, const double *v0, const d
  * equilibrium (eq:feq), collision with trapezoidal forcing (eq:collision), store into
  * s->pop[1 - s->cur], u* update.  Flips s->cur on success.
  *   r_n, r_np1: body-force factors at levels n and n+1.
- *   at_half: boundary data at t^{n+1/2}; may be NULL when all edges are periodic.
+ *   at_half: boundary data at t^{n+1/2}; may be NULL only when all edges are periodic
+ *     (LBM_ERR_ARG otherwise).
  *   record: device, lbm_record_bytes(), receives U^{n+1} (v, F - I), or NULL. */
 lbm_status lbm_step(const lbm_params *p, lbm_state *s, int64_t n, double r_n, double r_np1,
                     const lbm_edge_data *at_half, void *record, void *stream);

@@ -186,6 +186,7 @@ lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, do
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
     if ((st = check_state(p, s, false)) != LBM_OK) return st;
+    if (any_wall(p) && !at_half) return LBM_ERR_ARG;
     const hipStream_t hs = (hipStream_t)stream;
     const Common cm = make_common(p, s);
     const EdgeData ed = make_edges(at_half);
@@ -280,6 +281,7 @@ lbm_status lbm_adjoint_step(const lbm_params* p, const lbm_state* fwd, lbm_adj_s
     if (has_traction(p) && !adj->aux) return LBM_ERR_ARG;
     if (adj->nprobe < 0 || (adj->nprobe > 0 && (!adj->probe || !adj->ubar))) return LBM_ERR_ARG;
     if (m < 0 || m > adj->nsteps) return LBM_ERR_ARG;
+    if (any_wall(p) && !at_half) return LBM_ERR_ARG;
     if (p->storage != LBM_F64_PLAIN && (adj->g_mu || adj->g_lam || adj->g_body) && !adj->gsum)
         return LBM_ERR_ARG;
     AdjArgs a{};

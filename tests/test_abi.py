@@ -157,3 +157,13 @@ def test_adjoint_step_requires_block_sums_for_shifted_storage():
     assert lib.lbm_adj_sum_bytes(ctypes.byref(p)) == 4 * 64 * 64 * 4
     assert lib.lbm_adjoint_step(ctypes.byref(p), ctypes.byref(s), ctypes.byref(a), 3, 1.0, None,
                                 ctypes.c_void_p(fake), None) == L.LBM_ERR_ARG
+
+
+def test_walls_need_boundary_data():
+    """lbm_step on a grid with walls refuses a NULL at_half before any launch."""
+    lib = L.lib()
+    fake = 256
+    p = _params(bc=(L.LBM_VELOCITY, L.LBM_VELOCITY, 0, 0))
+    s = L.lbm_state()
+    s.pop[0], s.pop[1], s.fault = fake, fake, fake
+    assert lib.lbm_step(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, None, None, None) == L.LBM_ERR_ARG
