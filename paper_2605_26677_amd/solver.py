@@ -98,6 +98,12 @@ class StepGraph:
 
 
 class Solver:
+    """One grid's device state and the library calls on it (torch's current stream).
+
+    Parameters mirror lbm_params: grid size, lattice speed c and BGK rate omega, spacing
+    dx, law ("lognh", "nh", "svk", "mr", "yeoh", "gent") with optional law_k constants,
+    storage ("f32", "f16", "f64"), edge kinds, uniform or per-node mu, lam and body force."""
+
     def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
                  bc=("periodic",) * 4, mu=0.1, lam=0.2, body=None, newton_max_iter=0,
                  newton_tol=0.0, force_unstable=False, law_k=None, device="cuda"):
@@ -161,8 +167,8 @@ class Solver:
     def set_body_levels(self, body_prev, body_next):
         """Per-step body force fields: body_prev for level n, body_next for level n + 1
         of the next lbm_step (float32 device tensors (2, ny, nx); use r = 1)."""
-        self._body_prev = body_prev.contiguous()
-        self.body_t = body_next.contiguous()
+        self._body_prev = torch.as_tensor(body_prev, dtype=torch.float32, device=self.device).contiguous()
+        self.body_t = torch.as_tensor(body_next, dtype=torch.float32, device=self.device).contiguous()
         self.s.body = self.body_t.data_ptr()
         self.s.body_prev = self._body_prev.data_ptr()
 
