@@ -3,10 +3,12 @@
 Workload (default): 8192 x 8192 periodic grid, log-neo-Hookean mu = 0.1, lam = 0.2,
 F0 = I, initial velocity a seeded Gaussian random field with power spectrum ~ k^-3 and
 rms 5e-3 (seeds 301, 302), c = 2, omega = 2, populations in FP32 with F carried as F - I.
-A "step" is one call of lbm_step (pull streaming, moments, constitutive update,
-equilibrium, collision, store, displacement quadrature) over the whole grid; inputs are
-resident in HBM before timing.  Also measured: FP64 and FP16 storage of the same step, and
-forward + adjoint with every-K checkpointing on per-node mu, lam fields.
+A "step" is one time level of the whole hot path (pull streaming, moments, constitutive
+update, equilibrium, collision, store, displacement quadrature) over the whole grid; inputs
+are resident in HBM before timing.  The headline runs the steps in pairs through lbm_step2
+(two levels per pass over HBM, bit for bit the result of two lbm_step calls); the single-
+level lbm_step is timed beside it.  Also measured: FP64 and FP16 storage of the same step,
+and forward + adjoint with every-K checkpointing on per-node mu, lam fields.
 
 Prints one JSON line.  Only --gpus 1 is supported.
 """
@@ -28,9 +30,13 @@ METRIC = "MLUPS fwd & fwd+adjoint at 8192², FP32 vs FP64, % of HBM roofline"
 # read + written every step and U (double) read + written every 16th step (FP64: u* read
 # + written every step)
 BYTES_PER_LU = {"f32": 96 + 96 + 16 + 32 / 16, "f16": 48 + 48 + 16 + 32 / 16, "f64": 192 + 192 + 32}
+# the same per launch of the two-level kernel (lbm_step2): populations read and written
+# once per two levels, S read + written once, U folded once per 8 launches
+BYTES_PER_LU_PAIR = {"f32": 96 + 96 + 16 + 32 / 8, "f16": 48 + 48 + 16 + 32 / 8, "f64": 192 + 192 + 32}
 
 
-PROFILE_PMC = os.path.join(ROOT, "profiles", "step_f32_lognh_periodic_8192_pmc.txt")
+PROFILE_PMC = {"step": os.path.join(ROOT, "profiles", "step_f32_lognh_periodic_8192_pmc.txt"),
+               "step2": os.path.join(ROOT, "profiles", "step2_f32_lognh_periodic_8192_pmc.txt")}
 STEP_SOURCES = ("lbm_forward.hip", "lbm_device.hpp", "lbm_kernel_util.hpp", "lbm_internal.hpp")
 
 
@@ -43,14 +49,16 @@ def step_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(n):
-    """HBM bytes per step launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary (scaled by the same counters on a copy of known size), or None when the
-    summary is missing, was taken at another size, or the kernel source changed since."""
-    if not os.path.exists(PROFILE_PMC):
+def measured_traffic(n, kernel="step"):
+    """HBM bytes per launch of the step ("step") or two-level ("step2") kernel from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the same counters on a
+    copy of known size), or None when the summary is missing, was taken at another size,
+    or the kernel source changed since."""
+    path = PROFILE_PMC[kernel]
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(PROFILE_PMC) as fh:
+    with open(path) as fh:
         for line in fh:
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
@@ -91,26 +99,36 @@ def make_inputs(n):
     return v0
 
 
-def time_forward(n, storage, steps, warmup, v0, law="lognh"):
+def time_forward(n, storage, steps, warmup, v0, law="lognh", pairs=False):
+    """ms per level of `steps` levels after `warmup` untimed ones: single lbm_step calls, or
+    lbm_step2 calls of two levels each (`pairs`; steps and warmup rounded up to even)."""
     import torch
     from paper_2605_26677_amd.solver import Solver
     sv = Solver(n, n, c=2.0, omega=2.0, material=law, storage=storage, mu=0.1, lam=0.2)
     sv.init(v0)
-    for k in range(warmup):
-        sv.step(k)
+    if pairs:
+        steps, warmup = steps + steps % 2, warmup + warmup % 2
+
+    def run(k0, count):
+        if pairs:
+            for k in range(k0, k0 + count, 2):
+                sv.step2(k)
+        else:
+            for k in range(k0, k0 + count):
+                sv.step(k)
+    run(0, warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
-    for k in range(steps):
-        sv.step(warmup + k)
+    run(warmup, steps)
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
     faults = sv.faults()
     del sv
     torch.cuda.empty_cache()
-    return ms, faults
+    return ms, faults, steps
 
 
 def time_launch_bound(n=256, steps=4000, block=100):
@@ -273,10 +291,11 @@ def profile_run(n, steps):
     torch.cuda.synchronize()
     del a, b
     v0 = make_inputs(n)
-    ms, faults = time_forward(n, "f32", steps, 3, v0)
+    ms, faults, _ = time_forward(n, "f32", steps, 3, v0)
+    ms2, faults2, _ = time_forward(n, "f32", steps, 4, v0, pairs=True)
     adj = time_forward_adjoint(n, 20, 10)
     print(json.dumps({"profile": True, "copy_bytes_each_way": 2 ** 31, "ms_per_step": ms, "faults": faults,
-                      "fwd_adj": adj}))
+                      "ms_per_level_pairs": ms2, "faults_pairs": faults2, "fwd_adj": adj}))
 
 
 def cpu_baseline(budget_s=20.0):
@@ -338,25 +357,31 @@ def main():
     v0 = make_inputs(n)
     only = [s for s in args.only.split(",") if s] or ["f32", "f64", "f16"]
     res = {}
-    for storage in only:
-        steps = args.steps if storage == "f32" else args.variant_steps
-        log(f"bench: timing {storage} forward, {steps} steps")
-        ms, faults = time_forward(n, storage, steps, args.warmup, v0)
+
+    def record(key, storage, ms, faults, steps, pairs):
         mlups = n * n / (ms * 1e-3) / 1e6
-        gbs = BYTES_PER_LU[storage] * n * n / (ms * 1e-3) / 1e9
-        res[storage] = dict(ms_per_step=ms, mlups=mlups, algorithmic_GBps=gbs,
-                            frac_hbm=gbs * 1e9 / PEAK_HBM, faults=faults, steps=steps)
-        log(f"bench: {storage}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {gbs:.0f} GB/s")
+        bpl = BYTES_PER_LU_PAIR[storage] if pairs else BYTES_PER_LU[storage]
+        launch_ms = 2 * ms if pairs else ms
+        gbs = bpl * n * n / (launch_ms * 1e-3) / 1e9
+        res[key] = dict(ms_per_step=ms, mlups=mlups, kernel="step2_kernel" if pairs else "step_kernel",
+                        launch_ms=launch_ms, bytes_per_lu_per_launch=bpl, algorithmic_GBps=gbs,
+                        frac_hbm=gbs * 1e9 / PEAK_HBM, faults=faults, steps=steps)
+        log(f"bench: {key}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {gbs:.0f} GB/s per launch")
+
+    for storage in only:
+        for pairs in (True, False):
+            steps = args.steps if storage == "f32" else args.variant_steps
+            key = storage + ("_pairs" if pairs else "")
+            log(f"bench: timing {key} forward, {steps} steps")
+            ms, faults, steps = time_forward(n, storage, steps, args.warmup, v0, pairs=pairs)
+            record(key, storage, ms, faults, steps, pairs)
     if "f32" in only:
         # the St. Venant-Kirchhoff variant of the same workload (FP32 storage)
-        steps = args.variant_steps
-        log(f"bench: timing svk f32 forward, {steps} steps")
-        ms, faults = time_forward(n, "f32", steps, args.warmup, v0, law="svk")
-        mlups = n * n / (ms * 1e-3) / 1e6
-        gbs = BYTES_PER_LU["f32"] * n * n / (ms * 1e-3) / 1e9
-        res["svk_f32"] = dict(ms_per_step=ms, mlups=mlups, algorithmic_GBps=gbs, frac_hbm=gbs * 1e9 / PEAK_HBM,
-                              faults=faults, steps=steps)
-        log(f"bench: svk f32: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {gbs:.0f} GB/s")
+        for pairs in (True, False):
+            key = "svk_f32" + ("_pairs" if pairs else "")
+            log(f"bench: timing {key} forward, {args.variant_steps} steps")
+            ms, faults, steps = time_forward(n, "f32", args.variant_steps, args.warmup, v0, law="svk", pairs=pairs)
+            record(key, "f32", ms, faults, steps, pairs)
     log("bench: launch-bound grid, eager vs captured graph")
     res["launch_bound_256"] = time_launch_bound()
     log(f"bench: launch-bound: {res['launch_bound_256']}")
@@ -366,23 +391,33 @@ def main():
         log(f"bench: fwd+adj: {res['fwd_adj_f32']}")
     log("bench: copy ceiling")
     copy_gbs = copy_ceiling()
-    main_key = "f32" if "f32" in res else only[0]
+    main_storage = "f32" if "f32" in only else only[0]
+    main_key = main_storage + "_pairs"
     r = res[main_key]
-    traffic = measured_traffic(n) if main_key == "f32" else None
+    traffic = measured_traffic(n, "step2") if main_storage == "f32" else None
     out = {
         "metric": METRIC, "value": r["mlups"], "unit": "MLUPS", "n_gpus": 1,
         "steps": r["steps"], "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": main_key,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": main_storage,
         "data": "synthetic",
         "config": {"workload": f"{n}x{n} periodic random-field elastic waves (k^-3 spectrum, rms 5e-3), "
-                               f"log-NH mu=0.1 lam=0.2, c=2, omega=2, {main_key} storage",
-                   "grid": [n, n], "storage": main_key},
-        "roofline": {"bound": "hbm", "achieved": r["algorithmic_GBps"], "peak": PEAK_HBM / 1e9,
-                     "unit": "GB/s", "frac": r["frac_hbm"], "traffic": traffic,
-                     "algorithmic_bytes_per_launch": BYTES_PER_LU[main_key] * n * n,
-                     "copy_ceiling_GBps": copy_gbs},
+                               f"log-NH mu=0.1 lam=0.2, c=2, omega=2, {main_storage} storage, "
+                               f"two levels per pass (lbm_step2)",
+                   "grid": [n, n], "storage": main_storage},
+        "roofline": {"bound": "hbm", "kernel": "step2_kernel", "achieved": r["algorithmic_GBps"],
+                     "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": r["frac_hbm"], "traffic": traffic,
+                     "algorithmic_bytes_per_launch": BYTES_PER_LU_PAIR[main_storage] * n * n,
+                     "launch_ms": r["launch_ms"], "copy_ceiling_GBps": copy_gbs},
+        "single_step_roofline": None,
         "variants": res,
     }
+    if main_storage in res:
+        r1 = res[main_storage]
+        out["single_step_roofline"] = {
+            "bound": "hbm", "kernel": "step_kernel", "achieved": r1["algorithmic_GBps"], "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s", "frac": r1["frac_hbm"],
+            "traffic": measured_traffic(n, "step") if main_storage == "f32" else None,
+            "algorithmic_bytes_per_launch": BYTES_PER_LU[main_storage] * n * n, "mlups": r1["mlups"]}
     if not args.no_cpu:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline()

@@ -90,7 +90,7 @@ enum {
 #define LBM_DIAG_COUNT 10
 
 typedef struct {
-    int32_t nx, ny;            /* grid nodes, >= 4 along any axis with walls, >= 2 otherwise */
+    int32_t nx, ny;            /* grid nodes, >= 4 along any axis with walls, >= 3 otherwise */
     int32_t material;          /* LBM_LOGNH | LBM_NH | LBM_SVK | LBM_MR | LBM_YEOH | LBM_GENT */
     int32_t storage;           /* LBM_F32_SHIFTED | LBM_F16_SHIFTED | LBM_F64_PLAIN */
     int32_t bc[4];             /* per edge LBM_XMIN..LBM_YMAX: LBM_PERIODIC | LBM_VELOCITY | LBM_TRACTION */
@@ -207,6 +207,18 @@ lbm_status lbm_init(const lbm_params *p, lbm_state *s, const double *v0, const d
  *   record: device, lbm_record_bytes(), receives U^{n+1} (v, F - I), or NULL. */
 lbm_status lbm_step(const lbm_params *p, lbm_state *s, int64_t n, double r_n, double r_np1,
                     const lbm_edge_data *at_half, void *record, void *stream);
+
+/* Two time steps, level n -> n+2, in one pass over the grid (temporal blocking of the
+ * step of Sec. 3.7: level n+1 stays on chip).  The result, the u* accumulator and the
+ * fault bits are those of lbm_step(n) followed by lbm_step(n+1), bit for bit, at about
+ * half the HBM traffic per level.  Flips s->cur on success.
+ *   r_np1, r_np2: body-force factors at levels n+1 and n+2; the body field s->body (or
+ *     the uniform b0) is the same at both levels.
+ * Every edge must be periodic (LBM_ERR_UNSUPPORTED otherwise: the traction rule needs
+ * level n+1 along a whole wall).  No record is written; use lbm_step where U^{n+1} is
+ * needed. */
+lbm_status lbm_step2(const lbm_params *p, lbm_state *s, int64_t n, double r_np1, double r_np2,
+                     void *stream);
 
 /* Displacement at the current level n (eq:trapezoid-u): u^n = u*^{n+1} - (dt/2) v^n with
  * v^n recovered from the stored post-collision populations (sum_q f* = U + (dt/2) B).

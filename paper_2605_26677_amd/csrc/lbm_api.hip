@@ -217,6 +217,26 @@ lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, do
     return LBM_OK;
 }
 
+lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_np1, double r_np2, void* stream) {
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if (any_wall(p)) return LBM_ERR_UNSUPPORTED;
+    if ((st = check_state(p, s, false)) != LBM_OK) return st;
+    Step2Args a{};
+    a.cm = make_common(p, s);
+    a.src = s->pop[s->cur];
+    a.dst = s->pop[1 - s->cur];
+    a.ustar = s->ustar;
+    a.fold1 = (n + 1) % kUstarBlock == 0;
+    a.fold2 = (n + 2) % kUstarBlock == 0;
+    a.nstrip = (p->nx + kPairCols - 1) / kPairCols;
+    a.r_np1 = r_np1;
+    a.r_np2 = r_np2;
+    if (launch_step2(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
+    s->cur = 1 - s->cur;
+    return LBM_OK;
+}
+
 static lbm_status recover_common(const lbm_params* p, const lbm_state* s, double r_n, void* out,
                                  RecoverArgs& a, bool need_ustar = false) {
     lbm_status st = lbm_check_params(p);

@@ -117,6 +117,40 @@ __device__ __forceinline__ void wall_link(const Common& cm, const EdgeData& ed, 
     }
 }
 
+// One node's update from its pulled populations g: moments with the half-step source
+// (eq:moment-U), the constitutive response in registers, fluxes (eq:flux-vectors),
+// equilibrium (eq:feq) and the collision with trapezoidal forcing (eq:collision).
+// B0, B1: body acceleration at the new level.  Returns the post-collision populations
+// and U (velocity rows include the half-step source).
+template <typename R, int LAW, bool SH>
+__device__ __forceinline__ void collide_node(const Common& cm, const R g[4][6], R B0, R B1, R mu, R lam,
+                                             R out[4][6], R U[6], R& J) {
+    const R hdt = R(0.5 * cm.dt);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) U[k] = g[0][k] + g[1][k] + g[2][k] + g[3][k];
+    U[0] += hdt * B0;
+    U[1] += hdt * B1;
+    R P[4];
+    piola<R, LAW, SH>(&U[2], mu, lam, law_consts<R>(cm), P, J);
+    const R PhiX[6] = {-P[0], -P[2], -U[0], R(0), -U[1], R(0)};
+    const R PhiY[6] = {-P[1], -P[3], R(0), -U[0], R(0), -U[1]};
+    const R c2 = R(2.0 / cm.c);
+    const R om = R(cm.omega);
+    const R srcw = R(cm.dt * (2.0 - cm.omega) * 0.125);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const R i = R(dir_i(q)), j = R(dir_j(q));
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const R feq = R(0.25) * (U[k] + c2 * (i * PhiX[k] + j * PhiY[k]));
+            R v = g[q][k] + om * (feq - g[q][k]);
+            if (k == 0) v += srcw * B0;
+            if (k == 1) v += srcw * B1;
+            out[q][k] = v;
+        }
+    }
+}
+
 template <int ST, int LAW, bool WALLS, bool FIELDS>
 __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     using Tr = Storage<ST>;
@@ -164,41 +198,17 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
         if (miss3) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMAX, x, src, own, g[3]);
     }
 
-    // moments with the half-step source (eq:moment-U)
     double bd0, bd1;
     body_at<FIELDS>(cm, idx, n, a.r_np1, bd0, bd1);
-    const R B0 = R(bd0), B1 = R(bd1);
-    const R dt = R(cm.dt), hdt = R(0.5 * cm.dt);
-    R U[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) U[k] = g[0][k] + g[1][k] + g[2][k] + g[3][k];
-    U[0] += hdt * B0;
-    U[1] += hdt * B1;
-
-    // constitutive response in registers, fluxes (eq:flux-vectors), equilibrium (eq:feq)
     R mu, lam;
     params_at<FIELDS, R>(cm, idx, mu, lam);
-    R P[4], J;
-    piola<R, LAW, SH>(&U[2], mu, lam, law_consts<R>(cm), P, J);
-    const R PhiX[6] = {-P[0], -P[2], -U[0], R(0), -U[1], R(0)};
-    const R PhiY[6] = {-P[1], -P[3], R(0), -U[0], R(0), -U[1]};
-    const R c2 = R(2.0 / cm.c);
-    const R om = R(cm.omega);
-    const R srcw = R(cm.dt * (2.0 - cm.omega) * 0.125);
-
-    // collision with trapezoidal forcing (eq:collision), store to the own node
+    const R dt = R(cm.dt);
+    R out[4][6], U[6], J;
+    collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, out, U, J);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const R i = R(dir_i(q)), j = R(dir_j(q));
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const R feq = R(0.25) * (U[k] + c2 * (i * PhiX[k] + j * PhiY[k]));
-            R v = g[q][k] + om * (feq - g[q][k]);
-            if (k == 0) v += srcw * B0;
-            if (k == 1) v += srcw * B1;
-            store_stream(dst + own + (6 * q + k) * kTile, T(v));
-        }
-    }
+        for (int k = 0; k < 6; ++k) store_stream(dst + own + (6 * q + k) * kTile, T(out[q][k]));
 
     // displacement quadrature u*^{n+2} = u*^{n+1} + dt v^{n+1} (eq:trapezoid-u)
     if (!a.ustar) {
@@ -236,6 +246,150 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U[k]);
     const bool jbad = J <= R(0);
+    if (nonfinite || jbad)
+        atomicOr(cm.fault, (jbad ? (uint32_t)LBM_FAULT_J : 0u) | (nonfinite ? (uint32_t)LBM_FAULT_NONFINITE : 0u));
+}
+
+// ---------------------------------------------------------------- two fused steps
+
+// Temporal blocking of the periodic step: one pass takes f*^n to f*^{n+2} without storing
+// level n+1.  A workgroup of kPairWaves wavefronts owns a block of kPairRows rows of a strip
+// of kPairCols columns.  Wave w takes row y0 - 1 + w through level n+1 (pulling level n
+// straight from HBM); the level n+1 populations that cross rows go through LDS, those that
+// cross columns through lane shuffles, and waves 1 .. kPairRows take their row on to level
+// n+2.  Lanes hold columns c0 - 1 .. c0 + 62, so every level n+1 value that an output needs
+// is computed in the same workgroup (the halo rows and columns are computed twice, by the
+// neighbouring workgroups as well).  Each node's arithmetic is collide_node, as in
+// step_kernel, and level n+1 is rounded to the storage type, so the result is bit for bit
+// that of two single steps.
+template <int ST, int LAW, bool FIELDS>
+__global__ void __launch_bounds__(kPairWaves * kTile) step2_kernel(Step2Args a) {
+    using Tr = Storage<ST>;
+    using R = typename Tr::real;
+    using T = typename Tr::pop_t;
+    constexpr bool SH = Tr::shifted;
+    __shared__ R xq1[kPairWaves][6][kTile];   // level n+1, direction (0,1): read by the row above
+    __shared__ R xq3[kPairWaves][6][kTile];   // level n+1, direction (0,-1): read by the row below
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
+    const int64_t n = int64_t(nx) * ny;
+    const int b = remap_tile(blockIdx.x, gridDim.x);
+    const int strip = b % a.nstrip, blk = b / a.nstrip;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
+    const int c0 = strip * kPairCols, y0 = blk * kPairRows;
+    const int r = y0 - 1 + w;
+    const int xc = wrap_index(c0 - 1 + lane, nx);
+    const int yr = wrap_index(r, ny);
+    const T* __restrict__ src = (const T*)a.src;
+    T* __restrict__ dst = (T*)a.dst;
+
+    // level n -> n+1 on row r: q0 from x-1 and q2 from x+1 of row r (own lanes shifted, the
+    // two end lanes from the columns beyond the strip), q1 from row r-1, q3 from row r+1
+    const int64_t bo = tile_base(ntile, 24, xc, yr);
+    const int64_t bm = tile_base(ntile, 24, xc, wrap_index(r - 1, ny));
+    const int64_t bp = tile_base(ntile, 24, xc, wrap_index(r + 1, ny));
+    R own0[6], own2[6], g[4][6], h[6] = {};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        own0[k] = R(src[bo + k * kTile]);
+        own2[k] = R(src[bo + (12 + k) * kTile]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        g[1][k] = R(src[bm + (6 + k) * kTile]);
+        g[3][k] = R(src[bp + (18 + k) * kTile]);
+    }
+    if (lane == 0 || lane == kTile - 1) {
+        const int64_t bh = lane == 0 ? tile_base(ntile, 24, wrap_index(c0 - 2, nx), yr)
+                                     : tile_base(ntile, 24, wrap_index(c0 + kTile - 1, nx), yr) + 12 * kTile;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) h[k] = R(src[bh + k * kTile]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const R up = __shfl_up(own0[k], 1), dn = __shfl_down(own2[k], 1);
+        g[0][k] = lane == 0 ? h[k] : up;
+        g[2][k] = lane == kTile - 1 ? h[k] : dn;
+    }
+    const int idx1 = yr * nx + xc;
+    double bd0, bd1;
+    body_at<FIELDS>(cm, idx1, n, a.r_np1, bd0, bd1);
+    R mu, lam;
+    params_at<FIELDS, R>(cm, idx1, mu, lam);
+    R f1[4][6], U1[6], J1;
+    collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f1, U1, J1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) f1[q][k] = R(T(f1[q][k]));   // the stored value of level n+1
+    bool nonfinite = false;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U1[k]);
+    bool jbad = J1 <= R(0);
+
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        xq1[w][k][lane] = f1[1][k];
+        xq3[w][k][lane] = f1[3][k];
+        g[0][k] = __shfl_up(f1[0][k], 1);
+        g[2][k] = __shfl_down(f1[2][k], 1);
+    }
+    __syncthreads();
+
+    // level n+1 -> n+2 on row r for the inner waves; lanes 1 .. 62 are outputs
+    const int xo = c0 - 1 + lane;
+    const bool out = w >= 1 && w <= kPairRows && r < ny && lane >= 1 && lane <= kPairCols && xo < nx;
+    if (w >= 1 && w <= kPairRows) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            g[1][k] = xq1[w - 1][k][lane];
+            g[3][k] = xq3[w + 1][k][lane];
+        }
+        body_at<FIELDS>(cm, idx1, n, a.r_np2, bd0, bd1);
+        R f2[4][6], U2[6], J2;
+        collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f2, U2, J2);
+        if (out) {
+            const int64_t ob = tile_base(ntile, 24, xo, r);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) store_stream(dst + ob + (6 * q + k) * kTile, T(f2[q][k]));
+            // displacement quadrature over both levels (eq:trapezoid-u), with the same
+            // accumulator updates and folds as two single steps
+            const R dt = R(cm.dt);
+            if (!a.ustar) {
+            } else if constexpr (ST == LBM_F64_PLAIN) {
+                double* us = (double*)a.ustar + tile_base(ntile, 2, xo, r);
+                const double s0 = us[0] + dt * U1[0], s1 = us[kTile] + dt * U1[1];
+                store_stream(us, s0 + dt * U2[0]);
+                store_stream(us + kTile, s1 + dt * U2[1]);
+            } else {
+                const UstarRefs rf = ustar_refs(a.ustar, ntile, ny, xo, r);
+#pragma unroll
+                for (int cpt = 0; cpt < 2; ++cpt) {
+                    float sn = rf.S[cpt * kTile] + float(dt * U1[cpt]);
+                    bool moved = false;
+                    double u = 0.0;
+                    if (a.fold1) {
+                        u = rf.U[cpt * kTile] + double(sn);
+                        sn = 0.0f;
+                        moved = true;
+                    }
+                    sn = sn + float(dt * U2[cpt]);
+                    if (a.fold2) {
+                        u = (moved ? u : rf.U[cpt * kTile]) + double(sn);
+                        sn = 0.0f;
+                        moved = true;
+                    }
+                    if (moved) store_stream(rf.U + cpt * kTile, u);
+                    store_stream(rf.S + cpt * kTile, sn);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U2[k]);
+            jbad |= J2 <= R(0);
+        }
+    }
     if (nonfinite || jbad)
         atomicOr(cm.fault, (jbad ? (uint32_t)LBM_FAULT_J : 0u) | (nonfinite ? (uint32_t)LBM_FAULT_NONFINITE : 0u));
 }
@@ -594,6 +748,36 @@ static hipError_t step_st(const StepArgs& a, hipStream_t s) {
         case LBM_YEOH: return step_st_law<ST, LBM_YEOH>(a, s);
         case LBM_GENT: return step_st_law<ST, LBM_GENT>(a, s);
         default: return step_st_law<ST, LBM_SVK>(a, s);
+    }
+}
+
+template <int ST, int LAW>
+static hipError_t step2_st_law(const Step2Args& a, hipStream_t s) {
+    const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
+    const dim3 grid(unsigned(int64_t(a.nstrip) * ((a.cm.ny + kPairRows - 1) / kPairRows)));
+    const dim3 block(kPairWaves * kTile);
+    if (fields) hipLaunchKernelGGL((step2_kernel<ST, LAW, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((step2_kernel<ST, LAW, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t step2_st(const Step2Args& a, hipStream_t s) {
+    switch (a.cm.material) {
+        case LBM_LOGNH: return step2_st_law<ST, LBM_LOGNH>(a, s);
+        case LBM_NH: return step2_st_law<ST, LBM_NH>(a, s);
+        case LBM_MR: return step2_st_law<ST, LBM_MR>(a, s);
+        case LBM_YEOH: return step2_st_law<ST, LBM_YEOH>(a, s);
+        case LBM_GENT: return step2_st_law<ST, LBM_GENT>(a, s);
+        default: return step2_st_law<ST, LBM_SVK>(a, s);
+    }
+}
+
+hipError_t launch_step2(const Step2Args& a, hipStream_t s) {
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: return step2_st<LBM_F32_SHIFTED>(a, s);
+        case LBM_F16_SHIFTED: return step2_st<LBM_F16_SHIFTED>(a, s);
+        default: return step2_st<LBM_F64_PLAIN>(a, s);
     }
 }
 

@@ -54,6 +54,22 @@ struct StepArgs {
     EdgeData ed;                     // data at t^{n+1/2}
 };
 
+// Two fused steps on a periodic grid (step2_kernel): workgroups of kPairWaves wavefronts,
+// each owning kPairRows rows of a strip of kPairCols columns.
+constexpr int kPairWaves = 8;
+constexpr int kPairRows = kPairWaves - 2;
+constexpr int kPairCols = 62;
+
+struct Step2Args {
+    Common cm;
+    const void* src;                 // f*^n
+    void* dst;                       // f*^{n+2}
+    void* ustar;
+    int fold1, fold2;                // accumulator folds after the first / second step
+    int nstrip;                      // strips of kPairCols columns
+    double r_np1, r_np2;
+};
+
 struct TractionArgs {
     Common cm;
     const void* pop;                 // f*^n
@@ -122,6 +138,7 @@ struct AdjInitArgs {
 };
 
 hipError_t launch_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_step2(const Step2Args& a, hipStream_t s);
 hipError_t launch_traction(const TractionArgs& a, hipStream_t s);
 hipError_t launch_moments(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_record(const RecoverArgs& a, hipStream_t s);

@@ -16,6 +16,12 @@ __device__ __forceinline__ int remap_tile(int b, int nb) {
     return (b & 7) * per + (b >> 3);
 }
 
+// v mod n in [0, n) for any v (periodic index).
+__device__ __forceinline__ int wrap_index(int v, int n) {
+    const int m = v % n;
+    return m < 0 ? m + n : m;
+}
+
 template <typename R>
 __device__ __forceinline__ R edge_value(const EdgeData& ed, int e, int comp, int s, int L) {
     const double* f = ed.field[e];

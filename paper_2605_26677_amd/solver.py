@@ -85,10 +85,10 @@ class StepGraph:
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             for st in steps:
-                solver.step(**st)
+                solver._run(st)
         self.end_cur = solver.s.cur
         solver.s.cur = self.start_cur
-        self.nsteps = len(steps)
+        self.nsteps = sum(2 if st.get("pair") else 1 for st in steps)
 
     def replay(self):
         if self.sv.s.cur != self.start_cur:
@@ -213,25 +213,55 @@ class Solver:
         finally:
             self.s.ustar = keep
 
+    def step2(self, n, r_np1=1.0, r_np2=1.0, ustar=True):
+        """lbm_step2: levels n -> n + 2 in one pass (periodic grids), bit for bit the same as
+        step(n) then step(n + 1) with the same factors."""
+        keep = self.s.ustar
+        if not ustar:
+            self.s.ustar = None
+        try:
+            L.check(self.lib.lbm_step2(ctypes.byref(self.p), ctypes.byref(self.s), int(n), float(r_np1),
+                                       float(r_np2), _stream()), "lbm_step2")
+        finally:
+            self.s.ustar = keep
+
+    @property
+    def periodic(self):
+        return all(int(b) == L.BC["periodic"] for b in self.p.bc)
+
+    def _run(self, st):
+        if st.get("pair"):
+            self.step2(st["n"], st["r_np1"], st["r_np2"])
+        else:
+            self.step(**st)
+
     def capture(self, steps):
         """Records a fixed sequence of lbm_step calls as one HIP graph (``StepGraph``).
         ``steps`` is a list of dicts with the keyword arguments of ``step``."""
         return StepGraph(self, steps)
 
-    def advance(self, n0, count, ramp=None, edges=None, block=64):
+    def advance(self, n0, count, ramp=None, edges=None, block=64, fused=None):
         """Steps n0 .. n0 + count - 1 with ramp factors ``ramp(n)`` (default 1) and wall data
         ``edges(n)`` (default zero): whole blocks of ``block`` steps whose arguments equal
         those of the first captured block replay one captured graph, the rest run eagerly.
-        For launch-bound grids this removes the per-step host cost."""
+        For launch-bound grids this removes the per-step host cost.  On periodic grids
+        (``fused`` None or True) the steps go in pairs through lbm_step2, with the same
+        result bit for bit."""
         ramp = ramp or (lambda n: 1.0)
         edges = edges or (lambda n: None)
+        fused = self.periodic if fused is None else (bool(fused) and self.periodic)
 
-        def args(n):
-            return dict(n=n, r_n=float(ramp(n)), r_np1=float(ramp(n + 1)), edges=edges(n))
-
-        def same(a, b):
-            return (a["r_n"] == b["r_n"] and a["r_np1"] == b["r_np1"]
-                    and _edge_key(a["edges"]) == _edge_key(b["edges"]))
+        def block_calls(n, m):
+            # the calls for steps n .. m - 1
+            calls = []
+            while n < m:
+                if fused and n + 1 < m:
+                    calls.append(dict(pair=True, n=n, r_np1=float(ramp(n + 1)), r_np2=float(ramp(n + 2))))
+                    n += 2
+                else:
+                    calls.append(dict(n=n, r_n=float(ramp(n)), r_np1=float(ramp(n + 1)), edges=edges(n)))
+                    n += 1
+            return calls
 
         graph, proto = None, None
         n, end = n0, n0 + count
@@ -239,24 +269,31 @@ class Solver:
         # displacement accumulator's 16-step fold (lbm.h, lbm_state.ustar)
         block = max(16, -(-block // 16) * 16)
         while n < end:
-            blk = [args(m) for m in range(n, min(end, n + block))]
-            if len(blk) == block and graph is None and self._graph_ok(blk):
+            m = min(end, n + block)
+            blk = block_calls(n, m)
+            if m - n == block and graph is None and self._graph_ok(blk):
                 proto = blk
                 graph = self.capture(blk)
-            if (graph is not None and len(blk) == block and self.s.cur == graph.start_cur
-                    and all(same(a, b) for a, b in zip(blk, proto))):
+            if (graph is not None and m - n == block and self.s.cur == graph.start_cur
+                    and all(self._same(a, b) for a, b in zip(blk, proto))):
                 graph.replay()
             else:
                 for a in blk:
-                    self.step(**a)
-            n += len(blk)
+                    self._run(a)
+            n = m
 
     @staticmethod
-    def _graph_ok(blk):
-        # a block is capturable when its per-step arguments repeat exactly (every step
-        # index argument is unused by the kernels, so only factors and wall data matter)
-        return all(a["r_n"] == blk[0]["r_n"] and a["r_np1"] == blk[0]["r_np1"]
-                   and _edge_key(a["edges"]) == _edge_key(blk[0]["edges"]) for a in blk)
+    def _same(a, b):
+        keys = ("pair", "r_n", "r_np1", "r_np2")
+        return (all(a.get(k) == b.get(k) for k in keys)
+                and _edge_key(a.get("edges")) == _edge_key(b.get("edges")))
+
+    @classmethod
+    def _graph_ok(cls, blk):
+        # a block is capturable when its per-call arguments repeat exactly: the step index
+        # reaches the kernels only through the accumulator's fold, whose 16-level phase a
+        # block of a multiple of 16 steps keeps
+        return all(cls._same(a, blk[0]) for a in blk)
 
     def moments(self, r_n=1.0):
         out = torch.empty((6, self.ny, self.nx), dtype=torch.float64, device=self.device)
