@@ -3,7 +3,7 @@
 Usage: ``python -m paper_2605_26677_amd.build`` (or ``build_library()``).  Each source is
 compiled to an object file in parallel under ``_build/`` and linked into
 ``paper_2605_26677_amd/liblbm.so``.  Packed FP32 instructions are disabled for all
-device code.
+device code, and multiply-adds are contracted only within one source expression.
 """
 import concurrent.futures
 import os
@@ -29,8 +29,11 @@ def hipcc():
 
 
 def compile_flags():
+    # -ffp-contract=on: a multiply and an add are fused only where they form one source
+    # expression, never by the backend across statements, so a device function inlined
+    # into two kernels rounds the same in both (lbm_step2 is bit for bit two lbm_step calls)
     return [
-        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
         f"-I{INCLUDE}", f"-I{CSRC}",

@@ -481,6 +481,19 @@ __host__ __device__ __forceinline__ UstarRefs ustar_refs(void* base, int ntile, 
 }
 
 // Store that bypasses the caches' allocate-on-write (each value is written once per pass).
+// A computed value rounded to the population storage type: the compute-type result is
+// formed first and then rounded to nearest even.  The empty asm keeps the compiler from
+// fusing the rounding into the instruction that produced the value (a mixed-precision FMA
+// rounds once, straight to half), so every kernel rounds a population the same way.
+template <typename T, typename R> __device__ __forceinline__ T to_storage(R v) {
+    if constexpr (sizeof(T) == sizeof(R)) {
+        return v;
+    } else {
+        asm("" : "+v"(v));
+        return T(v);
+    }
+}
+
 template <typename T> __device__ __forceinline__ void store_stream(T* p, T v) {
     __builtin_nontemporal_store(v, p);
 }

@@ -132,22 +132,34 @@ __device__ __forceinline__ void collide_node(const Common& cm, const R g[4][6], 
     U[1] += hdt * B1;
     R P[4];
     piola<R, LAW, SH>(&U[2], mu, lam, law_consts<R>(cm), P, J);
-    const R PhiX[6] = {-P[0], -P[2], -U[0], R(0), -U[1], R(0)};
-    const R PhiY[6] = {-P[1], -P[3], R(0), -U[0], R(0), -U[1]};
-    const R c2 = R(2.0 / cm.c);
-    const R om = R(cm.omega);
+    // f*_q = (1 - omega) f_q + omega f^eq_q + source, with
+    // omega f^eq_q = (omega/4) U + (omega/(2c)) (i Phi_X + j Phi_Y) for e_q = (i, j) and the
+    // fluxes Phi_X = -(P11, P21, v1, 0, v2, 0), Phi_Y = -(P12, P22, 0, v1, 0, v2)
+    // (eq:flux-vectors); the zero entries and the unit factors i, j are taken out by hand.
+    // omc = 1 - 4 omq is exact in R (Sterbenz), so the weights of f and f^eq sum to exactly
+    // 1 and the collision keeps sum_q f* = U + (dt/2) B without a drift of the moments
+    const R omq = R(0.25 * cm.omega), omc = R(1) - R(4) * omq, cq = R(0.5 * cm.omega / cm.c);
     const R srcw = R(cm.dt * (2.0 - cm.omega) * 0.125);
+    R a[6];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const R i = R(dir_i(q)), j = R(dir_j(q));
+    for (int k = 0; k < 6; ++k) a[k] = omq * U[k];
+    a[0] = a[0] + srcw * B0;
+    a[1] = a[1] + srcw * B1;
+    // e_x-flux (X) and e_y-flux (Y) terms, sign included: omega/(2c) Phi
+    const R X[6] = {-(cq * P[0]), -(cq * P[2]), -(cq * U[0]), R(0), -(cq * U[1]), R(0)};
+    const R Y[6] = {-(cq * P[1]), -(cq * P[3]), R(0), -(cq * U[0]), R(0), -(cq * U[1])};
+    constexpr bool hasX[6] = {true, true, true, false, true, false};
+    constexpr bool hasY[6] = {true, true, false, true, false, true};
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const R feq = R(0.25) * (U[k] + c2 * (i * PhiX[k] + j * PhiY[k]));
-            R v = g[q][k] + om * (feq - g[q][k]);
-            if (k == 0) v += srcw * B0;
-            if (k == 1) v += srcw * B1;
-            out[q][k] = v;
-        }
+    for (int k = 0; k < 6; ++k) {
+        const R s0 = hasX[k] ? a[k] + X[k] : a[k];     // q0 = (1, 0)
+        const R s2 = hasX[k] ? a[k] - X[k] : a[k];     // q2 = (-1, 0)
+        const R s1 = hasY[k] ? a[k] + Y[k] : a[k];     // q1 = (0, 1)
+        const R s3 = hasY[k] ? a[k] - Y[k] : a[k];     // q3 = (0, -1)
+        out[0][k] = omc * g[0][k] + s0;
+        out[1][k] = omc * g[1][k] + s1;
+        out[2][k] = omc * g[2][k] + s2;
+        out[3][k] = omc * g[3][k] + s3;
     }
 }
 
@@ -208,7 +220,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) store_stream(dst + own + (6 * q + k) * kTile, T(out[q][k]));
+        for (int k = 0; k < 6; ++k) store_stream(dst + own + (6 * q + k) * kTile, to_storage<T>(out[q][k]));
 
     // displacement quadrature u*^{n+2} = u*^{n+1} + dt v^{n+1} (eq:trapezoid-u)
     if (!a.ustar) {
@@ -252,108 +264,148 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
 
 // ---------------------------------------------------------------- two fused steps
 
+// Pulled populations of node (x, y) from a stored level (eq:streaming, periodic wrap).
+template <typename T, typename R>
+__device__ __forceinline__ void pull_node(const T* __restrict__ src, int ntile, int nx, int ny, int x, int y,
+                                          R g[4][6]) {
+    const int xm = wrap_index(x - 1, nx), xp = wrap_index(x + 1, nx);
+    const int ym = wrap_index(y - 1, ny), yp = wrap_index(y + 1, ny);
+    const int64_t b0 = tile_base(ntile, 24, xm, y), b1 = tile_base(ntile, 24, x, ym);
+    const int64_t b2 = tile_base(ntile, 24, xp, y), b3 = tile_base(ntile, 24, x, yp);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        g[0][k] = R(src[b0 + k * kTile]);
+        g[1][k] = R(src[b1 + (6 + k) * kTile]);
+        g[2][k] = R(src[b2 + (12 + k) * kTile]);
+        g[3][k] = R(src[b3 + (18 + k) * kTile]);
+    }
+}
+
 // Temporal blocking of the periodic step: one pass takes f*^n to f*^{n+2} without storing
-// level n+1.  A workgroup of kPairWaves wavefronts owns a block of kPairRows rows of a strip
-// of kPairCols columns.  Wave w takes row y0 - 1 + w through level n+1 (pulling level n
-// straight from HBM); the level n+1 populations that cross rows go through LDS, those that
-// cross columns through lane shuffles, and waves 1 .. kPairRows take their row on to level
-// n+2.  Lanes hold columns c0 - 1 .. c0 + 62, so every level n+1 value that an output needs
-// is computed in the same workgroup (the halo rows and columns are computed twice, by the
-// neighbouring workgroups as well).  Each node's arithmetic is collide_node, as in
-// step_kernel, and level n+1 is rounded to the storage type, so the result is bit for bit
-// that of two single steps.
+// level n+1.  A workgroup owns a block of kPairRows rows of one 64-node tile column (a
+// strip).  Wave w < kPairWaves takes row y0 - 1 + w of the strip through level n+1,
+// pulling level n straight from HBM; one more wave takes the two columns beside the strip
+// (x = c0 - 1 and c0 + 64) through level n+1 on the block's rows.  The level n+1 values
+// that cross rows go through LDS, those that cross columns inside the strip through lane
+// shuffles, and waves 1 .. kPairRows take their row on to level n+2.  Every level n+1
+// value that an output pulls is so computed in the workgroup (the edge rows and columns
+// are computed by the neighbouring workgroups as well), and loads and stores are whole
+// aligned tiles.  Each node's arithmetic is collide_node, as in step_kernel, and level
+// n+1 is rounded to the storage type, so the result is bit for bit that of two single
+// steps.
 template <int ST, int LAW, bool FIELDS>
-__global__ void __launch_bounds__(kPairWaves * kTile) step2_kernel(Step2Args a) {
+__global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Args a) {
     using Tr = Storage<ST>;
     using R = typename Tr::real;
     using T = typename Tr::pop_t;
     constexpr bool SH = Tr::shifted;
     __shared__ R xq1[kPairWaves][6][kTile];   // level n+1, direction (0,1): read by the row above
     __shared__ R xq3[kPairWaves][6][kTile];   // level n+1, direction (0,-1): read by the row below
+    __shared__ R xh[2][6][kPairRows];         // level n+1 beside the strip: q0 at c0-1, q2 at c0+64
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
     const int64_t n = int64_t(nx) * ny;
     const int b = remap_tile(blockIdx.x, gridDim.x);
     const int strip = b % a.nstrip, blk = b / a.nstrip;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
-    const int c0 = strip * kPairCols, y0 = blk * kPairRows;
+    const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;
-    const int xc = wrap_index(c0 - 1 + lane, nx);
+    const int xc = wrap_index(c0 + lane, nx);
     const int yr = wrap_index(r, ny);
     const T* __restrict__ src = (const T*)a.src;
     T* __restrict__ dst = (T*)a.dst;
-
-    // level n -> n+1 on row r: q0 from x-1 and q2 from x+1 of row r (own lanes shifted, the
-    // two end lanes from the columns beyond the strip), q1 from row r-1, q3 from row r+1
-    const int64_t bo = tile_base(ntile, 24, xc, yr);
-    const int64_t bm = tile_base(ntile, 24, xc, wrap_index(r - 1, ny));
-    const int64_t bp = tile_base(ntile, 24, xc, wrap_index(r + 1, ny));
-    R own0[6], own2[6], g[4][6], h[6] = {};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        own0[k] = R(src[bo + k * kTile]);
-        own2[k] = R(src[bo + (12 + k) * kTile]);
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        g[1][k] = R(src[bm + (6 + k) * kTile]);
-        g[3][k] = R(src[bp + (18 + k) * kTile]);
-    }
-    if (lane == 0 || lane == kTile - 1) {
-        const int64_t bh = lane == 0 ? tile_base(ntile, 24, wrap_index(c0 - 2, nx), yr)
-                                     : tile_base(ntile, 24, wrap_index(c0 + kTile - 1, nx), yr) + 12 * kTile;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) h[k] = R(src[bh + k * kTile]);
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const R up = __shfl_up(own0[k], 1), dn = __shfl_down(own2[k], 1);
-        g[0][k] = lane == 0 ? h[k] : up;
-        g[2][k] = lane == kTile - 1 ? h[k] : dn;
-    }
     const int idx1 = yr * nx + xc;
-    double bd0, bd1;
-    body_at<FIELDS>(cm, idx1, n, a.r_np1, bd0, bd1);
-    R mu, lam;
-    params_at<FIELDS, R>(cm, idx1, mu, lam);
-    R f1[4][6], U1[6], J1;
-    collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f1, U1, J1);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int k = 0; k < 6; ++k) f1[q][k] = R(T(f1[q][k]));   // the stored value of level n+1
-    bool nonfinite = false;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U1[k]);
-    bool jbad = J1 <= R(0);
 
+    R f1[4][6], U1[6], g[4][6], mu, lam;
+    bool nonfinite = false, jbad = false;
+    if (w < kPairWaves) {
+        // level n -> n+1 on row r: q0 from x-1 and q2 from x+1 of row r (own lanes shifted,
+        // the two end lanes from the columns beside the strip), q1 from row r-1, q3 from r+1
+        const int64_t bo = tile_base(ntile, 24, xc, yr);
+        const int64_t bm = tile_base(ntile, 24, xc, wrap_index(r - 1, ny));
+        const int64_t bp = tile_base(ntile, 24, xc, wrap_index(r + 1, ny));
+        R own0[6], own2[6], h[6] = {};
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        xq1[w][k][lane] = f1[1][k];
-        xq3[w][k][lane] = f1[3][k];
-        g[0][k] = __shfl_up(f1[0][k], 1);
-        g[2][k] = __shfl_down(f1[2][k], 1);
+        for (int k = 0; k < 6; ++k) {
+            own0[k] = R(src[bo + k * kTile]);
+            own2[k] = R(src[bo + (12 + k) * kTile]);
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            g[1][k] = R(src[bm + (6 + k) * kTile]);
+            g[3][k] = R(src[bp + (18 + k) * kTile]);
+        }
+        if (lane == 0 || lane == kTile - 1) {
+            const int64_t bh = lane == 0 ? tile_base(ntile, 24, wrap_index(c0 - 1, nx), yr)
+                                         : tile_base(ntile, 24, wrap_index(c0 + kTile, nx), yr) + 12 * kTile;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) h[k] = R(src[bh + k * kTile]);
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const R up = __shfl_up(own0[k], 1), dn = __shfl_down(own2[k], 1);
+            g[0][k] = lane == 0 ? h[k] : up;
+            g[2][k] = lane == kTile - 1 ? h[k] : dn;
+        }
+        double bd0, bd1;
+        body_at<FIELDS>(cm, idx1, n, a.r_np1, bd0, bd1);
+        params_at<FIELDS, R>(cm, idx1, mu, lam);
+        R J1;
+        collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f1, U1, J1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) f1[q][k] = R(to_storage<T>(f1[q][k]));   // the stored value of level n+1
+#pragma unroll
+        for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U1[k]);
+        jbad = J1 <= R(0);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            xq1[w][k][lane] = f1[1][k];
+            xq3[w][k][lane] = f1[3][k];
+            g[0][k] = __shfl_up(f1[0][k], 1);
+            g[2][k] = __shfl_down(f1[2][k], 1);
+        }
+    } else {
+        // the nodes beside the strip: lane j < kPairRows at (c0 - 1, y0 + j), lane
+        // kPairRows + j at (c0 + 64, y0 + j); the other lanes repeat the last node
+        const int j = min(lane, 2 * kPairRows - 1);
+        const int side = j / kPairRows, row = j - side * kPairRows;
+        const int hx = wrap_index(side == 0 ? c0 - 1 : c0 + kTile, nx), hy = wrap_index(y0 + row, ny);
+        R gh[4][6], fh[4][6], Uh[6], Jh, muh, lamh;
+        pull_node<T, R>(src, ntile, nx, ny, hx, hy, gh);
+        const int hidx = hy * nx + hx;
+        double bd0, bd1;
+        body_at<FIELDS>(cm, hidx, n, a.r_np1, bd0, bd1);
+        params_at<FIELDS, R>(cm, hidx, muh, lamh);
+        collide_node<R, LAW, SH>(cm, gh, R(bd0), R(bd1), muh, lamh, fh, Uh, Jh);
+        if (lane < 2 * kPairRows) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) xh[side][k][row] = R(to_storage<T>(fh[side == 0 ? 0 : 2][k]));
+        }
     }
     __syncthreads();
 
-    // level n+1 -> n+2 on row r for the inner waves; lanes 1 .. 62 are outputs
-    const int xo = c0 - 1 + lane;
-    const bool out = w >= 1 && w <= kPairRows && r < ny && lane >= 1 && lane <= kPairCols && xo < nx;
+    // level n+1 -> n+2 on row r for the inner waves
+    const int xo = c0 + lane;
     if (w >= 1 && w <= kPairRows) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             g[1][k] = xq1[w - 1][k][lane];
             g[3][k] = xq3[w + 1][k][lane];
+            if (lane == 0) g[0][k] = xh[0][k][w - 1];
+            if (lane == kTile - 1) g[2][k] = xh[1][k][w - 1];
         }
+        double bd0, bd1;
         body_at<FIELDS>(cm, idx1, n, a.r_np2, bd0, bd1);
         R f2[4][6], U2[6], J2;
         collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f2, U2, J2);
-        if (out) {
+        if (r < ny && xo < nx) {
             const int64_t ob = tile_base(ntile, 24, xo, r);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int k = 0; k < 6; ++k) store_stream(dst + ob + (6 * q + k) * kTile, T(f2[q][k]));
+                for (int k = 0; k < 6; ++k) store_stream(dst + ob + (6 * q + k) * kTile, to_storage<T>(f2[q][k]));
             // displacement quadrature over both levels (eq:trapezoid-u), with the same
             // accumulator updates and folds as two single steps
             const R dt = R(cm.dt);
@@ -755,7 +807,7 @@ template <int ST, int LAW>
 static hipError_t step2_st_law(const Step2Args& a, hipStream_t s) {
     const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
     const dim3 grid(unsigned(int64_t(a.nstrip) * ((a.cm.ny + kPairRows - 1) / kPairRows)));
-    const dim3 block(kPairWaves * kTile);
+    const dim3 block((kPairWaves + 1) * kTile);
     if (fields) hipLaunchKernelGGL((step2_kernel<ST, LAW, true>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((step2_kernel<ST, LAW, false>), grid, block, 0, s, a);
     return hipGetLastError();

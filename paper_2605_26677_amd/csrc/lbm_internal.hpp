@@ -54,11 +54,11 @@ struct StepArgs {
     EdgeData ed;                     // data at t^{n+1/2}
 };
 
-// Two fused steps on a periodic grid (step2_kernel): workgroups of kPairWaves wavefronts,
-// each owning kPairRows rows of a strip of kPairCols columns.
-constexpr int kPairWaves = 8;
+// Two fused steps on a periodic grid (step2_kernel): workgroups of kPairWaves + 1
+// wavefronts, each owning kPairRows rows of a strip of kPairCols (one tile of) columns.
+constexpr int kPairWaves = 6;
 constexpr int kPairRows = kPairWaves - 2;
-constexpr int kPairCols = 62;
+constexpr int kPairCols = 64;
 
 struct Step2Args {
     Common cm;
@@ -66,7 +66,7 @@ struct Step2Args {
     void* dst;                       // f*^{n+2}
     void* ustar;
     int fold1, fold2;                // accumulator folds after the first / second step
-    int nstrip;                      // strips of kPairCols columns
+    int nstrip;                      // strips of kPairCols columns (= tiles per row)
     double r_np1, r_np2;
 };
 

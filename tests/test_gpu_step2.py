@@ -63,7 +63,6 @@ def _pair_vs_single(case, storage, start, pairs):
         pair.step2(n, case.ramp(n + 1), case.ramp(n + 2))
         n += 2
     torch.cuda.synchronize()
-    assert single.s.cur == pair.s.cur
     assert torch.equal(single.populations(), pair.populations())
     for a, b in zip(_ustar_words(single), _ustar_words(pair)):
         if a is not None:
@@ -133,8 +132,7 @@ def test_advance_in_pairs_equals_single_steps():
     N = 151
     for m in range(N):
         eager.step(m, case.ramp(m), case.ramp(m + 1))
-    adv.advance(0, N, ramp=case.ramp, block=32)
-    assert eager.s.cur == adv.s.cur
+    adv.advance(0, N, ramp=case.ramp, block=32)     # a pair flips the buffers once per two levels
     assert torch.equal(eager.populations(), adv.populations())
     assert torch.equal(eager.displacement(case.ramp(N)), adv.displacement(case.ramp(N)))
 
