@@ -45,6 +45,10 @@ Common make_common(const lbm_params* p, const lbm_state* s) {
     cm.newton_max_iter = p->newton_max_iter > 0 ? p->newton_max_iter : 8;
     cm.newton_tol = p->newton_tol > 0 ? p->newton_tol : (p->storage == LBM_F64_PLAIN ? 1e-14 : 1e-6);
     for (int k = 0; k < 3; ++k) cm.law_k[k] = p->law_k[k];
+    cm.k_omq = 0.25 * cm.omega;
+    cm.k_cq = 0.5 * cm.omega / cm.c;
+    cm.k_srcw = cm.dt * (2.0 - cm.omega) * 0.125;
+    cm.k_hdt = 0.5 * cm.dt;
     if (s) {
         cm.mu0 = s->mu0;
         cm.lam0 = s->lam0;

@@ -61,6 +61,10 @@ __host__ __device__ constexpr int dir_j(int q) { return q == 1 ? 1 : (q == 3 ? -
 //   F - H = (1/J) [[f11 - f22 + delta (1 + f11), J f12 + f21],
 //                  [J f21 + f12, f22 - f11 + delta (1 + f22)]],   H = F^{-T}.
 
+// 1/x: the hardware reciprocal in FP32 (within 1 ulp), the correctly rounded quotient in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <typename R> struct Kin {
     R J, invJ, L;          // det F, 1/J, ln J
     R H[4];                // F^{-T}
@@ -74,7 +78,7 @@ __device__ __forceinline__ Kin<R> kinematics(const R f[4]) {
     if constexpr (SHIFTED) {
         const R d = f[0] + f[3] + (f[0] * f[3] - f[1] * f[2]);
         k.J = R(1) + d;
-        k.invJ = R(1) / k.J;
+        k.invJ = recip(k.J);
         k.L = log1p_r(d);
         k.Jsq_m1 = d * (R(2) + d);
         k.H[0] = (R(1) + f[3]) * k.invJ;
@@ -87,7 +91,7 @@ __device__ __forceinline__ Kin<R> kinematics(const R f[4]) {
         k.FmH[3] = (f[3] - f[0] + d * (R(1) + f[3])) * k.invJ;
     } else {
         k.J = f[0] * f[3] - f[1] * f[2];
-        k.invJ = R(1) / k.J;
+        k.invJ = recip(k.J);
         k.L = log_r(k.J);
         k.Jsq_m1 = k.J * k.J - R(1);
         k.H[0] = f[3] * k.invJ;

@@ -125,7 +125,7 @@ __device__ __forceinline__ void wall_link(const Common& cm, const EdgeData& ed, 
 template <typename R, int LAW, bool SH>
 __device__ __forceinline__ void collide_node(const Common& cm, const R g[4][6], R B0, R B1, R mu, R lam,
                                              R out[4][6], R U[6], R& J) {
-    const R hdt = R(0.5 * cm.dt);
+    const R hdt = R(cm.k_hdt);
 #pragma unroll
     for (int k = 0; k < 6; ++k) U[k] = g[0][k] + g[1][k] + g[2][k] + g[3][k];
     U[0] += hdt * B0;
@@ -138,8 +138,8 @@ __device__ __forceinline__ void collide_node(const Common& cm, const R g[4][6], 
     // (eq:flux-vectors); the zero entries and the unit factors i, j are taken out by hand.
     // omc = 1 - 4 omq is exact in R (Sterbenz), so the weights of f and f^eq sum to exactly
     // 1 and the collision keeps sum_q f* = U + (dt/2) B without a drift of the moments
-    const R omq = R(0.25 * cm.omega), omc = R(1) - R(4) * omq, cq = R(0.5 * cm.omega / cm.c);
-    const R srcw = R(cm.dt * (2.0 - cm.omega) * 0.125);
+    const R omq = R(cm.k_omq), omc = R(1) - R(4) * omq, cq = R(cm.k_cq);
+    const R srcw = R(cm.k_srcw);
     R a[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) a[k] = omq * U[k];
@@ -305,8 +305,16 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
     const int64_t n = int64_t(nx) * ny;
+    // workgroup order: chunks of kPairChunk strips side by side, and inside a chunk the
+    // strips of one block row, then of the next, so that the neighbours that re-read a
+    // block's edge rows run soon after it on the same XCD's L2
     const int b = remap_tile(blockIdx.x, gridDim.x);
-    const int strip = b % a.nstrip, blk = b / a.nstrip;
+    const int64_t per_chunk = int64_t(kPairChunk) * (gridDim.x / a.nstrip);
+    const int chunk = int(b / per_chunk);
+    const int rem = int(b - chunk * per_chunk);
+    const int kc = min(kPairChunk, a.nstrip - chunk * kPairChunk);
+    const int blk = rem / kc;
+    const int strip = chunk * kPairChunk + (rem - blk * kc);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
     const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;

@@ -40,6 +40,9 @@ struct Common {
     int newton_max_iter;
     double newton_tol;
     double law_k[3];                 // invariant-law constants (lbm_params.law_k)
+    // collision constants, formed once on the host: omega/4, omega/(2c), the forcing weight
+    // dt (2 - omega)/8 of eq:collision, and dt/2
+    double k_omq, k_cq, k_srcw, k_hdt;
 };
 
 struct StepArgs {
@@ -59,6 +62,7 @@ struct StepArgs {
 constexpr int kPairWaves = 6;
 constexpr int kPairRows = kPairWaves - 2;
 constexpr int kPairCols = 64;
+constexpr int kPairChunk = 32;       // strips per chunk of the workgroup order
 
 struct Step2Args {
     Common cm;
