@@ -214,11 +214,12 @@ lbm_status lbm_step(const lbm_params *p, lbm_state *s, int64_t n, double r_n, do
  * half the HBM traffic per level.  Flips s->cur on success.
  *   r_np1, r_np2: body-force factors at levels n+1 and n+2; the body field s->body (or
  *     the uniform b0) is the same at both levels.
+ *   record1, record2: device, lbm_record_bytes() each, receive U^{n+1} and U^{n+2} (v,
+ *     F - I) as lbm_step's record would; either may be NULL.
  * Every edge must be periodic (LBM_ERR_UNSUPPORTED otherwise: the traction rule needs
- * level n+1 along a whole wall).  No record is written; use lbm_step where U^{n+1} is
- * needed. */
+ * level n+1 along a whole wall). */
 lbm_status lbm_step2(const lbm_params *p, lbm_state *s, int64_t n, double r_np1, double r_np2,
-                     void *stream);
+                     void *record1, void *record2, void *stream);
 
 /* Displacement at the current level n (eq:trapezoid-u): u^n = u*^{n+1} - (dt/2) v^n with
  * v^n recovered from the stored post-collision populations (sum_q f* = U + (dt/2) B).

@@ -221,7 +221,8 @@ lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, do
     return LBM_OK;
 }
 
-lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_np1, double r_np2, void* stream) {
+lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_np1, double r_np2, void* record1,
+                     void* record2, void* stream) {
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
     if (any_wall(p)) return LBM_ERR_UNSUPPORTED;
@@ -231,6 +232,8 @@ lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_np1,
     a.src = s->pop[s->cur];
     a.dst = s->pop[1 - s->cur];
     a.ustar = s->ustar;
+    a.record1 = record1;
+    a.record2 = record2;
     a.fold1 = (n + 1) % kUstarBlock == 0;
     a.fold2 = (n + 2) % kUstarBlock == 0;
     a.nstrip = (p->nx + kPairCols - 1) / kPairCols;

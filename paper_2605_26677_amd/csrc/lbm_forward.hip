@@ -163,6 +163,18 @@ __device__ __forceinline__ void collide_node(const Common& cm, const R g[4][6], 
     }
 }
 
+// The state record of one node (lbm_record_bytes: v and F - I, 6 tiled planes).
+template <typename R, bool SH>
+__device__ __forceinline__ void write_record(void* record, int ntile, int x, int y, const R U[6]) {
+    R* rec = (R*)record + tile_base(ntile, 6, x, y);
+    rec[0] = U[0];
+    rec[kTile] = U[1];
+    rec[2 * kTile] = SH ? U[2] : U[2] - R(1);
+    rec[3 * kTile] = U[3];
+    rec[4 * kTile] = U[4];
+    rec[5 * kTile] = SH ? U[5] : U[5] - R(1);
+}
+
 template <int ST, int LAW, bool WALLS, bool FIELDS>
 __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     using Tr = Storage<ST>;
@@ -244,15 +256,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
         }
     }
 
-    if (a.record) {
-        R* rec = (R*)a.record + tile_base(ntile, 6, x, y);
-        rec[0] = U[0];
-        rec[kTile] = U[1];
-        rec[2 * kTile] = SH ? U[2] : U[2] - R(1);
-        rec[3 * kTile] = U[3];
-        rec[4 * kTile] = U[4];
-        rec[5 * kTile] = SH ? U[5] : U[5] - R(1);
-    }
+    if (a.record) write_record<R, SH>(a.record, ntile, x, y, U);
 
     bool nonfinite = false;
 #pragma unroll
@@ -445,6 +449,8 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
                     store_stream(rf.S + cpt * kTile, sn);
                 }
             }
+            if (a.record1) write_record<R, SH>(a.record1, ntile, xo, r, U1);
+            if (a.record2) write_record<R, SH>(a.record2, ntile, xo, r, U2);
 #pragma unroll
             for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U2[k]);
             jbad |= J2 <= R(0);

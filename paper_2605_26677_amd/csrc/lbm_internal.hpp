@@ -69,6 +69,8 @@ struct Step2Args {
     const void* src;                 // f*^n
     void* dst;                       // f*^{n+2}
     void* ustar;
+    void* record1;                   // U^{n+1} or NULL
+    void* record2;                   // U^{n+2} or NULL
     int fold1, fold2;                // accumulator folds after the first / second step
     int nstrip;                      // strips of kPairCols columns (= tiles per row)
     double r_np1, r_np2;

@@ -239,13 +239,34 @@ def _step_to_snapshot(sv, cfg, n, ustar=True):
     return (sv.pop[sv.s.cur].clone(), rec)
 
 
+def _plain_steps(sv, cfg, n0, n1, ustar=True):
+    """Steps n0 .. n1 - 1 without records; on periodic grids in pairs through lbm_step2
+    (bit for bit the same result as single steps)."""
+    n = n0
+    while n < n1:
+        if sv.periodic and n + 1 < n1:
+            sv.step2(n, cfg.ramp(n + 1), cfg.ramp(n + 2), ustar=ustar)
+            n += 2
+        else:
+            sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), ustar=ustar)
+            n += 1
+
+
 def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
     """Adjoint levels end-1 .. start, starting from the snapshot of level `start`.  The
-    replay skips the displacement quadrature (the adjoint does not read u*)."""
+    replay skips the displacement quadrature (the adjoint does not read u*) and records
+    U of every level, two levels per call on periodic grids."""
     _restore(sv, snap)
     recs[0].copy_(snap[1], non_blocking=True)
-    for n in range(start, end - 1):
-        sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=recs[n + 1 - start], ustar=False)
+    n = start
+    while n < end - 1:
+        if sv.periodic and n + 1 < end - 1:
+            sv.step2(n, cfg.ramp(n + 1), cfg.ramp(n + 2), record1=recs[n + 1 - start],
+                     record2=recs[n + 2 - start], ustar=False)
+            n += 2
+        else:
+            sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=recs[n + 1 - start], ustar=False)
+            n += 1
     for m in range(end - 1, start - 1, -1):
         adj.step(sv, cfg, m, recs[m - start])
 
@@ -261,8 +282,7 @@ def _reverse_nested(sv, cfg, adj, start, end, snap, lengths, recs):
     snaps = [snap]
     _restore(sv, snap)
     for i in range(len(bounds) - 2):
-        for n in range(bounds[i], bounds[i + 1] - 1):
-            sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), ustar=False)
+        _plain_steps(sv, cfg, bounds[i], bounds[i + 1] - 1, ustar=False)
         snaps.append(_step_to_snapshot(sv, cfg, bounds[i + 1] - 1, ustar=False))
     for i in range(len(bounds) - 2, -1, -1):
         _reverse_nested(sv, cfg, adj, bounds[i], bounds[i + 1], snaps[i], lengths[1:], recs)
@@ -294,12 +314,16 @@ class LBMRollout(torch.autograd.Function):
         snaps = {0: (sv.pop[sv.s.cur].clone(), sv.record_state(cfg.ramp(0), sv.new_record()))} if keep else {}
         if keep and cfg.host_top:
             snaps[0] = tuple(_host_copy(t) for t in snaps[0])
-        for n in range(N):
-            if keep and (n + 1) % K == 0:
+        n = 0
+        while n < N:
+            # plain steps up to the next snapshot step (the one that reaches a multiple of K)
+            end = min(N, (n // K + 1) * K - 1) if keep else N
+            _plain_steps(sv, cfg, n, end)
+            n = end
+            if n < N:
                 snap = _step_to_snapshot(sv, cfg, n)
                 snaps[n + 1] = tuple(_host_copy(t) for t in snap) if cfg.host_top else snap
-            else:
-                sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n))
+                n += 1
         u = sv.displacement(cfg.ramp(N))
         probes = cfg.probes.to(device=mu.device, dtype=torch.long)
         out = u.reshape(2, -1)[:, probes]

@@ -213,15 +213,16 @@ class Solver:
         finally:
             self.s.ustar = keep
 
-    def step2(self, n, r_np1=1.0, r_np2=1.0, ustar=True):
+    def step2(self, n, r_np1=1.0, r_np2=1.0, record1=None, record2=None, ustar=True):
         """lbm_step2: levels n -> n + 2 in one pass (periodic grids), bit for bit the same as
-        step(n) then step(n + 1) with the same factors."""
+        step(n) then step(n + 1) with the same factors; record1 / record2 receive U^{n+1} and
+        U^{n+2}."""
         keep = self.s.ustar
         if not ustar:
             self.s.ustar = None
         try:
             L.check(self.lib.lbm_step2(ctypes.byref(self.p), ctypes.byref(self.s), int(n), float(r_np1),
-                                       float(r_np2), _stream()), "lbm_step2")
+                                       float(r_np2), _ptr(record1), _ptr(record2), _stream()), "lbm_step2")
         finally:
             self.s.ustar = keep
 

@@ -176,7 +176,7 @@ def test_step2_periodic_only():
     fake = 256
     s = L.lbm_state()
     p = _params()
-    assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, None) == L.LBM_ERR_ARG
+    assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, None, None, None) == L.LBM_ERR_ARG
     s.pop[0], s.pop[1], s.fault = fake, fake, fake
     p = _params(bc=(L.LBM_VELOCITY, L.LBM_TRACTION, 0, 0))
-    assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, None) == L.LBM_ERR_UNSUPPORTED
+    assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, None, None, None) == L.LBM_ERR_UNSUPPORTED

@@ -111,6 +111,34 @@ def test_step2_matches_oracle(storage, bar):
     assert ev <= bar and eF <= bar and eu <= bar
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
+def test_step2_records_equal_single_step_records(storage):
+    """The records of both levels (the checkpointed adjoint replays through them) are bit
+    for bit those of two lbm_step calls; also with the displacement quadrature skipped."""
+    case = _case(150, 37, fields=True)
+    single = make_solver(case, storage)
+    pair = make_solver(case, storage)
+    for sv in (single, pair):
+        sv.init(case.v0, r0=case.ramp(0))
+    for n in range(0, 12, 2):
+        ra, rb = single.new_record(), single.new_record()
+        pa, pb = pair.new_record(), pair.new_record()
+        ustar = n % 4 == 0
+        single.step(n, case.ramp(n), case.ramp(n + 1), record=ra, ustar=ustar)
+        single.step(n + 1, case.ramp(n + 1), case.ramp(n + 2), record=rb, ustar=ustar)
+        pair.step2(n, case.ramp(n + 1), case.ramp(n + 2), record1=pa, record2=pb, ustar=ustar)
+        torch.cuda.synchronize()
+        w = int(single.lib.lbm_tile_width())
+        T = single.tiles_per_row
+
+        def valid(r):
+            return r.view(case.ny, T, 6, w).permute(2, 0, 1, 3).reshape(6, case.ny, T * w)[:, :, :case.nx]
+        assert torch.equal(valid(ra), valid(pa)), n
+        assert torch.equal(valid(rb), valid(pb)), n
+    assert torch.equal(single.populations(), pair.populations())
+    assert single.faults() == pair.faults() == 0
+
+
 def test_step2_refuses_walls():
     from paper_2605_26677_amd._lib import LBMError
     case = _case(32, 32)
