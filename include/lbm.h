@@ -289,6 +289,32 @@ lbm_status lbm_adjoint_step(const lbm_params *p, const lbm_state *fwd, lbm_adj_s
                             int64_t m, double r_m, const lbm_edge_data *at_half,
                             const void *record_m, void *stream);
 
+/* Bytes of the probe mask of lbm_adjoint_step2: one 64-bit word per row of each 64-node
+ * tile (bit a mod 64 of word b * T + a / 64 marks node (a, b)). */
+size_t lbm_probe_mask_bytes(const lbm_params *p);
+
+/* Fills the probe table that lbm_adjoint_step2 reads, from a->probe and a->ubar (distinct
+ * cells): mask (device, lbm_probe_mask_bytes()) and field (device, 2 double planes of
+ * dL/du^N, zero away from the probes).  Clears both first (fill kernels, no memset).  Call
+ * once per backward pass, after a->probe and a->ubar are set. */
+lbm_status lbm_adjoint_probe_table(const lbm_params *p, const lbm_adj_state *a, uint64_t *mask,
+                                   double *field, void *stream);
+
+/* Two adjoint levels m and m - 1 in one pass over the grid (temporal blocking of
+ * lbm_adjoint_step; lambda^m stays on chip): lambda^{m+1} in a->adj[a->cur] -> lambda^{m-1}
+ * in a->adj[1 - a->cur], with the gradient updates and probe sources of both levels.  The
+ * result, the block sums and the FP64 gradients are those of lbm_adjoint_step(m) followed
+ * by lbm_adjoint_step(m - 1), bit for bit.  Flips a->cur.
+ *   r_m, r_mm1: body factors at levels m and m - 1.
+ *   record_m, record_mm1: device, U^m and U^{m-1} as lbm_adjoint_step reads them.
+ *   mask, field: the probe table (lbm_adjoint_probe_table); may be NULL when a->nprobe = 0.
+ * Requires every edge periodic (LBM_ERR_UNSUPPORTED otherwise) and 1 <= m < a->nsteps:
+ * level N carries the half-weight probe term and takes lbm_adjoint_step. */
+lbm_status lbm_adjoint_step2(const lbm_params *p, const lbm_state *fwd, lbm_adj_state *a,
+                             int64_t m, double r_m, double r_mm1, const void *record_m,
+                             const void *record_mm1, const uint64_t *mask, const double *field,
+                             void *stream);
+
 /* Adjoint of lbm_init: from lambda^0 = dL/df(0) in a->adj[a->cur], writes dL/dv0 into
  * g_v0 (device, 2 double planes; includes the direct term of u*^0 = u0 - (dt/2) v0) and
  * adds the initialisation parts of dL/dmu, dL/dlam, dL/db.  v0, u0, Fbar, r0 as given to

@@ -24,6 +24,52 @@ __device__ __forceinline__ R D_sign(int bc, int k) {
     return vrow ? R(1) : R(-1);
 }
 
+// One node of the adjoint step (see above): the pulled lambda*^m l and the state F - I of
+// the record -> lambda^m (out) and the increments of this level's parameter gradients
+// (inc: mu, lam, b1, b2; zero where not asked for).
+template <typename R, int LAW>
+__device__ __forceinline__ void adj_node(const Common& cm, const R l[4][6], const R ft[4], R mu, R lam, R rm,
+                                         bool grad_par, bool grad_body, R out[4][6], R inc[4]) {
+    R C[16];
+    tangent<R, LAW, true>(ft, mu, lam, law_consts<R>(cm), C);
+    R s6[6], dxl[6], dyl[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        s6[k] = l[0][k] + l[1][k] + l[2][k] + l[3][k];
+        dxl[k] = l[0][k] - l[2][k];
+        dyl[k] = l[1][k] - l[3][k];
+    }
+    R AT[6];
+    AT[0] = -dxl[2] - dyl[3];
+    AT[1] = -dxl[4] - dyl[5];
+#pragma unroll
+    for (int kB = 0; kB < 4; ++kB)
+        AT[2 + kB] = -(dxl[0] * C[kB] + dxl[1] * C[8 + kB]) - (dyl[0] * C[4 + kB] + dyl[1] * C[12 + kB]);
+    const R om = R(cm.omega);
+    const R c2 = R(cm.k_c2);
+    R gU[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gU[k] = om * R(0.25) * (s6[k] + c2 * AT[k]);
+    const R omc = R(1) - om;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) out[q][k] = omc * l[q][k] + gU[k];
+    const R hc = R(cm.k_hc);
+    inc[0] = inc[1] = inc[2] = inc[3] = R(0);
+    if (grad_par) {
+        R Pm[4], Pl[4];
+        piola_partials<R, LAW, true>(ft, law_consts<R>(cm), Pm, Pl);
+        inc[0] = om * hc * -(dxl[0] * Pm[0] + dxl[1] * Pm[2] + dyl[0] * Pm[1] + dyl[1] * Pm[3]);
+        inc[1] = om * hc * -(dxl[0] * Pl[0] + dxl[1] * Pl[2] + dyl[0] * Pl[1] + dyl[1] * Pl[3]);
+    }
+    if (grad_body) {
+        const R hdtr = R(cm.k_hdt), srcw = R(cm.k_srcw);
+        inc[2] = rm * (hdtr * gU[0] + srcw * s6[0]);
+        inc[3] = rm * (hdtr * gU[1] + srcw * s6[1]);
+    }
+}
+
 template <int ST, int LAW, bool WALLS, bool FIELDS>
 __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
     using R = typename Storage<ST>::real;
@@ -67,50 +113,17 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
     for (int k = 0; k < 4; ++k) ft[k] = rec[(2 + k) * kTile];
     R mu, lam;
     params_at<FIELDS, R>(cm, idx, mu, lam);
-    R C[16];
-    tangent<R, LAW, true>(ft, mu, lam, law_consts<R>(cm), C);
-
-    R s6[6], dxl[6], dyl[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        s6[k] = l[0][k] + l[1][k] + l[2][k] + l[3][k];
-        dxl[k] = l[0][k] - l[2][k];
-        dyl[k] = l[1][k] - l[3][k];
-    }
-    R AT[6];
-    AT[0] = -dxl[2] - dyl[3];
-    AT[1] = -dxl[4] - dyl[5];
-#pragma unroll
-    for (int kB = 0; kB < 4; ++kB)
-        AT[2 + kB] = -(dxl[0] * C[kB] + dxl[1] * C[8 + kB]) - (dyl[0] * C[4 + kB] + dyl[1] * C[12 + kB]);
-    const R om = R(cm.omega);
-    const R c2 = R(2.0 / cm.c);
-    R gU[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) gU[k] = om * R(0.25) * (s6[k] + c2 * AT[k]);
-    const R omc = R(1) - om;
+    R out[4][6], inc[4];
+    adj_node<R, LAW>(cm, l, ft, mu, lam, R(a.r_m), a.g_mu || a.g_lam, a.g_body != nullptr, out, inc);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) store_stream(dst + own + (6 * q + k) * kTile, omc * l[q][k] + gU[k]);
+        for (int k = 0; k < 6; ++k) store_stream(dst + own + (6 * q + k) * kTile, out[q][k]);
 
     // parameter gradients of this level's collision.  FP64 storage adds them to the FP64
     // gradients directly; the shifted storages sum them in FP32 per block (gsum, 4 tiled
     // planes mu, lam, b1, b2) and move the block sums into the FP64 gradients at the
     // levels m with m % kGradBlock == 0 (the last adjoint step, m = 0, always folds)
-    const R hc = R(0.5 / cm.c);
-    R inc[4] = {R(0), R(0), R(0), R(0)};
-    if (a.g_mu || a.g_lam) {
-        R Pm[4], Pl[4];
-        piola_partials<R, LAW, true>(ft, law_consts<R>(cm), Pm, Pl);
-        inc[0] = om * hc * -(dxl[0] * Pm[0] + dxl[1] * Pm[2] + dyl[0] * Pm[1] + dyl[1] * Pm[3]);
-        inc[1] = om * hc * -(dxl[0] * Pl[0] + dxl[1] * Pl[2] + dyl[0] * Pl[1] + dyl[1] * Pl[3]);
-    }
-    if (a.g_body) {
-        const R hdtr = R(0.5 * cm.dt), srcw = R(cm.dt * (2.0 - cm.omega) * 0.125), rm = R(a.r_m);
-        inc[2] = rm * (hdtr * gU[0] + srcw * s6[0]);
-        inc[3] = rm * (hdtr * gU[1] + srcw * s6[1]);
-    }
     double* const g64[4] = {a.g_mu, a.g_lam, a.g_body, a.g_body ? a.g_body + n : nullptr};
     if constexpr (ST == LBM_F64_PLAIN) {
 #pragma unroll
@@ -269,6 +282,247 @@ __global__ void adj_probe_kernel(AdjArgs a) {
             for (int q = 0; q < 4; ++q) d[(6 * q + k) * kTile] += R(src);
             if (a.g_body) a.g_body[k * n + id] += a.r_m * hdt * src;
         }
+    }
+}
+
+// ---------------------------------------------------------------- two fused adjoint levels
+
+// Pulled adjoint populations lambda*_q(X) = lambda_q(X + c_q) of node (x, y), periodic wrap.
+template <typename R>
+__device__ __forceinline__ void pull_adj_node(const R* __restrict__ src, int ntile, int nx, int ny, int x, int y,
+                                              R l[4][6]) {
+    const int64_t b0 = tile_base(ntile, 24, wrap_index(x + 1, nx), y);
+    const int64_t b1 = tile_base(ntile, 24, x, wrap_index(y + 1, ny));
+    const int64_t b2 = tile_base(ntile, 24, wrap_index(x - 1, nx), y);
+    const int64_t b3 = tile_base(ntile, 24, x, wrap_index(y - 1, ny));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        l[0][k] = src[b0 + k * kTile];
+        l[1][k] = src[b1 + (6 + k) * kTile];
+        l[2][k] = src[b2 + (12 + k) * kTile];
+        l[3][k] = src[b3 + (18 + k) * kTile];
+    }
+}
+
+// Probe source of level m at node (x, y) if it is a probe (bit x mod 64 of the word of its
+// tile row): lambda^m_q += weight ubar for every q, as adj_probe_kernel adds it.
+template <typename R>
+__device__ __forceinline__ bool probe_at(const Adj2Args& a, int x, int y, double src[2]) {
+    if (!a.pmask) return false;
+    const uint64_t word = a.pmask[int64_t(y) * a.cm.ntile + (x >> 6)];
+    if (!((word >> (x & 63)) & 1ull)) return false;
+    const int64_t n = int64_t(a.cm.nx) * a.cm.ny, idx = int64_t(y) * a.cm.nx + x;
+    src[0] = a.probe_weight * a.pfield[idx];
+    src[1] = a.probe_weight * a.pfield[n + idx];
+    return true;
+}
+
+// Two adjoint levels m and m - 1 per pass on a periodic grid, the transpose of the two-level
+// forward kernel: a workgroup owns kPairRows rows of one 64-node strip; wave w takes row
+// y0 - 1 + w from lambda^{m+1} to lambda^m (with the probe source of level m), one more wave
+// the two columns beside the strip, and waves 1 .. kPairRows take their row on to
+// lambda^{m-1}.  The adjoint pulls from X + c_q, so the rows and columns exchanged are the
+// mirror images of the forward's.  Per node the arithmetic is adj_node, as in
+// adjoint_kernel, and the gradient updates of the two levels (block sums, folds, the probe
+// body term of level m) run in the order of two single steps, so the result is bit for
+// bit theirs; the probe source of level m - 1 is added afterwards by adj_probe_kernel.
+template <int ST, int LAW, bool FIELDS>
+__global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2Args a) {
+    using R = typename Storage<ST>::real;
+    __shared__ R xq1[kPairWaves][6][kTile];   // lambda^m, direction (0,1): pulled by the row below
+    __shared__ R xq3[kPairWaves][6][kTile];   // lambda^m, direction (0,-1): pulled by the row above
+    __shared__ R xh[2][6][kPairRows];         // beside the strip: q2 at c0-1, q0 at c0+64
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
+    const int64_t n = int64_t(nx) * ny;
+    const int b = remap_tile(blockIdx.x, gridDim.x);
+    const int64_t per_chunk = int64_t(kPairChunk) * (gridDim.x / a.nstrip);
+    const int chunk = int(b / per_chunk);
+    const int rem = int(b - chunk * per_chunk);
+    const int kc = min(kPairChunk, a.nstrip - chunk * kPairChunk);
+    const int blk = rem / kc;
+    const int strip = chunk * kPairChunk + (rem - blk * kc);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
+    const int c0 = strip * kTile, y0 = blk * kPairRows;
+    const int r = y0 - 1 + w;
+    const int xc = wrap_index(c0 + lane, nx);
+    const int yr = wrap_index(r, ny);
+    const int idx = yr * nx + xc;
+    const R* __restrict__ src = (const R*)a.src;
+    R* __restrict__ dst = (R*)a.dst;
+    const bool gpar = a.g_mu || a.g_lam, gbody = a.g_body != nullptr;
+
+    R l[4][6], lm[4][6], inc1[4], mu, lam;
+    double ps[2] = {0.0, 0.0};
+    bool probe = false;
+    if (w < kPairWaves) {
+        // lambda^{m+1} -> lambda^m on row r: q0 from x+1 and q2 from x-1 of row r (own
+        // lanes shifted, the end lanes from the columns beside the strip), q1 from row r+1,
+        // q3 from row r-1
+        const int64_t bo = tile_base(ntile, 24, xc, yr);
+        const int64_t bp = tile_base(ntile, 24, xc, wrap_index(r + 1, ny));
+        const int64_t bm = tile_base(ntile, 24, xc, wrap_index(r - 1, ny));
+        R own0[6], own2[6], h[6] = {};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            own0[k] = src[bo + k * kTile];
+            own2[k] = src[bo + (12 + k) * kTile];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            l[1][k] = src[bp + (6 + k) * kTile];
+            l[3][k] = src[bm + (18 + k) * kTile];
+        }
+        if (lane == 0 || lane == kTile - 1) {
+            const int64_t bh = lane == kTile - 1 ? tile_base(ntile, 24, wrap_index(c0 + kTile, nx), yr)
+                                                 : tile_base(ntile, 24, wrap_index(c0 - 1, nx), yr) + 12 * kTile;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) h[k] = src[bh + k * kTile];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const R dn = __shfl_down(own0[k], 1), up = __shfl_up(own2[k], 1);
+            l[0][k] = lane == kTile - 1 ? h[k] : dn;
+            l[2][k] = lane == 0 ? h[k] : up;
+        }
+        const R* rec = (const R*)a.rec1 + tile_base(ntile, 6, xc, yr);
+        R ft[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ft[k] = rec[(2 + k) * kTile];
+        params_at<FIELDS, R>(cm, idx, mu, lam);
+        adj_node<R, LAW>(cm, l, ft, mu, lam, R(a.r1), gpar, gbody, lm, inc1);
+        probe = probe_at<R>(a, xc, yr, ps);
+        if (probe) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                lm[q][0] += R(ps[0]);
+                lm[q][1] += R(ps[1]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            xq1[w][k][lane] = lm[1][k];
+            xq3[w][k][lane] = lm[3][k];
+            l[0][k] = __shfl_down(lm[0][k], 1);
+            l[2][k] = __shfl_up(lm[2][k], 1);
+        }
+    } else {
+        // the nodes beside the strip: lane j < kPairRows at (c0 - 1, y0 + j), lane
+        // kPairRows + j at (c0 + 64, y0 + j); the other lanes repeat the last node
+        const int j = min(lane, 2 * kPairRows - 1);
+        const int side = j / kPairRows, row = j - side * kPairRows;
+        const int hx = wrap_index(side == 0 ? c0 - 1 : c0 + kTile, nx), hy = wrap_index(y0 + row, ny);
+        R lh[4][6], oh[4][6], ih[4], muh, lamh, fth[4];
+        pull_adj_node<R>(src, ntile, nx, ny, hx, hy, lh);
+        const R* rec = (const R*)a.rec1 + tile_base(ntile, 6, hx, hy);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fth[k] = rec[(2 + k) * kTile];
+        params_at<FIELDS, R>(cm, hy * nx + hx, muh, lamh);
+        adj_node<R, LAW>(cm, lh, fth, muh, lamh, R(a.r1), false, false, oh, ih);
+        double hs[2];
+        if (probe_at<R>(a, hx, hy, hs)) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                oh[q][0] += R(hs[0]);
+                oh[q][1] += R(hs[1]);
+            }
+        }
+        if (lane < 2 * kPairRows) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) xh[side][k][row] = side == 0 ? oh[2][k] : oh[0][k];
+        }
+    }
+    __syncthreads();
+
+    // lambda^m -> lambda^{m-1} on row r for the inner waves
+    const int xo = c0 + lane;
+    if (w >= 1 && w <= kPairRows) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            l[1][k] = xq1[w + 1][k][lane];
+            l[3][k] = xq3[w - 1][k][lane];
+            if (lane == kTile - 1) l[0][k] = xh[1][k][w - 1];
+            if (lane == 0) l[2][k] = xh[0][k][w - 1];
+        }
+        const R* rec = (const R*)a.rec2 + tile_base(ntile, 6, xc, yr);
+        R ft[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ft[k] = rec[(2 + k) * kTile];
+        R out[4][6], inc2[4];
+        adj_node<R, LAW>(cm, l, ft, mu, lam, R(a.r2), gpar, gbody, out, inc2);
+        if (r < ny && xo < nx) {
+            const int64_t ob = tile_base(ntile, 24, xo, r);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) store_stream(dst + ob + (6 * q + k) * kTile, out[q][k]);
+            const int64_t gi = int64_t(r) * nx + xo;
+            double* const g64[4] = {a.g_mu, a.g_lam, a.g_body, a.g_body ? a.g_body + n : nullptr};
+            const double hdt = 0.5 * cm.dt;
+            if constexpr (ST == LBM_F64_PLAIN) {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    if (g64[jj]) g64[jj][gi] += double(inc1[jj]);
+                if (probe && a.g_body) {
+                    a.g_body[gi] += a.r1 * hdt * ps[0];
+                    a.g_body[n + gi] += a.r1 * hdt * ps[1];
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    if (g64[jj]) g64[jj][gi] += double(inc2[jj]);
+            } else if (g64[0] || g64[1] || g64[2]) {
+                float* gs = (float*)a.gsum + tile_base(ntile, 4, xo, r);
+                float sj[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    if (!g64[jj]) continue;
+                    sj[jj] = gs[jj * kTile] + float(inc1[jj]);
+                    if (a.fold1) {
+                        g64[jj][gi] += double(sj[jj]);
+                        sj[jj] = 0.0f;
+                    }
+                }
+                if (probe && a.g_body) {
+                    a.g_body[gi] += a.r1 * hdt * ps[0];
+                    a.g_body[n + gi] += a.r1 * hdt * ps[1];
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    if (!g64[jj]) continue;
+                    sj[jj] = sj[jj] + float(inc2[jj]);
+                    if (a.fold2) {
+                        g64[jj][gi] += double(sj[jj]);
+                        sj[jj] = 0.0f;
+                    }
+                    store_stream(gs + jj * kTile, sj[jj]);
+                }
+            } else if (probe && a.g_body) {
+                a.g_body[gi] += a.r1 * hdt * ps[0];
+                a.g_body[n + gi] += a.r1 * hdt * ps[1];
+            }
+        }
+    }
+}
+
+// The probe table of lbm_adjoint_step2: bit x mod 64 of word (y, x / 64) marks a probe,
+// field holds its ubar (2 planes).  One thread walks the probes (the buffers are cleared by
+// adj_probe_clear_kernel first).
+__global__ void adj_probe_clear_kernel(uint64_t* mask, int64_t nmask, double* field, int64_t nfield) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nmask) mask[i] = 0ull;
+    if (i < nfield) field[i] = 0.0;
+}
+
+__global__ void adj_probe_table_kernel(Common cm, const int32_t* probe, const double* ubar, int nprobe,
+                                       uint64_t* mask, double* field) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int64_t n = int64_t(cm.nx) * cm.ny;
+    for (int p = 0; p < nprobe; ++p) {
+        const int id = probe[p];
+        const int py = id / cm.nx, px = id - py * cm.nx;
+        mask[int64_t(py) * cm.ntile + (px >> 6)] |= 1ull << (px & 63);
+        field[id] = ubar[p];
+        field[n + id] = ubar[nprobe + p];
     }
 }
 
@@ -485,6 +739,56 @@ static void adj_init_st(const AdjInitArgs& a, hipStream_t s, dim3 grid) {
         case LBM_GENT: adj_init_st_law<ST, LBM_GENT>(a, s, grid); break;
         default: adj_init_st_law<ST, LBM_SVK>(a, s, grid); break;
     }
+}
+
+hipError_t launch_adjoint_probe(const AdjArgs& a, hipStream_t s) {
+    if (a.nprobe <= 0 || a.probe_weight == 0.0) return hipSuccess;
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: hipLaunchKernelGGL((adj_probe_kernel<LBM_F32_SHIFTED>), dim3(1), dim3(64), 0, s, a); break;
+        case LBM_F16_SHIFTED: hipLaunchKernelGGL((adj_probe_kernel<LBM_F16_SHIFTED>), dim3(1), dim3(64), 0, s, a); break;
+        default: hipLaunchKernelGGL((adj_probe_kernel<LBM_F64_PLAIN>), dim3(1), dim3(64), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int ST, int LAW>
+static hipError_t adjoint2_st_law(const Adj2Args& a, hipStream_t s) {
+    const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
+    const dim3 grid(unsigned(int64_t(a.nstrip) * ((a.cm.ny + kPairRows - 1) / kPairRows)));
+    const dim3 block((kPairWaves + 1) * kTile);
+    if (fields) hipLaunchKernelGGL((adjoint2_kernel<ST, LAW, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((adjoint2_kernel<ST, LAW, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t adjoint2_st(const Adj2Args& a, hipStream_t s) {
+    switch (a.cm.material) {
+        case LBM_LOGNH: return adjoint2_st_law<ST, LBM_LOGNH>(a, s);
+        case LBM_NH: return adjoint2_st_law<ST, LBM_NH>(a, s);
+        case LBM_MR: return adjoint2_st_law<ST, LBM_MR>(a, s);
+        case LBM_YEOH: return adjoint2_st_law<ST, LBM_YEOH>(a, s);
+        case LBM_GENT: return adjoint2_st_law<ST, LBM_GENT>(a, s);
+        default: return adjoint2_st_law<ST, LBM_SVK>(a, s);
+    }
+}
+
+hipError_t launch_adjoint2(const Adj2Args& a, hipStream_t s) {
+    switch (a.cm.storage) {
+        case LBM_F32_SHIFTED: return adjoint2_st<LBM_F32_SHIFTED>(a, s);
+        case LBM_F16_SHIFTED: return adjoint2_st<LBM_F16_SHIFTED>(a, s);
+        default: return adjoint2_st<LBM_F64_PLAIN>(a, s);
+    }
+}
+
+hipError_t launch_probe_table(const Common& cm, const int32_t* probe, const double* ubar, int nprobe,
+                              uint64_t* mask, double* field, hipStream_t s) {
+    const int64_t nmask = int64_t(cm.ntile) * cm.ny, nfield = 2 * int64_t(cm.nx) * cm.ny;
+    const int64_t m = nmask > nfield ? nmask : nfield;
+    hipLaunchKernelGGL(adj_probe_clear_kernel, dim3(nblk(m)), dim3(kBlock), 0, s, mask, nmask, field, nfield);
+    if (nprobe > 0)
+        hipLaunchKernelGGL(adj_probe_table_kernel, dim3(1), dim3(64), 0, s, cm, probe, ubar, nprobe, mask, field);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_init(const AdjInitArgs& a, hipStream_t s) {

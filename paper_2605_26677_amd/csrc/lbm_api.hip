@@ -49,6 +49,8 @@ Common make_common(const lbm_params* p, const lbm_state* s) {
     cm.k_cq = 0.5 * cm.omega / cm.c;
     cm.k_srcw = cm.dt * (2.0 - cm.omega) * 0.125;
     cm.k_hdt = 0.5 * cm.dt;
+    cm.k_c2 = 2.0 / cm.c;
+    cm.k_hc = 0.5 / cm.c;
     if (s) {
         cm.mu0 = s->mu0;
         cm.lam0 = s->lam0;
@@ -329,6 +331,67 @@ lbm_status lbm_adjoint_step(const lbm_params* p, const lbm_state* fwd, lbm_adj_s
     a.nprobe = adj->nprobe;
     a.probe_weight = (m == adj->nsteps ? 0.5 : 1.0) * a.cm.dt;
     if (launch_adjoint(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
+    adj->cur = 1 - adj->cur;
+    return LBM_OK;
+}
+
+size_t lbm_probe_mask_bytes(const lbm_params* p) {
+    if (lbm_check_params(p) != LBM_OK) return 0;
+    return size_t((p->nx + kTile - 1) / kTile) * size_t(p->ny) * sizeof(uint64_t);
+}
+
+lbm_status lbm_adjoint_probe_table(const lbm_params* p, const lbm_adj_state* adj, uint64_t* mask, double* field,
+                                   void* stream) {
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if (!adj || !mask || !field) return LBM_ERR_ARG;
+    if (adj->nprobe < 0 || (adj->nprobe > 0 && (!adj->probe || !adj->ubar))) return LBM_ERR_ARG;
+    const Common cm = make_common(p, nullptr);
+    return launched(launch_probe_table(cm, adj->probe, adj->ubar, adj->nprobe, mask, field, (hipStream_t)stream));
+}
+
+lbm_status lbm_adjoint_step2(const lbm_params* p, const lbm_state* fwd, lbm_adj_state* adj, int64_t m, double r_m,
+                             double r_mm1, const void* record_m, const void* record_mm1, const uint64_t* mask,
+                             const double* field, void* stream) {
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if (any_wall(p)) return LBM_ERR_UNSUPPORTED;
+    if (!fwd || !adj || !adj->adj[0] || !adj->adj[1] || !record_m || !record_mm1) return LBM_ERR_ARG;
+    if (adj->cur != 0 && adj->cur != 1) return LBM_ERR_ARG;
+    if (adj->nprobe < 0 || (adj->nprobe > 0 && (!adj->probe || !adj->ubar || !mask || !field))) return LBM_ERR_ARG;
+    if (m < 1 || m >= adj->nsteps) return LBM_ERR_ARG;
+    if (p->storage != LBM_F64_PLAIN && (adj->g_mu || adj->g_lam || adj->g_body) && !adj->gsum)
+        return LBM_ERR_ARG;
+    Adj2Args a{};
+    a.cm = make_common(p, fwd);
+    a.src = adj->adj[adj->cur];
+    a.dst = adj->adj[1 - adj->cur];
+    a.rec1 = record_m;
+    a.rec2 = record_mm1;
+    a.g_mu = adj->g_mu;
+    a.g_lam = adj->g_lam;
+    a.g_body = adj->g_body;
+    a.gsum = adj->gsum;
+    a.fold1 = m % kGradBlock == 0;
+    a.fold2 = (m - 1) % kGradBlock == 0;
+    a.nstrip = (p->nx + kTile - 1) / kTile;
+    a.r1 = r_m;
+    a.r2 = r_mm1;
+    a.pmask = adj->nprobe > 0 ? mask : nullptr;
+    a.pfield = adj->nprobe > 0 ? field : nullptr;
+    a.probe_weight = a.cm.dt;                    // level m < N
+    if (launch_adjoint2(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
+    // the probe source of level m - 1 (< N), as lbm_adjoint_step adds it
+    AdjArgs pa{};
+    pa.cm = a.cm;
+    pa.dst = a.dst;
+    pa.g_body = adj->g_body;
+    pa.r_m = r_mm1;
+    pa.probe = adj->probe;
+    pa.ubar = adj->ubar;
+    pa.nprobe = adj->nprobe;
+    pa.probe_weight = a.cm.dt;
+    if (launch_adjoint_probe(pa, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
     adj->cur = 1 - adj->cur;
     return LBM_OK;
 }

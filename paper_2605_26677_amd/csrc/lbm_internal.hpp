@@ -43,6 +43,7 @@ struct Common {
     // collision constants, formed once on the host: omega/4, omega/(2c), the forcing weight
     // dt (2 - omega)/8 of eq:collision, and dt/2
     double k_omq, k_cq, k_srcw, k_hdt;
+    double k_c2, k_hc;               // 2/c and 1/(2c) (adjoint)
 };
 
 struct StepArgs {
@@ -126,6 +127,24 @@ struct AdjArgs {
     double probe_weight;             // dt * (1 or 1/2)
 };
 
+struct Adj2Args {
+    Common cm;
+    const void* src;                 // lambda^{m+1}
+    void* dst;                       // lambda^{m-1}
+    const void* rec1;                // U^m
+    const void* rec2;                // U^{m-1}
+    double* g_mu;
+    double* g_lam;
+    double* g_body;
+    void* gsum;
+    int fold1, fold2;                // block-sum folds at levels m and m - 1
+    int nstrip;
+    double r1, r2;                   // body factors r(m), r(m-1)
+    const uint64_t* pmask;           // probe table (lbm_adjoint_probe_table) or NULL
+    const double* pfield;
+    double probe_weight;             // weight of level m's probe source
+};
+
 struct AdjInitArgs {
     Common cm;
     const void* lam0;                // lambda^0
@@ -155,5 +174,9 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_init_state(const InitArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s);
 hipError_t launch_adjoint_init(const AdjInitArgs& a, hipStream_t s);
+hipError_t launch_adjoint2(const Adj2Args& a, hipStream_t s);
+hipError_t launch_adjoint_probe(const AdjArgs& a, hipStream_t s);
+hipError_t launch_probe_table(const Common& cm, const int32_t* probe, const double* ubar, int nprobe,
+                              uint64_t* mask, double* field, hipStream_t s);
 
 }  // namespace lbm

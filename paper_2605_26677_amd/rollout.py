@@ -214,11 +214,28 @@ class _Adjoint:
         a.aux = self.aux.data_ptr()
         a.gsum = self.gsum.data_ptr()
         self.a = a
+        # the probe table of the two-level adjoint (periodic grids)
+        self.pmask = self.pfield = None
+        if sv.periodic:
+            self.pmask = torch.empty(sv.lib.lbm_probe_mask_bytes(ctypes.byref(sv.p)), dtype=torch.uint8, device=dev)
+            self.pfield = torch.empty(2 * n, dtype=torch.float64, device=dev)
+            L.check(sv.lib.lbm_adjoint_probe_table(ctypes.byref(sv.p), ctypes.byref(self.a), _ptr(self.pmask),
+                                                   _ptr(self.pfield), _stream()), "lbm_adjoint_probe_table")
 
     def step(self, sv, cfg, m, record):
         L.check(sv.lib.lbm_adjoint_step(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), int(m),
                                         float(cfg.ramp(m)), ctypes.byref(_edges(cfg, m).c), _ptr(record),
                                         _stream()), "lbm_adjoint_step")
+
+    def pair_ok(self, sv, cfg, m, lowest):
+        """Levels m and m - 1 can go through lbm_adjoint_step2."""
+        return self.pmask is not None and lowest <= m - 1 and 1 <= m < cfg.nsteps
+
+    def step2(self, sv, cfg, m, record_m, record_mm1):
+        L.check(sv.lib.lbm_adjoint_step2(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), int(m),
+                                         float(cfg.ramp(m)), float(cfg.ramp(m - 1)), _ptr(record_m),
+                                         _ptr(record_mm1), _ptr(self.pmask), _ptr(self.pfield), _stream()),
+                "lbm_adjoint_step2")
 
     def init(self, sv, cfg, v0, u0):
         L.check(sv.lib.lbm_adjoint_init(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), _ptr(v0),
@@ -267,8 +284,14 @@ def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
         else:
             sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=recs[n + 1 - start], ustar=False)
             n += 1
-    for m in range(end - 1, start - 1, -1):
-        adj.step(sv, cfg, m, recs[m - start])
+    m = end - 1
+    while m >= start:
+        if adj.pair_ok(sv, cfg, m, start):
+            adj.step2(sv, cfg, m, recs[m - start], recs[m - 1 - start])
+            m -= 2
+        else:
+            adj.step(sv, cfg, m, recs[m - start])
+            m -= 1
 
 
 def _reverse_nested(sv, cfg, adj, start, end, snap, lengths, recs):

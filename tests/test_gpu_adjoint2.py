@@ -1,0 +1,134 @@
+"""Two fused adjoint levels (lbm_adjoint_step2) against two single adjoint steps
+(lbm_adjoint_step), and the checkpointed rollout that uses them against the oracle.
+
+lbm_adjoint_step2 promises the result of lbm_adjoint_step(m) followed by
+lbm_adjoint_step(m - 1), bit for bit: the adjoint populations, the FP32 gradient block sums
+and the FP64 gradients of mu, lam and the body force, with the probe sources of both levels.
+The cases cover every storage, a closed-form and an invariant-based law, per-node mu, lam
+and body force with a ramp, distinct probe cells (some at the strip edges), grids that are
+multiples of neither the 64-node strip nor the 4-row block and grids narrower than one
+strip, and both phases of the 16-level fold (on the first and on the second level of a
+pair).
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as li
+from gpu_cases import LAW_K, make_solver, Case
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(nx, ny, storage, law, N, seed=7):
+    rng = np.random.default_rng(seed)
+    if min(nx, ny) >= 4:
+        v0 = np.stack([li.gaussian_random_field(nx, ny, 601, 3e-3), li.gaussian_random_field(nx, ny, 602, 3e-3)])
+    else:
+        v0 = 3e-3 * rng.standard_normal((2, ny, nx))
+    mu = li.lognormal_field(nx, ny, 603, 0.1, 0.3, 4.0)
+    lam = li.lognormal_field(nx, ny, 604, 0.2, 0.3, 4.0)
+    body = li.uniform_body(nx, ny, (2e-4, -3e-4))
+    case = Case(f"adj2_{law}_{nx}x{ny}", nx, ny, 2.5, 1.9, N, law=law, mu=mu, lam=lam, body=body, ramp_steps=6,
+                v0=v0)
+    sv = make_solver(case, storage)
+    sv.init(v0, r0=case.ramp(0))
+    recs = [sv.record_state(case.ramp(0), sv.new_record())]
+    for n in range(N):
+        r = sv.new_record()
+        sv.step(n, case.ramp(n), case.ramp(n + 1), record=r)
+        recs.append(r)
+    nprobe = min(7, nx * ny)
+    cells = rng.choice(nx * ny, size=nprobe, replace=False)
+    cells[0] = (ny // 2) * nx + (63 % nx)            # a probe on a strip edge
+    cells = np.unique(cells)
+    ubar = rng.standard_normal((2, cells.size))
+    return case, sv, recs, cells, ubar
+
+
+def _adjoint_state(sv, case, N, cells, ubar):
+    from paper_2605_26677_amd.rollout import RolloutConfig, _Adjoint
+    cfg = RolloutConfig(nx=case.nx, ny=case.ny, c=case.c, omega=case.omega, nsteps=N,
+                        probes=torch.tensor(cells, dtype=torch.int64), storage=sv.storage, ramp=case.ramp)
+    return cfg, _Adjoint(sv, cfg, torch.tensor(ubar))
+
+
+def _valid_adj(sv, adj):
+    w = int(sv.lib.lbm_tile_width())
+    T = sv.tiles_per_row
+    dt = torch.float64 if sv.storage == "f64" else torch.float32
+    buf = adj.buf[adj.a.cur].view(dt).view(sv.ny, T, 24, w)
+    return buf.permute(2, 0, 1, 3).reshape(24, sv.ny, T * w)[:, :, : sv.nx]
+
+
+def _valid_gsum(sv, adj):
+    w = int(sv.lib.lbm_tile_width())
+    T = sv.tiles_per_row
+    g = adj.gsum.view(torch.float32).view(sv.ny, T, 4, w)
+    return g.permute(2, 0, 1, 3).reshape(4, sv.ny, T * w)[:, :, : sv.nx]
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 40), (130, 13), (5, 3)])
+@pytest.mark.parametrize("storage,law", [("f32", "lognh"), ("f16", "lognh"), ("f64", "lognh"), ("f32", "gent"),
+                                         ("f64", "svk")])
+def test_adjoint_step2_bitwise_equals_two_steps(storage, law, nx, ny):
+    N = 21
+    case, sv, recs, cells, ubar = _setup(nx, ny, storage, law, N)
+    for lead in (1, 2):                              # pairs (19,18), (17,16): fold second; then first
+        cfg, single = _adjoint_state(sv, case, N, cells, ubar)
+        _, pair = _adjoint_state(sv, case, N, cells, ubar)
+        m = N
+        for st in (single, pair):
+            for k in range(lead):
+                st.step(sv, cfg, N - k, recs[N - k])
+        m = N - lead
+        while m >= 1:
+            single.step(sv, cfg, m, recs[m])
+            single.step(sv, cfg, m - 1, recs[m - 1])
+            pair.step2(sv, cfg, m, recs[m], recs[m - 1])
+            m -= 2
+        torch.cuda.synchronize()
+        assert torch.equal(_valid_adj(sv, single), _valid_adj(sv, pair)), lead
+        if storage != "f64":
+            assert torch.equal(_valid_gsum(sv, single), _valid_gsum(sv, pair)), lead
+        for name in ("g_mu", "g_lam", "g_body"):
+            assert torch.equal(getattr(single, name), getattr(pair, name)), (lead, name)
+        assert float(single.g_mu.abs().max()) > 0 and float(single.g_body.abs().max()) > 0
+
+
+def test_adjoint_step2_refuses_walls_and_level_N():
+    from paper_2605_26677_amd._lib import LBMError
+    N = 6
+    case, sv, recs, cells, ubar = _setup(32, 32, "f32", "lognh", N)
+    cfg, adj = _adjoint_state(sv, case, N, cells, ubar)
+    with pytest.raises(LBMError):
+        adj.step2(sv, cfg, N, recs[N], recs[N - 1])         # level N takes the single step
+    with pytest.raises(LBMError):
+        adj.step2(sv, cfg, 0, recs[0], recs[0])             # no level -1
+
+
+@pytest.mark.parametrize("storage,bar", [("f64", 1e-10), ("f32", 2e-5)])
+def test_rollout_in_pairs_matches_oracle_adjoint(storage, bar):
+    """A periodic checkpointed rollout (forward, replays and adjoint all in pairs where they
+    can) gives the oracle's gradients."""
+    from oracle import adjoint as oadj
+    from oracle import lbm as olbm
+    from paper_2605_26677_amd.rollout import RolloutConfig, rollout
+    nx, ny, N = 70, 36, 23
+    mu0 = li.lognormal_field(nx, ny, 611, 0.1, 0.3, 4.0)
+    lam0 = li.lognormal_field(nx, ny, 612, 0.2, 0.3, 4.0)
+    b0 = li.uniform_body(nx, ny, (2e-4, -5e-4))
+    w0 = np.stack([li.gaussian_random_field(nx, ny, 613, 1e-3), li.gaussian_random_field(nx, ny, 614, 1e-3)])
+    ys, xs = li.random_probes(nx, ny, 6, 615)
+    ramp = lambda m: min(1.0, m / 10)
+    cfg = RolloutConfig(nx=nx, ny=ny, c=2.5, omega=1.95, nsteps=N, probes=torch.tensor(ys * nx + xs),
+                        storage=storage, ramp=ramp, checkpoint_every=6)
+    leaves = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True) for a in (mu0, lam0, b0, w0)]
+    (rollout(*leaves, cfg).double() ** 2).sum().backward()
+    pbo = olbm.Problem(nx=nx, ny=ny, c=2.5, omega=1.95, law="lognh", mu=mu0, lam=lam0, body=b0, ramp=ramp)
+    _, go = oadj.gradients(pbo, w0, N, (ys, xs), np.zeros((2, len(ys))))
+    for k, t in zip(("mu", "lam", "body", "v0"), leaves):
+        g = t.grad.cpu().numpy()
+        err = float(np.sqrt(((g - go[k]) ** 2).sum() / (go[k] ** 2).sum()))
+        print(f"\n[rollout pairs {storage}] {k}: {err:.2e}")
+        assert err <= bar, k
