@@ -336,12 +336,11 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
     const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
     const int64_t n = int64_t(nx) * ny;
     const int b = remap_tile(blockIdx.x, gridDim.x);
-    const int64_t per_chunk = int64_t(kPairChunk) * (gridDim.x / a.nstrip);
-    const int chunk = int(b / per_chunk);
-    const int rem = int(b - chunk * per_chunk);
-    const int kc = min(kPairChunk, a.nstrip - chunk * kPairChunk);
+    const int chunk = b / a.per_chunk;
+    const int rem = b - chunk * a.per_chunk;
+    const int kc = min(a.chunk, a.nstrip - chunk * a.chunk);
     const int blk = rem / kc;
-    const int strip = chunk * kPairChunk + (rem - blk * kc);
+    const int strip = chunk * a.chunk + (rem - blk * kc);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
     const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;

@@ -239,6 +239,7 @@ lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_np1,
     a.fold1 = (n + 1) % kUstarBlock == 0;
     a.fold2 = (n + 2) % kUstarBlock == 0;
     a.nstrip = (p->nx + kPairCols - 1) / kPairCols;
+    pair_chunks(a.nstrip, p->ny, a.chunk, a.per_chunk);
     a.r_np1 = r_np1;
     a.r_np2 = r_np2;
     if (launch_step2(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
@@ -375,6 +376,7 @@ lbm_status lbm_adjoint_step2(const lbm_params* p, const lbm_state* fwd, lbm_adj_
     a.fold1 = m % kGradBlock == 0;
     a.fold2 = (m - 1) % kGradBlock == 0;
     a.nstrip = (p->nx + kTile - 1) / kTile;
+    pair_chunks(a.nstrip, p->ny, a.chunk, a.per_chunk);
     a.r1 = r_m;
     a.r2 = r_mm1;
     a.pmask = adj->nprobe > 0 ? mask : nullptr;

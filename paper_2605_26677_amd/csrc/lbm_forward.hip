@@ -297,7 +297,7 @@ __device__ __forceinline__ void pull_node(const T* __restrict__ src, int ntile, 
 // aligned tiles.  Each node's arithmetic is collide_node, as in step_kernel, and level
 // n+1 is rounded to the storage type, so the result is bit for bit that of two single
 // steps.
-template <int ST, int LAW, bool FIELDS>
+template <int ST, int LAW, bool FIELDS, bool REC>
 __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Args a) {
     using Tr = Storage<ST>;
     using R = typename Tr::real;
@@ -313,12 +313,11 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
     // strips of one block row, then of the next, so that the neighbours that re-read a
     // block's edge rows run soon after it on the same XCD's L2
     const int b = remap_tile(blockIdx.x, gridDim.x);
-    const int64_t per_chunk = int64_t(kPairChunk) * (gridDim.x / a.nstrip);
-    const int chunk = int(b / per_chunk);
-    const int rem = int(b - chunk * per_chunk);
-    const int kc = min(kPairChunk, a.nstrip - chunk * kPairChunk);
+    const int chunk = b / a.per_chunk;
+    const int rem = b - chunk * a.per_chunk;
+    const int kc = min(a.chunk, a.nstrip - chunk * a.chunk);
     const int blk = rem / kc;
-    const int strip = chunk * kPairChunk + (rem - blk * kc);
+    const int strip = chunk * a.chunk + (rem - blk * kc);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
     const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;
@@ -449,8 +448,10 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
                     store_stream(rf.S + cpt * kTile, sn);
                 }
             }
-            if (a.record1) write_record<R, SH>(a.record1, ntile, xo, r, U1);
-            if (a.record2) write_record<R, SH>(a.record2, ntile, xo, r, U2);
+            if constexpr (REC) {
+                if (a.record1) write_record<R, SH>(a.record1, ntile, xo, r, U1);
+                if (a.record2) write_record<R, SH>(a.record2, ntile, xo, r, U2);
+            }
 #pragma unroll
             for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U2[k]);
             jbad |= J2 <= R(0);
@@ -822,8 +823,16 @@ static hipError_t step2_st_law(const Step2Args& a, hipStream_t s) {
     const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
     const dim3 grid(unsigned(int64_t(a.nstrip) * ((a.cm.ny + kPairRows - 1) / kPairRows)));
     const dim3 block((kPairWaves + 1) * kTile);
-    if (fields) hipLaunchKernelGGL((step2_kernel<ST, LAW, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((step2_kernel<ST, LAW, false>), grid, block, 0, s, a);
+    // the record writes are compiled in only where asked for: their mere presence costs the
+    // plain kernel about a tenth of its speed
+    const bool rec = a.record1 || a.record2;
+    if (fields) {
+        if (rec) hipLaunchKernelGGL((step2_kernel<ST, LAW, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((step2_kernel<ST, LAW, true, false>), grid, block, 0, s, a);
+    } else {
+        if (rec) hipLaunchKernelGGL((step2_kernel<ST, LAW, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((step2_kernel<ST, LAW, false, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -65,6 +65,17 @@ constexpr int kPairRows = kPairWaves - 2;
 constexpr int kPairCols = 64;
 constexpr int kPairChunk = 32;       // strips per chunk of the workgroup order
 
+// Chunk width of the two-level kernels' workgroup order for a grid of nstrip x nblk blocks:
+// kPairChunk strips, fewer where chunk * nblk would not fit 32-bit arithmetic.
+inline void pair_chunks(int nstrip, int ny, int& chunk, int& per_chunk) {
+    const int64_t nblk = (int64_t(ny) + kPairRows - 1) / kPairRows;
+    int64_t c = kPairChunk;
+    while (c > 1 && c * nblk > 0x7fffffff) c >>= 1;
+    if (c > nstrip) c = nstrip;
+    chunk = int(c);
+    per_chunk = int(c * nblk);
+}
+
 struct Step2Args {
     Common cm;
     const void* src;                 // f*^n
@@ -74,6 +85,7 @@ struct Step2Args {
     void* record2;                   // U^{n+2} or NULL
     int fold1, fold2;                // accumulator folds after the first / second step
     int nstrip;                      // strips of kPairCols columns (= tiles per row)
+    int chunk, per_chunk;            // strips per chunk of the workgroup order, workgroups per chunk
     double r_np1, r_np2;
 };
 
@@ -139,6 +151,7 @@ struct Adj2Args {
     void* gsum;
     int fold1, fold2;                // block-sum folds at levels m and m - 1
     int nstrip;
+    int chunk, per_chunk;            // as in Step2Args
     double r1, r2;                   // body factors r(m), r(m-1)
     const uint64_t* pmask;           // probe table (lbm_adjoint_probe_table) or NULL
     const double* pfield;
