@@ -328,6 +328,7 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
     const int idx1 = yr * nx + xc;
 
     R f1[4][6], U1[6], g[4][6], mu, lam;
+    double braw[2];                           // b(X) of this wave's node, for both levels
     bool nonfinite = false, jbad = false;
     if (w < kPairWaves) {
         // level n -> n+1 on row r: q0 from x-1 and q2 from x+1 of row r (own lanes shifted,
@@ -358,8 +359,8 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
             g[0][k] = lane == 0 ? h[k] : up;
             g[2][k] = lane == kTile - 1 ? h[k] : dn;
         }
-        double bd0, bd1;
-        body_at<FIELDS>(cm, idx1, n, a.r_np1, bd0, bd1);
+        body_raw<FIELDS>(cm, idx1, n, braw[0], braw[1]);
+        const double bd0 = a.r_np1 * braw[0], bd1 = a.r_np1 * braw[1];
         params_at<FIELDS, R>(cm, idx1, mu, lam);
         R J1;
         collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f1, U1, J1);
@@ -407,8 +408,7 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
             if (lane == 0) g[0][k] = xh[0][k][w - 1];
             if (lane == kTile - 1) g[2][k] = xh[1][k][w - 1];
         }
-        double bd0, bd1;
-        body_at<FIELDS>(cm, idx1, n, a.r_np2, bd0, bd1);
+        const double bd0 = a.r_np2 * braw[0], bd1 = a.r_np2 * braw[1];
         R f2[4][6], U2[6], J2;
         collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f2, U2, J2);
         if (r < ny && xo < nx) {
