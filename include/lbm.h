@@ -129,7 +129,8 @@ typedef struct {
                                   the same field as body.  Lets a caller drive a force that is
                                   not a fixed field times a ramp by swapping two buffers. */
     double b0[2];              /* uniform body acceleration when body is NULL */
-    void *aux;                 /* device, lbm_aux_bytes(): traction-wall staging (F^b per link) */
+    void *aux;                 /* device, lbm_aux_bytes(): wall staging (F^b per traction link;
+                                  level n+1 on the wall lines for lbm_step2) */
     uint32_t *fault;           /* device: fault word (LBM_FAULT_* bits are OR-ed in) */
 } lbm_state;
 
@@ -153,7 +154,8 @@ size_t lbm_padded_nodes(const lbm_params *p);
 size_t lbm_pop_bytes(const lbm_params *p);
 /* Bytes of the u* accumulator. */
 size_t lbm_ustar_bytes(const lbm_params *p);
-/* Bytes of the traction-wall staging buffer (forward and adjoint). */
+/* Bytes of the wall staging buffer (forward and adjoint): F^b of every link, and for
+ * lbm_step2 level n+1 on the wall line and first interior line of every edge. */
 size_t lbm_aux_bytes(const lbm_params *p);
 /* Bytes of one per-level state record (6 tiled planes of the compute type: v1, v2, F - I). */
 size_t lbm_record_bytes(const lbm_params *p);
@@ -209,16 +211,20 @@ lbm_status lbm_step(const lbm_params *p, lbm_state *s, int64_t n, double r_n, do
                     const lbm_edge_data *at_half, void *record, void *stream);
 
 /* Two time steps, level n -> n+2, in one pass over the grid (temporal blocking of the
- * step of Sec. 3.7: level n+1 stays on chip).  The result, the u* accumulator and the
- * fault bits are those of lbm_step(n) followed by lbm_step(n+1), bit for bit, at about
- * half the HBM traffic per level.  Flips s->cur on success.
- *   r_np1, r_np2: body-force factors at levels n+1 and n+2; the body field s->body (or
- *     the uniform b0) is the same at both levels.
+ * step of Sec. 3.7: level n+1 stays on chip).  The result, the u* accumulator, the records
+ * and the fault bits are those of lbm_step(n) followed by lbm_step(n+1), bit for bit, at
+ * about half the HBM traffic per level.  Flips s->cur on success.
+ *   r_n, r_np1, r_np2: body-force factors at levels n, n+1, n+2.  The body field s->body (or
+ *     the uniform b0) is that of every level: s->body_prev is not read.
+ *   at_half, at_half_next: boundary data at t^{n+1/2} and t^{n+3/2}; may be NULL only when
+ *     all edges are periodic (LBM_ERR_ARG otherwise).
  *   record1, record2: device, lbm_record_bytes() each, receive U^{n+1} and U^{n+2} (v,
  *     F - I) as lbm_step's record would; either may be NULL.
- * Every edge must be periodic (LBM_ERR_UNSUPPORTED otherwise: the traction rule needs
- * level n+1 along a whole wall). */
-lbm_status lbm_step2(const lbm_params *p, lbm_state *s, int64_t n, double r_np1, double r_np2,
+ * On a grid with walls the bulk pass also leaves level n+1 of the wall lines and the first
+ * interior lines in s->aux; the traction F^b of level n+1 is solved from them and a small
+ * pass completes the wall nodes (s->aux must hold lbm_aux_bytes()). */
+lbm_status lbm_step2(const lbm_params *p, lbm_state *s, int64_t n, double r_n, double r_np1,
+                     double r_np2, const lbm_edge_data *at_half, const lbm_edge_data *at_half_next,
                      void *record1, void *record2, void *stream);
 
 /* Displacement at the current level n (eq:trapezoid-u): u^n = u*^{n+1} - (dt/2) v^n with

@@ -116,7 +116,10 @@ size_t lbm_ustar_bytes(const lbm_params* p) {
     return p->storage == LBM_F64_PLAIN ? 2 * lbm_padded_nodes(p) * 8 : lbm_padded_nodes(p) * (2 * 4 + 2 * 8);
 }
 
-size_t lbm_aux_bytes(const lbm_params* p) { return (size_t)(2 * p->nx + 2 * p->ny) * 4 * 8; }
+// F^b of every link (4 values), and for the two-level step the wall lines of level n+1
+// (2 lines of 24 values per link) and U^{n+1} of the wall nodes (6 values), 8 bytes each
+// (WallLines in lbm_kernel_util.hpp).
+size_t lbm_aux_bytes(const lbm_params* p) { return (size_t)(2 * p->nx + 2 * p->ny) * (4 + 2 * 24 + 6) * 8; }
 
 size_t lbm_record_bytes(const lbm_params* p) { return 6 * lbm_padded_nodes(p) * real_size(p); }
 
@@ -223,17 +226,24 @@ lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, do
     return LBM_OK;
 }
 
-lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_np1, double r_np2, void* record1,
-                     void* record2, void* stream) {
+lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_n, double r_np1, double r_np2,
+                     const lbm_edge_data* at_half, const lbm_edge_data* at_half_next, void* record1, void* record2,
+                     void* stream) {
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
-    if (any_wall(p)) return LBM_ERR_UNSUPPORTED;
     if ((st = check_state(p, s, false)) != LBM_OK) return st;
+    const bool walls = any_wall(p);
+    if (walls && (!at_half || !at_half_next || !s->aux)) return LBM_ERR_ARG;
+    const hipStream_t hs = (hipStream_t)stream;
     Step2Args a{};
     a.cm = make_common(p, s);
+    a.cm.body_prev = nullptr;                    // the body field is that of every level
     a.src = s->pop[s->cur];
     a.dst = s->pop[1 - s->cur];
     a.ustar = s->ustar;
+    a.aux = s->aux;
+    a.ed = make_edges(at_half);
+    a.ed2 = make_edges(at_half_next);
     a.record1 = record1;
     a.record2 = record2;
     a.fold1 = (n + 1) % kUstarBlock == 0;
@@ -242,7 +252,37 @@ lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_np1,
     pair_chunks(a.nstrip, p->ny, a.chunk, a.per_chunk);
     a.r_np1 = r_np1;
     a.r_np2 = r_np2;
-    if (launch_step2(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
+    // F^b of level n from f*^n, as lbm_step takes it
+    for (int e = 0; e < 4; ++e) {
+        if (p->bc[e] != LBM_TRACTION) continue;
+        TractionArgs t{};
+        t.cm = a.cm;
+        t.pop = a.src;
+        t.aux = s->aux;
+        t.r_n = r_n;
+        t.ed = a.ed;
+        t.edge = e;
+        if (launch_traction(t, hs) != hipSuccess) return LBM_ERR_LAUNCH;
+    }
+    if (launch_step2(a, hs) != hipSuccess) return LBM_ERR_LAUNCH;
+    if (walls) {
+        // F^b of level n+1 from the wall lines the bulk kernel wrote, then the wall nodes
+        for (int e = 0; e < 4; ++e) {
+            if (p->bc[e] != LBM_TRACTION) continue;
+            TractionArgs t{};
+            t.cm = a.cm;
+            t.pop = nullptr;
+            t.aux = s->aux;
+            t.r_n = r_np1;
+            t.ed = a.ed2;
+            t.edge = e;
+            t.lines = 1;
+            if (launch_traction(t, hs) != hipSuccess) return LBM_ERR_LAUNCH;
+        }
+        Step2Args w = a;
+        w.wall_pass = 1;
+        if (launch_step2(w, hs) != hipSuccess) return LBM_ERR_LAUNCH;
+    }
     s->cur = 1 - s->cur;
     return LBM_OK;
 }

@@ -21,7 +21,7 @@ namespace lbm {
 // node, G = F_{.B} + (dt/2) d_B v (the kinematic identity moves F by half a step) and the
 // tangential column is 3/2 G(X0) - 1/2 G(X1) (linear extrapolation to the half-way wall);
 // the Newton guess for the normal column is 3/2 F_{.A}(X0) - 1/2 F_{.A}(X1).
-template <int ST, int LAW, bool FIELDS>
+template <int ST, int LAW, bool FIELDS, bool LINES>
 __global__ void __launch_bounds__(kBlock) traction_kernel(TractionArgs a) {
     using Tr = Storage<ST>;
     using R = typename Tr::real;
@@ -49,7 +49,14 @@ __global__ void __launch_bounds__(kBlock) traction_kernel(TractionArgs a) {
             const XY nd = edge_node(G, cm.nx, cm.ny, r, sten.p[j]);
             double b0, b1;
             body_at<FIELDS>(cm, nd.y * cm.nx + nd.x, n, a.r_n, b0, b1);
-            recover_node<T, R>(pop, cm.ntile, nd.x, nd.y, hdt * R(b0), hdt * R(b1), Us[j]);
+            if constexpr (LINES) {
+                // level n+1 of the two-level step, from the wall lines of the staging buffer
+                const T* lv = (const T*)wall_lines(a.aux, cm.nx, cm.ny).lines +
+                              line_slot(cm.nx, cm.ny, e, r, sten.p[j]) * 24;
+                recover_vals<T, R>(lv, 1, hdt * R(b0), hdt * R(b1), Us[j]);
+            } else {
+                recover_node<T, R>(pop, cm.ntile, nd.x, nd.y, hdt * R(b0), hdt * R(b1), Us[j]);
+            }
         }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -88,14 +95,16 @@ __global__ void __launch_bounds__(kBlock) traction_kernel(TractionArgs a) {
 // f_d = D f*_{-d}(X) + S_d, velocity rule eq:dirichlet-boundary-rule,
 // traction rule eq:neumann-boundary-rule.  In shifted storage only the traction F rows
 // change: g_d = -g*_{-d} + (F^b - I)/2 (F^b arrives from the staging buffer as F^b - I).
+// ownp points at the node's first population, plane stride `stride` (the tiled array or a
+// wall line of the staging buffer).
 template <typename T, typename R>
 __device__ __forceinline__ void wall_link(const Common& cm, const EdgeData& ed, const void* auxp,
-                                          int e, int s, const T* src, int64_t own, R out[6]) {
+                                          int e, int s, const T* ownp, int64_t stride, R out[6]) {
     const EdgeGeom G = edge_geom(e);
     const int L = (G.A == 0) ? cm.ny : cm.nx;
     R o[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) o[k] = R(src[own + (6 * G.od + k) * kTile]);
+    for (int k = 0; k < 6; ++k) o[k] = R(ownp[(6 * G.od + k) * stride]);
     const R w0 = edge_value<R>(ed, e, 0, s, L), w1 = edge_value<R>(ed, e, 1, s, L);
     const R c = R(cm.c);
     if (cm.bc[e] == LBM_VELOCITY) {
@@ -216,10 +225,10 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     }
 
     if constexpr (WALLS) {
-        if (miss0) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMIN, y, src, own, g[0]);
-        if (miss2) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMAX, y, src, own, g[2]);
-        if (miss1) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMIN, x, src, own, g[1]);
-        if (miss3) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMAX, x, src, own, g[3]);
+        if (miss0) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMIN, y, src + own, kTile, g[0]);
+        if (miss2) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMAX, y, src + own, kTile, g[2]);
+        if (miss1) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMIN, x, src + own, kTile, g[1]);
+        if (miss3) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMAX, x, src + own, kTile, g[3]);
     }
 
     double bd0, bd1;
@@ -285,6 +294,85 @@ __device__ __forceinline__ void pull_node(const T* __restrict__ src, int ntile, 
     }
 }
 
+// The per-node tail of a two-level update at output node (x, y): the displacement
+// quadrature over both levels (eq:trapezoid-u) with the accumulator updates and folds of two
+// single steps, and the records of both levels.
+template <int ST, bool REC>
+__device__ __forceinline__ void pair_tail(const Step2Args& a, int x, int y, const typename Storage<ST>::real U1[6],
+                                          const typename Storage<ST>::real U2[6]) {
+    using R = typename Storage<ST>::real;
+    constexpr bool SH = Storage<ST>::shifted;
+    const Common& cm = a.cm;
+    const int ntile = cm.ntile;
+    const R dt = R(cm.dt);
+    if (!a.ustar) {
+    } else if constexpr (ST == LBM_F64_PLAIN) {
+        double* us = (double*)a.ustar + tile_base(ntile, 2, x, y);
+        const double s0 = us[0] + dt * U1[0], s1 = us[kTile] + dt * U1[1];
+        store_stream(us, s0 + dt * U2[0]);
+        store_stream(us + kTile, s1 + dt * U2[1]);
+    } else {
+        const UstarRefs rf = ustar_refs(a.ustar, ntile, cm.ny, x, y);
+#pragma unroll
+        for (int cpt = 0; cpt < 2; ++cpt) {
+            float sn = rf.S[cpt * kTile] + float(dt * U1[cpt]);
+            bool moved = false;
+            double u = 0.0;
+            if (a.fold1) {
+                u = rf.U[cpt * kTile] + double(sn);
+                sn = 0.0f;
+                moved = true;
+            }
+            sn = sn + float(dt * U2[cpt]);
+            if (a.fold2) {
+                u = (moved ? u : rf.U[cpt * kTile]) + double(sn);
+                sn = 0.0f;
+                moved = true;
+            }
+            if (moved) store_stream(rf.U + cpt * kTile, u);
+            store_stream(rf.S + cpt * kTile, sn);
+        }
+    }
+    if constexpr (REC) {
+        if (a.record1) write_record<R, SH>(a.record1, ntile, x, y, U1);
+        if (a.record2) write_record<R, SH>(a.record2, ntile, x, y, U2);
+    }
+}
+
+// Level n+1 of a node on a wall line or first interior line into the wall lines of the
+// staging buffer (every such line through it), and U^{n+1} of a wall-line node.
+template <typename T, typename R>
+__device__ __forceinline__ void store_wall_lines(const Common& cm, void* aux, int xg, int xc, int r, int yr,
+                                                 const R f1[4][6], const R U1[6]) {
+    const int nx = cm.nx, ny = cm.ny;
+    const WallLines wl = wall_lines(aux, nx, ny);
+    int off[4], len[4];
+    edge_offsets(nx, ny, off, len);
+    int er[4] = {-1, -1, -1, -1}, es[4] = {0, 0, 0, 0};
+    if (!cm.periodic_x) {
+        if (xg <= 1) { er[LBM_XMIN] = xg; es[LBM_XMIN] = yr; }
+        if (xg >= nx - 2) { er[LBM_XMAX] = nx - 1 - xg; es[LBM_XMAX] = yr; }
+    }
+    if (!cm.periodic_y) {
+        if (r <= 1) { er[LBM_YMIN] = r; es[LBM_YMIN] = xc; }
+        if (r >= ny - 2) { er[LBM_YMAX] = ny - 1 - r; es[LBM_YMAX] = xc; }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (er[e] < 0) continue;
+        T* lv = (T*)wl.lines + line_slot(nx, ny, e, er[e], es[e]) * 24;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) lv[6 * q + k] = T(f1[q][k]);
+        if (er[e] == 0) {
+            R* u = (R*)wl.u1 + (int64_t(off[e]) + es[e]) * 6;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) u[k] = U1[k];
+        }
+    }
+}
+
 // Temporal blocking of the periodic step: one pass takes f*^n to f*^{n+2} without storing
 // level n+1.  A workgroup owns a block of kPairRows rows of one 64-node tile column (a
 // strip).  Wave w < kPairWaves takes row y0 - 1 + w of the strip through level n+1,
@@ -297,7 +385,7 @@ __device__ __forceinline__ void pull_node(const T* __restrict__ src, int ntile, 
 // aligned tiles.  Each node's arithmetic is collide_node, as in step_kernel, and level
 // n+1 is rounded to the storage type, so the result is bit for bit that of two single
 // steps.
-template <int ST, int LAW, bool FIELDS, bool REC>
+template <int ST, int LAW, bool FIELDS, bool REC, bool WALLS>
 __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Args a) {
     using Tr = Storage<ST>;
     using R = typename Tr::real;
@@ -321,11 +409,15 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
     const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;
-    const int xc = wrap_index(c0 + lane, nx);
+    const int xg = c0 + lane;
+    const int xc = wrap_index(xg, nx);
     const int yr = wrap_index(r, ny);
     const T* __restrict__ src = (const T*)a.src;
     T* __restrict__ dst = (T*)a.dst;
     const int idx1 = yr * nx + xc;
+    // a node of the grid (a lane or row beyond a wall is not; along a periodic axis every
+    // lane and row is the node it wraps to)
+    const bool valid = !WALLS || ((cm.periodic_x || xg < nx) && (cm.periodic_y || (r >= 0 && r < ny)));
 
     R f1[4][6], U1[6], g[4][6], mu, lam;
     double braw[2];                           // b(X) of this wave's node, for both levels
@@ -359,6 +451,17 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
             g[0][k] = lane == 0 ? h[k] : up;
             g[2][k] = lane == kTile - 1 ? h[k] : dn;
         }
+        if constexpr (WALLS) {
+            // the missing links of level n at wall nodes (eq:boundary-general), as in
+            // step_kernel; lanes and rows beyond a wall hold no node and feed only wall
+            // nodes, whose level n+2 the wall kernel computes
+            if (valid) {
+                if (!cm.periodic_x && xg == 0) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMIN, yr, src + bo, kTile, g[0]);
+                if (!cm.periodic_x && xg == nx - 1) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMAX, yr, src + bo, kTile, g[2]);
+                if (!cm.periodic_y && r == 0) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMIN, xc, src + bo, kTile, g[1]);
+                if (!cm.periodic_y && r == ny - 1) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMAX, xc, src + bo, kTile, g[3]);
+            }
+        }
         body_raw<FIELDS>(cm, idx1, n, braw[0], braw[1]);
         const double bd0 = a.r_np1 * braw[0], bd1 = a.r_np1 * braw[1];
         params_at<FIELDS, R>(cm, idx1, mu, lam);
@@ -368,9 +471,14 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int k = 0; k < 6; ++k) f1[q][k] = R(to_storage<T>(f1[q][k]));   // the stored value of level n+1
+        if (valid) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U1[k]);
-        jbad = J1 <= R(0);
+            for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U1[k]);
+            jbad = J1 <= R(0);
+        }
+        if constexpr (WALLS) {
+            if (valid) store_wall_lines<T, R>(cm, a.aux, xg, xc, r, yr, f1, U1);
+        }
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             xq1[w][k][lane] = f1[1][k];
@@ -386,6 +494,16 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
         const int hx = wrap_index(side == 0 ? c0 - 1 : c0 + kTile, nx), hy = wrap_index(y0 + row, ny);
         R gh[4][6], fh[4][6], Uh[6], Jh, muh, lamh;
         pull_node<T, R>(src, ntile, nx, ny, hx, hy, gh);
+        if constexpr (WALLS) {
+            const int hxg = side == 0 ? c0 - 1 : c0 + kTile, hyg = y0 + row;
+            if ((cm.periodic_x || (hxg >= 0 && hxg < nx)) && (cm.periodic_y || hyg < ny)) {
+                const T* hown = src + tile_base(ntile, 24, hx, hy);
+                if (!cm.periodic_x && hx == 0) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMIN, hy, hown, kTile, gh[0]);
+                if (!cm.periodic_x && hx == nx - 1) wall_link<T, R>(cm, a.ed, a.aux, LBM_XMAX, hy, hown, kTile, gh[2]);
+                if (!cm.periodic_y && hy == 0) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMIN, hx, hown, kTile, gh[1]);
+                if (!cm.periodic_y && hy == ny - 1) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMAX, hx, hown, kTile, gh[3]);
+            }
+        }
         const int hidx = hy * nx + hx;
         double bd0, bd1;
         body_at<FIELDS>(cm, hidx, n, a.r_np1, bd0, bd1);
@@ -411,52 +529,94 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
         const double bd0 = a.r_np2 * braw[0], bd1 = a.r_np2 * braw[1];
         R f2[4][6], U2[6], J2;
         collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f2, U2, J2);
-        if (r < ny && xo < nx) {
+        const bool wall_node = WALLS && ((!cm.periodic_x && (xo == 0 || xo == nx - 1)) ||
+                                         (!cm.periodic_y && (r == 0 || r == ny - 1)));
+        if (r < ny && xo < nx && !wall_node) {
             const int64_t ob = tile_base(ntile, 24, xo, r);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) store_stream(dst + ob + (6 * q + k) * kTile, to_storage<T>(f2[q][k]));
-            // displacement quadrature over both levels (eq:trapezoid-u), with the same
-            // accumulator updates and folds as two single steps
-            const R dt = R(cm.dt);
-            if (!a.ustar) {
-            } else if constexpr (ST == LBM_F64_PLAIN) {
-                double* us = (double*)a.ustar + tile_base(ntile, 2, xo, r);
-                const double s0 = us[0] + dt * U1[0], s1 = us[kTile] + dt * U1[1];
-                store_stream(us, s0 + dt * U2[0]);
-                store_stream(us + kTile, s1 + dt * U2[1]);
-            } else {
-                const UstarRefs rf = ustar_refs(a.ustar, ntile, ny, xo, r);
-#pragma unroll
-                for (int cpt = 0; cpt < 2; ++cpt) {
-                    float sn = rf.S[cpt * kTile] + float(dt * U1[cpt]);
-                    bool moved = false;
-                    double u = 0.0;
-                    if (a.fold1) {
-                        u = rf.U[cpt * kTile] + double(sn);
-                        sn = 0.0f;
-                        moved = true;
-                    }
-                    sn = sn + float(dt * U2[cpt]);
-                    if (a.fold2) {
-                        u = (moved ? u : rf.U[cpt * kTile]) + double(sn);
-                        sn = 0.0f;
-                        moved = true;
-                    }
-                    if (moved) store_stream(rf.U + cpt * kTile, u);
-                    store_stream(rf.S + cpt * kTile, sn);
-                }
-            }
-            if constexpr (REC) {
-                if (a.record1) write_record<R, SH>(a.record1, ntile, xo, r, U1);
-                if (a.record2) write_record<R, SH>(a.record2, ntile, xo, r, U2);
-            }
+            pair_tail<ST, REC>(a, xo, r, U1, U2);
 #pragma unroll
             for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U2[k]);
             jbad |= J2 <= R(0);
         }
     }
+    if (nonfinite || jbad)
+        atomicOr(cm.fault, (jbad ? (uint32_t)LBM_FAULT_J : 0u) | (nonfinite ? (uint32_t)LBM_FAULT_NONFINITE : 0u));
+}
+
+// Level n+1 -> n+2 at the wall nodes of a two-level step on a grid with walls: one thread
+// per link slot of the staging buffer (a corner node is taken by the first of its edges).
+// Level n+1 comes from the wall lines, F^b^{n+1} from the staging buffer (written by the
+// traction kernel from the same lines), the wall data of t^{n+3/2} from ed2; the arithmetic
+// is that of step_kernel at a wall node (collide_node, wall_link), the tail that of the
+// two-level kernel (pair_tail).
+template <int ST, int LAW, bool FIELDS, bool REC>
+__global__ void __launch_bounds__(kBlock) step2_wall_kernel(Step2Args a) {
+    using Tr = Storage<ST>;
+    using R = typename Tr::real;
+    using T = typename Tr::pop_t;
+    constexpr bool SH = Tr::shifted;
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny;
+    int off[4], len[4];
+    edge_offsets(nx, ny, off, len);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= off[LBM_YMAX] + len[LBM_YMAX]) return;
+    int e = LBM_YMAX;
+    while (e > 0 && t < off[e]) --e;
+    if (cm.bc[e] == LBM_PERIODIC) return;
+    const int s = t - off[e];
+    const XY nd = edge_node(edge_geom(e), nx, ny, 0, s);
+    const int x = nd.x, y = nd.y;
+    const bool on[4] = {!cm.periodic_x && x == 0, !cm.periodic_x && x == nx - 1,
+                        !cm.periodic_y && y == 0, !cm.periodic_y && y == ny - 1};
+    for (int e0 = 0; e0 < e; ++e0)
+        if (on[e0]) return;                      // a corner taken by an earlier edge
+    const WallLines wl = wall_lines(a.aux, nx, ny);
+    const T* lines = (const T*)wl.lines;
+    const T* ownp = lines + line_slot(nx, ny, e, 0, s) * 24;
+    // pulls from the lines: q0 from (x-1, y), q1 from (x, y-1), q2 from (x+1, y), q3 from (x, y+1)
+    R g[4][6];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool miss = on[q == 0 ? LBM_XMIN : q == 1 ? LBM_YMIN : q == 2 ? LBM_XMAX : LBM_YMAX];
+        if (miss) continue;
+        const int sx = wrap_index(x - dir_i(q), nx), sy = wrap_index(y - dir_j(q), ny);
+        int le = 0, lr = 0, ls = 0;
+        find_line(cm, sx, sy, le, lr, ls);
+        const T* sp = lines + line_slot(nx, ny, le, lr, ls) * 24;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) g[q][k] = R(sp[6 * q + k]);
+    }
+    if (on[LBM_XMIN]) wall_link<T, R>(cm, a.ed2, a.aux, LBM_XMIN, y, ownp, 1, g[0]);
+    if (on[LBM_XMAX]) wall_link<T, R>(cm, a.ed2, a.aux, LBM_XMAX, y, ownp, 1, g[2]);
+    if (on[LBM_YMIN]) wall_link<T, R>(cm, a.ed2, a.aux, LBM_YMIN, x, ownp, 1, g[1]);
+    if (on[LBM_YMAX]) wall_link<T, R>(cm, a.ed2, a.aux, LBM_YMAX, x, ownp, 1, g[3]);
+    const int64_t n = int64_t(nx) * ny;
+    const int idx = y * nx + x;
+    double bd0, bd1;
+    body_at<FIELDS>(cm, idx, n, a.r_np2, bd0, bd1);
+    R mu, lam;
+    params_at<FIELDS, R>(cm, idx, mu, lam);
+    R f2[4][6], U2[6], J2;
+    collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f2, U2, J2);
+    T* dst = (T*)a.dst + tile_base(cm.ntile, 24, x, y);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) store_stream(dst + (6 * q + k) * kTile, to_storage<T>(f2[q][k]));
+    R U1[6];
+    const R* u1 = (const R*)wl.u1 + (int64_t(off[e]) + s) * 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) U1[k] = u1[k];
+    pair_tail<ST, REC>(a, x, y, U1, U2);
+    bool nonfinite = false;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U2[k]);
+    const bool jbad = J2 <= R(0);
     if (nonfinite || jbad)
         atomicOr(cm.fault, (jbad ? (uint32_t)LBM_FAULT_J : 0u) | (nonfinite ? (uint32_t)LBM_FAULT_NONFINITE : 0u));
 }
@@ -818,20 +978,39 @@ static hipError_t step_st(const StepArgs& a, hipStream_t s) {
     }
 }
 
+template <int ST, int LAW, bool FIELDS, bool REC>
+static void step2_launch(const Step2Args& a, hipStream_t s, bool walls) {
+    const dim3 grid(unsigned(int64_t(a.nstrip) * ((a.cm.ny + kPairRows - 1) / kPairRows)));
+    const dim3 block((kPairWaves + 1) * kTile);
+    if (walls) hipLaunchKernelGGL((step2_kernel<ST, LAW, FIELDS, REC, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((step2_kernel<ST, LAW, FIELDS, REC, false>), grid, block, 0, s, a);
+}
+
 template <int ST, int LAW>
 static hipError_t step2_st_law(const Step2Args& a, hipStream_t s) {
     const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
-    const dim3 grid(unsigned(int64_t(a.nstrip) * ((a.cm.ny + kPairRows - 1) / kPairRows)));
-    const dim3 block((kPairWaves + 1) * kTile);
+    const bool walls = !(a.cm.periodic_x && a.cm.periodic_y);
     // the record writes are compiled in only where asked for: their mere presence costs the
     // plain kernel about a tenth of its speed
     const bool rec = a.record1 || a.record2;
+    if (a.wall_pass) {
+        const int links = 2 * a.cm.nx + 2 * a.cm.ny;
+        const dim3 grid(nblocks(links)), block(kBlock);
+        if (fields) {
+            if (rec) hipLaunchKernelGGL((step2_wall_kernel<ST, LAW, true, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((step2_wall_kernel<ST, LAW, true, false>), grid, block, 0, s, a);
+        } else {
+            if (rec) hipLaunchKernelGGL((step2_wall_kernel<ST, LAW, false, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((step2_wall_kernel<ST, LAW, false, false>), grid, block, 0, s, a);
+        }
+        return hipGetLastError();
+    }
     if (fields) {
-        if (rec) hipLaunchKernelGGL((step2_kernel<ST, LAW, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((step2_kernel<ST, LAW, true, false>), grid, block, 0, s, a);
+        if (rec) step2_launch<ST, LAW, true, true>(a, s, walls);
+        else step2_launch<ST, LAW, true, false>(a, s, walls);
     } else {
-        if (rec) hipLaunchKernelGGL((step2_kernel<ST, LAW, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((step2_kernel<ST, LAW, false, false>), grid, block, 0, s, a);
+        if (rec) step2_launch<ST, LAW, false, true>(a, s, walls);
+        else step2_launch<ST, LAW, false, false>(a, s, walls);
     }
     return hipGetLastError();
 }
@@ -868,8 +1047,13 @@ template <int ST, int LAW>
 static hipError_t traction_st_law(const TractionArgs& a, hipStream_t s) {
     const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
     const int L = (a.edge == LBM_XMIN || a.edge == LBM_XMAX) ? a.cm.ny : a.cm.nx;
-    if (fields) hipLaunchKernelGGL((traction_kernel<ST, LAW, true>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((traction_kernel<ST, LAW, false>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
+    if (a.lines) {
+        if (fields) hipLaunchKernelGGL((traction_kernel<ST, LAW, true, true>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((traction_kernel<ST, LAW, false, true>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
+    } else {
+        if (fields) hipLaunchKernelGGL((traction_kernel<ST, LAW, true, false>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((traction_kernel<ST, LAW, false, false>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -81,6 +81,10 @@ struct Step2Args {
     const void* src;                 // f*^n
     void* dst;                       // f*^{n+2}
     void* ustar;
+    void* aux;                       // F^b staging and wall lines (grids with walls)
+    EdgeData ed;                     // wall data at t^{n+1/2}
+    EdgeData ed2;                    // wall data at t^{n+3/2}
+    int wall_pass;                   // launch the wall-node kernel instead of the bulk kernel
     void* record1;                   // U^{n+1} or NULL
     void* record2;                   // U^{n+2} or NULL
     int fold1, fold2;                // accumulator folds after the first / second step
@@ -96,6 +100,7 @@ struct TractionArgs {
     double r_n;
     EdgeData ed;
     int edge;
+    int lines;                       // read level n from the wall lines of aux instead of pop
 };
 
 struct RecoverArgs {

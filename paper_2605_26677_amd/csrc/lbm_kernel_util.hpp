@@ -66,17 +66,21 @@ __device__ __forceinline__ LawK<R> law_consts(const Common& cm) {
 // Sum of the four stored post-collision populations of one node minus (dt/2) B: the
 // state of that level (sum_q f* = U + (dt/2) B, from eq:collision with sum_q w = 1/2).
 template <typename T, typename R>
-__device__ __forceinline__ void recover_node(const T* pop, int ntile, int x, int y, R hb0, R hb1, R U[6]) {
-    const int64_t b = tile_base(ntile, 24, x, y);
+__device__ __forceinline__ void recover_vals(const T* p, int64_t stride, R hb0, R hb1, R U[6]) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         R s = R(0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s += R(pop[b + (6 * q + k) * kTile]);
+        for (int q = 0; q < 4; ++q) s += R(p[(6 * q + k) * stride]);
         U[k] = s;
     }
     U[0] -= hb0;
     U[1] -= hb1;
+}
+
+template <typename T, typename R>
+__device__ __forceinline__ void recover_node(const T* pop, int ntile, int x, int y, R hb0, R hb1, R U[6]) {
+    recover_vals<T, R>(pop + tile_base(ntile, 24, x, y), kTile, hb0, hb1, U);
 }
 
 // ---------------------------------------------------------------- traction Newton
@@ -180,6 +184,46 @@ struct XY {
 __device__ __forceinline__ XY edge_node(const EdgeGeom& G, int nx, int ny, int r, int s2) {
     if (G.A == 0) return XY{(G.NA < 0) ? r : nx - 1 - r, s2};
     return XY{s2, (G.NA < 0) ? r : ny - 1 - r};
+}
+
+// Wall lines of the two-level step on grids with walls.  The staging buffer (aux) holds,
+// after the F^b of every link (4 values of 8 bytes each), the populations of level n+1 on
+// the wall line (r = 0) and the first interior line (r = 1) of every edge, 24 values of
+// 8 bytes per node, and the state U^{n+1} of the wall-line nodes, 6 values of 8 bytes:
+//   line value p of node s of line r of edge e at  lines + (2 off[e] + r len[e] + s) 24 + p
+//   U^{n+1} component k of wall node s of edge e at u1 + (off[e] + s) 6 + k
+// (off, len from edge_offsets, in links).
+struct WallLines {
+    char* lines;
+    char* u1;
+};
+
+__host__ __device__ inline WallLines wall_lines(void* aux, int nx, int ny) {
+    const int64_t links = 2 * int64_t(nx) + 2 * int64_t(ny);
+    WallLines w;
+    w.lines = (char*)aux + links * 4 * 8;
+    w.u1 = w.lines + links * 2 * 24 * 8;
+    return w;
+}
+
+__host__ __device__ inline int64_t line_slot(int nx, int ny, int e, int r, int s) {
+    int off[4], len[4];
+    edge_offsets(nx, ny, off, len);
+    return 2 * int64_t(off[e]) + int64_t(r) * len[e] + s;
+}
+
+// A line of a wall edge that holds node (x, y): the first of XMIN, XMAX, YMIN, YMAX whose
+// wall line or first interior line passes through it.
+__device__ __forceinline__ bool find_line(const Common& cm, int x, int y, int& e, int& r, int& s) {
+    if (!cm.periodic_x) {
+        if (x <= 1) { e = LBM_XMIN; r = x; s = y; return true; }
+        if (x >= cm.nx - 2) { e = LBM_XMAX; r = cm.nx - 1 - x; s = y; return true; }
+    }
+    if (!cm.periodic_y) {
+        if (y <= 1) { e = LBM_YMIN; r = y; s = x; return true; }
+        if (y >= cm.ny - 2) { e = LBM_YMAX; r = cm.ny - 1 - y; s = x; return true; }
+    }
+    return false;
 }
 
 // Tile-grid position of this thread for kernels with one wavefront per tile and

@@ -256,13 +256,18 @@ def _step_to_snapshot(sv, cfg, n, ustar=True):
     return (sv.pop[sv.s.cur].clone(), rec)
 
 
+def _pair(sv, cfg, n, record1=None, record2=None, ustar=True):
+    sv.step2(n, cfg.ramp(n + 1), cfg.ramp(n + 2), record1=record1, record2=record2, ustar=ustar,
+             r_n=cfg.ramp(n), edges=_edges(cfg, n), edges_next=_edges(cfg, n + 1))
+
+
 def _plain_steps(sv, cfg, n0, n1, ustar=True):
-    """Steps n0 .. n1 - 1 without records; on periodic grids in pairs through lbm_step2
-    (bit for bit the same result as single steps)."""
+    """Steps n0 .. n1 - 1 without records, in pairs through lbm_step2 (bit for bit the same
+    result as single steps)."""
     n = n0
     while n < n1:
-        if sv.periodic and n + 1 < n1:
-            sv.step2(n, cfg.ramp(n + 1), cfg.ramp(n + 2), ustar=ustar)
+        if sv.pairs_ok and n + 1 < n1:
+            _pair(sv, cfg, n, ustar=ustar)
             n += 2
         else:
             sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), ustar=ustar)
@@ -272,14 +277,13 @@ def _plain_steps(sv, cfg, n0, n1, ustar=True):
 def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
     """Adjoint levels end-1 .. start, starting from the snapshot of level `start`.  The
     replay skips the displacement quadrature (the adjoint does not read u*) and records
-    U of every level, two levels per call on periodic grids."""
+    U of every level, two levels per call."""
     _restore(sv, snap)
     recs[0].copy_(snap[1], non_blocking=True)
     n = start
     while n < end - 1:
-        if sv.periodic and n + 1 < end - 1:
-            sv.step2(n, cfg.ramp(n + 1), cfg.ramp(n + 2), record1=recs[n + 1 - start],
-                     record2=recs[n + 2 - start], ustar=False)
+        if sv.pairs_ok and n + 1 < end - 1:
+            _pair(sv, cfg, n, record1=recs[n + 1 - start], record2=recs[n + 2 - start], ustar=False)
             n += 2
         else:
             sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=recs[n + 1 - start], ustar=False)

@@ -81,7 +81,8 @@ class StepGraph:
     def __init__(self, solver, steps):
         self.sv = solver
         self.start_cur = solver.s.cur
-        self._keep = [st.get("edges") for st in steps] + [st.get("record") for st in steps]
+        self._keep = ([st.get("edges") for st in steps] + [st.get("edges_next") for st in steps]
+                      + [st.get("record") for st in steps])
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             for st in steps:
@@ -213,16 +214,20 @@ class Solver:
         finally:
             self.s.ustar = keep
 
-    def step2(self, n, r_np1=1.0, r_np2=1.0, record1=None, record2=None, ustar=True):
-        """lbm_step2: levels n -> n + 2 in one pass (periodic grids), bit for bit the same as
-        step(n) then step(n + 1) with the same factors; record1 / record2 receive U^{n+1} and
-        U^{n+2}."""
+    def step2(self, n, r_np1=1.0, r_np2=1.0, record1=None, record2=None, ustar=True, r_n=1.0, edges=None,
+              edges_next=None):
+        """lbm_step2: levels n -> n + 2 in one pass, bit for bit the same as step(n, r_n, r_np1,
+        edges) then step(n + 1, r_np1, r_np2, edges_next); record1 / record2 receive U^{n+1}
+        and U^{n+2}."""
+        e1 = edges if isinstance(edges, EdgeData) else EdgeData(edges)
+        e2 = edges_next if isinstance(edges_next, EdgeData) else EdgeData(edges_next)
         keep = self.s.ustar
         if not ustar:
             self.s.ustar = None
         try:
-            L.check(self.lib.lbm_step2(ctypes.byref(self.p), ctypes.byref(self.s), int(n), float(r_np1),
-                                       float(r_np2), _ptr(record1), _ptr(record2), _stream()), "lbm_step2")
+            L.check(self.lib.lbm_step2(ctypes.byref(self.p), ctypes.byref(self.s), int(n), float(r_n), float(r_np1),
+                                       float(r_np2), ctypes.byref(e1.c), ctypes.byref(e2.c), _ptr(record1),
+                                       _ptr(record2), _stream()), "lbm_step2")
         finally:
             self.s.ustar = keep
 
@@ -230,9 +235,15 @@ class Solver:
     def periodic(self):
         return all(int(b) == L.BC["periodic"] for b in self.p.bc)
 
+    @property
+    def pairs_ok(self):
+        """lbm_step2 equals two lbm_step calls unless per-level body fields are in use."""
+        return not self.s.body_prev
+
     def _run(self, st):
         if st.get("pair"):
-            self.step2(st["n"], st["r_np1"], st["r_np2"])
+            self.step2(st["n"], st["r_np1"], st["r_np2"], r_n=st["r_n"], edges=st.get("edges"),
+                       edges_next=st.get("edges_next"))
         else:
             self.step(**st)
 
@@ -245,19 +256,19 @@ class Solver:
         """Steps n0 .. n0 + count - 1 with ramp factors ``ramp(n)`` (default 1) and wall data
         ``edges(n)`` (default zero): whole blocks of ``block`` steps whose arguments equal
         those of the first captured block replay one captured graph, the rest run eagerly.
-        For launch-bound grids this removes the per-step host cost.  On periodic grids
-        (``fused`` None or True) the steps go in pairs through lbm_step2, with the same
-        result bit for bit."""
+        For launch-bound grids this removes the per-step host cost.  With ``fused`` None or
+        True the steps go in pairs through lbm_step2, with the same result bit for bit."""
         ramp = ramp or (lambda n: 1.0)
         edges = edges or (lambda n: None)
-        fused = self.periodic if fused is None else (bool(fused) and self.periodic)
+        fused = self.pairs_ok if fused is None else (bool(fused) and self.pairs_ok)
 
         def block_calls(n, m):
             # the calls for steps n .. m - 1
             calls = []
             while n < m:
                 if fused and n + 1 < m:
-                    calls.append(dict(pair=True, n=n, r_np1=float(ramp(n + 1)), r_np2=float(ramp(n + 2))))
+                    calls.append(dict(pair=True, n=n, r_n=float(ramp(n)), r_np1=float(ramp(n + 1)),
+                                      r_np2=float(ramp(n + 2)), edges=edges(n), edges_next=edges(n + 1)))
                     n += 2
                 else:
                     calls.append(dict(n=n, r_n=float(ramp(n)), r_np1=float(ramp(n + 1)), edges=edges(n)))
@@ -287,7 +298,8 @@ class Solver:
     def _same(a, b):
         keys = ("pair", "r_n", "r_np1", "r_np2")
         return (all(a.get(k) == b.get(k) for k in keys)
-                and _edge_key(a.get("edges")) == _edge_key(b.get("edges")))
+                and _edge_key(a.get("edges")) == _edge_key(b.get("edges"))
+                and _edge_key(a.get("edges_next")) == _edge_key(b.get("edges_next")))
 
     @classmethod
     def _graph_ok(cls, blk):

@@ -169,14 +169,23 @@ def test_walls_need_boundary_data():
     assert lib.lbm_step(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, None, None, None) == L.LBM_ERR_ARG
 
 
-def test_step2_periodic_only():
-    """lbm_step2 (two fused levels) refuses a grid with walls, and missing buffers, before
-    any launch."""
+def test_step2_argument_checks():
+    """lbm_step2 (two fused levels) refuses missing buffers, and on a grid with walls missing
+    boundary data of either half step or a missing staging buffer, before any launch."""
     lib = L.lib()
     fake = 256
     s = L.lbm_state()
     p = _params()
-    assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, None, None, None) == L.LBM_ERR_ARG
+    assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, 1.0, None, None, None, None,
+                         None) == L.LBM_ERR_ARG
     s.pop[0], s.pop[1], s.fault = fake, fake, fake
-    p = _params(bc=(L.LBM_VELOCITY, L.LBM_TRACTION, 0, 0))
-    assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, None, None, None) == L.LBM_ERR_UNSUPPORTED
+    p = _params(bc=(L.LBM_VELOCITY, L.LBM_VELOCITY, 0, 0))
+    ed = L.lbm_edge_data()
+    s.aux = fake
+    assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, 1.0, ctypes.byref(ed), None, None, None,
+                         None) == L.LBM_ERR_ARG
+    assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, 1.0, None, ctypes.byref(ed), None, None,
+                         None) == L.LBM_ERR_ARG
+    s.aux = None
+    assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, 1.0, ctypes.byref(ed), ctypes.byref(ed),
+                         None, None, None) == L.LBM_ERR_ARG

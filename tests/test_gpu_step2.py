@@ -3,7 +3,9 @@ steps (lbm_step) and against the FP64 oracle.
 
 lbm_step2 promises the result of lbm_step(n) followed by lbm_step(n + 1), bit for bit: the
 populations, both words of the displacement accumulator across its 16-level folds (or the
-FP64 planes), and the fault word.  The cases cover every storage and law; uniform and
+FP64 planes), the records and the fault word, on periodic grids and on grids with
+velocity and traction walls (corners, walls along one axis only, wall data that change
+every half step, per-node wall data).  The cases cover every storage and law; uniform and
 per-node mu, lam and body force, with different ramp factors at the two levels; grids that
 are multiples of neither the 62-column strip nor the 6-row block of the kernel, grids
 narrower than one strip (the lanes then wrap the periodic axis several times) down to the
@@ -139,14 +141,103 @@ def test_step2_records_equal_single_step_records(storage):
     assert single.faults() == pair.faults() == 0
 
 
-def test_step2_refuses_walls():
-    from paper_2605_26677_amd._lib import LBMError
-    case = _case(32, 32)
-    case.kinds = ("velocity", "traction", "traction", "traction")
-    sv = make_solver(case, "f32")
-    sv.init(case.v0)
-    with pytest.raises(LBMError):
-        sv.step2(0)
+WALL_KINDS = {
+    "block": ("velocity", "traction", "traction", "traction"),
+    "mixed": ("velocity", "traction", "traction", "velocity"),
+    "traction4": ("traction",) * 4,
+    "y_walls": ("periodic", "periodic", "traction", "velocity"),
+    "x_walls": ("velocity", "traction", "periodic", "periodic"),
+}
+
+
+def _wall_data(kinds, n, nx, ny, field_edge=None):
+    """Wall data of half step n: uniform values that change every half step, and on one
+    edge optionally a per-node field."""
+    base = {"velocity": (1e-4, -2e-4), "traction": (3e-4, -1e-4), "periodic": None}
+    out = []
+    for e, k in enumerate(kinds):
+        if base[k] is None:
+            out.append(None)
+            continue
+        f = 1.0 + 0.05 * n
+        if e == field_edge:
+            L = ny if e < 2 else nx
+            s = np.linspace(0.5, 1.5, L)
+            out.append(torch.tensor(np.stack([base[k][0] * f * s, base[k][1] * f * s[::-1]]), device="cuda"))
+        else:
+            out.append((base[k][0] * f, base[k][1] * f))
+    return out
+
+
+def _walls_pair_vs_single(kinds, nx, ny, storage, fields, start, pairs, law="lognh", field_edge=None, records=False):
+    case = _case(nx, ny, law=law, fields=fields, rms=1e-3)
+    case.kinds = kinds
+    single = make_solver(case, storage)
+    pair = make_solver(case, storage)
+    data = lambda n: _wall_data(kinds, n, nx, ny, field_edge)
+    for sv in (single, pair):
+        sv.init(case.v0, r0=case.ramp(0))
+        for m in range(start):
+            sv.step(m, case.ramp(m), case.ramp(m + 1), edges=data(m))
+    n = start
+    for _ in range(pairs):
+        ra = rb = pa = pb = None
+        if records:
+            ra, rb, pa, pb = (single.new_record() for _ in range(4))
+        single.step(n, case.ramp(n), case.ramp(n + 1), edges=data(n), record=ra)
+        single.step(n + 1, case.ramp(n + 1), case.ramp(n + 2), edges=data(n + 1), record=rb)
+        pair.step2(n, case.ramp(n + 1), case.ramp(n + 2), record1=pa, record2=pb, r_n=case.ramp(n),
+                   edges=data(n), edges_next=data(n + 1))
+        if records:
+            w = int(single.lib.lbm_tile_width())
+            T = single.tiles_per_row
+
+            def valid(r):
+                return r.view(ny, T, 6, w).permute(2, 0, 1, 3).reshape(6, ny, T * w)[:, :, :nx]
+            assert torch.equal(valid(ra), valid(pa)) and torch.equal(valid(rb), valid(pb)), n
+        n += 2
+    torch.cuda.synchronize()
+    diff = (single.populations().double() - pair.populations().double()).abs()
+    assert torch.equal(single.populations(), pair.populations()), (
+        f"{int((diff > 0).sum())} differences, first at {(diff > 0).nonzero()[:4].tolist()}")
+    for a, b in zip(_ustar_words(single), _ustar_words(pair)):
+        if a is not None:
+            assert torch.equal(a, b)
+    assert torch.equal(single.displacement(case.ramp(n)), pair.displacement(case.ramp(n)))
+    assert single.faults() == pair.faults() == 0
+
+
+@pytest.mark.parametrize("kind", list(WALL_KINDS))
+@pytest.mark.parametrize("nx,ny", [(64, 40), (130, 13), (5, 6)])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
+def test_step2_walls_bitwise_equals_two_steps(kind, nx, ny, storage):
+    for start, fields in ((0, False), (1, True)):
+        _walls_pair_vs_single(WALL_KINDS[kind], nx, ny, storage, fields, start, pairs=10)
+
+
+@pytest.mark.parametrize("law", ["svk", "gent", "nh"])
+def test_step2_walls_every_law_field_edge_records(law):
+    """Other laws, per-node wall data on one edge, and the records of both levels."""
+    _walls_pair_vs_single(WALL_KINDS["mixed"], 97, 20, "f32", True, 1, pairs=8, law=law, field_edge=1,
+                          records=True)
+
+
+def test_advance_in_pairs_with_walls_equals_single_steps():
+    """Solver.advance on a grid with walls (captured pairs and an eager tail)."""
+    case = _case(100, 70, fields=True, rms=1e-3)
+    case.kinds = WALL_KINDS["block"]
+    data = lambda n: _wall_data(case.kinds, 0, case.nx, case.ny)
+    eager = make_solver(case, "f32")
+    adv = make_solver(case, "f32")
+    for sv in (eager, adv):
+        sv.init(case.v0, r0=case.ramp(0))
+    N = 83
+    for m in range(N):
+        eager.step(m, case.ramp(m), case.ramp(m + 1), edges=data(m))
+    adv.advance(0, N, ramp=case.ramp, edges=data, block=32)
+    assert torch.equal(eager.populations(), adv.populations())
+    assert torch.equal(eager.displacement(case.ramp(N)), adv.displacement(case.ramp(N)))
+    assert eager.faults() == adv.faults() == 0
 
 
 def test_advance_in_pairs_equals_single_steps():
