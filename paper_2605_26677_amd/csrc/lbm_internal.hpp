@@ -60,7 +60,7 @@ struct StepArgs {
 
 // Two fused steps on a periodic grid (step2_kernel): workgroups of kPairWaves + 1
 // wavefronts, each owning kPairRows rows of a strip of kPairCols (one tile of) columns.
-constexpr int kPairWaves = 6;
+constexpr int kPairWaves = 7;
 constexpr int kPairRows = kPairWaves - 2;
 constexpr int kPairCols = 64;
 constexpr int kPairChunk = 32;       // strips per chunk of the workgroup order
