@@ -335,12 +335,8 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
     const int64_t n = int64_t(nx) * ny;
-    const int b = remap_tile(blockIdx.x, gridDim.x);
-    const int chunk = b / a.per_chunk;
-    const int rem = b - chunk * a.per_chunk;
-    const int kc = min(a.chunk, a.nstrip - chunk * a.chunk);
-    const int blk = rem / kc;
-    const int strip = chunk * a.chunk + (rem - blk * kc);
+    int strip, blk;
+    pair_block(a.map, remap_tile(blockIdx.x, gridDim.x), strip, blk);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
     const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;
@@ -753,7 +749,7 @@ hipError_t launch_adjoint_probe(const AdjArgs& a, hipStream_t s) {
 template <int ST, int LAW>
 static hipError_t adjoint2_st_law(const Adj2Args& a, hipStream_t s) {
     const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
-    const dim3 grid(unsigned(int64_t(a.nstrip) * ((a.cm.ny + kPairRows - 1) / kPairRows)));
+    const dim3 grid(unsigned(pair_map_blocks(a.map)));
     const dim3 block((kPairWaves + 1) * kTile);
     if (fields) hipLaunchKernelGGL((adjoint2_kernel<ST, LAW, true>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((adjoint2_kernel<ST, LAW, false>), grid, block, 0, s, a);

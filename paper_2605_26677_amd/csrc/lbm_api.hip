@@ -249,7 +249,6 @@ lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_n, d
     a.fold1 = (n + 1) % kUstarBlock == 0;
     a.fold2 = (n + 2) % kUstarBlock == 0;
     a.nstrip = (p->nx + kPairCols - 1) / kPairCols;
-    pair_chunks(a.nstrip, p->ny, a.chunk, a.per_chunk);
     a.r_np1 = r_np1;
     a.r_np2 = r_np2;
     // F^b of level n from f*^n, as lbm_step takes it
@@ -416,7 +415,10 @@ lbm_status lbm_adjoint_step2(const lbm_params* p, const lbm_state* fwd, lbm_adj_
     a.fold1 = m % kGradBlock == 0;
     a.fold2 = (m - 1) % kGradBlock == 0;
     a.nstrip = (p->nx + kTile - 1) / kTile;
-    pair_chunks(a.nstrip, p->ny, a.chunk, a.per_chunk);
+    {
+        const int nblk = (p->ny + kPairRows - 1) / kPairRows;
+        a.map = pair_map(a.nstrip, nblk, 0, a.nstrip, 0, nblk);
+    }
     a.r1 = r_m;
     a.r2 = r_mm1;
     a.pmask = adj->nprobe > 0 ? mask : nullptr;

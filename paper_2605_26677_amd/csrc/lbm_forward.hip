@@ -397,15 +397,8 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
     const int64_t n = int64_t(nx) * ny;
-    // workgroup order: chunks of kPairChunk strips side by side, and inside a chunk the
-    // strips of one block row, then of the next, so that the neighbours that re-read a
-    // block's edge rows run soon after it on the same XCD's L2
-    const int b = remap_tile(blockIdx.x, gridDim.x);
-    const int chunk = b / a.per_chunk;
-    const int rem = b - chunk * a.per_chunk;
-    const int kc = min(a.chunk, a.nstrip - chunk * a.chunk);
-    const int blk = rem / kc;
-    const int strip = chunk * a.chunk + (rem - blk * kc);
+    int strip, blk;
+    pair_block(a.map, remap_tile(blockIdx.x, gridDim.x), strip, blk);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
     const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;
@@ -978,12 +971,46 @@ static hipError_t step_st(const StepArgs& a, hipStream_t s) {
     }
 }
 
+// The two-level bulk launch.  On a grid with walls, the blocks whose level-(n+1) region
+// keeps two nodes away from every wall line run the periodic instantiation (no wall code:
+// compiled in, the wall branches cost every node about a sixth of its speed), and only the
+// blocks along the walls run the wall instantiation.
 template <int ST, int LAW, bool FIELDS, bool REC>
-static void step2_launch(const Step2Args& a, hipStream_t s, bool walls) {
-    const dim3 grid(unsigned(int64_t(a.nstrip) * ((a.cm.ny + kPairRows - 1) / kPairRows)));
+static void step2_launch(const Step2Args& a0, hipStream_t s, bool walls) {
     const dim3 block((kPairWaves + 1) * kTile);
-    if (walls) hipLaunchKernelGGL((step2_kernel<ST, LAW, FIELDS, REC, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((step2_kernel<ST, LAW, FIELDS, REC, false>), grid, block, 0, s, a);
+    const int nstrip = a0.nstrip, nblk = (a0.cm.ny + kPairRows - 1) / kPairRows;
+    auto go = [&](const PairMap& m, bool w) {
+        const int64_t nb = pair_map_blocks(m);
+        if (nb <= 0) return;
+        Step2Args a = a0;
+        a.map = m;
+        if (w) hipLaunchKernelGGL((step2_kernel<ST, LAW, FIELDS, REC, true>), dim3(unsigned(nb)), block, 0, s, a);
+        else hipLaunchKernelGGL((step2_kernel<ST, LAW, FIELDS, REC, false>), dim3(unsigned(nb)), block, 0, s, a);
+    };
+    if (!walls) {
+        go(pair_map(nstrip, nblk, 0, nstrip, 0, nblk), false);
+        return;
+    }
+    // interior: columns c0 - 1 .. c0 + 64 within [2, nx - 3], rows y0 - 1 .. y0 + R within
+    // [2, ny - 3] along each axis with walls
+    int s_lo = 0, s_hi = nstrip, b_lo = 0, b_hi = nblk;
+    if (!a0.cm.periodic_x) {
+        s_lo = 1;
+        s_hi = a0.cm.nx - 3 - kTile >= 0 ? (a0.cm.nx - 3 - kTile) / kTile + 1 : 0;
+    }
+    if (!a0.cm.periodic_y) {
+        b_lo = (3 + kPairRows - 1) / kPairRows;
+        b_hi = a0.cm.ny - 3 - kPairRows >= 0 ? (a0.cm.ny - 3 - kPairRows) / kPairRows + 1 : 0;
+    }
+    if (s_hi <= s_lo || b_hi <= b_lo) {
+        go(pair_map(nstrip, nblk, 0, nstrip, 0, nblk), true);
+        return;
+    }
+    const PairMap inner = pair_map(nstrip, nblk, s_lo, s_hi, b_lo, b_hi);
+    PairMap rim = inner;
+    rim.mode = 1;
+    go(inner, false);
+    go(rim, true);
 }
 
 template <int ST, int LAW>

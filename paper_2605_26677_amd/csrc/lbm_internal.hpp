@@ -65,15 +65,68 @@ constexpr int kPairRows = kPairWaves - 2;
 constexpr int kPairCols = 64;
 constexpr int kPairChunk = 32;       // strips per chunk of the workgroup order
 
-// Chunk width of the two-level kernels' workgroup order for a grid of nstrip x nblk blocks:
-// kPairChunk strips, fewer where chunk * nblk would not fit 32-bit arithmetic.
-inline void pair_chunks(int nstrip, int ny, int& chunk, int& per_chunk) {
-    const int64_t nblk = (int64_t(ny) + kPairRows - 1) / kPairRows;
+// Workgroups of a two-level launch.  mode 0: the blocks [s_lo, s_hi) x [b_lo, b_hi) of
+// strips x block rows, in chunks of `chunk` strips side by side and inside a chunk one
+// block row after the other (per_chunk = chunk * (b_hi - b_lo) workgroups per chunk), so
+// that the workgroups that re-read a block's edge rows run soon after it on the same
+// XCD's L2.  mode 1: every block outside that rectangle (the blocks along the walls):
+// block rows [0, b_lo) and [b_hi, nblk) over all strips, then the strips outside
+// [s_lo, s_hi) over the block rows [b_lo, b_hi).
+struct PairMap {
+    int mode;
+    int nstrip, nblk;
+    int s_lo, s_hi, b_lo, b_hi;
+    int chunk, per_chunk;
+};
+
+// Workgroups of mode 0 over the given rectangle; the chunk width is kPairChunk strips,
+// fewer where chunk * rows would not fit 32-bit arithmetic.
+inline PairMap pair_map(int nstrip, int nblk, int s_lo, int s_hi, int b_lo, int b_hi) {
+    PairMap m{};
+    m.mode = 0;
+    m.nstrip = nstrip;
+    m.nblk = nblk;
+    m.s_lo = s_lo; m.s_hi = s_hi; m.b_lo = b_lo; m.b_hi = b_hi;
+    const int64_t rows = b_hi - b_lo;
     int64_t c = kPairChunk;
-    while (c > 1 && c * nblk > 0x7fffffff) c >>= 1;
-    if (c > nstrip) c = nstrip;
-    chunk = int(c);
-    per_chunk = int(c * nblk);
+    while (c > 1 && c * rows > 0x7fffffff) c >>= 1;
+    if (c > s_hi - s_lo) c = s_hi - s_lo;
+    if (c < 1) c = 1;
+    m.chunk = int(c);
+    m.per_chunk = int(c * rows);
+    return m;
+}
+
+inline int64_t pair_map_blocks(const PairMap& m) {
+    const int64_t inner = int64_t(m.s_hi - m.s_lo) * (m.b_hi - m.b_lo);
+    return m.mode == 0 ? inner : int64_t(m.nstrip) * m.nblk - inner;
+}
+
+__device__ __forceinline__ void pair_block(const PairMap& m, int b, int& strip, int& blk) {
+    if (m.mode == 0) {
+        const int chunk = b / m.per_chunk;
+        const int rem = b - chunk * m.per_chunk;
+        const int kc = min(m.chunk, (m.s_hi - m.s_lo) - chunk * m.chunk);
+        const int bb = rem / kc;
+        strip = m.s_lo + chunk * m.chunk + (rem - bb * kc);
+        blk = m.b_lo + bb;
+        return;
+    }
+    const int n1 = m.b_lo * m.nstrip, n2 = (m.nblk - m.b_hi) * m.nstrip;
+    if (b < n1) {
+        blk = b / m.nstrip;
+        strip = b - blk * m.nstrip;
+    } else if (b < n1 + n2) {
+        const int j = b - n1;
+        blk = m.b_hi + j / m.nstrip;
+        strip = j % m.nstrip;
+    } else {
+        const int side = m.s_lo + (m.nstrip - m.s_hi);
+        const int j = b - n1 - n2;
+        blk = m.b_lo + j / side;
+        const int t = j % side;
+        strip = t < m.s_lo ? t : m.s_hi + (t - m.s_lo);
+    }
 }
 
 struct Step2Args {
@@ -89,7 +142,7 @@ struct Step2Args {
     void* record2;                   // U^{n+2} or NULL
     int fold1, fold2;                // accumulator folds after the first / second step
     int nstrip;                      // strips of kPairCols columns (= tiles per row)
-    int chunk, per_chunk;            // strips per chunk of the workgroup order, workgroups per chunk
+    PairMap map;                     // the workgroups of this launch
     double r_np1, r_np2;
 };
 
@@ -156,7 +209,7 @@ struct Adj2Args {
     void* gsum;
     int fold1, fold2;                // block-sum folds at levels m and m - 1
     int nstrip;
-    int chunk, per_chunk;            // as in Step2Args
+    PairMap map;                     // as in Step2Args
     double r1, r2;                   // body factors r(m), r(m-1)
     const uint64_t* pmask;           // probe table (lbm_adjoint_probe_table) or NULL
     const double* pfield;
