@@ -373,8 +373,8 @@ __device__ __forceinline__ void store_wall_lines(const Common& cm, void* aux, in
     }
 }
 
-// Temporal blocking of the periodic step: one pass takes f*^n to f*^{n+2} without storing
-// level n+1.  A workgroup owns a block of kPairRows rows of one 64-node tile column (a
+// Temporal blocking of the step: one pass takes f*^n to f*^{n+2} without storing level
+// n+1.  A workgroup owns a block of kPairRows rows of one 64-node tile column (a
 // strip).  Wave w < kPairWaves takes row y0 - 1 + w of the strip through level n+1,
 // pulling level n straight from HBM; one more wave takes the two columns beside the strip
 // (x = c0 - 1 and c0 + 64) through level n+1 on the block's rows.  The level n+1 values
@@ -384,7 +384,9 @@ __device__ __forceinline__ void store_wall_lines(const Common& cm, void* aux, in
 // are computed by the neighbouring workgroups as well), and loads and stores are whole
 // aligned tiles.  Each node's arithmetic is collide_node, as in step_kernel, and level
 // n+1 is rounded to the storage type, so the result is bit for bit that of two single
-// steps.
+// steps.  WALLS: the level-n links of wall nodes are rebuilt in the first level as
+// step_kernel rebuilds them, the wall nodes are left out of the second level, and level
+// n+1 of the wall lines goes to the staging buffer for step2_wall_kernel.
 template <int ST, int LAW, bool FIELDS, bool REC, bool WALLS>
 __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Args a) {
     using Tr = Storage<ST>;

@@ -58,8 +58,9 @@ struct StepArgs {
     EdgeData ed;                     // data at t^{n+1/2}
 };
 
-// Two fused steps on a periodic grid (step2_kernel): workgroups of kPairWaves + 1
-// wavefronts, each owning kPairRows rows of a strip of kPairCols (one tile of) columns.
+// Two fused steps (step2_kernel, adjoint2_kernel): workgroups of kPairWaves row wavefronts
+// and one edge wavefront, each owning kPairRows rows of a strip of kPairCols (one tile of)
+// columns.
 constexpr int kPairWaves = 7;
 constexpr int kPairRows = kPairWaves - 2;
 constexpr int kPairCols = 64;

@@ -67,8 +67,8 @@ def _edge_key(edges):
 
 
 class StepGraph:
-    """A fixed sequence of lbm_step calls recorded once as a HIP graph (the library's
-    launches are captured from torch's capture stream) and replayed as one launch.
+    """A fixed sequence of lbm_step / lbm_step2 calls recorded once as a HIP graph (the
+    library's launches are captured from torch's capture stream) and replayed as one launch.
 
     Every argument is frozen at capture: step factors, wall data (values, or the addresses
     of field tensors, which the graph keeps alive), record buffers, and the two population
@@ -249,7 +249,8 @@ class Solver:
 
     def capture(self, steps):
         """Records a fixed sequence of lbm_step calls as one HIP graph (``StepGraph``).
-        ``steps`` is a list of dicts with the keyword arguments of ``step``."""
+        ``steps`` is a list of dicts with the keyword arguments of ``step``, or, with
+        ``pair=True``, of ``step2`` (n, r_n, r_np1, r_np2, edges, edges_next)."""
         return StepGraph(self, steps)
 
     def advance(self, n0, count, ramp=None, edges=None, block=64, fused=None):
