@@ -48,6 +48,8 @@ class RolloutConfig:
     law_k: Optional[Sequence[float]] = None            # invariant-law constants (lbm.h law_k)
     Fbar: Optional[Sequence[Sequence[float]]] = None   # uniform predeformation at t = 0
     host_top: bool = False                             # outermost snapshots in pinned host memory
+    revolve: int = 0                                   # binomial checkpointing with this many
+                                                       # snapshot slots (0: every K or levels)
 
 
 def _sizes(nx, ny, storage):
@@ -175,6 +177,36 @@ def plan_checkpoints(nx, ny, storage, nsteps, device_budget_bytes, host_budget_b
             return dict(levels=K, host_top=host, model=m)
     raise ValueError(f"no schedule up to depth {max_depth} fits {device_budget_bytes / 2**30:.1f} GiB of device "
                      f"memory and {host_budget_bytes / 2**30:.1f} GiB of host memory")
+
+
+def revolve_actions(start, end, leaf, slots):
+    """Binomial checkpointing (Griewank's treeverse) of the reversal of levels [start, end)
+    (adjoint steps end-1 .. start), holding the snapshot of `start` and `slots` more
+    snapshot slots; the unit is a leaf segment of at most `leaf` levels, reversed from one
+    replay that records every level.  With l units and c free slots, r is the smallest
+    repetition count with beta(c, r) = C(c + r, c) >= l; the first checkpoint goes m units
+    in, m in [l - beta(c - 1, r), beta(c, r - 1)], so that the part after it is reversed
+    with c - 1 slots and the part before with c slots and one repetition less.
+
+    Yields ("take", a, m): restore the snapshot of level a, step to level m and keep its
+    snapshot; ("leaf", a, b): reverse levels [a, b) from the snapshot of level a;
+    ("free", m): drop the snapshot of level m."""
+    units = -(-(end - start) // leaf)
+    if units <= 1:
+        yield ("leaf", start, end)
+        return
+    if slots < 1:
+        raise ValueError("binomial checkpointing needs a free snapshot slot for more than one leaf segment")
+    r = 1
+    while math.comb(slots + r, slots) < units:
+        r += 1
+    m_units = max(1, units - math.comb(slots - 1 + r, slots - 1))
+    m_units = min(m_units, math.comb(slots + r - 1, slots), units - 1)
+    mid = start + m_units * leaf
+    yield ("take", start, mid)
+    yield from revolve_actions(mid, end, leaf, slots - 1)
+    yield ("free", mid)
+    yield from revolve_actions(start, mid, leaf, slots)
 
 
 def _host_copy(t):
@@ -343,8 +375,9 @@ class LBMRollout(torch.autograd.Function):
             snaps[0] = tuple(_host_copy(t) for t in snaps[0])
         n = 0
         while n < N:
-            # plain steps up to the next snapshot step (the one that reaches a multiple of K)
-            end = min(N, (n // K + 1) * K - 1) if keep else N
+            # plain steps up to the next snapshot step (the one that reaches a multiple of K;
+            # binomial checkpointing keeps only level 0 here)
+            end = min(N, (n // K + 1) * K - 1) if keep and not cfg.revolve else N
             _plain_steps(sv, cfg, n, end)
             n = end
             if n < N:
@@ -364,7 +397,20 @@ class LBMRollout(torch.autograd.Function):
         sv, cfg, snaps = ctx.sv, ctx.cfg, ctx.snaps
         N = cfg.nsteps
         adj = _Adjoint(sv, cfg, grad_out.detach())
-        if cfg.levels:
+        if cfg.revolve:
+            K = cfg.checkpoint_every
+            recs = [sv.new_record() for _ in range(K + 1)]
+            for act in revolve_actions(0, N + 1, K, cfg.revolve):
+                if act[0] == "take":
+                    a, m = act[1], act[2]
+                    _restore(sv, snaps[a])
+                    _plain_steps(sv, cfg, a, m - 1, ustar=False)
+                    snaps[m] = _step_to_snapshot(sv, cfg, m - 1, ustar=False)
+                elif act[0] == "free":
+                    del snaps[act[1]]
+                else:
+                    _reverse_segment(sv, cfg, adj, act[1], act[2], snaps[act[1]], recs)
+        elif cfg.levels:
             K0 = cfg.levels[0]
             inner = list(cfg.levels[1:])
             nrec = (inner[-1] if inner else K0) + 1

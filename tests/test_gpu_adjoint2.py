@@ -6,9 +6,9 @@ lbm_adjoint_step(m - 1), bit for bit: the adjoint populations, the FP32 gradient
 and the FP64 gradients of mu, lam and the body force, with the probe sources of both levels.
 The cases cover every storage, a closed-form and an invariant-based law, per-node mu, lam
 and body force with a ramp, distinct probe cells (some at the strip edges), grids that are
-multiples of neither the 64-node strip nor the 4-row block and grids narrower than one
+multiples of neither the 64-node strip nor the block of rows and grids narrower than one
 strip, and both phases of the 16-level fold (on the first and on the second level of a
-pair).
+pair).  Binomial checkpointing of the rollout is checked against the every-K schedule.
 """
 import numpy as np
 import pytest
@@ -132,3 +132,35 @@ def test_rollout_in_pairs_matches_oracle_adjoint(storage, bar):
         err = float(np.sqrt(((g - go[k]) ** 2).sum() / (go[k] ** 2).sum()))
         print(f"\n[rollout pairs {storage}] {k}: {err:.2e}")
         assert err <= bar, k
+
+
+@pytest.mark.parametrize("kind", ["periodic", "walls"])
+@pytest.mark.parametrize("slots", [1, 2, 3])
+def test_binomial_checkpointing_gives_the_every_k_gradients(kind, slots):
+    """Binomial checkpointing (RolloutConfig.revolve) replays the same levels with the same
+    records as the every-K schedule, so its gradients are bit for bit the same; u^N too."""
+    import dataclasses
+    from paper_2605_26677_amd.rollout import RolloutConfig, rollout
+    nx, ny, N = 48, 30, 41
+    mu0 = li.lognormal_field(nx, ny, 621, 0.1, 0.3, 4.0)
+    lam0 = li.lognormal_field(nx, ny, 622, 0.2, 0.3, 4.0)
+    b0 = li.uniform_body(nx, ny, (1e-4, -3e-4))
+    w0 = np.stack([li.gaussian_random_field(nx, ny, 623, 1e-3), li.gaussian_random_field(nx, ny, 624, 1e-3)])
+    ys, xs = li.random_probes(nx, ny, 5, 625)
+    kw = dict(nx=nx, ny=ny, c=2.5, omega=1.95, nsteps=N, probes=torch.tensor(ys * nx + xs), storage="f32",
+              ramp=lambda m: min(1.0, m / 8), checkpoint_every=4)
+    if kind == "walls":
+        data = [(0.0, 0.0), (2e-4, 0.0), (0.0, 0.0), (0.0, -3e-4)]
+        kw.update(bc=("velocity", "traction", "traction", "traction"), edges=lambda m: data)
+    cfg_k = RolloutConfig(**kw)
+    cfg_r = dataclasses.replace(cfg_k, revolve=slots)
+    res = []
+    for cfg in (cfg_k, cfg_r):
+        leaves = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True)
+                  for a in (mu0, lam0, b0, w0)]
+        out = rollout(*leaves, cfg)
+        (out.double() ** 2).sum().backward()
+        res.append((out.detach(), [t.grad for t in leaves]))
+    assert torch.equal(res[0][0], res[1][0])
+    for ga, gb in zip(res[0][1], res[1][1]):
+        assert torch.equal(ga, gb)

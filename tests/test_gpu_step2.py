@@ -7,7 +7,7 @@ FP64 planes), the records and the fault word, on periodic grids and on grids wit
 velocity and traction walls (corners, walls along one axis only, wall data that change
 every half step, per-node wall data).  The cases cover every storage and law; uniform and
 per-node mu, lam and body force, with different ramp factors at the two levels; grids that
-are multiples of neither the 62-column strip nor the 6-row block of the kernel, grids
+are multiples of neither the 64-node strip nor the block of rows of the kernel, grids
 narrower than one strip (the lanes then wrap the periodic axis several times) down to the
 3 x 3 minimum; start levels of both parities, so that the fold falls on the first and on
 the second level of a pair; and the 8192 x 8192 benchmark grid in the launch
