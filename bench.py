@@ -131,6 +131,47 @@ def time_forward(n, storage, steps, warmup, v0, law="lognh", pairs=False):
     return ms, faults, steps
 
 
+def time_block(n=1024, steps=2000, start=512):
+    """The walled block workload: n x n, velocity wall (v = 0) on the left, traction-free
+    elsewhere, log-NH mu = 0.1, lam = 0.3, b = (0, -1e-5) ramped over 500 steps, c = 10,
+    omega = 2 - 1.6/n, FP32.  Timed from level ``start`` (past the ramp, where the block
+    arguments repeat): eager lbm_step and lbm_step2 calls, and Solver.advance with single
+    steps and in pairs, both replaying captured HIP graphs."""
+    import torch
+    import lbm_inputs as li
+    from paper_2605_26677_amd.solver import Solver
+    v0 = np.stack([li.gaussian_random_field(n, n, 403, 1e-3), li.gaussian_random_field(n, n, 404, 1e-3)])
+    ramp = lambda k: min(1.0, k / 500)
+    edges = lambda k: [(0.0, 0.0)] * 4
+    out = {"grid": [n, n], "steps": steps, "start": start}
+    for mode in ("eager", "eager_pairs", "graph_single", "graph_pairs"):
+        sv = Solver(n, n, c=10.0, omega=2.0 - 1.6 / n, material="lognh", storage="f32", mu=0.1, lam=0.3,
+                    body=(0.0, -1e-5), bc=("velocity", "traction", "traction", "traction"))
+        sv.init(v0, r0=0.0)
+        pairs = mode.endswith("pairs")
+        sv.advance(0, start, ramp=ramp, edges=edges, block=64, fused=pairs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        if mode == "eager":
+            for k in range(start, start + steps):
+                sv.step(k, ramp(k), ramp(k + 1), edges=edges(k))
+        elif mode == "eager_pairs":
+            for k in range(start, start + steps, 2):
+                sv.step2(k, ramp(k + 1), ramp(k + 2), r_n=ramp(k), edges=edges(k), edges_next=edges(k + 1))
+        else:
+            sv.advance(start, steps, ramp=ramp, edges=edges, block=64, fused=pairs)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[f"{mode}_ms_per_step"] = ms
+        out[f"{mode}_mlups"] = n * n / (ms * 1e-3) / 1e6
+        out[f"{mode}_faults"] = sv.faults()
+        del sv
+        torch.cuda.empty_cache()
+    return out
+
+
 def time_launch_bound(n=256, steps=4000, block=100):
     """The same step on a small grid where the host launch cost dominates: per-step eager
     calls against blocks of steps replayed from a captured HIP graph (Solver.advance)."""
@@ -382,6 +423,9 @@ def main():
             log(f"bench: timing {key} forward, {args.variant_steps} steps")
             ms, faults, steps = time_forward(n, "f32", args.variant_steps, args.warmup, v0, law="svk", pairs=pairs)
             record(key, "f32", ms, faults, steps, pairs)
+    log("bench: walled 1024^2 block, single steps vs advance in pairs")
+    res["block_1024_walls"] = time_block()
+    log(f"bench: block: {res['block_1024_walls']}")
     log("bench: launch-bound grid, eager vs captured graph")
     res["launch_bound_256"] = time_launch_bound()
     log(f"bench: launch-bound: {res['launch_bound_256']}")

@@ -145,18 +145,23 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
     }
 }
 
-// Traction edge, stage 1 (one thread per wall link): F^b is rebuilt from the record of
+// Traction edges, stage 1 (one thread per wall link): F^b is rebuilt from the record of
 // U^m exactly as in the forward step, then dL/dF^b = lambda^{m+1}_d(X0)_F / 2 is carried
 // through the Newton solve by the implicit function theorem: with y = J^{-T} (dL/da),
 // the tangential column receives -N_A y_i C_iAjB and mu, lam receive -N_A y_i dP_iA/dp.
+// One launch covers every traction edge, one wavefront per workgroup (as the forward
+// solve).  Each link stages (tbar_1, tbar_2, dL/dmu, dL/dlam) in its own slot of the
+// staging buffer; the mu and lam terms reach the gradients in the scatter stage, which
+// goes one edge at a time, so the corner node two edges share takes them in edge order.
 template <int ST, int LAW, bool FIELDS>
-__global__ void __launch_bounds__(kBlock) adj_traction_kernel(AdjArgs a) {
+__global__ void __launch_bounds__(kTile) adj_traction_kernel(AdjArgs a) {
     using R = typename Storage<ST>::real;
     const Common& cm = a.cm;
-    const int e = a.edge;
+    int e = 0;
+    while (e < 3 && int(blockIdx.x) >= a.eblk[e + 1]) ++e;
     const EdgeGeom G = edge_geom(e);
     const int L = (G.A == 0) ? cm.ny : cm.nx;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = (int(blockIdx.x) - a.eblk[e]) * kTile + int(threadIdx.x);
     if (s >= L) return;
     const bool per_t = (G.A == 0) ? cm.periodic_y : cm.periodic_x;
     const int A = G.A, Bx = 1 - G.A;
@@ -211,17 +216,20 @@ __global__ void __launch_bounds__(kBlock) adj_traction_kernel(AdjArgs a) {
     R tbar[2];
     for (int jj = 0; jj < 2; ++jj)
         tbar[jj] = Fbar[2 * jj + Bx] - NA * (y0 * C[4 * A + 2 * jj + Bx] + y1 * C[8 + 4 * A + 2 * jj + Bx]);
+    R gm = R(0), gl = R(0);
     if (a.g_mu || a.g_lam) {
         R Pm[4], Pl[4];
         piola_partials<R, LAW, true>(f, law_consts<R>(cm), Pm, Pl);
-        if (a.g_mu) a.g_mu[id0] += double(-NA * (y0 * Pm[A] + y1 * Pm[2 + A]));
-        if (a.g_lam) a.g_lam[id0] += double(-NA * (y0 * Pl[A] + y1 * Pl[2 + A]));
+        gm = -NA * (y0 * Pm[A] + y1 * Pm[2 + A]);
+        gl = -NA * (y0 * Pl[A] + y1 * Pl[2 + A]);
     }
     int off[4], len[4];
     edge_offsets(cm.nx, cm.ny, off, len);
-    R* aux = (R*)a.aux + 2 * (int64_t)(off[e] + s);
+    R* aux = (R*)a.aux + 4 * (int64_t)(off[e] + s);
     aux[0] = tbar[0];
     aux[1] = tbar[1];
+    aux[2] = gm;
+    aux[3] = gl;
 }
 
 // Traction edge, stage 2 (one thread per node of the wall row and first interior row):
@@ -242,17 +250,22 @@ __global__ void __launch_bounds__(kBlock) adj_traction_scatter_kernel(AdjArgs a)
     const int64_t n = int64_t(cm.nx) * cm.ny;
     int off[4], len[4];
     edge_offsets(cm.nx, cm.ny, off, len);
-    const R* aux = (const R*)a.aux + 2 * (int64_t)off[e];
+    const R* aux = (const R*)a.aux + 4 * (int64_t)off[e];
     const R wr = (r == 0) ? R(1.5) : R(-0.5);
     const R hdt = R(0.5 * cm.dt);
     const R inv2h = R(1.0 / (2.0 * cm.dx));
     R E[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     for (int k = 0; k < 2; ++k) {
-        E[2 + 2 * k + Bx] = wr * aux[2 * s + k];
-        E[k] = hdt * wr * fd_along_T<R>([&](int s2) { return aux[2 * s2 + k]; }, s, L, per_t, inv2h);
+        E[2 + 2 * k + Bx] = wr * aux[4 * s + k];
+        E[k] = hdt * wr * fd_along_T<R>([&](int s2) { return aux[4 * s2 + k]; }, s, L, per_t, inv2h);
     }
     const XY nd = edge_node(G, cm.nx, cm.ny, r, s);
     const int id = nd.y * cm.nx + nd.x;
+    if (r == 0) {
+        // the mu and lam terms of this link's Newton solve (stage 1)
+        if (a.g_mu) a.g_mu[id] += double(aux[4 * s + 2]);
+        if (a.g_lam) a.g_lam[id] += double(aux[4 * s + 3]);
+    }
     R* dst = (R*)a.dst + tile_base(cm.ntile, 24, nd.x, nd.y);
     for (int q = 0; q < 4; ++q)
         for (int k = 0; k < 6; ++k) dst[(6 * q + k) * kTile] += E[k];
@@ -666,16 +679,16 @@ static hipError_t adjoint_st_law(const AdjArgs& a0, hipStream_t s) {
     AdjArgs a = a0;
     const bool walls = !(a.cm.periodic_x && a.cm.periodic_y);
     const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
-    // stage 1 of every traction edge reads lambda^{m+1} before the bulk kernel writes lambda^m
+    // stage 1 of every traction edge (one launch) reads lambda^{m+1} before the bulk kernel
+    // writes lambda^m; each edge stages its values in its own slice of aux
+    a.eblk[0] = 0;
     for (int e = 0; e < 4; ++e) {
-        if (a.cm.bc[e] != LBM_TRACTION) continue;
-        a.edge = e;
         const int L = (e == LBM_XMIN || e == LBM_XMAX) ? a.cm.ny : a.cm.nx;
-        int off[4], len[4];
-        edge_offsets(a.cm.nx, a.cm.ny, off, len);
-        // each edge stages its tbar values in its own slice of aux
-        if (fields) hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, true>), dim3(nblk(L)), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, false>), dim3(nblk(L)), dim3(kBlock), 0, s, a);
+        a.eblk[e + 1] = a.eblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (L + kTile - 1) / kTile : 0);
+    }
+    if (a.eblk[4] > 0) {
+        if (fields) hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, true>), dim3(a.eblk[4]), dim3(kTile), 0, s, a);
+        else hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, false>), dim3(a.eblk[4]), dim3(kTile), 0, s, a);
     }
     const dim3 grid(unsigned((int64_t(a.cm.ntile) * a.cm.ny + kTilesPerBlock - 1) / kTilesPerBlock));
     const dim3 block(kTile * kTilesPerBlock);

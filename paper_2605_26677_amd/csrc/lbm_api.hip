@@ -199,8 +199,7 @@ lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, do
     const hipStream_t hs = (hipStream_t)stream;
     const Common cm = make_common(p, s);
     const EdgeData ed = make_edges(at_half);
-    for (int e = 0; e < 4; ++e) {
-        if (p->bc[e] != LBM_TRACTION) continue;
+    {
         TractionArgs t{};
         t.cm = cm;
         if (cm.body_prev) t.cm.body = cm.body_prev;
@@ -208,7 +207,6 @@ lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, do
         t.aux = s->aux;
         t.r_n = r_n;
         t.ed = ed;
-        t.edge = e;
         if (launch_traction(t, hs) != hipSuccess) return LBM_ERR_LAUNCH;
     }
     StepArgs a{};
@@ -252,29 +250,25 @@ lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_n, d
     a.r_np1 = r_np1;
     a.r_np2 = r_np2;
     // F^b of level n from f*^n, as lbm_step takes it
-    for (int e = 0; e < 4; ++e) {
-        if (p->bc[e] != LBM_TRACTION) continue;
+    {
         TractionArgs t{};
         t.cm = a.cm;
         t.pop = a.src;
         t.aux = s->aux;
         t.r_n = r_n;
         t.ed = a.ed;
-        t.edge = e;
         if (launch_traction(t, hs) != hipSuccess) return LBM_ERR_LAUNCH;
     }
     if (launch_step2(a, hs) != hipSuccess) return LBM_ERR_LAUNCH;
     if (walls) {
         // F^b of level n+1 from the wall lines the bulk kernel wrote, then the wall nodes
-        for (int e = 0; e < 4; ++e) {
-            if (p->bc[e] != LBM_TRACTION) continue;
+        {
             TractionArgs t{};
             t.cm = a.cm;
             t.pop = nullptr;
             t.aux = s->aux;
             t.r_n = r_np1;
             t.ed = a.ed2;
-            t.edge = e;
             t.lines = 1;
             if (launch_traction(t, hs) != hipSuccess) return LBM_ERR_LAUNCH;
         }

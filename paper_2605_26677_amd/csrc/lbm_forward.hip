@@ -16,56 +16,98 @@
 
 namespace lbm {
 
-// F^b of every link of one traction edge at step n -> n+1 (Sec. 3.6).  Reading of the
+// F^b of every link of the traction edges at step n -> n+1 (Sec. 3.6).  Reading of the
 // extrapolation the paper leaves open: with X0 the wall node and X1 the first interior
 // node, G = F_{.B} + (dt/2) d_B v (the kinematic identity moves F by half a step) and the
 // tangential column is 3/2 G(X0) - 1/2 G(X1) (linear extrapolation to the half-way wall);
 // the Newton guess for the normal column is 3/2 F_{.A}(X0) - 1/2 F_{.A}(X1).
+//
+// One launch covers every traction edge (each edge reads level n only and writes its own
+// slice of the staging buffer), one wavefront per workgroup: the solve is latency-bound,
+// so the links are spread over as many compute units as there are wavefronts.  Lane l of
+// a wavefront recovers U at edge position s0 - 2 + l (wrapped on a periodic edge) on the
+// wall row and the first interior row; lanes 2 .. 61 solve the links s0 .. s0 + 59 and
+// take the velocities of their tangential stencil (central, or one-sided at the ends of
+// an open edge: never more than two positions away) from the neighbouring lanes.  Each
+// node is thus read once per wavefront instead of once per stencil use: on the edges
+// normal to x every lane reads its own tile row, 24 separate cache lines per node.
 template <int ST, int LAW, bool FIELDS, bool LINES>
-__global__ void __launch_bounds__(kBlock) traction_kernel(TractionArgs a) {
+__global__ void __launch_bounds__(kTracWin) traction_kernel(TractionArgs a) {
     using Tr = Storage<ST>;
     using R = typename Tr::real;
     using T = typename Tr::pop_t;
     constexpr bool SH = Tr::shifted;
     const Common& cm = a.cm;
-    const int e = a.edge;
+    int e = 0;
+    while (e < 3 && int(blockIdx.x) >= a.eblk[e + 1]) ++e;
     const EdgeGeom G = edge_geom(e);
     const int L = (G.A == 0) ? cm.ny : cm.nx;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= L) return;
     const bool per_t = (G.A == 0) ? cm.periodic_y : cm.periodic_x;
     const int Bx = 1 - G.A;
+    const int lane = int(threadIdx.x);
+    const int s = (int(blockIdx.x) - a.eblk[e]) * kTracOut - 2 + lane;   // this lane's position
     const T* pop = (const T*)a.pop;
     const int64_t n = int64_t(cm.nx) * cm.ny;
     const R hdt = R(0.5 * cm.dt);
     const R inv2h = R(1.0 / (2.0 * cm.dx));
-    const Stencil sten = tangential_stencil(s, L, per_t);
-    R Ghat[2][2], Fa[2][2];
+
+    // U of level n at this lane's window position, wall row (r = 0) and first interior row
+    int pw = s;
+    bool have = true;
+    if (per_t) pw = wrap_index(s, L);
+    else have = s >= 0 && s < L;
+    R Uw[2][6];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        R Us[3][6];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const XY nd = edge_node(G, cm.nx, cm.ny, r, sten.p[j]);
+        if (have) {
+            const XY nd = edge_node(G, cm.nx, cm.ny, r, pw);
             double b0, b1;
             body_at<FIELDS>(cm, nd.y * cm.nx + nd.x, n, a.r_n, b0, b1);
             if constexpr (LINES) {
                 // level n+1 of the two-level step, from the wall lines of the staging buffer
-                const T* lv = (const T*)wall_lines(a.aux, cm.nx, cm.ny).lines +
-                              line_slot(cm.nx, cm.ny, e, r, sten.p[j]) * 24;
-                recover_vals<T, R>(lv, 1, hdt * R(b0), hdt * R(b1), Us[j]);
+                const T* lv = (const T*)wall_lines(a.aux, cm.nx, cm.ny).lines + line_slot(cm.nx, cm.ny, e, r, pw) * 24;
+                recover_vals<T, R>(lv, 1, hdt * R(b0), hdt * R(b1), Uw[r]);
             } else {
-                recover_node<T, R>(pop, cm.ntile, nd.x, nd.y, hdt * R(b0), hdt * R(b1), Us[j]);
+                recover_node<T, R>(pop, cm.ntile, nd.x, nd.y, hdt * R(b0), hdt * R(b1), Uw[r]);
             }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Uw[r][k] = R(0);
         }
+    }
+
+    // the stencil of the link at s, as lane offsets (a wrapped position is also held by the
+    // lane at its unwrapped offset, so an offset beyond +-2 is taken modulo L)
+    const bool solve = lane >= 2 && lane < kTracWin - 2 && s < L;
+    Stencil sten = tangential_stencil(solve ? s : 0, L, per_t);
+    int dl[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        int d = sten.p[j] - (solve ? s : 0);
+        if (d > 2) d -= L;
+        if (d < -2) d += L;
+        dl[j] = solve ? d : 0;
+    }
+    R Vs[2][3][2];                     // velocity of row r at stencil entry j
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) Vs[r][j][k] = __shfl(Uw[r][k], lane + dl[j], kTracWin);
+    if (!solve) return;
+
+    R Ghat[2][2], Fa[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             R dv = R(0);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) dv += R(sten.w[j]) * Us[j][k];
+            for (int j = 0; j < 3; ++j) dv += R(sten.w[j]) * Vs[r][j][k];
             dv *= inv2h;
-            Ghat[r][k] = Us[sten.self][2 + 2 * k + Bx] + hdt * dv;
-            Fa[r][k] = Us[sten.self][2 + 2 * k + G.A];
+            Ghat[r][k] = Uw[r][2 + 2 * k + Bx] + hdt * dv;
+            Fa[r][k] = Uw[r][2 + 2 * k + G.A];
         }
     }
     R tang[2], acol[2], Tv[2];
@@ -1075,13 +1117,13 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
 template <int ST, int LAW>
 static hipError_t traction_st_law(const TractionArgs& a, hipStream_t s) {
     const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
-    const int L = (a.edge == LBM_XMIN || a.edge == LBM_XMAX) ? a.cm.ny : a.cm.nx;
+    const dim3 grid(unsigned(a.eblk[4])), block(kTracWin);
     if (a.lines) {
-        if (fields) hipLaunchKernelGGL((traction_kernel<ST, LAW, true, true>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((traction_kernel<ST, LAW, false, true>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
+        if (fields) hipLaunchKernelGGL((traction_kernel<ST, LAW, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((traction_kernel<ST, LAW, false, true>), grid, block, 0, s, a);
     } else {
-        if (fields) hipLaunchKernelGGL((traction_kernel<ST, LAW, true, false>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((traction_kernel<ST, LAW, false, false>), dim3(nblocks(L)), dim3(kBlock), 0, s, a);
+        if (fields) hipLaunchKernelGGL((traction_kernel<ST, LAW, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((traction_kernel<ST, LAW, false, false>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }
@@ -1098,7 +1140,14 @@ static hipError_t traction_st(const TractionArgs& a, hipStream_t s) {
     }
 }
 
-hipError_t launch_traction(const TractionArgs& a, hipStream_t s) {
+hipError_t launch_traction(TractionArgs a, hipStream_t s) {
+    // workgroup ranges of the traction edges; nothing to launch without one
+    a.eblk[0] = 0;
+    for (int e = 0; e < 4; ++e) {
+        const int L = (e == LBM_XMIN || e == LBM_XMAX) ? a.cm.ny : a.cm.nx;
+        a.eblk[e + 1] = a.eblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (L + kTracOut - 1) / kTracOut : 0);
+    }
+    if (a.eblk[4] == 0) return hipSuccess;
     switch (a.cm.storage) {
         case LBM_F32_SHIFTED: return traction_st<LBM_F32_SHIFTED>(a, s);
         case LBM_F16_SHIFTED: return traction_st<LBM_F16_SHIFTED>(a, s);

@@ -12,6 +12,8 @@ constexpr int kBlock = 256;          // threads per workgroup of the node-indexe
 constexpr int kTilesPerBlock = 2;    // 64-node tiles (one wavefront each) per workgroup of the
                                      // step and adjoint kernels
 constexpr int kDiagBlocks = 1024;    // partial sums of the diagnostics reduction
+constexpr int kTracWin = 64;         // edge positions one wavefront of the traction solve loads
+constexpr int kTracOut = kTracWin - 4;   // wall links it solves (two positions of halo a side)
 
 // Offsets of each edge's links in the traction staging buffer (links, not bytes).
 __host__ __device__ inline void edge_offsets(int nx, int ny, int off[4], int len[4]) {
@@ -153,7 +155,7 @@ struct TractionArgs {
     void* aux;
     double r_n;
     EdgeData ed;
-    int edge;
+    int eblk[5];                     // workgroups of edge e: [eblk[e], eblk[e+1]) (0 for non-traction)
     int lines;                       // read level n from the wall lines of aux instead of pop
 };
 
@@ -191,7 +193,8 @@ struct AdjArgs {
     void* aux;
     double r_m;
     EdgeData ed;
-    int edge;
+    int edge;                        // the edge of the scatter stage
+    int eblk[5];                     // stage 1: workgroups of edge e, [eblk[e], eblk[e+1])
     const int32_t* probe;
     const double* ubar;
     int nprobe;
@@ -236,7 +239,7 @@ struct AdjInitArgs {
 
 hipError_t launch_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_step2(const Step2Args& a, hipStream_t s);
-hipError_t launch_traction(const TractionArgs& a, hipStream_t s);
+hipError_t launch_traction(TractionArgs a, hipStream_t s);   // every traction edge, one launch
 hipError_t launch_moments(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_record(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_displacement(const RecoverArgs& a, hipStream_t s);

@@ -50,6 +50,9 @@ class RolloutConfig:
     host_top: bool = False                             # outermost snapshots in pinned host memory
     revolve: int = 0                                   # binomial checkpointing with this many
                                                        # snapshot slots (0: every K or levels)
+    pairs: Optional[bool] = None                       # forward levels in pairs (lbm_step2):
+                                                       # None where faster (Solver.pairs_pay),
+                                                       # True wherever they apply, False never
 
 
 def _sizes(nx, ny, storage):
@@ -260,8 +263,9 @@ class _Adjoint:
                                         _stream()), "lbm_adjoint_step")
 
     def pair_ok(self, sv, cfg, m, lowest):
-        """Levels m and m - 1 can go through lbm_adjoint_step2."""
-        return self.pmask is not None and lowest <= m - 1 and 1 <= m < cfg.nsteps
+        """Levels m and m - 1 can go through lbm_adjoint_step2 (periodic grids, unless the
+        configuration turns pairs off)."""
+        return cfg.pairs is not False and self.pmask is not None and lowest <= m - 1 and 1 <= m < cfg.nsteps
 
     def step2(self, sv, cfg, m, record_m, record_mm1):
         L.check(sv.lib.lbm_adjoint_step2(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), int(m),
@@ -288,17 +292,23 @@ def _step_to_snapshot(sv, cfg, n, ustar=True):
     return (sv.pop[sv.s.cur].clone(), rec)
 
 
+def _pairs(sv, cfg):
+    """Whether the forward levels of this rollout go two per lbm_step2 call."""
+    return sv.pairs_pay if cfg.pairs is None else (bool(cfg.pairs) and sv.pairs_ok)
+
+
 def _pair(sv, cfg, n, record1=None, record2=None, ustar=True):
     sv.step2(n, cfg.ramp(n + 1), cfg.ramp(n + 2), record1=record1, record2=record2, ustar=ustar,
              r_n=cfg.ramp(n), edges=_edges(cfg, n), edges_next=_edges(cfg, n + 1))
 
 
 def _plain_steps(sv, cfg, n0, n1, ustar=True):
-    """Steps n0 .. n1 - 1 without records, in pairs through lbm_step2 (bit for bit the same
-    result as single steps)."""
+    """Steps n0 .. n1 - 1 without records, in pairs through lbm_step2 where the rollout
+    takes pairs (_pairs; bit for bit the same result as single steps)."""
     n = n0
+    pairs = _pairs(sv, cfg)
     while n < n1:
-        if sv.pairs_ok and n + 1 < n1:
+        if pairs and n + 1 < n1:
             _pair(sv, cfg, n, ustar=ustar)
             n += 2
         else:
@@ -313,8 +323,9 @@ def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
     _restore(sv, snap)
     recs[0].copy_(snap[1], non_blocking=True)
     n = start
+    pairs = _pairs(sv, cfg)
     while n < end - 1:
-        if sv.pairs_ok and n + 1 < end - 1:
+        if pairs and n + 1 < end - 1:
             _pair(sv, cfg, n, record1=recs[n + 1 - start], record2=recs[n + 2 - start], ustar=False)
             n += 2
         else:

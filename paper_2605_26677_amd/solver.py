@@ -105,6 +105,15 @@ class Solver:
     dx, law ("lognh", "nh", "svk", "mr", "yeoh", "gent") with optional law_k constants,
     storage ("f32", "f16", "f64"), edge kinds, uniform or per-node mu, lam and body force."""
 
+    # Defaults of advance() and of the checkpointed rollout, from timings on one MI355X
+    # (FP32, log-NH): a captured graph beats eager launches only where the host launch cost
+    # dominates (2.0x single steps, 1.07x pairs at 256^2; 0.92x pairs at 384^2, and a few
+    # microseconds lost per kernel node above); on walled grids the two-level step adds
+    # three latency-bound launches per pair and loses below about 640^2 (256^2: 22.5 against
+    # 15.1 us per level; 768^2: 34.5 against 36.7).
+    GRAPH_MAX_NODES = 320 * 320
+    PAIR_MIN_WALLED_NODES = 640 * 640
+
     def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
                  bc=("periodic",) * 4, mu=0.1, lam=0.2, body=None, newton_max_iter=0,
                  newton_tol=0.0, force_unstable=False, law_k=None, device="cuda"):
@@ -240,6 +249,12 @@ class Solver:
         """lbm_step2 equals two lbm_step calls unless per-level body fields are in use."""
         return not self.s.body_prev
 
+    @property
+    def pairs_pay(self):
+        """lbm_step2 applies (pairs_ok) and is faster than two lbm_step calls: on periodic
+        grids always, on walled grids from PAIR_MIN_WALLED_NODES nodes."""
+        return self.pairs_ok and (self.periodic or self.nx * self.ny >= self.PAIR_MIN_WALLED_NODES)
+
     def _run(self, st):
         if st.get("pair"):
             self.step2(st["n"], st["r_np1"], st["r_np2"], r_n=st["r_n"], edges=st.get("edges"),
@@ -253,15 +268,23 @@ class Solver:
         ``pair=True``, of ``step2`` (n, r_n, r_np1, r_np2, edges, edges_next)."""
         return StepGraph(self, steps)
 
-    def advance(self, n0, count, ramp=None, edges=None, block=64, fused=None):
+    def advance(self, n0, count, ramp=None, edges=None, block=64, fused=None, graph=None):
         """Steps n0 .. n0 + count - 1 with ramp factors ``ramp(n)`` (default 1) and wall data
-        ``edges(n)`` (default zero): whole blocks of ``block`` steps whose arguments equal
-        those of the first captured block replay one captured graph, the rest run eagerly.
-        For launch-bound grids this removes the per-step host cost.  With ``fused`` None or
-        True the steps go in pairs through lbm_step2, with the same result bit for bit."""
+        ``edges(n)`` (default zero).  With ``graph`` True, whole blocks of ``block`` steps
+        whose arguments equal those of the first captured block replay one captured graph
+        and the rest run eagerly; this removes the per-step host cost where it dominates.
+        ``graph`` None captures only grids of at most GRAPH_MAX_NODES nodes: on larger ones
+        eager launches already follow each other without a gap, and a graph replay adds a
+        few microseconds between its kernel nodes.  With ``fused`` True the steps go in
+        pairs through lbm_step2 (where pairs_ok), with the same result bit for bit; None
+        takes pairs where they are faster (pairs_pay)."""
         ramp = ramp or (lambda n: 1.0)
         edges = edges or (lambda n: None)
-        fused = self.pairs_ok if fused is None else (bool(fused) and self.pairs_ok)
+        fused = self.pairs_pay if fused is None else (bool(fused) and self.pairs_ok)
+        if graph is None:
+            graph_on = self.nx * self.ny <= self.GRAPH_MAX_NODES
+        else:
+            graph_on = bool(graph)
 
         def block_calls(n, m):
             # the calls for steps n .. m - 1
@@ -284,7 +307,7 @@ class Solver:
         while n < end:
             m = min(end, n + block)
             blk = block_calls(n, m)
-            if m - n == block and graph is None and self._graph_ok(blk):
+            if graph_on and m - n == block and graph is None and self._graph_ok(blk):
                 proto = blk
                 graph = self.capture(blk)
             if (graph is not None and m - n == block and self.s.cur == graph.start_cur

@@ -164,3 +164,35 @@ def test_binomial_checkpointing_gives_the_every_k_gradients(kind, slots):
     assert torch.equal(res[0][0], res[1][0])
     for ga, gb in zip(res[0][1], res[1][1]):
         assert torch.equal(ga, gb)
+
+
+@pytest.mark.parametrize("kind", ["periodic", "walls"])
+def test_rollout_pairs_on_and_off_give_the_same_gradients(kind):
+    """The rollout with its levels in pairs (forward sweep, replays with records and, on
+    periodic grids, the adjoint) and with single levels only: u^N and every gradient bit
+    for bit the same.  Small walled grids step one level at a time by default, so the
+    pairs are forced on here."""
+    import dataclasses
+    from paper_2605_26677_amd.rollout import RolloutConfig, rollout
+    nx, ny, N = 66, 37, 29
+    mu0 = li.lognormal_field(nx, ny, 631, 0.1, 0.3, 4.0)
+    lam0 = li.lognormal_field(nx, ny, 632, 0.2, 0.3, 4.0)
+    b0 = li.uniform_body(nx, ny, (1e-4, -3e-4))
+    w0 = np.stack([li.gaussian_random_field(nx, ny, 633, 1e-3), li.gaussian_random_field(nx, ny, 634, 1e-3)])
+    ys, xs = li.random_probes(nx, ny, 5, 635)
+    kw = dict(nx=nx, ny=ny, c=2.5, omega=1.95, nsteps=N, probes=torch.tensor(ys * nx + xs), storage="f32",
+              ramp=lambda m: min(1.0, m / 8), checkpoint_every=7)
+    if kind == "walls":
+        data = [(0.0, 0.0), (2e-4, 0.0), (0.0, 0.0), (0.0, -3e-4)]
+        kw.update(bc=("velocity", "traction", "traction", "traction"), edges=lambda m: data)
+    res = []
+    for pairs in (True, False):
+        cfg = dataclasses.replace(RolloutConfig(**kw), pairs=pairs)
+        leaves = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True)
+                  for a in (mu0, lam0, b0, w0)]
+        out = rollout(*leaves, cfg)
+        (out.double() ** 2).sum().backward()
+        res.append((out.detach(), [t.grad for t in leaves]))
+    assert torch.equal(res[0][0], res[1][0])
+    for ga, gb in zip(res[0][1], res[1][1]):
+        assert torch.equal(ga, gb)

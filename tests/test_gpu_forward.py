@@ -243,6 +243,6 @@ def test_step_graph_replays_match_eager(kinds, storage):
         sv.init(case.v0, r0=1.0)
     for m in range(150):
         eager2.step(m, edges=data)
-    adv.advance(0, 150, edges=lambda n: data, block=32)
+    adv.advance(0, 150, edges=lambda n: data, block=32, graph=True)
     assert torch.equal(eager2.moments(), adv.moments())
     assert eager2.faults() == 0 and adv.faults() == 0

@@ -234,7 +234,7 @@ def test_advance_in_pairs_with_walls_equals_single_steps():
     N = 83
     for m in range(N):
         eager.step(m, case.ramp(m), case.ramp(m + 1), edges=data(m))
-    adv.advance(0, N, ramp=case.ramp, edges=data, block=32)
+    adv.advance(0, N, ramp=case.ramp, edges=data, block=32, fused=True, graph=True)
     assert torch.equal(eager.populations(), adv.populations())
     assert torch.equal(eager.displacement(case.ramp(N)), adv.displacement(case.ramp(N)))
     assert eager.faults() == adv.faults() == 0
@@ -251,7 +251,7 @@ def test_advance_in_pairs_equals_single_steps():
     N = 151
     for m in range(N):
         eager.step(m, case.ramp(m), case.ramp(m + 1))
-    adv.advance(0, N, ramp=case.ramp, block=32)     # a pair flips the buffers once per two levels
+    adv.advance(0, N, ramp=case.ramp, block=32, fused=True, graph=True)   # a pair flips the buffers once per two levels
     assert torch.equal(eager.populations(), adv.populations())
     assert torch.equal(eager.displacement(case.ramp(N)), adv.displacement(case.ramp(N)))
 
