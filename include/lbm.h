@@ -259,7 +259,8 @@ typedef struct {
     int32_t cur;               /* buffer holding lambda^{m+1} = dL/df^{m+1} before a step */
     double *g_mu, *g_lam;      /* device, 1 plane each: accumulated dL/dmu, dL/dlam, or NULL */
     double *g_body;            /* device, 2 planes: accumulated dL/db, or NULL */
-    const int32_t *probe;      /* device: nprobe node indices (b*nx + a), distinct */
+    const int32_t *probe;      /* device: nprobe node indices (b*nx + a); a cell may repeat
+                                  (its sources add up) */
     const double *ubar;        /* device: 2*nprobe values (component-major), dL/du^N at the probes */
     int32_t nprobe;
     int64_t nsteps;            /* N, the level at which u^N enters the loss */
@@ -271,6 +272,11 @@ typedef struct {
                                   summed here in FP32 (4 tiled planes) and moved into the FP64
                                   gradients at every level m with m % 16 == 0, which includes
                                   the last step m = 0; it is zero again after that step */
+    /* device, optional: the probe table of these probes (lbm_adjoint_probe_table).  With
+     * both set, lbm_adjoint_step adds the probe sources inside its bulk kernel; with either
+     * NULL one thread walks the probes after it (its cost grows with nprobe). */
+    const uint64_t *probe_mask;
+    const double *probe_field;
 } lbm_adj_state;
 
 /* Bytes of one adjoint population buffer (24 tiled planes of the compute type). */
@@ -299,10 +305,11 @@ lbm_status lbm_adjoint_step(const lbm_params *p, const lbm_state *fwd, lbm_adj_s
  * tile (bit a mod 64 of word b * T + a / 64 marks node (a, b)). */
 size_t lbm_probe_mask_bytes(const lbm_params *p);
 
-/* Fills the probe table that lbm_adjoint_step2 reads, from a->probe and a->ubar (distinct
- * cells): mask (device, lbm_probe_mask_bytes()) and field (device, 2 double planes of
- * dL/du^N, zero away from the probes).  Clears both first (fill kernels, no memset).  Call
- * once per backward pass, after a->probe and a->ubar are set. */
+/* Fills the probe table that lbm_adjoint_step2 (and lbm_adjoint_step, through
+ * a->probe_mask / a->probe_field) reads, from a->probe and a->ubar: mask (device,
+ * lbm_probe_mask_bytes()) and field (device, 2 double planes of dL/du^N summed over the
+ * probes of each cell, zero away from the probes).  Clears both first (fill kernels, no
+ * memset).  Call once per backward pass, after a->probe and a->ubar are set. */
 lbm_status lbm_adjoint_probe_table(const lbm_params *p, const lbm_adj_state *a, uint64_t *mask,
                                    double *field, void *stream);
 
@@ -310,7 +317,7 @@ lbm_status lbm_adjoint_probe_table(const lbm_params *p, const lbm_adj_state *a, 
  * lbm_adjoint_step; lambda^m stays on chip): lambda^{m+1} in a->adj[a->cur] -> lambda^{m-1}
  * in a->adj[1 - a->cur], with the gradient updates and probe sources of both levels.  The
  * result, the block sums and the FP64 gradients are those of lbm_adjoint_step(m) followed
- * by lbm_adjoint_step(m - 1), bit for bit.  Flips a->cur.
+ * by lbm_adjoint_step(m - 1) with the same probe table set in a, bit for bit.  Flips a->cur.
  *   r_m, r_mm1: body factors at levels m and m - 1.
  *   record_m, record_mm1: device, U^m and U^{m-1} as lbm_adjoint_step reads them.
  *   mask, field: the probe table (lbm_adjoint_probe_table); may be NULL when a->nprobe = 0.

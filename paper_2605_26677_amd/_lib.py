@@ -55,7 +55,7 @@ class lbm_adj_state(ctypes.Structure):
     _fields_ = [
         ("adj", c_vp * 2), ("cur", c_i32), ("g_mu", c_vp), ("g_lam", c_vp), ("g_body", c_vp),
         ("probe", c_vp), ("ubar", c_vp), ("nprobe", c_i32), ("nsteps", c_i64), ("aux", c_vp),
-        ("gsum", c_vp),
+        ("gsum", c_vp), ("probe_mask", c_vp), ("probe_field", c_vp),
     ]
 
 

@@ -70,6 +70,21 @@ __device__ __forceinline__ void adj_node(const Common& cm, const R l[4][6], cons
     }
 }
 
+// Probe source of the level at node (x, y) if it is a probe (bit x mod 64 of the word of
+// its tile row in the probe table): lambda_q += weight ubar for every q (the sum of the
+// ubar of every probe on that cell).  Without a table the probes are walked by
+// adj_probe_kernel instead.
+template <typename R, typename Args>
+__device__ __forceinline__ bool probe_at(const Args& a, int x, int y, double src[2]) {
+    if (!a.pmask) return false;
+    const uint64_t word = a.pmask[int64_t(y) * a.cm.ntile + (x >> 6)];
+    if (!((word >> (x & 63)) & 1ull)) return false;
+    const int64_t n = int64_t(a.cm.nx) * a.cm.ny, idx = int64_t(y) * a.cm.nx + x;
+    src[0] = a.probe_weight * a.pfield[idx];
+    src[1] = a.probe_weight * a.pfield[n + idx];
+    return true;
+}
+
 template <int ST, int LAW, bool WALLS, bool FIELDS>
 __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
     using R = typename Storage<ST>::real;
@@ -115,6 +130,15 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
     params_at<FIELDS, R>(cm, idx, mu, lam);
     R out[4][6], inc[4];
     adj_node<R, LAW>(cm, l, ft, mu, lam, R(a.r_m), a.g_mu || a.g_lam, a.g_body != nullptr, out, inc);
+    double ps[2];
+    const bool probe = probe_at<R>(a, x, y, ps);
+    if (probe) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            out[q][0] += R(ps[0]);
+            out[q][1] += R(ps[1]);
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -143,46 +167,86 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
             }
         }
     }
+    // the probe's body term (its source enters the body force's adjoint)
+    if (probe && a.g_body) {
+        const double hdt = 0.5 * cm.dt;
+        a.g_body[idx] += a.r_m * hdt * ps[0];
+        a.g_body[n + idx] += a.r_m * hdt * ps[1];
+    }
 }
 
 // Traction edges, stage 1 (one thread per wall link): F^b is rebuilt from the record of
-// U^m exactly as in the forward step, then dL/dF^b = lambda^{m+1}_d(X0)_F / 2 is carried
-// through the Newton solve by the implicit function theorem: with y = J^{-T} (dL/da),
-// the tangential column receives -N_A y_i C_iAjB and mu, lam receive -N_A y_i dP_iA/dp.
-// One launch covers every traction edge, one wavefront per workgroup (as the forward
-// solve).  Each link stages (tbar_1, tbar_2, dL/dmu, dL/dlam) in its own slot of the
-// staging buffer; the mu and lam terms reach the gradients in the scatter stage, which
-// goes one edge at a time, so the corner node two edges share takes them in edge order.
+// U^m with the forward step's extrapolation and Newton solve, then dL/dF^b =
+// lambda^{m+1}_d(X0)_F / 2 is carried through the solve by the implicit function theorem:
+// with y = J^{-T} (dL/da), the tangential column receives -N_A y_i C_iAjB and mu, lam
+// receive -N_A y_i dP_iA/dp.  One launch covers every traction edge, one wavefront per
+// workgroup, each lane reading the record at one edge position (as the forward solve).
+// Each link stages (tbar_1, tbar_2, dL/dmu, dL/dlam) in its own slot of the staging
+// buffer; the mu and lam terms reach the gradients in the scatter stage, which gives a
+// corner node the terms of its edges in edge order.
 template <int ST, int LAW, bool FIELDS>
-__global__ void __launch_bounds__(kTile) adj_traction_kernel(AdjArgs a) {
+__global__ void __launch_bounds__(kTracWin) adj_traction_kernel(AdjArgs a) {
     using R = typename Storage<ST>::real;
     const Common& cm = a.cm;
     int e = 0;
     while (e < 3 && int(blockIdx.x) >= a.eblk[e + 1]) ++e;
     const EdgeGeom G = edge_geom(e);
     const int L = (G.A == 0) ? cm.ny : cm.nx;
-    const int s = (int(blockIdx.x) - a.eblk[e]) * kTile + int(threadIdx.x);
-    if (s >= L) return;
     const bool per_t = (G.A == 0) ? cm.periodic_y : cm.periodic_x;
     const int A = G.A, Bx = 1 - G.A;
+    const int lane = int(threadIdx.x);
+    const int s = (int(blockIdx.x) - a.eblk[e]) * kTracOut - 2 + lane;   // this lane's position
     const int64_t n = int64_t(cm.nx) * cm.ny;
     const R* rec = (const R*)a.record;
     const R hdt = R(0.5 * cm.dt);
     const R inv2h = R(1.0 / (2.0 * cm.dx));
-    const Stencil sten = tangential_stencil(s, L, per_t);
-    R Ghat[2][2], Fa[2][2];
+    // the record of U^m at this lane's window position (as in the forward solve: lanes
+    // 2 .. 61 solve, the stencil velocities come from the neighbouring lanes)
+    int pw = s;
+    bool have = true;
+    if (per_t) pw = wrap_index(s, L);
+    else have = s >= 0 && s < L;
+    R Uw[2][6];
+#pragma unroll
     for (int r = 0; r < 2; ++r) {
-        R Us[3][6];
-        for (int j = 0; j < 3; ++j) {
-            const XY nd = edge_node(G, cm.nx, cm.ny, r, sten.p[j]);
+        if (have) {
+            const XY nd = edge_node(G, cm.nx, cm.ny, r, pw);
             const int64_t rb = tile_base(cm.ntile, 6, nd.x, nd.y);
-            for (int k = 0; k < 6; ++k) Us[j][k] = rec[rb + k * kTile];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Uw[r][k] = rec[rb + k * kTile];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Uw[r][k] = R(0);
         }
+    }
+    const bool solve = lane >= 2 && lane < kTracWin - 2 && s < L;
+    const Stencil sten = tangential_stencil(solve ? s : 0, L, per_t);
+    int dl[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        int d = sten.p[j] - (solve ? s : 0);
+        if (d > 2) d -= L;
+        if (d < -2) d += L;
+        dl[j] = solve ? d : 0;
+    }
+    R Vs[2][3][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) Vs[r][j][k] = __shfl(Uw[r][k], lane + dl[j], kTracWin);
+    if (!solve) return;
+    R Ghat[2][2], Fa[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
         for (int k = 0; k < 2; ++k) {
             R dv = R(0);
-            for (int j = 0; j < 3; ++j) dv += R(sten.w[j]) * Us[j][k];
-            Ghat[r][k] = Us[sten.self][2 + 2 * k + Bx] + hdt * dv * inv2h;
-            Fa[r][k] = Us[sten.self][2 + 2 * k + A];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dv += R(sten.w[j]) * Vs[r][j][k];
+            Ghat[r][k] = Uw[r][2 + 2 * k + Bx] + hdt * dv * inv2h;
+            Fa[r][k] = Uw[r][2 + 2 * k + A];
         }
     }
     R tang[2], acol[2], Tv[2];
@@ -232,19 +296,15 @@ __global__ void __launch_bounds__(kTile) adj_traction_kernel(AdjArgs a) {
     aux[3] = gl;
 }
 
-// Traction edge, stage 2 (one thread per node of the wall row and first interior row):
-// transpose of the extrapolation 3/2 G(X0) - 1/2 G(X1) and of G = F_{.B} + (dt/2) d_B v,
-// giving dL/dU^m at those nodes; it enters lambda^m_q for every q and the body gradient.
-template <int ST>
-__global__ void __launch_bounds__(kBlock) adj_traction_scatter_kernel(AdjArgs a) {
-    using R = typename Storage<ST>::real;
+// Traction edges, stage 2: transpose of the extrapolation 3/2 G(X0) - 1/2 G(X1) and of
+// G = F_{.B} + (dt/2) d_B v for the node at position s of row r of edge e, giving dL/dU^m
+// there; it enters lambda^m_q for every q and the body gradient.  With r = 0 the mu and lam
+// terms of the link's Newton solve (stage 1) are added too.
+template <typename R>
+__device__ void adj_scatter_edge(const AdjArgs& a, int e, int r, int s) {
     const Common& cm = a.cm;
-    const int e = a.edge;
     const EdgeGeom G = edge_geom(e);
     const int L = (G.A == 0) ? cm.ny : cm.nx;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * L) return;
-    const int r = t / L, s = t - r * L;
     const bool per_t = (G.A == 0) ? cm.periodic_y : cm.periodic_x;
     const int Bx = 1 - G.A;
     const int64_t n = int64_t(cm.nx) * cm.ny;
@@ -262,7 +322,6 @@ __global__ void __launch_bounds__(kBlock) adj_traction_scatter_kernel(AdjArgs a)
     const XY nd = edge_node(G, cm.nx, cm.ny, r, s);
     const int id = nd.y * cm.nx + nd.x;
     if (r == 0) {
-        // the mu and lam terms of this link's Newton solve (stage 1)
         if (a.g_mu) a.g_mu[id] += double(aux[4 * s + 2]);
         if (a.g_lam) a.g_lam[id] += double(aux[4 * s + 3]);
     }
@@ -273,6 +332,34 @@ __global__ void __launch_bounds__(kBlock) adj_traction_scatter_kernel(AdjArgs a)
         a.g_body[id] += a.r_m * double(hdt * E[0]);
         a.g_body[n + id] += a.r_m * double(hdt * E[1]);
     }
+}
+
+// Stage 2 of every traction edge in one launch, one thread per node of the wall row and
+// first interior row of each edge (workgroups [sblk[e], sblk[e+1]) for edge e).  Near a
+// corner a node can lie in the rows of two traction edges; the thread of the first of
+// them (XMIN, XMAX, YMIN, YMAX order) applies both edges' terms in that order and the
+// other thread skips the node, so every node takes its terms in the same order as edge
+// after edge.
+template <int ST>
+__global__ void __launch_bounds__(kTile) adj_traction_scatter_kernel(AdjArgs a) {
+    using R = typename Storage<ST>::real;
+    const Common& cm = a.cm;
+    int e = 0;
+    while (e < 3 && int(blockIdx.x) >= a.sblk[e + 1]) ++e;
+    const int L = (e == LBM_XMIN || e == LBM_XMAX) ? cm.ny : cm.nx;
+    const int t = (int(blockIdx.x) - a.sblk[e]) * kTile + int(threadIdx.x);
+    if (t >= 2 * L) return;
+    const int r = t / L, s = t - r * L;
+    const XY nd = edge_node(edge_geom(e), cm.nx, cm.ny, r, s);
+    // the traction edges whose two rows hold this node, in edge order
+    int ee[4], er[4], es[4], ne = 0;
+    const int x = nd.x, y = nd.y;
+    if (cm.bc[LBM_XMIN] == LBM_TRACTION && x <= 1) { ee[ne] = LBM_XMIN; er[ne] = x; es[ne] = y; ++ne; }
+    if (cm.bc[LBM_XMAX] == LBM_TRACTION && x >= cm.nx - 2) { ee[ne] = LBM_XMAX; er[ne] = cm.nx - 1 - x; es[ne] = y; ++ne; }
+    if (cm.bc[LBM_YMIN] == LBM_TRACTION && y <= 1) { ee[ne] = LBM_YMIN; er[ne] = y; es[ne] = x; ++ne; }
+    if (cm.bc[LBM_YMAX] == LBM_TRACTION && y >= cm.ny - 2) { ee[ne] = LBM_YMAX; er[ne] = cm.ny - 1 - y; es[ne] = x; ++ne; }
+    if (ne == 0 || ee[0] != e) return;
+    for (int i = 0; i < ne; ++i) adj_scatter_edge<R>(a, ee[i], er[i], es[i]);
 }
 
 // Probe source of the displacement loss at level m: u^N = u0 - (dt/2) v0 + dt sum_{m<N} v^m
@@ -317,19 +404,6 @@ __device__ __forceinline__ void pull_adj_node(const R* __restrict__ src, int nti
     }
 }
 
-// Probe source of level m at node (x, y) if it is a probe (bit x mod 64 of the word of its
-// tile row): lambda^m_q += weight ubar for every q, as adj_probe_kernel adds it.
-template <typename R>
-__device__ __forceinline__ bool probe_at(const Adj2Args& a, int x, int y, double src[2]) {
-    if (!a.pmask) return false;
-    const uint64_t word = a.pmask[int64_t(y) * a.cm.ntile + (x >> 6)];
-    if (!((word >> (x & 63)) & 1ull)) return false;
-    const int64_t n = int64_t(a.cm.nx) * a.cm.ny, idx = int64_t(y) * a.cm.nx + x;
-    src[0] = a.probe_weight * a.pfield[idx];
-    src[1] = a.probe_weight * a.pfield[n + idx];
-    return true;
-}
-
 // Two adjoint levels m and m - 1 per pass on a periodic grid, the transpose of the two-level
 // forward kernel: a workgroup owns kPairRows rows of one 64-node strip; wave w takes row
 // y0 - 1 + w from lambda^{m+1} to lambda^m (with the probe source of level m), one more wave
@@ -338,7 +412,7 @@ __device__ __forceinline__ bool probe_at(const Adj2Args& a, int x, int y, double
 // mirror images of the forward's.  Per node the arithmetic is adj_node, as in
 // adjoint_kernel, and the gradient updates of the two levels (block sums, folds, the probe
 // body term of level m) run in the order of two single steps, so the result is bit for
-// bit theirs; the probe source of level m - 1 is added afterwards by adj_probe_kernel.
+// bit theirs (with the probe table in both), the probe sources of both levels included.
 template <int ST, int LAW, bool FIELDS>
 __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2Args a) {
     using R = typename Storage<ST>::real;
@@ -458,6 +532,14 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
         for (int k = 0; k < 4; ++k) ft[k] = rec[(2 + k) * kTile];
         R out[4][6], inc2[4];
         adj_node<R, LAW>(cm, l, ft, mu, lam, R(a.r2), gpar, gbody, out, inc2);
+        if (probe) {
+            // the probe source of level m - 1 (same node, same weight as level m)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                out[q][0] += R(ps[0]);
+                out[q][1] += R(ps[1]);
+            }
+        }
         if (r < ny && xo < nx) {
             const int64_t ob = tile_base(ntile, 24, xo, r);
 #pragma unroll
@@ -478,6 +560,10 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj)
                     if (g64[jj]) g64[jj][gi] += double(inc2[jj]);
+                if (probe && a.g_body) {
+                    a.g_body[gi] += a.r2 * hdt * ps[0];
+                    a.g_body[n + gi] += a.r2 * hdt * ps[1];
+                }
             } else if (g64[0] || g64[1] || g64[2]) {
                 float* gs = (float*)a.gsum + tile_base(ntile, 4, xo, r);
                 float sj[4];
@@ -504,17 +590,18 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
                     }
                     store_stream(gs + jj * kTile, sj[jj]);
                 }
-            } else if (probe && a.g_body) {
-                a.g_body[gi] += a.r1 * hdt * ps[0];
-                a.g_body[n + gi] += a.r1 * hdt * ps[1];
+                if (probe && a.g_body) {
+                    a.g_body[gi] += a.r2 * hdt * ps[0];
+                    a.g_body[n + gi] += a.r2 * hdt * ps[1];
+                }
             }
         }
     }
 }
 
-// The probe table of lbm_adjoint_step2: bit x mod 64 of word (y, x / 64) marks a probe,
-// field holds its ubar (2 planes).  One thread walks the probes (the buffers are cleared by
-// adj_probe_clear_kernel first).
+// The probe table: bit x mod 64 of word (y, x / 64) marks a probe, field holds the sum of
+// the ubar of the probes on that cell (2 planes).  One thread walks the probes in order (the
+// buffers are cleared by adj_probe_clear_kernel first).
 __global__ void adj_probe_clear_kernel(uint64_t* mask, int64_t nmask, double* field, int64_t nfield) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < nmask) mask[i] = 0ull;
@@ -529,8 +616,8 @@ __global__ void adj_probe_table_kernel(Common cm, const int32_t* probe, const do
         const int id = probe[p];
         const int py = id / cm.nx, px = id - py * cm.nx;
         mask[int64_t(py) * cm.ntile + (px >> 6)] |= 1ull << (px & 63);
-        field[id] = ubar[p];
-        field[n + id] = ubar[nprobe + p];
+        field[id] += ubar[p];
+        field[n + id] += ubar[nprobe + p];
     }
 }
 
@@ -684,11 +771,11 @@ static hipError_t adjoint_st_law(const AdjArgs& a0, hipStream_t s) {
     a.eblk[0] = 0;
     for (int e = 0; e < 4; ++e) {
         const int L = (e == LBM_XMIN || e == LBM_XMAX) ? a.cm.ny : a.cm.nx;
-        a.eblk[e + 1] = a.eblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (L + kTile - 1) / kTile : 0);
+        a.eblk[e + 1] = a.eblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (L + kTracOut - 1) / kTracOut : 0);
     }
     if (a.eblk[4] > 0) {
-        if (fields) hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, true>), dim3(a.eblk[4]), dim3(kTile), 0, s, a);
-        else hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, false>), dim3(a.eblk[4]), dim3(kTile), 0, s, a);
+        if (fields) hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, true>), dim3(a.eblk[4]), dim3(kTracWin), 0, s, a);
+        else hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, false>), dim3(a.eblk[4]), dim3(kTracWin), 0, s, a);
     }
     const dim3 grid(unsigned((int64_t(a.cm.ntile) * a.cm.ny + kTilesPerBlock - 1) / kTilesPerBlock));
     const dim3 block(kTile * kTilesPerBlock);
@@ -699,14 +786,16 @@ static hipError_t adjoint_st_law(const AdjArgs& a0, hipStream_t s) {
         if (fields) hipLaunchKernelGGL((adjoint_kernel<ST, LAW, false, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((adjoint_kernel<ST, LAW, false, false>), grid, block, 0, s, a);
     }
-    // stage 2, one edge at a time (corner nodes belong to two edges)
+    // stage 2 of every traction edge, one launch (nodes two edges share go to the first)
+    a.sblk[0] = 0;
     for (int e = 0; e < 4; ++e) {
-        if (a.cm.bc[e] != LBM_TRACTION) continue;
-        a.edge = e;
         const int L = (e == LBM_XMIN || e == LBM_XMAX) ? a.cm.ny : a.cm.nx;
-        hipLaunchKernelGGL((adj_traction_scatter_kernel<ST>), dim3(nblk(2 * L)), dim3(kBlock), 0, s, a);
+        a.sblk[e + 1] = a.sblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (2 * L + kTile - 1) / kTile : 0);
     }
-    if (a.nprobe > 0 && a.probe_weight != 0.0) hipLaunchKernelGGL((adj_probe_kernel<ST>), dim3(1), dim3(64), 0, s, a);
+    if (a.sblk[4] > 0) hipLaunchKernelGGL((adj_traction_scatter_kernel<ST>), dim3(a.sblk[4]), dim3(kTile), 0, s, a);
+    // without a probe table the probe sources are added by one thread walking the probes
+    if (!a.pmask && a.nprobe > 0 && a.probe_weight != 0.0)
+        hipLaunchKernelGGL((adj_probe_kernel<ST>), dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -747,16 +836,6 @@ static void adj_init_st(const AdjInitArgs& a, hipStream_t s, dim3 grid) {
         case LBM_GENT: adj_init_st_law<ST, LBM_GENT>(a, s, grid); break;
         default: adj_init_st_law<ST, LBM_SVK>(a, s, grid); break;
     }
-}
-
-hipError_t launch_adjoint_probe(const AdjArgs& a, hipStream_t s) {
-    if (a.nprobe <= 0 || a.probe_weight == 0.0) return hipSuccess;
-    switch (a.cm.storage) {
-        case LBM_F32_SHIFTED: hipLaunchKernelGGL((adj_probe_kernel<LBM_F32_SHIFTED>), dim3(1), dim3(64), 0, s, a); break;
-        case LBM_F16_SHIFTED: hipLaunchKernelGGL((adj_probe_kernel<LBM_F16_SHIFTED>), dim3(1), dim3(64), 0, s, a); break;
-        default: hipLaunchKernelGGL((adj_probe_kernel<LBM_F64_PLAIN>), dim3(1), dim3(64), 0, s, a); break;
-    }
-    return hipGetLastError();
 }
 
 template <int ST, int LAW>

@@ -364,6 +364,10 @@ lbm_status lbm_adjoint_step(const lbm_params* p, const lbm_state* fwd, lbm_adj_s
     a.ubar = adj->ubar;
     a.nprobe = adj->nprobe;
     a.probe_weight = (m == adj->nsteps ? 0.5 : 1.0) * a.cm.dt;
+    if (adj->nprobe > 0 && adj->probe_mask && adj->probe_field) {
+        a.pmask = adj->probe_mask;
+        a.pfield = adj->probe_field;
+    }
     if (launch_adjoint(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
     adj->cur = 1 - adj->cur;
     return LBM_OK;
@@ -417,19 +421,8 @@ lbm_status lbm_adjoint_step2(const lbm_params* p, const lbm_state* fwd, lbm_adj_
     a.r2 = r_mm1;
     a.pmask = adj->nprobe > 0 ? mask : nullptr;
     a.pfield = adj->nprobe > 0 ? field : nullptr;
-    a.probe_weight = a.cm.dt;                    // level m < N
+    a.probe_weight = a.cm.dt;                    // levels m and m - 1 are below N
     if (launch_adjoint2(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
-    // the probe source of level m - 1 (< N), as lbm_adjoint_step adds it
-    AdjArgs pa{};
-    pa.cm = a.cm;
-    pa.dst = a.dst;
-    pa.g_body = adj->g_body;
-    pa.r_m = r_mm1;
-    pa.probe = adj->probe;
-    pa.ubar = adj->ubar;
-    pa.nprobe = adj->nprobe;
-    pa.probe_weight = a.cm.dt;
-    if (launch_adjoint_probe(pa, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
     adj->cur = 1 - adj->cur;
     return LBM_OK;
 }

@@ -193,12 +193,14 @@ struct AdjArgs {
     void* aux;
     double r_m;
     EdgeData ed;
-    int edge;                        // the edge of the scatter stage
-    int eblk[5];                     // stage 1: workgroups of edge e, [eblk[e], eblk[e+1])
+    int eblk[5];                     // traction stage 1: workgroups of edge e, [eblk[e], eblk[e+1])
+    int sblk[5];                     // traction stage 2: the same for the scatter
     const int32_t* probe;
     const double* ubar;
     int nprobe;
     double probe_weight;             // dt * (1 or 1/2)
+    const uint64_t* pmask;           // probe table (mask, summed ubar field) or NULL
+    const double* pfield;
 };
 
 struct Adj2Args {
@@ -250,7 +252,6 @@ hipError_t launch_init_state(const InitArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s);
 hipError_t launch_adjoint_init(const AdjInitArgs& a, hipStream_t s);
 hipError_t launch_adjoint2(const Adj2Args& a, hipStream_t s);
-hipError_t launch_adjoint_probe(const AdjArgs& a, hipStream_t s);
 hipError_t launch_probe_table(const Common& cm, const int32_t* probe, const double* ubar, int nprobe,
                               uint64_t* mask, double* field, hipStream_t s);
 

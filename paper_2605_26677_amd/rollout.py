@@ -249,13 +249,15 @@ class _Adjoint:
         a.aux = self.aux.data_ptr()
         a.gsum = self.gsum.data_ptr()
         self.a = a
-        # the probe table of the two-level adjoint (periodic grids)
-        self.pmask = self.pfield = None
-        if sv.periodic:
-            self.pmask = torch.empty(sv.lib.lbm_probe_mask_bytes(ctypes.byref(sv.p)), dtype=torch.uint8, device=dev)
-            self.pfield = torch.empty(2 * n, dtype=torch.float64, device=dev)
-            L.check(sv.lib.lbm_adjoint_probe_table(ctypes.byref(sv.p), ctypes.byref(self.a), _ptr(self.pmask),
-                                                   _ptr(self.pfield), _stream()), "lbm_adjoint_probe_table")
+        # the probe table: the adjoint kernels add the probe sources where they write the
+        # probe nodes (both levels of the two-level adjoint; the single step through the
+        # state's probe_mask / probe_field)
+        self.periodic = sv.periodic
+        self.pmask = torch.empty(sv.lib.lbm_probe_mask_bytes(ctypes.byref(sv.p)), dtype=torch.uint8, device=dev)
+        self.pfield = torch.empty(2 * n, dtype=torch.float64, device=dev)
+        L.check(sv.lib.lbm_adjoint_probe_table(ctypes.byref(sv.p), ctypes.byref(self.a), _ptr(self.pmask),
+                                               _ptr(self.pfield), _stream()), "lbm_adjoint_probe_table")
+        a.probe_mask, a.probe_field = self.pmask.data_ptr(), self.pfield.data_ptr()
 
     def step(self, sv, cfg, m, record):
         L.check(sv.lib.lbm_adjoint_step(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), int(m),
@@ -265,7 +267,7 @@ class _Adjoint:
     def pair_ok(self, sv, cfg, m, lowest):
         """Levels m and m - 1 can go through lbm_adjoint_step2 (periodic grids, unless the
         configuration turns pairs off)."""
-        return cfg.pairs is not False and self.pmask is not None and lowest <= m - 1 and 1 <= m < cfg.nsteps
+        return cfg.pairs is not False and self.periodic and lowest <= m - 1 and 1 <= m < cfg.nsteps
 
     def step2(self, sv, cfg, m, record_m, record_mm1):
         L.check(sv.lib.lbm_adjoint_step2(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), int(m),
