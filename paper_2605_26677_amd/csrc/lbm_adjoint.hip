@@ -523,8 +523,10 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
         for (int k = 0; k < 6; ++k) {
             l[1][k] = xq1[w + 1][k][lane];
             l[3][k] = xq3[w - 1][k][lane];
-            if (lane == kTile - 1) l[0][k] = xh[1][k][w - 1];
-            if (lane == 0) l[2][k] = xh[0][k][w - 1];
+            // selected by value, as in the forward two-level kernel
+            const R e0 = xh[1][k][w - 1], e2 = xh[0][k][w - 1];
+            l[0][k] = lane == kTile - 1 ? e0 : l[0][k];
+            l[2][k] = lane == 0 ? e2 : l[2][k];
         }
         const R* rec = (const R*)a.rec2 + tile_base(ntile, 6, xc, yr);
         R ft[4];

@@ -548,7 +548,7 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
         collide_node<R, LAW, SH>(cm, gh, R(bd0), R(bd1), muh, lamh, fh, Uh, Jh);
         if (lane < 2 * kPairRows) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) xh[side][k][row] = R(to_storage<T>(fh[side == 0 ? 0 : 2][k]));
+            for (int k = 0; k < 6; ++k) xh[side][k][row] = R(to_storage<T>(side == 0 ? fh[0][k] : fh[2][k]));
         }
     }
     __syncthreads();
@@ -560,8 +560,12 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
         for (int k = 0; k < 6; ++k) {
             g[1][k] = xq1[w - 1][k][lane];
             g[3][k] = xq3[w + 1][k][lane];
-            if (lane == 0) g[0][k] = xh[0][k][w - 1];
-            if (lane == kTile - 1) g[2][k] = xh[1][k][w - 1];
+            // both end values are read by every lane (one address per wave) and selected
+            // by value: a store guarded by the lane would let the compiler merge the two
+            // into one write at a lane-dependent index of g, a select over all 24 entries
+            const R e0 = xh[0][k][w - 1], e2 = xh[1][k][w - 1];
+            g[0][k] = lane == 0 ? e0 : g[0][k];
+            g[2][k] = lane == kTile - 1 ? e2 : g[2][k];
         }
         const double bd0 = a.r_np2 * braw[0], bd1 = a.r_np2 * braw[1];
         R f2[4][6], U2[6], J2;
