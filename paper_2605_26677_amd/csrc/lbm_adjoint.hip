@@ -45,8 +45,8 @@ __device__ __forceinline__ void adj_node(const Common& cm, const R l[4][6], cons
 #pragma unroll
     for (int kB = 0; kB < 4; ++kB)
         AT[2 + kB] = -(dxl[0] * C[kB] + dxl[1] * C[8 + kB]) - (dyl[0] * C[4 + kB] + dyl[1] * C[12 + kB]);
-    const R om = R(cm.omega);
-    const R c2 = R(cm.k_c2);
+    const R om = kval<R>(cm.omega, cm.f_omega);
+    const R c2 = kval<R>(cm.k_c2, cm.f_c2);
     R gU[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) gU[k] = om * R(0.25) * (s6[k] + c2 * AT[k]);
@@ -55,7 +55,7 @@ __device__ __forceinline__ void adj_node(const Common& cm, const R l[4][6], cons
     for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int k = 0; k < 6; ++k) out[q][k] = omc * l[q][k] + gU[k];
-    const R hc = R(cm.k_hc);
+    const R hc = kval<R>(cm.k_hc, cm.f_hc);
     inc[0] = inc[1] = inc[2] = inc[3] = R(0);
     if (grad_par) {
         R Pm[4], Pl[4];
@@ -64,7 +64,7 @@ __device__ __forceinline__ void adj_node(const Common& cm, const R l[4][6], cons
         inc[1] = om * hc * -(dxl[0] * Pl[0] + dxl[1] * Pl[2] + dyl[0] * Pl[1] + dyl[1] * Pl[3]);
     }
     if (grad_body) {
-        const R hdtr = R(cm.k_hdt), srcw = R(cm.k_srcw);
+        const R hdtr = kval<R>(cm.k_hdt, cm.f_hdt), srcw = kval<R>(cm.k_srcw, cm.f_srcw);
         inc[2] = rm * (hdtr * gU[0] + srcw * s6[0]);
         inc[3] = rm * (hdtr * gU[1] + srcw * s6[1]);
     }
@@ -391,10 +391,10 @@ __global__ void adj_probe_kernel(AdjArgs a) {
 template <typename R>
 __device__ __forceinline__ void pull_adj_node(const R* __restrict__ src, int ntile, int nx, int ny, int x, int y,
                                               R l[4][6]) {
-    const int64_t b0 = tile_base(ntile, 24, wrap_index(x + 1, nx), y);
-    const int64_t b1 = tile_base(ntile, 24, x, wrap_index(y + 1, ny));
-    const int64_t b2 = tile_base(ntile, 24, wrap_index(x - 1, nx), y);
-    const int64_t b3 = tile_base(ntile, 24, x, wrap_index(y - 1, ny));
+    const int64_t b0 = tile_base(ntile, 24, wrap_inc(x, nx), y);
+    const int64_t b1 = tile_base(ntile, 24, x, wrap_inc(y, ny));
+    const int64_t b2 = tile_base(ntile, 24, wrap_dec(x, nx), y);
+    const int64_t b3 = tile_base(ntile, 24, x, wrap_dec(y, ny));
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         l[0][k] = src[b0 + k * kTile];
@@ -427,8 +427,8 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
     const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;
-    const int xc = wrap_index(c0 + lane, nx);
-    const int yr = wrap_index(r, ny);
+    const int xc = wrap_near(c0 + lane, nx);
+    const int yr = wrap_near(r, ny);
     const int idx = yr * nx + xc;
     const R* __restrict__ src = (const R*)a.src;
     R* __restrict__ dst = (R*)a.dst;
@@ -442,8 +442,8 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
         // lanes shifted, the end lanes from the columns beside the strip), q1 from row r+1,
         // q3 from row r-1
         const int64_t bo = tile_base(ntile, 24, xc, yr);
-        const int64_t bp = tile_base(ntile, 24, xc, wrap_index(r + 1, ny));
-        const int64_t bm = tile_base(ntile, 24, xc, wrap_index(r - 1, ny));
+        const int64_t bp = tile_base(ntile, 24, xc, wrap_near(r + 1, ny));
+        const int64_t bm = tile_base(ntile, 24, xc, wrap_near(r - 1, ny));
         R own0[6], own2[6], h[6] = {};
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -456,8 +456,8 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
             l[3][k] = src[bm + (18 + k) * kTile];
         }
         if (lane == 0 || lane == kTile - 1) {
-            const int64_t bh = lane == kTile - 1 ? tile_base(ntile, 24, wrap_index(c0 + kTile, nx), yr)
-                                                 : tile_base(ntile, 24, wrap_index(c0 - 1, nx), yr) + 12 * kTile;
+            const int64_t bh = lane == kTile - 1 ? tile_base(ntile, 24, wrap_near(c0 + kTile, nx), yr)
+                                                 : tile_base(ntile, 24, wrap_near(c0 - 1, nx), yr) + 12 * kTile;
 #pragma unroll
             for (int k = 0; k < 6; ++k) h[k] = src[bh + k * kTile];
         }
@@ -493,7 +493,7 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
         // kPairRows + j at (c0 + 64, y0 + j); the other lanes repeat the last node
         const int j = min(lane, 2 * kPairRows - 1);
         const int side = j / kPairRows, row = j - side * kPairRows;
-        const int hx = wrap_index(side == 0 ? c0 - 1 : c0 + kTile, nx), hy = wrap_index(y0 + row, ny);
+        const int hx = wrap_near(side == 0 ? c0 - 1 : c0 + kTile, nx), hy = wrap_near(y0 + row, ny);
         R lh[4][6], oh[4][6], ih[4], muh, lamh, fth[4];
         pull_adj_node<R>(src, ntile, nx, ny, hx, hy, lh);
         const R* rec = (const R*)a.rec1 + tile_base(ntile, 6, hx, hy);

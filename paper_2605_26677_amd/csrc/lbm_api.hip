@@ -62,6 +62,17 @@ Common make_common(const lbm_params* p, const lbm_state* s) {
         cm.body_prev = s->body_prev;
         cm.fault = s->fault;
     }
+    cm.f_omq = float(cm.k_omq);
+    cm.f_cq = float(cm.k_cq);
+    cm.f_srcw = float(cm.k_srcw);
+    cm.f_hdt = float(cm.k_hdt);
+    cm.f_c2 = float(cm.k_c2);
+    cm.f_hc = float(cm.k_hc);
+    cm.f_dt = float(cm.dt);
+    cm.f_mu0 = float(cm.mu0);
+    cm.f_lam0 = float(cm.lam0);
+    for (int k = 0; k < 3; ++k) cm.f_law_k[k] = float(cm.law_k[k]);
+    cm.f_omega = float(cm.omega);
     return cm;
 }
 
@@ -249,6 +260,10 @@ lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_n, d
     a.nstrip = (p->nx + kPairCols - 1) / kPairCols;
     a.r_np1 = r_np1;
     a.r_np2 = r_np2;
+    for (int k = 0; k < 2; ++k) {
+        a.fb1[k] = float(r_np1 * a.cm.b0[k]);
+        a.fb2[k] = float(r_np2 * a.cm.b0[k]);
+    }
     // F^b of level n from f*^n, as lbm_step takes it
     {
         TractionArgs t{};

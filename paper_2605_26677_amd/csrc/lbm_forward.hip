@@ -176,7 +176,7 @@ __device__ __forceinline__ void wall_link(const Common& cm, const EdgeData& ed, 
 template <typename R, int LAW, bool SH>
 __device__ __forceinline__ void collide_node(const Common& cm, const R g[4][6], R B0, R B1, R mu, R lam,
                                              R out[4][6], R U[6], R& J) {
-    const R hdt = R(cm.k_hdt);
+    const R hdt = kval<R>(cm.k_hdt, cm.f_hdt);
 #pragma unroll
     for (int k = 0; k < 6; ++k) U[k] = g[0][k] + g[1][k] + g[2][k] + g[3][k];
     U[0] += hdt * B0;
@@ -189,8 +189,8 @@ __device__ __forceinline__ void collide_node(const Common& cm, const R g[4][6], 
     // (eq:flux-vectors); the zero entries and the unit factors i, j are taken out by hand.
     // omc = 1 - 4 omq is exact in R (Sterbenz), so the weights of f and f^eq sum to exactly
     // 1 and the collision keeps sum_q f* = U + (dt/2) B without a drift of the moments
-    const R omq = R(cm.k_omq), omc = R(1) - R(4) * omq, cq = R(cm.k_cq);
-    const R srcw = R(cm.k_srcw);
+    const R omq = kval<R>(cm.k_omq, cm.f_omq), omc = R(1) - R(4) * omq, cq = kval<R>(cm.k_cq, cm.f_cq);
+    const R srcw = kval<R>(cm.k_srcw, cm.f_srcw);
     R a[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) a[k] = omq * U[k];
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
     body_at<FIELDS>(cm, idx, n, a.r_np1, bd0, bd1);
     R mu, lam;
     params_at<FIELDS, R>(cm, idx, mu, lam);
-    const R dt = R(cm.dt);
+    const R dt = kval<R>(cm.dt, cm.f_dt);
     R out[4][6], U[6], J;
     collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, out, U, J);
 #pragma unroll
@@ -323,8 +323,8 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs a) {
 template <typename T, typename R>
 __device__ __forceinline__ void pull_node(const T* __restrict__ src, int ntile, int nx, int ny, int x, int y,
                                           R g[4][6]) {
-    const int xm = wrap_index(x - 1, nx), xp = wrap_index(x + 1, nx);
-    const int ym = wrap_index(y - 1, ny), yp = wrap_index(y + 1, ny);
+    const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+    const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
     const int64_t b0 = tile_base(ntile, 24, xm, y), b1 = tile_base(ntile, 24, x, ym);
     const int64_t b2 = tile_base(ntile, 24, xp, y), b3 = tile_base(ntile, 24, x, yp);
 #pragma unroll
@@ -346,7 +346,7 @@ __device__ __forceinline__ void pair_tail(const Step2Args& a, int x, int y, cons
     constexpr bool SH = Storage<ST>::shifted;
     const Common& cm = a.cm;
     const int ntile = cm.ntile;
-    const R dt = R(cm.dt);
+    const R dt = kval<R>(cm.dt, cm.f_dt);
     if (!a.ustar) {
     } else if constexpr (ST == LBM_F64_PLAIN) {
         double* us = (double*)a.ustar + tile_base(ntile, 2, x, y);
@@ -447,8 +447,8 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
     const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;
     const int xg = c0 + lane;
-    const int xc = wrap_index(xg, nx);
-    const int yr = wrap_index(r, ny);
+    const int xc = wrap_near(xg, nx);
+    const int yr = wrap_near(r, ny);
     const T* __restrict__ src = (const T*)a.src;
     T* __restrict__ dst = (T*)a.dst;
     const int idx1 = yr * nx + xc;
@@ -457,14 +457,14 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
     const bool valid = !WALLS || ((cm.periodic_x || xg < nx) && (cm.periodic_y || (r >= 0 && r < ny)));
 
     R f1[4][6], U1[6], g[4][6], mu, lam;
-    double braw[2];                           // b(X) of this wave's node, for both levels
+    R B2[2];                                  // r_np2 b(X) of this wave's node (level n+2)
     bool nonfinite = false, jbad = false;
     if (w < kPairWaves) {
         // level n -> n+1 on row r: q0 from x-1 and q2 from x+1 of row r (own lanes shifted,
         // the two end lanes from the columns beside the strip), q1 from row r-1, q3 from r+1
         const int64_t bo = tile_base(ntile, 24, xc, yr);
-        const int64_t bm = tile_base(ntile, 24, xc, wrap_index(r - 1, ny));
-        const int64_t bp = tile_base(ntile, 24, xc, wrap_index(r + 1, ny));
+        const int64_t bm = tile_base(ntile, 24, xc, wrap_near(r - 1, ny));
+        const int64_t bp = tile_base(ntile, 24, xc, wrap_near(r + 1, ny));
         R own0[6], own2[6], h[6] = {};
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -477,8 +477,8 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
             g[3][k] = R(src[bp + (18 + k) * kTile]);
         }
         if (lane == 0 || lane == kTile - 1) {
-            const int64_t bh = lane == 0 ? tile_base(ntile, 24, wrap_index(c0 - 1, nx), yr)
-                                         : tile_base(ntile, 24, wrap_index(c0 + kTile, nx), yr) + 12 * kTile;
+            const int64_t bh = lane == 0 ? tile_base(ntile, 24, wrap_near(c0 - 1, nx), yr)
+                                         : tile_base(ntile, 24, wrap_near(c0 + kTile, nx), yr) + 12 * kTile;
 #pragma unroll
             for (int k = 0; k < 6; ++k) h[k] = R(src[bh + k * kTile]);
         }
@@ -499,11 +499,12 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
                 if (!cm.periodic_y && r == ny - 1) wall_link<T, R>(cm, a.ed, a.aux, LBM_YMAX, xc, src + bo, kTile, g[3]);
             }
         }
-        body_raw<FIELDS>(cm, idx1, n, braw[0], braw[1]);
-        const double bd0 = a.r_np1 * braw[0], bd1 = a.r_np1 * braw[1];
+        R B1[2];
+        body_r<FIELDS, R>(cm, idx1, n, a.r_np1, a.fb1, B1[0], B1[1]);
+        body_r<FIELDS, R>(cm, idx1, n, a.r_np2, a.fb2, B2[0], B2[1]);
         params_at<FIELDS, R>(cm, idx1, mu, lam);
         R J1;
-        collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f1, U1, J1);
+        collide_node<R, LAW, SH>(cm, g, B1[0], B1[1], mu, lam, f1, U1, J1);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -528,7 +529,7 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
         // kPairRows + j at (c0 + 64, y0 + j); the other lanes repeat the last node
         const int j = min(lane, 2 * kPairRows - 1);
         const int side = j / kPairRows, row = j - side * kPairRows;
-        const int hx = wrap_index(side == 0 ? c0 - 1 : c0 + kTile, nx), hy = wrap_index(y0 + row, ny);
+        const int hx = wrap_near(side == 0 ? c0 - 1 : c0 + kTile, nx), hy = wrap_near(y0 + row, ny);
         R gh[4][6], fh[4][6], Uh[6], Jh, muh, lamh;
         pull_node<T, R>(src, ntile, nx, ny, hx, hy, gh);
         if constexpr (WALLS) {
@@ -542,10 +543,10 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
             }
         }
         const int hidx = hy * nx + hx;
-        double bd0, bd1;
-        body_at<FIELDS>(cm, hidx, n, a.r_np1, bd0, bd1);
+        R Bh0, Bh1;
+        body_r<FIELDS, R>(cm, hidx, n, a.r_np1, a.fb1, Bh0, Bh1);
         params_at<FIELDS, R>(cm, hidx, muh, lamh);
-        collide_node<R, LAW, SH>(cm, gh, R(bd0), R(bd1), muh, lamh, fh, Uh, Jh);
+        collide_node<R, LAW, SH>(cm, gh, Bh0, Bh1, muh, lamh, fh, Uh, Jh);
         if (lane < 2 * kPairRows) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) xh[side][k][row] = R(to_storage<T>(side == 0 ? fh[0][k] : fh[2][k]));
@@ -567,9 +568,8 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
             g[0][k] = lane == 0 ? e0 : g[0][k];
             g[2][k] = lane == kTile - 1 ? e2 : g[2][k];
         }
-        const double bd0 = a.r_np2 * braw[0], bd1 = a.r_np2 * braw[1];
         R f2[4][6], U2[6], J2;
-        collide_node<R, LAW, SH>(cm, g, R(bd0), R(bd1), mu, lam, f2, U2, J2);
+        collide_node<R, LAW, SH>(cm, g, B2[0], B2[1], mu, lam, f2, U2, J2);
         const bool wall_node = WALLS && ((!cm.periodic_x && (xo == 0 || xo == nx - 1)) ||
                                          (!cm.periodic_y && (r == 0 || r == ny - 1)));
         if (r < ny && xo < nx && !wall_node) {

@@ -46,7 +46,20 @@ struct Common {
     // dt (2 - omega)/8 of eq:collision, and dt/2
     double k_omq, k_cq, k_srcw, k_hdt;
     double k_c2, k_hc;               // 2/c and 1/(2c) (adjoint)
+    // The same constants, dt, the uniform mu, lam and the law constants rounded to float
+    // on the host, for the FP32 compute type: a float kernel argument enters an
+    // instruction as a scalar operand, while converting the double costs a vector
+    // instruction per wavefront and use.  kval() picks the copy of the compute type.
+    float f_omq, f_cq, f_srcw, f_hdt, f_c2, f_hc, f_dt, f_mu0, f_lam0, f_law_k[3], f_omega;
 };
+
+// A Common constant in the compute type R: the float copy for R = float (the same value
+// as converting the double on the device), the double otherwise.
+template <typename R>
+__host__ __device__ __forceinline__ R kval(double d, float f) {
+    if constexpr (sizeof(R) == sizeof(float)) return f;
+    else return R(d);
+}
 
 struct StepArgs {
     Common cm;
@@ -75,11 +88,39 @@ constexpr int kPairChunk = 32;       // strips per chunk of the workgroup order
 // XCD's L2.  mode 1: every block outside that rectangle (the blocks along the walls):
 // block rows [0, b_lo) and [b_hi, nblk) over all strips, then the strips outside
 // [s_lo, s_hi) over the block rows [b_lo, b_hi).
+// Division of 0 <= v < 2^31 by a divisor d >= 1 fixed per launch, by multiplication
+// (Granlund and Montgomery, division by invariant integers): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, v / d = (mulhi(m, v) + v) >> l.  The host forms m and l;
+// on the device both steps are scalar instructions for a wave-uniform v, where a plain
+// integer division would take a vector reciprocal sequence.
+struct FastDiv {
+    uint32_t m;
+    int l;
+    int d;
+};
+
+inline FastDiv fast_div(int d) {
+    FastDiv f{};
+    f.d = d < 1 ? 1 : d;
+    int l = 0;
+    while ((int64_t(1) << l) < f.d) ++l;
+    f.l = l;
+    f.m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << l) - uint64_t(f.d))) / uint64_t(f.d) + 1);
+    return f;
+}
+
+__device__ __forceinline__ int fdiv(int v, const FastDiv& f) {
+    const uint32_t t = __umulhi(f.m, uint32_t(v));
+    return int((t + uint32_t(v)) >> f.l);
+}
+
 struct PairMap {
     int mode;
     int nstrip, nblk;
     int s_lo, s_hi, b_lo, b_hi;
     int chunk, per_chunk;
+    FastDiv d_per_chunk, d_chunk, d_last;    // mode 0: divisions by per_chunk, by chunk and
+                                             // by the width of the last (narrower) chunk
 };
 
 // Workgroups of mode 0 over the given rectangle; the chunk width is kPairChunk strips,
@@ -97,6 +138,10 @@ inline PairMap pair_map(int nstrip, int nblk, int s_lo, int s_hi, int b_lo, int 
     if (c < 1) c = 1;
     m.chunk = int(c);
     m.per_chunk = int(c * rows);
+    m.d_per_chunk = fast_div(m.per_chunk);
+    m.d_chunk = fast_div(m.chunk);
+    const int width = s_hi - s_lo, last = width - (width - 1) / m.chunk * m.chunk;
+    m.d_last = fast_div(last);
     return m;
 }
 
@@ -107,10 +152,10 @@ inline int64_t pair_map_blocks(const PairMap& m) {
 
 __device__ __forceinline__ void pair_block(const PairMap& m, int b, int& strip, int& blk) {
     if (m.mode == 0) {
-        const int chunk = b / m.per_chunk;
+        const int chunk = fdiv(b, m.d_per_chunk);
         const int rem = b - chunk * m.per_chunk;
         const int kc = min(m.chunk, (m.s_hi - m.s_lo) - chunk * m.chunk);
-        const int bb = rem / kc;
+        const int bb = kc == m.chunk ? fdiv(rem, m.d_chunk) : fdiv(rem, m.d_last);
         strip = m.s_lo + chunk * m.chunk + (rem - bb * kc);
         blk = m.b_lo + bb;
         return;
@@ -140,6 +185,7 @@ struct Step2Args {
     void* aux;                       // F^b staging and wall lines (grids with walls)
     EdgeData ed;                     // wall data at t^{n+1/2}
     EdgeData ed2;                    // wall data at t^{n+3/2}
+    float fb1[2], fb2[2];            // uniform body r_np1 b0 and r_np2 b0 rounded to float
     int wall_pass;                   // launch the wall-node kernel instead of the bulk kernel
     void* record1;                   // U^{n+1} or NULL
     void* record2;                   // U^{n+2} or NULL

@@ -22,6 +22,20 @@ __device__ __forceinline__ int wrap_index(int v, int n) {
     return m < 0 ? m + n : m;
 }
 
+// wrap_index for v >= -n, with the division only where v >= 2n (a lane index beyond a grid
+// narrower than one tile): one compare and subtract in the common case.
+__device__ __forceinline__ int wrap_near(int v, int n) {
+    if (v < 0) return v + n;
+    if (v < n) return v;
+    v -= n;
+    if (v < n) return v;
+    return v % n;
+}
+
+// The neighbours x - 1 and x + 1 of 0 <= x < n on a periodic axis.
+__device__ __forceinline__ int wrap_dec(int x, int n) { return x == 0 ? n - 1 : x - 1; }
+__device__ __forceinline__ int wrap_inc(int x, int n) { return x + 1 == n ? 0 : x + 1; }
+
 template <typename R>
 __device__ __forceinline__ R edge_value(const EdgeData& ed, int e, int comp, int s, int L) {
     const double* f = ed.field[e];
@@ -52,15 +66,30 @@ __device__ __forceinline__ void body_at(const Common& cm, int idx, int64_t n, do
     }
 }
 
+// r b(X) of node idx in the compute type: r times the field (in double, then rounded), or
+// the uniform r b0, which the host forms and rounds for R = float (fb).
+template <bool FIELDS, typename R>
+__device__ __forceinline__ void body_r(const Common& cm, int idx, int64_t n, double r, const float fb[2], R& B0,
+                                       R& B1) {
+    if (FIELDS && cm.body) {
+        B0 = R(r * double(cm.body[idx]));
+        B1 = R(r * double(cm.body[n + idx]));
+    } else {
+        B0 = kval<R>(r * cm.b0[0], fb[0]);
+        B1 = kval<R>(r * cm.b0[1], fb[1]);
+    }
+}
+
 template <bool FIELDS, typename R>
 __device__ __forceinline__ void params_at(const Common& cm, int idx, R& mu, R& lam) {
-    if (FIELDS && cm.mu) mu = R(cm.mu[idx]); else mu = R(cm.mu0);
-    if (FIELDS && cm.lam) lam = R(cm.lam[idx]); else lam = R(cm.lam0);
+    if (FIELDS && cm.mu) mu = R(cm.mu[idx]); else mu = kval<R>(cm.mu0, cm.f_mu0);
+    if (FIELDS && cm.lam) lam = R(cm.lam[idx]); else lam = kval<R>(cm.lam0, cm.f_lam0);
 }
 
 template <typename R>
 __device__ __forceinline__ LawK<R> law_consts(const Common& cm) {
-    return LawK<R>{R(cm.law_k[0]), R(cm.law_k[1]), R(cm.law_k[2])};
+    return LawK<R>{kval<R>(cm.law_k[0], cm.f_law_k[0]), kval<R>(cm.law_k[1], cm.f_law_k[1]),
+                   kval<R>(cm.law_k[2], cm.f_law_k[2])};
 }
 
 // Sum of the four stored post-collision populations of one node minus (dt/2) B: the
