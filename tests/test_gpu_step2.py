@@ -83,6 +83,13 @@ def test_step2_bitwise_equals_two_steps(storage, nx, ny, fields):
         _pair_vs_single(case, storage, start, pairs=20)
 
 
+@pytest.mark.parametrize("nx,ny", [(2500, 23), (4160, 11)])
+def test_step2_bitwise_wide_grids(nx, ny):
+    """More strips than one chunk of the workgroup order (32), with a narrower last chunk
+    (40 strips: 32 + 8; 65 strips: 2 x 32 + 1), so the block map divides by both widths."""
+    _pair_vs_single(_case(nx, ny, fields=True), "f32", 1, pairs=4)
+
+
 @pytest.mark.parametrize("law", [l for l in ALL_LAWS if l != "lognh"])
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 def test_step2_bitwise_every_law(storage, law):
@@ -213,6 +220,12 @@ def _walls_pair_vs_single(kinds, nx, ny, storage, fields, start, pairs, law="log
 def test_step2_walls_bitwise_equals_two_steps(kind, nx, ny, storage):
     for start, fields in ((0, False), (1, True)):
         _walls_pair_vs_single(WALL_KINDS[kind], nx, ny, storage, fields, start, pairs=10)
+
+
+def test_step2_walls_bitwise_wide_grid():
+    """A walled grid whose interior spans more than one chunk of strips (41 strips, 39 of
+    them interior: 32 + 7)."""
+    _walls_pair_vs_single(WALL_KINDS["block"], 2600, 40, "f32", True, 1, pairs=3)
 
 
 @pytest.mark.parametrize("law", ["svk", "gent", "nh"])
