@@ -429,20 +429,29 @@ __device__ __forceinline__ void store_wall_lines(const Common& cm, void* aux, in
 // steps.  WALLS: the level-n links of wall nodes are rebuilt in the first level as
 // step_kernel rebuilds them, the wall nodes are left out of the second level, and level
 // n+1 of the wall lines goes to the staging buffer for step2_wall_kernel.
+// The LDS of one two-level workgroup: level n+1 of the q1 and q3 planes of every row wave
+// (read by the rows above and below) and of the nodes beside the strip (q0 at c0 - 1, q2
+// at c0 + 64).
+template <typename R>
+struct PairLds {
+    R xq1[kPairWaves][6][kTile];
+    R xq3[kPairWaves][6][kTile];
+    R xh[2][6][kPairRows];
+};
+
 template <int ST, int LAW, bool FIELDS, bool REC, bool WALLS>
-__global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Args a) {
+__device__ __forceinline__ void step2_body(const Step2Args& a, int strip, int blk,
+                                           PairLds<typename Storage<ST>::real>& sh) {
     using Tr = Storage<ST>;
     using R = typename Tr::real;
     using T = typename Tr::pop_t;
     constexpr bool SH = Tr::shifted;
-    __shared__ R xq1[kPairWaves][6][kTile];   // level n+1, direction (0,1): read by the row above
-    __shared__ R xq3[kPairWaves][6][kTile];   // level n+1, direction (0,-1): read by the row below
-    __shared__ R xh[2][6][kPairRows];         // level n+1 beside the strip: q0 at c0-1, q2 at c0+64
+    auto& xq1 = sh.xq1;
+    auto& xq3 = sh.xq3;
+    auto& xh = sh.xh;
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
     const int64_t n = int64_t(nx) * ny;
-    int strip, blk;
-    pair_block(a.map, remap_tile(blockIdx.x, gridDim.x), strip, blk);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
     const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;
@@ -586,6 +595,43 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Ar
     }
     if (nonfinite || jbad)
         atomicOr(cm.fault, (jbad ? (uint32_t)LBM_FAULT_J : 0u) | (nonfinite ? (uint32_t)LBM_FAULT_NONFINITE : 0u));
+}
+
+template <int ST, int LAW, bool FIELDS, bool REC, bool WALLS>
+__global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_kernel(Step2Args a) {
+    __shared__ PairLds<typename Storage<ST>::real> sh;
+    int strip, blk;
+    pair_block(a.map, remap_tile(blockIdx.x, gridDim.x), strip, blk);
+    step2_body<ST, LAW, FIELDS, REC, WALLS>(a, strip, blk, sh);
+}
+
+// The interior blocks (the periodic code) and the blocks along the walls (the wall code)
+// of a walled grid in one launch, so that the few rim blocks fill the tail of the bulk
+// instead of running as a launch of their own.  Every rim_period-th block of the order is
+// a rim block while they last: each XCD's contiguous share of the order (remap_tile) then
+// holds its share of them.  Each block computes what it computes in its own launch.
+template <int ST, int LAW, bool FIELDS, bool REC>
+__global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_split_kernel(Step2Args a) {
+    __shared__ PairLds<typename Storage<ST>::real> sh;
+    const int b = remap_tile(blockIdx.x, gridDim.x);
+    const int p = a.rim_period;
+    bool rim = false;
+    int i = b;
+    if (b < a.n_rim * p) {
+        const int g = fdiv(b, a.d_rim_period), pos = b - g * p;
+        rim = pos == p - 1;
+        i = rim ? g : g * (p - 1) + pos;
+    } else {
+        i = a.n_rim * (p - 1) + (b - a.n_rim * p);
+    }
+    int strip, blk;
+    if (rim) {
+        pair_block(a.map2, i, strip, blk);
+        step2_body<ST, LAW, FIELDS, REC, true>(a, strip, blk, sh);
+    } else {
+        pair_block(a.map, i, strip, blk);
+        step2_body<ST, LAW, FIELDS, REC, false>(a, strip, blk, sh);
+    }
 }
 
 // Level n+1 -> n+2 at the wall nodes of a two-level step on a grid with walls: one thread
@@ -1057,8 +1103,21 @@ static void step2_launch(const Step2Args& a0, hipStream_t s, bool walls) {
     const PairMap inner = pair_map(nstrip, nblk, s_lo, s_hi, b_lo, b_hi);
     PairMap rim = inner;
     rim.mode = 1;
-    go(inner, false);
-    go(rim, true);
+    const int64_t n_in = pair_map_blocks(inner), n_rim = pair_map_blocks(rim);
+    // FP64 keeps two launches: holding both codes costs its kernel an occupancy step
+    if (ST == LBM_F64_PLAIN || n_rim <= 0) {
+        go(inner, false);
+        go(rim, true);
+        return;
+    }
+    Step2Args a = a0;
+    a.map = inner;
+    a.map2 = rim;
+    a.n_rim = int(n_rim);
+    a.rim_period = int((n_in + n_rim) / n_rim);
+    a.d_rim_period = fast_div(a.rim_period);
+    if constexpr (ST != LBM_F64_PLAIN)
+        hipLaunchKernelGGL((step2_split_kernel<ST, LAW, FIELDS, REC>), dim3(unsigned(n_in + n_rim)), block, 0, s, a);
 }
 
 template <int ST, int LAW>

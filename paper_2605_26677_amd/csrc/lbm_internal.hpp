@@ -191,7 +191,11 @@ struct Step2Args {
     void* record2;                   // U^{n+2} or NULL
     int fold1, fold2;                // accumulator folds after the first / second step
     int nstrip;                      // strips of kPairCols columns (= tiles per row)
-    PairMap map;                     // the workgroups of this launch
+    PairMap map;                     // the workgroups of this launch (the interior ones
+                                     // of a split launch)
+    PairMap map2;                    // split launch: the rim workgroups (wall code)
+    int n_rim, rim_period;           // split launch: rim workgroups, one every rim_period
+    FastDiv d_rim_period;
     double r_np1, r_np2;
 };
 
