@@ -106,13 +106,13 @@ class Solver:
     storage ("f32", "f16", "f64"), edge kinds, uniform or per-node mu, lam and body force."""
 
     # Defaults of advance() and of the checkpointed rollout, from timings on one MI355X
-    # (FP32, log-NH): a captured graph beats eager launches only where the host launch cost
-    # dominates (2.0x single steps, 1.07x pairs at 256^2; 0.92x pairs at 384^2, and a few
-    # microseconds lost per kernel node above); on walled grids the two-level step adds
-    # three latency-bound launches per pair and loses below about 640^2 (256^2: 22.5 against
-    # 15.1 us per level; 768^2: 34.5 against 36.7).
-    GRAPH_MAX_NODES = 320 * 320
-    PAIR_MIN_WALLED_NODES = 640 * 640
+    # (FP32, log-NH, us per level): a captured graph beats eager launches only where the
+    # host launch cost dominates (256^2 periodic pairs 3.42 against 4.44, 384^2 4.37
+    # against 4.52; from 512^2 up a replay adds a few microseconds per kernel node); on
+    # walled grids a pair adds latency-bound launches and loses on small grids (384^2:
+    # 19.9 against 17.8 single; 512^2: 23.9 against 24.6).
+    GRAPH_MAX_NODES = 400 * 400
+    PAIR_MIN_WALLED_NODES = 448 * 448
 
     def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
                  bc=("periodic",) * 4, mu=0.1, lam=0.2, body=None, newton_max_iter=0,
