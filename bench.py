@@ -148,8 +148,8 @@ def time_block(n=1024, steps=2000, start=512):
         sv = Solver(n, n, c=10.0, omega=2.0 - 1.6 / n, material="lognh", storage="f32", mu=0.1, lam=0.3,
                     body=(0.0, -1e-5), bc=("velocity", "traction", "traction", "traction"))
         sv.init(v0, r0=0.0)
-        pairs = mode.endswith("pairs")
-        sv.advance(0, start, ramp=ramp, edges=edges, block=64, fused=pairs)
+        pairs, graph = mode.endswith("pairs"), mode.startswith("graph")
+        sv.advance(0, start, ramp=ramp, edges=edges, block=64, fused=pairs, graph=graph)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -160,7 +160,7 @@ def time_block(n=1024, steps=2000, start=512):
             for k in range(start, start + steps, 2):
                 sv.step2(k, ramp(k + 1), ramp(k + 2), r_n=ramp(k), edges=edges(k), edges_next=edges(k + 1))
         else:
-            sv.advance(start, steps, ramp=ramp, edges=edges, block=64, fused=pairs)
+            sv.advance(start, steps, ramp=ramp, edges=edges, block=64, fused=pairs, graph=True)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
@@ -174,7 +174,8 @@ def time_block(n=1024, steps=2000, start=512):
 
 def time_launch_bound(n=256, steps=4000, block=100):
     """The same step on a small grid where the host launch cost dominates: per-step eager
-    calls against blocks of steps replayed from a captured HIP graph (Solver.advance)."""
+    lbm_step calls against blocks of the same single steps replayed from a captured HIP
+    graph (Solver.advance)."""
     import torch
     from paper_2605_26677_amd.solver import Solver
     v0 = make_inputs(n)
@@ -185,7 +186,7 @@ def time_launch_bound(n=256, steps=4000, block=100):
         for k in range(20):
             sv.step(k)
         if mode == "graph":
-            sv.advance(20, 2 * block, block=block)      # capture outside the timed region
+            sv.advance(20, 2 * block, block=block, fused=False, graph=True)   # capture outside the timed region
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -193,7 +194,7 @@ def time_launch_bound(n=256, steps=4000, block=100):
             for k in range(steps):
                 sv.step(k)
         else:
-            sv.advance(0, steps, block=block)
+            sv.advance(0, steps, block=block, fused=False, graph=True)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
