@@ -437,6 +437,16 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
     R l[4][6], lm[4][6], inc1[4], mu, lam;
     double ps[2] = {0.0, 0.0};
     bool probe = false;
+    // the record of level m - 1 at an inner wave's node, loaded with level m + 1 so that the
+    // load is in flight across the barrier (FP32 compute; in FP64 the four held values
+    // would cost the kernel an occupancy step, so it loads them after the barrier)
+    constexpr bool kPre = ST != LBM_F64_PLAIN;
+    R ft2[4] = {R(0), R(0), R(0), R(0)};
+    if (kPre && w >= 1 && w <= kPairRows) {
+        const R* rec = (const R*)a.rec2 + tile_base(ntile, 6, xc, yr);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ft2[k] = rec[(2 + k) * kTile];
+    }
     if (w < kPairWaves) {
         // lambda^{m+1} -> lambda^m on row r: q0 from x+1 and q2 from x-1 of row r (own
         // lanes shifted, the end lanes from the columns beside the strip), q1 from row r+1,
@@ -528,12 +538,13 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
             l[0][k] = lane == kTile - 1 ? e0 : l[0][k];
             l[2][k] = lane == 0 ? e2 : l[2][k];
         }
-        const R* rec = (const R*)a.rec2 + tile_base(ntile, 6, xc, yr);
-        R ft[4];
+        if constexpr (!kPre) {
+            const R* rec = (const R*)a.rec2 + tile_base(ntile, 6, xc, yr);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) ft[k] = rec[(2 + k) * kTile];
+            for (int k = 0; k < 4; ++k) ft2[k] = rec[(2 + k) * kTile];
+        }
         R out[4][6], inc2[4];
-        adj_node<R, LAW>(cm, l, ft, mu, lam, R(a.r2), gpar, gbody, out, inc2);
+        adj_node<R, LAW>(cm, l, ft2, mu, lam, R(a.r2), gpar, gbody, out, inc2);
         if (probe) {
             // the probe source of level m - 1 (same node, same weight as level m)
 #pragma unroll

@@ -338,10 +338,11 @@ __device__ __forceinline__ void pull_node(const T* __restrict__ src, int ntile, 
 
 // The per-node tail of a two-level update at output node (x, y): the displacement
 // quadrature over both levels (eq:trapezoid-u) with the accumulator updates and folds of two
-// single steps, and the records of both levels.
+// single steps, and the records of both levels.  spre: the node's block sums S, loaded
+// earlier by the caller (shifted storages), or NULL to load them here.
 template <int ST, bool REC>
 __device__ __forceinline__ void pair_tail(const Step2Args& a, int x, int y, const typename Storage<ST>::real U1[6],
-                                          const typename Storage<ST>::real U2[6]) {
+                                          const typename Storage<ST>::real U2[6], const float* spre) {
     using R = typename Storage<ST>::real;
     constexpr bool SH = Storage<ST>::shifted;
     const Common& cm = a.cm;
@@ -357,7 +358,7 @@ __device__ __forceinline__ void pair_tail(const Step2Args& a, int x, int y, cons
         const UstarRefs rf = ustar_refs(a.ustar, ntile, cm.ny, x, y);
 #pragma unroll
         for (int cpt = 0; cpt < 2; ++cpt) {
-            float sn = rf.S[cpt * kTile] + float(dt * U1[cpt]);
+            float sn = (spre ? spre[cpt] : rf.S[cpt * kTile]) + float(dt * U1[cpt]);
             bool moved = false;
             double u = 0.0;
             if (a.fold1) {
@@ -468,6 +469,16 @@ __device__ __forceinline__ void step2_body(const Step2Args& a, int strip, int bl
     R f1[4][6], U1[6], g[4][6], mu, lam;
     R B2[2];                                  // r_np2 b(X) of this wave's node (level n+2)
     bool nonfinite = false, jbad = false;
+    // the displacement block sums S of an inner wave's output node, loaded with level n so
+    // that the load is in flight across the barrier (shifted storages)
+    float spre[2] = {0.0f, 0.0f};
+    if constexpr (ST != LBM_F64_PLAIN) {
+        if (a.ustar && w >= 1 && w <= kPairRows && r < ny) {
+            const float* S = ustar_refs(a.ustar, ntile, ny, xg, r).S;
+            spre[0] = S[0];
+            spre[1] = S[kTile];
+        }
+    }
     if (w < kPairWaves) {
         // level n -> n+1 on row r: q0 from x-1 and q2 from x+1 of row r (own lanes shifted,
         // the two end lanes from the columns beside the strip), q1 from row r-1, q3 from r+1
@@ -587,7 +598,7 @@ __device__ __forceinline__ void step2_body(const Step2Args& a, int strip, int bl
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) store_stream(dst + ob + (6 * q + k) * kTile, to_storage<T>(f2[q][k]));
-            pair_tail<ST, REC>(a, xo, r, U1, U2);
+            pair_tail<ST, REC>(a, xo, r, U1, U2, ST != LBM_F64_PLAIN && a.ustar ? spre : nullptr);
 #pragma unroll
             for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U2[k]);
             jbad |= J2 <= R(0);
@@ -699,7 +710,7 @@ __global__ void __launch_bounds__(kBlock) step2_wall_kernel(Step2Args a) {
     const R* u1 = (const R*)wl.u1 + (int64_t(off[e]) + s) * 6;
 #pragma unroll
     for (int k = 0; k < 6; ++k) U1[k] = u1[k];
-    pair_tail<ST, REC>(a, x, y, U1, U2);
+    pair_tail<ST, REC>(a, x, y, U1, U2, nullptr);
     bool nonfinite = false;
 #pragma unroll
     for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U2[k]);
