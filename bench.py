@@ -207,12 +207,15 @@ def time_launch_bound(n=256, steps=4000, block=100):
     return out
 
 
-def time_forward_adjoint(n, steps, K, nprobe=16):
+def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32"):
     """Forward + checkpointed adjoint of the probe-displacement loss with per-node mu, lam
-    (log-normal, median 0.1 / 0.2, sigma_log 0.3, correlation length 32), FP32 storage."""
+    (log-normal, median 0.1 / 0.2, sigma_log 0.3, correlation length 32), every-K
+    checkpoints on the device."""
     import torch
     import lbm_inputs as li
     from paper_2605_26677_amd.rollout import RolloutConfig, rollout
+    torch.cuda.empty_cache()                  # the blocks of an earlier rollout
+    torch.cuda.reset_peak_memory_stats()
     mu = torch.tensor(li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0), device="cuda", requires_grad=True)
     lam = torch.tensor(li.lognormal_field(n, n, 402, 0.2, 0.3, 32.0), device="cuda", requires_grad=True)
     body = torch.zeros((2, n, n), dtype=torch.float64, device="cuda", requires_grad=True)
@@ -221,7 +224,7 @@ def time_forward_adjoint(n, steps, K, nprobe=16):
     probes = torch.tensor(ys * n + xs, dtype=torch.int64)
     # c from the audit bound sqrt(lam_max + 2 mu_max) / c <= 1/2 with margin
     c = float(np.ceil(2.0 * np.sqrt(float(lam.max()) + 2 * float(mu.max())) * 1.1 * 4) / 4)
-    cfg = RolloutConfig(nx=n, ny=n, c=c, omega=2.0, nsteps=steps, probes=probes, storage="f32",
+    cfg = RolloutConfig(nx=n, ny=n, c=c, omega=2.0, nsteps=steps, probes=probes, storage=storage,
                         checkpoint_every=K)
     # one untimed rollout first, so that the timed one reuses the allocator's blocks
     (rollout(mu, lam, body, v0, cfg) ** 2).sum().backward()
@@ -238,8 +241,12 @@ def time_forward_adjoint(n, steps, K, nprobe=16):
     t_f, t_b = e0.elapsed_time(e1), e1.elapsed_time(e2)
     mem = torch.cuda.max_memory_allocated() / 2 ** 30
     ok = all(torch.isfinite(t.grad).all().item() for t in (mu, lam, v0))
-    return dict(ms_fwd=t_f, ms_bwd=t_b, mlups=n * n * steps / ((t_f + t_b) * 1e-3) / 1e6,
-                bwd_over_fwd=t_b / t_f, peak_mem_GiB=mem, grads_finite=ok, steps=steps, K=K, c=c)
+    out = dict(ms_fwd=t_f, ms_bwd=t_b, mlups=n * n * steps / ((t_f + t_b) * 1e-3) / 1e6,
+               bwd_over_fwd=t_b / t_f, peak_mem_GiB=mem, grads_finite=ok, steps=steps, K=K, c=c,
+               storage=storage)
+    del u, mu, lam, body, v0
+    torch.cuda.empty_cache()
+    return out
 
 
 def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0, host_gib=0.0):
@@ -434,6 +441,12 @@ def main():
         log(f"bench: forward + adjoint, {args.adjoint_steps} steps, checkpoint every {args.adjoint_every}")
         res["fwd_adj_f32"] = time_forward_adjoint(n, args.adjoint_steps, args.adjoint_every)
         log(f"bench: fwd+adj: {res['fwd_adj_f32']}")
+        # FP64: half the levels and half the segment length, so that the every-K schedule
+        # (the same levels per segment) fits the 268 GiB of HBM (212 GiB modelled)
+        log(f"bench: forward + adjoint FP64, {args.adjoint_steps // 2} steps, "
+            f"checkpoint every {args.adjoint_every // 2}")
+        res["fwd_adj_f64"] = time_forward_adjoint(n, args.adjoint_steps // 2, args.adjoint_every // 2, storage="f64")
+        log(f"bench: fwd+adj f64: {res['fwd_adj_f64']}")
     log("bench: copy ceiling")
     copy_gbs = copy_ceiling()
     main_storage = "f32" if "f32" in only else only[0]
