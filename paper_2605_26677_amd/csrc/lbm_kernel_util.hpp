@@ -42,19 +42,7 @@ __device__ __forceinline__ R edge_value(const EdgeData& ed, int e, int comp, int
     return f ? R(f[comp * L + s]) : R(ed.value[e][comp]);
 }
 
-// The unscaled body acceleration b(X) of node idx (the field, or the uniform value);
-// body_at(r) is r times it.
-template <bool FIELDS>
-__device__ __forceinline__ void body_raw(const Common& cm, int idx, int64_t n, double& b0, double& b1) {
-    if (FIELDS && cm.body) {
-        b0 = double(cm.body[idx]);
-        b1 = double(cm.body[n + idx]);
-    } else {
-        b0 = cm.b0[0];
-        b1 = cm.b0[1];
-    }
-}
-
+// r b(X) of node idx: r times the body field, or the uniform value.
 template <bool FIELDS>
 __device__ __forceinline__ void body_at(const Common& cm, int idx, int64_t n, double r, double& b0, double& b1) {
     if (FIELDS && cm.body) {
