@@ -184,16 +184,14 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
 // Each link stages (tbar_1, tbar_2, dL/dmu, dL/dlam) in its own slot of the staging
 // buffer; the mu and lam terms reach the gradients in the scatter stage, which gives a
 // corner node the terms of its edges in edge order.
-template <int ST, int LAW, bool FIELDS>
-__global__ void __launch_bounds__(kTracWin) adj_traction_kernel(AdjArgs a) {
+template <int ST, int LAW, bool FIELDS, int A>
+__device__ __forceinline__ void adj_traction_solve(const AdjArgs& a, int e) {
     using R = typename Storage<ST>::real;
     const Common& cm = a.cm;
-    int e = 0;
-    while (e < 3 && int(blockIdx.x) >= a.eblk[e + 1]) ++e;
     const EdgeGeom G = edge_geom(e);
-    const int L = (G.A == 0) ? cm.ny : cm.nx;
-    const bool per_t = (G.A == 0) ? cm.periodic_y : cm.periodic_x;
-    const int A = G.A, Bx = 1 - G.A;
+    const int L = (A == 0) ? cm.ny : cm.nx;
+    const bool per_t = (A == 0) ? cm.periodic_y : cm.periodic_x;
+    constexpr int Bx = 1 - A;
     const int lane = int(threadIdx.x);
     const int s = (int(blockIdx.x) - a.eblk[e]) * kTracOut - 2 + lane;   // this lane's position
     const int64_t n = int64_t(cm.nx) * cm.ny;
@@ -259,7 +257,8 @@ __global__ void __launch_bounds__(kTracWin) adj_traction_kernel(AdjArgs a) {
     const int id0 = n0.y * cm.nx + n0.x;
     R mu, lam;
     params_at<FIELDS, R>(cm, id0, mu, lam);
-    newton_column<R, LAW, true>(A, R(G.NA), tang, Tv, mu, lam, law_consts<R>(cm), acol, cm.newton_max_iter, R(cm.newton_tol));
+    newton_column<R, LAW, true, A>(R(G.NA), tang, Tv, mu, lam, law_consts<R>(cm), acol, cm.newton_max_iter,
+                                   R(cm.newton_tol));
     R f[4];
     f[A] = acol[0]; f[2 + A] = acol[1];
     f[Bx] = tang[0]; f[2 + Bx] = tang[1];
@@ -287,30 +286,36 @@ __global__ void __launch_bounds__(kTracWin) adj_traction_kernel(AdjArgs a) {
         gm = -NA * (y0 * Pm[A] + y1 * Pm[2 + A]);
         gl = -NA * (y0 * Pl[A] + y1 * Pl[2 + A]);
     }
-    int off[4], len[4];
-    edge_offsets(cm.nx, cm.ny, off, len);
-    R* aux = (R*)a.aux + 4 * (int64_t)(off[e] + s);
+    R* aux = (R*)a.aux + 4 * (int64_t)(edge_off(cm.nx, cm.ny, e) + s);
     aux[0] = tbar[0];
     aux[1] = tbar[1];
     aux[2] = gm;
     aux[3] = gl;
 }
 
+// The edge's normal axis is a template parameter of the solve (fixed per edge, so per
+// wavefront), so F, the tangent and the per-node vectors index with constants.
+template <int ST, int LAW, bool FIELDS>
+__global__ void __launch_bounds__(kTracWin) adj_traction_kernel(AdjArgs a) {
+    int e = 0;
+    while (e < 3 && int(blockIdx.x) >= a.eblk[e + 1]) ++e;
+    if (e == LBM_XMIN || e == LBM_XMAX) adj_traction_solve<ST, LAW, FIELDS, 0>(a, e);
+    else adj_traction_solve<ST, LAW, FIELDS, 1>(a, e);
+}
+
 // Traction edges, stage 2: transpose of the extrapolation 3/2 G(X0) - 1/2 G(X1) and of
 // G = F_{.B} + (dt/2) d_B v for the node at position s of row r of edge e, giving dL/dU^m
 // there; it enters lambda^m_q for every q and the body gradient.  With r = 0 the mu and lam
 // terms of the link's Newton solve (stage 1) are added too.
-template <typename R>
-__device__ void adj_scatter_edge(const AdjArgs& a, int e, int r, int s) {
+template <typename R, int AX>
+__device__ __forceinline__ void adj_scatter_edge(const AdjArgs& a, int e, int r, int s) {
     const Common& cm = a.cm;
     const EdgeGeom G = edge_geom(e);
-    const int L = (G.A == 0) ? cm.ny : cm.nx;
-    const bool per_t = (G.A == 0) ? cm.periodic_y : cm.periodic_x;
-    const int Bx = 1 - G.A;
+    const int L = (AX == 0) ? cm.ny : cm.nx;
+    const bool per_t = (AX == 0) ? cm.periodic_y : cm.periodic_x;
+    constexpr int Bx = 1 - AX;
     const int64_t n = int64_t(cm.nx) * cm.ny;
-    int off[4], len[4];
-    edge_offsets(cm.nx, cm.ny, off, len);
-    const R* aux = (const R*)a.aux + 4 * (int64_t)off[e];
+    const R* aux = (const R*)a.aux + 4 * (int64_t)edge_off(cm.nx, cm.ny, e);
     const R wr = (r == 0) ? R(1.5) : R(-0.5);
     const R hdt = R(0.5 * cm.dt);
     const R inv2h = R(1.0 / (2.0 * cm.dx));
@@ -351,15 +356,17 @@ __global__ void __launch_bounds__(kTile) adj_traction_scatter_kernel(AdjArgs a) 
     if (t >= 2 * L) return;
     const int r = t / L, s = t - r * L;
     const XY nd = edge_node(edge_geom(e), cm.nx, cm.ny, r, s);
-    // the traction edges whose two rows hold this node, in edge order
-    int ee[4], er[4], es[4], ne = 0;
+    // the traction edges whose two rows hold this node: at most one along x and one along
+    // y (nx, ny >= 4), the x edge first in edge order
     const int x = nd.x, y = nd.y;
-    if (cm.bc[LBM_XMIN] == LBM_TRACTION && x <= 1) { ee[ne] = LBM_XMIN; er[ne] = x; es[ne] = y; ++ne; }
-    if (cm.bc[LBM_XMAX] == LBM_TRACTION && x >= cm.nx - 2) { ee[ne] = LBM_XMAX; er[ne] = cm.nx - 1 - x; es[ne] = y; ++ne; }
-    if (cm.bc[LBM_YMIN] == LBM_TRACTION && y <= 1) { ee[ne] = LBM_YMIN; er[ne] = y; es[ne] = x; ++ne; }
-    if (cm.bc[LBM_YMAX] == LBM_TRACTION && y >= cm.ny - 2) { ee[ne] = LBM_YMAX; er[ne] = cm.ny - 1 - y; es[ne] = x; ++ne; }
-    if (ne == 0 || ee[0] != e) return;
-    for (int i = 0; i < ne; ++i) adj_scatter_edge<R>(a, ee[i], er[i], es[i]);
+    int ex = -1, rx = 0, ey = -1, ry = 0;
+    if (cm.bc[LBM_XMIN] == LBM_TRACTION && x <= 1) { ex = LBM_XMIN; rx = x; }
+    else if (cm.bc[LBM_XMAX] == LBM_TRACTION && x >= cm.nx - 2) { ex = LBM_XMAX; rx = cm.nx - 1 - x; }
+    if (cm.bc[LBM_YMIN] == LBM_TRACTION && y <= 1) { ey = LBM_YMIN; ry = y; }
+    else if (cm.bc[LBM_YMAX] == LBM_TRACTION && y >= cm.ny - 2) { ey = LBM_YMAX; ry = cm.ny - 1 - y; }
+    if ((ex >= 0 ? ex : ey) != e) return;
+    if (ex >= 0) adj_scatter_edge<R, 0>(a, ex, rx, y);
+    if (ey >= 0) adj_scatter_edge<R, 1>(a, ey, ry, x);
 }
 
 // Probe source of the displacement loss at level m: u^N = u0 - (dt/2) v0 + dt sum_{m<N} v^m

@@ -31,19 +31,20 @@ namespace lbm {
 // an open edge: never more than two positions away) from the neighbouring lanes.  Each
 // node is thus read once per wavefront instead of once per stencil use: on the edges
 // normal to x every lane reads its own tile row, 24 separate cache lines per node.
-template <int ST, int LAW, bool FIELDS, bool LINES>
-__global__ void __launch_bounds__(kTracWin) traction_kernel(TractionArgs a) {
+// The edge's normal axis AX is a template parameter (fixed per edge, so per wavefront):
+// with the axis known, F, the tangent and the per-node vectors index with constants and
+// stay in registers.
+template <int ST, int LAW, bool FIELDS, bool LINES, int AX>
+__device__ __forceinline__ void traction_solve(const TractionArgs& a, int e) {
     using Tr = Storage<ST>;
     using R = typename Tr::real;
     using T = typename Tr::pop_t;
     constexpr bool SH = Tr::shifted;
     const Common& cm = a.cm;
-    int e = 0;
-    while (e < 3 && int(blockIdx.x) >= a.eblk[e + 1]) ++e;
     const EdgeGeom G = edge_geom(e);
-    const int L = (G.A == 0) ? cm.ny : cm.nx;
-    const bool per_t = (G.A == 0) ? cm.periodic_y : cm.periodic_x;
-    const int Bx = 1 - G.A;
+    const int L = (AX == 0) ? cm.ny : cm.nx;
+    const bool per_t = (AX == 0) ? cm.periodic_y : cm.periodic_x;
+    constexpr int Bx = 1 - AX;
     const int lane = int(threadIdx.x);
     const int s = (int(blockIdx.x) - a.eblk[e]) * kTracOut - 2 + lane;   // this lane's position
     const T* pop = (const T*)a.pop;
@@ -107,7 +108,7 @@ __global__ void __launch_bounds__(kTracWin) traction_kernel(TractionArgs a) {
             for (int j = 0; j < 3; ++j) dv += R(sten.w[j]) * Vs[r][j][k];
             dv *= inv2h;
             Ghat[r][k] = Uw[r][2 + 2 * k + Bx] + hdt * dv;
-            Fa[r][k] = Uw[r][2 + 2 * k + G.A];
+            Fa[r][k] = Uw[r][2 + 2 * k + AX];
         }
     }
     R tang[2], acol[2], Tv[2];
@@ -119,16 +120,24 @@ __global__ void __launch_bounds__(kTracWin) traction_kernel(TractionArgs a) {
     const XY n0 = edge_node(G, cm.nx, cm.ny, 0, s);
     R mu, lam;
     params_at<FIELDS, R>(cm, n0.y * cm.nx + n0.x, mu, lam);
-    const bool ok = newton_column<R, LAW, SH>(G.A, R(G.NA), tang, Tv, mu, lam, law_consts<R>(cm), acol,
-                                             cm.newton_max_iter, R(cm.newton_tol));
+    const bool ok = newton_column<R, LAW, SH, AX>(R(G.NA), tang, Tv, mu, lam, law_consts<R>(cm), acol,
+                                                 cm.newton_max_iter, R(cm.newton_tol));
     if (!ok) atomicOr(cm.fault, (uint32_t)LBM_FAULT_NEWTON);
     int off[4], len[4];
     edge_offsets(cm.nx, cm.ny, off, len);
     R* aux = (R*)a.aux + 4 * (int64_t)(off[e] + s);
     for (int k = 0; k < 2; ++k) {
-        aux[2 * k + G.A] = acol[k];
+        aux[2 * k + AX] = acol[k];
         aux[2 * k + Bx] = tang[k];
     }
+}
+
+template <int ST, int LAW, bool FIELDS, bool LINES>
+__global__ void __launch_bounds__(kTracWin) traction_kernel(TractionArgs a) {
+    int e = 0;
+    while (e < 3 && int(blockIdx.x) >= a.eblk[e + 1]) ++e;
+    if (e == LBM_XMIN || e == LBM_XMAX) traction_solve<ST, LAW, FIELDS, LINES, 0>(a, e);
+    else traction_solve<ST, LAW, FIELDS, LINES, 1>(a, e);
 }
 
 // ---------------------------------------------------------------- the fused step
@@ -659,20 +668,21 @@ __global__ void __launch_bounds__(kBlock) step2_wall_kernel(Step2Args a) {
     constexpr bool SH = Tr::shifted;
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny;
-    int off[4], len[4];
-    edge_offsets(nx, ny, off, len);
+    // the edge of this link slot (selected without arrays indexed by a lane-dependent edge,
+    // which would go to scratch memory)
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= off[LBM_YMAX] + len[LBM_YMAX]) return;
-    int e = LBM_YMAX;
-    while (e > 0 && t < off[e]) --e;
-    if (cm.bc[e] == LBM_PERIODIC) return;
-    const int s = t - off[e];
+    if (t >= 2 * ny + 2 * nx) return;
+    const int e = t < ny ? LBM_XMIN : t < 2 * ny ? LBM_XMAX : t < 2 * ny + nx ? LBM_YMIN : LBM_YMAX;
+    const int bce = e == LBM_XMIN ? cm.bc[LBM_XMIN] : e == LBM_XMAX ? cm.bc[LBM_XMAX]
+                  : e == LBM_YMIN ? cm.bc[LBM_YMIN] : cm.bc[LBM_YMAX];
+    if (bce == LBM_PERIODIC) return;
+    const int s = t - edge_off(nx, ny, e);
     const XY nd = edge_node(edge_geom(e), nx, ny, 0, s);
     const int x = nd.x, y = nd.y;
     const bool on[4] = {!cm.periodic_x && x == 0, !cm.periodic_x && x == nx - 1,
                         !cm.periodic_y && y == 0, !cm.periodic_y && y == ny - 1};
-    for (int e0 = 0; e0 < e; ++e0)
-        if (on[e0]) return;                      // a corner taken by an earlier edge
+    // a corner taken by an earlier edge
+    if ((e > LBM_XMIN && on[LBM_XMIN]) || (e > LBM_XMAX && on[LBM_XMAX]) || (e > LBM_YMIN && on[LBM_YMIN])) return;
     const WallLines wl = wall_lines(a.aux, nx, ny);
     const T* lines = (const T*)wl.lines;
     const T* ownp = lines + line_slot(nx, ny, e, 0, s) * 24;
@@ -707,7 +717,7 @@ __global__ void __launch_bounds__(kBlock) step2_wall_kernel(Step2Args a) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) store_stream(dst + (6 * q + k) * kTile, to_storage<T>(f2[q][k]));
     R U1[6];
-    const R* u1 = (const R*)wl.u1 + (int64_t(off[e]) + s) * 6;
+    const R* u1 = (const R*)wl.u1 + (int64_t(edge_off(nx, ny, e)) + s) * 6;
 #pragma unroll
     for (int k = 0; k < 6; ++k) U1[k] = u1[k];
     pair_tail<ST, REC>(a, x, y, U1, U2, nullptr);

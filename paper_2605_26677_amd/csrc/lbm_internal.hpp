@@ -21,6 +21,15 @@ __host__ __device__ inline void edge_offsets(int nx, int ny, int off[4], int len
     off[LBM_XMIN] = 0; off[LBM_XMAX] = ny; off[LBM_YMIN] = 2 * ny; off[LBM_YMAX] = 2 * ny + nx;
 }
 
+// The same for one edge, without an array: where e differs between the lanes of a
+// wavefront, an array indexed by e would be placed in scratch memory.
+__host__ __device__ inline int edge_off(int nx, int ny, int e) {
+    return e == LBM_XMIN ? 0 : e == LBM_XMAX ? ny : e == LBM_YMIN ? 2 * ny : 2 * ny + nx;
+}
+__host__ __device__ inline int edge_len(int nx, int ny, int e) {
+    return (e == LBM_XMIN || e == LBM_XMAX) ? ny : nx;
+}
+
 struct EdgeData {
     double value[4][2];
     const double* field[4];

@@ -105,11 +105,13 @@ __device__ __forceinline__ void recover_node(const T* pop, int ntile, int x, int
 // N_A P_iA(F^b) = T_i (Sec. 3.6, eq:neumann-boundary-rule).  Newton steps
 // delta = -J^{-1} r with J_ik = N_A C_iAkA; step lengths 1, 1/2, ..., 2^-10, the first with
 // det F^b > 0 and a smaller |r| is taken; stop at |r| <= tol (|T| + mu |F^b - I|), when no
-// step length is accepted, or after max_iter updates.  Returns false on failure.
-template <typename R, int LAW, bool SH>
-__device__ bool newton_column(int A, R NA, const R tang[2], const R T[2], R mu, R lam,
+// step length is accepted, or after max_iter updates.  Returns false on failure.  The axis
+// A is a template parameter: indexed at run time, F and the tangent would live in scratch
+// memory, one round trip per access inside the iteration.
+template <typename R, int LAW, bool SH, int A>
+__device__ bool newton_column(R NA, const R tang[2], const R T[2], R mu, R lam,
                               const LawK<R>& lk, R a[2], int max_iter, R tol) {
-    const int B = 1 - A;
+    constexpr int B = 1 - A;
     auto assemble = [&](const R ac[2], R f[4]) {
         f[A] = ac[0]; f[2 + A] = ac[1];
         f[B] = tang[0]; f[2 + B] = tang[1];
@@ -224,9 +226,7 @@ __host__ __device__ inline WallLines wall_lines(void* aux, int nx, int ny) {
 }
 
 __host__ __device__ inline int64_t line_slot(int nx, int ny, int e, int r, int s) {
-    int off[4], len[4];
-    edge_offsets(nx, ny, off, len);
-    return 2 * int64_t(off[e]) + int64_t(r) * len[e] + s;
+    return 2 * int64_t(edge_off(nx, ny, e)) + int64_t(r) * edge_len(nx, ny, e) + s;
 }
 
 // A line of a wall edge that holds node (x, y): the first of XMIN, XMAX, YMIN, YMAX whose
