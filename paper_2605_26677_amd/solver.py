@@ -110,7 +110,7 @@ class Solver:
     # host launch cost dominates (256^2 periodic pairs 3.42 against 4.44, 384^2 4.37
     # against 4.52; from 512^2 up a replay adds a few microseconds per kernel node); on
     # walled grids a pair adds latency-bound launches and loses on small grids (384^2:
-    # 19.9 against 17.8 single; 512^2: 23.9 against 24.6).
+    # 17.8 against 16.3 single; 512^2: 22.3 against 22.8).
     GRAPH_MAX_NODES = 400 * 400
     PAIR_MIN_WALLED_NODES = 448 * 448
 
