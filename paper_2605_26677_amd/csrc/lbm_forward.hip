@@ -661,7 +661,7 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) step2_split_kernel(S
 // is that of step_kernel at a wall node (collide_node, wall_link), the tail that of the
 // two-level kernel (pair_tail).
 template <int ST, int LAW, bool FIELDS, bool REC>
-__global__ void __launch_bounds__(kBlock) step2_wall_kernel(Step2Args a) {
+__global__ void __launch_bounds__(kTile) step2_wall_kernel(Step2Args a) {
     using Tr = Storage<ST>;
     using R = typename Tr::real;
     using T = typename Tr::pop_t;
@@ -1149,8 +1149,10 @@ static hipError_t step2_st_law(const Step2Args& a, hipStream_t s) {
     // plain kernel about a tenth of its speed
     const bool rec = a.record1 || a.record2;
     if (a.wall_pass) {
+        // one wavefront per workgroup: the pass is latency-bound, so its few thousand
+        // links are spread over as many compute units as there are wavefronts
         const int links = 2 * a.cm.nx + 2 * a.cm.ny;
-        const dim3 grid(nblocks(links)), block(kBlock);
+        const dim3 grid(unsigned((links + kTile - 1) / kTile)), block(kTile);
         if (fields) {
             if (rec) hipLaunchKernelGGL((step2_wall_kernel<ST, LAW, true, true>), grid, block, 0, s, a);
             else hipLaunchKernelGGL((step2_wall_kernel<ST, LAW, true, false>), grid, block, 0, s, a);

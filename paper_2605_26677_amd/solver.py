@@ -110,9 +110,9 @@ class Solver:
     # host launch cost dominates (256^2 periodic pairs 3.42 against 4.44, 384^2 4.37
     # against 4.52; from 512^2 up a replay adds a few microseconds per kernel node); on
     # walled grids a pair adds latency-bound launches and loses on small grids (384^2:
-    # 17.8 against 16.3 single; 512^2: 22.3 against 22.8).
+    # 16.2 against 15.6 single; 512^2: 20.4 against 22.9).
     GRAPH_MAX_NODES = 400 * 400
-    PAIR_MIN_WALLED_NODES = 448 * 448
+    PAIR_MIN_WALLED_NODES = 416 * 416
 
     def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
                  bc=("periodic",) * 4, mu=0.1, lam=0.2, body=None, newton_max_iter=0,
