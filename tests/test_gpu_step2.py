@@ -222,10 +222,12 @@ def test_step2_walls_bitwise_equals_two_steps(kind, nx, ny, storage):
         _walls_pair_vs_single(WALL_KINDS[kind], nx, ny, storage, fields, start, pairs=10)
 
 
-def test_step2_walls_bitwise_wide_grid():
+@pytest.mark.parametrize("storage,records", [("f32", False), ("f32", True), ("f16", True)])
+def test_step2_walls_bitwise_wide_grid(storage, records):
     """A walled grid whose interior spans more than one chunk of strips (41 strips, 39 of
-    them interior: 32 + 7)."""
-    _walls_pair_vs_single(WALL_KINDS["block"], 2600, 40, "f32", True, 1, pairs=3)
+    them interior: 32 + 7): interior and rim blocks in one launch, with per-node fields,
+    and with the records of both levels (as the checkpointed replays write them)."""
+    _walls_pair_vs_single(WALL_KINDS["block"], 2600, 40, storage, True, 1, pairs=3, records=records)
 
 
 @pytest.mark.parametrize("law", ["svk", "gent", "nh"])
