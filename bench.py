@@ -379,6 +379,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--adjoint-every", type=int, default=50)
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (copy + 20 f32 steps)")
+    ap.add_argument("--block", action="store_true",
+                    help="only the walled 1024^2 block (single steps and pairs; separate JSON line)")
     ap.add_argument("--adjoint-at-scale", action="store_true",
                     help="the 4096^2 adjoint workload under a 64 GiB checkpoint budget (separate JSON line)")
     ap.add_argument("--scale-size", type=int, default=4096)
@@ -396,6 +398,9 @@ def main():
     n = args.size
     if args.profile:
         profile_run(n, 20)
+        return
+    if args.block:
+        print(json.dumps({"block_1024_walls": time_block()}), flush=True)
         return
     if args.adjoint_at_scale:
         r = adjoint_at_scale(args.scale_size, args.scale_steps, args.scale_budget_gib, args.scale_fd_dirs,
