@@ -194,7 +194,6 @@ __device__ __forceinline__ void adj_traction_solve(const AdjArgs& a, int e) {
     constexpr int Bx = 1 - A;
     const int lane = int(threadIdx.x);
     const int s = (int(blockIdx.x) - a.eblk[e]) * kTracOut - 2 + lane;   // this lane's position
-    const int64_t n = int64_t(cm.nx) * cm.ny;
     const R* rec = (const R*)a.record;
     const R hdt = R(0.5 * cm.dt);
     const R inv2h = R(1.0 / (2.0 * cm.dx));
