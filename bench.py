@@ -37,7 +37,8 @@ BYTES_PER_LU_PAIR = {"f32": 96 + 96 + 16 + 32 / 8, "f16": 48 + 48 + 16 + 32 / 8,
 
 PROFILE_PMC = {"step": os.path.join(ROOT, "profiles", "step_f32_lognh_periodic_8192_pmc.txt"),
                "step2": os.path.join(ROOT, "profiles", "step2_f32_lognh_periodic_8192_pmc.txt")}
-STEP_SOURCES = ("lbm_forward.hip", "lbm_device.hpp", "lbm_kernel_util.hpp", "lbm_internal.hpp")
+STEP_SOURCES = ("lbm_forward.hip", "lbm_pair.hip", "lbm_collide.hpp", "lbm_device.hpp", "lbm_kernel_util.hpp",
+                "lbm_internal.hpp")
 
 
 def step_source_hash():
