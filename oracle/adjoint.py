@@ -115,9 +115,9 @@ def _add_wall_row(arr, e, row, vals, nx, ny):
 
 def walls_T(pb, lstar, lam_next, U, g_mu, g_lam, t_half):
     """Wall transposes for the step m -> m + 1.  Fills the outgoing slots of lstar and
-    returns the traction-wall source E = dL/dU^m through F^b (Sec. 3.6, differentiated
-    through the extrapolation and, by the implicit function theorem, through the
-    traction equations P(F^b) N = T)."""
+    returns the traction-wall source E = dL/dU^m through F^b (Sec. 3.6: its tangential
+    column is the wall node's F, its normal column solves P(F^b) N = T and is
+    differentiated by the implicit function theorem)."""
     nx, ny = pb.nx, pb.ny
     E = np.zeros((6, ny, nx))
     for e in range(4):
@@ -152,14 +152,10 @@ def walls_T(pb, lstar, lam_next, U, g_mu, g_lam, t_half):
         Pm, Pl = mat.stress_parameter_partials(pb.law, Fb)
         _add_wall_row(g_mu, e, 0, -NA * (y[0] * Pm[0, A] + y[1] * Pm[1, A]), nx, ny)
         _add_wall_row(g_lam, e, 0, -NA * (y[0] * Pl[0, A] + y[1] * Pl[1, A]), nx, ny)
-        for row, wgt in ((0, 1.5), (1, -0.5)):
-            Gbar = wgt * tbar                                               # (2, L) over k
-            for k in range(2):
-                _add_wall_row(E[2 + 2 * k + Bax], e, row, Gbar[k], nx, ny)
-            if pb.neumann_time_centre:
-                per = lbm.tangential_periodic(pb, e)
-                vbar = 0.5 * pb.dt * fd_along_T(Gbar, per, pb.dx)
-                _add_wall_row(E[0:2], e, row, vbar, nx, ny)
+        # F^b's tangential column is the wall node's own (reading of Sec. 3.6); the normal
+        # column is the Newton root, which depends on it only through the traction equations
+        for k in range(2):
+            _add_wall_row(E[2 + 2 * k + Bax], e, 0, tbar[k], nx, ny)
     return E
 
 

@@ -10,11 +10,14 @@ p_R(t) = 2 p0 / (sqrt(3 s) pi^(1/4)) (1 - z^2) exp(-z^2 / 2), z = (t - t0) / s, 
 (eq:nh-model) with mu = 1, nu = 0.2 (lam = 2 mu nu / (1 - 2 nu)); c = 10, tau = 1/omega =
 0.5025; second-order initialisation from rest.
 
-Reading of the taper w(Y) (the paper says only that it is smooth, vanishes over eight
-lattice nodes near the loaded-end corners and is normalised to preserve the resultant):
-w_b = sin^2(pi (d + 1/2) / 16) for the node at distance d < 8 (in nodes) from the nearer
-corner, 1 elsewhere, then scaled so that sum_b w_b dx = 1 (the resultant of T equals
-p_R times the edge length).
+Reading of the taper w(Y) (Sec. 5.4 asks only for a smooth factor that rises from zero over
+the eight nodes next to each loaded-end corner, scaled so the total load is unchanged):
+w_b = sin^2(pi d / 14) for the node at distance d = 0 .. 7 (in nodes) from the nearer
+corner (zero on the corner node, one from the eighth node on), 1 elsewhere, then scaled so
+that sum_b w_b dx = 1 (the resultant of T equals p_R times the edge length).  With this
+taper and the traction reading of oracle.lbm the run reproduces the four values Sec. 5.4
+prints for t = 12: J in [0.949, 1.043], max |u_y| on the loaded end 1.54e-2 and max |u|
+over the beam 2.81e-2.
 """
 import numpy as np
 
@@ -37,7 +40,7 @@ def ricker(t):
 
 def taper(ny=NY, width=8):
     d = np.minimum(np.arange(ny), ny - 1 - np.arange(ny))
-    w = np.where(d < width, np.sin(np.pi * (d + 0.5) / (2 * width)) ** 2, 1.0)
+    w = np.where(d < width, np.sin(np.pi * d / (2 * (width - 1))) ** 2, 1.0)
     dx = HEIGHT / ny
     return w / (w.sum() * dx)
 
@@ -54,24 +57,15 @@ def problem(law="nh"):
     return lbm.Problem(nx=NX, ny=NY, c=C, omega=OMEGA, law=law, mu=MU, lam=LAM, dx=dx, edges=edges)
 
 
-def run(t_end=12.0, every=None):
-    """Runs to t_end; returns the J range at t_end, the maximum over time of the absolute
-    vertical displacement at the free end (right-edge nodes), the maximum over time of the
-    displacement magnitude over the beam, and the final (U, u)."""
+def run(t_end=12.0):
+    """Runs to t_end and returns, at t_end, the J range, the largest absolute vertical
+    displacement on the loaded end (right-edge nodes), the largest displacement magnitude
+    over the beam (the quantities Sec. 5.4 prints for t = 12), and U, u."""
     pb = problem()
     st = lbm.initial_state(pb, np.zeros((2, NY, NX)))
     nsteps = int(round(t_end / pb.dt))
-    tip_max = 0.0
-    umag_max = 0.0
-    for k in range(nsteps):
-        _, u = lbm.step(pb, st)
-        tip_max = max(tip_max, float(np.abs(u[1, :, -1]).max()))
-        umag_max = max(umag_max, float(np.sqrt((u ** 2).sum(0)).max()))
-    U, u = lbm.observe(pb, st)
-    tip_max = max(tip_max, float(np.abs(u[1, :, -1]).max()))
-    umag_max = max(umag_max, float(np.sqrt((u ** 2).sum(0)).max()))
-    F = lbm.F_of(U)
+    U, u = lbm.run(pb, st, nsteps)
     from . import material as mat
-    J = mat.det(F)
-    return dict(J_min=float(J.min()), J_max=float(J.max()), tip_max=tip_max, umag_max=umag_max,
-                steps=nsteps, U=U, u=u)
+    J = mat.det(lbm.F_of(U))
+    return dict(J_min=float(J.min()), J_max=float(J.max()), tip=float(np.abs(u[1, :, -1]).max()),
+                umag=float(np.sqrt((u ** 2).sum(0)).max()), steps=nsteps, U=U, u=u)

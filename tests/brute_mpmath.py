@@ -6,9 +6,9 @@ nodes, directions and components, mpmath numbers at 40 significant digits, the t
 C = dP/dF obtained by numerical differentiation of P at that precision (not from the
 oracle's closed forms), a hand 2 x 2 solve for the boundary Newton iteration.  The readings
 of the points the paper leaves open are the same as the oracle's (they are readings of
-the paper, not of the oracle's code): tangential column of F^b extrapolated as
-3/2 G(X0) - 1/2 G(X1) with G = F_.B + (dt/2) d_B v; Newton guess 3/2 F_.A(X0) - 1/2 F_.A(X1);
-backtracking 1, 1/2, ..., 2^-10 with det > 0 and decreasing |r|.
+the paper, not of the oracle's code): tangential column of F^b = that of the wall node's
+own F; Newton guess = the wall node's normal column; backtracking 1, 1/2, ..., 2^-10 with
+det > 0 and decreasing |r|.
 """
 import mpmath as mp
 
@@ -219,41 +219,13 @@ class Brute:
         return [Dg[k] * out[k] + S[k] for k in range(6)]
 
     def boundary_F(self, e, b, a, Us, T):
-        nx, ny, dt, h = self.nx, self.ny, self.dt, self.dx
         A = 0 if e in (0, 1) else 1
         Bx = 1 - A
         NA = -1 if e in (0, 2) else 1
-        # node (b, a) is on the wall; step one node inward along -N
-        ib, ia = (b, a - NA) if A == 0 else (b - NA, a)
-        periodic_t = self.py if A == 0 else self.px
-        L = ny if A == 0 else nx
-        s = b if A == 0 else a
-
-        def node(row_b, row_a, s2):
-            return (s2, row_a) if A == 0 else (row_b, s2)
-
-        def G(row_b, row_a):
-            vals = []
-            for k in range(2):
-                def vk(s2):
-                    nb, na = node(row_b, row_a, s2)
-                    return Us[nb][na][k]
-                if periodic_t:
-                    dv = (vk((s + 1) % L) - vk((s - 1) % L)) / (2 * h)
-                elif s == 0:
-                    dv = (-3 * vk(0) + 4 * vk(1) - vk(2)) / (2 * h)
-                elif s == L - 1:
-                    dv = (3 * vk(L - 1) - 4 * vk(L - 2) + vk(L - 3)) / (2 * h)
-                else:
-                    dv = (vk(s + 1) - vk(s - 1)) / (2 * h)
-                Fk = Fmat(Us[row_b][row_a])[k][Bx]
-                vals.append(Fk + dt / 2 * dv)
-            return vals
-
-        G0, G1 = G(b, a), G(ib, ia)
-        tang = [G0[k] * mp.mpf(3) / 2 - G1[k] / 2 for k in range(2)]
-        F0, F1 = Fmat(Us[b][a]), Fmat(Us[ib][ia])
-        acol = [F0[k][A] * mp.mpf(3) / 2 - F1[k][A] / 2 for k in range(2)]
+        # the wall node's own F: tangential column kept, normal column the Newton guess
+        F0 = Fmat(Us[b][a])
+        tang = [F0[k][Bx] for k in range(2)]
+        acol = [F0[k][A] for k in range(2)]
         mu, lam = self.mu[b][a], self.lam[b][a]
 
         def build(ac):
