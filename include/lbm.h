@@ -83,7 +83,9 @@ enum {
     LBM_FAULT_J = 1,          /* inadmissible state at some node: det F <= 0 (Sec. 2.2), or
                                  barI1 - 3 >= J_m for the Gent law (Appendix A) */
     LBM_FAULT_NONFINITE = 2,  /* a recovered state value is not finite */
-    LBM_FAULT_NEWTON = 4      /* a traction-boundary Newton solve failed (Sec. 3.6) */
+    LBM_FAULT_NEWTON = 4,     /* a traction-boundary Newton solve failed (Sec. 3.6) */
+    LBM_FAULT_PROBE = 8       /* an adjoint kernel met a probe index outside [0, nx*ny) and
+                                 skipped it (the gradients then miss that probe's term) */
 };
 
 /* Number of FP64 values written by lbm_diagnostics. */
@@ -259,8 +261,11 @@ typedef struct {
     int32_t cur;               /* buffer holding lambda^{m+1} = dL/df^{m+1} before a step */
     double *g_mu, *g_lam;      /* device, 1 plane each: accumulated dL/dmu, dL/dlam, or NULL */
     double *g_body;            /* device, 2 planes: accumulated dL/db, or NULL */
-    const int32_t *probe;      /* device: nprobe node indices (b*nx + a); a cell may repeat
-                                  (its sources add up) */
+    const int32_t *probe;      /* device: nprobe node indices (b*nx + a), each in
+                                  [0, nx*ny); a cell may repeat (its sources add up).  The
+                                  library cannot read device memory before launching: the
+                                  kernels skip an index outside the grid and set
+                                  LBM_FAULT_PROBE, so callers validate indices on the host */
     const double *ubar;        /* device: 2*nprobe values (component-major), dL/du^N at the probes */
     int32_t nprobe;
     int64_t nsteps;            /* N, the level at which u^N enters the loss */

@@ -16,7 +16,7 @@ LBM_F32_SHIFTED, LBM_F16_SHIFTED, LBM_F64_PLAIN = range(3)
 LBM_LOGNH, LBM_NH, LBM_SVK, LBM_MR, LBM_YEOH, LBM_GENT = range(6)
 LBM_PERIODIC, LBM_VELOCITY, LBM_TRACTION = range(3)
 LBM_XMIN, LBM_XMAX, LBM_YMIN, LBM_YMAX = range(4)
-LBM_FAULT_J, LBM_FAULT_NONFINITE, LBM_FAULT_NEWTON = 1, 2, 4
+LBM_FAULT_J, LBM_FAULT_NONFINITE, LBM_FAULT_NEWTON, LBM_FAULT_PROBE = 1, 2, 4, 8
 LBM_DIAG_COUNT = 10
 
 STORAGE = {"f32": LBM_F32_SHIFTED, "f16": LBM_F16_SHIFTED, "f64": LBM_F64_PLAIN}

@@ -176,83 +176,31 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjArgs a) {
 }
 
 // Traction edges, stage 1 (one thread per wall link): F^b is rebuilt from the record of
-// U^m with the forward step's extrapolation and Newton solve, then dL/dF^b =
-// lambda^{m+1}_d(X0)_F / 2 is carried through the solve by the implicit function theorem:
-// with y = J^{-T} (dL/da), the tangential column receives -N_A y_i C_iAjB and mu, lam
-// receive -N_A y_i dP_iA/dp.  One launch covers every traction edge, one wavefront per
-// workgroup, each lane reading the record at one edge position (as the forward solve).
-// Each link stages (tbar_1, tbar_2, dL/dmu, dL/dlam) in its own slot of the staging
-// buffer; the mu and lam terms reach the gradients in the scatter stage, which gives a
-// corner node the terms of its edges in edge order.
+// U^m as the forward step builds it (tangential column = the wall node's own, normal
+// column by the Newton solve), then dL/dF^b = lambda^{m+1}_d(X0)_F / 2 is carried through
+// the solve by the implicit function theorem: with y = J^{-T} (dL/da), the tangential
+// column receives -N_A y_i C_iAjB and mu, lam receive -N_A y_i dP_iA/dp.  One launch
+// covers every traction edge, one wavefront per workgroup.  Each link stages
+// (tbar_1, tbar_2, dL/dmu, dL/dlam) in its own slot of the staging buffer; they reach
+// lambda^m and the gradients in the scatter stage, which gives a corner node the terms of
+// its edges in edge order.
 template <int ST, int LAW, bool FIELDS, int A>
 __device__ __forceinline__ void adj_traction_solve(const AdjArgs& a, int e) {
     using R = typename Storage<ST>::real;
     const Common& cm = a.cm;
     const EdgeGeom G = edge_geom(e);
     const int L = (A == 0) ? cm.ny : cm.nx;
-    const bool per_t = (A == 0) ? cm.periodic_y : cm.periodic_x;
     constexpr int Bx = 1 - A;
-    const int lane = int(threadIdx.x);
-    const int s = (int(blockIdx.x) - a.eblk[e]) * kTracOut - 2 + lane;   // this lane's position
-    const R* rec = (const R*)a.record;
-    const R hdt = R(0.5 * cm.dt);
-    const R inv2h = R(1.0 / (2.0 * cm.dx));
-    // the record of U^m at this lane's window position (as in the forward solve: lanes
-    // 2 .. 61 solve, the stencil velocities come from the neighbouring lanes)
-    int pw = s;
-    bool have = true;
-    if (per_t) pw = wrap_index(s, L);
-    else have = s >= 0 && s < L;
-    R Uw[2][6];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        if (have) {
-            const XY nd = edge_node(G, cm.nx, cm.ny, r, pw);
-            const int64_t rb = tile_base(cm.ntile, 6, nd.x, nd.y);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) Uw[r][k] = rec[rb + k * kTile];
-        } else {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) Uw[r][k] = R(0);
-        }
-    }
-    const bool solve = lane >= 2 && lane < kTracWin - 2 && s < L;
-    const Stencil sten = tangential_stencil(solve ? s : 0, L, per_t);
-    int dl[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        int d = sten.p[j] - (solve ? s : 0);
-        if (d > 2) d -= L;
-        if (d < -2) d += L;
-        dl[j] = solve ? d : 0;
-    }
-    R Vs[2][3][2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) Vs[r][j][k] = __shfl(Uw[r][k], lane + dl[j], kTracWin);
-    if (!solve) return;
-    R Ghat[2][2], Fa[2][2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            R dv = R(0);
-#pragma unroll
-            for (int j = 0; j < 3; ++j) dv += R(sten.w[j]) * Vs[r][j][k];
-            Ghat[r][k] = Uw[r][2 + 2 * k + Bx] + hdt * dv * inv2h;
-            Fa[r][k] = Uw[r][2 + 2 * k + A];
-        }
-    }
+    const int s = (int(blockIdx.x) - a.eblk[e]) * kTracWin + int(threadIdx.x);
+    if (s >= L) return;
+    const XY n0 = edge_node(G, cm.nx, cm.ny, 0, s);
+    const R* rec = (const R*)a.record + tile_base(cm.ntile, 6, n0.x, n0.y);
     R tang[2], acol[2], Tv[2];
     for (int k = 0; k < 2; ++k) {
-        tang[k] = R(1.5) * Ghat[0][k] - R(0.5) * Ghat[1][k];
-        acol[k] = R(1.5) * Fa[0][k] - R(0.5) * Fa[1][k];
+        tang[k] = rec[(2 + 2 * k + Bx) * kTile];
+        acol[k] = rec[(2 + 2 * k + A) * kTile];
         Tv[k] = edge_value<R>(a.ed, e, k, s, L);
     }
-    const XY n0 = edge_node(G, cm.nx, cm.ny, 0, s);
     const int id0 = n0.y * cm.nx + n0.x;
     R mu, lam;
     params_at<FIELDS, R>(cm, id0, mu, lam);
@@ -302,48 +250,29 @@ __global__ void __launch_bounds__(kTracWin) adj_traction_kernel(AdjArgs a) {
     else adj_traction_solve<ST, LAW, FIELDS, 1>(a, e);
 }
 
-// Traction edges, stage 2: transpose of the extrapolation 3/2 G(X0) - 1/2 G(X1) and of
-// G = F_{.B} + (dt/2) d_B v for the node at position s of row r of edge e, giving dL/dU^m
-// there; it enters lambda^m_q for every q and the body gradient.  With r = 0 the mu and lam
-// terms of the link's Newton solve (stage 1) are added too.
+// Traction edges, stage 2, for the wall node at position s of edge e: F^b's tangential
+// column is that node's F of level m, so dL/dU^m there receives the staged tbar in those
+// two components, for every q of lambda^m; the mu and lam terms of the link's Newton
+// solve (stage 1) go to the gradients.
 template <typename R, int AX>
-__device__ __forceinline__ void adj_scatter_edge(const AdjArgs& a, int e, int r, int s) {
+__device__ __forceinline__ void adj_scatter_edge(const AdjArgs& a, int e, int s) {
     const Common& cm = a.cm;
-    const EdgeGeom G = edge_geom(e);
-    const int L = (AX == 0) ? cm.ny : cm.nx;
-    const bool per_t = (AX == 0) ? cm.periodic_y : cm.periodic_x;
     constexpr int Bx = 1 - AX;
-    const int64_t n = int64_t(cm.nx) * cm.ny;
-    const R* aux = (const R*)a.aux + 4 * (int64_t)edge_off(cm.nx, cm.ny, e);
-    const R wr = (r == 0) ? R(1.5) : R(-0.5);
-    const R hdt = R(0.5 * cm.dt);
-    const R inv2h = R(1.0 / (2.0 * cm.dx));
-    R E[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    for (int k = 0; k < 2; ++k) {
-        E[2 + 2 * k + Bx] = wr * aux[4 * s + k];
-        E[k] = hdt * wr * fd_along_T<R>([&](int s2) { return aux[4 * s2 + k]; }, s, L, per_t, inv2h);
-    }
-    const XY nd = edge_node(G, cm.nx, cm.ny, r, s);
+    const R* aux = (const R*)a.aux + 4 * ((int64_t)edge_off(cm.nx, cm.ny, e) + s);
+    const XY nd = edge_node(edge_geom(e), cm.nx, cm.ny, 0, s);
     const int id = nd.y * cm.nx + nd.x;
-    if (r == 0) {
-        if (a.g_mu) a.g_mu[id] += double(aux[4 * s + 2]);
-        if (a.g_lam) a.g_lam[id] += double(aux[4 * s + 3]);
-    }
+    if (a.g_mu) a.g_mu[id] += double(aux[2]);
+    if (a.g_lam) a.g_lam[id] += double(aux[3]);
     R* dst = (R*)a.dst + tile_base(cm.ntile, 24, nd.x, nd.y);
     for (int q = 0; q < 4; ++q)
-        for (int k = 0; k < 6; ++k) dst[(6 * q + k) * kTile] += E[k];
-    if (a.g_body) {
-        a.g_body[id] += a.r_m * double(hdt * E[0]);
-        a.g_body[n + id] += a.r_m * double(hdt * E[1]);
-    }
+        for (int k = 0; k < 2; ++k) dst[(6 * q + 2 + 2 * k + Bx) * kTile] += aux[k];
 }
 
-// Stage 2 of every traction edge in one launch, one thread per node of the wall row and
-// first interior row of each edge (workgroups [sblk[e], sblk[e+1]) for edge e).  Near a
-// corner a node can lie in the rows of two traction edges; the thread of the first of
-// them (XMIN, XMAX, YMIN, YMAX order) applies both edges' terms in that order and the
-// other thread skips the node, so every node takes its terms in the same order as edge
-// after edge.
+// Stage 2 of every traction edge in one launch, one thread per wall node of each edge
+// (workgroups [sblk[e], sblk[e+1]) for edge e).  A corner node lies on the wall lines of
+// two traction edges; the thread of the first of them (XMIN, XMAX, YMIN, YMAX order)
+// applies both edges' terms in that order and the other thread skips the node, so every
+// node takes its terms in the same order as edge after edge.
 template <int ST>
 __global__ void __launch_bounds__(kTile) adj_traction_scatter_kernel(AdjArgs a) {
     using R = typename Storage<ST>::real;
@@ -351,21 +280,20 @@ __global__ void __launch_bounds__(kTile) adj_traction_scatter_kernel(AdjArgs a) 
     int e = 0;
     while (e < 3 && int(blockIdx.x) >= a.sblk[e + 1]) ++e;
     const int L = (e == LBM_XMIN || e == LBM_XMAX) ? cm.ny : cm.nx;
-    const int t = (int(blockIdx.x) - a.sblk[e]) * kTile + int(threadIdx.x);
-    if (t >= 2 * L) return;
-    const int r = t / L, s = t - r * L;
-    const XY nd = edge_node(edge_geom(e), cm.nx, cm.ny, r, s);
-    // the traction edges whose two rows hold this node: at most one along x and one along
-    // y (nx, ny >= 4), the x edge first in edge order
+    const int s = (int(blockIdx.x) - a.sblk[e]) * kTile + int(threadIdx.x);
+    if (s >= L) return;
+    const XY nd = edge_node(edge_geom(e), cm.nx, cm.ny, 0, s);
+    // the traction edges whose wall line holds this node: at most one along x and one
+    // along y, the x edge first in edge order
     const int x = nd.x, y = nd.y;
-    int ex = -1, rx = 0, ey = -1, ry = 0;
-    if (cm.bc[LBM_XMIN] == LBM_TRACTION && x <= 1) { ex = LBM_XMIN; rx = x; }
-    else if (cm.bc[LBM_XMAX] == LBM_TRACTION && x >= cm.nx - 2) { ex = LBM_XMAX; rx = cm.nx - 1 - x; }
-    if (cm.bc[LBM_YMIN] == LBM_TRACTION && y <= 1) { ey = LBM_YMIN; ry = y; }
-    else if (cm.bc[LBM_YMAX] == LBM_TRACTION && y >= cm.ny - 2) { ey = LBM_YMAX; ry = cm.ny - 1 - y; }
+    int ex = -1, ey = -1;
+    if (cm.bc[LBM_XMIN] == LBM_TRACTION && x == 0) ex = LBM_XMIN;
+    else if (cm.bc[LBM_XMAX] == LBM_TRACTION && x == cm.nx - 1) ex = LBM_XMAX;
+    if (cm.bc[LBM_YMIN] == LBM_TRACTION && y == 0) ey = LBM_YMIN;
+    else if (cm.bc[LBM_YMAX] == LBM_TRACTION && y == cm.ny - 1) ey = LBM_YMAX;
     if ((ex >= 0 ? ex : ey) != e) return;
-    if (ex >= 0) adj_scatter_edge<R, 0>(a, ex, rx, y);
-    if (ey >= 0) adj_scatter_edge<R, 1>(a, ey, ry, x);
+    if (ex >= 0) adj_scatter_edge<R, 0>(a, ex, y);
+    if (ey >= 0) adj_scatter_edge<R, 1>(a, ey, x);
 }
 
 // Probe source of the displacement loss at level m: u^N = u0 - (dt/2) v0 + dt sum_{m<N} v^m
@@ -381,6 +309,10 @@ __global__ void adj_probe_kernel(AdjArgs a) {
     const double hdt = 0.5 * cm.dt;
     for (int p = 0; p < a.nprobe; ++p) {
         const int id = a.probe[p];
+        if (id < 0 || int64_t(id) >= n) {
+            if (cm.fault) atomicOr(cm.fault, (uint32_t)LBM_FAULT_PROBE);
+            continue;
+        }
         const int py = id / cm.nx, px = id - py * cm.nx;
         R* d = dst + tile_base(cm.ntile, 24, px, py);
         for (int k = 0; k < 2; ++k) {
@@ -633,6 +565,10 @@ __global__ void adj_probe_table_kernel(Common cm, const int32_t* probe, const do
     const int64_t n = int64_t(cm.nx) * cm.ny;
     for (int p = 0; p < nprobe; ++p) {
         const int id = probe[p];
+        if (id < 0 || int64_t(id) >= n) {
+            if (cm.fault) atomicOr(cm.fault, (uint32_t)LBM_FAULT_PROBE);
+            continue;
+        }
         const int py = id / cm.nx, px = id - py * cm.nx;
         mask[int64_t(py) * cm.ntile + (px >> 6)] |= 1ull << (px & 63);
         field[id] += ubar[p];
@@ -772,8 +708,14 @@ __global__ void adj_init_probe_kernel(AdjInitArgs a) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     const int64_t n = int64_t(a.cm.nx) * a.cm.ny;
     const double hdt = 0.5 * a.cm.dt;
-    for (int p = 0; p < a.nprobe; ++p)
-        for (int k = 0; k < 2; ++k) a.g_v0[k * n + a.probe[p]] -= hdt * a.ubar[k * a.nprobe + p];
+    for (int p = 0; p < a.nprobe; ++p) {
+        const int id = a.probe[p];
+        if (id < 0 || int64_t(id) >= n) {
+            if (a.cm.fault) atomicOr(a.cm.fault, (uint32_t)LBM_FAULT_PROBE);
+            continue;
+        }
+        for (int k = 0; k < 2; ++k) a.g_v0[k * n + id] -= hdt * a.ubar[k * a.nprobe + p];
+    }
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -790,7 +732,7 @@ static hipError_t adjoint_st_law(const AdjArgs& a0, hipStream_t s) {
     a.eblk[0] = 0;
     for (int e = 0; e < 4; ++e) {
         const int L = (e == LBM_XMIN || e == LBM_XMAX) ? a.cm.ny : a.cm.nx;
-        a.eblk[e + 1] = a.eblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (L + kTracOut - 1) / kTracOut : 0);
+        a.eblk[e + 1] = a.eblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (L + kTracWin - 1) / kTracWin : 0);
     }
     if (a.eblk[4] > 0) {
         if (fields) hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, true>), dim3(a.eblk[4]), dim3(kTracWin), 0, s, a);
@@ -809,7 +751,7 @@ static hipError_t adjoint_st_law(const AdjArgs& a0, hipStream_t s) {
     a.sblk[0] = 0;
     for (int e = 0; e < 4; ++e) {
         const int L = (e == LBM_XMIN || e == LBM_XMAX) ? a.cm.ny : a.cm.nx;
-        a.sblk[e + 1] = a.sblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (2 * L + kTile - 1) / kTile : 0);
+        a.sblk[e + 1] = a.sblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (L + kTile - 1) / kTile : 0);
     }
     if (a.sblk[4] > 0) hipLaunchKernelGGL((adj_traction_scatter_kernel<ST>), dim3(a.sblk[4]), dim3(kTile), 0, s, a);
     // without a probe table the probe sources are added by one thread walking the probes

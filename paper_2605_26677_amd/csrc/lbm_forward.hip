@@ -19,23 +19,16 @@
 namespace lbm {
 
 // F^b of every link of the traction edges at step n -> n+1 (Sec. 3.6).  Reading of the
-// extrapolation the paper leaves open: with X0 the wall node and X1 the first interior
-// node, G = F_{.B} + (dt/2) d_B v (the kinematic identity moves F by half a step) and the
-// tangential column is 3/2 G(X0) - 1/2 G(X1) (linear extrapolation to the half-way wall);
-// the Newton guess for the normal column is 3/2 F_{.A}(X0) - 1/2 F_{.A}(X1).
+// interior values the paper takes F^b's tangential column from: the wall node's own F of
+// level n (recovered from its stored populations); the Newton solve of the traction
+// equations starts from that node's normal column.
 //
 // One launch covers every traction edge (each edge reads level n only and writes its own
-// slice of the staging buffer), one wavefront per workgroup: the solve is latency-bound,
-// so the links are spread over as many compute units as there are wavefronts.  Lane l of
-// a wavefront recovers U at edge position s0 - 2 + l (wrapped on a periodic edge) on the
-// wall row and the first interior row; lanes 2 .. 61 solve the links s0 .. s0 + 59 and
-// take the velocities of their tangential stencil (central, or one-sided at the ends of
-// an open edge: never more than two positions away) from the neighbouring lanes.  Each
-// node is thus read once per wavefront instead of once per stencil use: on the edges
-// normal to x every lane reads its own tile row, 24 separate cache lines per node.
-// The edge's normal axis AX is a template parameter (fixed per edge, so per wavefront):
-// with the axis known, F, the tangent and the per-node vectors index with constants and
-// stay in registers.
+// slice of the staging buffer), one wavefront per workgroup and one lane per link: the
+// solve is latency-bound, so the links are spread over as many compute units as there are
+// wavefronts.  The edge's normal axis AX is a template parameter (fixed per edge, so per
+// wavefront): with the axis known, F, the tangent and the per-node vectors index with
+// constants and stay in registers.
 template <int ST, int LAW, bool FIELDS, bool LINES, int AX>
 __device__ __forceinline__ void traction_solve(const TractionArgs& a, int e) {
     using Tr = Storage<ST>;
@@ -45,89 +38,36 @@ __device__ __forceinline__ void traction_solve(const TractionArgs& a, int e) {
     const Common& cm = a.cm;
     const EdgeGeom G = edge_geom(e);
     const int L = (AX == 0) ? cm.ny : cm.nx;
-    const bool per_t = (AX == 0) ? cm.periodic_y : cm.periodic_x;
     constexpr int Bx = 1 - AX;
-    const int lane = int(threadIdx.x);
-    const int s = (int(blockIdx.x) - a.eblk[e]) * kTracOut - 2 + lane;   // this lane's position
-    const T* pop = (const T*)a.pop;
+    const int s = (int(blockIdx.x) - a.eblk[e]) * kTracWin + int(threadIdx.x);
+    if (s >= L) return;
     const int64_t n = int64_t(cm.nx) * cm.ny;
     const R hdt = R(0.5 * cm.dt);
-    const R inv2h = R(1.0 / (2.0 * cm.dx));
 
-    // U of level n at this lane's window position, wall row (r = 0) and first interior row
-    int pw = s;
-    bool have = true;
-    if (per_t) pw = wrap_index(s, L);
-    else have = s >= 0 && s < L;
-    R Uw[2][6];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        if (have) {
-            const XY nd = edge_node(G, cm.nx, cm.ny, r, pw);
-            double b0, b1;
-            body_at<FIELDS>(cm, nd.y * cm.nx + nd.x, n, a.r_n, b0, b1);
-            if constexpr (LINES) {
-                // level n+1 of the two-level step, from the wall lines of the staging buffer
-                const T* lv = (const T*)wall_lines(a.aux, cm.nx, cm.ny).lines + line_slot(cm.nx, cm.ny, e, r, pw) * 24;
-                recover_vals<T, R>(lv, 1, hdt * R(b0), hdt * R(b1), Uw[r]);
-            } else {
-                recover_node<T, R>(pop, cm.ntile, nd.x, nd.y, hdt * R(b0), hdt * R(b1), Uw[r]);
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) Uw[r][k] = R(0);
-        }
-    }
-
-    // the stencil of the link at s, as lane offsets (a wrapped position is also held by the
-    // lane at its unwrapped offset, so an offset beyond +-2 is taken modulo L)
-    const bool solve = lane >= 2 && lane < kTracWin - 2 && s < L;
-    Stencil sten = tangential_stencil(solve ? s : 0, L, per_t);
-    int dl[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        int d = sten.p[j] - (solve ? s : 0);
-        if (d > 2) d -= L;
-        if (d < -2) d += L;
-        dl[j] = solve ? d : 0;
-    }
-    R Vs[2][3][2];                     // velocity of row r at stencil entry j
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) Vs[r][j][k] = __shfl(Uw[r][k], lane + dl[j], kTracWin);
-    if (!solve) return;
-
-    R Ghat[2][2], Fa[2][2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            R dv = R(0);
-#pragma unroll
-            for (int j = 0; j < 3; ++j) dv += R(sten.w[j]) * Vs[r][j][k];
-            dv *= inv2h;
-            Ghat[r][k] = Uw[r][2 + 2 * k + Bx] + hdt * dv;
-            Fa[r][k] = Uw[r][2 + 2 * k + AX];
-        }
+    // U of level n at the wall node
+    const XY n0 = edge_node(G, cm.nx, cm.ny, 0, s);
+    double b0, b1;
+    body_at<FIELDS>(cm, n0.y * cm.nx + n0.x, n, a.r_n, b0, b1);
+    R Uw[6];
+    if constexpr (LINES) {
+        // level n+1 of the two-level step, from the wall line of the staging buffer
+        const T* lv = (const T*)wall_lines(a.aux, cm.nx, cm.ny).lines + line_slot(cm.nx, cm.ny, e, 0, s) * 24;
+        recover_vals<T, R>(lv, 1, hdt * R(b0), hdt * R(b1), Uw);
+    } else {
+        recover_node<T, R>((const T*)a.pop, cm.ntile, n0.x, n0.y, hdt * R(b0), hdt * R(b1), Uw);
     }
     R tang[2], acol[2], Tv[2];
     for (int k = 0; k < 2; ++k) {
-        tang[k] = R(1.5) * Ghat[0][k] - R(0.5) * Ghat[1][k];
-        acol[k] = R(1.5) * Fa[0][k] - R(0.5) * Fa[1][k];
+        tang[k] = Uw[2 + 2 * k + Bx];
+        acol[k] = Uw[2 + 2 * k + AX];
         Tv[k] = edge_value<R>(a.ed, e, k, s, L);
     }
-    const XY n0 = edge_node(G, cm.nx, cm.ny, 0, s);
     R mu, lam;
     params_at<FIELDS, R>(cm, n0.y * cm.nx + n0.x, mu, lam);
     const bool ok = newton_column<R, LAW, SH, AX>(R(G.NA), tang, Tv, mu, lam, law_consts<R>(cm), acol,
                                                  cm.newton_max_iter, R(cm.newton_tol));
     if (!ok) atomicOr(cm.fault, (uint32_t)LBM_FAULT_NEWTON);
-    int off[4], len[4];
-    edge_offsets(cm.nx, cm.ny, off, len);
-    R* aux = (R*)a.aux + 4 * (int64_t)(off[e] + s);
+    R* aux = (R*)a.aux + 4 * (int64_t)(edge_off(cm.nx, cm.ny, e) + s);
     for (int k = 0; k < 2; ++k) {
         aux[2 * k + AX] = acol[k];
         aux[2 * k + Bx] = tang[k];
@@ -636,7 +576,7 @@ hipError_t launch_traction(TractionArgs a, hipStream_t s) {
     a.eblk[0] = 0;
     for (int e = 0; e < 4; ++e) {
         const int L = (e == LBM_XMIN || e == LBM_XMAX) ? a.cm.ny : a.cm.nx;
-        a.eblk[e + 1] = a.eblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (L + kTracOut - 1) / kTracOut : 0);
+        a.eblk[e + 1] = a.eblk[e] + (a.cm.bc[e] == LBM_TRACTION ? (L + kTracWin - 1) / kTracWin : 0);
     }
     if (a.eblk[4] == 0) return hipSuccess;
     switch (a.cm.storage) {

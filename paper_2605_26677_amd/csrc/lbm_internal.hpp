@@ -12,8 +12,7 @@ constexpr int kBlock = 256;          // threads per workgroup of the node-indexe
 constexpr int kTilesPerBlock = 2;    // 64-node tiles (one wavefront each) per workgroup of the
                                      // step and adjoint kernels
 constexpr int kDiagBlocks = 1024;    // partial sums of the diagnostics reduction
-constexpr int kTracWin = 64;         // edge positions one wavefront of the traction solve loads
-constexpr int kTracOut = kTracWin - 4;   // wall links it solves (two positions of halo a side)
+constexpr int kTracWin = 64;         // wall links one wavefront of the traction solve takes
 
 // Offsets of each edge's links in the traction staging buffer (links, not bytes).
 __host__ __device__ inline void edge_offsets(int nx, int ny, int off[4], int len[4]) {

@@ -169,33 +169,6 @@ __device__ bool newton_column(R NA, const R tang[2], const R T[2], R mu, R lam,
     return (rn <= R(1e-4) * scale(a) + floor) && (J > R(0)) && finite_r(rn);
 }
 
-// Tangential stencil of the traction-wall extrapolation at position s of an edge of
-// length L: positions p[] and weights w[] (in units of 1/(2 dx)), and which entry is s.
-struct Stencil {
-    int p[3];
-    int w[3];
-    int self;
-};
-__device__ __forceinline__ Stencil tangential_stencil(int s, int L, bool periodic) {
-    Stencil t;
-    if (periodic || (s >= 1 && s <= L - 2)) {
-        t.p[0] = (s == 0) ? L - 1 : s - 1;
-        t.p[1] = (s + 1 == L) ? 0 : s + 1;
-        t.p[2] = s;
-        t.w[0] = -1; t.w[1] = 1; t.w[2] = 0;
-        t.self = 2;
-    } else if (s == 0) {
-        t.p[0] = 0; t.p[1] = 1; t.p[2] = 2;
-        t.w[0] = -3; t.w[1] = 4; t.w[2] = -1;
-        t.self = 0;
-    } else {
-        t.p[0] = L - 1; t.p[1] = L - 2; t.p[2] = L - 3;
-        t.w[0] = 3; t.w[1] = -4; t.w[2] = 1;
-        t.self = 0;
-    }
-    return t;
-}
-
 // Node (x, y) of row r (0 = wall row, 1 = first interior row) at position s2 of edge e.
 struct XY {
     int x, y;

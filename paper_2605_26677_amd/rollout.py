@@ -54,6 +54,24 @@ class RolloutConfig:
                                                        # None where faster (Solver.pairs_pay),
                                                        # True wherever they apply, False never
 
+    def __post_init__(self):
+        check_probes(self.probes, self.nx, self.ny)
+
+
+def check_probes(probes, nx, ny):
+    """Raises ValueError unless ``probes`` is a 1-D integer tensor of node indices in
+    [0, nx * ny).  The adjoint kernels index device memory with them, and the library cannot
+    inspect device memory before it launches, so the check happens here, on the host."""
+    if not isinstance(probes, torch.Tensor) or probes.dim() != 1:
+        raise ValueError("probes must be a 1-D tensor of node indices")
+    if probes.dtype.is_floating_point or probes.dtype.is_complex or probes.dtype == torch.bool:
+        raise ValueError(f"probes must hold integers, not {probes.dtype}")
+    if probes.numel() == 0:
+        return
+    lo, hi = int(probes.min()), int(probes.max())
+    if lo < 0 or hi >= int(nx) * int(ny):
+        raise ValueError(f"probe indices must lie in [0, {int(nx) * int(ny)}), got [{lo}, {hi}]")
+
 
 def _sizes(nx, ny, storage):
     p = L.lbm_params()

@@ -54,3 +54,24 @@ def test_host_top_level_cuts_replays_within_budgets():
     assert with_host["model"]["peak"] <= dev and with_host["model"]["host"] <= host
     m = memory_model(n, n, "f32", N, with_host["levels"], host_top=True)
     assert m["host"] == (N // with_host["levels"][0] + 1) * (96 + 24) * n * n
+
+
+@pytest.mark.parametrize("bad", [[-1, 3], [0, 64], [5, 4096]])
+def test_rollout_rejects_probes_outside_the_grid(bad):
+    """Probe indices reach device memory in the adjoint kernels; RolloutConfig rejects any
+    outside [0, nx*ny) before a GPU is touched (an 8 x 8 grid has nodes 0..63)."""
+    import torch
+    from paper_2605_26677_amd.rollout import RolloutConfig
+    with pytest.raises(ValueError):
+        RolloutConfig(nx=8, ny=8, c=2.0, omega=2.0, nsteps=4, probes=torch.tensor(bad))
+
+
+def test_rollout_probe_dtype_and_shape():
+    import torch
+    from paper_2605_26677_amd.rollout import RolloutConfig
+    with pytest.raises(ValueError):
+        RolloutConfig(nx=8, ny=8, c=2.0, omega=2.0, nsteps=4, probes=torch.tensor([1.0, 2.0]))
+    with pytest.raises(ValueError):
+        RolloutConfig(nx=8, ny=8, c=2.0, omega=2.0, nsteps=4, probes=torch.tensor([[1, 2]]))
+    cfg = RolloutConfig(nx=8, ny=8, c=2.0, omega=2.0, nsteps=4, probes=torch.tensor([0, 63]))
+    assert cfg.probes.numel() == 2
