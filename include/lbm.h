@@ -254,6 +254,18 @@ lbm_status lbm_stress(const lbm_params *p, const lbm_state *s, double r_n, doubl
 lbm_status lbm_diagnostics(const lbm_params *p, const lbm_state *s, double r_n, double *out,
                            void *scratch, void *stream);
 
+/* lbm_diagnostics for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same kernels and result,
+ * bit for bit, with the reduction's partial sums in a fixed 80 KiB device array of the
+ * library instead of caller scratch.  Allocates nothing; the array's device address is
+ * looked up once per device (hipGetSymbolAddress) on the first call with that device
+ * current.  The array covers every grid lbm_check_params accepts (LBM_ERR_UNSUPPORTED
+ * otherwise).  Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller.  Nothing in the
+ * array needs clearing: each call writes every partial it reads. */
+lbm_status lbm_diagnostics_noalloc(const lbm_params *p, const lbm_state *s, double r_n, double *out,
+                                   void *stream);
+
 /* ------------------------------------------------------------------ adjoint */
 
 typedef struct {

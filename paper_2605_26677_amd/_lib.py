@@ -84,6 +84,7 @@ SIGNATURES = {
     "lbm_moments": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp]),
     "lbm_stress": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp, c_vp]),
     "lbm_diagnostics": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp, c_vp]),
+    "lbm_diagnostics_noalloc": (c_i32, [P(lbm_params), P(lbm_state), c_dbl, c_vp, c_vp]),
     "lbm_adjoint_step": (c_i32, [P(lbm_params), P(lbm_state), P(lbm_adj_state), c_i64, c_dbl,
                                  P(lbm_edge_data), c_vp, c_vp]),
     "lbm_adjoint_init": (c_i32, [P(lbm_params), P(lbm_state), P(lbm_adj_state), c_vp, c_vp, c_vp,

@@ -3,12 +3,40 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 
 using namespace lbm;
 
 namespace {
+
+// Device scratch of lbm_diagnostics_noalloc: the per-workgroup partial sums of the
+// diagnostics reduction, kDiagBlocks x LBM_DIAG_COUNT doubles (80 KiB), enough for every
+// grid because the reduction kernel strides over the nodes with at most kDiagBlocks
+// workgroups.  Every GPU the library runs on holds its own copy until the process ends.
+// On the host this name is only a stand-in for the symbol: host code uses the device
+// address that scratch_address obtains for the current device.
+__device__ __align__(256) double scratch[kDiagBlocks * LBM_DIAG_COUNT];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+lbm_status scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LBM_ERR_LAUNCH;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM_ERR_LAUNCH;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
 
 bool any_wall(const lbm_params* p) {
     for (int e = 0; e < 4; ++e)
@@ -348,6 +376,15 @@ lbm_status lbm_diagnostics(const lbm_params* p, const lbm_state* s, double r_n, 
     if (!scratch) return LBM_ERR_ARG;
     a.scratch = scratch;
     return launched(launch_diagnostics(a, (hipStream_t)stream));
+}
+
+lbm_status lbm_diagnostics_noalloc(const lbm_params* p, const lbm_state* s, double r_n, double* out,
+                                   void* stream) {
+    if (p && lbm_diag_scratch_bytes(p) > sizeof(scratch)) return LBM_ERR_UNSUPPORTED;
+    void* ptr = nullptr;
+    const lbm_status st = scratch_address(&ptr);
+    if (st != LBM_OK) return st;
+    return lbm_diagnostics(p, s, r_n, out, ptr, stream);
 }
 
 lbm_status lbm_adjoint_step(const lbm_params* p, const lbm_state* fwd, lbm_adj_state* adj, int64_t m,
