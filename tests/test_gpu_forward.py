@@ -1,7 +1,11 @@
 """Parity of the HIP forward path (lbm_init, lbm_step, lbm_moments, lbm_displacement,
 lbm_diagnostics) with the FP64 oracle on the same seeded inputs.
 
-Bars (element-wise relative L2 over all nodes and components):
+On grids with walls every case also checks the wall line and the first interior line of
+each wall edge element by element: max |GPU - oracle| over those lines, divided by the
+largest oracle value of that quantity, at most 1e-10 (F64), 3e-5 (F32), 5e-2 (F16).
+
+Bars (relative L2 over all nodes and components):
   F64 plain storage: 1e-10 on v, F - I, u and the populations (both sides carry the
       unshifted F in FP64; the bound allows ~1e-16 rounding per operation on O(1) values
       relative to |F - I| ~ 1e-4..1e-2 and its growth over the steps);
@@ -16,8 +20,8 @@ import numpy as np
 import pytest
 
 import lbm_inputs as li
-from gpu_cases import (ALL_LAWS, Case, block_case, mixed_case, random_field_case, rel_l2, run_library,
-                       run_oracle, shear_wave_case, shifted_state, make_solver)
+from gpu_cases import (ALL_LAWS, WALL_BAR, Case, block_case, mixed_case, random_field_case, rel_l2, run_library,
+                       run_oracle, shear_wave_case, shifted_state, make_solver, wall_line_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +47,11 @@ def _compare(case, storage, report=None):
     errs["pop"] = rel_l2(pops, ref)
     print(f"\n[{case.name} {storage}] rel L2: " + " ".join(f"{k}={v:.3e}" for k, v in errs.items()))
     assert sv.faults() == 0
+    if any(k != "periodic" for k in case.kinds):
+        we = wall_line_errors(Ug, ug, Uo_s, uo, case.kinds)
+        print(f"[{case.name} {storage}] wall lines, max |err| / max |oracle|: "
+              + " ".join(f"{k}={v:.3e}" for k, v in we.items()))
+        assert max(we.values()) <= WALL_BAR[storage], we
     return errs
 
 

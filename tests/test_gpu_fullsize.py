@@ -117,6 +117,18 @@ def test_block_1024_against_oracle_samples(storage, bar):
     ev, eF, eu = _rel(Ug[:, :2], ref[:, 2:4]), _rel(Ug[:, 2:6], ref[:, 4:8]), _rel(ug, ref[:, 8:10])
     print(f"\n[block 1024 {storage} vs oracle samples, 1000 steps] v={ev:.2e} F-I={eF:.2e} u={eu:.2e}")
     assert ev <= bar and eF <= bar and eu <= bar
+    # element by element on the sampled wall lines and first interior lines (rows and
+    # columns 0, 1, N-2, N-1), each scaled by the largest sampled oracle value
+    N = 1024
+    on_wall = (ys <= 1) | (ys >= N - 2) | (xs <= 1) | (xs >= N - 2)
+    got = np.concatenate([Ug, ug], axis=1)[on_wall]
+    want = ref[on_wall, 2:10]
+    werr = {}
+    for key, cols in (("v", slice(0, 2)), ("Ft", slice(2, 6)), ("u", slice(6, 8))):
+        werr[key] = float(np.abs(got[:, cols] - want[:, cols]).max() / np.abs(ref[:, 2:10][:, cols]).max())
+    print(f"[block 1024 {storage}] wall lines: " + " ".join(f"{k}={v:.2e}" for k, v in werr.items()))
+    from gpu_cases import WALL_BAR
+    assert max(werr.values()) <= WALL_BAR[storage], werr
 
 
 def test_block_1024_fp32_against_fp64_20000_steps():

@@ -101,3 +101,44 @@ def test_cantilever_pulse(storage, bar):
     ev, eF, eu = _errors(U, u, Uo, uo, np.sqrt(cv.LAM + 2 * cv.MU))
     print(f"\n[cantilever {storage}] v={ev:.2e} F-I={eF:.2e} u={eu:.2e} max|u|={np.abs(uo).max():.3e}")
     assert ev <= bar and eF <= bar and eu <= bar
+    from gpu_cases import WALL_BAR, shifted_state, wall_line_errors
+    we = wall_line_errors(U, u, shifted_state(Uo), uo, ("velocity",) * 4)
+    print(f"[cantilever {storage}] wall lines: " + " ".join(f"{k}={v:.2e}" for k, v in we.items()))
+    assert max(we.values()) <= WALL_BAR[storage], we
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_cantilever_printed_values(storage):
+    """The library's own run of the Sec. 5.4 cantilever to t = 12 (4800 steps) reproduces
+    the printed J range, largest |u_y| on the loaded end and largest |u| over the beam, each
+    at the printed number of decimals (tests/golden/cantilever_t12.txt)."""
+    import os
+    from oracle import cantilever as cv
+    from paper_2605_26677_amd.solver import Solver
+    want = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "cantilever_t12.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                key, val, dec = line.split()
+                want[key] = (float(val), int(dec))
+    pb = cv.problem()
+    sv = Solver(cv.NX, cv.NY, c=cv.C, omega=cv.OMEGA, dx=pb.dx, material="nh", storage=storage, mu=cv.MU,
+                lam=cv.LAM, bc=("velocity", "traction", "traction", "traction"))
+    sv.init(np.zeros((2, cv.NY, cv.NX)))
+    w = cv.taper()
+    dev = sv.device
+    steps = int(round(12.0 / pb.dt))
+    zero = torch.zeros((2, cv.NY), dtype=torch.float64, device=dev)
+    for m in range(steps):
+        p = cv.ricker((m + 0.5) * pb.dt)
+        T = torch.tensor(np.array([np.zeros(cv.NY), p * w]), dtype=torch.float64, device=dev) if p != 0.0 else zero
+        sv.step(m, edges=[(0, 0), T, (0, 0), (0, 0)])
+    U = sv.moments().cpu().numpy()
+    u = sv.displacement().cpu().numpy()
+    torch.cuda.synchronize()
+    assert sv.faults() == 0
+    J = (1 + U[2]) * (1 + U[5]) - U[3] * U[4]
+    got = dict(J_min=J.min(), J_max=J.max(), tip=np.abs(u[1, :, -1]).max(), umag=np.sqrt((u ** 2).sum(0)).max())
+    print(f"\n[cantilever t=12 {storage}] " + " ".join(f"{k}={v:.5e}" for k, v in got.items()))
+    for key, (val, dec) in want.items():
+        assert round(float(got[key]), dec) == pytest.approx(val, abs=1e-12), (key, got[key], val)
