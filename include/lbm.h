@@ -336,12 +336,18 @@ lbm_status lbm_adjoint_probe_table(const lbm_params *p, const lbm_adj_state *a, 
  * result, the block sums and the FP64 gradients are those of lbm_adjoint_step(m) followed
  * by lbm_adjoint_step(m - 1) with the same probe table set in a, bit for bit.  Flips a->cur.
  *   r_m, r_mm1: body factors at levels m and m - 1.
+ *   at_half, at_half_prev: boundary data at t^{m+1/2} and t^{m-1/2} (the steps m -> m+1 and
+ *     m-1 -> m); may be NULL only when all edges are periodic (LBM_ERR_ARG otherwise).
  *   record_m, record_mm1: device, U^m and U^{m-1} as lbm_adjoint_step reads them.
  *   mask, field: the probe table (lbm_adjoint_probe_table); may be NULL when a->nprobe = 0.
- * Requires every edge periodic (LBM_ERR_UNSUPPORTED otherwise) and 1 <= m < a->nsteps:
- * level N carries the half-weight probe term and takes lbm_adjoint_step. */
+ * On a grid with walls a->aux (lbm_aux_bytes()) is required: the bulk pass leaves lambda^m
+ * of the wall lines and first interior lines there, a small kernel completes the wall nodes
+ * over both levels, and the traction stages of level m - 1 read lambda^m from those lines.
+ * Requires 1 <= m < a->nsteps: level N carries the half-weight probe term and takes
+ * lbm_adjoint_step. */
 lbm_status lbm_adjoint_step2(const lbm_params *p, const lbm_state *fwd, lbm_adj_state *a,
-                             int64_t m, double r_m, double r_mm1, const void *record_m,
+                             int64_t m, double r_m, double r_mm1, const lbm_edge_data *at_half,
+                             const lbm_edge_data *at_half_prev, const void *record_m,
                              const void *record_mm1, const uint64_t *mask, const double *field,
                              void *stream);
 

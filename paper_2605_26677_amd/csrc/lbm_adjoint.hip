@@ -209,10 +209,17 @@ __device__ __forceinline__ void adj_traction_solve(const AdjArgs& a, int e) {
     R f[4];
     f[A] = acol[0]; f[2 + A] = acol[1];
     f[Bx] = tang[0]; f[2 + Bx] = tang[1];
-    const R* src = (const R*)a.src;
+    // dL/dF^b = lambda^{m+1}_d(X0)_F / 2: from the populations, or (the second level of a
+    // two-level step) from the wall line of the staging buffer
     R Fbar[4];
-    const int64_t wb = tile_base(cm.ntile, 24, n0.x, n0.y);
-    for (int k = 0; k < 4; ++k) Fbar[k] = R(0.5) * src[wb + (6 * G.d + 2 + k) * kTile];
+    if (a.lines) {
+        const R* lv = (const R*)wall_lines(a.aux, cm.nx, cm.ny).lines + line_slot(cm.nx, cm.ny, e, 0, s) * 24;
+        for (int k = 0; k < 4; ++k) Fbar[k] = R(0.5) * lv[6 * G.d + 2 + k];
+    } else {
+        const R* src = (const R*)a.src;
+        const int64_t wb = tile_base(cm.ntile, 24, n0.x, n0.y);
+        for (int k = 0; k < 4; ++k) Fbar[k] = R(0.5) * src[wb + (6 * G.d + 2 + k) * kTile];
+    }
     R C[16];
     tangent<R, LAW, true>(f, mu, lam, law_consts<R>(cm), C);
     const R NA = R(G.NA);
@@ -342,35 +349,229 @@ __device__ __forceinline__ void pull_adj_node(const R* __restrict__ src, int nti
     }
 }
 
-// Two adjoint levels m and m - 1 per pass on a periodic grid, the transpose of the two-level
-// forward kernel: a workgroup owns kPairRows rows of one 64-node strip; wave w takes row
-// y0 - 1 + w from lambda^{m+1} to lambda^m (with the probe source of level m), one more wave
-// the two columns beside the strip, and waves 1 .. kPairRows take their row on to
-// lambda^{m-1}.  The adjoint pulls from X + c_q, so the rows and columns exchanged are the
-// mirror images of the forward's.  Per node the arithmetic is adj_node, as in
-// adjoint_kernel, and the gradient updates of the two levels (block sums, folds, the probe
-// body term of level m) run in the order of two single steps, so the result is bit for
-// bit theirs (with the probe table in both), the probe sources of both levels included.
-template <int ST, int LAW, bool FIELDS>
-__global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2Args a) {
+// The adjoint of the missing links of a wall node (transpose of eq:boundary-general): the
+// slot of the outgoing direction N of each wall takes D lambda_d of the node itself, d = -N
+// the missing direction (XMIN: q2 from q0, XMAX: q0 from q2, YMIN: q3 from q1, YMAX: q1 from
+// q3).  `own(q, k)` gives lambda_q component k of the node.
+template <typename R, typename Own>
+__device__ __forceinline__ void adj_wall_slots(const Common& cm, int x, int y, Own own, R l[4][6]) {
+    if (!cm.periodic_x) {
+        if (x == 0)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) l[2][k] = D_sign<R>(cm.bc[LBM_XMIN], k) * own(0, k);
+        if (x == cm.nx - 1)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) l[0][k] = D_sign<R>(cm.bc[LBM_XMAX], k) * own(2, k);
+    }
+    if (!cm.periodic_y) {
+        if (y == 0)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) l[3][k] = D_sign<R>(cm.bc[LBM_YMIN], k) * own(1, k);
+        if (y == cm.ny - 1)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) l[1][k] = D_sign<R>(cm.bc[LBM_YMAX], k) * own(3, k);
+    }
+}
+
+// The traction edges whose wall line holds node (x, y), x edge first (edge order), or -1.
+__device__ __forceinline__ void traction_edges_at(const Common& cm, int x, int y, int& ex, int& ey) {
+    ex = ey = -1;
+    if (!cm.periodic_x) {
+        if (x == 0 && cm.bc[LBM_XMIN] == LBM_TRACTION) ex = LBM_XMIN;
+        else if (x == cm.nx - 1 && cm.bc[LBM_XMAX] == LBM_TRACTION) ex = LBM_XMAX;
+    }
+    if (!cm.periodic_y) {
+        if (y == 0 && cm.bc[LBM_YMIN] == LBM_TRACTION) ey = LBM_YMIN;
+        else if (y == cm.ny - 1 && cm.bc[LBM_YMAX] == LBM_TRACTION) ey = LBM_YMAX;
+    }
+}
+
+// The traction terms of a wall node at one level, as adj_traction_scatter_kernel adds them
+// after a single step: lambda_q of the node takes each of its links' staged tbar in the two
+// components of F^b's tangential column (F12, F22 on an x edge, F11, F21 on a y edge).
+template <typename R>
+__device__ __forceinline__ void add_traction_tbar(const Common& cm, const void* aux, int x, int y, R l[4][6]) {
+    int ex, ey;
+    traction_edges_at(cm, x, y, ex, ey);
+    if (ex >= 0) {
+        const R* t = (const R*)aux + 4 * (int64_t(edge_off(cm.nx, cm.ny, ex)) + y);
+        const R t0 = t[0], t1 = t[1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            l[q][3] += t0;
+            l[q][5] += t1;
+        }
+    }
+    if (ey >= 0) {
+        const R* t = (const R*)aux + 4 * (int64_t(edge_off(cm.nx, cm.ny, ey)) + x);
+        const R t0 = t[0], t1 = t[1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            l[q][2] += t0;
+            l[q][4] += t1;
+        }
+    }
+}
+
+// ... and its staged mu and lam terms, into the FP64 gradients in edge order.
+template <typename R>
+__device__ __forceinline__ void add_traction_params(const Common& cm, const void* aux, int x, int y, double* g_mu,
+                                                    double* g_lam) {
+    int ex, ey;
+    traction_edges_at(cm, x, y, ex, ey);
+    const int64_t id = int64_t(y) * cm.nx + x;
+    if (ex >= 0) {
+        const R* t = (const R*)aux + 4 * (int64_t(edge_off(cm.nx, cm.ny, ex)) + y);
+        if (g_mu) g_mu[id] += double(t[2]);
+        if (g_lam) g_lam[id] += double(t[3]);
+    }
+    if (ey >= 0) {
+        const R* t = (const R*)aux + 4 * (int64_t(edge_off(cm.nx, cm.ny, ey)) + x);
+        if (g_mu) g_mu[id] += double(t[2]);
+        if (g_lam) g_lam[id] += double(t[3]);
+    }
+}
+
+// lambda^m of a node on a wall line or first interior line into the wall lines of the
+// staging buffer (every such line through it; 24 values of the compute type per slot).
+template <typename R>
+__device__ __forceinline__ void store_adj_lines(const Common& cm, void* aux, int x, int y, const R l[4][6]) {
+    const int nx = cm.nx, ny = cm.ny;
+    const WallLines wl = wall_lines(aux, nx, ny);
+    int er[4] = {-1, -1, -1, -1}, es[4] = {0, 0, 0, 0};
+    if (!cm.periodic_x) {
+        if (x <= 1) { er[LBM_XMIN] = x; es[LBM_XMIN] = y; }
+        if (x >= nx - 2) { er[LBM_XMAX] = nx - 1 - x; es[LBM_XMAX] = y; }
+    }
+    if (!cm.periodic_y) {
+        if (y <= 1) { er[LBM_YMIN] = y; es[LBM_YMIN] = x; }
+        if (y >= ny - 2) { er[LBM_YMAX] = ny - 1 - y; es[LBM_YMAX] = x; }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (er[e] < 0) continue;
+        R* lv = (R*)wl.lines + line_slot(nx, ny, e, er[e], es[e]) * 24;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) lv[6 * q + k] = l[q][k];
+    }
+}
+
+// The LDS of one two-level adjoint workgroup: lambda^m of the q1 and q3 planes of every row
+// wave (read by the rows below and above) and of the nodes beside the strip (q2 at c0 - 1,
+// q0 at c0 + 64).
+template <typename R>
+struct Adj2Lds {
+    R xq1[kPairWaves][6][kTile];
+    R xq3[kPairWaves][6][kTile];
+    R xh[2][6][kPairRows];
+};
+
+// The FP64 gradients and FP32 block sums of one node over two adjoint levels, in the order
+// of two single steps: level m's increments (block sum, fold), its probe body term, the
+// traction terms of level m's links at a traction wall node (tw, staged by stage 1: what
+// adj_traction_scatter_kernel adds after a single step), then level m - 1's increments and
+// probe body term.
+template <int ST, typename R>
+__device__ __forceinline__ void adj_pair_gradients(const Adj2Args& a, int x, int y, const R inc1[4], const R inc2[4],
+                                                   bool probe, const double ps[2], const void* tw) {
+    const Common& cm = a.cm;
+    const int64_t n = int64_t(cm.nx) * cm.ny;
+    const int64_t gi = int64_t(y) * cm.nx + x;
+    double* const g64[4] = {a.g_mu, a.g_lam, a.g_body, a.g_body ? a.g_body + n : nullptr};
+    const double hdt = 0.5 * cm.dt;
+    if constexpr (ST == LBM_F64_PLAIN) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+            if (g64[jj]) g64[jj][gi] += double(inc1[jj]);
+        if (probe && a.g_body) {
+            a.g_body[gi] += a.r1 * hdt * ps[0];
+            a.g_body[n + gi] += a.r1 * hdt * ps[1];
+        }
+        if (tw) add_traction_params<R>(cm, tw, x, y, a.g_mu, a.g_lam);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+            if (g64[jj]) g64[jj][gi] += double(inc2[jj]);
+        if (probe && a.g_body) {
+            a.g_body[gi] += a.r2 * hdt * ps[0];
+            a.g_body[n + gi] += a.r2 * hdt * ps[1];
+        }
+    } else {
+        const bool any = g64[0] || g64[1] || g64[2];
+        float* gs = (float*)a.gsum + tile_base(cm.ntile, 4, x, y);
+        float sj[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (any) {
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                if (!g64[jj]) continue;
+                sj[jj] = gs[jj * kTile] + float(inc1[jj]);
+                if (a.fold1) {
+                    g64[jj][gi] += double(sj[jj]);
+                    sj[jj] = 0.0f;
+                }
+            }
+        }
+        if (probe && a.g_body) {
+            a.g_body[gi] += a.r1 * hdt * ps[0];
+            a.g_body[n + gi] += a.r1 * hdt * ps[1];
+        }
+        if (tw) add_traction_params<R>(cm, tw, x, y, a.g_mu, a.g_lam);
+        if (any) {
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                if (!g64[jj]) continue;
+                sj[jj] = sj[jj] + float(inc2[jj]);
+                if (a.fold2) {
+                    g64[jj][gi] += double(sj[jj]);
+                    sj[jj] = 0.0f;
+                }
+                store_stream(gs + jj * kTile, sj[jj]);
+            }
+        }
+        if (probe && a.g_body) {
+            a.g_body[gi] += a.r2 * hdt * ps[0];
+            a.g_body[n + gi] += a.r2 * hdt * ps[1];
+        }
+    }
+}
+
+// Two adjoint levels m and m - 1 per pass, the transpose of the two-level forward kernel: a
+// workgroup owns kPairRows rows of one 64-node strip; wave w takes row y0 - 1 + w from
+// lambda^{m+1} to lambda^m (with the probe source of level m), one more wave the two
+// columns beside the strip, and waves 1 .. kPairRows take their row on to lambda^{m-1}.
+// The adjoint pulls from X + c_q, so the rows and columns exchanged are the mirror images
+// of the forward's.  Per node the arithmetic is adj_node, as in adjoint_kernel, and the
+// gradient updates of the two levels (block sums, folds, the probe body term of level m)
+// run in the order of two single steps, so the result is bit for bit theirs (with the
+// probe table in both), the probe sources of both levels included.  WALLS: the wall slots
+// of level m take the transposed wall rules and a traction wall node its staged level-m
+// terms, as in adjoint_kernel followed by adj_traction_scatter_kernel; level m of the wall
+// lines and first interior lines goes to the staging buffer, and the wall nodes are left
+// out of the second level and of the gradients (adjoint2_wall_kernel does them).
+template <int ST, int LAW, bool FIELDS, bool WALLS>
+__device__ __forceinline__ void adjoint2_body(const Adj2Args& a, int strip, int blk,
+                                              Adj2Lds<typename Storage<ST>::real>& sh) {
     using R = typename Storage<ST>::real;
-    __shared__ R xq1[kPairWaves][6][kTile];   // lambda^m, direction (0,1): pulled by the row below
-    __shared__ R xq3[kPairWaves][6][kTile];   // lambda^m, direction (0,-1): pulled by the row above
-    __shared__ R xh[2][6][kPairRows];         // beside the strip: q2 at c0-1, q0 at c0+64
+    auto& xq1 = sh.xq1;
+    auto& xq3 = sh.xq3;
+    auto& xh = sh.xh;
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
     const int64_t n = int64_t(nx) * ny;
-    int strip, blk;
-    pair_block(a.map, remap_tile(blockIdx.x, gridDim.x), strip, blk);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & (kTile - 1);
     const int c0 = strip * kTile, y0 = blk * kPairRows;
     const int r = y0 - 1 + w;
-    const int xc = wrap_near(c0 + lane, nx);
+    const int xg = c0 + lane;
+    const int xc = wrap_near(xg, nx);
     const int yr = wrap_near(r, ny);
     const int idx = yr * nx + xc;
     const R* __restrict__ src = (const R*)a.src;
     R* __restrict__ dst = (R*)a.dst;
     const bool gpar = a.g_mu || a.g_lam, gbody = a.g_body != nullptr;
+    // a node of the grid (a lane or row beyond a wall is not; along a periodic axis every
+    // lane and row is the node it wraps to)
+    const bool valid = !WALLS || ((cm.periodic_x || xg < nx) && (cm.periodic_y || (r >= 0 && r < ny)));
 
     R l[4][6], lm[4][6], inc1[4], mu, lam;
     double ps[2] = {0.0, 0.0};
@@ -415,6 +616,16 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
             l[0][k] = lane == kTile - 1 ? h[k] : dn;
             l[2][k] = lane == 0 ? h[k] : up;
         }
+        // (a valid node's unwrapped position equals its wrapped one along every wall axis,
+        // and the wrapped one is the node along a periodic axis: the wall code takes xc, yr)
+        if constexpr (WALLS) {
+            if (valid) {
+                const R* on = src + bo;
+                adj_wall_slots<R>(cm, xc, yr, [&](int q, int k) {
+                    return q == 0 ? own0[k] : q == 2 ? own2[k] : on[(6 * q + k) * kTile];
+                }, l);
+            }
+        }
         const R* rec = (const R*)a.rec1 + tile_base(ntile, 6, xc, yr);
         R ft[4];
 #pragma unroll
@@ -427,6 +638,12 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
             for (int q = 0; q < 4; ++q) {
                 lm[q][0] += R(ps[0]);
                 lm[q][1] += R(ps[1]);
+            }
+        }
+        if constexpr (WALLS) {
+            if (valid) {
+                add_traction_tbar<R>(cm, a.aux, xc, yr, lm);
+                store_adj_lines<R>(cm, a.aux, xc, yr, lm);
             }
         }
 #pragma unroll
@@ -444,6 +661,15 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
         const int hx = wrap_near(side == 0 ? c0 - 1 : c0 + kTile, nx), hy = wrap_near(y0 + row, ny);
         R lh[4][6], oh[4][6], ih[4], muh, lamh, fth[4];
         pull_adj_node<R>(src, ntile, nx, ny, hx, hy, lh);
+        bool hvalid = true;
+        if constexpr (WALLS) {
+            const int hxg = side == 0 ? c0 - 1 : c0 + kTile, hyg = y0 + row;
+            hvalid = (cm.periodic_x || (hxg >= 0 && hxg < nx)) && (cm.periodic_y || hyg < ny);
+            if (hvalid) {
+                const R* hown = src + tile_base(ntile, 24, hx, hy);
+                adj_wall_slots<R>(cm, hx, hy, [&](int q, int k) { return hown[(6 * q + k) * kTile]; }, lh);
+            }
+        }
         const R* rec = (const R*)a.rec1 + tile_base(ntile, 6, hx, hy);
 #pragma unroll
         for (int k = 0; k < 4; ++k) fth[k] = rec[(2 + k) * kTile];
@@ -456,6 +682,9 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
                 oh[q][0] += R(hs[0]);
                 oh[q][1] += R(hs[1]);
             }
+        }
+        if constexpr (WALLS) {
+            if (hvalid) add_traction_tbar<R>(cm, a.aux, hx, hy, oh);
         }
         if (lane < 2 * kPairRows) {
 #pragma unroll
@@ -491,63 +720,121 @@ __global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2
                 out[q][1] += R(ps[1]);
             }
         }
-        if (r < ny && xo < nx) {
+        const bool wall_node = WALLS && ((!cm.periodic_x && (xo == 0 || xo == nx - 1)) ||
+                                         (!cm.periodic_y && (r == 0 || r == ny - 1)));
+        if (r < ny && xo < nx && !wall_node) {
             const int64_t ob = tile_base(ntile, 24, xo, r);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) store_stream(dst + ob + (6 * q + k) * kTile, out[q][k]);
-            const int64_t gi = int64_t(r) * nx + xo;
-            double* const g64[4] = {a.g_mu, a.g_lam, a.g_body, a.g_body ? a.g_body + n : nullptr};
-            const double hdt = 0.5 * cm.dt;
-            if constexpr (ST == LBM_F64_PLAIN) {
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
-                    if (g64[jj]) g64[jj][gi] += double(inc1[jj]);
-                if (probe && a.g_body) {
-                    a.g_body[gi] += a.r1 * hdt * ps[0];
-                    a.g_body[n + gi] += a.r1 * hdt * ps[1];
-                }
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
-                    if (g64[jj]) g64[jj][gi] += double(inc2[jj]);
-                if (probe && a.g_body) {
-                    a.g_body[gi] += a.r2 * hdt * ps[0];
-                    a.g_body[n + gi] += a.r2 * hdt * ps[1];
-                }
-            } else if (g64[0] || g64[1] || g64[2]) {
-                float* gs = (float*)a.gsum + tile_base(ntile, 4, xo, r);
-                float sj[4];
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    if (!g64[jj]) continue;
-                    sj[jj] = gs[jj * kTile] + float(inc1[jj]);
-                    if (a.fold1) {
-                        g64[jj][gi] += double(sj[jj]);
-                        sj[jj] = 0.0f;
-                    }
-                }
-                if (probe && a.g_body) {
-                    a.g_body[gi] += a.r1 * hdt * ps[0];
-                    a.g_body[n + gi] += a.r1 * hdt * ps[1];
-                }
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    if (!g64[jj]) continue;
-                    sj[jj] = sj[jj] + float(inc2[jj]);
-                    if (a.fold2) {
-                        g64[jj][gi] += double(sj[jj]);
-                        sj[jj] = 0.0f;
-                    }
-                    store_stream(gs + jj * kTile, sj[jj]);
-                }
-                if (probe && a.g_body) {
-                    a.g_body[gi] += a.r2 * hdt * ps[0];
-                    a.g_body[n + gi] += a.r2 * hdt * ps[1];
-                }
-            }
+            adj_pair_gradients<ST>(a, xo, r, inc1, inc2, probe, ps, nullptr);
         }
     }
+}
+
+template <int ST, int LAW, bool FIELDS, bool WALLS>
+__global__ void __launch_bounds__((kPairWaves + 1) * kTile) adjoint2_kernel(Adj2Args a) {
+    __shared__ Adj2Lds<typename Storage<ST>::real> sh;
+    int strip, blk;
+    pair_block(a.map, remap_tile(blockIdx.x, gridDim.x), strip, blk);
+    adjoint2_body<ST, LAW, FIELDS, WALLS>(a, strip, blk, sh);
+}
+
+// The wall nodes of a two-level adjoint step on a grid with walls, one thread per link slot
+// of the staging buffer (a corner node is taken by the first of its edges): level m as the
+// bulk pass computes it (pulled from lambda^{m+1} in HBM), level m - 1 from the wall lines
+// of lambda^m that the bulk pass staged, and both levels' gradient updates in the order of
+// two single steps.  The traction terms of level m - 1 come after this kernel, from stage 1
+// on the staged lines and the scatter, as after a single step.
+template <int ST, int LAW, bool FIELDS>
+__global__ void __launch_bounds__(kTile) adjoint2_wall_kernel(Adj2Args a) {
+    using R = typename Storage<ST>::real;
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * ny + 2 * nx) return;
+    const int e = t < ny ? LBM_XMIN : t < 2 * ny ? LBM_XMAX : t < 2 * ny + nx ? LBM_YMIN : LBM_YMAX;
+    const int bce = e == LBM_XMIN ? cm.bc[LBM_XMIN] : e == LBM_XMAX ? cm.bc[LBM_XMAX]
+                  : e == LBM_YMIN ? cm.bc[LBM_YMIN] : cm.bc[LBM_YMAX];
+    if (bce == LBM_PERIODIC) return;
+    const int s = t - edge_off(nx, ny, e);
+    const XY nd = edge_node(edge_geom(e), nx, ny, 0, s);
+    const int x = nd.x, y = nd.y;
+    const bool on[4] = {!cm.periodic_x && x == 0, !cm.periodic_x && x == nx - 1,
+                        !cm.periodic_y && y == 0, !cm.periodic_y && y == ny - 1};
+    // a corner taken by an earlier edge
+    if ((e > LBM_XMIN && on[LBM_XMIN]) || (e > LBM_XMAX && on[LBM_XMAX]) || (e > LBM_YMIN && on[LBM_YMIN])) return;
+    const int ntile = cm.ntile;
+    const R* src = (const R*)a.src;
+    const int idx = y * nx + x;
+    const bool gpar = a.g_mu || a.g_lam, gbody = a.g_body != nullptr;
+    // the wall beyond which the pull of direction q would reach: q0 pulls from x+1 (XMAX),
+    // q1 from y+1 (YMAX), q2 from x-1 (XMIN), q3 from y-1 (YMIN)
+    const bool beyond[4] = {on[LBM_XMAX], on[LBM_YMAX], on[LBM_XMIN], on[LBM_YMIN]};
+
+    // level m
+    R l[4][6], lm[4][6], inc1[4], mu, lam;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (beyond[q]) continue;
+        const int sx = wrap_index(x + dir_i(q), nx), sy = wrap_index(y + dir_j(q), ny);
+        const R* sp = src + tile_base(ntile, 24, sx, sy);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) l[q][k] = sp[(6 * q + k) * kTile];
+    }
+    {
+        const R* on_ = src + tile_base(ntile, 24, x, y);
+        adj_wall_slots<R>(cm, x, y, [&](int q, int k) { return on_[(6 * q + k) * kTile]; }, l);
+    }
+    const R* rec1 = (const R*)a.rec1 + tile_base(ntile, 6, x, y);
+    R ft[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ft[k] = rec1[(2 + k) * kTile];
+    params_at<FIELDS, R>(cm, idx, mu, lam);
+    adj_node<R, LAW>(cm, l, ft, mu, lam, R(a.r1), gpar, gbody, lm, inc1);
+    double ps[2] = {0.0, 0.0};
+    const bool probe = probe_at<R>(a, x, y, ps);
+    if (probe) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            lm[q][0] += R(ps[0]);
+            lm[q][1] += R(ps[1]);
+        }
+    }
+    add_traction_tbar<R>(cm, a.aux, x, y, lm);
+
+    // level m - 1: lambda^m of the neighbours from the wall lines, of the node itself from lm
+    const WallLines wl = wall_lines(a.aux, nx, ny);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (beyond[q]) continue;
+        const int sx = wrap_index(x + dir_i(q), nx), sy = wrap_index(y + dir_j(q), ny);
+        int le = 0, lr = 0, ls = 0;
+        find_line(cm, sx, sy, le, lr, ls);
+        const R* sp = (const R*)wl.lines + line_slot(nx, ny, le, lr, ls) * 24;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) l[q][k] = sp[6 * q + k];
+    }
+    adj_wall_slots<R>(cm, x, y, [&](int q, int k) { return lm[q][k]; }, l);
+    const R* rec2 = (const R*)a.rec2 + tile_base(ntile, 6, x, y);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ft[k] = rec2[(2 + k) * kTile];
+    R out[4][6], inc2[4];
+    adj_node<R, LAW>(cm, l, ft, mu, lam, R(a.r2), gpar, gbody, out, inc2);
+    if (probe) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            out[q][0] += R(ps[0]);
+            out[q][1] += R(ps[1]);
+        }
+    }
+    R* dst = (R*)a.dst + tile_base(ntile, 24, x, y);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) store_stream(dst + (6 * q + k) * kTile, out[q][k]);
+    adj_pair_gradients<ST>(a, x, y, inc1, inc2, probe, ps, a.aux);
 }
 
 // The probe table: bit x mod 64 of word (y, x / 64) marks a probe, field holds the sum of
@@ -799,13 +1086,90 @@ static void adj_init_st(const AdjInitArgs& a, hipStream_t s, dim3 grid) {
     }
 }
 
+// The traction stages of the adjoint at one level (AdjArgs of a two-level step): stage 1
+// reads lambda of the level above from `src` or, with `lines`, from the staged wall lines.
+static AdjArgs traction_args(const Adj2Args& a2, const void* record, const EdgeData& ed, int lines) {
+    AdjArgs a{};
+    a.cm = a2.cm;
+    a.src = a2.src;
+    a.dst = a2.dst;
+    a.record = record;
+    a.g_mu = a2.g_mu;
+    a.g_lam = a2.g_lam;
+    a.aux = a2.aux;
+    a.ed = ed;
+    a.lines = lines;
+    a.eblk[0] = a.sblk[0] = 0;
+    for (int e = 0; e < 4; ++e) {
+        const int L = (e == LBM_XMIN || e == LBM_XMAX) ? a.cm.ny : a.cm.nx;
+        const bool tr = a.cm.bc[e] == LBM_TRACTION;
+        a.eblk[e + 1] = a.eblk[e] + (tr ? (L + kTracWin - 1) / kTracWin : 0);
+        a.sblk[e + 1] = a.sblk[e] + (tr ? (L + kTile - 1) / kTile : 0);
+    }
+    return a;
+}
+
+template <int ST, int LAW, bool FIELDS>
+static void adj_traction_stage1(const AdjArgs& a, hipStream_t s) {
+    if (a.eblk[4] > 0) hipLaunchKernelGGL((adj_traction_kernel<ST, LAW, FIELDS>), dim3(a.eblk[4]), dim3(kTracWin), 0, s, a);
+}
+
+template <int ST, int LAW, bool FIELDS>
+static void adjoint2_launch(const Adj2Args& a0, hipStream_t s) {
+    const dim3 block((kPairWaves + 1) * kTile);
+    const int nstrip = a0.nstrip, nblk = (a0.cm.ny + kPairRows - 1) / kPairRows;
+    auto go = [&](const PairMap& m, bool w) {
+        const int64_t nb = pair_map_blocks(m);
+        if (nb <= 0) return;
+        Adj2Args a = a0;
+        a.map = m;
+        if (w) hipLaunchKernelGGL((adjoint2_kernel<ST, LAW, FIELDS, true>), dim3(unsigned(nb)), block, 0, s, a);
+        else hipLaunchKernelGGL((adjoint2_kernel<ST, LAW, FIELDS, false>), dim3(unsigned(nb)), block, 0, s, a);
+    };
+    const bool walls = !(a0.cm.periodic_x && a0.cm.periodic_y);
+    if (!walls) {
+        go(pair_map(nstrip, nblk, 0, nstrip, 0, nblk), false);
+        return;
+    }
+    // stage 1 of level m's traction links, from lambda^{m+1}
+    adj_traction_stage1<ST, LAW, FIELDS>(traction_args(a0, a0.rec1, a0.ed1, 0), s);
+    // the bulk: the blocks whose level-m region (columns c0 - 1 .. c0 + 64, rows y0 - 1 ..
+    // y0 + kPairRows) keeps two nodes away from every wall run the periodic code, the
+    // blocks along the walls the wall code (the same split as the two-level forward)
+    int s_lo = 0, s_hi = nstrip, b_lo = 0, b_hi = nblk;
+    if (!a0.cm.periodic_x) {
+        s_lo = 1;
+        s_hi = a0.cm.nx - 3 - kTile >= 0 ? (a0.cm.nx - 3 - kTile) / kTile + 1 : 0;
+    }
+    if (!a0.cm.periodic_y) {
+        b_lo = (3 + kPairRows - 1) / kPairRows;
+        b_hi = a0.cm.ny - 3 - kPairRows >= 0 ? (a0.cm.ny - 3 - kPairRows) / kPairRows + 1 : 0;
+    }
+    if (s_hi <= s_lo || b_hi <= b_lo) {
+        go(pair_map(nstrip, nblk, 0, nstrip, 0, nblk), true);
+    } else {
+        const PairMap inner = pair_map(nstrip, nblk, s_lo, s_hi, b_lo, b_hi);
+        PairMap rim = inner;
+        rim.mode = 1;
+        go(inner, false);
+        go(rim, true);
+    }
+    // the wall nodes over both levels (one wavefront per workgroup: latency-bound)
+    const int links = 2 * a0.cm.nx + 2 * a0.cm.ny;
+    hipLaunchKernelGGL((adjoint2_wall_kernel<ST, LAW, FIELDS>), dim3(unsigned((links + kTile - 1) / kTile)),
+                       dim3(kTile), 0, s, a0);
+    // level m - 1's traction links: stage 1 from the staged wall lines of lambda^m, then the
+    // scatter into lambda^{m-1} and the gradients
+    const AdjArgs t2 = traction_args(a0, a0.rec2, a0.ed2, 1);
+    adj_traction_stage1<ST, LAW, FIELDS>(t2, s);
+    if (t2.sblk[4] > 0) hipLaunchKernelGGL((adj_traction_scatter_kernel<ST>), dim3(t2.sblk[4]), dim3(kTile), 0, s, t2);
+}
+
 template <int ST, int LAW>
 static hipError_t adjoint2_st_law(const Adj2Args& a, hipStream_t s) {
     const bool fields = a.cm.mu || a.cm.lam || a.cm.body;
-    const dim3 grid(unsigned(pair_map_blocks(a.map)));
-    const dim3 block((kPairWaves + 1) * kTile);
-    if (fields) hipLaunchKernelGGL((adjoint2_kernel<ST, LAW, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((adjoint2_kernel<ST, LAW, false>), grid, block, 0, s, a);
+    if (fields) adjoint2_launch<ST, LAW, true>(a, s);
+    else adjoint2_launch<ST, LAW, false>(a, s);
     return hipGetLastError();
 }
 

@@ -441,12 +441,13 @@ lbm_status lbm_adjoint_probe_table(const lbm_params* p, const lbm_adj_state* adj
 }
 
 lbm_status lbm_adjoint_step2(const lbm_params* p, const lbm_state* fwd, lbm_adj_state* adj, int64_t m, double r_m,
-                             double r_mm1, const void* record_m, const void* record_mm1, const uint64_t* mask,
+                             double r_mm1, const lbm_edge_data* at_half, const lbm_edge_data* at_half_prev,
+                             const void* record_m, const void* record_mm1, const uint64_t* mask,
                              const double* field, void* stream) {
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
-    if (any_wall(p)) return LBM_ERR_UNSUPPORTED;
     if (!fwd || !adj || !adj->adj[0] || !adj->adj[1] || !record_m || !record_mm1) return LBM_ERR_ARG;
+    if (any_wall(p) && (!at_half || !at_half_prev || !adj->aux)) return LBM_ERR_ARG;
     if (adj->cur != 0 && adj->cur != 1) return LBM_ERR_ARG;
     if (adj->nprobe < 0 || (adj->nprobe > 0 && (!adj->probe || !adj->ubar || !mask || !field))) return LBM_ERR_ARG;
     if (m < 1 || m >= adj->nsteps) return LBM_ERR_ARG;
@@ -474,6 +475,11 @@ lbm_status lbm_adjoint_step2(const lbm_params* p, const lbm_state* fwd, lbm_adj_
     a.pmask = adj->nprobe > 0 ? mask : nullptr;
     a.pfield = adj->nprobe > 0 ? field : nullptr;
     a.probe_weight = a.cm.dt;                    // levels m and m - 1 are below N
+    a.aux = adj->aux;
+    if (any_wall(p)) {
+        a.ed1 = make_edges(at_half);
+        a.ed2 = make_edges(at_half_prev);
+    }
     if (launch_adjoint2(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
     adj->cur = 1 - adj->cur;
     return LBM_OK;

@@ -259,6 +259,8 @@ struct AdjArgs {
     double probe_weight;             // dt * (1 or 1/2)
     const uint64_t* pmask;           // probe table (mask, summed ubar field) or NULL
     const double* pfield;
+    int lines;                       // traction stage 1: lambda^{m+1} of the wall nodes from
+                                     // the staged wall lines of aux instead of src
 };
 
 struct Adj2Args {
@@ -278,6 +280,8 @@ struct Adj2Args {
     const uint64_t* pmask;           // probe table (lbm_adjoint_probe_table) or NULL
     const double* pfield;
     double probe_weight;             // weight of level m's probe source
+    void* aux;                       // grids with walls: traction staging and wall lines
+    EdgeData ed1, ed2;               // wall data at t^{m+1/2} and t^{m-1/2}
 };
 
 struct AdjInitArgs {

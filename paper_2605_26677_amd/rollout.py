@@ -283,14 +283,15 @@ class _Adjoint:
                                         _stream()), "lbm_adjoint_step")
 
     def pair_ok(self, sv, cfg, m, lowest):
-        """Levels m and m - 1 can go through lbm_adjoint_step2 (periodic grids, unless the
-        configuration turns pairs off)."""
-        return cfg.pairs is not False and self.periodic and lowest <= m - 1 and 1 <= m < cfg.nsteps
+        """Levels m and m - 1 can go through lbm_adjoint_step2 (unless the configuration
+        turns pairs off)."""
+        return cfg.pairs is not False and lowest <= m - 1 and 1 <= m < cfg.nsteps
 
     def step2(self, sv, cfg, m, record_m, record_mm1):
         L.check(sv.lib.lbm_adjoint_step2(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), int(m),
-                                         float(cfg.ramp(m)), float(cfg.ramp(m - 1)), _ptr(record_m),
-                                         _ptr(record_mm1), _ptr(self.pmask), _ptr(self.pfield), _stream()),
+                                         float(cfg.ramp(m)), float(cfg.ramp(m - 1)), ctypes.byref(_edges(cfg, m).c),
+                                         ctypes.byref(_edges(cfg, m - 1).c), _ptr(record_m), _ptr(record_mm1),
+                                         _ptr(self.pmask), _ptr(self.pfield), _stream()),
                 "lbm_adjoint_step2")
 
     def init(self, sv, cfg, v0, u0):

@@ -1,5 +1,6 @@
 """Two fused adjoint levels (lbm_adjoint_step2) against two single adjoint steps
-(lbm_adjoint_step), and the checkpointed rollout that uses them against the oracle.
+(lbm_adjoint_step), on periodic and walled grids, and the checkpointed rollout that uses
+them against the oracle.
 
 lbm_adjoint_step2 promises the result of lbm_adjoint_step(m) followed by
 lbm_adjoint_step(m - 1), bit for bit: the adjoint populations, the FP32 gradient block sums
@@ -96,7 +97,85 @@ def test_adjoint_step2_bitwise_equals_two_steps(storage, law, nx, ny):
         assert float(single.g_mu.abs().max()) > 0 and float(single.g_body.abs().max()) > 0
 
 
-def test_adjoint_step2_refuses_walls_and_level_N():
+WALL_KINDS = {"vttt": ("velocity", "traction", "traction", "traction"), "tttt": ("traction",) * 4,
+              "ppvt": ("periodic", "periodic", "velocity", "traction"),
+              "vvtv": ("velocity", "velocity", "traction", "velocity")}
+
+
+def _wall_data(m):
+    """Moving velocity walls and loaded traction walls, changing with the level, so that the
+    data of t^{m+1/2} and t^{m-1/2} differ."""
+    s = 1.0 + 0.05 * m
+    return [(1e-4 * s, -2e-4), (-1e-4, 1e-4 * s), (2e-4 * s, 1e-4), (-1e-4, -3e-4 * s)]
+
+
+def _setup_walls(nx, ny, storage, law, N, kinds):
+    rng = np.random.default_rng(11)
+    v0 = np.stack([li.gaussian_random_field(nx, ny, 661, 3e-3), li.gaussian_random_field(nx, ny, 662, 3e-3)])
+    mu = li.lognormal_field(nx, ny, 663, 0.1, 0.3, 4.0)
+    lam = li.lognormal_field(nx, ny, 664, 0.2, 0.3, 4.0)
+    body = li.uniform_body(nx, ny, (2e-4, -3e-4))
+    case = Case(f"adj2w_{law}_{nx}x{ny}", nx, ny, 2.5, 1.9, N, law=law, mu=mu, lam=lam, body=body, ramp_steps=6,
+                kinds=kinds, v0=v0)
+    sv = make_solver(case, storage)
+    sv.init(v0, r0=case.ramp(0))
+    recs = [sv.record_state(case.ramp(0), sv.new_record())]
+    for n in range(N):
+        r = sv.new_record()
+        sv.step(n, case.ramp(n), case.ramp(n + 1), edges=_wall_data(n), record=r)
+        recs.append(r)
+    assert sv.faults() == 0
+    # probes on the wall lines, at corners, next to the walls and inside
+    cells = {0, nx - 1, (ny - 1) * nx, ny * nx - 1, (ny // 2) * nx, (ny // 2) * nx + nx - 1, nx // 2,
+             (ny - 1) * nx + nx // 3, 1 * nx + 1, (ny // 3) * nx + (63 % nx)}
+    cells |= set(rng.choice(nx * ny, size=4, replace=False).tolist())
+    cells = np.array(sorted(cells))
+    ubar = rng.standard_normal((2, cells.size))
+    return case, sv, recs, cells, ubar
+
+
+def _adjoint_state_walls(sv, case, N, cells, ubar):
+    from paper_2605_26677_amd.rollout import RolloutConfig, _Adjoint
+    cfg = RolloutConfig(nx=case.nx, ny=case.ny, c=case.c, omega=case.omega, nsteps=N,
+                        probes=torch.tensor(cells, dtype=torch.int64), storage=sv.storage, ramp=case.ramp,
+                        bc=tuple(case.kinds), edges=_wall_data)
+    return cfg, _Adjoint(sv, cfg, torch.tensor(ubar))
+
+
+@pytest.mark.parametrize("kinds", list(WALL_KINDS))
+@pytest.mark.parametrize("nx,ny", [(64, 40), (200, 64), (130, 13), (4, 5)])
+@pytest.mark.parametrize("storage,law", [("f32", "lognh"), ("f64", "lognh"), ("f16", "lognh"), ("f32", "gent"),
+                                         ("f64", "svk")])
+def test_walled_adjoint_step2_bitwise_equals_two_steps(storage, law, nx, ny, kinds):
+    """Walled grids: velocity and traction walls with level-dependent data, corners of every
+    kind, a periodic axis beside walls, grids with and without interior blocks and grids
+    smaller than one block; probes on walls and corners; both fold phases."""
+    N = 21
+    kd = WALL_KINDS[kinds]
+    case, sv, recs, cells, ubar = _setup_walls(nx, ny, storage, law, N, kd)
+    for lead in (1, 2):
+        cfg, single = _adjoint_state_walls(sv, case, N, cells, ubar)
+        _, pair = _adjoint_state_walls(sv, case, N, cells, ubar)
+        for st in (single, pair):
+            for k in range(lead):
+                st.step(sv, cfg, N - k, recs[N - k])
+        m = N - lead
+        while m >= 1:
+            single.step(sv, cfg, m, recs[m])
+            single.step(sv, cfg, m - 1, recs[m - 1])
+            pair.step2(sv, cfg, m, recs[m], recs[m - 1])
+            m -= 2
+        torch.cuda.synchronize()
+        assert torch.equal(_valid_adj(sv, single), _valid_adj(sv, pair)), lead
+        if storage != "f64":
+            assert torch.equal(_valid_gsum(sv, single), _valid_gsum(sv, pair)), lead
+        for name in ("g_mu", "g_lam", "g_body"):
+            assert torch.equal(getattr(single, name), getattr(pair, name)), (lead, name)
+        assert float(single.g_mu.abs().max()) > 0 and float(single.g_body.abs().max()) > 0
+    assert sv.faults() == 0
+
+
+def test_adjoint_step2_refuses_level_N_and_0():
     from paper_2605_26677_amd._lib import LBMError
     N = 6
     case, sv, recs, cells, ubar = _setup(32, 32, "f32", "lognh", N)
