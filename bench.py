@@ -7,8 +7,16 @@ A "step" is one time level of the whole hot path (pull streaming, moments, const
 update, equilibrium, collision, store, displacement quadrature) over the whole grid; inputs
 are resident in HBM before timing.  The headline runs the steps in pairs through lbm_step2
 (two levels per pass over HBM, bit for bit the result of two lbm_step calls); the single-
-level lbm_step is timed beside it.  Also measured: FP64 and FP16 storage of the same step,
-and forward + adjoint with every-K checkpointing on per-node mu, lam fields.
+level lbm_step is timed beside it.  Also measured:
+  - FP64 and FP16 storage of the same step, and the St. Venant-Kirchhoff law;
+  - forward + adjoint at 8192^2 with every-K checkpointing on per-node mu, lam fields
+    (FP32 200 levels every 50; FP32 and FP64 on one schedule, 100 levels every 25), with
+    the HBM roofline fraction of the whole run from the kernels' algorithmic bytes;
+  - the walled 1024^2 block, a launch-bound 256^2 grid with and without HIP graphs;
+  - the walled 4096^2 adjoint workload (20 000 steps, 256 probes, 64 GiB device budget,
+    device only and with the outermost checkpoints in pinned host memory), its gradient
+    checked against FP64 central differences on 8 directions;
+  - the FP64 numpy oracle on one host core.
 
 Prints one JSON line.  Only --gpus 1 is supported.
 """
@@ -18,7 +26,12 @@ import os
 import sys
 import time
 
-import numpy as np
+# the CPU baseline runs the numpy oracle on one core; set before numpy is imported
+os.environ["OMP_NUM_THREADS"] = "1"
+os.environ["OPENBLAS_NUM_THREADS"] = "1"
+os.environ["MKL_NUM_THREADS"] = "1"
+
+import numpy as np  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -33,6 +46,42 @@ BYTES_PER_LU = {"f32": 96 + 96 + 16 + 32 / 16, "f16": 48 + 48 + 16 + 32 / 16, "f
 # the same per launch of the two-level kernel (lbm_step2): populations read and written
 # once per two levels, S read + written once, U folded once per 8 launches
 BYTES_PER_LU_PAIR = {"f32": 96 + 96 + 16 + 32 / 8, "f16": 48 + 48 + 16 + 32 / 8, "f64": 192 + 192 + 32}
+
+
+# Single-pass algorithmic bytes per lattice update of the path (one level, every value
+# through HBM once): 24 populations read + written, the compensated u* pair read + written
+BYTES_PER_LU_SINGLE_PASS = {"f32": 96 + 96 + 32, "f16": 48 + 48 + 32, "f64": 192 + 192 + 32}
+
+# Algorithmic bytes per node and launch of the kernels of the forward + adjoint run (FP32,
+# per-node mu, lam and body force b, two levels per launch):
+#   forward step2_kernel: populations 96 + 96, u* block sum S 8 + 8, U fold 32 / 8, mu lam 8,
+#     b 8 -> 228
+#   replay step2_kernel with the records of both levels, no u*: 96 + 96, records 2 x 24,
+#     mu lam 8, b 8 -> 256
+#   adjoint2_kernel: adjoint populations 96 + 96, F - I of two records 2 x 16, mu lam 8,
+#     FP32 block sums 4 x 4 read + written 32, FP64 fold 64 / 8 -> 272
+#   every-K snapshot: populations and record copied (read + written) once per K levels
+# (FP64: populations 192 + 192, u* 16 + 16, records 2 x 48, adjoint F - I 2 x 32, mu lam 8,
+# b 8; gradients added to the FP64 planes directly, 4 x 8 read + written per level)
+FWD_ADJ_BYTES = {
+    "f32": dict(fwd=228, replay=256, adj=272, snapshot=2 * (96 + 24)),
+    "f64": dict(fwd=192 + 192 + 32 + 8 + 8, replay=192 + 192 + 96 + 8 + 8, adj=192 + 192 + 64 + 8 + 2 * 64,
+                snapshot=2 * (192 + 48)),
+}
+
+
+# The same run in the single-pass model (every level of every pass through HBM once, per
+# node and level): forward (populations, u* pair, mu lam 8, b 8) + replay (populations, the
+# record of U written, mu lam, b) + adjoint (adjoint populations, U of the record, mu lam,
+# FP64 gradients of mu, lam, b1, b2 read + written 64)
+SINGLE_PASS_FWD_ADJ = {"f32": (224 + 16) + (192 + 24 + 16) + (192 + 24 + 8 + 64),
+                       "f64": (416 + 16) + (384 + 48 + 16) + (384 + 48 + 8 + 64)}
+
+
+def fwd_adj_bytes_per_level(storage, K):
+    """Algorithmic bytes per node and level of the every-K forward + adjoint run in pairs."""
+    b = FWD_ADJ_BYTES[storage]
+    return (b["fwd"] + b["replay"] + b["adj"]) / 2 + b["snapshot"] / K
 
 
 PROFILE_PMC = {"step": os.path.join(ROOT, "profiles", "step_f32_lognh_periodic_8192_pmc.txt"),
@@ -242,64 +291,88 @@ def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32"):
     t_f, t_b = e0.elapsed_time(e1), e1.elapsed_time(e2)
     mem = torch.cuda.max_memory_allocated() / 2 ** 30
     ok = all(torch.isfinite(t.grad).all().item() for t in (mu, lam, v0))
+    bpl = fwd_adj_bytes_per_level(storage, K)
+    gbs = bpl * n * n * steps / ((t_f + t_b) * 1e-3) / 1e9
+    single = SINGLE_PASS_FWD_ADJ[storage]
     out = dict(ms_fwd=t_f, ms_bwd=t_b, mlups=n * n * steps / ((t_f + t_b) * 1e-3) / 1e6,
                bwd_over_fwd=t_b / t_f, peak_mem_GiB=mem, grads_finite=ok, steps=steps, K=K, c=c,
-               storage=storage)
+               storage=storage,
+               roofline={"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                         "frac": gbs * 1e9 / PEAK_HBM,
+                         "bytes_per_node_level": bpl,
+                         "byte_model": "blocked kernels per launch / 2 levels: forward step2 "
+                                       f"{FWD_ADJ_BYTES[storage]['fwd']}, recorded replay step2 "
+                                       f"{FWD_ADJ_BYTES[storage]['replay']}, adjoint2 "
+                                       f"{FWD_ADJ_BYTES[storage]['adj']} B per node and launch, snapshots "
+                                       f"{FWD_ADJ_BYTES[storage]['snapshot']} B per node every K levels",
+                         "single_pass_bytes_per_node_level": single,
+                         "single_pass_effective_GBps": single * n * n * steps / ((t_f + t_b) * 1e-3) / 1e9})
     del u, mu, lam, body, v0
     torch.cuda.empty_cache()
     return out
 
 
-def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0, host_gib=0.0):
+def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0, host_gibs=(0.0,)):
     """The large adjoint workload: n x n, velocity wall (v = 0) at the bottom, traction
     (0, -2e-4 min(1, t/(2000 dt))) on the top evaluated at t^{m+1/2}, traction-free sides,
     per-node log-NH mu, lam log-normal fields (median 0.1 / 0.4, sigma_log 0.3, correlation
-    length 32), c = 10 (traction-free corners go unstable over thousands of steps at
-    lattice speeds near the P-wave bound), omega = 2 - 1.6/n, loss sum |u|^2 at 256
-    random probes after `steps` steps, FP32 forward and
-    adjoint with FP64 gradient accumulation, checkpoint levels planned for a device-memory
-    budget.  Reports forward + adjoint throughput, peak device memory against the budget
-    and the relative error of directional derivatives against FP64 central differences."""
+    length 32), c = 10 (at c near twice the P-wave speed the walled runs go unstable after
+    some thousands of steps when omega is this close to 2), omega = 2 - 1.6/n, loss sum |u|^2
+    at 256 random probes after `steps` steps, FP32 forward and adjoint with FP64 gradient
+    accumulation, checkpoint levels planned for a device-memory budget (and, for each entry
+    of host_gibs above 0, with the outermost level in that much pinned host memory).
+    Reports forward + adjoint throughput, peak device memory against the budget and the
+    relative error of directional derivatives against FP64 central differences: half of
+    the directions perturb every parameter group at once, the others one group each (mu,
+    lam, b, v0 in turn)."""
     import torch
     import lbm_inputs as li
     from paper_2605_26677_amd.rollout import RolloutConfig, plan_checkpoints, rollout
     budget = int(budget_gib * 2 ** 30)
-    plan = plan_checkpoints(n, n, "f32", steps, budget, int(host_gib * 2 ** 30))
-    levels, host_top, model = plan["levels"], plan["host_top"], plan["model"]
-    log(f"bench: adjoint at scale {n}^2 x {steps}, levels {levels}, outer level on host {host_top}, "
-        f"model device peak {model['peak'] / 2**30:.1f} GiB, host {model['host'] / 2**30:.1f} GiB")
-    mu0 = li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0)
-    lam0 = li.lognormal_field(n, n, 402, 0.4, 0.3, 32.0)
-    ys, xs = li.random_probes(n, n, 256, 405)
+    mu0 = li.lognormal_field(n, n, 501, 0.1, 0.3, 32.0)
+    lam0 = li.lognormal_field(n, n, 502, 0.4, 0.3, 32.0)
+    ys, xs = li.random_probes(n, n, 256, 505)
     probes = torch.tensor(ys * n + xs, dtype=torch.int64)
     top = lambda m: (0.0, -2e-4 * min(1.0, (m + 0.5) / 2000.0))
     common = dict(nx=n, ny=n, c=c, omega=2.0 - 1.6 / n, nsteps=steps, probes=probes,
                   bc=("traction", "traction", "velocity", "traction"),
                   edges=lambda m: [(0.0, 0.0), (0.0, 0.0), (0.0, 0.0), top(m)])
     dev = "cuda"
-    torch.cuda.synchronize()
-    torch.cuda.empty_cache()
-    torch.cuda.reset_peak_memory_stats()
-    base_mem = torch.cuda.memory_allocated()
-    mu = torch.tensor(mu0, dtype=torch.float64, device=dev, requires_grad=True)
-    lam = torch.tensor(lam0, dtype=torch.float64, device=dev, requires_grad=True)
-    body = torch.zeros((2, n, n), dtype=torch.float64, device=dev, requires_grad=True)
-    v0 = torch.zeros((2, n, n), dtype=torch.float64, device=dev, requires_grad=True)
-    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    e0.record()
-    u = rollout(mu, lam, body, v0, RolloutConfig(storage="f32", levels=levels, host_top=host_top, **common))
-    e1.record()
-    torch.cuda.synchronize()
-    log(f"bench: forward done, {e0.elapsed_time(e1) / 1e3:.1f} s")
-    (u.double() ** 2).sum().backward()
-    e2.record()
-    torch.cuda.synchronize()
-    t_f, t_b = e0.elapsed_time(e1), e1.elapsed_time(e2)
-    peak = torch.cuda.max_memory_allocated() - base_mem
-    log(f"bench: backward done, {t_b / 1e3:.1f} s, peak {peak / 2**30:.1f} GiB")
-    g = {k: t.grad.cpu().numpy() for k, t in (("mu", mu), ("lam", lam), ("body", body), ("v0", v0))}
-    del mu, lam, body, v0, u
-    torch.cuda.empty_cache()
+    runs = []
+    g = None
+    for host_gib in host_gibs:
+        plan = plan_checkpoints(n, n, "f32", steps, budget, int(host_gib * 2 ** 30))
+        levels, host_top, model = plan["levels"], plan["host_top"], plan["model"]
+        log(f"bench: adjoint at scale {n}^2 x {steps}, levels {levels}, outer level on host {host_top}, "
+            f"model device peak {model['peak'] / 2**30:.1f} GiB, host {model['host'] / 2**30:.1f} GiB")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        base_mem = torch.cuda.memory_allocated()
+        mu = torch.tensor(mu0, dtype=torch.float64, device=dev, requires_grad=True)
+        lam = torch.tensor(lam0, dtype=torch.float64, device=dev, requires_grad=True)
+        body = torch.zeros((2, n, n), dtype=torch.float64, device=dev, requires_grad=True)
+        v0 = torch.zeros((2, n, n), dtype=torch.float64, device=dev, requires_grad=True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        u = rollout(mu, lam, body, v0, RolloutConfig(storage="f32", levels=levels, host_top=host_top, **common))
+        e1.record()
+        torch.cuda.synchronize()
+        log(f"bench: forward done, {e0.elapsed_time(e1) / 1e3:.1f} s")
+        (u.double() ** 2).sum().backward()
+        e2.record()
+        torch.cuda.synchronize()
+        t_f, t_b = e0.elapsed_time(e1), e1.elapsed_time(e2)
+        peak = torch.cuda.max_memory_allocated() - base_mem
+        log(f"bench: backward done, {t_b / 1e3:.1f} s, peak {peak / 2**30:.1f} GiB")
+        if g is None:
+            g = {k: t.grad.cpu().numpy() for k, t in (("mu", mu), ("lam", lam), ("body", body), ("v0", v0))}
+        runs.append(dict(levels=levels, host_top=host_top, host_budget_GiB=host_gib,
+                         model_host_GiB=model["host"] / 2 ** 30, model_peak_GiB=model["peak"] / 2 ** 30,
+                         peak_mem_GiB=peak / 2 ** 30, forward_passes=model["forward_passes"], ms_fwd=t_f,
+                         ms_bwd=t_b, bwd_over_fwd=t_b / t_f, mlups=n * n * steps / ((t_f + t_b) * 1e-3) / 1e6))
+        del mu, lam, body, v0, u
+        torch.cuda.empty_cache()
     cfg64 = RolloutConfig(storage="f64", **common)
 
     def loss(p):
@@ -310,24 +383,36 @@ def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0, host_gib=0.0):
 
     base = dict(mu=mu0, lam=lam0, body=np.zeros((2, n, n)), v0=np.zeros((2, n, n)))
     scale = dict(mu=0.1, lam=0.4, body=1e-6, v0=1e-4)
-    errs = []
-    for d in li.fd_directions({k: base[k].shape for k in base}, fd_dirs, 406):
+    groups = list(base)
+    dirs = li.fd_directions({k: base[k].shape for k in base}, fd_dirs, 406)
+    errs, kinds, scaled, cancel = [], [], [], []
+    for j, d in enumerate(dirs):
+        # the first half joint, the rest one group each
+        only = None if j < (fd_dirs + 1) // 2 else groups[(j - (fd_dirs + 1) // 2) % len(groups)]
         plus, minus = {}, {}
         for k in base:
-            step = 1e-3 * scale[k] * d[k]
+            step = 1e-3 * scale[k] * d[k] * (1.0 if only in (None, k) else 0.0)
             if k == "v0":
                 plus[k], minus[k] = base[k] + step, base[k] - step
             else:
                 plus[k], minus[k] = li.round_f32(base[k] + step), li.round_f32(base[k] - step)
         fd = loss(plus) - loss(minus)
         an = sum((g[k] * (plus[k] - minus[k])).sum() for k in base)
+        # the sum of |dL/dp_i dp_i|: where the terms of the directional derivative cancel,
+        # the rounding of the FP32 adjoint shows relative to this sum, not to the result
+        mag = sum(np.abs(g[k] * (plus[k] - minus[k])).sum() for k in base)
         errs.append(abs(fd - an) / abs(fd))
-        log(f"bench: FD {fd:.6e} adjoint {an:.6e} rel {errs[-1]:.2e}")
-    return dict(grid=[n, n], steps=steps, levels=levels, host_top=host_top, budget_GiB=budget_gib,
-                host_budget_GiB=host_gib, model_host_GiB=model["host"] / 2 ** 30,
-                model_peak_GiB=model["peak"] / 2 ** 30, peak_mem_GiB=peak / 2 ** 30,
-                forward_passes=model["forward_passes"], ms_fwd=t_f, ms_bwd=t_b, bwd_over_fwd=t_b / t_f,
-                mlups=n * n * steps / ((t_f + t_b) * 1e-3) / 1e6, fd_rel_err=errs, c=c)
+        scaled.append(abs(fd - an) / mag)
+        cancel.append(mag / abs(an))
+        kinds.append(only or "all")
+        log(f"bench: FD ({kinds[-1]}) {fd:.6e} adjoint {an:.6e} rel {errs[-1]:.2e} "
+            f"(sum |terms| / |result| {cancel[-1]:.1f}, error / sum |terms| {scaled[-1]:.2e})")
+    best = min(runs, key=lambda r: r["ms_bwd"])
+    return dict(grid=[n, n], steps=steps, budget_GiB=budget_gib, runs=runs, c=c,
+                ms_fwd=best["ms_fwd"], ms_bwd=best["ms_bwd"], bwd_over_fwd=best["bwd_over_fwd"],
+                mlups=best["mlups"], fd_rel_err=[float(e) for e in errs], fd_groups=kinds,
+                fd_cancellation=[float(x) for x in cancel], fd_err_over_term_sum=[float(x) for x in scaled],
+                fd_max_rel_err=float(max(errs)), fd_max_err_over_term_sum=float(max(scaled)))
 
 
 def profile_run(n, steps):
@@ -348,23 +433,51 @@ def profile_run(n, steps):
                       "ms_per_level_pairs": ms2, "faults_pairs": faults2, "fwd_adj": adj}))
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(budget_s=20.0):
-    """The FP64 oracle on the host: 1024 x 1024 sample of the same workload."""
+    """The FP64 oracle on the host, one core (OMP_NUM_THREADS=1 before numpy's import; the
+    process CPU time over the wall time confirms it): the 64 x 64 shear-wave workload in full
+    (200 steps) and a bounded sample of the headline workload, the 1024 x 1024 periodic
+    random-field grid (at most 50 steps or budget_s seconds).  The value is the 1024^2
+    sample's rate, in the headline's unit."""
     from oracle import lbm as olbm
+    import lbm_inputs as li
+    out = {}
+    # the 64 x 64 shear wave of the plain-method workload, in full
+    pb = olbm.Problem(nx=64, ny=64, c=2.0, omega=2.0, law="lognh", mu=0.1, lam=0.2)
+    st = olbm.initial_state(pb, li.shear_wave_v0(64, 64))
+    t0, c0 = time.perf_counter(), time.process_time()
+    for _ in range(200):
+        olbm.step(pb, st)
+    dt1, ct1 = time.perf_counter() - t0, time.process_time() - c0
+    out["shear_wave_64"] = dict(steps=200, seconds=dt1, mlups=64 * 64 * 200 / dt1 / 1e6)
     n = 1024
     v0 = make_inputs(n)
     pb = olbm.Problem(nx=n, ny=n, c=2.0, omega=2.0, law="lognh", mu=0.1, lam=0.2)
     st = olbm.initial_state(pb, v0)
-    t0 = time.perf_counter()
+    t0, c0 = time.perf_counter(), time.process_time()
     steps = 0
     while True:
         olbm.step(pb, st)
         steps += 1
         if time.perf_counter() - t0 > budget_s or steps >= 50:
             break
-    dt = time.perf_counter() - t0
+    dt, ct = time.perf_counter() - t0, time.process_time() - c0
     return dict(value=n * n * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
-                sample=f"1024x1024 periodic random-field workload, {steps} FP64 numpy oracle steps, {dt:.1f} s")
+                sample=f"1024x1024 periodic random-field workload (the 8192^2 headline's setup on a "
+                       f"1024^2 grid), {steps} FP64 numpy oracle steps, {dt:.1f} s",
+                cpu_time_over_wall=(ct + ct1) / (dt + dt1), omp_num_threads=os.environ.get("OMP_NUM_THREADS"),
+                cpu_model=_cpu_model(), os_cpu_count=os.cpu_count(), **out)
 
 
 def main():
@@ -387,9 +500,11 @@ def main():
     ap.add_argument("--scale-size", type=int, default=4096)
     ap.add_argument("--scale-steps", type=int, default=20000)
     ap.add_argument("--scale-budget-gib", type=float, default=64.0)
-    ap.add_argument("--scale-fd-dirs", type=int, default=1)
-    ap.add_argument("--scale-host-gib", type=float, default=48.0,
-                    help="pinned host memory for the outermost checkpoints (0: device only)")
+    ap.add_argument("--scale-fd-dirs", type=int, default=8)
+    ap.add_argument("--scale-host-gib", default="0,48",
+                    help="comma list of pinned host memory sizes (GiB) for the outermost checkpoints, "
+                         "one timed run each (0: device only)")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 4096^2 adjoint workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
@@ -405,7 +520,7 @@ def main():
         return
     if args.adjoint_at_scale:
         r = adjoint_at_scale(args.scale_size, args.scale_steps, args.scale_budget_gib, args.scale_fd_dirs,
-                             host_gib=args.scale_host_gib)
+                             host_gibs=[float(x) for x in args.scale_host_gib.split(",")])
         print(json.dumps({"adjoint_at_scale": r}), flush=True)
         return
     log(f"bench: generating {n}x{n} inputs")
@@ -447,12 +562,20 @@ def main():
         log(f"bench: forward + adjoint, {args.adjoint_steps} steps, checkpoint every {args.adjoint_every}")
         res["fwd_adj_f32"] = time_forward_adjoint(n, args.adjoint_steps, args.adjoint_every)
         log(f"bench: fwd+adj: {res['fwd_adj_f32']}")
-        # FP64: half the levels and half the segment length, so that the every-K schedule
-        # (the same levels per segment) fits the 268 GiB of HBM (212 GiB modelled)
-        log(f"bench: forward + adjoint FP64, {args.adjoint_steps // 2} steps, "
-            f"checkpoint every {args.adjoint_every // 2}")
-        res["fwd_adj_f64"] = time_forward_adjoint(n, args.adjoint_steps // 2, args.adjoint_every // 2, storage="f64")
-        log(f"bench: fwd+adj f64: {res['fwd_adj_f64']}")
+        # FP32 against FP64 on one schedule: FP64 takes half the levels and half the segment
+        # length, because 200 levels every 50 do not fit the 288 GB of HBM in FP64 (5
+        # snapshots of 16.1 GB, 51 records of 3.2 GB, about 60 GB of working buffers)
+        half_n, half_k = args.adjoint_steps // 2, args.adjoint_every // 2
+        for st in ("f32", "f64"):
+            log(f"bench: forward + adjoint {st}, {half_n} steps, checkpoint every {half_k}")
+            res[f"fwd_adj_{st}_{half_n}"] = time_forward_adjoint(n, half_n, half_k, storage=st)
+            log(f"bench: fwd+adj {st}: {res[f'fwd_adj_{st}_{half_n}']}")
+    if not args.no_scale:
+        log("bench: the 4096^2 walled adjoint workload")
+        res["adjoint_at_scale"] = adjoint_at_scale(args.scale_size, args.scale_steps, args.scale_budget_gib,
+                                                   args.scale_fd_dirs,
+                                                   host_gibs=[float(x) for x in args.scale_host_gib.split(",")])
+        log(f"bench: adjoint at scale: {res['adjoint_at_scale']}")
     log("bench: copy ceiling")
     copy_gbs = copy_ceiling()
     main_storage = "f32" if "f32" in only else only[0]
@@ -471,7 +594,20 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "step2_kernel", "achieved": r["algorithmic_GBps"],
                      "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": r["frac_hbm"], "traffic": traffic,
                      "algorithmic_bytes_per_launch": BYTES_PER_LU_PAIR[main_storage] * n * n,
-                     "launch_ms": r["launch_ms"], "copy_ceiling_GBps": copy_gbs},
+                     "launch_ms": r["launch_ms"], "copy_ceiling_GBps": copy_gbs,
+                     "byte_models": {
+                         "blocked_per_launch": {
+                             "bytes_per_node": BYTES_PER_LU_PAIR[main_storage], "levels_per_launch": 2,
+                             "achieved_GBps": r["algorithmic_GBps"], "frac": r["frac_hbm"],
+                             "note": "what step2_kernel itself moves per launch (two levels)"},
+                         "single_pass_per_level": {
+                             "bytes_per_node": BYTES_PER_LU_SINGLE_PASS[main_storage],
+                             "effective_GBps": BYTES_PER_LU_SINGLE_PASS[main_storage] * n * n
+                             / (r["ms_per_step"] * 1e-3) / 1e9,
+                             "frac": BYTES_PER_LU_SINGLE_PASS[main_storage] * n * n
+                             / (r["ms_per_step"] * 1e-3) / PEAK_HBM,
+                             "note": "bytes one level would move in a single pass, per level time; above 1 "
+                                     "because two levels share one pass"}}},
         "single_step_roofline": None,
         "variants": res,
     }
@@ -482,6 +618,18 @@ def main():
             "unit": "GB/s", "frac": r1["frac_hbm"],
             "traffic": measured_traffic(n, "step") if main_storage == "f32" else None,
             "algorithmic_bytes_per_launch": BYTES_PER_LU[main_storage] * n * n, "mlups": r1["mlups"]}
+    fa = {}
+    for key, label in (("fwd_adj_f32", "f32"), (f"fwd_adj_f32_{args.adjoint_steps // 2}", "f32_same_schedule_as_f64"),
+                       (f"fwd_adj_f64_{args.adjoint_steps // 2}", "f64")):
+        if key in res:
+            v = res[key]
+            fa[label] = dict(mlups=v["mlups"], frac_hbm=v["roofline"]["frac"], steps=v["steps"], K=v["K"],
+                             bwd_over_fwd=v["bwd_over_fwd"])
+    if fa:
+        out["fwd_adjoint"] = fa
+    if "f64_pairs" in res:
+        out["fwd_f64"] = dict(mlups=res["f64_pairs"]["mlups"], frac_hbm=res["f64_pairs"]["frac_hbm"],
+                              mlups_single=res.get("f64", {}).get("mlups"))
     if not args.no_cpu:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline()
