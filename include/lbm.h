@@ -172,14 +172,23 @@ lbm_status lbm_check_params(const lbm_params *p);
 /* Lattice-speed audit (Sec. 4 audits c against the largest tangent wave speed, Table
  * tab:validation-setup): at F = I the fastest wave is the P wave, sqrt(lam + 2 mu) for the
  * Lame-parametrised laws and sqrt(lam + 4/3 G) for the invariant laws with small-strain
- * shear modulus G; the linearised D2Q4 x 6 step is stable for a P-wave speed of at most
- * c/2 at omega = 2.  Returns LBM_ERR_CFL above that ratio, LBM_OK otherwise.  Finite
- * strains can raise the tangent speeds (lbm_diagnostics out[9] audits the current state).
- * Grids whose walls meet at corners need more margin over long runs: a slowly growing
- * corner instability was observed at a P-wave speed of c/4 after some thousands of steps
- * (none at c/5 over 8000 steps, nor at c/16 over 20000); the bound of c/2 is the periodic
- * one. */
+ * shear modulus G.  Returns LBM_ERR_CFL
+ *   - when that speed exceeds c/2: the linearised D2Q4 x 6 step is then unstable in the
+ *     bulk at omega = 2 (periodic grids);
+ *   - on a grid with a traction edge, when lbm_wall_mode_growth exceeds 2e-4 per step (an
+ *     e-folding within 5000 steps): traction walls carry modes confined to the wall line
+ *     and its corners that grow at omega = 2 at a rate set by c_p / c and independent of
+ *     the grid size, so they need 2 - omega > 0 to be damped;
+ * and LBM_OK otherwise.  Finite strains can raise the tangent speeds (lbm_diagnostics out[9]
+ * audits the current state).  lbm_init runs this audit unless force_unstable, which short
+ * runs near omega = 2 (the manufactured solutions of Sec. 4.2) set. */
 lbm_status lbm_check_cfl(const lbm_params *p, double mu_max, double lam_max);
+
+/* Estimated growth per step of the traction-wall modes (0 without a traction edge): a
+ * measured growth at omega = 2 as a function of c_p / c (linear between the measured ratios
+ * 0.05 ... 0.28 and beyond them along the last segment), minus 0.45 (2 - omega), the damping
+ * the BGK rate gives them.  A negative value means the modes decay. */
+double lbm_wall_mode_growth(const lbm_params *p, double mu_max, double lam_max);
 
 /* ------------------------------------------------------------------ forward */
 

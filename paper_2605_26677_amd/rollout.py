@@ -53,6 +53,8 @@ class RolloutConfig:
     pairs: Optional[bool] = None                       # forward levels in pairs (lbm_step2):
                                                        # None where faster (Solver.pairs_pay),
                                                        # True wherever they apply, False never
+    force_unstable: bool = False                       # skip the lattice-speed audit (short
+                                                       # runs outside its long-run region)
 
     def __post_init__(self):
         check_probes(self.probes, self.nx, self.ny)
@@ -393,7 +395,7 @@ class LBMRollout(torch.autograd.Function):
         sv = Solver(cfg.nx, cfg.ny, c=cfg.c, omega=cfg.omega, dx=cfg.dx, material=cfg.material,
                     storage=cfg.storage, bc=tuple(cfg.bc), mu=mu.detach(), lam=lam.detach(),
                     body=body.detach(), newton_max_iter=cfg.newton_max_iter, law_k=cfg.law_k,
-                    device=mu.device)
+                    force_unstable=cfg.force_unstable, device=mu.device)
         v0d = v0.detach().to(torch.float64).contiguous()
         u0 = None if cfg.u0 is None else cfg.u0.to(device=mu.device, dtype=torch.float64).contiguous()
         sv.init(v0d, u0, r0=cfg.ramp(0), Fbar=cfg.Fbar)

@@ -40,6 +40,8 @@ class Case:
     u0: Optional[np.ndarray] = None
     dx: float = 1.0
     law_k: Optional[tuple] = None        # invariant-law constants (None: LAW_K[law])
+    force_unstable: bool = False         # skip the lattice-speed audit (a short transient
+                                         # outside the long-run stability region)
 
     def ramp(self, n):
         return 1.0 if self.ramp_steps == 0 else min(1.0, n / self.ramp_steps)
@@ -63,9 +65,12 @@ def block_case(nx=96, ny=80, steps=300, law="lognh", fields=False):
     lam = li.lognormal_field(nx, ny, 402, 0.3, 0.3, 8.0) if fields else 0.3
     body = li.uniform_body(nx, ny, (0.0, -2e-4)) if fields else (0.0, -2e-4)
     v0 = np.stack([li.gaussian_random_field(nx, ny, 403, 1e-3), li.gaussian_random_field(nx, ny, 404, 1e-3)])
+    # with the per-node fields the largest P-wave speed is 0.48 c, where the traction-wall
+    # modes grow by about 4e-3 per step at omega = 1.99 (lbm_wall_mode_growth): the audit
+    # refuses such a run for long times, and this parity case runs a few hundred steps
     return Case(f"block_{law}_{'fields' if fields else 'uniform'}", nx, ny, 2.5, 1.99, steps, law=law,
                 mu=mu, lam=lam, body=body, ramp_steps=50,
-                kinds=("velocity", "traction", "traction", "traction"), v0=v0)
+                kinds=("velocity", "traction", "traction", "traction"), v0=v0, force_unstable=fields)
 
 
 def mixed_case(nx=40, ny=36, steps=120, law="lognh"):
@@ -107,7 +112,7 @@ def make_solver(case, storage):
     law_k = case.law_k if case.law_k is not None else LAW_K.get(case.law)
     return Solver(case.nx, case.ny, c=case.c, omega=case.omega, dx=case.dx, material=case.law,
                   storage=storage, bc=tuple(case.kinds), mu=case.mu, lam=case.lam, body=case.body,
-                  law_k=law_k)
+                  law_k=law_k, force_unstable=case.force_unstable)
 
 
 def run_library(case, storage, steps=None):

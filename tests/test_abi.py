@@ -189,3 +189,29 @@ def test_step2_argument_checks():
     s.aux = None
     assert lib.lbm_step2(ctypes.byref(p), ctypes.byref(s), 0, 1.0, 1.0, 1.0, ctypes.byref(ed), ctypes.byref(ed),
                          None, None, None) == L.LBM_ERR_ARG
+
+
+@pytest.mark.parametrize("bc", [(2, 2, 2, 2), (1, 2, 2, 2), (0, 0, 2, 2)])
+def test_traction_wall_stability_region(bc):
+    """Traction walls carry modes that grow at omega = 2 at a rate set by c_p / c; the audit
+    refuses what the measured map (FP64, 512^2) shows growing, and passes what it shows
+    decaying.  mu = 0.1, lam = 0.3 (c_p = 0.707):
+      c = 2.5, omega = 1.996875 (2 - 1.6/512): grows (+3e-3 per step) -> refused;
+      c = 2.5, omega = 1.99: decays -> passes;
+      c = 3.5, omega = 1.998: grows (+7e-4) -> refused;  omega = 1.995: decays -> passes;
+      c = 10, omega = 1.9995: decays -> passes;
+      periodic grids and velocity walls only: no wall term."""
+    lib = L.lib()
+    mu, lam = 0.1, 0.3
+    p = _params(64, 64, bc=bc)
+    for c, om, ok in ((2.5, 2.0 - 1.6 / 512, False), (2.5, 1.99, True), (3.5, 1.998, False),
+                      (3.5, 1.995, True), (10.0, 1.9995, True), (10.0, 2.0, False)):
+        p.c, p.omega = c, om
+        want = L.LBM_OK if ok else L.LBM_ERR_CFL
+        assert lib.lbm_check_cfl(ctypes.byref(p), mu, lam) == want, (c, om)
+        g = lib.lbm_wall_mode_growth(ctypes.byref(p), mu, lam)
+        assert (g <= 2e-4) == ok, (c, om, g)
+    p = _params(64, 64, bc=(1, 1, 1, 1))
+    p.c, p.omega = 2.5, 2.0
+    assert lib.lbm_wall_mode_growth(ctypes.byref(p), mu, lam) == 0.0
+    assert lib.lbm_check_cfl(ctypes.byref(p), mu, lam) == L.LBM_OK

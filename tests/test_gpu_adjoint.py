@@ -29,8 +29,11 @@ def _case(kind, nx=24, ny=20, steps=30):
         bc, data, omega = ("velocity", "traction", "traction", "traction"), [(0, 0), (2e-4, 0), (0, 0), (0, -3e-4)], 1.99
     else:
         bc, data, omega = ("traction", "traction", "velocity", "traction"), [(1e-4, 0), (0, 0), (1e-4, -1e-4), (0, 2e-4)], 1.95
+    # the walled cases run tens to hundreds of steps with the fields' largest P-wave speed
+    # near 0.5 c, outside the region where the traction-wall modes decay for all time
+    # (lbm_wall_mode_growth): the audit is skipped for them
     return dict(nx=nx, ny=ny, steps=steps, mu=mu, lam=lam, body=body, v0=v0, probes=(ys, xs), bc=bc, data=data,
-                omega=omega, c=2.5, ramp=lambda n: min(1.0, n / 10))
+                omega=omega, c=2.5, ramp=lambda n: min(1.0, n / 10), force=kind != "periodic")
 
 
 def _oracle_grads(cs, law="lognh"):
@@ -53,7 +56,7 @@ def _gpu_grads(cs, storage, law="lognh", **kw):
     probes = torch.tensor(ys * cs["nx"] + xs, dtype=torch.int64)
     cfg = RolloutConfig(nx=cs["nx"], ny=cs["ny"], c=cs["c"], omega=cs["omega"], nsteps=cs["steps"], probes=probes,
                         material=law, storage=storage, bc=cs["bc"], ramp=cs["ramp"],
-                        edges=lambda n: cs["data"], **kw)
+                        edges=lambda n: cs["data"], force_unstable=cs["force"], **kw)
     # float64 leaves holding float32-exact values: the library computes with them in
     # float32 and returns FP64 gradients
     mu = torch.tensor(cs["mu"], dtype=torch.float64, device=dev, requires_grad=True)
@@ -141,7 +144,8 @@ def test_adjoint_against_fp64_central_differences():
     ys, xs = cs["probes"]
     probes = torch.tensor(ys * cs["nx"] + xs, dtype=torch.int64)
     cfg = RolloutConfig(nx=cs["nx"], ny=cs["ny"], c=cs["c"], omega=cs["omega"], nsteps=cs["steps"], probes=probes,
-                        storage="f64", bc=cs["bc"], ramp=cs["ramp"], edges=lambda n: cs["data"])
+                        storage="f64", bc=cs["bc"], ramp=cs["ramp"], edges=lambda n: cs["data"],
+                        force_unstable=cs["force"])
 
     def loss(p):
         with torch.no_grad():
@@ -172,9 +176,10 @@ def test_adjoint_512_2000_steps_against_fp64_central_differences():
     elsewhere, per-node log-normal mu, lam (median 0.1 / 0.2, sigma_log 0.3, correlation
     length 32), body force (0, -1e-5) ramped over 500 steps, loss sum |u - u_target|^2 at
     16 random probes after 2000 steps; FP32 forward and adjoint with FP64 gradient
-    accumulation and a checkpoint every 100 steps; c = 10, omega = 2 - 1.6/512 (with
-    traction-free corners the step goes unstable over a few thousand steps for
-    c_p/c above about 0.35, so the wall workloads use c = 10).  Directional derivatives
+    accumulation and a checkpoint every 100 steps; c = 10, omega = 2 - 1.6/512 (at the
+    lattice speeds near twice the P-wave speed, the traction walls' modes grow when omega is
+    this close to 2; lbm_check_cfl refuses those, and c = 10 lies inside the region where
+    they decay).  Directional derivatives
     along 8 random directions in (mu, lam, b, v0) against FP64 central differences: 1e-4
     relative, and every value finite."""
     from paper_2605_26677_amd.rollout import RolloutConfig, rollout
