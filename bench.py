@@ -412,7 +412,8 @@ def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0, host_gibs=(0.0,)):
                 ms_fwd=best["ms_fwd"], ms_bwd=best["ms_bwd"], bwd_over_fwd=best["bwd_over_fwd"],
                 mlups=best["mlups"], fd_rel_err=[float(e) for e in errs], fd_groups=kinds,
                 fd_cancellation=[float(x) for x in cancel], fd_err_over_term_sum=[float(x) for x in scaled],
-                fd_max_rel_err=float(max(errs)), fd_max_err_over_term_sum=float(max(scaled)))
+                fd_max_rel_err=float(max(errs)) if errs else None,
+                fd_max_err_over_term_sum=float(max(scaled)) if scaled else None)
 
 
 def profile_run(n, steps):
