@@ -208,6 +208,18 @@ double lbm_wall_mode_growth(const lbm_params *p, double mu_max, double lam_max);
 lbm_status lbm_init(const lbm_params *p, lbm_state *s, const double *v0, const double *u0,
                     const double *Fbar, double r0, void *stream);
 
+/* The second-order initialisation of lbm_init from a state and its spatial derivatives that
+ * the caller gives (for fields known in closed form, as the manufactured solutions of
+ * Sec. 4, whose runs start from the exact derivatives), then the same first collision and
+ * u*^1 = u0 - (dt/2) v0 + dt v^0.
+ *   U0: device, 6 double planes (v1, v2, F11 - 1, F12, F21, F22 - 1).
+ *   dUdX, dUdY: device, 6 double planes each, the X and Y derivatives of those components.
+ *   u0: device, 2 double planes, initial displacement, or NULL for 0.
+ *   r0: factor applied to the body force at t = 0.
+ * s->pop[1 - s->cur] is not touched.  Runs the CFL audit unless force_unstable. */
+lbm_status lbm_init_state(const lbm_params *p, lbm_state *s, const double *U0, const double *dUdX,
+                          const double *dUdY, const double *u0, double r0, void *stream);
+
 /* One time step (Sec. 3.7), level n -> n+1, fused in one pass over the grid: pull
  * streaming (eq:streaming) from s->pop[s->cur], half-way reconstruction of every missing
  * link with the data at t^{n+1/2} (eq:boundary-general; traction links first solve for

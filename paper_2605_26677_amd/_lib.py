@@ -74,6 +74,7 @@ SIGNATURES = {
     "lbm_check_cfl": (c_i32, [P(lbm_params), c_dbl, c_dbl]),
     "lbm_wall_mode_growth": (c_dbl, [P(lbm_params), c_dbl, c_dbl]),
     "lbm_init": (c_i32, [P(lbm_params), P(lbm_state), c_vp, c_vp, c_vp, c_dbl, c_vp]),
+    "lbm_init_state": (c_i32, [P(lbm_params), P(lbm_state), c_vp, c_vp, c_vp, c_vp, c_dbl, c_vp]),
     "lbm_step": (c_i32, [P(lbm_params), P(lbm_state), c_i64, c_dbl, c_dbl, P(lbm_edge_data), c_vp, c_vp]),
     "lbm_step2": (c_i32, [P(lbm_params), P(lbm_state), c_i64, c_dbl, c_dbl, c_dbl, P(lbm_edge_data),
                           P(lbm_edge_data), c_vp, c_vp, c_vp]),

@@ -264,6 +264,30 @@ lbm_status lbm_init(const lbm_params* p, lbm_state* s, const double* v0, const d
     return launched(launch_init(a, (hipStream_t)stream));
 }
 
+lbm_status lbm_init_state(const lbm_params* p, lbm_state* s, const double* U0, const double* dUdX,
+                          const double* dUdY, const double* u0, double r0, void* stream) {
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if ((st = check_state(p, s)) != LBM_OK) return st;
+    if (!U0 || !dUdX || !dUdY) return LBM_ERR_ARG;
+    if (!p->force_unstable) {
+        const double mu = s->mu ? s->mu_max : s->mu0;
+        const double lam = s->lam ? s->lam_max : s->lam0;
+        if ((st = lbm_check_cfl(p, mu, lam)) != LBM_OK) return st;
+    }
+    InitArgs a{};
+    a.cm = make_common(p, s);
+    a.v0 = U0;                       // planes 0, 1 of U0 are v0
+    a.u0 = u0;
+    a.r0 = r0;
+    a.scratch = const_cast<double*>(U0);
+    a.dst = s->pop[s->cur];
+    a.ustar = s->ustar;
+    a.dUdX = dUdX;
+    a.dUdY = dUdY;
+    return launched(launch_init_given(a, (hipStream_t)stream));
+}
+
 lbm_status lbm_step(const lbm_params* p, lbm_state* s, int64_t n, double r_n, double r_np1,
                     const lbm_edge_data* at_half, void* record, void* stream) {
     lbm_status st = lbm_check_params(p);

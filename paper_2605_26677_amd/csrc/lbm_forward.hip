@@ -412,8 +412,13 @@ __global__ void __launch_bounds__(kBlock) init_pop_kernel(InitArgs a) {
     for (int k = 0; k < 6; ++k) {
         const double* pl = U0p + k * n;
         U0[k] = pl[idx];
-        dX[k] = fd_along<double>([&](int s) { return pl[int64_t(y) * nx + s]; }, x, nx, cm.periodic_x, inv2h);
-        dY[k] = fd_along<double>([&](int s) { return pl[int64_t(s) * nx + x]; }, y, ny, cm.periodic_y, inv2h);
+        if (a.dUdX) {
+            dX[k] = a.dUdX[k * n + idx];
+            dY[k] = a.dUdY[k * n + idx];
+        } else {
+            dX[k] = fd_along<double>([&](int s) { return pl[int64_t(y) * nx + s]; }, x, nx, cm.periodic_x, inv2h);
+            dY[k] = fd_along<double>([&](int s) { return pl[int64_t(s) * nx + x]; }, y, ny, cm.periodic_y, inv2h);
+        }
     }
     double mu, lam, b0, b1;
     params_at<FIELDS, double>(cm, (int)idx, mu, lam);
@@ -695,6 +700,12 @@ hipError_t launch_init_state(const InitArgs& a, hipStream_t s) {
 hipError_t launch_init(const InitArgs& a, hipStream_t s) {
     const dim3 grid(nblocks(int64_t(a.cm.nx) * a.cm.ny));
     hipLaunchKernelGGL(init_state_kernel, grid, dim3(kBlock), 0, s, a);
+    return launch_init_given(a, s);
+}
+
+// The populations from U0 already in a.scratch (and its derivatives, if given).
+hipError_t launch_init_given(const InitArgs& a, hipStream_t s) {
+    const dim3 grid(nblocks(int64_t(a.cm.nx) * a.cm.ny));
     switch (a.cm.storage) {
         case LBM_F32_SHIFTED: init_st<LBM_F32_SHIFTED>(a, s, grid); break;
         case LBM_F16_SHIFTED: init_st<LBM_F16_SHIFTED>(a, s, grid); break;

@@ -236,6 +236,8 @@ struct InitArgs {
     void* scratch;                   // U0 as 6 double planes (stride n)
     void* dst;                       // f*^0
     void* ustar;
+    const double* dUdX;              // derivatives of U0 (6 double planes each) given by the
+    const double* dUdY;              // caller, or NULL: finite differences of U0
 };
 
 struct AdjArgs {
@@ -310,6 +312,7 @@ hipError_t launch_displacement(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_diagnostics(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_stress(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
+hipError_t launch_init_given(const InitArgs& a, hipStream_t s);
 hipError_t launch_init_state(const InitArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s);
 hipError_t launch_adjoint_init(const AdjInitArgs& a, hipStream_t s);

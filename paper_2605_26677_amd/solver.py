@@ -211,6 +211,20 @@ class Solver:
         L.check(self.lib.lbm_init(ctypes.byref(self.p), ctypes.byref(self.s), _ptr(self._v0), _ptr(self._u0),
                                   host_matrix(Fbar), float(r0), _stream()), "lbm_init")
 
+    def init_state(self, U0, dUdX, dUdY, u0=None, r0=0.0):
+        """lbm_init_state: the initialisation from U0 = (v, F - I) (6, ny, nx) and its X and Y
+        derivatives given by the caller."""
+        def dev(a):
+            return torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+        self._U0, self._dUdX, self._dUdY = dev(U0), dev(dUdX), dev(dUdY)
+        self._u0 = None if u0 is None else dev(u0)
+        self.s.cur = 0
+        self.fault.zero_()
+        self.ustar.zero_()
+        L.check(self.lib.lbm_init_state(ctypes.byref(self.p), ctypes.byref(self.s), _ptr(self._U0),
+                                        _ptr(self._dUdX), _ptr(self._dUdY), _ptr(self._u0), float(r0),
+                                        _stream()), "lbm_init_state")
+
     def step(self, n, r_n=1.0, r_np1=1.0, edges=None, record=None, ustar=True):
         """lbm_step; ustar=False skips the displacement quadrature (replays)."""
         ed = edges if isinstance(edges, EdgeData) else EdgeData(edges)

@@ -180,8 +180,8 @@ def test_adjoint_512_2000_steps_against_fp64_central_differences():
     lattice speeds near twice the P-wave speed, the traction walls' modes grow when omega is
     this close to 2; lbm_check_cfl refuses those, and c = 10 lies inside the region where
     they decay).  Directional derivatives
-    along 8 random directions in (mu, lam, b, v0) against FP64 central differences: 1e-4
-    relative, and every value finite."""
+    along 8 random directions in (mu, lam, b, v0), and 2 more in b alone and in v0 alone,
+    against FP64 central differences: 1e-4 relative, and every value finite."""
     from paper_2605_26677_amd.rollout import RolloutConfig, rollout
     n, N = 512, 2000
     mu0 = li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0)
@@ -215,11 +215,15 @@ def test_adjoint_512_2000_steps_against_fp64_central_differences():
 
     base = dict(mu=mu0, lam=lam0, body=body0, v0=v00)
     scale = dict(mu=0.1, lam=0.2, body=1e-5, v0=1e-4)
-    worst = 0.0
-    for d in li.fd_directions({k: base[k].shape for k in base}, 8, 406):
+    worst, worst_group = 0.0, {}
+    # 8 directions over every group at once, then 2 more for each of b and v0 alone, so that
+    # a wrong body-force or initial-velocity gradient cannot hide behind the mu, lam terms
+    dirs = li.fd_directions({k: base[k].shape for k in base}, 12, 406)
+    for j, d in enumerate(dirs):
+        only = None if j < 8 else ("body", "v0")[(j - 8) % 2]
         plus, minus = {}, {}
         for k in base:
-            step = 1e-3 * scale[k] * d[k]
+            step = 1e-3 * scale[k] * d[k] * (1.0 if only in (None, k) else 0.0)
             if k == "v0":
                 plus[k], minus[k] = base[k] + step, base[k] - step
             else:
@@ -227,9 +231,14 @@ def test_adjoint_512_2000_steps_against_fp64_central_differences():
         fd = loss(plus) - loss(minus)
         an = sum((g[k] * (plus[k] - minus[k])).sum() for k in base)
         assert np.isfinite(fd) and np.isfinite(an) and fd != 0.0
-        worst = max(worst, abs(fd - an) / abs(fd))
-        print(f"\n[adjoint 512^2 x 2000] FD {fd:.6e} adjoint {an:.6e} rel {abs(fd - an) / abs(fd):.2e}")
+        err = abs(fd - an) / abs(fd)
+        if only is None:
+            worst = max(worst, err)
+        else:
+            worst_group[only] = max(worst_group.get(only, 0.0), err)
+        print(f"\n[adjoint 512^2 x 2000, {only or 'all'}] FD {fd:.6e} adjoint {an:.6e} rel {err:.2e}")
     assert worst <= 1e-4
+    assert max(worst_group.values()) <= 1e-4, worst_group
 
 
 def test_checkpoint_plan_memory_model_matches_measurement():
