@@ -250,6 +250,20 @@ lbm_status lbm_step2(const lbm_params *p, lbm_state *s, int64_t n, double r_n, d
                      double r_np2, const lbm_edge_data *at_half, const lbm_edge_data *at_half_next,
                      void *record1, void *record2, void *stream);
 
+/* `levels` time steps (2 to 4), level n -> n+levels, in one pass over a periodic grid
+ * (temporal blocking of the step of Sec. 3.7; the levels in between stay in registers).
+ * The result, the u* accumulator and the fault bits are those of `levels` calls of lbm_step,
+ * bit for bit on every node, at about 1/levels of the HBM traffic per level; the padding
+ * nodes of the tiled arrays (beyond nx in a row's last tile) receive unspecified values,
+ * which no entry point reads.  Flips s->cur on success.
+ *   r_next: host array of `levels` body-force factors r(n+1) ... r(n+levels).  The body
+ *     field s->body (or the uniform b0) is that of every level: s->body_prev is not read.
+ * s->ustar must be set.  Returns LBM_ERR_ARG when levels is outside [2, 4], r_next is NULL
+ * or s->ustar is NULL, and
+ * LBM_ERR_UNSUPPORTED on a grid with a wall (lbm_step2 takes those). */
+lbm_status lbm_step_multi(const lbm_params *p, lbm_state *s, int64_t n, int levels,
+                          const double *r_next, void *stream);
+
 /* Displacement at the current level n (eq:trapezoid-u): u^n = u*^{n+1} - (dt/2) v^n with
  * v^n recovered from the stored post-collision populations (sum_q f* = U + (dt/2) B).
  *   r_n: body-force factor at level n.  u_out: device, 2 double planes. */

@@ -382,6 +382,55 @@ lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_n, d
     return LBM_OK;
 }
 
+lbm_status lbm_step_multi(const lbm_params* p, lbm_state* s, int64_t n, int levels, const double* r_next,
+                          void* stream) {
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if ((st = check_state(p, s, false)) != LBM_OK) return st;
+    if (levels < 2 || levels > kMarchMaxLevels || !r_next || !s->ustar) return LBM_ERR_ARG;
+    if (any_wall(p)) return LBM_ERR_UNSUPPORTED;
+    MarchArgs a{};
+    a.cm = make_common(p, s);
+    a.cm.body_prev = nullptr;
+    a.src = s->pop[s->cur];
+    a.dst = s->pop[1 - s->cur];
+    a.ustar = s->ustar;
+    a.levels = levels;
+    for (int t = 0; t < levels; ++t) {
+        a.fold[t] = (n + 1 + t) % kUstarBlock == 0;
+        a.r[t] = r_next[t];
+        for (int k = 0; k < 2; ++k) a.fb[t][k] = float(r_next[t] * a.cm.b0[k]);
+    }
+    a.nspan = (a.cm.ntile + kMarchTiles - 1) / kMarchTiles;
+    // rows per segment: a segment repeats 2 (levels - 1) rows of level n+1 and fewer of the
+    // later levels, and the launch runs in rounds of one workgroup per compute unit; take
+    // the length between 8 and 64 rows that minimises rounds x iterations per workgroup
+    int cus = 256;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            int v = 0;
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+        }
+    }
+    int best = 8;
+    int64_t best_cost = -1;
+    for (int sg = 8; sg <= 64; ++sg) {
+        const int64_t nseg = (p->ny + sg - 1) / sg;
+        const int64_t rounds = (nseg * a.nspan + cus - 1) / cus;
+        const int64_t cost = rounds * (sg + 2 * (levels - 1));
+        if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = sg; }
+    }
+    a.seg = best < p->ny ? best : p->ny;
+    const int64_t nseg = (p->ny + a.seg - 1) / a.seg;
+    if (nseg * a.nspan > 0x7fffffff) return LBM_ERR_UNSUPPORTED;
+    a.nwg = int(nseg * a.nspan);
+    a.d_nspan = fast_div(a.nspan);
+    if (launch_march(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
+    s->cur = 1 - s->cur;
+    return LBM_OK;
+}
+
 static lbm_status recover_common(const lbm_params* p, const lbm_state* s, double r_n, void* out,
                                  RecoverArgs& a, bool need_ustar = false) {
     lbm_status st = lbm_check_params(p);

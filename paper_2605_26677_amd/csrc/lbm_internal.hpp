@@ -207,6 +207,27 @@ struct Step2Args {
     double r_np1, r_np2;
 };
 
+// Several levels per pass on periodic grids (march_kernel): workgroups of kMarchWaves
+// wavefronts, each workgroup owning a span of kMarchTiles aligned tiles and a segment of
+// `seg` rows.
+constexpr int kMarchMaxLevels = 4;
+constexpr int kMarchWaves = 8;
+constexpr int kMarchTiles = 7;
+constexpr int kMarchSpan = kMarchTiles * 64;
+
+struct MarchArgs {
+    Common cm;
+    const void* src;                 // f*^n
+    void* dst;                       // f*^{n+levels}
+    void* ustar;
+    int levels;                      // 2 .. kMarchMaxLevels
+    int fold[kMarchMaxLevels];       // accumulator fold after level n+1+t
+    double r[kMarchMaxLevels];       // body factor r(n+1+t)
+    float fb[kMarchMaxLevels][2];    // uniform body r(n+1+t) b0 rounded to float
+    int nspan, seg, nwg;             // spans per row, rows per segment, workgroups
+    FastDiv d_nspan;
+};
+
 struct TractionArgs {
     Common cm;
     const void* pop;                 // f*^n
@@ -305,6 +326,7 @@ struct AdjInitArgs {
 
 hipError_t launch_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_step2(const Step2Args& a, hipStream_t s);
+hipError_t launch_march(const MarchArgs& a, hipStream_t s);
 hipError_t launch_traction(TractionArgs a, hipStream_t s);   // every traction edge, one launch
 hipError_t launch_moments(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_record(const RecoverArgs& a, hipStream_t s);

@@ -254,6 +254,22 @@ class Solver:
         finally:
             self.s.ustar = keep
 
+    def step_multi(self, n, levels, r_next=None, ustar=True):
+        """lbm_step_multi: levels n -> n + levels in one pass on a periodic grid, bit for bit
+        the same as `levels` calls of step; r_next[t] is the body factor of level n + 1 + t."""
+        r = [1.0] * levels if r_next is None else [float(x) for x in r_next]
+        if len(r) != levels:
+            raise ValueError("r_next needs one factor per level")
+        arr = (ctypes.c_double * levels)(*r)
+        keep = self.s.ustar
+        if not ustar:
+            self.s.ustar = None
+        try:
+            L.check(self.lib.lbm_step_multi(ctypes.byref(self.p), ctypes.byref(self.s), int(n), int(levels),
+                                            ctypes.cast(arr, ctypes.c_void_p), _stream()), "lbm_step_multi")
+        finally:
+            self.s.ustar = keep
+
     @property
     def periodic(self):
         return all(int(b) == L.BC["periodic"] for b in self.p.bc)
