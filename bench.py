@@ -5,9 +5,10 @@ F0 = I, initial velocity a seeded Gaussian random field with power spectrum ~ k^
 rms 5e-3 (seeds 301, 302), c = 2, omega = 2, populations in FP32 with F carried as F - I.
 A "step" is one time level of the whole hot path (pull streaming, moments, constitutive
 update, equilibrium, collision, store, displacement quadrature) over the whole grid; inputs
-are resident in HBM before timing.  The headline runs the steps in pairs through lbm_step2
-(two levels per pass over HBM, bit for bit the result of two lbm_step calls); the single-
-level lbm_step is timed beside it.  Also measured:
+are resident in HBM before timing.  The headline runs the steps four at a time through
+lbm_step_multi (four levels per pass over HBM, bit for bit the result of four lbm_step
+calls); pairs through lbm_step2 and the single-level lbm_step are timed beside it.  Also
+measured:
   - FP64 and FP16 storage of the same step, and the St. Venant-Kirchhoff law;
   - forward + adjoint at 8192^2 with every-K checkpointing on per-node mu, lam fields
     (FP32 200 levels every 50; FP32 and FP64 on one schedule, 100 levels every 25), with
@@ -46,6 +47,18 @@ BYTES_PER_LU = {"f32": 96 + 96 + 16 + 32 / 16, "f16": 48 + 48 + 16 + 32 / 16, "f
 # the same per launch of the two-level kernel (lbm_step2): populations read and written
 # once per two levels, S read + written once, U folded once per 8 launches
 BYTES_PER_LU_PAIR = {"f32": 96 + 96 + 16 + 32 / 8, "f16": 48 + 48 + 16 + 32 / 8, "f64": 192 + 192 + 32}
+# levels per launch of the headline (lbm_step_multi)
+MULTI_LEVELS = 4
+
+
+def bytes_per_lu_multi(storage, levels=MULTI_LEVELS):
+    """Algorithmic bytes per node and launch of the multi-level kernel (lbm_step_multi):
+    populations read and written once per launch, S read + written once, U folded on
+    levels / 16 of the launches (FP64: u* read + written once)."""
+    if storage == "f64":
+        return 192 + 192 + 32
+    pops = {"f32": 96 + 96, "f16": 48 + 48}[storage]
+    return pops + 16 + 32 * levels / 16
 
 
 # Single-pass algorithmic bytes per lattice update of the path (one level, every value
@@ -63,10 +76,12 @@ BYTES_PER_LU_SINGLE_PASS = {"f32": 96 + 96 + 32, "f16": 48 + 48 + 32, "f64": 192
 #   every-K snapshot: populations and record copied (read + written) once per K levels
 # (FP64: populations 192 + 192, u* 16 + 16, records 2 x 48, adjoint F - I 2 x 32, mu lam 8,
 # b 8; gradients added to the FP64 planes directly, 4 x 8 read + written per level)
+#   forward march_kernel (four levels per launch, FP32): populations 96 + 96, S 8 + 8, U fold
+#     32 / 4, mu lam 8, b 8 -> 232
 FWD_ADJ_BYTES = {
-    "f32": dict(fwd=228, replay=256, adj=272, snapshot=2 * (96 + 24)),
-    "f64": dict(fwd=192 + 192 + 32 + 8 + 8, replay=192 + 192 + 96 + 8 + 8, adj=192 + 192 + 64 + 8 + 2 * 64,
-                snapshot=2 * (192 + 48)),
+    "f32": dict(fwd=228, fwd_multi=232, replay=256, adj=272, snapshot=2 * (96 + 24)),
+    "f64": dict(fwd=192 + 192 + 32 + 8 + 8, fwd_multi=None, replay=192 + 192 + 96 + 8 + 8,
+                adj=192 + 192 + 64 + 8 + 2 * 64, snapshot=2 * (192 + 48)),
 }
 
 
@@ -78,32 +93,37 @@ SINGLE_PASS_FWD_ADJ = {"f32": (224 + 16) + (192 + 24 + 16) + (192 + 24 + 8 + 64)
                        "f64": (416 + 16) + (384 + 48 + 16) + (384 + 48 + 8 + 64)}
 
 
-def fwd_adj_bytes_per_level(storage, K):
-    """Algorithmic bytes per node and level of the every-K forward + adjoint run in pairs."""
+def fwd_adj_bytes_per_level(storage, K, multi=0):
+    """Algorithmic bytes per node and level of the every-K forward + adjoint run: the forward
+    sweep in launches of `multi` levels (lbm_step_multi) or in pairs, the recorded replay and
+    the adjoint in pairs."""
     b = FWD_ADJ_BYTES[storage]
-    return (b["fwd"] + b["replay"] + b["adj"]) / 2 + b["snapshot"] / K
+    fwd = b["fwd_multi"] / multi if multi else b["fwd"] / 2
+    return fwd + (b["replay"] + b["adj"]) / 2 + b["snapshot"] / K
 
 
 PROFILE_PMC = {"step": os.path.join(ROOT, "profiles", "step_f32_lognh_periodic_8192_pmc.txt"),
-               "step2": os.path.join(ROOT, "profiles", "step2_f32_lognh_periodic_8192_pmc.txt")}
+               "step2": os.path.join(ROOT, "profiles", "step2_f32_lognh_periodic_8192_pmc.txt"),
+               "march": os.path.join(ROOT, "profiles", "march4_f32_lognh_periodic_8192_pmc.txt")}
 STEP_SOURCES = ("lbm_forward.hip", "lbm_pair.hip", "lbm_collide.hpp", "lbm_device.hpp", "lbm_kernel_util.hpp",
                 "lbm_internal.hpp")
+MARCH_SOURCES = ("lbm_march.hip", "lbm_collide.hpp", "lbm_device.hpp", "lbm_kernel_util.hpp", "lbm_internal.hpp")
 
 
-def step_source_hash():
+def step_source_hash(files=STEP_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in STEP_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2605_26677_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def measured_traffic(n, kernel="step"):
-    """HBM bytes per launch of the step ("step") or two-level ("step2") kernel from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the same counters on a
-    copy of known size), or None when the summary is missing, was taken at another size,
-    or the kernel source changed since."""
+    """HBM bytes per launch of the step ("step"), two-level ("step2") or four-level
+    ("march") kernel from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by
+    the same counters on a copy of known size), or None when the summary is missing, was
+    taken at another size, or the kernel source changed since."""
     path = PROFILE_PMC[kernel]
     if not os.path.exists(path):
         return None
@@ -113,7 +133,8 @@ def measured_traffic(n, kernel="step"):
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != step_source_hash() or kv.get("grid") != f"{n}x{n}":
+    files = MARCH_SOURCES if kernel == "march" else STEP_SOURCES
+    if kv.get("source_sha256") != step_source_hash(files) or kv.get("grid") != f"{n}x{n}":
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -149,22 +170,24 @@ def make_inputs(n):
     return v0
 
 
-def time_forward(n, storage, steps, warmup, v0, law="lognh", pairs=False):
-    """ms per level of `steps` levels after `warmup` untimed ones: single lbm_step calls, or
-    lbm_step2 calls of two levels each (`pairs`; steps and warmup rounded up to even)."""
+def time_forward(n, storage, steps, warmup, v0, law="lognh", mode="single"):
+    """ms per level of `steps` levels after `warmup` untimed ones: single lbm_step calls
+    ("single"), lbm_step2 calls of two levels each ("pairs") or lbm_step_multi calls of
+    MULTI_LEVELS levels each ("multi"); steps and warmup rounded up to whole calls."""
     import torch
     from paper_2605_26677_amd.solver import Solver
     sv = Solver(n, n, c=2.0, omega=2.0, material=law, storage=storage, mu=0.1, lam=0.2)
     sv.init(v0)
-    if pairs:
-        steps, warmup = steps + steps % 2, warmup + warmup % 2
+    per = {"single": 1, "pairs": 2, "multi": MULTI_LEVELS}[mode]
+    steps, warmup = -(-steps // per) * per, -(-warmup // per) * per
 
     def run(k0, count):
-        if pairs:
-            for k in range(k0, k0 + count, 2):
+        for k in range(k0, k0 + count, per):
+            if mode == "multi":
+                sv.step_multi(k, per)
+            elif mode == "pairs":
                 sv.step2(k)
-        else:
-            for k in range(k0, k0 + count):
+            else:
                 sv.step(k)
     run(0, warmup)
     torch.cuda.synchronize()
@@ -225,18 +248,20 @@ def time_block(n=1024, steps=2000, start=512):
 def time_launch_bound(n=256, steps=4000, block=100):
     """The same step on a small grid where the host launch cost dominates: per-step eager
     lbm_step calls against blocks of the same single steps replayed from a captured HIP
-    graph (Solver.advance)."""
+    graph (Solver.advance), and blocks of fused launches replayed the same way (the fused
+    form advance takes on this grid: pairs; four-level launches pay from 1024^2)."""
     import torch
     from paper_2605_26677_amd.solver import Solver
     v0 = make_inputs(n)
     out = {}
-    for mode in ("eager", "graph"):
+    for mode in ("eager", "graph", "graph_fused"):
+        fused = mode == "graph_fused"
         sv = Solver(n, n, c=2.0, omega=2.0, storage="f32", mu=0.1, lam=0.2)
         sv.init(v0)
         for k in range(20):
             sv.step(k)
-        if mode == "graph":
-            sv.advance(20, 2 * block, block=block, fused=False, graph=True)   # capture outside the timed region
+        if mode != "eager":
+            sv.advance(20, 2 * block, block=block, fused=fused, graph=True)   # capture outside the timed region
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -244,7 +269,7 @@ def time_launch_bound(n=256, steps=4000, block=100):
             for k in range(steps):
                 sv.step(k)
         else:
-            sv.advance(0, steps, block=block, fused=False, graph=True)
+            sv.advance(0, steps, block=block, fused=fused, graph=True)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
@@ -254,6 +279,7 @@ def time_launch_bound(n=256, steps=4000, block=100):
         del sv
     out["grid"] = [n, n]
     out["speedup"] = out["eager_ms_per_step"] / out["graph_ms_per_step"]
+    out["speedup_fused"] = out["eager_ms_per_step"] / out["graph_fused_ms_per_step"]
     return out
 
 
@@ -291,7 +317,10 @@ def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32"):
     t_f, t_b = e0.elapsed_time(e1), e1.elapsed_time(e2)
     mem = torch.cuda.max_memory_allocated() / 2 ** 30
     ok = all(torch.isfinite(t.grad).all().item() for t in (mu, lam, v0))
-    bpl = fwd_adj_bytes_per_level(storage, K)
+    # the rollout's forward sweep goes through lbm_step_multi on this periodic grid in the
+    # shifted storages (Solver.multi_levels), in pairs in FP64
+    multi = MULTI_LEVELS if storage != "f64" else 0
+    bpl = fwd_adj_bytes_per_level(storage, K, multi)
     gbs = bpl * n * n * steps / ((t_f + t_b) * 1e-3) / 1e9
     single = SINGLE_PASS_FWD_ADJ[storage]
     out = dict(ms_fwd=t_f, ms_bwd=t_b, mlups=n * n * steps / ((t_f + t_b) * 1e-3) / 1e6,
@@ -300,11 +329,13 @@ def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32"):
                roofline={"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                          "frac": gbs * 1e9 / PEAK_HBM,
                          "bytes_per_node_level": bpl,
-                         "byte_model": "blocked kernels per launch / 2 levels: forward step2 "
-                                       f"{FWD_ADJ_BYTES[storage]['fwd']}, recorded replay step2 "
-                                       f"{FWD_ADJ_BYTES[storage]['replay']}, adjoint2 "
-                                       f"{FWD_ADJ_BYTES[storage]['adj']} B per node and launch, snapshots "
-                                       f"{FWD_ADJ_BYTES[storage]['snapshot']} B per node every K levels",
+                         "byte_model": ("blocked kernels per launch / levels per launch: forward "
+                                        + (f"march_kernel {FWD_ADJ_BYTES[storage]['fwd_multi']} / {multi}"
+                                           if multi else f"step2 {FWD_ADJ_BYTES[storage]['fwd']} / 2")
+                                        + ", recorded replay step2 "
+                                        f"{FWD_ADJ_BYTES[storage]['replay']} / 2, adjoint2 "
+                                        f"{FWD_ADJ_BYTES[storage]['adj']} / 2 B per node and launch, snapshots "
+                                        f"{FWD_ADJ_BYTES[storage]['snapshot']} B per node every K levels"),
                          "single_pass_bytes_per_node_level": single,
                          "single_pass_effective_GBps": single * n * n * steps / ((t_f + t_b) * 1e-3) / 1e9})
     del u, mu, lam, body, v0
@@ -428,10 +459,12 @@ def profile_run(n, steps):
     del a, b
     v0 = make_inputs(n)
     ms, faults, _ = time_forward(n, "f32", steps, 3, v0)
-    ms2, faults2, _ = time_forward(n, "f32", steps, 4, v0, pairs=True)
+    ms2, faults2, _ = time_forward(n, "f32", steps, 4, v0, mode="pairs")
+    ms4, faults4, _ = time_forward(n, "f32", steps, 4, v0, mode="multi")
     adj = time_forward_adjoint(n, 20, 10)
     print(json.dumps({"profile": True, "copy_bytes_each_way": 2 ** 31, "ms_per_step": ms, "faults": faults,
-                      "ms_per_level_pairs": ms2, "faults_pairs": faults2, "fwd_adj": adj}))
+                      "ms_per_level_pairs": ms2, "faults_pairs": faults2, "ms_per_level_multi": ms4,
+                      "faults_multi": faults4, "fwd_adj": adj}))
 
 
 def _cpu_model():
@@ -529,30 +562,37 @@ def main():
     only = [s for s in args.only.split(",") if s] or ["f32", "f64", "f16"]
     res = {}
 
-    def record(key, storage, ms, faults, steps, pairs):
+    kernels = {"single": "step_kernel", "pairs": "step2_kernel", "multi": "march_kernel"}
+
+    def record(key, storage, ms, faults, steps, mode):
         mlups = n * n / (ms * 1e-3) / 1e6
-        bpl = BYTES_PER_LU_PAIR[storage] if pairs else BYTES_PER_LU[storage]
-        launch_ms = 2 * ms if pairs else ms
+        per = {"single": 1, "pairs": 2, "multi": MULTI_LEVELS}[mode]
+        bpl = {"single": BYTES_PER_LU[storage], "pairs": BYTES_PER_LU_PAIR[storage],
+               "multi": bytes_per_lu_multi(storage)}[mode]
+        launch_ms = per * ms
         gbs = bpl * n * n / (launch_ms * 1e-3) / 1e9
-        res[key] = dict(ms_per_step=ms, mlups=mlups, kernel="step2_kernel" if pairs else "step_kernel",
+        res[key] = dict(ms_per_step=ms, mlups=mlups, kernel=kernels[mode], levels_per_launch=per,
                         launch_ms=launch_ms, bytes_per_lu_per_launch=bpl, algorithmic_GBps=gbs,
                         frac_hbm=gbs * 1e9 / PEAK_HBM, faults=faults, steps=steps)
         log(f"bench: {key}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, {gbs:.0f} GB/s per launch")
 
+    suffix = {"single": "", "pairs": "_pairs", "multi": f"_multi{MULTI_LEVELS}"}
     for storage in only:
-        for pairs in (True, False):
-            steps = args.steps if storage == "f32" else args.variant_steps
-            key = storage + ("_pairs" if pairs else "")
+        # FP64: pairs are its fastest fused form (its multi-level kernel runs short of registers)
+        modes = ("pairs", "single") if storage == "f64" else ("multi", "pairs", "single")
+        for mode in modes:
+            steps = args.steps if (storage == "f32" and mode == "multi") else args.variant_steps
+            key = storage + suffix[mode]
             log(f"bench: timing {key} forward, {steps} steps")
-            ms, faults, steps = time_forward(n, storage, steps, args.warmup, v0, pairs=pairs)
-            record(key, storage, ms, faults, steps, pairs)
+            ms, faults, steps = time_forward(n, storage, steps, args.warmup, v0, mode=mode)
+            record(key, storage, ms, faults, steps, mode)
     if "f32" in only:
         # the St. Venant-Kirchhoff variant of the same workload (FP32 storage)
-        for pairs in (True, False):
-            key = "svk_f32" + ("_pairs" if pairs else "")
+        for mode in ("multi", "single"):
+            key = "svk_f32" + suffix[mode]
             log(f"bench: timing {key} forward, {args.variant_steps} steps")
-            ms, faults, steps = time_forward(n, "f32", args.variant_steps, args.warmup, v0, law="svk", pairs=pairs)
-            record(key, "f32", ms, faults, steps, pairs)
+            ms, faults, steps = time_forward(n, "f32", args.variant_steps, args.warmup, v0, law="svk", mode=mode)
+            record(key, "f32", ms, faults, steps, mode)
     log("bench: walled 1024^2 block, single steps vs advance in pairs")
     res["block_1024_walls"] = time_block()
     log(f"bench: block: {res['block_1024_walls']}")
@@ -580,27 +620,30 @@ def main():
     log("bench: copy ceiling")
     copy_gbs = copy_ceiling()
     main_storage = "f32" if "f32" in only else only[0]
-    main_key = main_storage + "_pairs"
+    main_key = main_storage + (suffix["pairs"] if main_storage == "f64" else suffix["multi"])
     r = res[main_key]
-    traffic = measured_traffic(n, "step2") if main_storage == "f32" else None
+    main_kernel = "march" if r["kernel"] == "march_kernel" else "step2"
+    traffic = measured_traffic(n, main_kernel) if main_storage == "f32" else None
+    per = r["levels_per_launch"]
+    how = (f"{per} levels per pass (lbm_step_multi)" if r["kernel"] == "march_kernel"
+           else "two levels per pass (lbm_step2)")
     out = {
         "metric": METRIC, "value": r["mlups"], "unit": "MLUPS", "n_gpus": 1,
         "steps": r["steps"], "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": main_storage,
         "data": "synthetic",
         "config": {"workload": f"{n}x{n} periodic random-field elastic waves (k^-3 spectrum, rms 5e-3), "
-                               f"log-NH mu=0.1 lam=0.2, c=2, omega=2, {main_storage} storage, "
-                               f"two levels per pass (lbm_step2)",
+                               f"log-NH mu=0.1 lam=0.2, c=2, omega=2, {main_storage} storage, {how}",
                    "grid": [n, n], "storage": main_storage},
-        "roofline": {"bound": "hbm", "kernel": "step2_kernel", "achieved": r["algorithmic_GBps"],
+        "roofline": {"bound": "hbm", "kernel": r["kernel"], "achieved": r["algorithmic_GBps"],
                      "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": r["frac_hbm"], "traffic": traffic,
-                     "algorithmic_bytes_per_launch": BYTES_PER_LU_PAIR[main_storage] * n * n,
+                     "algorithmic_bytes_per_launch": r["bytes_per_lu_per_launch"] * n * n,
                      "launch_ms": r["launch_ms"], "copy_ceiling_GBps": copy_gbs,
                      "byte_models": {
                          "blocked_per_launch": {
-                             "bytes_per_node": BYTES_PER_LU_PAIR[main_storage], "levels_per_launch": 2,
+                             "bytes_per_node": r["bytes_per_lu_per_launch"], "levels_per_launch": per,
                              "achieved_GBps": r["algorithmic_GBps"], "frac": r["frac_hbm"],
-                             "note": "what step2_kernel itself moves per launch (two levels)"},
+                             "note": f"what {r['kernel']} itself moves per launch ({per} levels)"},
                          "single_pass_per_level": {
                              "bytes_per_node": BYTES_PER_LU_SINGLE_PASS[main_storage],
                              "effective_GBps": BYTES_PER_LU_SINGLE_PASS[main_storage] * n * n
@@ -608,10 +651,19 @@ def main():
                              "frac": BYTES_PER_LU_SINGLE_PASS[main_storage] * n * n
                              / (r["ms_per_step"] * 1e-3) / PEAK_HBM,
                              "note": "bytes one level would move in a single pass, per level time; above 1 "
-                                     "because two levels share one pass"}}},
+                                     f"because {per} levels share one pass"}}},
+        "pairs_roofline": None,
         "single_step_roofline": None,
         "variants": res,
     }
+    pk = main_storage + suffix["pairs"]
+    if pk in res and pk != main_key:
+        r2 = res[pk]
+        out["pairs_roofline"] = {
+            "bound": "hbm", "kernel": "step2_kernel", "achieved": r2["algorithmic_GBps"], "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s", "frac": r2["frac_hbm"],
+            "traffic": measured_traffic(n, "step2") if main_storage == "f32" else None,
+            "algorithmic_bytes_per_launch": BYTES_PER_LU_PAIR[main_storage] * n * n, "mlups": r2["mlups"]}
     if main_storage in res:
         r1 = res[main_storage]
         out["single_step_roofline"] = {

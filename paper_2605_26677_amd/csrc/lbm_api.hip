@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "lbm_device.hpp"
@@ -382,6 +383,18 @@ lbm_status lbm_step2(const lbm_params* p, lbm_state* s, int64_t n, double r_n, d
     return LBM_OK;
 }
 
+// Compute units of the current device, queried once per device (256 on an MI355X).
+static int compute_units() {
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cached[dev].store(v, std::memory_order_relaxed);
+    return v;
+}
+
 lbm_status lbm_step_multi(const lbm_params* p, lbm_state* s, int64_t n, int levels, const double* r_next,
                           void* stream) {
     lbm_status st = lbm_check_params(p);
@@ -405,14 +418,7 @@ lbm_status lbm_step_multi(const lbm_params* p, lbm_state* s, int64_t n, int leve
     // rows per segment: a segment repeats 2 (levels - 1) rows of level n+1 and fewer of the
     // later levels, and the launch runs in rounds of one workgroup per compute unit; take
     // the length between 8 and 64 rows that minimises rounds x iterations per workgroup
-    int cus = 256;
-    {
-        int dev = 0;
-        if (hipGetDevice(&dev) == hipSuccess) {
-            int v = 0;
-            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-        }
-    }
+    const int cus = compute_units();
     int best = 8;
     int64_t best_cost = -1;
     for (int sg = 8; sg <= 64; ++sg) {

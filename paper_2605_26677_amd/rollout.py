@@ -326,12 +326,18 @@ def _pair(sv, cfg, n, record1=None, record2=None, ustar=True):
 
 
 def _plain_steps(sv, cfg, n0, n1, ustar=True):
-    """Steps n0 .. n1 - 1 without records, in pairs through lbm_step2 where the rollout
-    takes pairs (_pairs; bit for bit the same result as single steps)."""
+    """Steps n0 .. n1 - 1 without records: where the rollout fuses levels (_pairs), in
+    groups through lbm_step_multi where that applies (Solver.multi_levels; it updates u*,
+    so not where u* is skipped) and else in pairs through lbm_step2; bit for bit the same
+    result as single steps."""
     n = n0
     pairs = _pairs(sv, cfg)
+    multi = sv.multi_levels if (pairs and ustar) else 0
     while n < n1:
-        if pairs and n + 1 < n1:
+        if multi and n + multi <= n1:
+            sv.step_multi(n, multi, [cfg.ramp(n + 1 + t) for t in range(multi)])
+            n += multi
+        elif pairs and n + 1 < n1:
             _pair(sv, cfg, n, ustar=ustar)
             n += 2
         else:

@@ -89,7 +89,7 @@ class StepGraph:
                 solver._run(st)
         self.end_cur = solver.s.cur
         solver.s.cur = self.start_cur
-        self.nsteps = sum(2 if st.get("pair") else 1 for st in steps)
+        self.nsteps = sum(st["multi"] if st.get("multi") else 2 if st.get("pair") else 1 for st in steps)
 
     def replay(self):
         if self.sv.s.cur != self.start_cur:
@@ -113,6 +113,12 @@ class Solver:
     # 16.2 against 15.6 single; 512^2: 20.4 against 22.9).
     GRAPH_MAX_NODES = 400 * 400
     PAIR_MIN_WALLED_NODES = 416 * 416
+    # levels per lbm_step_multi call (8192^2 FP32: 2 levels 50.2k, 3 levels 70.3k, 4 levels
+    # 78.3k MLUPS, pairs through lbm_step2 51.1k), and the grid size from which it beats
+    # pairs (FP32 MLUPS, four levels against pairs: 512^2 21.4k against 32.6k, 1024^2 57.0k
+    # against 46.1k, 2048^2 79.4k against 49.7k: a small grid leaves compute units idle)
+    MULTI_LEVELS = 4
+    MULTI_MIN_NODES = 1024 * 1024
 
     def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
                  bc=("periodic",) * 4, mu=0.1, lam=0.2, body=None, newton_max_iter=0,
@@ -271,6 +277,16 @@ class Solver:
             self.s.ustar = keep
 
     @property
+    def multi_levels(self):
+        """Levels per lbm_step_multi call where that is the fastest way to advance: periodic
+        grids of at least MULTI_MIN_NODES nodes in the shifted storages (FP32, FP16) with a
+        body field shared by all levels; 0 elsewhere (walls: lbm_step2; FP64: pairs are
+        faster, its multi-level kernel has too few registers for the levels it holds)."""
+        ok = (self.periodic and self.pairs_ok and self.storage != "f64" and self.s.ustar
+              and self.nx * self.ny >= self.MULTI_MIN_NODES)
+        return self.MULTI_LEVELS if ok else 0
+
+    @property
     def periodic(self):
         return all(int(b) == L.BC["periodic"] for b in self.p.bc)
 
@@ -286,7 +302,9 @@ class Solver:
         return self.pairs_ok and (self.periodic or self.nx * self.ny >= self.PAIR_MIN_WALLED_NODES)
 
     def _run(self, st):
-        if st.get("pair"):
+        if st.get("multi"):
+            self.step_multi(st["n"], st["multi"], st["r_next"])
+        elif st.get("pair"):
             self.step2(st["n"], st["r_np1"], st["r_np2"], r_n=st["r_n"], edges=st.get("edges"),
                        edges_next=st.get("edges_next"))
         else:
@@ -306,8 +324,9 @@ class Solver:
         ``graph`` None captures only grids of at most GRAPH_MAX_NODES nodes: on larger ones
         eager launches already follow each other without a gap, and a graph replay adds a
         few microseconds between its kernel nodes.  With ``fused`` True the steps go in
-        pairs through lbm_step2 (where pairs_ok), with the same result bit for bit; None
-        takes pairs where they are faster (pairs_pay)."""
+        groups of multi_levels through lbm_step_multi where that applies, else in pairs
+        through lbm_step2 (where pairs_ok), with the same result bit for bit; None fuses
+        where it is faster (pairs_pay)."""
         ramp = ramp or (lambda n: 1.0)
         edges = edges or (lambda n: None)
         fused = self.pairs_pay if fused is None else (bool(fused) and self.pairs_ok)
@@ -316,11 +335,16 @@ class Solver:
         else:
             graph_on = bool(graph)
 
+        multi = self.multi_levels if fused else 0
+
         def block_calls(n, m):
             # the calls for steps n .. m - 1
             calls = []
             while n < m:
-                if fused and n + 1 < m:
+                if multi and n + multi <= m:
+                    calls.append(dict(multi=multi, n=n, r_next=tuple(float(ramp(n + 1 + t)) for t in range(multi))))
+                    n += multi
+                elif fused and n + 1 < m:
                     calls.append(dict(pair=True, n=n, r_n=float(ramp(n)), r_np1=float(ramp(n + 1)),
                                       r_np2=float(ramp(n + 2)), edges=edges(n), edges_next=edges(n + 1)))
                     n += 2
@@ -350,7 +374,7 @@ class Solver:
 
     @staticmethod
     def _same(a, b):
-        keys = ("pair", "r_n", "r_np1", "r_np2")
+        keys = ("multi", "r_next", "pair", "r_n", "r_np1", "r_np2")
         return (all(a.get(k) == b.get(k) for k in keys)
                 and _edge_key(a.get("edges")) == _edge_key(b.get("edges"))
                 and _edge_key(a.get("edges_next")) == _edge_key(b.get("edges_next")))

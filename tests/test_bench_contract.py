@@ -24,6 +24,11 @@ def test_byte_counts():
     # populations and S once per two levels
     assert bench.BYTES_PER_LU == {"f32": 210.0, "f16": 114.0, "f64": 416}
     assert bench.BYTES_PER_LU_PAIR == {"f32": 212.0, "f16": 116.0, "f64": 416}
+    # four levels per launch: populations and S once per launch, U folded on a quarter of them
+    assert [bench.bytes_per_lu_multi(s, 4) for s in ("f32", "f16", "f64")] == [216.0, 120.0, 416]
+    assert bench.bytes_per_lu_multi("f32", 2) == 212.0
+    # the forward + adjoint byte model: the forward sweep in four-level launches
+    assert bench.fwd_adj_bytes_per_level("f32", 50, 4) == 232 / 4 + (256 + 272) / 2 + 240 / 50
 
 
 def test_profile_summaries_parse():
