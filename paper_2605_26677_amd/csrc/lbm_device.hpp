@@ -37,7 +37,39 @@ template <typename T, typename R> __device__ __forceinline__ void store_as(T* p,
     *p = static_cast<T>(v);
 }
 
-__device__ __forceinline__ float log1p_r(float x) { return log1pf(x); }
+// 2 atanh(s) = ln((1 + s) / (1 - s)) for |s| <= 1/5 by its Taylor series
+// 2 (s + s^3/3 + ... + s^11/11): the first omitted term is below 2^-27 of the sum.
+__device__ __forceinline__ float atanh2_series(float s) {
+    const float s2 = s * s;
+    float t = 1.0f / 11.0f;
+    t = fmaf(t, s2, 1.0f / 9.0f);
+    t = fmaf(t, s2, 1.0f / 7.0f);
+    t = fmaf(t, s2, 1.0f / 5.0f);
+    t = fmaf(t, s2, 1.0f / 3.0f);
+    const float d = 2.0f * s;
+    return fmaf(d * s2, t, d);
+}
+
+// ln(1 + x) in FP32 from ln(1 + x) = 2 atanh(x / (2 + x)).  For -1/4 <= x < 1/2 (|J - 1| of
+// every state the workloads reach) the series applies directly, so a small x keeps its
+// relative accuracy; elsewhere 1 + x = m 2^e with m in [sqrt(1/2), sqrt(2)) and
+// ln(1 + x) = e ln 2 + 2 atanh((m - 1) / (m + 1)).  The quotients use the hardware
+// reciprocal; the result is within a few units in the last place (checked against FP64
+// through lbm_stress), at about a tenth of the instructions of the library's log1pf, whose
+// compensated arithmetic the collision does not need.
+__device__ __forceinline__ float log1p_r(float x) {
+    if (x >= -0.25f && x < 0.5f) return atanh2_series(x * __builtin_amdgcn_rcpf(2.0f + x));
+    const float u = 1.0f + x;
+    if (!(u > 0.0f)) return u == 0.0f ? -__builtin_inff() : __builtin_nanf("");
+    if (u == __builtin_inff()) return u;
+    int e;
+    float m = frexpf(u, &e);                  // u = m 2^e, m in [1/2, 1)
+    if (m < 0.70710678f) {
+        m *= 2.0f;
+        e -= 1;
+    }
+    return fmaf(float(e), 0.69314718f, atanh2_series((m - 1.0f) * __builtin_amdgcn_rcpf(m + 1.0f)));
+}
 __device__ __forceinline__ double log1p_r(double x) { return log1p(x); }
 __device__ __forceinline__ float expm1_r(float x) { return expm1f(x); }
 __device__ __forceinline__ double expm1_r(double x) { return expm1(x); }

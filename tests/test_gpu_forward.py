@@ -255,3 +255,47 @@ def test_step_graph_replays_match_eager(kinds, storage):
     adv.advance(0, 150, edges=lambda n: data, block=32, graph=True)
     assert torch.equal(eager2.moments(), adv.moments())
     assert eager2.faults() == 0 and adv.faults() == 0
+
+
+# (F11, F12, F21, F22) of uniform states: J from 0.3 to 4 on both sides of the boundaries
+# -1/4 and 1/2 of J - 1 where the FP32 ln(1 + (J - 1)) changes method, strains down to
+# 1e-7, and a shear at J = 1
+PIOLA_STATES = [(1 + 1e-7, 0.0, 0.0, 1.0), (1.0, 3e-6, 0.0, 1 - 2e-6), (1 + 1e-4, 2e-4, -1e-4, 1 - 3e-4),
+                (1.05, 0.01, 0.02, 0.97), (1.2, 0.1, -0.05, 1.1), (0.9, 0.0, 0.0, 0.8334),
+                (0.866, 0.0, 0.0, 0.866), (0.8661, 0.0, 0.0, 0.8661), (1.2247, 0.0, 0.0, 1.2247),
+                (1.2248, 0.0, 0.0, 1.2248), (0.5, 0.1, 0.0, 0.6), (1.0, 0.5, 0.0, 1.0),
+                (2.0, 0.3, 0.2, 2.0), (0.3, 0.0, 0.0, 1.0), (4.0, 0.0, 0.0, 1.0)]
+
+
+@pytest.mark.parametrize("Fbar", PIOLA_STATES)
+def test_piola_fp32_accuracy(Fbar):
+    """The FP32 collision's first Piola stress (log-NH: mu (F - F^-T) + lam ln J F^-T, ln J by
+    the kernels' own ln(1 + (J - 1))) within 8 units in the last place of its terms.  A
+    uniform state, one step at omega = 1: the post-collision population of direction (1, 0)
+    in the v1 row is U_v1 / 4 - P11 / (2c), and that of (0, 1) is U_v1 / 4 - P12 / (2c); the
+    reference forms the step's moments from the stored level-0 populations in the kernel's
+    FP32 order and P in FP64."""
+    import torch
+    c, mu, lam = 2.0, 0.1, 0.2
+    n = 4
+    case = Case("piola", n, n, c, 1.0, 1, mu=mu, lam=lam, v0=np.zeros((2, n, n)), force_unstable=True)
+    sv = make_solver(case, "f32")
+    sv.init(case.v0, Fbar=np.array(Fbar, dtype=np.float64).reshape(2, 2))
+    f0 = sv.populations()[:, :, 0, 0].cpu().numpy()            # (4, 6) float32, uniform
+    sv.step(0)
+    f1 = sv.populations()[:, :, 0, 0].cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    U = ((f0[0] + f0[1]) + f0[2]) + f0[3]                      # float32, q0 .. q3 in order
+    t = U[2:6].astype(np.float64)
+    F = np.array([[1 + t[0], t[1]], [t[2], 1 + t[3]]])
+    J = np.linalg.det(F)
+    H = np.linalg.inv(F).T
+    P = mu * (F - H) + lam * np.log(J) * H
+    cq = float(np.float32(1.0 / (2 * c)))                      # omega / (2c) as the kernel rounds it
+    scale = cq * (mu * np.abs(F - H) + lam * abs(np.log(J)) * np.abs(H)).max() + 1e-30
+    ulp = 2.0 ** -24
+    exp = {(0, 0): U[0] / 4 - cq * P[0, 0], (1, 0): U[0] / 4 - cq * P[0, 1],
+           (0, 1): U[1] / 4 - cq * P[1, 0], (1, 1): U[1] / 4 - cq * P[1, 1]}
+    for (q, k), e in exp.items():
+        err = abs(f1[q, k] - e) / scale
+        assert err <= 8 * ulp, (Fbar, q, k, f1[q, k], e, err / ulp)
