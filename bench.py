@@ -76,13 +76,21 @@ BYTES_PER_LU_SINGLE_PASS = {"f32": 96 + 96 + 32, "f16": 48 + 48 + 32, "f64": 192
 #   every-K snapshot: populations and record copied (read + written) once per K levels
 # (FP64: populations 192 + 192, u* 16 + 16, records 2 x 48, adjoint F - I 2 x 32, mu lam 8,
 # b 8; gradients added to the FP64 planes directly, 4 x 8 read + written per level)
-#   forward march_kernel (four levels per launch, FP32): populations 96 + 96, S 8 + 8, U fold
+# and in the multi-level kernels the rollout takes on periodic FP32 grids:
+#   forward march_kernel, four levels per launch: populations 96 + 96, S 8 + 8, U fold
 #     32 / 4, mu lam 8, b 8 -> 232
+#   replay march_kernel, three levels with the record of each: 96 + 96, records 3 x 24,
+#     mu lam 8, b 8 -> 280
+#   march_adj_kernel, three levels: adjoint populations 96 + 96, F - I of three records
+#     3 x 16, mu lam 8, FP32 block sums 16 + 16, FP64 fold 64 x 3 / 16 -> 280
 FWD_ADJ_BYTES = {
-    "f32": dict(fwd=228, fwd_multi=232, replay=256, adj=272, snapshot=2 * (96 + 24)),
-    "f64": dict(fwd=192 + 192 + 32 + 8 + 8, fwd_multi=None, replay=192 + 192 + 96 + 8 + 8,
+    "f32": dict(fwd=228, replay=256, adj=272, snapshot=2 * (96 + 24),
+                fwd_multi=232, replay_multi=280, adj_multi=280),
+    "f64": dict(fwd=192 + 192 + 32 + 8 + 8, replay=192 + 192 + 96 + 8 + 8,
                 adj=192 + 192 + 64 + 8 + 2 * 64, snapshot=2 * (192 + 48)),
 }
+# levels per launch of the forward, replay and adjoint multi-level kernels of the rollout
+FWD_ADJ_MULTI = (4, 3, 3)
 
 
 # The same run in the single-pass model (every level of every pass through HBM once, per
@@ -93,13 +101,15 @@ SINGLE_PASS_FWD_ADJ = {"f32": (224 + 16) + (192 + 24 + 16) + (192 + 24 + 8 + 64)
                        "f64": (416 + 16) + (384 + 48 + 16) + (384 + 48 + 8 + 64)}
 
 
-def fwd_adj_bytes_per_level(storage, K, multi=0):
+def fwd_adj_bytes_per_level(storage, K, multi=None):
     """Algorithmic bytes per node and level of the every-K forward + adjoint run: the forward
-    sweep in launches of `multi` levels (lbm_step_multi) or in pairs, the recorded replay and
-    the adjoint in pairs."""
+    sweep, the recorded replay and the adjoint in launches of multi = (forward, replay,
+    adjoint) levels (the multi-level kernels), or all in pairs (multi None)."""
     b = FWD_ADJ_BYTES[storage]
-    fwd = b["fwd_multi"] / multi if multi else b["fwd"] / 2
-    return fwd + (b["replay"] + b["adj"]) / 2 + b["snapshot"] / K
+    if multi:
+        f, r, a = multi
+        return b["fwd_multi"] / f + b["replay_multi"] / r + b["adj_multi"] / a + b["snapshot"] / K
+    return (b["fwd"] + b["replay"] + b["adj"]) / 2 + b["snapshot"] / K
 
 
 PROFILE_PMC = {"step": os.path.join(ROOT, "profiles", "step_f32_lognh_periodic_8192_pmc.txt"),
@@ -317,9 +327,10 @@ def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32"):
     t_f, t_b = e0.elapsed_time(e1), e1.elapsed_time(e2)
     mem = torch.cuda.max_memory_allocated() / 2 ** 30
     ok = all(torch.isfinite(t.grad).all().item() for t in (mu, lam, v0))
-    # the rollout's forward sweep goes through lbm_step_multi on this periodic grid in the
-    # shifted storages (Solver.multi_levels), in pairs in FP64
-    multi = MULTI_LEVELS if storage != "f64" else 0
+    # the rollout's forward sweep, replay and adjoint go through the multi-level kernels on
+    # this periodic grid in the shifted storages (Solver.multi_levels, replay_multi_levels,
+    # adj_multi_levels), in pairs in FP64
+    multi = FWD_ADJ_MULTI if storage != "f64" else None
     bpl = fwd_adj_bytes_per_level(storage, K, multi)
     gbs = bpl * n * n * steps / ((t_f + t_b) * 1e-3) / 1e9
     single = SINGLE_PASS_FWD_ADJ[storage]
@@ -329,13 +340,16 @@ def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32"):
                roofline={"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                          "frac": gbs * 1e9 / PEAK_HBM,
                          "bytes_per_node_level": bpl,
-                         "byte_model": ("blocked kernels per launch / levels per launch: forward "
-                                        + (f"march_kernel {FWD_ADJ_BYTES[storage]['fwd_multi']} / {multi}"
-                                           if multi else f"step2 {FWD_ADJ_BYTES[storage]['fwd']} / 2")
-                                        + ", recorded replay step2 "
-                                        f"{FWD_ADJ_BYTES[storage]['replay']} / 2, adjoint2 "
-                                        f"{FWD_ADJ_BYTES[storage]['adj']} / 2 B per node and launch, snapshots "
-                                        f"{FWD_ADJ_BYTES[storage]['snapshot']} B per node every K levels"),
+                         "byte_model": (("multi-level kernels, B per node and launch / levels per launch: "
+                                         f"forward march_kernel {FWD_ADJ_BYTES[storage]['fwd_multi']} / {multi[0]}, "
+                                         f"recorded replay march_kernel {FWD_ADJ_BYTES[storage]['replay_multi']} / "
+                                         f"{multi[1]}, march_adj_kernel {FWD_ADJ_BYTES[storage]['adj_multi']} / "
+                                         f"{multi[2]}")
+                                        if multi else
+                                        ("two-level kernels, B per node and launch / 2: forward step2 "
+                                         f"{FWD_ADJ_BYTES[storage]['fwd']}, recorded replay step2 "
+                                         f"{FWD_ADJ_BYTES[storage]['replay']}, adjoint2 {FWD_ADJ_BYTES[storage]['adj']}"))
+                                       + f"; snapshots {FWD_ADJ_BYTES[storage]['snapshot']} B per node every K levels",
                          "single_pass_bytes_per_node_level": single,
                          "single_pass_effective_GBps": single * n * n * steps / ((t_f + t_b) * 1e-3) / 1e9})
     del u, mu, lam, body, v0

@@ -252,17 +252,21 @@ lbm_status lbm_step2(const lbm_params *p, lbm_state *s, int64_t n, double r_n, d
 
 /* `levels` time steps (2 to 4), level n -> n+levels, in one pass over a periodic grid
  * (temporal blocking of the step of Sec. 3.7; the levels in between stay in registers).
- * The result, the u* accumulator and the fault bits are those of `levels` calls of lbm_step,
- * bit for bit on every node, at about 1/levels of the HBM traffic per level; the padding
- * nodes of the tiled arrays (beyond nx in a row's last tile) receive unspecified values,
- * which no entry point reads.  Flips s->cur on success.
+ * The result, the u* accumulator, the records and the fault bits are those of `levels`
+ * calls of lbm_step, bit for bit on every node, at about 1/levels of the HBM traffic per
+ * level; the padding nodes of the tiled arrays (beyond nx in a row's last tile) receive
+ * unspecified values, which no entry point reads.  Flips s->cur on success.
  *   r_next: host array of `levels` body-force factors r(n+1) ... r(n+levels).  The body
  *     field s->body (or the uniform b0) is that of every level: s->body_prev is not read.
- * s->ustar must be set.  Returns LBM_ERR_ARG when levels is outside [2, 4], r_next is NULL
- * or s->ustar is NULL, and
+ *   records: NULL, or a host array of `levels` device pointers that receive U^{n+1} ...
+ *     U^{n+levels} (lbm_record_bytes() each) as lbm_step's record would: the replay of the
+ *     checkpointed adjoint, which requires s->ustar = NULL (the accumulator is not
+ *     updated), F32 or F16 storage and at most 3 levels (LBM_ERR_UNSUPPORTED otherwise).
+ * Without records s->ustar must be set.  Returns LBM_ERR_ARG when levels is outside
+ * [2, 4], r_next or a record pointer is NULL, or s->ustar is NULL without records, and
  * LBM_ERR_UNSUPPORTED on a grid with a wall (lbm_step2 takes those). */
 lbm_status lbm_step_multi(const lbm_params *p, lbm_state *s, int64_t n, int levels,
-                          const double *r_next, void *stream);
+                          const double *r_next, void *const *records, void *stream);
 
 /* Displacement at the current level n (eq:trapezoid-u): u^n = u*^{n+1} - (dt/2) v^n with
  * v^n recovered from the stored post-collision populations (sum_q f* = U + (dt/2) B).
@@ -385,6 +389,25 @@ lbm_status lbm_adjoint_step2(const lbm_params *p, const lbm_state *fwd, lbm_adj_
                              const lbm_edge_data *at_half_prev, const void *record_m,
                              const void *record_mm1, const uint64_t *mask, const double *field,
                              void *stream);
+
+/* `levels` adjoint levels (2 to 4), m, m - 1, ..., m - levels + 1, in one pass over a
+ * periodic grid (temporal blocking of lbm_adjoint_step; the levels in between stay in
+ * registers): lambda^{m+1} in a->adj[a->cur] -> lambda^{m-levels+1} in a->adj[1 - a->cur],
+ * with the gradient updates (block sums, their folds into the FP64 gradients) and probe
+ * sources of every level.  The result, the block sums and the FP64 gradients are those of
+ * lbm_adjoint_step(m), ..., lbm_adjoint_step(m - levels + 1) with the same probe table set
+ * in a, bit for bit on every node; the padding nodes of the tiled arrays receive
+ * unspecified values.  Flips a->cur.
+ *   r: host array of `levels` body factors r(m), r(m - 1), ...
+ *   records: host array of `levels` device pointers, U^m, U^{m-1}, ... as lbm_adjoint_step
+ *     reads them.
+ *   mask, field: the probe table (lbm_adjoint_probe_table); may be NULL when a->nprobe = 0.
+ * Requires levels - 1 <= m < a->nsteps (level N carries the half-weight probe term and
+ * takes lbm_adjoint_step); LBM_ERR_ARG otherwise.  FP32 and FP16 storage on periodic grids;
+ * LBM_ERR_UNSUPPORTED for FP64 storage or a grid with a wall (lbm_adjoint_step2 takes those). */
+lbm_status lbm_adjoint_step_multi(const lbm_params *p, const lbm_state *fwd, lbm_adj_state *a,
+                                  int64_t m, int levels, const double *r, const void *const *records,
+                                  const uint64_t *mask, const double *field, void *stream);
 
 /* Adjoint of lbm_init: from lambda^0 = dL/df(0) in a->adj[a->cur], writes dL/dv0 into
  * g_v0 (device, 2 double planes; includes the direct term of u*^0 = u0 - (dt/2) v0) and

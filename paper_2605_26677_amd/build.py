@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["lbm_api.hip", "lbm_forward.hip", "lbm_pair.hip", "lbm_march.hip", "lbm_adjoint.hip"]
+SOURCES = ["lbm_api.hip", "lbm_forward.hip", "lbm_pair.hip", "lbm_march.hip", "lbm_adjoint.hip", "lbm_march_adj.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

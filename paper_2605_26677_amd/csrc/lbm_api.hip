@@ -395,13 +395,45 @@ static int compute_units() {
     return v;
 }
 
+// Workgroups of the multi-level kernels: spans of kMarchTiles tiles per row, segments of
+// `seg` rows.  A segment repeats 2 (levels - 1) rows of the first level and fewer of the
+// later ones, and the launch runs in rounds of one workgroup per compute unit: the length
+// between 8 and 64 rows that minimises rounds x iterations per workgroup.
+static bool march_geometry(const lbm_params* p, int levels, int& nspan, int& seg, int& nwg, FastDiv& d_nspan) {
+    const int ntile = (p->nx + kTile - 1) / kTile;
+    nspan = (ntile + kMarchTiles - 1) / kMarchTiles;
+    const int cus = compute_units();
+    int best = 8;
+    int64_t best_cost = -1;
+    for (int sg = 8; sg <= 64; ++sg) {
+        const int64_t ns = (p->ny + sg - 1) / sg;
+        const int64_t rounds = (ns * nspan + cus - 1) / cus;
+        const int64_t cost = rounds * (sg + 2 * (levels - 1));
+        if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = sg; }
+    }
+    seg = best < p->ny ? best : p->ny;
+    const int64_t nseg = (p->ny + seg - 1) / seg;
+    if (nseg * nspan > 0x7fffffff) return false;
+    nwg = int(nseg * nspan);
+    d_nspan = fast_div(nspan);
+    return true;
+}
+
 lbm_status lbm_step_multi(const lbm_params* p, lbm_state* s, int64_t n, int levels, const double* r_next,
-                          void* stream) {
+                          void* const* records, void* stream) {
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
     if ((st = check_state(p, s, false)) != LBM_OK) return st;
-    if (levels < 2 || levels > kMarchMaxLevels || !r_next || !s->ustar) return LBM_ERR_ARG;
+    if (levels < 2 || levels > kMarchMaxLevels || !r_next) return LBM_ERR_ARG;
+    if (records) {
+        for (int t = 0; t < levels; ++t)
+            if (!records[t]) return LBM_ERR_ARG;
+    } else if (!s->ustar) {
+        return LBM_ERR_ARG;
+    }
     if (any_wall(p)) return LBM_ERR_UNSUPPORTED;
+    // the replay form: records, no accumulator, shifted storages, up to three levels
+    if (records && (s->ustar || p->storage == LBM_F64_PLAIN || levels > 3)) return LBM_ERR_UNSUPPORTED;
     MarchArgs a{};
     a.cm = make_common(p, s);
     a.cm.body_prev = nullptr;
@@ -411,27 +443,11 @@ lbm_status lbm_step_multi(const lbm_params* p, lbm_state* s, int64_t n, int leve
     a.levels = levels;
     for (int t = 0; t < levels; ++t) {
         a.fold[t] = (n + 1 + t) % kUstarBlock == 0;
+        a.rec[t] = records ? records[t] : nullptr;
         a.r[t] = r_next[t];
         for (int k = 0; k < 2; ++k) a.fb[t][k] = float(r_next[t] * a.cm.b0[k]);
     }
-    a.nspan = (a.cm.ntile + kMarchTiles - 1) / kMarchTiles;
-    // rows per segment: a segment repeats 2 (levels - 1) rows of level n+1 and fewer of the
-    // later levels, and the launch runs in rounds of one workgroup per compute unit; take
-    // the length between 8 and 64 rows that minimises rounds x iterations per workgroup
-    const int cus = compute_units();
-    int best = 8;
-    int64_t best_cost = -1;
-    for (int sg = 8; sg <= 64; ++sg) {
-        const int64_t nseg = (p->ny + sg - 1) / sg;
-        const int64_t rounds = (nseg * a.nspan + cus - 1) / cus;
-        const int64_t cost = rounds * (sg + 2 * (levels - 1));
-        if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = sg; }
-    }
-    a.seg = best < p->ny ? best : p->ny;
-    const int64_t nseg = (p->ny + a.seg - 1) / a.seg;
-    if (nseg * a.nspan > 0x7fffffff) return LBM_ERR_UNSUPPORTED;
-    a.nwg = int(nseg * a.nspan);
-    a.d_nspan = fast_div(a.nspan);
+    if (!march_geometry(p, levels, a.nspan, a.seg, a.nwg, a.d_nspan)) return LBM_ERR_UNSUPPORTED;
     if (launch_march(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
     s->cur = 1 - s->cur;
     return LBM_OK;
@@ -595,6 +611,43 @@ lbm_status lbm_adjoint_step2(const lbm_params* p, const lbm_state* fwd, lbm_adj_
         a.ed2 = make_edges(at_half_prev);
     }
     if (launch_adjoint2(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
+    adj->cur = 1 - adj->cur;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_step_multi(const lbm_params* p, const lbm_state* fwd, lbm_adj_state* adj, int64_t m,
+                                  int levels, const double* r, const void* const* records, const uint64_t* mask,
+                                  const double* field, void* stream) {
+    lbm_status st = lbm_check_params(p);
+    if (st != LBM_OK) return st;
+    if (!fwd || !adj || !adj->adj[0] || !adj->adj[1] || !r || !records) return LBM_ERR_ARG;
+    if (levels < 2 || levels > kMarchMaxLevels) return LBM_ERR_ARG;
+    if (adj->cur != 0 && adj->cur != 1) return LBM_ERR_ARG;
+    if (adj->nprobe < 0 || (adj->nprobe > 0 && (!adj->probe || !adj->ubar || !mask || !field))) return LBM_ERR_ARG;
+    if (m - (levels - 1) < 0 || m >= adj->nsteps) return LBM_ERR_ARG;
+    for (int t = 0; t < levels; ++t)
+        if (!records[t]) return LBM_ERR_ARG;
+    if (any_wall(p) || p->storage == LBM_F64_PLAIN) return LBM_ERR_UNSUPPORTED;
+    if ((adj->g_mu || adj->g_lam || adj->g_body) && !adj->gsum) return LBM_ERR_ARG;
+    MarchAdjArgs a{};
+    a.cm = make_common(p, fwd);
+    a.src = adj->adj[adj->cur];
+    a.dst = adj->adj[1 - adj->cur];
+    for (int t = 0; t < levels; ++t) {
+        a.rec[t] = records[t];
+        a.r[t] = r[t];
+        a.fold[t] = (m - t) % kGradBlock == 0;
+    }
+    a.g_mu = adj->g_mu;
+    a.g_lam = adj->g_lam;
+    a.g_body = adj->g_body;
+    a.gsum = adj->gsum;
+    a.pmask = adj->nprobe > 0 ? mask : nullptr;
+    a.pfield = adj->nprobe > 0 ? field : nullptr;
+    a.probe_weight = a.cm.dt;                    // every level of the pass is below N
+    a.levels = levels;
+    if (!march_geometry(p, levels, a.nspan, a.seg, a.nwg, a.d_nspan)) return LBM_ERR_UNSUPPORTED;
+    if (launch_march_adjoint(a, (hipStream_t)stream) != hipSuccess) return LBM_ERR_LAUNCH;
     adj->cur = 1 - adj->cur;
     return LBM_OK;
 }

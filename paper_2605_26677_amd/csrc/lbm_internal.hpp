@@ -224,7 +224,29 @@ struct MarchArgs {
     int fold[kMarchMaxLevels];       // accumulator fold after level n+1+t
     double r[kMarchMaxLevels];       // body factor r(n+1+t)
     float fb[kMarchMaxLevels][2];    // uniform body r(n+1+t) b0 rounded to float
+    void* rec[kMarchMaxLevels];      // records of U^{n+1+t} (the replay form), or NULL
     int nspan, seg, nwg;             // spans per row, rows per segment, workgroups
+    FastDiv d_nspan;
+};
+
+// Several adjoint levels per pass on periodic grids (march_adj_kernel), the same workgroups
+// as march_kernel.
+struct MarchAdjArgs {
+    Common cm;
+    const void* src;                 // lambda^{m+1}
+    void* dst;                       // lambda^{m+1-levels}
+    const void* rec[kMarchMaxLevels];   // U^{m-t}, t = 0 .. levels - 1
+    double r[kMarchMaxLevels];       // body factors r(m - t)
+    int fold[kMarchMaxLevels];       // block-sum fold at level m - t
+    double* g_mu;
+    double* g_lam;
+    double* g_body;
+    void* gsum;
+    const uint64_t* pmask;           // probe table (lbm_adjoint_probe_table) or NULL
+    const double* pfield;
+    double probe_weight;
+    int levels;
+    int nspan, seg, nwg;
     FastDiv d_nspan;
 };
 
@@ -327,6 +349,7 @@ struct AdjInitArgs {
 hipError_t launch_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_step2(const Step2Args& a, hipStream_t s);
 hipError_t launch_march(const MarchArgs& a, hipStream_t s);
+hipError_t launch_march_adjoint(const MarchAdjArgs& a, hipStream_t s);
 hipError_t launch_traction(TractionArgs a, hipStream_t s);   // every traction edge, one launch
 hipError_t launch_moments(const RecoverArgs& a, hipStream_t s);
 hipError_t launch_record(const RecoverArgs& a, hipStream_t s);

@@ -9,76 +9,27 @@
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 #include "lbm_kernel_util.hpp"
+#include "lbm_march.hpp"
 
 namespace lbm {
-
-// Element offset of column x inside one row of population tiles (24 planes per tile).
-typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ int pop_col(int x) { return (x >> 6) * (24 * kTile) + (x & (kTile - 1)); }
-
-// The value of lane l - 1 (from_prev) or l + 1 (from_next) across the whole wavefront, by a
-// DPP wave shift (one vector move instead of a permute through the LDS unit); lane 0, resp.
-// 63, receives 0, a value that the kernel below never uses.
-__device__ __forceinline__ float from_prev(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
-}
-__device__ __forceinline__ float from_next(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
-}
-__device__ __forceinline__ double from_prev(double v) {
-    const u32x2_t h = __builtin_bit_cast(u32x2_t, v);
-    const u32x2_t r = {uint32_t(__builtin_amdgcn_update_dpp(0, int(h.x), 0x138, 0xf, 0xf, true)),
-                       uint32_t(__builtin_amdgcn_update_dpp(0, int(h.y), 0x138, 0xf, 0xf, true))};
-    return __builtin_bit_cast(double, r);
-}
-__device__ __forceinline__ double from_next(double v) {
-    const u32x2_t h = __builtin_bit_cast(u32x2_t, v);
-    const u32x2_t r = {uint32_t(__builtin_amdgcn_update_dpp(0, int(h.x), 0x130, 0xf, 0xf, true)),
-                       uint32_t(__builtin_amdgcn_update_dpp(0, int(h.y), 0x130, 0xf, 0xf, true))};
-    return __builtin_bit_cast(double, r);
-}
-
-// Stores through a buffer resource that spans one row of an array: a lane whose byte offset
-// is kNoStore (beyond any row) stores nothing, which the hardware's range check of raw
-// buffers guarantees.  The kernel below issues every store of an iteration this way, on
-// every lane and in every iteration, so that all its iterations issue the same sequence of
-// memory operations (see there).
-constexpr uint32_t kNoStore = 0x80000000u;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, int64_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, int(bytes), 0x00020000);
-}
-
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-constexpr int kStoreNT = 2;     // cache policy: non-temporal, as store_stream
-
-__device__ __forceinline__ void row_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, kStoreNT);
-}
-__device__ __forceinline__ void row_store(__amdgpu_buffer_rsrc_t r, uint32_t off, _Float16 v) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, off, 0, kStoreNT);
-}
-__device__ __forceinline__ void row_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kStoreNT);
-}
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void row_store16(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 v) {
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, kStoreNT);
-}
-__device__ __forceinline__ void row_store8(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x2 v) {
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, kStoreNT);
-}
 
 // The LDS of one workgroup: the output row of its span, in the storage type, and the
 // accumulator words of that row; two buffers (one for FP64, whose row is twice as large)
 // so that one barrier per iteration separates the writes of a row from its reads.
-template <int ST>
+template <int ST, int NT, bool REC>
 struct MarchLds {
     static constexpr int nbuf = ST == LBM_F64_PLAIN ? 1 : 2;
     __attribute__((aligned(16))) typename Storage<ST>::pop_t pop[nbuf][24][kMarchSpan];
     __attribute__((aligned(16))) float S[nbuf][2][kMarchSpan];
     __attribute__((aligned(16))) double U[nbuf][2][kMarchSpan];
+};
+// The replay form (REC: records of every level, no displacement accumulator): the output
+// row of the populations and the rows of the records of the NT levels.
+template <int ST, int NT>
+struct MarchLds<ST, NT, true> {
+    static constexpr int nbuf = 2;
+    __attribute__((aligned(16))) typename Storage<ST>::pop_t pop[2][24][kMarchSpan];
+    __attribute__((aligned(16))) float rec[2][NT][6][kMarchSpan];
 };
 
 // Geometry.  A workgroup owns a span of kMarchTiles = 7 aligned tiles (448 columns) and a
@@ -105,7 +56,11 @@ struct MarchLds {
 // wait for the path with the fewest.  Hence every iteration stores a full tile row on every
 // lane of every wavefront (lanes, wavefronts and iterations without output store to
 // kNoStore), and before the loop one such row of empty stores follows the first loads.
-template <int ST, int LAW, bool FIELDS, int NT>
+//
+// REC (the replay of the checkpointed adjoint): no displacement accumulator; the record of
+// every level (v and F - I, as lbm_step writes it) goes through LDS like the output row
+// and is stored whole per tile for the rows of the segment.
+template <int ST, int LAW, bool FIELDS, int NT, bool REC>
 __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a) {
     using Tr = Storage<ST>;
     using R = typename Tr::real;
@@ -114,8 +69,9 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
     constexpr int OW = kTile - 2 * (NT - 1);
     static_assert(kMarchTiles * OW + OW >= kMarchSpan, "the windows must cover the span");
     constexpr uint32_t kPlane = kTile * sizeof(T);     // bytes between planes of a tile
-    constexpr int NB = MarchLds<ST>::nbuf;
-    __shared__ MarchLds<ST> sh;
+    static_assert(!REC || SH, "records of the shifted storages only");
+    constexpr int NB = MarchLds<ST, NT, REC>::nbuf;
+    __shared__ MarchLds<ST, NT, REC> sh;
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
     const int64_t n = int64_t(nx) * ny;
@@ -184,7 +140,8 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
                 pprm[3] = cm.body[n + idx];
             }
         }
-        if constexpr (ST == LBM_F64_PLAIN) {
+        if constexpr (REC) {
+        } else if constexpr (ST == LBM_F64_PLAIN) {
             const double* us = Ubase + yo * rowu + ou;
             pU[0] = us[0];
             pU[1] = us[kTile];
@@ -206,7 +163,7 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
     // columns (wrapped copies of real nodes, never read).  No branch may choose between
     // store sequences of different lengths here: the compiler's waits would then assume the
     // shortest, and a path that skips both would be taken as possible.
-    auto store_row = [&](int yo, bool outp, int b, bool moved) {
+    auto store_row = [&](int yo, bool outp, int b, bool moved, int outp_iter) {
         const bool on = outp && w < kMarchTiles && st < ntile;
         const __amdgpu_buffer_rsrc_t rp = row_rsrc(dst + yo * rowe, rowe * int64_t(sizeof(T)));
         const uint32_t tb = uint32_t(st * 24 * kTile) * uint32_t(sizeof(T));   // tile's first byte
@@ -220,18 +177,37 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
             const u32x4 v = *(const u32x4*)&sh.pop[b][p][lc + col];
             row_store16(rp, on ? tb + uint32_t(p * kTile + col) * uint32_t(sizeof(T)) : kNoStore, v);
         }
-        // two u* planes of 64 words: 32 lanes per plane
-        const int cp = lane >> 5, cc = (lane & 31) * 2;
-        const uint32_t uw = uint32_t(st * 2 * kTile + cp * kTile + cc);
-        if constexpr (ST != LBM_F64_PLAIN) {
-            const __amdgpu_buffer_rsrc_t rs = row_rsrc(Sbase + yo * rowu, rowu * 4);
-            const u32x2 v = *(const u32x2*)&sh.S[b][cp][lc + cc];
-            row_store8(rs, on ? uw * 4u : kNoStore, v);
-        }
-        if (ST == LBM_F64_PLAIN || moved) {
-            const __amdgpu_buffer_rsrc_t ru = row_rsrc(Ubase + yo * rowu, rowu * 8);
-            const u32x4 v = *(const u32x4*)&sh.U[b][cp][lc + cc];
-            row_store16(ru, on ? uw * 8u : kNoStore, v);
+        if constexpr (REC) {
+            // the record rows of the levels whose rows lie in the segment: 6 planes of 64
+            // words per tile, planes 0 .. 3 in one instruction and 4, 5 on half the lanes
+            const int pl = lane >> 4, col = (lane & 15) * 4;
+            const int64_t rowr = int64_t(ntile) * 6 * kTile;
+#pragma unroll
+            for (int L = 1; L <= NT; ++L) {
+                const int i0 = NT + L - 2;                  // first iteration of a segment row
+                const bool rin = outp_iter >= i0 && outp_iter < i0 + Sy && w < kMarchTiles && st < ntile;
+                const __amdgpu_buffer_rsrc_t rr = row_rsrc((float*)a.rec[L - 1] + rw[L] * rowr, rowr * 4);
+                const uint32_t tr = uint32_t(st * 6 * kTile);
+                const u32x4 v0 = *(const u32x4*)&sh.rec[b][L - 1][pl][lc + col];
+                row_store16(rr, rin ? (tr + uint32_t(pl * kTile + col)) * 4u : kNoStore, v0);
+                const int p1 = 4 + (pl & 1);
+                const u32x4 v1 = *(const u32x4*)&sh.rec[b][L - 1][p1][lc + col];
+                row_store16(rr, rin && pl < 2 ? (tr + uint32_t(p1 * kTile + col)) * 4u : kNoStore, v1);
+            }
+        } else {
+            // two u* planes of 64 words: 32 lanes per plane
+            const int cp = lane >> 5, cc = (lane & 31) * 2;
+            const uint32_t uw = uint32_t(st * 2 * kTile + cp * kTile + cc);
+            if constexpr (ST != LBM_F64_PLAIN) {
+                const __amdgpu_buffer_rsrc_t rs = row_rsrc(Sbase + yo * rowu, rowu * 4);
+                const u32x2 v = *(const u32x2*)&sh.S[b][cp][lc + cc];
+                row_store8(rs, on ? uw * 4u : kNoStore, v);
+            }
+            if (ST == LBM_F64_PLAIN || moved) {
+                const __amdgpu_buffer_rsrc_t ru = row_rsrc(Ubase + yo * rowu, rowu * 8);
+                const u32x4 v = *(const u32x4*)&sh.U[b][cp][lc + cc];
+                row_store16(ru, on ? uw * 8u : kNoStore, v);
+            }
         }
     };
     // parameters (mu, lam, body) of the rows of levels n+1 .. n+NT, newest first
@@ -267,8 +243,18 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
 
     const int iters = Sy + 2 * (NT - 1);
     prefetch(rw[0], rw[1], rw[2], rw[NT]);
-    store_row(rw[NT], false, 0, false);
+    store_row(rw[NT], false, 0, false, -1);
     for (int i = 0; i < iters; ++i) {
+        const int b = NB == 1 ? 0 : (i & 1);
+        // REC: the record of level t at this lane's output column into LDS buffer b
+        auto stage_record = [&](int t, const R Uv[6]) {
+            if constexpr (REC) {
+                if (out_lane) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) sh.rec[b][t][k][pos] = Uv[k];
+                }
+            }
+        };
         R f[4][6], U[6], J;
         R cv[NT][2] = {};
         R gq[4][6];
@@ -302,6 +288,7 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
             jbad |= J <= R(0);
             cv[0][0] = U[0];
             cv[0][1] = U[1];
+            stage_record(0, U);
         }
 #pragma unroll
         for (int L = 2; L <= NT; ++L) {
@@ -340,6 +327,7 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
             }
             cv[L - 1][0] = U[0];
             cv[L - 1][1] = U[1];
+            stage_record(L - 1, U);
         }
         // f: level n+NT of output row y1 - (NT - 1) from iteration 2 (NT - 1) on.  The
         // displacement quadrature over the NT levels (eq:trapezoid-u), with the accumulator
@@ -350,7 +338,8 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
         bool moved = false;
 #pragma unroll
         for (int cpt = 0; cpt < 2; ++cpt) {
-            if constexpr (ST == LBM_F64_PLAIN) {
+            if constexpr (REC) {
+            } else if constexpr (ST == LBM_F64_PLAIN) {
                 double s = Up[cpt];
 #pragma unroll
                 for (int L = 1; L <= NT; ++L) s = s + dt * (L == NT ? cv[NT - 1][cpt] : vh[L - 1][NT - L - 1][cpt]);
@@ -374,19 +363,20 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
                 moved = mv;
             }
         }
-        const int b = NB == 1 ? 0 : (i & 1);
         if (NB == 1) __syncthreads();               // the previous row has been read
         if (outp && out_lane) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) sh.pop[b][6 * q + k][pos] = to_storage<T>(f[q][k]);
-            if constexpr (ST != LBM_F64_PLAIN) {
-                sh.S[b][0][pos] = Sn[0];
-                sh.S[b][1][pos] = Sn[1];
+            if constexpr (!REC) {
+                if constexpr (ST != LBM_F64_PLAIN) {
+                    sh.S[b][0][pos] = Sn[0];
+                    sh.S[b][1][pos] = Sn[1];
+                }
+                sh.U[b][0][pos] = Un[0];
+                sh.U[b][1][pos] = Un[1];
             }
-            sh.U[b][0][pos] = Un[0];
-            sh.U[b][1][pos] = Un[1];
             if (lane >= NT - 1 && lane <= kTile - NT) {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) nonfinite |= !finite_r(U[k]);
@@ -394,7 +384,7 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
             }
         }
         __syncthreads();
-        store_row(rw[NT], outp, b, moved);
+        store_row(rw[NT], outp, b, moved, i);
         // the velocity history moves one row on
 #pragma unroll
         for (int L = 1; L < NT; ++L) {
@@ -419,10 +409,19 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
 template <int ST, int LAW, bool FIELDS>
 static hipError_t march_levels(const MarchArgs& a, hipStream_t s) {
     const dim3 grid(unsigned(a.nwg)), block(kMarchWaves * kTile);
+    if (a.rec[0]) {
+        // the replay form: records of every level, no accumulator; up to three levels (four
+        // levels of records would not fit the LDS beside the output row)
+        if constexpr (ST != LBM_F64_PLAIN) {
+            if (a.levels == 2) hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 2, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 3, true>), grid, block, 0, s, a);
+        }
+        return hipGetLastError();
+    }
     switch (a.levels) {
-        case 2: hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 2>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 3>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 4>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 2, false>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 3, false>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 4, false>), grid, block, 0, s, a); break;
     }
     return hipGetLastError();
 }

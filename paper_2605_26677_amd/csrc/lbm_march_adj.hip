@@ -1,0 +1,338 @@
+// Several levels of the hand-written adjoint per pass over HBM on periodic grids
+// (lbm_adjoint_step_multi): the transpose of march_kernel.  A wavefront marches a window of
+// 64 columns down a segment of rows; each iteration pulls one new row of lambda^{m+1} from
+// memory and takes it to lambda^m, and takes the rows behind it one adjoint level further
+// each, so that the levels in between never leave registers.  Every node's arithmetic is
+// adj_node, as in adjoint_kernel, with the probe source and the gradient updates of each
+// level in the order of single steps, so the result is bit for bit that of as many
+// lbm_adjoint_step calls.
+#include "lbm_adjoint.hpp"
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+#include "lbm_kernel_util.hpp"
+#include "lbm_march.hpp"
+
+namespace lbm {
+
+// The LDS of one workgroup: the output row of lambda and of the FP32 gradient block sums,
+// two buffers so that one barrier per iteration separates the writes of a row from its
+// reads.
+struct MarchAdjLds {
+    __attribute__((aligned(16))) float lam[2][24][kMarchSpan];
+    __attribute__((aligned(16))) float gs[2][4][kMarchSpan];
+};
+
+// Geometry and memory operations as in march_kernel.  The adjoint pulls from X + c_q: level
+// t+1 of row y takes q0 from x+1 and q2 from x-1 of row y (lanes shifted), q1 from row y+1
+// (this iteration) and q3 from row y-1 (two iterations before).  Level t of the pass is
+// adjoint level m - t and reads the record of U^{m-t}.  The FP32 compute type is the
+// storage of lambda, so no level is rounded.
+//
+// Gradients (GRAD): the increments of each level of a node are kept until the node's last
+// level, then added to its block sums in level order, with the folds into the FP64
+// gradients at the levels that fold and the probe body term of each level after its
+// increment, as single steps do.
+template <int ST, int LAW, bool FIELDS, int NT, bool GRAD>
+__global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdjArgs a) {
+    using R = float;
+    constexpr int OW = kTile - 2 * (NT - 1);
+    static_assert(ST != LBM_F64_PLAIN, "the FP32 compute type only");
+    static_assert(kMarchTiles * OW + OW >= kMarchSpan, "the windows must cover the span");
+    __shared__ MarchAdjLds sh;
+    const Common& cm = a.cm;
+    const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
+    const int64_t n = int64_t(nx) * ny;
+    const int lane = threadIdx.x & (kTile - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = remap_tile(blockIdx.x, gridDim.x);
+    if (g >= a.nwg) return;
+    const int seg = fdiv(g, a.d_nspan), span = g - seg * a.nspan;
+    const int c0 = span * kMarchSpan;
+    const int ws = w < kMarchTiles ? w * OW : kMarchSpan - OW;
+    const int xg = c0 + ws - (NT - 1) + lane;
+    const int xc = wrap_index(xg, nx);
+    const int om = pop_col(wrap_dec(xc, nx)), oc = pop_col(xc), op = pop_col(wrap_inc(xc, nx));
+    const int orc = (xc >> 6) * (6 * kTile) + (xc & (kTile - 1));     // in a row of record tiles
+    const int64_t rowe = int64_t(ntile) * 24 * kTile;
+    const int64_t rowr = int64_t(ntile) * 6 * kTile;
+    const int64_t rowg = int64_t(ntile) * 4 * kTile;
+    const int og = (xc >> 6) * (4 * kTile) + (xc & (kTile - 1));      // in a row of block-sum tiles
+    const int Y0 = seg * a.seg, Sy = min(a.seg, ny - Y0);
+    const int pos = ws - (NT - 1) + lane;
+    const bool out_lane = lane >= NT - 1 && lane <= kTile - NT &&
+                          (w < kMarchTiles || pos >= (kMarchTiles - 1) * OW + OW);
+    const int st = c0 / kTile + w;
+    const R* __restrict__ src = (const R*)a.src;
+    R* __restrict__ dst = (R*)a.dst;
+    float* gsum = (float*)a.gsum;
+    const bool gpar = a.g_mu || a.g_lam, gbody = a.g_body != nullptr;
+    const bool has[4] = {a.g_mu != nullptr, a.g_lam != nullptr, gbody, gbody};
+    double* const g64[4] = {a.g_mu, a.g_lam, a.g_body, a.g_body ? a.g_body + n : nullptr};
+    const double hdt = 0.5 * cm.dt;
+
+    int rw[NT + 1];
+#pragma unroll
+    for (int j = 0; j <= NT; ++j) rw[j] = wrap_index(Y0 - (NT - 1) + 1 - j, ny);
+
+    // Loaded one iteration ahead: lambda^{m+1} pulled for the next row to enter level m, the
+    // records and probe-mask words of the rows of every level, mu and lam of the new row, and
+    // the block sums of the next output row.
+    float pre[24];
+    float prec[NT][4];
+    uint64_t pmw[NT];
+    float pprm[2] = {0.0f, 0.0f};
+    float pgs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    auto prefetch = [&](int yp, int yc, int ym, int yo) {
+        const R* rc = src + yc * rowe;
+        const R* rp = src + yp * rowe;
+        const R* rm = src + ym * rowe;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            pre[k] = rc[op + k * kTile];
+            pre[12 + k] = rc[om + (12 + k) * kTile];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            pre[6 + k] = rp[oc + (6 + k) * kTile];
+            pre[18 + k] = rm[oc + (18 + k) * kTile];
+        }
+        // level t's row in the next iteration: yc - t (rows behind the new one)
+        int yt = yc;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const R* rec = (const R*)a.rec[t] + yt * rowr + orc;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) prec[t][k] = rec[(2 + k) * kTile];
+            pmw[t] = a.pmask ? a.pmask[int64_t(yt) * ntile + (xc >> 6)] : 0ull;
+            yt = yt == 0 ? ny - 1 : yt - 1;
+        }
+        if constexpr (FIELDS) {
+            const int idx = yc * nx + xc;
+            if (cm.mu) pprm[0] = cm.mu[idx];
+            if (cm.lam) pprm[1] = cm.lam[idx];
+        }
+        if constexpr (GRAD) {
+            const float* gp = gsum + yo * rowg + og;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pgs[j] = gp[j * kTile];
+        }
+    };
+    // the stores of output row yo from LDS buffer b (byte offsets kNoStore where nothing is
+    // stored; see march_kernel): tile st of lambda and of the block sums, whole, in 16-byte
+    // pieces
+    auto store_row = [&](int yo, bool outp, int b) {
+        const bool on = outp && w < kMarchTiles && st < ntile;
+        const int lc = w < kMarchTiles ? w * kTile : 0;
+        const __amdgpu_buffer_rsrc_t rl = row_rsrc(dst + yo * rowe, rowe * int64_t(sizeof(R)));
+        const uint32_t tb = uint32_t(st * 24 * kTile) * uint32_t(sizeof(R));
+        const int pl = lane >> 4, col = (lane & 15) * 4;   // 4 planes of 64 words per instruction
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const int p = 4 * j + pl;
+            const u32x4 v = *(const u32x4*)&sh.lam[b][p][lc + col];
+            row_store16(rl, on ? tb + uint32_t(p * kTile + col) * 4u : kNoStore, v);
+        }
+        if constexpr (GRAD) {
+            const __amdgpu_buffer_rsrc_t rg = row_rsrc(gsum + yo * rowg, rowg * 4);
+            const u32x4 v = *(const u32x4*)&sh.gs[b][pl][lc + col];
+            row_store16(rg, on ? uint32_t(st * 4 * kTile + pl * kTile + col) * 4u : kNoStore, v);
+        }
+    };
+    // mu, lam of the rows of the levels, newest first
+    float prm[NT][2];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) prm[t][0] = prm[t][1] = 0.0f;
+
+    // lambda of levels t = 0 .. NT-2 of the rows behind: q3 of the last two rows, q0 and q2 of
+    // the last row shifted to the lanes that pull them
+    R hq3a[NT - 1][6], hq3b[NT - 1][6], ho0[NT - 1][6], ho2[NT - 1][6];
+    // gradient increments of level t (< NT-1) of the last NT-1-t rows, newest first
+    R gh[NT][NT][4];
+#pragma unroll
+    for (int t = 0; t < NT - 1; ++t)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) hq3a[t][k] = hq3b[t][k] = ho0[t][k] = ho2[t][k] = R(0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) gh[t][j][c] = R(0);
+
+    const int iters = Sy + 2 * (NT - 1);
+    prefetch(rw[0], rw[1], rw[2], rw[NT]);
+    store_row(rw[NT], false, 0);
+    for (int i = 0; i < iters; ++i) {
+        R f[4][6];
+        R cinc[NT][4] = {};
+        R l[4][6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            l[0][k] = pre[k];
+            l[1][k] = pre[6 + k];
+            l[2][k] = pre[12 + k];
+            l[3][k] = pre[18 + k];
+        }
+        float rec[NT][4];
+        uint64_t mw[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rec[t][k] = prec[t][k];
+            mw[t] = pmw[t];
+        }
+        if constexpr (FIELDS) {
+#pragma unroll
+            for (int t = NT - 1; t >= 1; --t) {
+                prm[t][0] = prm[t - 1][0];
+                prm[t][1] = prm[t - 1][1];
+            }
+            prm[0][0] = pprm[0];
+            prm[0][1] = pprm[1];
+        }
+        float gsp[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gsp[j] = pgs[j];
+        prefetch(wrap_inc(rw[0], ny), rw[0], rw[1], rw[NT - 1]);
+
+        auto level = [&](int t, int y, R out[4][6], double ps[2], bool& probe) {
+            R mu, lam;
+            if (FIELDS && cm.mu) mu = prm[t][0]; else mu = kval<R>(cm.mu0, cm.f_mu0);
+            if (FIELDS && cm.lam) lam = prm[t][1]; else lam = kval<R>(cm.lam0, cm.f_lam0);
+            adj_node<R, LAW>(cm, l, rec[t], mu, lam, R(a.r[t]), gpar, gbody, out, cinc[t]);
+            probe = (mw[t] >> (xc & 63)) & 1ull;
+            if (probe) {
+                const int64_t idx = int64_t(y) * nx + xc;
+                ps[0] = a.probe_weight * a.pfield[idx];
+                ps[1] = a.probe_weight * a.pfield[n + idx];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    out[q][0] += R(ps[0]);
+                    out[q][1] += R(ps[1]);
+                }
+            }
+        };
+        double ps[2] = {0.0, 0.0};
+        bool probe = false;
+        level(0, rw[1], f, ps, probe);
+#pragma unroll
+        for (int L = 2; L <= NT; ++L) {
+            if (i < 2 * (L - 2)) break;             // level L-1 of the pass has not started
+            const bool act = i >= 2 * (L - 1);
+            if (act) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    l[0][k] = ho0[L - 2][k];
+                    l[1][k] = f[1][k];
+                    l[2][k] = ho2[L - 2][k];
+                    l[3][k] = hq3b[L - 2][k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                hq3b[L - 2][k] = hq3a[L - 2][k];
+                hq3a[L - 2][k] = f[3][k];
+                ho0[L - 2][k] = from_next(f[0][k]);
+                ho2[L - 2][k] = from_prev(f[2][k]);
+            }
+            if (!act) break;
+            level(L - 1, rw[L], f, ps, probe);
+        }
+        // f: lambda of the pass's last level at output row y1 - (NT - 1) from iteration
+        // 2 (NT - 1) on; ps and probe: that node's probe source
+        const bool outp = i >= 2 * (NT - 1);
+        float gn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (GRAD) {
+            const int64_t gi = int64_t(rw[NT]) * nx + xc;
+            // the lane that owns the node for the direct FP64 updates: on a grid narrower
+            // than the span, columns beyond nx wrap onto nodes other lanes own
+            const bool own = outp && out_lane && c0 + pos < nx;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) gn[j] = gsp[j];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const R* inc = t == NT - 1 ? cinc[NT - 1] : gh[t][NT - t - 2];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (!has[j]) continue;
+                    gn[j] = gn[j] + float(inc[j]);
+                    if (a.fold[t]) {
+                        if (own) g64[j][gi] += double(gn[j]);
+                        gn[j] = 0.0f;
+                    }
+                }
+                if (own && probe && gbody) {
+                    a.g_body[gi] += a.r[t] * hdt * ps[0];
+                    a.g_body[n + gi] += a.r[t] * hdt * ps[1];
+                }
+            }
+        }
+        const int b = i & 1;
+        if (outp && out_lane) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) sh.lam[b][6 * q + k][pos] = f[q][k];
+            if constexpr (GRAD) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) sh.gs[b][j][pos] = gn[j];
+            }
+        }
+        __syncthreads();
+        store_row(rw[NT], outp, b);
+        // the increment history moves one row on
+        if constexpr (GRAD) {
+#pragma unroll
+            for (int t = 0; t < NT - 1; ++t) {
+#pragma unroll
+                for (int j = NT - t - 2; j >= 1; --j)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) gh[t][j][c] = gh[t][j - 1][c];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) gh[t][0][c] = cinc[t][c];
+            }
+        }
+#pragma unroll
+        for (int j = NT; j >= 1; --j) rw[j] = rw[j - 1];
+        rw[0] = wrap_inc(rw[0], ny);
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+template <int ST, int LAW, bool FIELDS, bool GRAD>
+static hipError_t march_adj_levels(const MarchAdjArgs& a, hipStream_t s) {
+    const dim3 grid(unsigned(a.nwg)), block(kMarchWaves * kTile);
+    switch (a.levels) {
+        case 2: hipLaunchKernelGGL((march_adj_kernel<ST, LAW, FIELDS, 2, GRAD>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((march_adj_kernel<ST, LAW, FIELDS, 3, GRAD>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((march_adj_kernel<ST, LAW, FIELDS, 4, GRAD>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int ST, int LAW>
+static hipError_t march_adj_st_law(const MarchAdjArgs& a, hipStream_t s) {
+    const bool fields = a.cm.mu || a.cm.lam;
+    const bool grad = a.g_mu || a.g_lam || a.g_body;
+    if (fields) return grad ? march_adj_levels<ST, LAW, true, true>(a, s) : march_adj_levels<ST, LAW, true, false>(a, s);
+    return grad ? march_adj_levels<ST, LAW, false, true>(a, s) : march_adj_levels<ST, LAW, false, false>(a, s);
+}
+
+template <int ST>
+static hipError_t march_adj_st(const MarchAdjArgs& a, hipStream_t s) {
+    switch (a.cm.material) {
+        case LBM_LOGNH: return march_adj_st_law<ST, LBM_LOGNH>(a, s);
+        case LBM_NH: return march_adj_st_law<ST, LBM_NH>(a, s);
+        case LBM_MR: return march_adj_st_law<ST, LBM_MR>(a, s);
+        case LBM_YEOH: return march_adj_st_law<ST, LBM_YEOH>(a, s);
+        case LBM_GENT: return march_adj_st_law<ST, LBM_GENT>(a, s);
+        default: return march_adj_st_law<ST, LBM_SVK>(a, s);
+    }
+}
+
+// FP32 and FP16 storage share the kernel: the adjoint populations and the records are in
+// the FP32 compute type for both.
+hipError_t launch_march_adjoint(const MarchAdjArgs& a, hipStream_t s) { return march_adj_st<LBM_F32_SHIFTED>(a, s); }
+
+}  // namespace lbm

@@ -296,6 +296,18 @@ class _Adjoint:
                                          _ptr(self.pmask), _ptr(self.pfield), _stream()),
                 "lbm_adjoint_step2")
 
+    def step_multi(self, sv, cfg, m, records):
+        """lbm_adjoint_step_multi: levels m, m - 1, ..., m - len(records) + 1 in one pass;
+        records[t] holds U^{m-t}."""
+        k = len(records)
+        r = (ctypes.c_double * k)(*[float(cfg.ramp(m - t)) for t in range(k)])
+        recs = (ctypes.c_void_p * k)(*[rec.data_ptr() for rec in records])
+        L.check(sv.lib.lbm_adjoint_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), int(m),
+                                              int(k), ctypes.cast(r, ctypes.c_void_p),
+                                              ctypes.cast(recs, ctypes.c_void_p), _ptr(self.pmask),
+                                              _ptr(self.pfield), _stream()),
+                "lbm_adjoint_step_multi")
+
     def init(self, sv, cfg, v0, u0):
         L.check(sv.lib.lbm_adjoint_init(ctypes.byref(sv.p), ctypes.byref(sv.s), ctypes.byref(self.a), _ptr(v0),
                                         _ptr(u0), host_matrix(cfg.Fbar), float(cfg.ramp(0)), _ptr(self.g_v0),
@@ -348,21 +360,31 @@ def _plain_steps(sv, cfg, n0, n1, ustar=True):
 def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
     """Adjoint levels end-1 .. start, starting from the snapshot of level `start`.  The
     replay skips the displacement quadrature (the adjoint does not read u*) and records
-    U of every level, two levels per call."""
+    U of every level, several levels per call (Solver.replay_multi_levels, else pairs);
+    the adjoint takes several levels per call (Solver.adj_multi_levels, else pairs)."""
     _restore(sv, snap)
     recs[0].copy_(snap[1], non_blocking=True)
     n = start
     pairs = _pairs(sv, cfg)
+    rmulti = sv.replay_multi_levels if pairs else 0
     while n < end - 1:
-        if pairs and n + 1 < end - 1:
+        if rmulti and n + rmulti <= end - 1:
+            sv.step_multi(n, rmulti, [cfg.ramp(n + 1 + t) for t in range(rmulti)],
+                          records=[recs[n + 1 + t - start] for t in range(rmulti)], ustar=False)
+            n += rmulti
+        elif pairs and n + 1 < end - 1:
             _pair(sv, cfg, n, record1=recs[n + 1 - start], record2=recs[n + 2 - start], ustar=False)
             n += 2
         else:
             sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=recs[n + 1 - start], ustar=False)
             n += 1
     m = end - 1
+    multi = sv.adj_multi_levels if cfg.pairs is not False else 0
     while m >= start:
-        if adj.pair_ok(sv, cfg, m, start):
+        if multi and m - (multi - 1) >= start and m < cfg.nsteps:
+            adj.step_multi(sv, cfg, m, [recs[m - t - start] for t in range(multi)])
+            m -= multi
+        elif adj.pair_ok(sv, cfg, m, start):
             adj.step2(sv, cfg, m, recs[m - start], recs[m - 1 - start])
             m -= 2
         else:

@@ -119,6 +119,12 @@ class Solver:
     # against 46.1k, 2048^2 79.4k against 49.7k: a small grid leaves compute units idle)
     MULTI_LEVELS = 4
     MULTI_MIN_NODES = 1024 * 1024
+    # adjoint levels per lbm_adjoint_step_multi call (8192^2 FP32, per-node mu lam, gradients:
+    # pairs through lbm_adjoint_step2 1.78 ms per level, three levels 1.41, four 1.86: its
+    # registers then overflow)
+    ADJ_MULTI_LEVELS = 3
+    # levels per lbm_step_multi call in the replay form (records of every level): at most 3
+    REPLAY_MULTI_LEVELS = 3
 
     def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
                  bc=("periodic",) * 4, mu=0.1, lam=0.2, body=None, newton_max_iter=0,
@@ -260,19 +266,28 @@ class Solver:
         finally:
             self.s.ustar = keep
 
-    def step_multi(self, n, levels, r_next=None, ustar=True):
+    def step_multi(self, n, levels, r_next=None, records=None, ustar=True):
         """lbm_step_multi: levels n -> n + levels in one pass on a periodic grid, bit for bit
-        the same as `levels` calls of step; r_next[t] is the body factor of level n + 1 + t."""
+        the same as `levels` calls of step; r_next[t] is the body factor of level n + 1 + t.
+        With records (one record tensor per level) the replay form: records of every level
+        and no accumulator update (then ustar must be False)."""
         r = [1.0] * levels if r_next is None else [float(x) for x in r_next]
         if len(r) != levels:
             raise ValueError("r_next needs one factor per level")
         arr = (ctypes.c_double * levels)(*r)
+        recs = None
+        if records is not None:
+            if len(records) != levels:
+                raise ValueError("one record per level")
+            recs = (ctypes.c_void_p * levels)(*[t.data_ptr() for t in records])
         keep = self.s.ustar
         if not ustar:
             self.s.ustar = None
         try:
             L.check(self.lib.lbm_step_multi(ctypes.byref(self.p), ctypes.byref(self.s), int(n), int(levels),
-                                            ctypes.cast(arr, ctypes.c_void_p), _stream()), "lbm_step_multi")
+                                            ctypes.cast(arr, ctypes.c_void_p),
+                                            ctypes.cast(recs, ctypes.c_void_p) if recs is not None else None,
+                                            _stream()), "lbm_step_multi")
         finally:
             self.s.ustar = keep
 
@@ -285,6 +300,21 @@ class Solver:
         ok = (self.periodic and self.pairs_ok and self.storage != "f64" and self.s.ustar
               and self.nx * self.ny >= self.MULTI_MIN_NODES)
         return self.MULTI_LEVELS if ok else 0
+
+    @property
+    def replay_multi_levels(self):
+        """Levels per lbm_step_multi call in the replay form (records, no accumulator) where
+        that is faster than pairs, as multi_levels; 0 elsewhere."""
+        ok = (self.periodic and self.pairs_ok and self.storage != "f64"
+              and self.nx * self.ny >= self.MULTI_MIN_NODES)
+        return self.REPLAY_MULTI_LEVELS if ok else 0
+
+    @property
+    def adj_multi_levels(self):
+        """Adjoint levels per lbm_adjoint_step_multi call where that is the fastest way: as
+        multi_levels (periodic grids of at least MULTI_MIN_NODES nodes, FP32 or FP16), else 0."""
+        ok = self.periodic and self.storage != "f64" and self.nx * self.ny >= self.MULTI_MIN_NODES
+        return self.ADJ_MULTI_LEVELS if ok else 0
 
     @property
     def periodic(self):

@@ -27,8 +27,9 @@ def test_byte_counts():
     # four levels per launch: populations and S once per launch, U folded on a quarter of them
     assert [bench.bytes_per_lu_multi(s, 4) for s in ("f32", "f16", "f64")] == [216.0, 120.0, 416]
     assert bench.bytes_per_lu_multi("f32", 2) == 212.0
-    # the forward + adjoint byte model: the forward sweep in four-level launches
-    assert bench.fwd_adj_bytes_per_level("f32", 50, 4) == 232 / 4 + (256 + 272) / 2 + 240 / 50
+    # the forward + adjoint byte model: forward, replay and adjoint in multi-level launches
+    assert bench.fwd_adj_bytes_per_level("f32", 50, (4, 3, 3)) == 232 / 4 + 280 / 3 + 280 / 3 + 240 / 50
+    assert bench.fwd_adj_bytes_per_level("f64", 25) == (432 + 496 + 584) / 2 + 480 / 25
 
 
 def test_profile_summaries_parse():

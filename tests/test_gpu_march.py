@@ -85,6 +85,46 @@ def test_multi_bitwise_equals_single_steps(storage, levels, nx, ny, fields):
         _multi_vs_single(case, storage, levels, start, passes=12 // levels)
 
 
+def _replay_vs_single(case, storage, levels, start, passes):
+    """The replay form: single steps with a record each and no accumulator against
+    lbm_step_multi with the records of every level."""
+    single = make_solver(case, storage)
+    multi = make_solver(case, storage)
+    for sv in (single, multi):
+        sv.init(case.v0, r0=case.ramp(0))
+        for m in range(start):
+            sv.step(m, case.ramp(m), case.ramp(m + 1))
+    n = start
+    for _ in range(passes):
+        ra = [single.new_record() for _ in range(levels)]
+        rb = [multi.new_record() for _ in range(levels)]
+        for t in range(levels):
+            single.step(n + t, case.ramp(n + t), case.ramp(n + t + 1), record=ra[t], ustar=False)
+        multi.step_multi(n, levels, [case.ramp(n + 1 + t) for t in range(levels)], records=rb, ustar=False)
+        n += levels
+        torch.cuda.synchronize()
+        for a, b in zip(ra, rb):
+            assert torch.equal(_record_nodes(single, a), _record_nodes(multi, b))
+    assert torch.equal(single.populations(), multi.populations())
+    assert single.faults() == multi.faults() == 0
+
+
+def _record_nodes(sv, rec):
+    """The 6 planes of a record at the grid's nodes (its tiled layout without padding)."""
+    w = int(sv.lib.lbm_tile_width())
+    T = sv.tiles_per_row
+    r = rec.view(torch.float32).view(sv.ny, T, 6, w)
+    return r.permute(2, 0, 1, 3).reshape(6, sv.ny, T * w)[:, :, : sv.nx]
+
+
+@pytest.mark.parametrize("fields", [False, True])
+@pytest.mark.parametrize("nx,ny", [(64, 64), (121, 13), (500, 9), (5, 3), (3, 3)])
+@pytest.mark.parametrize("levels", [2, 3])
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_multi_replay_bitwise_equals_single_steps(storage, levels, nx, ny, fields):
+    _replay_vs_single(_case(nx, ny, fields=fields), storage, levels, 1, passes=12 // levels)
+
+
 @pytest.mark.parametrize("nx,ny", [(2500, 23), (4160, 70)])
 @pytest.mark.parametrize("levels", [2, 3, 4])
 def test_multi_bitwise_wide_grids(nx, ny, levels):
@@ -140,15 +180,28 @@ def test_multi_refuses_bad_arguments():
     r = (ctypes.c_double * 5)(1, 1, 1, 1, 1)
     for levels in (0, 1, 5):
         st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, levels,
-                                   ctypes.cast(r, ctypes.c_void_p), None)
+                                   ctypes.cast(r, ctypes.c_void_p), None, None)
         assert st == L.LBM_ERR_ARG
-    st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 3, None, None)
+    st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 3, None, None, None)
     assert st == L.LBM_ERR_ARG
+    # the replay form: records need no accumulator, at most three levels, no FP64
+    recs = [sv.new_record() for _ in range(4)]
+    rp = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in recs])
+    st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 3, ctypes.cast(r, ctypes.c_void_p),
+                               ctypes.cast(rp, ctypes.c_void_p), None)
+    assert st == L.LBM_ERR_UNSUPPORTED                  # s->ustar is set
+    keep = sv.s.ustar
+    sv.s.ustar = None
+    st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 4, ctypes.cast(r, ctypes.c_void_p),
+                               ctypes.cast(rp, ctypes.c_void_p), None)
+    assert st == L.LBM_ERR_UNSUPPORTED                  # four levels of records
+    sv.s.ustar = keep
     walled = Case("multi_walled", 32, 16, 10.0, 1.95, 0, kinds=("velocity", "traction", "periodic", "periodic"),
                   mu=0.1, lam=0.2, v0=np.zeros((2, 16, 32)))
     sw = make_solver(walled, "f32")
     sw.init(walled.v0)
-    st = sw.lib.lbm_step_multi(ctypes.byref(sw.p), ctypes.byref(sw.s), 0, 3, ctypes.cast(r, ctypes.c_void_p), None)
+    st = sw.lib.lbm_step_multi(ctypes.byref(sw.p), ctypes.byref(sw.s), 0, 3, ctypes.cast(r, ctypes.c_void_p), None,
+                               None)
     assert st == L.LBM_ERR_UNSUPPORTED
 
 

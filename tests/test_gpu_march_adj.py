@@ -1,0 +1,131 @@
+"""Several fused adjoint levels per pass (lbm_adjoint_step_multi, periodic grids) against
+single adjoint steps (lbm_adjoint_step).
+
+lbm_adjoint_step_multi promises the result of lbm_adjoint_step(m), ..., lbm_adjoint_step(m -
+levels + 1), bit for bit: the adjoint populations, the FP32 gradient block sums and the FP64
+gradients of mu, lam and the body force, with the probe sources of every level.  The cases
+cover 2, 3 and 4 levels per pass; FP32 and FP16 storage; a closed-form and an invariant-based
+law; per-node mu, lam and body force with a ramp and uniform parameters; probe cells on
+window edges and elsewhere; gradients requested or not; grids that are multiples neither of
+the kernel's window nor of its segment of rows, down to 3 x 3; start levels that put the
+16-level fold of the block sums on each level of a pass; and refusals of what it does not
+take (FP64, walls, level N, a level below 0).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as li
+from gpu_cases import Case, make_solver
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(nx, ny, storage, law, N, fields=True, seed=7):
+    rng = np.random.default_rng(seed)
+    if min(nx, ny) >= 4:
+        v0 = np.stack([li.gaussian_random_field(nx, ny, 701, 3e-3), li.gaussian_random_field(nx, ny, 702, 3e-3)])
+    else:
+        v0 = 3e-3 * rng.standard_normal((2, ny, nx))
+    mu = li.lognormal_field(nx, ny, 703, 0.1, 0.3, 4.0) if fields else 0.1
+    lam = li.lognormal_field(nx, ny, 704, 0.2, 0.3, 4.0) if fields else 0.2
+    body = li.uniform_body(nx, ny, (2e-4, -3e-4)) if fields else (1e-4, -2e-4)
+    case = Case(f"madj_{law}_{nx}x{ny}", nx, ny, 2.5, 1.9, N, law=law, mu=mu, lam=lam, body=body, ramp_steps=6,
+                v0=v0)
+    sv = make_solver(case, storage)
+    sv.init(v0, r0=case.ramp(0))
+    recs = [sv.record_state(case.ramp(0), sv.new_record())]
+    for n in range(N):
+        r = sv.new_record()
+        sv.step(n, case.ramp(n), case.ramp(n + 1), record=r)
+        recs.append(r)
+    nprobe = min(9, nx * ny)
+    cells = set(rng.choice(nx * ny, size=nprobe, replace=False).tolist())
+    # probes on the columns where windows of four levels meet (58, 116) and at a span edge
+    for x in (57, 58, 63, 64, 447, 448):
+        cells.add((ny // 2) * nx + (x % nx))
+    cells = np.array(sorted(cells))
+    ubar = rng.standard_normal((2, cells.size))
+    return case, sv, recs, cells, ubar
+
+
+def _adjoint_state(sv, case, N, cells, ubar, grads=True):
+    from paper_2605_26677_amd.rollout import RolloutConfig, _Adjoint
+    cfg = RolloutConfig(nx=case.nx, ny=case.ny, c=case.c, omega=case.omega, nsteps=N,
+                        probes=torch.tensor(cells, dtype=torch.int64), storage=sv.storage, ramp=case.ramp)
+    st = _Adjoint(sv, cfg, torch.tensor(ubar))
+    if not grads:
+        st.a.g_mu = st.a.g_lam = st.a.g_body = None
+    return cfg, st
+
+
+def _valid(sv, buf, planes, dtype):
+    w = int(sv.lib.lbm_tile_width())
+    T = sv.tiles_per_row
+    b = buf.view(dtype).view(sv.ny, T, planes, w)
+    return b.permute(2, 0, 1, 3).reshape(planes, sv.ny, T * w)[:, :, : sv.nx]
+
+
+def _compare(sv, case, recs, cells, ubar, N, levels, lead, grads=True):
+    cfg, single = _adjoint_state(sv, case, N, cells, ubar, grads)
+    _, multi = _adjoint_state(sv, case, N, cells, ubar, grads)
+    for st in (single, multi):
+        for k in range(lead):                     # level N (half-weight probe term) and more singles
+            st.step(sv, cfg, N - k, recs[N - k])
+    m = N - lead
+    while m - (levels - 1) >= 0:
+        for t in range(levels):
+            single.step(sv, cfg, m - t, recs[m - t])
+        multi.step_multi(sv, cfg, m, [recs[m - t] for t in range(levels)])
+        m -= levels
+    torch.cuda.synchronize()
+    assert torch.equal(_valid(sv, single.buf[single.a.cur], 24, torch.float32),
+                       _valid(sv, multi.buf[multi.a.cur], 24, torch.float32)), (levels, lead)
+    if grads:
+        assert torch.equal(_valid(sv, single.gsum, 4, torch.float32), _valid(sv, multi.gsum, 4, torch.float32))
+        for name in ("g_mu", "g_lam", "g_body"):
+            assert torch.equal(getattr(single, name), getattr(multi, name)), (levels, lead, name)
+        assert float(single.g_mu.abs().max()) > 0 and float(single.g_body.abs().max()) > 0
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 40), (121, 13), (500, 9), (5, 3), (3, 3)])
+@pytest.mark.parametrize("levels", [2, 3, 4])
+@pytest.mark.parametrize("storage,law", [("f32", "lognh"), ("f16", "lognh"), ("f32", "gent")])
+def test_adjoint_multi_bitwise_equals_single_steps(storage, law, levels, nx, ny):
+    N = 37
+    case, sv, recs, cells, ubar = _setup(nx, ny, storage, law, N)
+    # level N and lead - 1 more singles first: over the leads the fold at level 32 falls on
+    # every level of a pass
+    for lead in range(1, levels + 1):
+        _compare(sv, case, recs, cells, ubar, N, levels, lead)
+
+
+@pytest.mark.parametrize("levels", [3, 4])
+def test_adjoint_multi_uniform_and_no_gradients(levels):
+    N = 21
+    case, sv, recs, cells, ubar = _setup(200, 30, "f32", "lognh", N, fields=False)
+    _compare(sv, case, recs, cells, ubar, N, levels, 1)
+    _compare(sv, case, recs, cells, ubar, N, levels, 2, grads=False)
+
+
+def test_adjoint_multi_refusals():
+    from paper_2605_26677_amd import _lib as L
+    N = 9
+    case, sv, recs, cells, ubar = _setup(32, 16, "f32", "lognh", N)
+    cfg, st = _adjoint_state(sv, case, N, cells, ubar)
+
+    def call(m, levels, stt=st, svv=sv):
+        r = (ctypes.c_double * 4)(1, 1, 1, 1)
+        rr = (ctypes.c_void_p * 4)(*[recs[0].data_ptr()] * 4)
+        return svv.lib.lbm_adjoint_step_multi(ctypes.byref(svv.p), ctypes.byref(svv.s), ctypes.byref(stt.a), m,
+                                              levels, ctypes.cast(r, ctypes.c_void_p), ctypes.cast(rr, ctypes.c_void_p),
+                                              ctypes.c_void_p(stt.pmask.data_ptr()),
+                                              ctypes.c_void_p(stt.pfield.data_ptr()), None)
+    assert call(N, 3) == L.LBM_ERR_ARG            # level N takes the single step
+    assert call(1, 3) == L.LBM_ERR_ARG            # would reach level -1
+    assert call(5, 1) == L.LBM_ERR_ARG and call(5, 5) == L.LBM_ERR_ARG
+    case64, sv64, recs64, cells64, ubar64 = _setup(32, 16, "f64", "lognh", N)
+    _, st64 = _adjoint_state(sv64, case64, N, cells64, ubar64)
+    assert call(5, 3, st64, sv64) == L.LBM_ERR_UNSUPPORTED
