@@ -293,7 +293,7 @@ def time_launch_bound(n=256, steps=4000, block=100):
     return out
 
 
-def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32"):
+def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32", multi=None):
     """Forward + checkpointed adjoint of the probe-displacement loss with per-node mu, lam
     (log-normal, median 0.1 / 0.2, sigma_log 0.3, correlation length 32), every-K
     checkpoints on the device."""
@@ -311,7 +311,7 @@ def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32"):
     # c from the audit bound sqrt(lam_max + 2 mu_max) / c <= 1/2 with margin
     c = float(np.ceil(2.0 * np.sqrt(float(lam.max()) + 2 * float(mu.max())) * 1.1 * 4) / 4)
     cfg = RolloutConfig(nx=n, ny=n, c=c, omega=2.0, nsteps=steps, probes=probes, storage=storage,
-                        checkpoint_every=K)
+                        checkpoint_every=K, multi=multi)
     # one untimed rollout first, so that the timed one reuses the allocator's blocks
     (rollout(mu, lam, body, v0, cfg) ** 2).sum().backward()
     for t in (mu, lam, body, v0):
@@ -329,8 +329,8 @@ def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32"):
     ok = all(torch.isfinite(t.grad).all().item() for t in (mu, lam, v0))
     # the rollout's forward sweep, replay and adjoint go through the multi-level kernels on
     # this periodic grid in the shifted storages (Solver.multi_levels, replay_multi_levels,
-    # adj_multi_levels), in pairs in FP64
-    multi = FWD_ADJ_MULTI if storage != "f64" else None
+    # adj_multi_levels), in pairs in FP64 or when turned off
+    multi = FWD_ADJ_MULTI if (storage != "f64" and cfg.multi is not False) else None
     bpl = fwd_adj_bytes_per_level(storage, K, multi)
     gbs = bpl * n * n * steps / ((t_f + t_b) * 1e-3) / 1e9
     single = SINGLE_PASS_FWD_ADJ[storage]
@@ -476,7 +476,8 @@ def profile_run(n, steps):
     ms2, faults2, _ = time_forward(n, "f32", steps, 4, v0, mode="pairs")
     ms4, faults4, _ = time_forward(n, "f32", steps, 4, v0, mode="multi")
     adj = time_forward_adjoint(n, 20, 10)
-    print(json.dumps({"profile": True, "copy_bytes_each_way": 2 ** 31, "ms_per_step": ms, "faults": faults,
+    adj_pairs = time_forward_adjoint(n, 20, 10, multi=False)   # the two-level kernels
+    print(json.dumps({"profile": True, "fwd_adj_pairs": adj_pairs, "copy_bytes_each_way": 2 ** 31, "ms_per_step": ms, "faults": faults,
                       "ms_per_level_pairs": ms2, "faults_pairs": faults2, "ms_per_level_multi": ms4,
                       "faults_multi": faults4, "fwd_adj": adj}))
 
@@ -617,6 +618,9 @@ def main():
         log(f"bench: forward + adjoint, {args.adjoint_steps} steps, checkpoint every {args.adjoint_every}")
         res["fwd_adj_f32"] = time_forward_adjoint(n, args.adjoint_steps, args.adjoint_every)
         log(f"bench: fwd+adj: {res['fwd_adj_f32']}")
+        # the same run with the two-level kernels only (the multi-level kernels turned off)
+        res["fwd_adj_f32_pairs"] = time_forward_adjoint(n, args.adjoint_steps, args.adjoint_every, multi=False)
+        log(f"bench: fwd+adj pairs: {res['fwd_adj_f32_pairs']}")
         # FP32 against FP64 on one schedule: FP64 takes half the levels and half the segment
         # length, because 200 levels every 50 do not fit the 288 GB of HBM in FP64 (5
         # snapshots of 16.1 GB, 51 records of 3.2 GB, about 60 GB of working buffers)
@@ -686,7 +690,8 @@ def main():
             "traffic": measured_traffic(n, "step") if main_storage == "f32" else None,
             "algorithmic_bytes_per_launch": BYTES_PER_LU[main_storage] * n * n, "mlups": r1["mlups"]}
     fa = {}
-    for key, label in (("fwd_adj_f32", "f32"), (f"fwd_adj_f32_{args.adjoint_steps // 2}", "f32_same_schedule_as_f64"),
+    for key, label in (("fwd_adj_f32", "f32"), ("fwd_adj_f32_pairs", "f32_two_level_kernels"),
+                       (f"fwd_adj_f32_{args.adjoint_steps // 2}", "f32_same_schedule_as_f64"),
                        (f"fwd_adj_f64_{args.adjoint_steps // 2}", "f64")):
         if key in res:
             v = res[key]

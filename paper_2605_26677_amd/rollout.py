@@ -55,6 +55,10 @@ class RolloutConfig:
                                                        # True wherever they apply, False never
     force_unstable: bool = False                       # skip the lattice-speed audit (short
                                                        # runs outside its long-run region)
+    multi: Optional[bool] = None                       # several levels per call (lbm_step_multi,
+                                                       # lbm_adjoint_step_multi) where they apply
+                                                       # and pay (Solver.multi_levels ...): None
+                                                       # there, False never (pairs instead)
 
     def __post_init__(self):
         check_probes(self.probes, self.nx, self.ny)
@@ -344,7 +348,7 @@ def _plain_steps(sv, cfg, n0, n1, ustar=True):
     result as single steps."""
     n = n0
     pairs = _pairs(sv, cfg)
-    multi = sv.multi_levels if (pairs and ustar) else 0
+    multi = sv.multi_levels if (pairs and ustar and cfg.multi is not False) else 0
     while n < n1:
         if multi and n + multi <= n1:
             sv.step_multi(n, multi, [cfg.ramp(n + 1 + t) for t in range(multi)])
@@ -366,7 +370,7 @@ def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
     recs[0].copy_(snap[1], non_blocking=True)
     n = start
     pairs = _pairs(sv, cfg)
-    rmulti = sv.replay_multi_levels if pairs else 0
+    rmulti = sv.replay_multi_levels if (pairs and cfg.multi is not False) else 0
     while n < end - 1:
         if rmulti and n + rmulti <= end - 1:
             sv.step_multi(n, rmulti, [cfg.ramp(n + 1 + t) for t in range(rmulti)],
@@ -379,7 +383,7 @@ def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
             sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=recs[n + 1 - start], ustar=False)
             n += 1
     m = end - 1
-    multi = sv.adj_multi_levels if cfg.pairs is not False else 0
+    multi = sv.adj_multi_levels if (cfg.pairs is not False and cfg.multi is not False) else 0
     while m >= start:
         if multi and m - (multi - 1) >= start and m < cfg.nsteps:
             adj.step_multi(sv, cfg, m, [recs[m - t - start] for t in range(multi)])
