@@ -216,3 +216,29 @@ def test_multi_full_size_bitwise():
     single, multi = _multi_vs_single(case, "f32", 3, 14, passes=4)
     del single, multi
     torch.cuda.empty_cache()
+
+
+def test_multi_in_captured_graphs():
+    """Solver.advance on a 1024^2 grid takes four-level launches (multi_levels) and, with
+    graph=True, replays captured blocks of them: bitwise equal to eager single steps after
+    every replay, with eager work and host synchronisation between the replays."""
+    n = 1024
+    case = _case(n, n)                               # uniform mu, lam: per-node fields this large
+    eager = make_solver(case, "f32")                 # reach the lattice-speed bound at c = 2.5
+    graph = make_solver(case, "f32")
+    assert graph.multi_levels == 4
+    for sv in (eager, graph):
+        sv.init(case.v0, r0=case.ramp(0))
+        for m in range(16):                          # past the ramp, also loads the kernels
+            sv.step(m, case.ramp(m), case.ramp(m + 1))
+    blk = 32
+    n0 = 16
+    for rep in range(3):
+        for m in range(n0, n0 + blk):
+            eager.step(m, case.ramp(m), case.ramp(m + 1))
+        graph.advance(n0, blk, ramp=case.ramp, block=blk, fused=True, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(eager.populations(), graph.populations()), rep
+        assert torch.equal(eager.displacement(case.ramp(n0 + blk)), graph.displacement(case.ramp(n0 + blk))), rep
+        n0 += blk
+    assert eager.faults() == graph.faults() == 0
