@@ -76,21 +76,19 @@ BYTES_PER_LU_SINGLE_PASS = {"f32": 96 + 96 + 32, "f16": 48 + 48 + 32, "f64": 192
 #   every-K snapshot: populations and record copied (read + written) once per K levels
 # (FP64: populations 192 + 192, u* 16 + 16, records 2 x 48, adjoint F - I 2 x 32, mu lam 8,
 # b 8; gradients added to the FP64 planes directly, 4 x 8 read + written per level)
-# and in the multi-level kernels the rollout takes on periodic FP32 grids:
-#   forward march_kernel, four levels per launch: populations 96 + 96, S 8 + 8, U fold
-#     32 / 4, mu lam 8, b 8 -> 232
-#   replay march_kernel, three levels with the record of each: 96 + 96, records 3 x 24,
-#     mu lam 8, b 8 -> 280
-#   march_adj_kernel, three levels: adjoint populations 96 + 96, F - I of three records
-#     3 x 16, mu lam 8, FP32 block sums 16 + 16, FP64 fold 64 x 3 / 16 -> 280
+# and in the multi-level kernels the rollout takes on periodic FP32 grids, T levels per launch
+# (fwd_adj_multi_bytes):
+#   forward march_kernel: populations 96 + 96, S 8 + 8, U fold 32 T / 16, mu lam 8, b 8
+#     -> 224 + 2 T (232 at T = 4)
+#   replay march_kernel with the record of each level: 96 + 96, records T x 24, mu lam 8, b 8
+#     -> 208 + 24 T (280 at T = 3)
+#   march_adj_kernel: adjoint populations 96 + 96, F - I of T records T x 16, mu lam 8, FP32
+#     block sums 16 + 16, FP64 fold 64 T / 16 -> 232 + 20 T (312 at T = 4)
 FWD_ADJ_BYTES = {
-    "f32": dict(fwd=228, replay=256, adj=272, snapshot=2 * (96 + 24),
-                fwd_multi=232, replay_multi=280, adj_multi=280),
+    "f32": dict(fwd=228, replay=256, adj=272, snapshot=2 * (96 + 24)),
     "f64": dict(fwd=192 + 192 + 32 + 8 + 8, replay=192 + 192 + 96 + 8 + 8,
                 adj=192 + 192 + 64 + 8 + 2 * 64, snapshot=2 * (192 + 48)),
 }
-# levels per launch of the forward, replay and adjoint multi-level kernels of the rollout
-FWD_ADJ_MULTI = (4, 3, 3)
 
 
 # The same run in the single-pass model (every level of every pass through HBM once, per
@@ -101,6 +99,12 @@ SINGLE_PASS_FWD_ADJ = {"f32": (224 + 16) + (192 + 24 + 16) + (192 + 24 + 8 + 64)
                        "f64": (416 + 16) + (384 + 48 + 16) + (384 + 48 + 8 + 64)}
 
 
+def fwd_adj_multi_bytes(kind, levels):
+    """Algorithmic bytes per node and launch of a multi-level kernel of the FP32 rollout:
+    kind "fwd" (forward march), "replay" (recorded replay march) or "adj" (adjoint march)."""
+    return {"fwd": 224 + 2 * levels, "replay": 208 + 24 * levels, "adj": 232 + 20 * levels}[kind]
+
+
 def fwd_adj_bytes_per_level(storage, K, multi=None):
     """Algorithmic bytes per node and level of the every-K forward + adjoint run: the forward
     sweep, the recorded replay and the adjoint in launches of multi = (forward, replay,
@@ -108,7 +112,8 @@ def fwd_adj_bytes_per_level(storage, K, multi=None):
     b = FWD_ADJ_BYTES[storage]
     if multi:
         f, r, a = multi
-        return b["fwd_multi"] / f + b["replay_multi"] / r + b["adj_multi"] / a + b["snapshot"] / K
+        return (fwd_adj_multi_bytes("fwd", f) / f + fwd_adj_multi_bytes("replay", r) / r
+                + fwd_adj_multi_bytes("adj", a) / a + b["snapshot"] / K)
     return (b["fwd"] + b["replay"] + b["adj"]) / 2 + b["snapshot"] / K
 
 
@@ -309,7 +314,7 @@ def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32", multi=None):
     ys, xs = li.random_probes(n, n, nprobe, 405)
     probes = torch.tensor(ys * n + xs, dtype=torch.int64)
     # c from the audit bound sqrt(lam_max + 2 mu_max) / c <= 1/2 with margin
-    c = float(np.ceil(2.0 * np.sqrt(float(lam.max()) + 2 * float(mu.max())) * 1.1 * 4) / 4)
+    c = float(np.ceil(2.0 * np.sqrt(float(lam.detach().max()) + 2 * float(mu.detach().max())) * 1.1 * 4) / 4)
     cfg = RolloutConfig(nx=n, ny=n, c=c, omega=2.0, nsteps=steps, probes=probes, storage=storage,
                         checkpoint_every=K, multi=multi)
     # one untimed rollout first, so that the timed one reuses the allocator's blocks
@@ -330,7 +335,9 @@ def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32", multi=None):
     # the rollout's forward sweep, replay and adjoint go through the multi-level kernels on
     # this periodic grid in the shifted storages (Solver.multi_levels, replay_multi_levels,
     # adj_multi_levels), in pairs in FP64 or when turned off
-    multi = FWD_ADJ_MULTI if (storage != "f64" and cfg.multi is not False) else None
+    from paper_2605_26677_amd.solver import Solver
+    multi = ((Solver.MULTI_LEVELS, Solver.REPLAY_MULTI_LEVELS, Solver.ADJ_MULTI_LEVELS)
+             if (storage != "f64" and cfg.multi is not False) else None)
     bpl = fwd_adj_bytes_per_level(storage, K, multi)
     gbs = bpl * n * n * steps / ((t_f + t_b) * 1e-3) / 1e9
     single = SINGLE_PASS_FWD_ADJ[storage]
@@ -341,9 +348,9 @@ def time_forward_adjoint(n, steps, K, nprobe=16, storage="f32", multi=None):
                          "frac": gbs * 1e9 / PEAK_HBM,
                          "bytes_per_node_level": bpl,
                          "byte_model": (("multi-level kernels, B per node and launch / levels per launch: "
-                                         f"forward march_kernel {FWD_ADJ_BYTES[storage]['fwd_multi']} / {multi[0]}, "
-                                         f"recorded replay march_kernel {FWD_ADJ_BYTES[storage]['replay_multi']} / "
-                                         f"{multi[1]}, march_adj_kernel {FWD_ADJ_BYTES[storage]['adj_multi']} / "
+                                         f"forward march_kernel {fwd_adj_multi_bytes('fwd', multi[0])} / {multi[0]}, "
+                                         f"recorded replay march_kernel {fwd_adj_multi_bytes('replay', multi[1])} / "
+                                         f"{multi[1]}, march_adj_kernel {fwd_adj_multi_bytes('adj', multi[2])} / "
                                          f"{multi[2]}")
                                         if multi else
                                         ("two-level kernels, B per node and launch / 2: forward step2 "

@@ -261,7 +261,7 @@ lbm_status lbm_step2(const lbm_params *p, lbm_state *s, int64_t n, double r_n, d
  *   records: NULL, or a host array of `levels` device pointers that receive U^{n+1} ...
  *     U^{n+levels} (lbm_record_bytes() each) as lbm_step's record would: the replay of the
  *     checkpointed adjoint, which requires s->ustar = NULL (the accumulator is not
- *     updated), F32 or F16 storage and at most 3 levels (LBM_ERR_UNSUPPORTED otherwise).
+ *     updated) and F32 or F16 storage (LBM_ERR_UNSUPPORTED otherwise).
  * Without records s->ustar must be set.  Returns LBM_ERR_ARG when levels is outside
  * [2, 4], r_next or a record pointer is NULL, or s->ustar is NULL without records, and
  * LBM_ERR_UNSUPPORTED on a grid with a wall (lbm_step2 takes those). */

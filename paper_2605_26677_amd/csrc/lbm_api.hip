@@ -432,8 +432,8 @@ lbm_status lbm_step_multi(const lbm_params* p, lbm_state* s, int64_t n, int leve
         return LBM_ERR_ARG;
     }
     if (any_wall(p)) return LBM_ERR_UNSUPPORTED;
-    // the replay form: records, no accumulator, shifted storages, up to three levels
-    if (records && (s->ustar || p->storage == LBM_F64_PLAIN || levels > 3)) return LBM_ERR_UNSUPPORTED;
+    // the replay form: records, no accumulator, shifted storages
+    if (records && (s->ustar || p->storage == LBM_F64_PLAIN)) return LBM_ERR_UNSUPPORTED;
     MarchArgs a{};
     a.cm = make_common(p, s);
     a.cm.body_prev = nullptr;

@@ -24,13 +24,24 @@ struct MarchLds {
     __attribute__((aligned(16))) double U[nbuf][2][kMarchSpan];
 };
 // The replay form (REC: records of every level, no displacement accumulator): the output
-// row of the populations and the rows of the records of the NT levels.
+// row of the populations and the rows of the records of the NT levels.  Where two buffers
+// of records do not fit the 160 KB of LDS beside the two population rows (four FP32 levels:
+// 86 KB of records, 86 KB of populations), they have one, and a second barrier per
+// iteration follows their stores.
 template <int ST, int NT>
 struct MarchLds<ST, NT, true> {
     static constexpr int nbuf = 2;
+    static constexpr int rbuf =
+        2 * 24 * kMarchSpan * sizeof(typename Storage<ST>::pop_t) + 2 * NT * 6 * kMarchSpan * sizeof(float) <=
+                160 * 1024 ? 2 : 1;
     __attribute__((aligned(16))) typename Storage<ST>::pop_t pop[2][24][kMarchSpan];
-    __attribute__((aligned(16))) float rec[2][NT][6][kMarchSpan];
+    __attribute__((aligned(16))) float rec[rbuf][NT][6][kMarchSpan];
 };
+
+template <int ST, int NT, bool REC> constexpr int rec_buffers() {
+    if constexpr (REC) return MarchLds<ST, NT, true>::rbuf;
+    else return 0;
+}
 
 // Geometry.  A workgroup owns a span of kMarchTiles = 7 aligned tiles (448 columns) and a
 // segment of rows; its kMarchWaves = 8 wavefronts each compute a window of 64 columns.
@@ -71,6 +82,8 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
     constexpr uint32_t kPlane = kTile * sizeof(T);     // bytes between planes of a tile
     static_assert(!REC || SH, "records of the shifted storages only");
     constexpr int NB = MarchLds<ST, NT, REC>::nbuf;
+    constexpr int NRB = rec_buffers<ST, NT, REC>();
+    auto record_buffer = [](int i) { return NRB == 1 ? 0 : (i & 1); };
     __shared__ MarchLds<ST, NT, REC> sh;
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
@@ -182,16 +195,17 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
             // words per tile, planes 0 .. 3 in one instruction and 4, 5 on half the lanes
             const int pl = lane >> 4, col = (lane & 15) * 4;
             const int64_t rowr = int64_t(ntile) * 6 * kTile;
+            const int rb = NRB == 1 ? 0 : b;
 #pragma unroll
             for (int L = 1; L <= NT; ++L) {
                 const int i0 = NT + L - 2;                  // first iteration of a segment row
                 const bool rin = outp_iter >= i0 && outp_iter < i0 + Sy && w < kMarchTiles && st < ntile;
                 const __amdgpu_buffer_rsrc_t rr = row_rsrc((float*)a.rec[L - 1] + rw[L] * rowr, rowr * 4);
                 const uint32_t tr = uint32_t(st * 6 * kTile);
-                const u32x4 v0 = *(const u32x4*)&sh.rec[b][L - 1][pl][lc + col];
+                const u32x4 v0 = *(const u32x4*)&sh.rec[rb][L - 1][pl][lc + col];
                 row_store16(rr, rin ? (tr + uint32_t(pl * kTile + col)) * 4u : kNoStore, v0);
                 const int p1 = 4 + (pl & 1);
-                const u32x4 v1 = *(const u32x4*)&sh.rec[b][L - 1][p1][lc + col];
+                const u32x4 v1 = *(const u32x4*)&sh.rec[rb][L - 1][p1][lc + col];
                 row_store16(rr, rin && pl < 2 ? (tr + uint32_t(p1 * kTile + col)) * 4u : kNoStore, v1);
             }
         } else {
@@ -246,12 +260,13 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
     store_row(rw[NT], false, 0, false, -1);
     for (int i = 0; i < iters; ++i) {
         const int b = NB == 1 ? 0 : (i & 1);
+        const int rb = record_buffer(i);
         // REC: the record of level t at this lane's output column into LDS buffer b
         auto stage_record = [&](int t, const R Uv[6]) {
             if constexpr (REC) {
                 if (out_lane) {
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) sh.rec[b][t][k][pos] = Uv[k];
+                    for (int k = 0; k < 6; ++k) sh.rec[rb][t][k][pos] = Uv[k];
                 }
             }
         };
@@ -385,6 +400,8 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
         }
         __syncthreads();
         store_row(rw[NT], outp, b, moved, i);
+        // one buffer of records: every wavefront has read them before the next are staged
+        if constexpr (REC && NRB == 1) __syncthreads();
         // the velocity history moves one row on
 #pragma unroll
         for (int L = 1; L < NT; ++L) {
@@ -410,11 +427,11 @@ template <int ST, int LAW, bool FIELDS>
 static hipError_t march_levels(const MarchArgs& a, hipStream_t s) {
     const dim3 grid(unsigned(a.nwg)), block(kMarchWaves * kTile);
     if (a.rec[0]) {
-        // the replay form: records of every level, no accumulator; up to three levels (four
-        // levels of records would not fit the LDS beside the output row)
+        // the replay form: records of every level, no accumulator
         if constexpr (ST != LBM_F64_PLAIN) {
             if (a.levels == 2) hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 2, true>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 3, true>), grid, block, 0, s, a);
+            else if (a.levels == 3) hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 3, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((march_kernel<ST, LAW, FIELDS, 4, true>), grid, block, 0, s, a);
         }
         return hipGetLastError();
     }

@@ -16,10 +16,12 @@ namespace lbm {
 
 // The LDS of one workgroup: the output row of lambda and of the FP32 gradient block sums,
 // two buffers so that one barrier per iteration separates the writes of a row from its
-// reads.
-struct MarchAdjLds {
+// reads; and, per lane, the running block sums of the rows between their first and last
+// level (a ring of NT rows, each lane reading back only what it wrote).
+template <int NT> struct MarchAdjLds {
     __attribute__((aligned(16))) float lam[2][24][kMarchSpan];
     __attribute__((aligned(16))) float gs[2][4][kMarchSpan];
+    __attribute__((aligned(16))) float4 ring[NT][kMarchWaves][kTile];
 };
 
 // Geometry and memory operations as in march_kernel.  The adjoint pulls from X + c_q: level
@@ -28,17 +30,17 @@ struct MarchAdjLds {
 // adjoint level m - t and reads the record of U^{m-t}.  The FP32 compute type is the
 // storage of lambda, so no level is rounded.
 //
-// Gradients (GRAD): the increments of each level of a node are kept until the node's last
-// level, then added to its block sums in level order, with the folds into the FP64
-// gradients at the levels that fold and the probe body term of each level after its
-// increment, as single steps do.
+// Gradients (GRAD): a row's block sums are loaded with its first level and carried from
+// level to level in the LDS ring; each level adds its increment, folds into the FP64
+// gradients if it folds and then adds its probe body term, in the order of single steps;
+// the last level stores the sums with lambda.
 template <int ST, int LAW, bool FIELDS, int NT, bool GRAD>
 __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdjArgs a) {
     using R = float;
     constexpr int OW = kTile - 2 * (NT - 1);
     static_assert(ST != LBM_F64_PLAIN, "the FP32 compute type only");
     static_assert(kMarchTiles * OW + OW >= kMarchSpan, "the windows must cover the span");
-    __shared__ MarchAdjLds sh;
+    __shared__ MarchAdjLds<NT> sh;
     const Common& cm = a.cm;
     const int nx = cm.nx, ny = cm.ny, ntile = cm.ntile;
     const int64_t n = int64_t(nx) * ny;
@@ -74,15 +76,16 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
 #pragma unroll
     for (int j = 0; j <= NT; ++j) rw[j] = wrap_index(Y0 - (NT - 1) + 1 - j, ny);
 
-    // Loaded one iteration ahead: lambda^{m+1} pulled for the next row to enter level m, the
-    // records and probe-mask words of the rows of every level, mu and lam of the new row, and
-    // the block sums of the next output row.
+    // Loaded one iteration ahead, each right after the level that consumed the values before
+    // (so that the two share registers): lambda^{m+1} pulled for the next row to enter level
+    // m, mu and lam of that row and its block sums after level 0; the record and the
+    // probe-table word of level t's next row after level t.
     float pre[24];
     float prec[NT][4];
-    uint64_t pmw[NT];
+    uint32_t pmw[NT];
     float pprm[2] = {0.0f, 0.0f};
     float pgs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    auto prefetch = [&](int yp, int yc, int ym, int yo) {
+    auto prefetch_row = [&](int yp, int yc, int ym) {
         const R* rc = src + yc * rowe;
         const R* rp = src + yp * rowe;
         const R* rm = src + ym * rowe;
@@ -96,26 +99,23 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
             pre[6 + k] = rp[oc + (6 + k) * kTile];
             pre[18 + k] = rm[oc + (18 + k) * kTile];
         }
-        // level t's row in the next iteration: yc - t (rows behind the new one)
-        int yt = yc;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const R* rec = (const R*)a.rec[t] + yt * rowr + orc;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) prec[t][k] = rec[(2 + k) * kTile];
-            pmw[t] = a.pmask ? a.pmask[int64_t(yt) * ntile + (xc >> 6)] : 0ull;
-            yt = yt == 0 ? ny - 1 : yt - 1;
-        }
         if constexpr (FIELDS) {
             const int idx = yc * nx + xc;
             if (cm.mu) pprm[0] = cm.mu[idx];
             if (cm.lam) pprm[1] = cm.lam[idx];
         }
         if constexpr (GRAD) {
-            const float* gp = gsum + yo * rowg + og;
+            const float* gp = gsum + yc * rowg + og;
 #pragma unroll
             for (int j = 0; j < 4; ++j) pgs[j] = gp[j * kTile];
         }
+    };
+    auto prefetch_level = [&](int t, int yt) {
+        const R* rec = (const R*)a.rec[t] + yt * rowr + orc;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) prec[t][k] = rec[(2 + k) * kTile];
+        // the 32-bit half of the probe-table word that holds bit x mod 64
+        pmw[t] = a.pmask ? ((const uint32_t*)a.pmask)[2 * (int64_t(yt) * ntile + (xc >> 6)) + ((xc >> 5) & 1)] : 0u;
     };
     // the stores of output row yo from LDS buffer b (byte offsets kNoStore where nothing is
     // stored; see march_kernel): tile st of lambda and of the block sums, whole, in 16-byte
@@ -146,25 +146,21 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
     // lambda of levels t = 0 .. NT-2 of the rows behind: q3 of the last two rows, q0 and q2 of
     // the last row shifted to the lanes that pull them
     R hq3a[NT - 1][6], hq3b[NT - 1][6], ho0[NT - 1][6], ho2[NT - 1][6];
-    // gradient increments of level t (< NT-1) of the last NT-1-t rows, newest first
-    R gh[NT][NT][4];
 #pragma unroll
     for (int t = 0; t < NT - 1; ++t)
 #pragma unroll
         for (int k = 0; k < 6; ++k) hq3a[t][k] = hq3b[t][k] = ho0[t][k] = ho2[t][k] = R(0);
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int j = 0; j < NT; ++j)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) gh[t][j][c] = R(0);
+    // the lane that owns its column for the direct FP64 updates: on a grid narrower than the
+    // span, columns beyond nx wrap onto nodes other lanes own
+    const bool own_col = out_lane && c0 + pos < nx;
 
     const int iters = Sy + 2 * (NT - 1);
-    prefetch(rw[0], rw[1], rw[2], rw[NT]);
+    prefetch_row(rw[0], rw[1], rw[2]);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) prefetch_level(t, rw[t + 1]);
     store_row(rw[NT], false, 0);
     for (int i = 0; i < iters; ++i) {
         R f[4][6];
-        R cinc[NT][4] = {};
         R l[4][6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
@@ -172,14 +168,6 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
             l[1][k] = pre[6 + k];
             l[2][k] = pre[12 + k];
             l[3][k] = pre[18 + k];
-        }
-        float rec[NT][4];
-        uint64_t mw[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) rec[t][k] = prec[t][k];
-            mw[t] = pmw[t];
         }
         if constexpr (FIELDS) {
 #pragma unroll
@@ -190,19 +178,20 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
             prm[0][0] = pprm[0];
             prm[0][1] = pprm[1];
         }
-        float gsp[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) gsp[j] = pgs[j];
-        prefetch(wrap_inc(rw[0], ny), rw[0], rw[1], rw[NT - 1]);
 
-        auto level = [&](int t, int y, R out[4][6], double ps[2], bool& probe) {
+        // ring slot of the row of level t: the iteration in which its first level ran, mod NT
+        const int slot0 = i % NT;
+        float gn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        auto level = [&](int t, int y, R out[4][6]) {
             R mu, lam;
             if (FIELDS && cm.mu) mu = prm[t][0]; else mu = kval<R>(cm.mu0, cm.f_mu0);
             if (FIELDS && cm.lam) lam = prm[t][1]; else lam = kval<R>(cm.lam0, cm.f_lam0);
-            adj_node<R, LAW>(cm, l, rec[t], mu, lam, R(a.r[t]), gpar, gbody, out, cinc[t]);
-            probe = (mw[t] >> (xc & 63)) & 1ull;
+            R inc[4];
+            adj_node<R, LAW>(cm, l, prec[t], mu, lam, R(a.r[t]), gpar, gbody, out, inc);
+            const bool probe = (pmw[t] >> (xc & 31)) & 1u;
+            const int64_t idx = int64_t(y) * nx + xc;
+            double ps[2] = {0.0, 0.0};
             if (probe) {
-                const int64_t idx = int64_t(y) * nx + xc;
                 ps[0] = a.probe_weight * a.pfield[idx];
                 ps[1] = a.probe_weight * a.pfield[n + idx];
 #pragma unroll
@@ -211,13 +200,41 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
                     out[q][1] += R(ps[1]);
                 }
             }
+            if constexpr (GRAD) {
+                const int slot = slot0 - t < 0 ? slot0 - t + NT : slot0 - t;
+                if (t == 0) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) gn[j] = pgs[j];
+                } else {
+                    const float4 v = sh.ring[slot][w][lane];
+                    gn[0] = v.x; gn[1] = v.y; gn[2] = v.z; gn[3] = v.w;
+                }
+                // the row of level t is an output row of the segment
+                const bool own = own_col && i >= NT - 1 + t && i < Sy + NT - 1 + t;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (!has[j]) continue;
+                    gn[j] = gn[j] + float(inc[j]);
+                    if (a.fold[t]) {
+                        if (own) g64[j][idx] += double(gn[j]);
+                        gn[j] = 0.0f;
+                    }
+                }
+                if (own && probe && gbody) {
+                    a.g_body[idx] += a.r[t] * hdt * ps[0];
+                    a.g_body[n + idx] += a.r[t] * hdt * ps[1];
+                }
+                if (t < NT - 1) sh.ring[slot][w][lane] = make_float4(gn[0], gn[1], gn[2], gn[3]);
+            }
         };
-        double ps[2] = {0.0, 0.0};
-        bool probe = false;
-        level(0, rw[1], f, ps, probe);
+        level(0, rw[1], f);
+        // every load is issued on every iteration, whether its level runs or not, so that the
+        // memory operations in flight are the same on all paths through the loop
+        prefetch_row(wrap_inc(rw[0], ny), rw[0], rw[1]);
+        prefetch_level(0, rw[0]);
 #pragma unroll
         for (int L = 2; L <= NT; ++L) {
-            if (i < 2 * (L - 2)) break;             // level L-1 of the pass has not started
+            const bool started = i >= 2 * (L - 2);  // level L-2 of the pass has run
             const bool act = i >= 2 * (L - 1);
             if (act) {
 #pragma unroll
@@ -228,45 +245,21 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
                     l[3][k] = hq3b[L - 2][k];
                 }
             }
+            if (started) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                hq3b[L - 2][k] = hq3a[L - 2][k];
-                hq3a[L - 2][k] = f[3][k];
-                ho0[L - 2][k] = from_next(f[0][k]);
-                ho2[L - 2][k] = from_prev(f[2][k]);
+                for (int k = 0; k < 6; ++k) {
+                    hq3b[L - 2][k] = hq3a[L - 2][k];
+                    hq3a[L - 2][k] = f[3][k];
+                    ho0[L - 2][k] = from_next(f[0][k]);
+                    ho2[L - 2][k] = from_prev(f[2][k]);
+                }
             }
-            if (!act) break;
-            level(L - 1, rw[L], f, ps, probe);
+            if (act) level(L - 1, rw[L], f);
+            prefetch_level(L - 1, rw[L - 1]);
         }
-        // f: lambda of the pass's last level at output row y1 - (NT - 1) from iteration
-        // 2 (NT - 1) on; ps and probe: that node's probe source
+        // f, gn: lambda and the block sums of the pass's last level at output row
+        // y1 - (NT - 1) from iteration 2 (NT - 1) on
         const bool outp = i >= 2 * (NT - 1);
-        float gn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if constexpr (GRAD) {
-            const int64_t gi = int64_t(rw[NT]) * nx + xc;
-            // the lane that owns the node for the direct FP64 updates: on a grid narrower
-            // than the span, columns beyond nx wrap onto nodes other lanes own
-            const bool own = outp && out_lane && c0 + pos < nx;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) gn[j] = gsp[j];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const R* inc = t == NT - 1 ? cinc[NT - 1] : gh[t][NT - t - 2];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (!has[j]) continue;
-                    gn[j] = gn[j] + float(inc[j]);
-                    if (a.fold[t]) {
-                        if (own) g64[j][gi] += double(gn[j]);
-                        gn[j] = 0.0f;
-                    }
-                }
-                if (own && probe && gbody) {
-                    a.g_body[gi] += a.r[t] * hdt * ps[0];
-                    a.g_body[n + gi] += a.r[t] * hdt * ps[1];
-                }
-            }
-        }
         const int b = i & 1;
         if (outp && out_lane) {
 #pragma unroll
@@ -280,18 +273,6 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
         }
         __syncthreads();
         store_row(rw[NT], outp, b);
-        // the increment history moves one row on
-        if constexpr (GRAD) {
-#pragma unroll
-            for (int t = 0; t < NT - 1; ++t) {
-#pragma unroll
-                for (int j = NT - t - 2; j >= 1; --j)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) gh[t][j][c] = gh[t][j - 1][c];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) gh[t][0][c] = cinc[t][c];
-            }
-        }
 #pragma unroll
         for (int j = NT; j >= 1; --j) rw[j] = rw[j - 1];
         rw[0] = wrap_inc(rw[0], ny);

@@ -119,12 +119,14 @@ class Solver:
     # against 46.1k, 2048^2 79.4k against 49.7k: a small grid leaves compute units idle)
     MULTI_LEVELS = 4
     MULTI_MIN_NODES = 1024 * 1024
-    # adjoint levels per lbm_adjoint_step_multi call (8192^2 FP32, per-node mu lam, gradients:
-    # pairs through lbm_adjoint_step2 1.78 ms per level, three levels 1.41, four 1.86: its
-    # registers then overflow)
-    ADJ_MULTI_LEVELS = 3
-    # levels per lbm_step_multi call in the replay form (records of every level): at most 3
-    REPLAY_MULTI_LEVELS = 3
+    # adjoint levels per lbm_adjoint_step_multi call (8192^2 FP32 log-NH, per-node mu lam,
+    # gradients: pairs through lbm_adjoint_step2 1.78 ms per level, three levels 1.31, four
+    # 1.14); three for the invariant-based laws, whose four-level kernel runs out of registers
+    ADJ_MULTI_LEVELS = 4
+    ADJ_MULTI_LEVELS_INVARIANT = 3
+    # levels per lbm_step_multi call in the replay form (records of every level; 8192^2 FP32,
+    # per-node mu lam: pairs 1.61 ms per level, three levels 1.24, four 1.03)
+    REPLAY_MULTI_LEVELS = 4
 
     def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
                  bc=("periodic",) * 4, mu=0.1, lam=0.2, body=None, newton_max_iter=0,
@@ -314,7 +316,11 @@ class Solver:
         """Adjoint levels per lbm_adjoint_step_multi call where that is the fastest way: as
         multi_levels (periodic grids of at least MULTI_MIN_NODES nodes, FP32 or FP16), else 0."""
         ok = self.periodic and self.storage != "f64" and self.nx * self.ny >= self.MULTI_MIN_NODES
-        return self.ADJ_MULTI_LEVELS if ok else 0
+        if not ok:
+            return 0
+        if self.material in ("mr", "yeoh", "gent"):
+            return self.ADJ_MULTI_LEVELS_INVARIANT
+        return self.ADJ_MULTI_LEVELS
 
     @property
     def periodic(self):

@@ -119,7 +119,7 @@ def _record_nodes(sv, rec):
 
 @pytest.mark.parametrize("fields", [False, True])
 @pytest.mark.parametrize("nx,ny", [(64, 64), (121, 13), (500, 9), (5, 3), (3, 3)])
-@pytest.mark.parametrize("levels", [2, 3])
+@pytest.mark.parametrize("levels", [2, 3, 4])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_multi_replay_bitwise_equals_single_steps(storage, levels, nx, ny, fields):
     _replay_vs_single(_case(nx, ny, fields=fields), storage, levels, 1, passes=12 // levels)
@@ -132,10 +132,22 @@ def test_multi_bitwise_wide_grids(nx, ny, levels):
     _multi_vs_single(_case(nx, ny, fields=True), "f32", levels, 1, passes=3)
 
 
+@pytest.mark.parametrize("nx,ny", [(2500, 23), (4160, 70)])
+def test_multi_replay_bitwise_wide_grids(nx, ny):
+    """The replay form at four levels (one LDS buffer of records) on many windows per row and
+    more than one segment of rows."""
+    _replay_vs_single(_case(nx, ny, fields=True), "f32", 4, 1, passes=3)
+
+
 @pytest.mark.parametrize("law", [l for l in ALL_LAWS if l != "lognh"])
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 def test_multi_bitwise_every_law(storage, law):
     _multi_vs_single(_case(97, 20, law=law, fields=True), storage, 3, 1, passes=4)
+
+
+@pytest.mark.parametrize("law", [l for l in ALL_LAWS if l != "lognh"])
+def test_multi_replay_bitwise_every_law(law):
+    _replay_vs_single(_case(97, 20, law=law, fields=True), "f32", 4, 1, passes=3)
 
 
 def test_multi_fault_words_agree():
@@ -184,18 +196,20 @@ def test_multi_refuses_bad_arguments():
         assert st == L.LBM_ERR_ARG
     st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 3, None, None, None)
     assert st == L.LBM_ERR_ARG
-    # the replay form: records need no accumulator, at most three levels, no FP64
+    # the replay form: records need no accumulator, no FP64
     recs = [sv.new_record() for _ in range(4)]
     rp = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in recs])
     st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 3, ctypes.cast(r, ctypes.c_void_p),
                                ctypes.cast(rp, ctypes.c_void_p), None)
     assert st == L.LBM_ERR_UNSUPPORTED                  # s->ustar is set
-    keep = sv.s.ustar
-    sv.s.ustar = None
-    st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 4, ctypes.cast(r, ctypes.c_void_p),
-                               ctypes.cast(rp, ctypes.c_void_p), None)
-    assert st == L.LBM_ERR_UNSUPPORTED                  # four levels of records
-    sv.s.ustar = keep
+    s64 = make_solver(case, "f64")
+    s64.init(case.v0)
+    keep = s64.s.ustar
+    s64.s.ustar = None
+    st = s64.lib.lbm_step_multi(ctypes.byref(s64.p), ctypes.byref(s64.s), 0, 3, ctypes.cast(r, ctypes.c_void_p),
+                                ctypes.cast(rp, ctypes.c_void_p), None)
+    assert st == L.LBM_ERR_UNSUPPORTED                  # records of FP64 states
+    s64.s.ustar = keep
     walled = Case("multi_walled", 32, 16, 10.0, 1.95, 0, kinds=("velocity", "traction", "periodic", "periodic"),
                   mu=0.1, lam=0.2, v0=np.zeros((2, 16, 32)))
     sw = make_solver(walled, "f32")
