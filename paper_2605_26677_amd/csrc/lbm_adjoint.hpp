@@ -20,8 +20,17 @@ namespace lbm {
 template <typename R, int LAW>
 __device__ __forceinline__ void adj_node(const Common& cm, const R l[4][6], const R ft[4], R mu, R lam, R rm,
                                          bool grad_par, bool grad_body, R out[4][6], R inc[4]) {
+    // log-NH and NH: one evaluation of the kinematics gives the tangent and, below,
+    // dP/dmu = F - H and dP/dlam = ln J H (log-NH) or (J^2 - 1)/2 H (NH)
+    constexpr bool lame = LAW == LBM_LOGNH || LAW == LBM_NH;
     R C[16];
-    tangent<R, LAW, true>(ft, mu, lam, law_consts<R>(cm), C);
+    Kin<R> kk;
+    if constexpr (lame) {
+        kk = kinematics<R, true>(ft);
+        tangent_lame<R, LAW>(kk, mu, lam, C);
+    } else {
+        tangent<R, LAW, true>(ft, mu, lam, law_consts<R>(cm), C);
+    }
     R s6[6], dxl[6], dyl[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -49,7 +58,16 @@ __device__ __forceinline__ void adj_node(const Common& cm, const R l[4][6], cons
     inc[0] = inc[1] = inc[2] = inc[3] = R(0);
     if (grad_par) {
         R Pm[4], Pl[4];
-        piola_partials<R, LAW, true>(ft, law_consts<R>(cm), Pm, Pl);
+        if constexpr (lame) {
+            const R v = LAW == LBM_LOGNH ? kk.L : R(0.5) * kk.Jsq_m1;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                Pm[a] = kk.FmH[a];
+                Pl[a] = v * kk.H[a];
+            }
+        } else {
+            piola_partials<R, LAW, true>(ft, law_consts<R>(cm), Pm, Pl);
+        }
         inc[0] = om * hc * -(dxl[0] * Pm[0] + dxl[1] * Pm[2] + dyl[0] * Pm[1] + dyl[1] * Pm[3]);
         inc[1] = om * hc * -(dxl[0] * Pl[0] + dxl[1] * Pl[2] + dyl[0] * Pl[1] + dyl[1] * Pl[3]);
     }

@@ -368,6 +368,32 @@ __device__ __forceinline__ void piola_partials(const R f[4], const LawK<R>& lk, 
 // The invariant-based laws are differentiated in forward mode (Dual4 seeded with the four
 // entries of F), which is exact up to rounding like the closed forms.
 
+// The tangent of log-NH and NH from the kinematics of the state.
+template <typename R, int LAW>
+__device__ __forceinline__ void tangent_lame(const Kin<R>& kk, R mu, R lam, R C[16]) {
+    R a, b;
+    if constexpr (LAW == LBM_LOGNH) {
+        a = mu - lam * kk.L;
+        b = lam;
+    } else {
+        a = mu - R(0.5) * lam * kk.Jsq_m1;
+        b = lam * kk.J * kk.J;
+    }
+    const R* H = kk.H;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int A = 0; A < 2; ++A)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int B = 0; B < 2; ++B) {
+                    R v = a * H[2 * i + B] * H[2 * k + A] + b * H[2 * i + A] * H[2 * k + B];
+                    if (i == k && A == B) v += mu;
+                    C[8 * i + 4 * A + 2 * k + B] = v;
+                }
+}
+
 template <typename R, int LAW, bool SHIFTED>
 __device__ __forceinline__ void tangent(const R f[4], R mu, R lam, const LawK<R>& lk, R C[16]) {
     if constexpr (invariant_law<LAW>()) {
@@ -412,28 +438,7 @@ __device__ __forceinline__ void tangent(const R f[4], R mu, R lam, const LawK<R>
                         C[8 * i + 4 * A + 2 * k + B] = v;
                     }
     } else {
-        const Kin<R> kk = kinematics<R, SHIFTED>(f);
-        R a, b;
-        if constexpr (LAW == LBM_LOGNH) {
-            a = mu - lam * kk.L;
-            b = lam;
-        } else {
-            a = mu - R(0.5) * lam * kk.Jsq_m1;
-            b = lam * kk.J * kk.J;
-        }
-        const R* H = kk.H;
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int A = 0; A < 2; ++A)
-#pragma unroll
-                for (int k = 0; k < 2; ++k)
-#pragma unroll
-                    for (int B = 0; B < 2; ++B) {
-                        R v = a * H[2 * i + B] * H[2 * k + A] + b * H[2 * i + A] * H[2 * k + B];
-                        if (i == k && A == B) v += mu;
-                        C[8 * i + 4 * A + 2 * k + B] = v;
-                    }
+        tangent_lame<R, LAW>(kinematics<R, SHIFTED>(f), mu, lam, C);
     }
 }
 

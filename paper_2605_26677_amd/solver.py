@@ -98,6 +98,14 @@ class StepGraph:
         self.sv.s.cur = self.end_cur
 
 
+def _as_device(a, device):
+    """A contiguous FP64 copy (or view) of a field on the device; a read-only numpy array is
+    copied on the host first (torch does not wrap read-only memory)."""
+    if isinstance(a, np.ndarray) and not a.flags.writeable:
+        a = a.copy()
+    return torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()
+
+
 class Solver:
     """One grid's device state and the library calls on it (torch's current stream).
 
@@ -217,8 +225,8 @@ class Solver:
     # ------------------------------------------------------------ entry points
     def init(self, v0, u0=None, r0=0.0, Fbar=None):
         """lbm_init; Fbar (2, 2) is an optional uniform predeformation (F = Fbar + grad u0)."""
-        self._v0 = torch.as_tensor(v0, dtype=torch.float64, device=self.device).contiguous()
-        self._u0 = None if u0 is None else torch.as_tensor(u0, dtype=torch.float64, device=self.device).contiguous()
+        self._v0 = _as_device(v0, self.device)
+        self._u0 = None if u0 is None else _as_device(u0, self.device)
         self.s.cur = 0
         self.fault.zero_()
         self.ustar.zero_()
