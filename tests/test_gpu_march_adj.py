@@ -131,9 +131,9 @@ def test_adjoint_multi_refusals():
     assert call(5, 3, st64, sv64) == L.LBM_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("law", ["lognh", "mr"])
-def test_rollout_multi_equals_pairs(law):
-    """The differentiable rollout on a 1024^2 periodic FP32 grid, where the multi-level
+@pytest.mark.parametrize("law,storage", [("lognh", "f32"), ("mr", "f32"), ("lognh", "f16")])
+def test_rollout_multi_equals_pairs(law, storage):
+    """The differentiable rollout on a 1024^2 periodic FP32 or FP16 grid, where the multi-level
     kernels take the forward sweep and the recorded replay (four levels per call) and the
     adjoint (four for the closed-form laws, three for the invariant-based ones), gives
     bit for bit the probe values and the gradients of the same rollout in two-level kernels
@@ -148,7 +148,7 @@ def test_rollout_multi_equals_pairs(law):
     v00 = np.stack([li.gaussian_random_field(n, n, 413, 1e-3), li.gaussian_random_field(n, n, 414, 1e-3)])
     ys, xs = li.random_probes(n, n, 16, 415)
     common = dict(nx=n, ny=n, c=2.75, omega=2.0, nsteps=N, probes=torch.tensor(ys * n + xs, dtype=torch.int64),
-                  storage="f32", material=law, checkpoint_every=18, ramp=lambda m: min(1.0, m / 10))
+                  storage=storage, material=law, checkpoint_every=18, ramp=lambda m: min(1.0, m / 10))
 
     def run(multi):
         leaves = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True)
@@ -158,7 +158,7 @@ def test_rollout_multi_equals_pairs(law):
         torch.cuda.synchronize()
         return u.detach().cpu(), [t.grad.cpu() for t in leaves]
 
-    sv = Solver(n, n, c=2.75, omega=2.0, material=law, storage="f32", mu=0.1, lam=0.2)
+    sv = Solver(n, n, c=2.75, omega=2.0, material=law, storage=storage, mu=0.1, lam=0.2)
     assert sv.multi_levels == 4 and sv.replay_multi_levels == 4
     assert sv.adj_multi_levels == (3 if law == "mr" else 4)
     del sv
