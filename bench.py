@@ -468,6 +468,98 @@ def adjoint_at_scale(n, steps, budget_gib, fd_dirs, c=10.0, host_gibs=(0.0,)):
                 fd_max_err_over_term_sum=float(max(scaled)) if scaled else None)
 
 
+def time_levels(n=8192, steps=48, N=24):
+    """ms per level against the levels each call takes, on the n x n periodic FP32 workload
+    (log-NH; `steps` timed levels after 12 untimed ones, rounded up to whole calls):
+    - forward, uniform mu, lam: lbm_step, lbm_step2, lbm_step_multi of 3 and 4 levels;
+    - recorded replay, per-node mu, lam (the fields of the forward + adjoint run), the
+      record of every level, no u*: lbm_step2 and lbm_step_multi of 3 and 4 levels;
+    - adjoint with the gradients of mu, lam and b, per-node mu, lam, 16 probes: levels
+      N .. 1 by lbm_adjoint_step, _step2 and _step_multi of 3 and 4 levels (best of 3)."""
+    import torch
+    import lbm_inputs as li
+    from paper_2605_26677_amd.rollout import RolloutConfig, _Adjoint
+    from paper_2605_26677_amd.solver import Solver
+    v0 = make_inputs(n)
+    out = {"grid": [n, n], "storage": "f32"}
+
+    def timed(call, per, count):
+        count = -(-count // per) * per
+        for k in range(0, 12, per):
+            call(k, per)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(12, 12 + count, per):
+            call(k, per)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / count
+
+    sv = Solver(n, n, c=2.0, omega=2.0, material="lognh", storage="f32", mu=0.1, lam=0.2)
+    sv.init(v0)
+    fwd = {"single": timed(lambda k, p: sv.step(k), 1, steps),
+           "pairs": timed(lambda k, p: sv.step2(k), 2, steps)}
+    for L in (3, 4):
+        fwd[f"multi{L}"] = timed(lambda k, p: sv.step_multi(k, p), L, steps)
+    fwd["faults"] = sv.faults()
+    out["forward_ms_per_level"] = fwd
+    del sv
+    torch.cuda.empty_cache()
+
+    mu = torch.tensor(li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0), dtype=torch.float64, device="cuda")
+    lam = torch.tensor(li.lognormal_field(n, n, 402, 0.2, 0.3, 32.0), dtype=torch.float64, device="cuda")
+    body = torch.zeros((2, n, n), dtype=torch.float64, device="cuda")
+    c = float(np.ceil(2.0 * np.sqrt(float(lam.max()) + 2 * float(mu.max())) * 1.1 * 4) / 4)
+    sv = Solver(n, n, c=c, omega=2.0, material="lognh", storage="f32", mu=mu, lam=lam, body=body)
+    sv.init(v0)
+    recs = [sv.new_record() for _ in range(4)]
+    rep = {"pairs": timed(lambda k, p: sv.step2(k, record1=recs[0], record2=recs[1], ustar=False), 2, steps)}
+    for L in (3, 4):
+        rep[f"multi{L}"] = timed(lambda k, p: sv.step_multi(k, p, [1.0] * p, records=recs[:p], ustar=False), L,
+                                 steps)
+    rep["faults"] = sv.faults()
+    out["replay_ms_per_level"] = rep
+    del recs
+
+    # the adjoint: records of levels 0 .. N from a fresh forward run
+    sv.init(v0)
+    recs = [sv.record_state(1.0, sv.new_record())]
+    for k in range(N):
+        r = sv.new_record()
+        sv.step(k, record=r)
+        recs.append(r)
+    ys, xs = li.random_probes(n, n, 16, 405)
+    cfg = RolloutConfig(nx=n, ny=n, c=c, omega=2.0, nsteps=N + 1, probes=torch.tensor(ys * n + xs),
+                        storage="f32")
+    adj = _Adjoint(sv, cfg, torch.ones((2, 16), dtype=torch.float64))
+    res = {}
+    for mode, per in (("single", 1), ("pairs", 2), ("multi3", 3), ("multi4", 4)):
+        best = None
+        for _ in range(3):
+            m = N
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            while m - (per - 1) >= 1:
+                if per == 1:
+                    adj.step(sv, cfg, m, recs[m])
+                elif per == 2:
+                    adj.step2(sv, cfg, m, recs[m], recs[m - 1])
+                else:
+                    adj.step_multi(sv, cfg, m, [recs[m - t] for t in range(per)])
+                m -= per
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / (N - m)
+            best = ms if best is None else min(best, ms)
+        res[mode] = best
+    out["adjoint_ms_per_level"] = res
+    del adj, recs, sv
+    torch.cuda.empty_cache()
+    return out
+
+
 def profile_run(n, steps):
     """Short run for rocprofv3: a plain device copy of known size (counter calibration)
     followed by FP32 steps of the benchmark workload."""
@@ -561,6 +653,8 @@ def main():
                     help="comma list of pinned host memory sizes (GiB) for the outermost checkpoints, "
                          "one timed run each (0: device only)")
     ap.add_argument("--no-scale", action="store_true", help="skip the 4096^2 adjoint workload")
+    ap.add_argument("--levels", action="store_true",
+                    help="ms per level of forward, recorded replay and adjoint against the levels per call")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
@@ -578,6 +672,9 @@ def main():
         r = adjoint_at_scale(args.scale_size, args.scale_steps, args.scale_budget_gib, args.scale_fd_dirs,
                              host_gibs=[float(x) for x in args.scale_host_gib.split(",")])
         print(json.dumps({"adjoint_at_scale": r}), flush=True)
+        return
+    if args.levels:
+        print(json.dumps({"levels": time_levels(n)}), flush=True)
         return
     log(f"bench: generating {n}x{n} inputs")
     v0 = make_inputs(n)

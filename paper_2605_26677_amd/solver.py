@@ -121,12 +121,16 @@ class Solver:
     # 16.2 against 15.6 single; 512^2: 20.4 against 22.9).
     GRAPH_MAX_NODES = 400 * 400
     PAIR_MIN_WALLED_NODES = 416 * 416
-    # levels per lbm_step_multi call (8192^2 FP32: 2 levels 50.2k, 3 levels 70.3k, 4 levels
-    # 78.3k MLUPS, pairs through lbm_step2 51.1k), and the grid size from which it beats
-    # pairs (FP32 MLUPS, four levels against pairs: 512^2 21.4k against 32.6k, 1024^2 57.0k
-    # against 46.1k, 2048^2 79.4k against 49.7k: a small grid leaves compute units idle)
+    # levels per lbm_step_multi call, and the grid size from which it beats pairs (bench.py
+    # --levels, FP32, ms per level, four levels against pairs: 512^2 0.0128 against 0.0082,
+    # 1024^2 0.0203 against 0.0230, 8192^2 0.735 against 1.295: a small grid leaves compute
+    # units idle)
     MULTI_LEVELS = 4
     MULTI_MIN_NODES = 1024 * 1024
+    # the same for the recorded replay and the adjoint, which only pay from a larger grid
+    # (four levels against pairs, replay: 1024^2 0.0280 against 0.0270, 2048^2 0.0716
+    # against 0.1119; adjoint: 1024^2 0.0302 against 0.0309, 2048^2 0.0771 against 0.1194)
+    BACKWARD_MULTI_MIN_NODES = 2048 * 2048
     # adjoint levels per lbm_adjoint_step_multi call (8192^2 FP32 log-NH, per-node mu lam,
     # gradients: pairs through lbm_adjoint_step2 1.78 ms per level, three levels 1.31, four
     # 1.14); three for the invariant-based laws, whose four-level kernel runs out of registers
@@ -314,16 +318,17 @@ class Solver:
     @property
     def replay_multi_levels(self):
         """Levels per lbm_step_multi call in the replay form (records, no accumulator) where
-        that is faster than pairs, as multi_levels; 0 elsewhere."""
+        that is faster than pairs: periodic grids of at least BACKWARD_MULTI_MIN_NODES nodes
+        in the shifted storages; 0 elsewhere."""
         ok = (self.periodic and self.pairs_ok and self.storage != "f64"
-              and self.nx * self.ny >= self.MULTI_MIN_NODES)
+              and self.nx * self.ny >= self.BACKWARD_MULTI_MIN_NODES)
         return self.REPLAY_MULTI_LEVELS if ok else 0
 
     @property
     def adj_multi_levels(self):
-        """Adjoint levels per lbm_adjoint_step_multi call where that is the fastest way: as
-        multi_levels (periodic grids of at least MULTI_MIN_NODES nodes, FP32 or FP16), else 0."""
-        ok = self.periodic and self.storage != "f64" and self.nx * self.ny >= self.MULTI_MIN_NODES
+        """Adjoint levels per lbm_adjoint_step_multi call where that is the fastest way:
+        periodic grids of at least BACKWARD_MULTI_MIN_NODES nodes, FP32 or FP16; else 0."""
+        ok = self.periodic and self.storage != "f64" and self.nx * self.ny >= self.BACKWARD_MULTI_MIN_NODES
         if not ok:
             return 0
         if self.material in ("mr", "yeoh", "gent"):

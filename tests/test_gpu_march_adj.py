@@ -133,7 +133,7 @@ def test_adjoint_multi_refusals():
 
 @pytest.mark.parametrize("law,storage", [("lognh", "f32"), ("mr", "f32"), ("lognh", "f16")])
 def test_rollout_multi_equals_pairs(law, storage):
-    """The differentiable rollout on a 1024^2 periodic FP32 or FP16 grid, where the multi-level
+    """The differentiable rollout on a 2048^2 periodic FP32 or FP16 grid, where the multi-level
     kernels take the forward sweep and the recorded replay (four levels per call) and the
     adjoint (four for the closed-form laws, three for the invariant-based ones), gives
     bit for bit the probe values and the gradients of the same rollout in two-level kernels
@@ -141,7 +141,7 @@ def test_rollout_multi_equals_pairs(law, storage):
     calls do not divide, and the folds of levels 32, 16 and 0 fall inside multi calls."""
     from paper_2605_26677_amd.rollout import RolloutConfig, rollout
     from paper_2605_26677_amd.solver import Solver
-    n, N = 1024, 37
+    n, N = 2048, 37
     mu0 = li.lognormal_field(n, n, 411, 0.1, 0.3, 32.0)
     lam0 = li.lognormal_field(n, n, 412, 0.2, 0.3, 32.0)
     body0 = li.uniform_body(n, n, (1e-5, -2e-5))
