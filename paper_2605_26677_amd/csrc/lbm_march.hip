@@ -256,6 +256,19 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
     bool nonfinite = false, jbad = false;
 
     const int iters = Sy + 2 * (NT - 1);
+    // A window wholly past the grid's last column (in a row's last span) outputs only
+    // padding columns, and the tile of its wavefront lies past the last column as well
+    // (a window starts no later than its tile), so nothing it computes would be stored: the
+    // wavefront only takes part in the workgroup's barriers.  The padding columns of the
+    // stored tiles then hold unspecified values, which no kernel or entry point reads.
+    if (c0 + ws >= nx) {
+        for (int i = 0; i < iters; ++i) {
+            if (NB == 1) __syncthreads();
+            __syncthreads();
+            if constexpr (REC && NRB == 1) __syncthreads();
+        }
+        return;
+    }
     prefetch(rw[0], rw[1], rw[2], rw[NT]);
     store_row(rw[NT], false, 0, false, -1);
     for (int i = 0; i < iters; ++i) {

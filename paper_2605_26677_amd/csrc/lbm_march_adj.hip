@@ -155,6 +155,11 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
     const bool own_col = out_lane && c0 + pos < nx;
 
     const int iters = Sy + 2 * (NT - 1);
+    // a window wholly past the grid's last column: barriers only (see march_kernel)
+    if (c0 + ws >= nx) {
+        for (int i = 0; i < iters; ++i) __syncthreads();
+        return;
+    }
     prefetch_row(rw[0], rw[1], rw[2]);
 #pragma unroll
     for (int t = 0; t < NT; ++t) prefetch_level(t, rw[t + 1]);
