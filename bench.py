@@ -122,7 +122,9 @@ PROFILE_PMC = {"step": os.path.join(ROOT, "profiles", "step_f32_lognh_periodic_8
                "march": os.path.join(ROOT, "profiles", "march4_f32_lognh_periodic_8192_pmc.txt")}
 STEP_SOURCES = ("lbm_forward.hip", "lbm_pair.hip", "lbm_collide.hpp", "lbm_device.hpp", "lbm_kernel_util.hpp",
                 "lbm_internal.hpp")
-MARCH_SOURCES = ("lbm_march.hip", "lbm_collide.hpp", "lbm_device.hpp", "lbm_kernel_util.hpp", "lbm_internal.hpp")
+# the march kernel's sources and lbm_api.hip, which sets its launch geometry (segment length)
+MARCH_SOURCES = ("lbm_march.hip", "lbm_march.hpp", "lbm_collide.hpp", "lbm_device.hpp", "lbm_kernel_util.hpp",
+                 "lbm_internal.hpp", "lbm_api.hip")
 
 
 def step_source_hash(files=STEP_SOURCES):
