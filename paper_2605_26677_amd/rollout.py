@@ -323,11 +323,19 @@ def _restore(sv, snap):
     sv.pop[sv.s.cur].copy_(snap[0], non_blocking=True)
 
 
-def _step_to_snapshot(sv, cfg, n, ustar=True):
-    """Step n -> n + 1 and keep (f*^{n+1}, U^{n+1}); the record comes from the step kernel
-    itself, exactly as a replay would produce it, so every schedule sees the same records."""
+def _steps_to_snapshot(sv, cfg, n0, n, ustar=True):
+    """Steps n0 .. n - 1 as _plain_steps, then step n -> n + 1, and keep (f*^{n+1}, U^{n+1});
+    the record comes from the step kernel itself, exactly as a replay would produce it, so
+    every schedule sees the same records.  Where the rollout fuses levels and a plain step
+    precedes, that step and step n run as one pair that records its second level (bit for
+    bit the two single steps)."""
     rec = sv.new_record()
-    sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=rec, ustar=ustar)
+    if n > n0 and _pairs(sv, cfg):
+        _plain_steps(sv, cfg, n0, n - 1, ustar=ustar)
+        _pair(sv, cfg, n - 1, record2=rec, ustar=ustar)
+    else:
+        _plain_steps(sv, cfg, n0, n, ustar=ustar)
+        sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=rec, ustar=ustar)
     return (sv.pop[sv.s.cur].clone(), rec)
 
 
@@ -344,15 +352,19 @@ def _pair(sv, cfg, n, record1=None, record2=None, ustar=True):
 def _plain_steps(sv, cfg, n0, n1, ustar=True):
     """Steps n0 .. n1 - 1 without records: where the rollout fuses levels (_pairs), in
     groups through lbm_step_multi where that applies (Solver.multi_levels; it updates u*,
-    so not where u* is skipped) and else in pairs through lbm_step2; bit for bit the same
-    result as single steps."""
+    so not where u* is skipped; a shorter group where fewer levels remain, and never a
+    single level left over where two groups can share the rest) and else in pairs through
+    lbm_step2; bit for bit the same result as single steps."""
     n = n0
     pairs = _pairs(sv, cfg)
     multi = sv.multi_levels if (pairs and ustar and cfg.multi is not False) else 0
     while n < n1:
-        if multi and n + multi <= n1:
-            sv.step_multi(n, multi, [cfg.ramp(n + 1 + t) for t in range(multi)])
-            n += multi
+        if multi and n + 1 < n1:
+            L = min(multi, n1 - n)
+            if n1 - n - L == 1 and L > 2:
+                L -= 1
+            sv.step_multi(n, L, [cfg.ramp(n + 1 + t) for t in range(L)])
+            n += L
         elif pairs and n + 1 < n1:
             _pair(sv, cfg, n, ustar=ustar)
             n += 2
@@ -407,8 +419,7 @@ def _reverse_nested(sv, cfg, adj, start, end, snap, lengths, recs):
     snaps = [snap]
     _restore(sv, snap)
     for i in range(len(bounds) - 2):
-        _plain_steps(sv, cfg, bounds[i], bounds[i + 1] - 1, ustar=False)
-        snaps.append(_step_to_snapshot(sv, cfg, bounds[i + 1] - 1, ustar=False))
+        snaps.append(_steps_to_snapshot(sv, cfg, bounds[i], bounds[i + 1] - 1, ustar=False))
     for i in range(len(bounds) - 2, -1, -1):
         _reverse_nested(sv, cfg, adj, bounds[i], bounds[i + 1], snaps[i], lengths[1:], recs)
         snaps.pop()
@@ -444,12 +455,13 @@ class LBMRollout(torch.autograd.Function):
             # plain steps up to the next snapshot step (the one that reaches a multiple of K;
             # binomial checkpointing keeps only level 0 here)
             end = min(N, (n // K + 1) * K - 1) if keep and not cfg.revolve else N
-            _plain_steps(sv, cfg, n, end)
-            n = end
-            if n < N:
-                snap = _step_to_snapshot(sv, cfg, n)
-                snaps[n + 1] = tuple(_host_copy(t) for t in snap) if cfg.host_top else snap
-                n += 1
+            if end < N:
+                snap = _steps_to_snapshot(sv, cfg, n, end)
+                snaps[end + 1] = tuple(_host_copy(t) for t in snap) if cfg.host_top else snap
+                n = end + 1
+            else:
+                _plain_steps(sv, cfg, n, end)
+                n = end
         u = sv.displacement(cfg.ramp(N))
         probes = cfg.probes.to(device=mu.device, dtype=torch.long)
         out = u.reshape(2, -1)[:, probes]
@@ -470,8 +482,7 @@ class LBMRollout(torch.autograd.Function):
                 if act[0] == "take":
                     a, m = act[1], act[2]
                     _restore(sv, snaps[a])
-                    _plain_steps(sv, cfg, a, m - 1, ustar=False)
-                    snaps[m] = _step_to_snapshot(sv, cfg, m - 1, ustar=False)
+                    snaps[m] = _steps_to_snapshot(sv, cfg, a, m - 1, ustar=False)
                 elif act[0] == "free":
                     del snaps[act[1]]
                 else:
