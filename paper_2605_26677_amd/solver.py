@@ -122,14 +122,14 @@ class Solver:
     GRAPH_MAX_NODES = 400 * 400
     PAIR_MIN_WALLED_NODES = 416 * 416
     # levels per lbm_step_multi call, and the grid size from which it beats pairs (bench.py
-    # --levels, FP32, ms per level, four levels against pairs: 512^2 0.0128 against 0.0082,
-    # 1024^2 0.0203 against 0.0230, 8192^2 0.735 against 1.295: a small grid leaves compute
+    # --levels, FP32, ms per level, four levels against pairs: 512^2 0.0125 against 0.0083,
+    # 1024^2 0.0212 against 0.0228, 8192^2 0.705 against 1.301: a small grid leaves compute
     # units idle)
     MULTI_LEVELS = 4
     MULTI_MIN_NODES = 1024 * 1024
-    # the same for the recorded replay and the adjoint, which only pay from a larger grid
-    # (four levels against pairs, replay: 1024^2 0.0280 against 0.0270, 2048^2 0.0716
-    # against 0.1119; adjoint: 1024^2 0.0302 against 0.0309, 2048^2 0.0771 against 0.1194)
+    # the same for the recorded replay and the adjoint, which pay clearly only from a larger
+    # grid (four levels against pairs, replay: 1024^2 0.0262 against 0.0269, 2048^2 0.0701
+    # against 0.1121; adjoint: 1024^2 0.0298 against 0.0311, 2048^2 0.0770 against 0.1193)
     BACKWARD_MULTI_MIN_NODES = 2048 * 2048
     # adjoint levels per lbm_adjoint_step_multi call (8192^2 FP32 log-NH, per-node mu lam,
     # gradients: pairs through lbm_adjoint_step2 1.78 ms per level, three levels 1.31, four
