@@ -80,8 +80,8 @@ BYTES_PER_LU_SINGLE_PASS = {"f32": 96 + 96 + 32, "f16": 48 + 48 + 32, "f64": 192
 # (fwd_adj_multi_bytes):
 #   forward march_kernel: populations 96 + 96, S 8 + 8, U fold 32 T / 16, mu lam 8, b 8
 #     -> 224 + 2 T (232 at T = 4)
-#   replay march_kernel with the record of each level: 96 + 96, records T x 24, mu lam 8, b 8
-#     -> 208 + 24 T (280 at T = 3)
+#   replay march_kernel with the F - I planes of the record of each level (the rollout's
+#     record_planes = 4): 96 + 96, records T x 16, mu lam 8, b 8 -> 208 + 16 T (272 at T = 4)
 #   march_adj_kernel: adjoint populations 96 + 96, F - I of T records T x 16, mu lam 8, FP32
 #     block sums 16 + 16, FP64 fold 64 T / 16 -> 232 + 20 T (312 at T = 4)
 FWD_ADJ_BYTES = {
@@ -102,7 +102,7 @@ SINGLE_PASS_FWD_ADJ = {"f32": (224 + 16) + (192 + 24 + 16) + (192 + 24 + 8 + 64)
 def fwd_adj_multi_bytes(kind, levels):
     """Algorithmic bytes per node and launch of a multi-level kernel of the FP32 rollout:
     kind "fwd" (forward march), "replay" (recorded replay march) or "adj" (adjoint march)."""
-    return {"fwd": 224 + 2 * levels, "replay": 208 + 24 * levels, "adj": 232 + 20 * levels}[kind]
+    return {"fwd": 224 + 2 * levels, "replay": 208 + 16 * levels, "adj": 232 + 20 * levels}[kind]
 
 
 def fwd_adj_bytes_per_level(storage, K, multi=None):
@@ -475,7 +475,8 @@ def time_levels(n=8192, steps=48, N=24):
     (log-NH; `steps` timed levels after 12 untimed ones, rounded up to whole calls):
     - forward, uniform mu, lam: lbm_step, lbm_step2, lbm_step_multi of 3 and 4 levels;
     - recorded replay, per-node mu, lam (the fields of the forward + adjoint run), the
-      record of every level, no u*: lbm_step2 and lbm_step_multi of 3 and 4 levels;
+      record of every level, no u*: lbm_step2 (whole records) and lbm_step_multi of 3 and 4
+      levels (the F - I planes of the records, as the rollout asks);
     - adjoint with the gradients of mu, lam and b, per-node mu, lam, 16 probes: levels
       N .. 1 by lbm_adjoint_step, _step2 and _step_multi of 3 and 4 levels (best of 3)."""
     import torch
@@ -518,8 +519,8 @@ def time_levels(n=8192, steps=48, N=24):
     recs = [sv.new_record() for _ in range(4)]
     rep = {"pairs": timed(lambda k, p: sv.step2(k, record1=recs[0], record2=recs[1], ustar=False), 2, steps)}
     for L in (3, 4):
-        rep[f"multi{L}"] = timed(lambda k, p: sv.step_multi(k, p, [1.0] * p, records=recs[:p], ustar=False), L,
-                                 steps)
+        rep[f"multi{L}"] = timed(lambda k, p: sv.step_multi(k, p, [1.0] * p, records=recs[:p], ustar=False,
+                                                            record_planes=4), L, steps)
     rep["faults"] = sv.faults()
     out["replay_ms_per_level"] = rep
     del recs

@@ -262,11 +262,16 @@ lbm_status lbm_step2(const lbm_params *p, lbm_state *s, int64_t n, double r_n, d
  *     U^{n+levels} (lbm_record_bytes() each) as lbm_step's record would: the replay of the
  *     checkpointed adjoint, which requires s->ustar = NULL (the accumulator is not
  *     updated) and F32 or F16 storage (LBM_ERR_UNSUPPORTED otherwise).
+ *   record_planes: with records, 6 writes whole records; 4 writes only the F - I planes
+ *     (2 .. 5), all that the adjoint entry points read, and leaves the velocity planes of
+ *     the records as they were (a third fewer record bytes).  Ignored without records.
  * Without records s->ustar must be set.  Returns LBM_ERR_ARG when levels is outside
- * [2, 4], r_next or a record pointer is NULL, or s->ustar is NULL without records, and
+ * [2, 4], r_next or a record pointer is NULL, record_planes is neither 6 nor 4 with
+ * records, or s->ustar is NULL without records, and
  * LBM_ERR_UNSUPPORTED on a grid with a wall (lbm_step2 takes those). */
 lbm_status lbm_step_multi(const lbm_params *p, lbm_state *s, int64_t n, int levels,
-                          const double *r_next, void *const *records, void *stream);
+                          const double *r_next, void *const *records, int record_planes,
+                          void *stream);
 
 /* Displacement at the current level n (eq:trapezoid-u): u^n = u*^{n+1} - (dt/2) v^n with
  * v^n recovered from the stored post-collision populations (sum_q f* = U + (dt/2) B).

@@ -78,7 +78,7 @@ SIGNATURES = {
     "lbm_step": (c_i32, [P(lbm_params), P(lbm_state), c_i64, c_dbl, c_dbl, P(lbm_edge_data), c_vp, c_vp]),
     "lbm_step2": (c_i32, [P(lbm_params), P(lbm_state), c_i64, c_dbl, c_dbl, c_dbl, P(lbm_edge_data),
                           P(lbm_edge_data), c_vp, c_vp, c_vp]),
-    "lbm_step_multi": (c_i32, [P(lbm_params), P(lbm_state), c_i64, c_i32, c_vp, c_vp, c_vp]),
+    "lbm_step_multi": (c_i32, [P(lbm_params), P(lbm_state), c_i64, c_i32, c_vp, c_vp, c_i32, c_vp]),
     "lbm_probe_mask_bytes": (ctypes.c_size_t, [P(lbm_params)]),
     "lbm_adjoint_probe_table": (c_i32, [P(lbm_params), P(lbm_adj_state), c_vp, c_vp, c_vp]),
     "lbm_adjoint_step_multi": (c_i32, [P(lbm_params), P(lbm_state), P(lbm_adj_state), c_i64, c_i32, c_vp, c_vp,

@@ -421,7 +421,7 @@ static bool march_geometry(const lbm_params* p, int levels, int& nspan, int& seg
 }
 
 lbm_status lbm_step_multi(const lbm_params* p, lbm_state* s, int64_t n, int levels, const double* r_next,
-                          void* const* records, void* stream) {
+                          void* const* records, int record_planes, void* stream) {
     lbm_status st = lbm_check_params(p);
     if (st != LBM_OK) return st;
     if ((st = check_state(p, s, false)) != LBM_OK) return st;
@@ -429,6 +429,7 @@ lbm_status lbm_step_multi(const lbm_params* p, lbm_state* s, int64_t n, int leve
     if (records) {
         for (int t = 0; t < levels; ++t)
             if (!records[t]) return LBM_ERR_ARG;
+        if (record_planes != 6 && record_planes != 4) return LBM_ERR_ARG;
     } else if (!s->ustar) {
         return LBM_ERR_ARG;
     }
@@ -442,6 +443,7 @@ lbm_status lbm_step_multi(const lbm_params* p, lbm_state* s, int64_t n, int leve
     a.dst = s->pop[1 - s->cur];
     a.ustar = s->ustar;
     a.levels = levels;
+    a.rec_planes = records ? record_planes : 6;
     for (int t = 0; t < levels; ++t) {
         a.fold[t] = (n + 1 + t) % kUstarBlock == 0;
         a.rec[t] = records ? records[t] : nullptr;

@@ -225,6 +225,7 @@ struct MarchArgs {
     double r[kMarchMaxLevels];       // body factor r(n+1+t)
     float fb[kMarchMaxLevels][2];    // uniform body r(n+1+t) b0 rounded to float
     void* rec[kMarchMaxLevels];      // records of U^{n+1+t} (the replay form), or NULL
+    int rec_planes;                  // 6: whole records; 4: the F - I planes 2 .. 5 only
     int nspan, seg, nwg;             // spans per row, rows per segment, workgroups
     FastDiv d_nspan;
 };

@@ -193,6 +193,7 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
         if constexpr (REC) {
             // the record rows of the levels whose rows lie in the segment: 6 planes of 64
             // words per tile, planes 0 .. 3 in one instruction and 4, 5 on half the lanes
+            // (with rec_planes = 4 the velocity planes 0, 1 are left out)
             const int pl = lane >> 4, col = (lane & 15) * 4;
             const int64_t rowr = int64_t(ntile) * 6 * kTile;
             const int rb = NRB == 1 ? 0 : b;
@@ -203,7 +204,8 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
                 const __amdgpu_buffer_rsrc_t rr = row_rsrc((float*)a.rec[L - 1] + rw[L] * rowr, rowr * 4);
                 const uint32_t tr = uint32_t(st * 6 * kTile);
                 const u32x4 v0 = *(const u32x4*)&sh.rec[rb][L - 1][pl][lc + col];
-                row_store16(rr, rin ? (tr + uint32_t(pl * kTile + col)) * 4u : kNoStore, v0);
+                row_store16(rr, rin && (pl >= 2 || a.rec_planes == 6) ? (tr + uint32_t(pl * kTile + col)) * 4u
+                                                                     : kNoStore, v0);
                 const int p1 = 4 + (pl & 1);
                 const u32x4 v1 = *(const u32x4*)&sh.rec[rb][L - 1][p1][lc + col];
                 row_store16(rr, rin && pl < 2 ? (tr + uint32_t(p1 * kTile + col)) * 4u : kNoStore, v1);

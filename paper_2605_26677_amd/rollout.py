@@ -376,7 +376,8 @@ def _plain_steps(sv, cfg, n0, n1, ustar=True):
 def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
     """Adjoint levels end-1 .. start, starting from the snapshot of level `start`.  The
     replay skips the displacement quadrature (the adjoint does not read u*) and records
-    U of every level, several levels per call (Solver.replay_multi_levels, else pairs);
+    U of every level, several levels per call (Solver.replay_multi_levels, else pairs;
+    the multi-level calls write only the F - I planes, which is all the adjoint reads);
     the adjoint takes several levels per call (Solver.adj_multi_levels, else pairs)."""
     _restore(sv, snap)
     recs[0].copy_(snap[1], non_blocking=True)
@@ -386,7 +387,8 @@ def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
     while n < end - 1:
         if rmulti and n + rmulti <= end - 1:
             sv.step_multi(n, rmulti, [cfg.ramp(n + 1 + t) for t in range(rmulti)],
-                          records=[recs[n + 1 + t - start] for t in range(rmulti)], ustar=False)
+                          records=[recs[n + 1 + t - start] for t in range(rmulti)], ustar=False,
+                          record_planes=4)
             n += rmulti
         elif pairs and n + 1 < end - 1:
             _pair(sv, cfg, n, record1=recs[n + 1 - start], record2=recs[n + 2 - start], ustar=False)

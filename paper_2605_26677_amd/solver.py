@@ -280,11 +280,12 @@ class Solver:
         finally:
             self.s.ustar = keep
 
-    def step_multi(self, n, levels, r_next=None, records=None, ustar=True):
+    def step_multi(self, n, levels, r_next=None, records=None, ustar=True, record_planes=6):
         """lbm_step_multi: levels n -> n + levels in one pass on a periodic grid, bit for bit
         the same as `levels` calls of step; r_next[t] is the body factor of level n + 1 + t.
         With records (one record tensor per level) the replay form: records of every level
-        and no accumulator update (then ustar must be False)."""
+        and no accumulator update (then ustar must be False); record_planes = 4 writes only
+        their F - I planes (what the adjoint reads)."""
         r = [1.0] * levels if r_next is None else [float(x) for x in r_next]
         if len(r) != levels:
             raise ValueError("r_next needs one factor per level")
@@ -301,7 +302,7 @@ class Solver:
             L.check(self.lib.lbm_step_multi(ctypes.byref(self.p), ctypes.byref(self.s), int(n), int(levels),
                                             ctypes.cast(arr, ctypes.c_void_p),
                                             ctypes.cast(recs, ctypes.c_void_p) if recs is not None else None,
-                                            _stream()), "lbm_step_multi")
+                                            int(record_planes), _stream()), "lbm_step_multi")
         finally:
             self.s.ustar = keep
 

@@ -29,11 +29,12 @@ def test_byte_counts():
     assert bench.bytes_per_lu_multi("f32", 2) == 212.0
     # the forward + adjoint byte model: forward, replay and adjoint in multi-level launches
     assert [bench.fwd_adj_multi_bytes("fwd", t) for t in (2, 3, 4)] == [228, 230, 232]
-    assert [bench.fwd_adj_multi_bytes("replay", t) for t in (2, 3)] == [256, 280]
+    # the replay's records: the F - I planes only (16 B per node and level)
+    assert [bench.fwd_adj_multi_bytes("replay", t) for t in (2, 3, 4)] == [240, 256, 272]
     # the adjoint: populations 192, F - I 16 per level, mu lam 8, block sums 32, FP64 fold
     # 64 B once in 16 levels
     assert [bench.fwd_adj_multi_bytes("adj", t) for t in (2, 3, 4)] == [272, 292, 312]
-    assert bench.fwd_adj_bytes_per_level("f32", 50, (4, 3, 4)) == 232 / 4 + 280 / 3 + 312 / 4 + 240 / 50
+    assert bench.fwd_adj_bytes_per_level("f32", 50, (4, 4, 4)) == 232 / 4 + 272 / 4 + 312 / 4 + 240 / 50
     assert bench.fwd_adj_bytes_per_level("f64", 25) == (432 + 496 + 584) / 2 + 480 / 25
 
 

@@ -85,9 +85,10 @@ def test_multi_bitwise_equals_single_steps(storage, levels, nx, ny, fields):
         _multi_vs_single(case, storage, levels, start, passes=12 // levels)
 
 
-def _replay_vs_single(case, storage, levels, start, passes):
+def _replay_vs_single(case, storage, levels, start, passes, planes=6):
     """The replay form: single steps with a record each and no accumulator against
-    lbm_step_multi with the records of every level."""
+    lbm_step_multi with the records of every level; with planes = 4 only the F - I planes
+    of the records are written, and the velocity planes keep what they held."""
     single = make_solver(case, storage)
     multi = make_solver(case, storage)
     for sv in (single, multi):
@@ -97,14 +98,20 @@ def _replay_vs_single(case, storage, levels, start, passes):
     n = start
     for _ in range(passes):
         ra = [single.new_record() for _ in range(levels)]
-        rb = [multi.new_record() for _ in range(levels)]
+        rb = [multi.new_record().fill_(1234.5) for _ in range(levels)]
         for t in range(levels):
             single.step(n + t, case.ramp(n + t), case.ramp(n + t + 1), record=ra[t], ustar=False)
-        multi.step_multi(n, levels, [case.ramp(n + 1 + t) for t in range(levels)], records=rb, ustar=False)
+        multi.step_multi(n, levels, [case.ramp(n + 1 + t) for t in range(levels)], records=rb, ustar=False,
+                         record_planes=planes)
         n += levels
         torch.cuda.synchronize()
         for a, b in zip(ra, rb):
-            assert torch.equal(_record_nodes(single, a), _record_nodes(multi, b))
+            ua, ub = _record_nodes(single, a), _record_nodes(multi, b)
+            if planes == 6:
+                assert torch.equal(ua, ub)
+            else:
+                assert torch.equal(ua[2:], ub[2:])
+                assert bool((ub[:2] == 1234.5).all())
     assert torch.equal(single.populations(), multi.populations())
     assert single.faults() == multi.faults() == 0
 
@@ -130,6 +137,15 @@ def test_multi_replay_bitwise_equals_single_steps(storage, levels, nx, ny, field
 def test_multi_bitwise_wide_grids(nx, ny, levels):
     """Many windows per row, and with 70 rows more than one segment of rows."""
     _multi_vs_single(_case(nx, ny, fields=True), "f32", levels, 1, passes=3)
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 64), (121, 13), (3, 3)])
+@pytest.mark.parametrize("levels", [2, 3, 4])
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_multi_replay_strain_planes(storage, levels, nx, ny):
+    """record_planes = 4: the F - I planes bit for bit those of single steps, the velocity
+    planes untouched."""
+    _replay_vs_single(_case(nx, ny, fields=True), storage, levels, 1, passes=12 // levels, planes=4)
 
 
 @pytest.mark.parametrize("nx,ny", [(2500, 23), (4160, 70)])
@@ -192,22 +208,26 @@ def test_multi_refuses_bad_arguments():
     r = (ctypes.c_double * 5)(1, 1, 1, 1, 1)
     for levels in (0, 1, 5):
         st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, levels,
-                                   ctypes.cast(r, ctypes.c_void_p), None, None)
+                                   ctypes.cast(r, ctypes.c_void_p), None, 6, None)
         assert st == L.LBM_ERR_ARG
-    st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 3, None, None, None)
+    st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 3, None, None, 6, None)
     assert st == L.LBM_ERR_ARG
     # the replay form: records need no accumulator, no FP64
     recs = [sv.new_record() for _ in range(4)]
     rp = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in recs])
     st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 3, ctypes.cast(r, ctypes.c_void_p),
-                               ctypes.cast(rp, ctypes.c_void_p), None)
+                               ctypes.cast(rp, ctypes.c_void_p), 6, None)
     assert st == L.LBM_ERR_UNSUPPORTED                  # s->ustar is set
+    for planes in (0, 5, 7):
+        st = sv.lib.lbm_step_multi(ctypes.byref(sv.p), ctypes.byref(sv.s), 0, 3, ctypes.cast(r, ctypes.c_void_p),
+                                   ctypes.cast(rp, ctypes.c_void_p), planes, None)
+        assert st == L.LBM_ERR_ARG                      # records of 6 or 4 planes only
     s64 = make_solver(case, "f64")
     s64.init(case.v0)
     keep = s64.s.ustar
     s64.s.ustar = None
     st = s64.lib.lbm_step_multi(ctypes.byref(s64.p), ctypes.byref(s64.s), 0, 3, ctypes.cast(r, ctypes.c_void_p),
-                                ctypes.cast(rp, ctypes.c_void_p), None)
+                                ctypes.cast(rp, ctypes.c_void_p), 6, None)
     assert st == L.LBM_ERR_UNSUPPORTED                  # records of FP64 states
     s64.s.ustar = keep
     walled = Case("multi_walled", 32, 16, 10.0, 1.95, 0, kinds=("velocity", "traction", "periodic", "periodic"),
@@ -215,7 +235,7 @@ def test_multi_refuses_bad_arguments():
     sw = make_solver(walled, "f32")
     sw.init(walled.v0)
     st = sw.lib.lbm_step_multi(ctypes.byref(sw.p), ctypes.byref(sw.s), 0, 3, ctypes.cast(r, ctypes.c_void_p), None,
-                               None)
+                               6, None)
     assert st == L.LBM_ERR_UNSUPPORTED
 
 
