@@ -20,17 +20,9 @@ namespace lbm {
 template <typename R, int LAW>
 __device__ __forceinline__ void adj_node(const Common& cm, const R l[4][6], const R ft[4], R mu, R lam, R rm,
                                          bool grad_par, bool grad_body, R out[4][6], R inc[4]) {
-    // log-NH and NH: one evaluation of the kinematics gives the tangent and, below,
+    // log-NH and NH: one evaluation of the kinematics gives the tangent's action and, below,
     // dP/dmu = F - H and dP/dlam = ln J H (log-NH) or (J^2 - 1)/2 H (NH)
     constexpr bool lame = LAW == LBM_LOGNH || LAW == LBM_NH;
-    R C[16];
-    Kin<R> kk;
-    if constexpr (lame) {
-        kk = kinematics<R, true>(ft);
-        tangent_lame<R, LAW>(kk, mu, lam, C);
-    } else {
-        tangent<R, LAW, true>(ft, mu, lam, law_consts<R>(cm), C);
-    }
     R s6[6], dxl[6], dyl[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -38,12 +30,46 @@ __device__ __forceinline__ void adj_node(const Common& cm, const R l[4][6], cons
         dxl[k] = l[0][k] - l[2][k];
         dyl[k] = l[1][k] - l[3][k];
     }
+    // AT_kB = -sum_iA W_iA C_iAkB with W = [[dxl0, dyl0], [dxl1, dyl1]] (the flux rows that
+    // carry P_i1 and P_i2)
     R AT[6];
     AT[0] = -dxl[2] - dyl[3];
     AT[1] = -dxl[4] - dyl[5];
+    Kin<R> kk;
+    if constexpr (lame) {
+        // with C_iAkB = mu d_ik d_AB + a H_iB H_kA + b H_iA H_kB (tangent_lame) the action
+        // needs no C: AT_kB = -(mu W_kB + a (H M^T)_kB + b tr(M) H_kB), M = H^T W
+        kk = kinematics<R, true>(ft);
+        R a, b;
+        if constexpr (LAW == LBM_LOGNH) {
+            a = mu - lam * kk.L;
+            b = lam;
+        } else {
+            a = mu - R(0.5) * lam * kk.Jsq_m1;
+            b = lam * kk.J * kk.J;
+        }
+        const R* H = kk.H;
+        const R W[2][2] = {{dxl[0], dyl[0]}, {dxl[1], dyl[1]}};
+        R M[2][2];
 #pragma unroll
-    for (int kB = 0; kB < 4; ++kB)
-        AT[2 + kB] = -(dxl[0] * C[kB] + dxl[1] * C[8 + kB]) - (dyl[0] * C[4 + kB] + dyl[1] * C[12 + kB]);
+        for (int B = 0; B < 2; ++B)
+#pragma unroll
+            for (int A = 0; A < 2; ++A) M[B][A] = H[B] * W[0][A] + H[2 + B] * W[1][A];
+        const R tr = M[0][0] + M[1][1];
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int B = 0; B < 2; ++B) {
+                const R hm = H[2 * k] * M[B][0] + H[2 * k + 1] * M[B][1];
+                AT[2 + 2 * k + B] = -(mu * W[k][B] + a * hm + b * tr * H[2 * k + B]);
+            }
+    } else {
+        R C[16];
+        tangent<R, LAW, true>(ft, mu, lam, law_consts<R>(cm), C);
+#pragma unroll
+        for (int kB = 0; kB < 4; ++kB)
+            AT[2 + kB] = -(dxl[0] * C[kB] + dxl[1] * C[8 + kB]) - (dyl[0] * C[4 + kB] + dyl[1] * C[12 + kB]);
+    }
     const R om = kval<R>(cm.omega, cm.f_omega);
     const R c2 = kval<R>(cm.k_c2, cm.f_c2);
     R gU[6];
