@@ -252,6 +252,21 @@ def test_multi_full_size_bitwise():
     torch.cuda.empty_cache()
 
 
+def test_multi_replay_full_size_four_planes():
+    """The replay of the 8192^2 forward + adjoint benchmark (per-node mu, lam log-normal with
+    correlation length 32, a uniform body force under a ramp): four-level passes writing
+    the F - I planes of every record against single steps with records, bit for bit."""
+    n = 8192
+    mu = li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0)
+    lam = li.lognormal_field(n, n, 402, 0.2, 0.3, 32.0)
+    c = float(np.ceil(2.0 * np.sqrt(float(lam.max()) + 2 * float(mu.max())) * 1.1 * 4) / 4)
+    v0 = np.stack([li.gaussian_random_field(n, n, 301, 5e-3), li.gaussian_random_field(n, n, 302, 5e-3)])
+    case = Case("replay_8192", n, n, c, 2.0, 0, mu=mu, lam=lam, body=li.uniform_body(n, n, (1e-5, -2e-5)),
+                ramp_steps=7, v0=v0)
+    _replay_vs_single(case, "f32", 4, 1, passes=2, planes=4)
+    torch.cuda.empty_cache()
+
+
 def test_multi_in_captured_graphs():
     """Solver.advance on a 1024^2 grid takes four-level launches (multi_levels) and, with
     graph=True, replays captured blocks of them: bitwise equal to eager single steps after

@@ -169,3 +169,34 @@ def test_rollout_multi_equals_pairs(law, storage):
     for a, b in zip(g_m, g_p):
         assert torch.isfinite(a).all() and a.abs().max() > 0
         assert torch.equal(a, b)
+
+
+def test_adjoint_multi_full_size_bitwise():
+    """The 8192^2 workload of the forward + adjoint benchmark (per-node mu, lam log-normal
+    with correlation length 32, a small uniform body force under a ramp, 16 random probes
+    and probes where windows and spans meet): adjoint levels 16 .. 1 in four-level passes
+    against single adjoint steps, bit for bit, with the fold of level 16 on a pass's first
+    level."""
+    n, N = 8192, 17
+    mu = li.lognormal_field(n, n, 401, 0.1, 0.3, 32.0)
+    lam = li.lognormal_field(n, n, 402, 0.2, 0.3, 32.0)
+    c = float(np.ceil(2.0 * np.sqrt(float(lam.max()) + 2 * float(mu.max())) * 1.1 * 4) / 4)
+    v0 = np.stack([li.gaussian_random_field(n, n, 301, 5e-3), li.gaussian_random_field(n, n, 302, 5e-3)])
+    case = Case("madj_8192", n, n, c, 2.0, N, mu=mu, lam=lam, body=li.uniform_body(n, n, (1e-5, -2e-5)),
+                ramp_steps=6, v0=v0)
+    sv = make_solver(case, "f32")
+    sv.init(v0, r0=case.ramp(0))
+    recs = [sv.record_state(case.ramp(0), sv.new_record())]
+    for k in range(N):
+        r = sv.new_record()
+        sv.step(k, case.ramp(k), case.ramp(k + 1), record=r)
+        recs.append(r)
+    ys, xs = li.random_probes(n, n, 16, 405)
+    cells = set((ys * n + xs).tolist())
+    for x in (57, 58, 63, 64, 447, 448, n - 1):
+        cells.add((n // 3) * n + x)
+    cells = np.array(sorted(cells))
+    ubar = np.random.default_rng(406).standard_normal((2, cells.size))
+    _compare(sv, case, recs, cells, ubar, N, 4, 1)
+    del sv, recs
+    torch.cuda.empty_cache()
