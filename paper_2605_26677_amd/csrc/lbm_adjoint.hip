@@ -829,11 +829,71 @@ __global__ void __launch_bounds__(kBlock) adj_init_kernel(AdjInitArgs a) {
     }
     double mu, lam;
     params_at<FIELDS, double>(cm, (int)idx, mu, lam);
+    // The actions on a 2 x 2 array Z (flat index 2i + A) of the tangent C = dP/dF and of
+    // its parts Cm = dC/dmu, Cl = dC/dlam (each symmetric in iA <-> kB).  For log-NH and NH,
+    // C_iAkB = mu d_ik d_AB + a H_iB H_kA + b H_iA H_kB, whose action is
+    // mu Z + a H Z^T H + b tr(H^T Z) H, so no 4 x 4 array is formed (the three arrays would
+    // hold 96 registers); the other laws form them from their forward-mode tangent.
+    constexpr bool lame = LAW == LBM_LOGNH || LAW == LBM_NH;
     double C[16], Cm[16], Cl[16], Pm[4], Pl[4];
-    tangent<double, LAW, true>(&U0[2], mu, lam, law_consts<double>(cm), C);
-    tangent<double, LAW, true>(&U0[2], 1.0, 0.0, law_consts<double>(cm), Cm);
-    tangent<double, LAW, true>(&U0[2], 0.0, 1.0, law_consts<double>(cm), Cl);
-    piola_partials<double, LAW, true>(&U0[2], law_consts<double>(cm), Pm, Pl);
+    Kin<double> kk;
+    double aC = 0.0, bC = 0.0, aL = 0.0, bL = 0.0;
+    if constexpr (lame) {
+        kk = kinematics<double, true>(&U0[2]);
+        if constexpr (LAW == LBM_LOGNH) {
+            aC = mu - lam * kk.L;
+            bC = lam;
+            aL = -kk.L;
+            bL = 1.0;
+        } else {
+            aC = mu - 0.5 * lam * kk.Jsq_m1;
+            bC = lam * kk.J * kk.J;
+            aL = -0.5 * kk.Jsq_m1;
+            bL = kk.J * kk.J;
+        }
+        const double v = LAW == LBM_LOGNH ? kk.L : 0.5 * kk.Jsq_m1;
+        for (int k = 0; k < 4; ++k) {
+            Pm[k] = kk.FmH[k];
+            Pl[k] = v * kk.H[k];
+        }
+    } else {
+        tangent<double, LAW, true>(&U0[2], mu, lam, law_consts<double>(cm), C);
+        tangent<double, LAW, true>(&U0[2], 1.0, 0.0, law_consts<double>(cm), Cm);
+        tangent<double, LAW, true>(&U0[2], 0.0, 1.0, law_consts<double>(cm), Cl);
+        piola_partials<double, LAW, true>(&U0[2], law_consts<double>(cm), Pm, Pl);
+    }
+    // which: 0 C, 1 Cm, 2 Cl
+    auto act = [&](int which, const double Z[4], double out[4]) {
+        if constexpr (lame) {
+            const double* H = kk.H;
+            const double m = which == 0 ? mu : which == 1 ? 1.0 : 0.0;
+            const double a2 = which == 0 ? aC : which == 1 ? 1.0 : aL;
+            const double b2 = which == 0 ? bC : which == 1 ? 0.0 : bL;
+            const double tr = H[0] * Z[0] + H[1] * Z[1] + H[2] * Z[2] + H[3] * Z[3];
+            for (int i = 0; i < 2; ++i)
+                for (int A = 0; A < 2; ++A) {
+                    double hz = 0.0;
+                    for (int B = 0; B < 2; ++B)
+                        hz += H[2 * i + B] * (Z[B] * H[A] + Z[2 + B] * H[2 + A]);
+                    out[2 * i + A] = m * Z[2 * i + A] + a2 * hz + b2 * tr * H[2 * i + A];
+                }
+        } else if (which == 0) {
+            // the transposed action sum_iA C_iAkB Z_iA (the forward-mode C is symmetric only
+            // up to rounding)
+            for (int kB = 0; kB < 4; ++kB) {
+                double acc = 0.0;
+                for (int iA = 0; iA < 4; ++iA) acc += C[4 * iA + kB] * Z[iA];
+                out[kB] = acc;
+            }
+        } else {
+            const double* T = which == 1 ? Cm : Cl;
+            for (int iA = 0; iA < 4; ++iA) {
+                double acc = 0.0;
+                for (int kB = 0; kB < 4; ++kB) acc += T[4 * iA + kB] * Z[kB];
+                out[iA] = acc;
+            }
+        }
+    };
     const R* l0 = (const R*)a.lam0;
     double vb[2] = {0, 0}, vXb[2] = {0, 0}, vYb[2] = {0, 0}, Bb[2] = {0, 0};
     double dPXb[4] = {0, 0, 0, 0}, dPYb[4] = {0, 0, 0, 0};
@@ -859,20 +919,14 @@ __global__ void __launch_bounds__(kBlock) adj_init_kernel(AdjInitArgs a) {
         ZF[1] = dY[0] + c * (i * dX[3] + j * dY[3]);
         ZF[2] = dX[1] + c * (i * dX[4] + j * dY[4]);
         ZF[3] = dY[1] + c * (i * dX[5] + j * dY[5]);
-        double ZFb[4];
-        for (int kB = 0; kB < 4; ++kB) {
-            double sacc = 0.25 * w[2 + kB];
-            for (int iA = 0; iA < 4; ++iA) sacc += C[4 * iA + kB] * dPb[iA];
-            ZFb[kB] = sacc;
-        }
+        double ZFb[4], CdP[4], CmZ[4], ClZ[4];
+        act(0, dPb, CdP);                         // sum_iA C_iAkB dPb_iA
+        for (int kB = 0; kB < 4; ++kB) ZFb[kB] = 0.25 * w[2 + kB] + CdP[kB];
+        act(1, ZF, CmZ);
+        act(2, ZF, ClZ);
         for (int iA = 0; iA < 4; ++iA) {
-            double sm = 0.0, sl = 0.0;
-            for (int kB = 0; kB < 4; ++kB) {
-                sm += Cm[4 * iA + kB] * ZF[kB];
-                sl += Cl[4 * iA + kB] * ZF[kB];
-            }
-            gmu += dPb[iA] * sm;
-            glam += dPb[iA] * sl;
+            gmu += dPb[iA] * CmZ[iA];
+            glam += dPb[iA] * ClZ[iA];
         }
         Bb[0] += Z1b;
         Bb[1] += Z2b;
@@ -885,16 +939,16 @@ __global__ void __launch_bounds__(kBlock) adj_init_kernel(AdjInitArgs a) {
         vXb[1] += c * i * Z2b + ZFb[2];
         vYb[1] += c * j * Z2b + ZFb[3];
     }
-    for (int iA = 0; iA < 4; ++iA) {
-        double smx = 0.0, smy = 0.0, slx = 0.0, sly = 0.0;
-        for (int kB = 0; kB < 4; ++kB) {
-            smx += Cm[4 * iA + kB] * dX[2 + kB];
-            smy += Cm[4 * iA + kB] * dY[2 + kB];
-            slx += Cl[4 * iA + kB] * dX[2 + kB];
-            sly += Cl[4 * iA + kB] * dY[2 + kB];
+    {
+        double CmX[4], CmY[4], ClX[4], ClY[4];
+        act(1, &dX[2], CmX);
+        act(1, &dY[2], CmY);
+        act(2, &dX[2], ClX);
+        act(2, &dY[2], ClY);
+        for (int iA = 0; iA < 4; ++iA) {
+            gmu += dPXb[iA] * CmX[iA] + dPYb[iA] * CmY[iA];
+            glam += dPXb[iA] * ClX[iA] + dPYb[iA] * ClY[iA];
         }
-        gmu += dPXb[iA] * smx + dPYb[iA] * smy;
-        glam += dPXb[iA] * slx + dPYb[iA] * sly;
     }
     if (a.g_mu) a.g_mu[idx] += gmu;
     if (a.g_lam) a.g_lam[idx] += glam;
