@@ -101,7 +101,8 @@ def memory_model(nx, ny, storage, nsteps, levels, leaf_bytes_per_node=48, host_t
                  first top segment is reversed, ceil(K_{l-1} / K_l) - 1 more per level;
       records:   K_last + 1 records for the innermost replay.
     With host_top the forward's snapshots (the outermost level) live in pinned host
-    memory instead (``host`` bytes) and leave the device."""
+    memory instead (``host`` bytes) and leave the device; the backward then holds device
+    copies of two of them (the one in use and the next one, fetched ahead)."""
     z = _sizes(nx, ny, storage)
     n, N = z["nodes"], int(nsteps)
     fixed = (2 * z["pop"] + z["ustar"] + 2 * z["aux"] + 16 * n + 16 * n + 16 * n
@@ -109,7 +110,7 @@ def memory_model(nx, ny, storage, nsteps, levels, leaf_bytes_per_node=48, host_t
     pair = z["pop"] + z["rec"]
     K = [int(k) for k in levels]
     top = (N // K[0] + 1) * pair
-    snaps = 0 if host_top else top
+    snaps = 2 * pair if host_top else top
     for a, b in zip(K[:-1], K[1:]):
         snaps += (math.ceil((a + 1) / b) - 1) * pair
     records = (K[-1] + 1) * z["rec"]
@@ -234,6 +235,43 @@ def revolve_actions(start, end, leaf, slots):
     yield from revolve_actions(mid, end, leaf, slots - 1)
     yield ("free", mid)
     yield from revolve_actions(start, mid, leaf, slots)
+
+
+class _HostPrefetch:
+    """Device copies of the pinned host snapshots the backward uses, in its order of use:
+    each crosses PCIe once, on a copy stream of its own (default priority), and the copy
+    of the next one starts when the current one is taken, so that it overlaps the current
+    segment's compute.  The copy stream first waits for the work already queued on the
+    current stream (the forward's host copies among it)."""
+
+    def __init__(self, device, snaps, keys):
+        self.device, self.snaps, self.keys = device, snaps, list(keys)
+        self.stream = torch.cuda.Stream(device=device)
+        self.stream.wait_stream(torch.cuda.current_stream(device))
+        self.pending = {}
+
+    def _start(self, key):
+        if key in self.pending:
+            return
+        with torch.cuda.stream(self.stream):
+            dev = tuple(t.to(self.device, non_blocking=True) for t in self.snaps[key])
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        self.pending[key] = (dev, ev)
+
+    def take(self, j):
+        """The device copy of snapshot keys[j], ordered before the current stream's next
+        work; starts the copy of keys[j + 1]."""
+        key = self.keys[j]
+        self._start(key)
+        if j + 1 < len(self.keys):
+            self._start(self.keys[j + 1])
+        dev, ev = self.pending.pop(key)
+        cur = torch.cuda.current_stream(self.device)
+        cur.wait_event(ev)
+        for t in dev:
+            t.record_stream(cur)
+        return dev
 
 
 def _host_copy(t):
@@ -497,16 +535,24 @@ class LBMRollout(torch.autograd.Function):
             bounds = list(range(0, N + 1, K0))
             if bounds[-1] != N + 1:
                 bounds.append(N + 1)
-            for i in range(len(bounds) - 2, -1, -1):
-                _reverse_nested(sv, cfg, adj, bounds[i], bounds[i + 1], snaps[bounds[i]], inner, recs)
+            order = list(range(len(bounds) - 2, -1, -1))
+            fetch = _HostPrefetch(sv.device, snaps, [bounds[i] for i in order]) if cfg.host_top else None
+            for j, i in enumerate(order):
+                snap = fetch.take(j) if fetch else snaps[bounds[i]]
+                _reverse_nested(sv, cfg, adj, bounds[i], bounds[i + 1], snap, inner, recs)
+                del snap
         else:
             K = cfg.checkpoint_every
             recs = [sv.new_record() for _ in range(K + 1)]
             starts = list(range(0, N + 1, K))
-            for i in range(len(starts) - 1, -1, -1):
+            order = list(range(len(starts) - 1, -1, -1))
+            fetch = _HostPrefetch(sv.device, snaps, [starts[i] for i in order]) if cfg.host_top else None
+            for j, i in enumerate(order):
                 start = starts[i]
                 end = min(start + K, N + 1)
-                _reverse_segment(sv, cfg, adj, start, end, snaps[start], recs)
+                snap = fetch.take(j) if fetch else snaps[start]
+                _reverse_segment(sv, cfg, adj, start, end, snap, recs)
+                del snap
         adj.init(sv, cfg, ctx.v0, ctx.u0)
         ny, nx = cfg.ny, cfg.nx
         g_mu = adj.g_mu.view(ny, nx).to(ctx.dtypes[0])
