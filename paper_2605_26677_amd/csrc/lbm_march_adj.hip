@@ -221,7 +221,19 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
                     if (!has[j]) continue;
                     gn[j] = gn[j] + float(inc[j]);
                     if (a.fold[t]) {
-                        if (own) g64[j][idx] += double(gn[j]);
+                        // One lane owns each node and at most one level of a pass folds
+                        // (levels <= 4 < kGradBlock), so a return-less FP64 atomic add at
+                        // L2 performs the same addition as a load, add and store, without
+                        // the wave waiting for the load.  At a probe node the body gradient
+                        // also takes the probe term below by load and store, so both of its
+                        // updates stay plain there: every address sees one kind of access.
+                        if (own) {
+                            if (j >= 2 && probe)
+                                g64[j][idx] += double(gn[j]);
+                            else
+                                __hip_atomic_fetch_add(g64[j] + idx, double(gn[j]), __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                        }
                         gn[j] = 0.0f;
                     }
                 }
