@@ -358,7 +358,9 @@ class _Adjoint:
 
 
 def _restore(sv, snap):
-    sv.pop[sv.s.cur].copy_(snap[0], non_blocking=True)
+    """Level of the snapshot as the solver's current level: its populations are lent to the
+    next launch, which reads them in place (no copy), and are left unchanged."""
+    sv.lend(snap[0])
 
 
 def _steps_to_snapshot(sv, cfg, n0, n, ustar=True):
@@ -366,7 +368,8 @@ def _steps_to_snapshot(sv, cfg, n0, n, ustar=True):
     the record comes from the step kernel itself, exactly as a replay would produce it, so
     every schedule sees the same records.  Where the rollout fuses levels and a plain step
     precedes, that step and step n run as one pair that records its second level (bit for
-    bit the two single steps)."""
+    bit the two single steps).  The snapshot takes over the buffer the last step wrote
+    (Solver.detach_current) rather than a copy of it."""
     rec = sv.new_record()
     if n > n0 and _pairs(sv, cfg):
         _plain_steps(sv, cfg, n0, n - 1, ustar=ustar)
@@ -374,7 +377,7 @@ def _steps_to_snapshot(sv, cfg, n0, n, ustar=True):
     else:
         _plain_steps(sv, cfg, n0, n, ustar=ustar)
         sv.step(n, cfg.ramp(n), cfg.ramp(n + 1), _edges(cfg, n), record=rec, ustar=ustar)
-    return (sv.pop[sv.s.cur].clone(), rec)
+    return (sv.detach_current(), rec)
 
 
 def _pairs(sv, cfg):
@@ -416,9 +419,11 @@ def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
     replay skips the displacement quadrature (the adjoint does not read u*) and records
     U of every level, several levels per call (Solver.replay_multi_levels, else pairs;
     the multi-level calls write only the F - I planes, which is all the adjoint reads);
-    the adjoint takes several levels per call (Solver.adj_multi_levels, else pairs)."""
+    the adjoint takes several levels per call (Solver.adj_multi_levels, else pairs).  The
+    snapshot's populations and record are read in place: the replay's first launch reads
+    the former, the adjoint's last level the latter."""
     _restore(sv, snap)
-    recs[0].copy_(snap[1], non_blocking=True)
+    recs = [snap[1]] + recs[1:]
     n = start
     pairs = _pairs(sv, cfg)
     rmulti = sv.replay_multi_levels if (pairs and cfg.multi is not False) else 0
@@ -487,7 +492,7 @@ class LBMRollout(torch.autograd.Function):
         # checkpoints only when a gradient will be asked for (a no-grad evaluation, such as
         # a finite-difference probe, keeps nothing)
         keep = any(ctx.needs_input_grad[:4])
-        snaps = {0: (sv.pop[sv.s.cur].clone(), sv.record_state(cfg.ramp(0), sv.new_record()))} if keep else {}
+        snaps = {0: (sv.detach_current(), sv.record_state(cfg.ramp(0), sv.new_record()))} if keep else {}
         if keep and cfg.host_top:
             snaps[0] = tuple(_host_copy(t) for t in snaps[0])
         n = 0

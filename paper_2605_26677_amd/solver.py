@@ -79,6 +79,8 @@ class StepGraph:
     so its launches are capture-safe; the capture itself executes nothing."""
 
     def __init__(self, solver, steps):
+        if solver._lent is not None:
+            raise RuntimeError("StepGraph: the current level is in a lent buffer; advance once before capturing")
         self.sv = solver
         self.start_cur = solver.s.cur
         self._keep = ([st.get("edges") for st in steps] + [st.get("edges_next") for st in steps]
@@ -176,6 +178,7 @@ class Solver:
         s.aux = self.aux.data_ptr()
         s.fault = self.fault.data_ptr()
         self.s = s
+        self._lent = None          # (slot, own buffer) while a lent buffer holds the current level
         self.set_parameters(mu, lam, body)
 
     # ------------------------------------------------------------ parameters
@@ -226,9 +229,42 @@ class Solver:
         """A state record (6 tiled planes of the compute type, see lbm.h)."""
         return torch.empty(self.record_bytes // self.real_dtype.itemsize, dtype=self.real_dtype, device=self.device)
 
+    # ------------------------------------------------------------ lent buffers
+    def lend(self, buf):
+        """Take the current level from `buf`, a population buffer of lbm_pop_bytes() that the
+        caller keeps (a snapshot), in place of copying it in: the next call that advances
+        the state reads buf and writes the solver's other buffer, and the solver's own buffer
+        is back in its slot after that call.  No launch writes the buffer that holds the
+        current level, so buf is left as it was."""
+        self._give_back()
+        slot = self.s.cur
+        self._lent = (slot, self.pop[slot])
+        self.pop[slot] = buf
+        self.s.pop[slot] = buf.data_ptr()
+
+    def detach_current(self):
+        """The buffer that holds the current level, handed over to the caller (a snapshot,
+        in place of a copy): the solver's slot gets a fresh buffer, and the next call that
+        advances the state still reads the level from the handed-over one (see lend)."""
+        slot = self.s.cur
+        if self._lent is not None:
+            return self.pop[slot]          # already the caller's buffer
+        cur = self.pop[slot]
+        self.pop[slot] = torch.empty_like(cur)
+        self.lend(cur)
+        return cur
+
+    def _give_back(self):
+        if self._lent is not None:
+            slot, own = self._lent
+            self._lent = None
+            self.pop[slot] = own
+            self.s.pop[slot] = own.data_ptr()
+
     # ------------------------------------------------------------ entry points
     def init(self, v0, u0=None, r0=0.0, Fbar=None):
         """lbm_init; Fbar (2, 2) is an optional uniform predeformation (F = Fbar + grad u0)."""
+        self._give_back()
         self._v0 = _as_device(v0, self.device)
         self._u0 = None if u0 is None else _as_device(u0, self.device)
         self.s.cur = 0
@@ -242,6 +278,7 @@ class Solver:
         derivatives given by the caller."""
         def dev(a):
             return torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+        self._give_back()
         self._U0, self._dUdX, self._dUdY = dev(U0), dev(dUdX), dev(dUdY)
         self._u0 = None if u0 is None else dev(u0)
         self.s.cur = 0
@@ -260,6 +297,7 @@ class Solver:
         try:
             L.check(self.lib.lbm_step(ctypes.byref(self.p), ctypes.byref(self.s), int(n), float(r_n),
                                       float(r_np1), ctypes.byref(ed.c), _ptr(record), _stream()), "lbm_step")
+            self._give_back()
         finally:
             self.s.ustar = keep
 
@@ -277,6 +315,7 @@ class Solver:
             L.check(self.lib.lbm_step2(ctypes.byref(self.p), ctypes.byref(self.s), int(n), float(r_n), float(r_np1),
                                        float(r_np2), ctypes.byref(e1.c), ctypes.byref(e2.c), _ptr(record1),
                                        _ptr(record2), _stream()), "lbm_step2")
+            self._give_back()
         finally:
             self.s.ustar = keep
 
@@ -303,6 +342,7 @@ class Solver:
                                             ctypes.cast(arr, ctypes.c_void_p),
                                             ctypes.cast(recs, ctypes.c_void_p) if recs is not None else None,
                                             int(record_planes), _stream()), "lbm_step_multi")
+            self._give_back()
         finally:
             self.s.ustar = keep
 
