@@ -258,12 +258,13 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
     bool nonfinite = false, jbad = false;
 
     const int iters = Sy + 2 * (NT - 1);
-    // A window wholly past the grid's last column (in a row's last span) outputs only
-    // padding columns, and the tile of its wavefront lies past the last column as well
-    // (a window starts no later than its tile), so nothing it computes would be stored: the
-    // wavefront only takes part in the workgroup's barriers.  The padding columns of the
-    // stored tiles then hold unspecified values, which no kernel or entry point reads.
-    if (c0 + ws >= nx) {
+    // A window that starts past the last stored tile (in a row's last span) outputs no
+    // column of a stored tile, and its own tile is not stored either (a window starts no
+    // later than its tile): the wavefront only takes part in the workgroup's barriers.  A
+    // window that starts past the grid's last column but inside the last tile still runs,
+    // so that the padding columns of that tile receive the wrapped copies of real nodes
+    // and every stored word is defined.
+    if (c0 + ws >= ntile * kTile) {
         for (int i = 0; i < iters; ++i) {
             if (NB == 1) __syncthreads();
             __syncthreads();

@@ -155,8 +155,8 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
     const bool own_col = out_lane && c0 + pos < nx;
 
     const int iters = Sy + 2 * (NT - 1);
-    // a window wholly past the grid's last column: barriers only (see march_kernel)
-    if (c0 + ws >= nx) {
+    // a window that starts past the last stored tile: barriers only (see march_kernel)
+    if (c0 + ws >= ntile * kTile) {
         for (int i = 0; i < iters; ++i) __syncthreads();
         return;
     }
