@@ -94,6 +94,8 @@ class StepGraph:
         self.nsteps = sum(st["multi"] if st.get("multi") else 2 if st.get("pair") else 1 for st in steps)
 
     def replay(self):
+        if self.sv._lent is not None:
+            raise RuntimeError("StepGraph.replay: the current level is in a lent buffer, which the graph does not read")
         if self.sv.s.cur != self.start_cur:
             raise RuntimeError("StepGraph.replay: the solver's current buffer differs from the capture's")
         self.graph.replay()
@@ -451,10 +453,13 @@ class Solver:
         while n < end:
             m = min(end, n + block)
             blk = block_calls(n, m)
-            if graph_on and m - n == block and graph is None and self._graph_ok(blk):
+            # a graph holds the solver's own buffers: a block that starts from a lent buffer
+            # runs eagerly (and gives the buffer back)
+            eager = self._lent is not None
+            if graph_on and m - n == block and graph is None and not eager and self._graph_ok(blk):
                 proto = blk
                 graph = self.capture(blk)
-            if (graph is not None and m - n == block and self.s.cur == graph.start_cur
+            if (graph is not None and not eager and m - n == block and self.s.cur == graph.start_cur
                     and all(self._same(a, b) for a, b in zip(blk, proto))):
                 graph.replay()
             else:
