@@ -136,12 +136,12 @@ class Solver:
     # against 0.1121; adjoint: 1024^2 0.0298 against 0.0311, 2048^2 0.0770 against 0.1193)
     BACKWARD_MULTI_MIN_NODES = 2048 * 2048
     # adjoint levels per lbm_adjoint_step_multi call (8192^2 FP32 log-NH, per-node mu lam,
-    # gradients: pairs through lbm_adjoint_step2 1.78 ms per level, three levels 1.31, four
-    # 1.14); three for the invariant-based laws, whose four-level kernel runs out of registers
+    # gradients: pairs through lbm_adjoint_step2 1.77 ms per level, three levels 1.23, four
+    # 1.00); three for the invariant-based laws, whose four-level kernel runs out of registers
     ADJ_MULTI_LEVELS = 4
     ADJ_MULTI_LEVELS_INVARIANT = 3
     # levels per lbm_step_multi call in the replay form (records of every level; 8192^2 FP32,
-    # per-node mu lam: pairs 1.61 ms per level, three levels 1.24, four 1.03)
+    # per-node mu lam: pairs 1.63 ms per level, three levels 1.10, four 0.90)
     REPLAY_MULTI_LEVELS = 4
 
     def __init__(self, nx, ny, *, c, omega, dx=1.0, material="lognh", storage="f32",
