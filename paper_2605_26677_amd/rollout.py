@@ -359,8 +359,13 @@ class _Adjoint:
 
 def _restore(sv, snap):
     """Level of the snapshot as the solver's current level: its populations are lent to the
-    next launch, which reads them in place (no copy), and are left unchanged."""
+    next launch, which reads them in place (no copy), and are left unchanged.  A snapshot in
+    host memory (the forward's level 0 with host_top, as binomial checkpointing reads it)
+    is copied to the device first.  Returns the snapshot as the device holds it."""
+    if snap[0].device.type != sv.pop[sv.s.cur].device.type:
+        snap = tuple(t.to(sv.pop[sv.s.cur].device, non_blocking=True) for t in snap)
     sv.lend(snap[0])
+    return snap
 
 
 def _steps_to_snapshot(sv, cfg, n0, n, ustar=True):
@@ -422,7 +427,7 @@ def _reverse_segment(sv, cfg, adj, start, end, snap, recs):
     the adjoint takes several levels per call (Solver.adj_multi_levels, else pairs).  The
     snapshot's populations and record are read in place: the replay's first launch reads
     the former, the adjoint's last level the latter."""
-    _restore(sv, snap)
+    snap = _restore(sv, snap)
     recs = [snap[1]] + recs[1:]
     n = start
     pairs = _pairs(sv, cfg)

@@ -217,7 +217,10 @@ def test_rollout_in_pairs_matches_oracle_adjoint(storage, bar):
 @pytest.mark.parametrize("slots", [1, 2, 3])
 def test_binomial_checkpointing_gives_the_every_k_gradients(kind, slots):
     """Binomial checkpointing (RolloutConfig.revolve) replays the same levels with the same
-    records as the every-K schedule, so its gradients are bit for bit the same; u^N too."""
+    records as the every-K schedule, so its gradients are bit for bit the same; u^N too.
+    Both schedules also with their outermost snapshots in pinned host memory (host_top:
+    every-K fetches them ahead, binomial checkpointing copies level 0 in where it restores
+    it)."""
     import dataclasses
     from paper_2605_26677_amd.rollout import RolloutConfig, rollout
     nx, ny, N = 48, 30, 41
@@ -234,15 +237,16 @@ def test_binomial_checkpointing_gives_the_every_k_gradients(kind, slots):
     cfg_k = RolloutConfig(**kw)
     cfg_r = dataclasses.replace(cfg_k, revolve=slots)
     res = []
-    for cfg in (cfg_k, cfg_r):
+    for cfg in (cfg_k, cfg_r, dataclasses.replace(cfg_r, host_top=True), dataclasses.replace(cfg_k, host_top=True)):
         leaves = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True)
                   for a in (mu0, lam0, b0, w0)]
         out = rollout(*leaves, cfg)
         (out.double() ** 2).sum().backward()
         res.append((out.detach(), [t.grad for t in leaves]))
-    assert torch.equal(res[0][0], res[1][0])
-    for ga, gb in zip(res[0][1], res[1][1]):
-        assert torch.equal(ga, gb)
+    for other in res[1:]:
+        assert torch.equal(res[0][0], other[0])
+        for ga, gb in zip(res[0][1], other[1]):
+            assert torch.equal(ga, gb)
 
 
 @pytest.mark.parametrize("kind", ["periodic", "walls"])
