@@ -316,7 +316,10 @@ typedef struct {
     void *adj[2];              /* device: two adjoint population buffers, lbm_adj_bytes() each */
     int32_t cur;               /* buffer holding lambda^{m+1} = dL/df^{m+1} before a step */
     double *g_mu, *g_lam;      /* device, 1 plane each: accumulated dL/dmu, dL/dlam, or NULL */
-    double *g_body;            /* device, 2 planes: accumulated dL/db, or NULL */
+    double *g_body;            /* device, 2 planes: accumulated dL/db, or NULL.  The three
+                                  must be ordinary device memory (not host memory mapped into
+                                  the device): lbm_adjoint_step_multi adds to them with FP64
+                                  atomic adds, which such memory may not perform */
     const int32_t *probe;      /* device: nprobe node indices (b*nx + a), each in
                                   [0, nx*ny); a cell may repeat (its sources add up).  The
                                   library cannot read device memory before launching: the
