@@ -242,7 +242,7 @@ class _HostPrefetch:
     each crosses PCIe once, on a copy stream of its own (default priority), and the copy
     of the next one starts when the current one is taken, so that it overlaps the current
     segment's compute.  The copy stream first waits for the work already queued on the
-    current stream (the forward's host copies among it)."""
+    current stream, which itself waits for the forward's host copies (_HostSaver.finish)."""
 
     def __init__(self, device, snaps, keys):
         self.device, self.snaps, self.keys = device, snaps, list(keys)
@@ -274,11 +274,32 @@ class _HostPrefetch:
         return dev
 
 
-def _host_copy(t):
-    """Pinned host copy of a device tensor, ordered on the current stream."""
-    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
-    h.copy_(t, non_blocking=True)
-    return h
+class _HostSaver:
+    """Pinned host copies of the forward's snapshots on a copy stream of its own (default
+    priority), so that they overlap the forward's compute: each copy starts after the work
+    already queued on the current stream (the step that wrote the snapshot), the device
+    tensor stays allocated until its copy is done, and ``finish`` makes the current stream
+    wait for every copy, so that all later work (the backward's fetches among it) sees
+    complete host snapshots."""
+
+    def __init__(self, device):
+        self.device = device
+        self.stream = torch.cuda.Stream(device=device)
+
+    def save(self, snap):
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        out = []
+        with torch.cuda.stream(self.stream):
+            for t in snap:
+                h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+                h.copy_(t, non_blocking=True)
+                t.record_stream(self.stream)
+                out.append(h)
+        return tuple(out)
+
+    def finish(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
 
 def _edges(cfg, n):
@@ -498,8 +519,9 @@ class LBMRollout(torch.autograd.Function):
         # a finite-difference probe, keeps nothing)
         keep = any(ctx.needs_input_grad[:4])
         snaps = {0: (sv.detach_current(), sv.record_state(cfg.ramp(0), sv.new_record()))} if keep else {}
-        if keep and cfg.host_top:
-            snaps[0] = tuple(_host_copy(t) for t in snaps[0])
+        saver = _HostSaver(sv.device) if keep and cfg.host_top else None
+        if saver:
+            snaps[0] = saver.save(snaps[0])
         n = 0
         while n < N:
             # plain steps up to the next snapshot step (the one that reaches a multiple of K;
@@ -507,11 +529,13 @@ class LBMRollout(torch.autograd.Function):
             end = min(N, (n // K + 1) * K - 1) if keep and not cfg.revolve else N
             if end < N:
                 snap = _steps_to_snapshot(sv, cfg, n, end)
-                snaps[end + 1] = tuple(_host_copy(t) for t in snap) if cfg.host_top else snap
+                snaps[end + 1] = saver.save(snap) if saver else snap
                 n = end + 1
             else:
                 _plain_steps(sv, cfg, n, end)
                 n = end
+        if saver:
+            saver.finish()
         u = sv.displacement(cfg.ramp(N))
         probes = cfg.probes.to(device=mu.device, dtype=torch.long)
         out = u.reshape(2, -1)[:, probes]
