@@ -656,6 +656,8 @@ def main():
                     help="comma list of pinned host memory sizes (GiB) for the outermost checkpoints, "
                          "one timed run each (0: device only)")
     ap.add_argument("--no-scale", action="store_true", help="skip the 4096^2 adjoint workload")
+    ap.add_argument("--fwd-adj", action="store_true",
+                    help="only the FP32 forward + adjoint leg (one untimed and one timed rollout), for rocprofv3")
     ap.add_argument("--levels", action="store_true",
                     help="ms per level of forward, recorded replay and adjoint against the levels per call")
     args = ap.parse_args()
@@ -678,6 +680,9 @@ def main():
         return
     if args.levels:
         print(json.dumps({"levels": time_levels(n)}), flush=True)
+        return
+    if args.fwd_adj:
+        print(json.dumps({"fwd_adj": time_forward_adjoint(n, args.adjoint_steps, args.adjoint_every)}), flush=True)
         return
     log(f"bench: generating {n}x{n} inputs")
     v0 = make_inputs(n)
