@@ -274,7 +274,8 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
     }
     prefetch(rw[0], rw[1], rw[2], rw[NT]);
     store_row(rw[NT], false, 0, false, -1);
-    for (int i = 0; i < iters; ++i) {
+    auto iteration = [&](int i, auto steady_c) {
+        constexpr bool steady = decltype(steady_c)::value;
         const int b = NB == 1 ? 0 : (i & 1);
         const int rb = record_buffer(i);
         // REC: the record of level t at this lane's output column into LDS buffer b
@@ -323,13 +324,13 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
         }
 #pragma unroll
         for (int L = 2; L <= NT; ++L) {
-            if (i < 2 * (L - 2)) break;             // level n+L-1 has not started
+            if (!steady && i < 2 * (L - 2)) break;  // level n+L-1 has not started
             // f: level n+L-1 of row y1 - (L - 2), rounded to the stored value
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) f[q][k] = R(to_storage<T>(f[q][k]));
-            const bool act = i >= 2 * (L - 1);
+            const bool act = steady || i >= 2 * (L - 1);
             if (act) {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
@@ -363,7 +364,7 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
         // f: level n+NT of output row y1 - (NT - 1) from iteration 2 (NT - 1) on.  The
         // displacement quadrature over the NT levels (eq:trapezoid-u), with the accumulator
         // updates and folds of NT single steps.
-        const bool outp = i >= 2 * (NT - 1);
+        const bool outp = steady || i >= 2 * (NT - 1);
         float Sn[2] = {0.0f, 0.0f};
         double Un[2] = {0.0, 0.0};
         bool moved = false;
@@ -432,7 +433,11 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
 #pragma unroll
         for (int j = NT; j >= 1; --j) rw[j] = rw[j - 1];
         rw[0] = wrap_inc(rw[0], ny);
-    }
+    };
+    const int warm = iters < 2 * (NT - 1) ? iters : 2 * (NT - 1);
+    int i = 0;
+    for (; i < warm; ++i) iteration(i, std::false_type{});
+    for (; i < iters; ++i) iteration(i, std::true_type{});
     if (nonfinite || jbad)
         atomicOr(cm.fault, (jbad ? (uint32_t)LBM_FAULT_J : 0u) | (nonfinite ? (uint32_t)LBM_FAULT_NONFINITE : 0u));
 }
