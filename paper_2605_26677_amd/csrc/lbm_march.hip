@@ -434,10 +434,17 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_kernel(MarchArgs a)
         for (int j = NT; j >= 1; --j) rw[j] = rw[j - 1];
         rw[0] = wrap_inc(rw[0], ny);
     };
-    const int warm = iters < 2 * (NT - 1) ? iters : 2 * (NT - 1);
+    // (the invariant-based laws, short of registers already, keep one loop: a second copy
+    // of the body made them spill more)
+    constexpr bool kPeel = LAW == LBM_LOGNH || LAW == LBM_NH || LAW == LBM_SVK;
     int i = 0;
-    for (; i < warm; ++i) iteration(i, std::false_type{});
-    for (; i < iters; ++i) iteration(i, std::true_type{});
+    if constexpr (kPeel) {
+        const int warm = iters < 2 * (NT - 1) ? iters : 2 * (NT - 1);
+        for (; i < warm; ++i) iteration(i, std::false_type{});
+        for (; i < iters; ++i) iteration(i, std::true_type{});
+    } else {
+        for (; i < iters; ++i) iteration(i, std::false_type{});
+    }
     if (nonfinite || jbad)
         atomicOr(cm.fault, (jbad ? (uint32_t)LBM_FAULT_J : 0u) | (nonfinite ? (uint32_t)LBM_FAULT_NONFINITE : 0u));
 }

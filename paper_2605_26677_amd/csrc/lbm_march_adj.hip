@@ -164,7 +164,10 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
 #pragma unroll
     for (int t = 0; t < NT; ++t) prefetch_level(t, rw[t + 1]);
     store_row(rw[NT], false, 0);
-    for (int i = 0; i < iters; ++i) {
+    // The first 2 (NT - 1) iterations, in which levels are still starting, are peeled off
+    // the steady loop, which then needs no checks for them (a compile-time flag).
+    auto iteration = [&](int i, auto steady_c) {
+        constexpr bool steady = decltype(steady_c)::value;
         R f[4][6];
         R l[4][6];
 #pragma unroll
@@ -215,7 +218,7 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
                     gn[0] = v.x; gn[1] = v.y; gn[2] = v.z; gn[3] = v.w;
                 }
                 // the row of level t is an output row of the segment
-                const bool own = own_col && i >= NT - 1 + t && i < Sy + NT - 1 + t;
+                const bool own = own_col && (steady || i >= NT - 1 + t) && i < Sy + NT - 1 + t;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if (!has[j]) continue;
@@ -251,8 +254,8 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
         prefetch_level(0, rw[0]);
 #pragma unroll
         for (int L = 2; L <= NT; ++L) {
-            const bool started = i >= 2 * (L - 2);  // level L-2 of the pass has run
-            const bool act = i >= 2 * (L - 1);
+            const bool started = steady || i >= 2 * (L - 2);  // level L-2 of the pass has run
+            const bool act = steady || i >= 2 * (L - 1);
             if (act) {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
@@ -276,7 +279,7 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
         }
         // f, gn: lambda and the block sums of the pass's last level at output row
         // y1 - (NT - 1) from iteration 2 (NT - 1) on
-        const bool outp = i >= 2 * (NT - 1);
+        const bool outp = steady || i >= 2 * (NT - 1);
         const int b = i & 1;
         if (outp && out_lane) {
 #pragma unroll
@@ -293,6 +296,17 @@ __global__ void __launch_bounds__(kMarchWaves * kTile) march_adj_kernel(MarchAdj
 #pragma unroll
         for (int j = NT; j >= 1; --j) rw[j] = rw[j - 1];
         rw[0] = wrap_inc(rw[0], ny);
+    };
+    // (the invariant-based laws, short of registers already, keep one loop: a second copy
+    // of the body made them spill more)
+    constexpr bool kPeel = LAW == LBM_LOGNH || LAW == LBM_NH || LAW == LBM_SVK;
+    int i = 0;
+    if constexpr (kPeel) {
+        const int warm = iters < 2 * (NT - 1) ? iters : 2 * (NT - 1);
+        for (; i < warm; ++i) iteration(i, std::false_type{});
+        for (; i < iters; ++i) iteration(i, std::true_type{});
+    } else {
+        for (; i < iters; ++i) iteration(i, std::false_type{});
     }
 }
 
